@@ -1,0 +1,325 @@
+"""FP64 serial CPU oracle of the ensemble flood model (test infrastructure).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  The product library (``paper_2302_08341_amd``) never
+imports, links or calls it; the two share no code.  The arithmetic lives in
+``flood_oracle.c`` (plain C, double precision, contraction off); this module
+only marshals arguments and performs the particle filter's member copy, which
+is plain array copying.
+
+Readings of the paper that the oracle adopts (where it is silent or
+ambiguous) are listed in DESIGN.md under "Readings".
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "flood_oracle.c")
+_LIB = os.path.join(_HERE, "_liborc.so")
+
+EDGE_WALL, EDGE_OPEN = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (serial, -O2, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                               "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Model(C.Structure):
+    _fields_ = [("ny", C.c_int32), ("nx", C.c_int32), ("dx", C.c_double),
+                ("z", C.POINTER(C.c_double)), ("n", C.POINTER(C.c_double)),
+                ("edge_kind", C.c_int32 * 4), ("edge_slope", C.c_double * 4),
+                ("rain", C.POINTER(C.c_double)), ("n_rain", C.c_int32), ("rain_interval", C.c_double),
+                ("alpha", C.c_double), ("h_dry", C.c_double), ("dt_cap", C.c_double),
+                ("dt_fixed", C.c_double), ("g", C.c_double)]
+
+
+class _Member(C.Structure):
+    _fields_ = [("h", C.POINTER(C.c_double)), ("qx", C.POINTER(C.c_double)), ("qy", C.POINTER(C.c_double)),
+                ("t", C.c_double), ("s", C.c_double), ("mu", C.c_double),
+                ("v_rain", C.c_double), ("v_out", C.c_double), ("v_clamp", C.c_double),
+                ("steps", C.c_int64)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = C.CDLL(_LIB)
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int32)
+        lp = C.POINTER(C.c_int64)
+        Mp = C.POINTER(_Model)
+        Sp = C.POINTER(_Member)
+        lib.orc_dt_cfl.restype = C.c_double
+        lib.orc_dt_cfl.argtypes = [Mp, dp]
+        lib.orc_step.argtypes = [Mp, Sp, C.c_double]
+        lib.orc_advance.argtypes = [Mp, Sp, C.c_double, C.c_int64, dp, C.c_int64, lp]
+        lib.orc_storage.restype = C.c_double
+        lib.orc_storage.argtypes = [Mp, dp]
+        lib.orc_pf_weights.argtypes = [C.c_int32, C.c_int32, dp, dp, dp, dp, dp, dp, dp]
+        lib.orc_systematic.argtypes = [C.c_int32, dp, C.c_double, ip]
+        lib.orc_pf.argtypes = [C.c_int32, C.c_int32, dp, dp, dp, dp, C.c_double, C.c_double, dp, ip, ip]
+        lib.orc_loss.argtypes = [Mp, Sp, C.c_double, C.c_double, C.c_int32, ip, dp, dp, dp, C.c_int64, dp]
+        lib.orc_adjoint.argtypes = [Mp, Sp, C.c_double, C.c_double, C.c_int32, ip, dp, C.c_int32, dp, dp, dp,
+                                    dp, dp, C.c_int64, lp]
+        lib.orc_adj_step.argtypes = [Mp, C.c_double, C.c_double, dp, dp, dp, C.c_double, C.c_double, dp, dp, dp,
+                                     dp, dp]
+        _lib = lib
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32)) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Model:
+    """Static description of one catchment: grid, bed, roughness, edges, rain, step policy."""
+
+    def __init__(self, dem, manning, dx, rain, rain_interval=300.0, edge_kind=(0, 0, 0, 0),
+                 edge_slope=(0.0, 0.0, 0.0, 0.0), alpha=0.7, h_dry=1e-3, dt_cap=10.0, dt_fixed=0.0, g=9.81):
+        self.z = _f64(dem)
+        self.n = _f64(manning)
+        self.ny, self.nx = self.z.shape
+        self.dx = float(dx)
+        self.rain = _f64(rain).ravel()
+        if self.rain.size == 0:
+            self.rain = np.zeros(1)
+            n_rain = 0
+        else:
+            n_rain = self.rain.size
+        self._m = _Model(self.ny, self.nx, self.dx, _dp(self.z), _dp(self.n),
+                         (C.c_int32 * 4)(*edge_kind), (C.c_double * 4)(*edge_slope),
+                         _dp(self.rain), n_rain, float(rain_interval), float(alpha), float(h_dry),
+                         float(dt_cap), float(dt_fixed), float(g))
+        self.edge_kind = tuple(edge_kind)
+        self.edge_slope = tuple(edge_slope)
+        self.h_dry = h_dry
+        self.g = g
+
+    @classmethod
+    def from_workload(cls, wl, catchment=0, **over):
+        c = wl.catchments[catchment]
+        kw = dict(rain_interval=wl.rain_interval, edge_kind=c.edge_kind, edge_slope=c.edge_slope,
+                  alpha=wl.cfl_alpha, h_dry=wl.h_dry, dt_cap=wl.dt_cap, dt_fixed=wl.dt_fixed, g=wl.g)
+        kw.update(over)
+        return cls(c.dem, c.manning, c.dx, wl.rain, **kw)
+
+    @property
+    def ptr(self):
+        return C.byref(self._m)
+
+
+@dataclass
+class Member:
+    h: np.ndarray
+    qx: np.ndarray
+    qy: np.ndarray
+    t: float = 0.0
+    s: float = 1.0
+    mu: float = 1.0
+    v_rain: float = 0.0
+    v_out: float = 0.0
+    v_clamp: float = 0.0
+    steps: int = 0
+    dt_log: list = field(default_factory=list)
+
+    @classmethod
+    def dry(cls, model: Model, s=1.0, mu=1.0, h0=None):
+        h = np.zeros((model.ny, model.nx)) if h0 is None else _f64(h0).copy()
+        return cls(h=h, qx=np.zeros((model.ny, model.nx + 1)), qy=np.zeros((model.ny + 1, model.nx)),
+                   s=float(s), mu=float(mu))
+
+    def copy(self):
+        return Member(self.h.copy(), self.qx.copy(), self.qy.copy(), self.t, self.s, self.mu, self.v_rain,
+                      self.v_out, self.v_clamp, self.steps, list(self.dt_log))
+
+    def _c(self):
+        for a in (self.h, self.qx, self.qy):
+            assert a.flags.c_contiguous and a.dtype == np.float64
+        return _Member(_dp(self.h), _dp(self.qx), _dp(self.qy), self.t, self.s, self.mu, self.v_rain,
+                       self.v_out, self.v_clamp, self.steps)
+
+    def _back(self, cm):
+        self.t, self.v_rain, self.v_out, self.v_clamp, self.steps = cm.t, cm.v_rain, cm.v_out, cm.v_clamp, cm.steps
+
+
+def dt_cfl(model: Model, h) -> float:
+    h = _f64(h)
+    return _load().orc_dt_cfl(model.ptr, _dp(h))
+
+
+def step(model: Model, mem: Member, dt: float) -> None:
+    cm = mem._c()
+    rc = _load().orc_step(model.ptr, C.byref(cm), float(dt))
+    if rc:
+        raise ValueError("orc_step failed: %d" % rc)
+    mem._back(cm)
+
+
+def advance(model: Model, mem: Member, t_end: float, max_steps: int = 10 ** 12, log_dt: bool = False) -> int:
+    cm = mem._c()
+    n = C.c_int64(0)
+    cap = 0
+    buf = None
+    if log_dt:
+        cap = 1 << 20
+        buf = np.zeros(cap)
+    rc = _load().orc_advance(model.ptr, C.byref(cm), float(t_end), int(max_steps), _dp(buf), cap, C.byref(n))
+    if rc:
+        raise ValueError("orc_advance failed: %d" % rc)
+    mem._back(cm)
+    if log_dt:
+        mem.dt_log.extend(buf[:min(n.value, cap)].tolist())
+    return n.value
+
+
+def storage(model: Model, h) -> float:
+    h = _f64(h)
+    return _load().orc_storage(model.ptr, _dp(h))
+
+
+def pf_weights(y, d, sigma, logw_prior):
+    y = _f64(y)
+    N, K = y.shape
+    d, sigma, lw = _f64(d), _f64(sigma), _f64(logw_prior)
+    lp = np.zeros(N)
+    w = np.zeros(N)
+    neff = C.c_double(0.0)
+    rc = _load().orc_pf_weights(N, K, _dp(y), _dp(d), _dp(sigma), _dp(lw), _dp(lp), _dp(w), C.byref(neff))
+    if rc:
+        raise ValueError("orc_pf_weights failed: %d" % rc)
+    return lp, w, neff.value
+
+
+def systematic(w, u0: float) -> np.ndarray:
+    w = _f64(w)
+    anc = np.zeros(w.size, dtype=np.int32)
+    rc = _load().orc_systematic(w.size, _dp(w), float(u0), _ip(anc))
+    if rc:
+        raise ValueError("orc_systematic failed: %d" % rc)
+    return anc
+
+
+def pf(y, d, sigma, logw, neff_frac: float, u0: float):
+    """Filter update; returns (new logw, neff, ancestors, resampled)."""
+    y = _f64(y)
+    N, K = y.shape
+    d, sigma = _f64(d), _f64(sigma)
+    lw = _f64(logw).copy()
+    neff = C.c_double(0.0)
+    anc = np.zeros(N, dtype=np.int32)
+    res = C.c_int32(0)
+    rc = _load().orc_pf(N, K, _dp(y), _dp(d), _dp(sigma), _dp(lw), float(neff_frac), float(u0),
+                        C.byref(neff), _ip(anc), C.byref(res))
+    if rc:
+        raise ValueError("orc_pf failed: %d" % rc)
+    return lw, neff.value, anc, bool(res.value)
+
+
+def gauge_values(members, gauges) -> np.ndarray:
+    """Observation operator: depth at each gauge cell for every member, [N, K]."""
+    g = np.asarray(gauges, dtype=np.int64).reshape(-1, 2)
+    return np.array([[m.h[r, c] for r, c in g] for m in members], dtype=np.float64).reshape(len(members), len(g))
+
+
+class Ensemble:
+    """Members of one catchment plus their log-weights (equal at start)."""
+
+    def __init__(self, model: Model, s, mu, h0=None):
+        self.model = model
+        self.members = [Member.dry(model, s[i], mu[i], h0) for i in range(len(s))]
+        self.logw = np.full(len(s), -np.log(len(s)))
+
+    def advance(self, t_end: float, log_dt=False):
+        return [advance(self.model, m, t_end, log_dt=log_dt) for m in self.members]
+
+    def assimilate(self, gauges, obs, sigma, neff_frac, u0, beta=None):
+        """Filter cycle steps I-V of Sec. 3.3: gauge values, weights, N_eff, resampling, replacement."""
+        y = gauge_values(self.members, gauges)
+        lw, neff, anc, res = pf(y, obs, sigma, self.logw, neff_frac, u0)
+        self.logw = lw
+        if res:
+            old = [m.copy() for m in self.members]
+            self.members = [old[a].copy() for a in anc]
+            if beta is not None:
+                for j, m in enumerate(self.members):
+                    m.mu = m.mu * float(beta[j])
+        return neff, anc, res
+
+
+def loss(model: Model, mem: Member, t_end, sample_dt, gauges, obs, replay=None) -> float:
+    g = np.ascontiguousarray(np.asarray(gauges, dtype=np.int32).reshape(-1, 2))
+    obs = _f64(obs)
+    K = g.shape[0]
+    cm = mem._c()
+    out = C.c_double(0.0)
+    rdt = rte = None
+    nrep = 0
+    if replay is not None:
+        rdt, rte = _f64(replay[0]), _f64(replay[1])
+        nrep = rdt.size
+    rc = _load().orc_loss(model.ptr, C.byref(cm), float(t_end), float(sample_dt), K, _ip(g), _dp(obs),
+                          _dp(rdt), _dp(rte), nrep, C.byref(out))
+    if rc:
+        raise ValueError("orc_loss failed: %d" % rc)
+    mem._back(cm)
+    return out.value
+
+
+def adjoint(model: Model, mem: Member, t_end, sample_dt, gauges, obs, ckpt_every=100):
+    """(loss, grad_n [ny,nx], grad_mu, (dt seq, end-time seq)) of one member."""
+    g = np.ascontiguousarray(np.asarray(gauges, dtype=np.int32).reshape(-1, 2))
+    obs = _f64(obs)
+    K = g.shape[0]
+    cm = mem._c()
+    L = C.c_double(0.0)
+    gmu = C.c_double(0.0)
+    gn = np.zeros((model.ny, model.nx))
+    cap = 1 << 20
+    dts = np.zeros(cap)
+    tes = np.zeros(cap)
+    ns = C.c_int64(0)
+    rc = _load().orc_adjoint(model.ptr, C.byref(cm), float(t_end), float(sample_dt), K, _ip(g), _dp(obs),
+                             int(ckpt_every), C.byref(L), _dp(gn), C.byref(gmu), _dp(dts), _dp(tes), cap,
+                             C.byref(ns))
+    if rc:
+        raise ValueError("orc_adjoint failed: %d" % rc)
+    mem._back(cm)
+    n = ns.value
+    return L.value, gn, gmu.value, (dts[:n].copy(), tes[:n].copy())
+
+
+def adj_step(model: Model, mem: Member, dt, lh, lqx, lqy):
+    """Reverse one step of length dt from mem's state; returns (lh, lqx, lqy, grad_n, grad_mu)."""
+    lh, lqx, lqy = _f64(lh).copy(), _f64(lqx).copy(), _f64(lqy).copy()
+    gn = np.zeros((model.ny, model.nx))
+    gmu = C.c_double(0.0)
+    rc = _load().orc_adj_step(model.ptr, float(mem.s), float(mem.mu), _dp(mem.h), _dp(mem.qx), _dp(mem.qy),
+                              float(dt), float(mem.t), _dp(lh), _dp(lqx), _dp(lqy), _dp(gn), C.byref(gmu))
+    if rc:
+        raise ValueError("orc_adj_step failed: %d" % rc)
+    return lh, lqx, lqy, gn, gmu.value
