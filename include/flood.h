@@ -1,0 +1,210 @@
+/*
+ * flood.h - C ABI of the MI355X ensemble local-inertial flood library.
+ *
+ * The library advances an ensemble of storage-cell flood models (paper Sec.
+ * 2.1, Eqs. 1-5) over one or more catchments on one AMD Instinct MI355X
+ * (gfx950), assimilates gauge observations with a particle filter (Sec. 2.2,
+ * Eqs. 6-12, and the five-step cycle of Sec. 3.3) and differentiates a
+ * gauge-misfit loss with respect to the Manning field and the per-member rain
+ * multipliers by a hand-written discrete adjoint.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Cells are row-major [r][c], r = 0 is the north edge, cell size dx = dy.
+ * - Host-facing discharge layouts: QX is ny x (nx+1), column c the link
+ *   between cells (r,c-1) and (r,c) (column 0 = west edge, nx = east edge);
+ *   QY is (ny+1) x nx, row r the link between (r-1,c) and (r,c).  Positive
+ *   discharge points toward +c / +r; units m^2/s (per unit width).
+ * - Edges are indexed N=0, E=1, S=2, W=3.
+ * - Every pointer argument is caller-owned and read (or written) during the
+ *   call only; the library keeps no reference to it.  The handle owns all
+ *   device memory it allocates.
+ * - Work is enqueued on the HIP stream given at creation.  Calls that return
+ *   host data synchronise that stream; the others return after enqueueing,
+ *   except flood_step, which polls a small device counter to know when every
+ *   member has reached its end time.
+ * - Functions return FLOOD_OK (0) or a negative status.  Nothing throws
+ *   across the ABI.  Arguments are validated before any HIP call, so a
+ *   rejected call leaves the handle unchanged.  flood_last_error() gives a
+ *   human-readable reason.
+ * - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef FLOOD_H
+#define FLOOD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t flood_status;
+#define FLOOD_OK 0
+#define FLOOD_EINVAL (-1)   /* bad argument; nothing was done */
+#define FLOOD_ENOMEM (-2)   /* device or pinned host allocation failed */
+#define FLOOD_EHIP (-3)     /* a HIP runtime call failed (no device, launch error) */
+#define FLOOD_ESTATE (-4)   /* call not valid in the handle's current state */
+#define FLOOD_ENUMERIC (-5) /* a member produced a non-finite depth; it is frozen */
+
+#define FLOOD_EDGE_WALL 0   /* zero-flux edge (Sec. 4.1 Neumann walls) */
+#define FLOOD_EDGE_OPEN 1   /* free outflow with a fixed outward surface slope */
+
+#define FLOOD_FIELD_H 0
+#define FLOOD_FIELD_QX 1
+#define FLOOD_FIELD_QY 2
+
+#define FLOOD_MAX_CATCHMENTS 8
+#define FLOOD_MAX_MEMBERS 1024 /* per catchment (one workgroup runs the filter) */
+
+/* One catchment's static description (Sec. 4.1: DEM and roughness rasters). */
+typedef struct flood_grid {
+    int32_t ny, nx;            /* cells; 1 <= ny, nx; ny*nx <= 2^28 */
+    double dx;                 /* cell size in metres, > 0 */
+    const float* dem;          /* host [ny*nx] bed elevation, finite */
+    const float* manning_n;    /* host [ny*nx] Manning n (s m^-1/3), finite, > 0 */
+    const float* h0;           /* host [ny*nx] initial depth >= 0, or NULL for a dry start */
+    int32_t edge_kind[4];      /* FLOOD_EDGE_WALL or FLOOD_EDGE_OPEN per edge N,E,S,W */
+    double edge_slope[4];      /* outward water-surface slope of an open edge, > 0 */
+} flood_grid;
+
+/* Forcing and numerics shared by all members of a catchment. */
+typedef struct flood_params {
+    const double* rain_rate;   /* host [n_rain] rain rate in m/s, piecewise constant per block
+                                  (Sec. 3.1 step I refreshes rain every 5 min); zero after the series */
+    int32_t n_rain;            /* >= 0 */
+    double rain_interval;      /* block length in s, > 0 (300 in the paper) */
+    double cfl_alpha;          /* Courant coefficient k of Eq. 4, in (0, 1] */
+    double h_dry;              /* links with flow depth <= h_dry carry no flow, >= 0 */
+    double dt_cap;             /* upper bound on the adaptive step in s, > 0 */
+    double dt_fixed;           /* > 0: use this fixed step instead of Eq. 4 (the paper ran 0.25 s) */
+    double g;                  /* gravity, > 0 (9.81) */
+    int32_t real_bytes;        /* 4: FP32 state and arithmetic, 8: FP64 */
+    int32_t member_interleave; /* 0: autotune; else 1, 2, 4 or 8 members adjacent in the fastest index.
+                                  Must agree across catchments of one handle. */
+    int32_t tile_rows;         /* 0: autotune; else 1, 2, 4 or 8 cell rows per 256-lane tile */
+    int32_t chunks_per_block;  /* 0: autotune; else member chunks processed by one workgroup */
+} flood_params;
+
+typedef struct flood_handle flood_handle;
+
+/* Create a handle for one catchment with n_members members (Eq. 6: each
+ * member evolves under its own parameters).  n_scale[i] multiplies the shared
+ * Manning field for member i and rain_mult[i] its rain series (Sec. 4.1 treats
+ * roughness and precipitation as the uncertain inputs); either may be NULL
+ * (all ones).  hip_stream may be NULL (the default stream).  All members start
+ * at t = 0 with equal log-weights -log N (Eq. 7).
+ * Errors: EINVAL (validation), ENOMEM, EHIP.  *out is NULL on failure. */
+flood_status flood_create(const flood_grid* grid, const flood_params* params, int32_t n_members,
+                          const double* n_scale, const double* rain_mult, void* hip_stream,
+                          flood_handle** out);
+
+/* Create one handle holding n_catch catchments of possibly different sizes
+ * (members_per_catch[i] members each).  Every step advances all of them in
+ * one batched launch.  n_scale[i] / rain_mult[i] point to per-catchment
+ * arrays or are NULL.  params[i].member_interleave must be equal for all i. */
+flood_status flood_create_batch(int32_t n_catch, const flood_grid* grids, const flood_params* params,
+                                const int32_t* members_per_catch, const double* const* n_scale,
+                                const double* const* rain_mult, void* hip_stream, flood_handle** out);
+
+/* Advance every member of every catchment to time t_end (s).  Each member
+ * takes Eq. 4 steps computed from its own maximum depth (or the fixed step),
+ * clipped so that a step ends exactly on every rain-block edge and on t_end.
+ * Members already at or beyond t_end are left unchanged.
+ * Errors: EINVAL (t_end not finite), ESTATE (handle faulted), ENUMERIC (a
+ * member produced a non-finite depth; it stays frozen and the others still
+ * reach t_end), EHIP. */
+flood_status flood_step(flood_handle* h, double t_end);
+
+/* Particle-filter cycle of Sec. 3.3 on one catchment whose members are all at
+ * the same time: (I) gauge depths y_ik = h_i(gauge_k), (II) weights
+ * w_i ~ w_i^- exp(-1/2 sum_k ((y_ik - d_k)/sigma_k)^2) (Eqs. 9-11, computed in
+ * log space), (III) N_eff = 1/sum w_i^2 (Eq. 12); if N_eff < neff_frac * N,
+ * (IV) systematic resampling with offset u0 in [0,1) and (V) replacement of
+ * every member by a copy of its ancestor, followed by rain_mult_i *= beta_i
+ * (Sec. 4.4 perturbation).  After resampling every log-weight is -log N.
+ *   gauge_rc  host [2*n_gauges] (row, col) pairs inside the grid
+ *   obs       host [n_gauges] observed depths d_k
+ *   sigma     host [n_gauges] observation standard deviations, > 0
+ *   beta      host [N] or NULL (no perturbation)
+ *   neff_out, ancestors_out [N], resampled_out: host outputs, each may be NULL
+ * Errors: EINVAL, ESTATE (members not at a common time, or faulted), EHIP. */
+flood_status flood_assimilate(flood_handle* h, int32_t catchment, int32_t n_gauges, const int32_t* gauge_rc,
+                              const double* obs, const double* sigma, double neff_frac, double u0,
+                              const double* beta, double* neff_out, int32_t* ancestors_out,
+                              int32_t* resampled_out);
+
+/* Gradient of the gauge-misfit loss
+ *   L = sum_members sum_{s=1..S} sum_k (h_m(g_k, t0 + s*sample_dt) - obs[s-1][k])^2,
+ * S = floor((t_end - t0)/sample_dt), over the members of one catchment that
+ * are all at time t0, with respect to the catchment's shared Manning field
+ * (grad_n_out, host [ny*nx]) and each member's rain multiplier
+ * (grad_mult_out, host [N]).  The forward run records its step lengths and
+ * stores a checkpoint every ckpt_every steps; the reverse sweep recomputes
+ * each segment into a tape and applies the discrete adjoint of the step with
+ * those step lengths and the forward's wet/dry, limiter and clamp branches
+ * held fixed.  On return the members are at the last sample time.
+ *   obs host [S*n_gauges]; loss_out, grad_n_out, grad_mult_out may be NULL.
+ * Errors: EINVAL, ENOMEM (tape does not fit), ESTATE, ENUMERIC, EHIP. */
+flood_status flood_adjoint(flood_handle* h, int32_t catchment, double t_end, double sample_dt,
+                           int32_t n_gauges, const int32_t* gauge_rc, const double* obs, int32_t ckpt_every,
+                           double* loss_out, double* grad_n_out, double* grad_mult_out);
+
+/* Copy one member's field to host memory in the host layout described above
+ * (H: ny*nx, QX: ny*(nx+1), QY: (ny+1)*nx), converted to double. */
+flood_status flood_get_field(flood_handle* h, int32_t catchment, int32_t member, int32_t which,
+                             double* host_out);
+
+/* Overwrite one member's state (h: ny*nx, qx: ny*(nx+1), qy: (ny+1)*nx, all
+ * host doubles, rounded to the handle's precision) and its time t.  Depths
+ * must be >= 0 and finite.  Wall links must be zero. */
+flood_status flood_set_state(flood_handle* h, int32_t catchment, int32_t member, const double* hh,
+                             const double* qx, const double* qy, double t);
+
+/* Replace the shared Manning field (host [ny*nx], > 0) and, when non-NULL,
+ * the per-member scales and rain multipliers (host [N]) of one catchment. */
+flood_status flood_set_params(flood_handle* h, int32_t catchment, const float* manning_n,
+                              const double* n_scale, const double* rain_mult);
+
+/* Mass ledger of one catchment, each output host [N] or NULL:
+ * storage = sum h dx^2, rain_in = total rain volume added, outflow = volume
+ * that left through open edges, clamp = volume added by clamping negative
+ * depths to zero; t = member times; steps = steps taken.  Invariant:
+ * storage - storage(t=0) = rain_in - outflow + clamp. */
+flood_status flood_get_ledger(flood_handle* h, int32_t catchment, double* storage, double* rain_in,
+                              double* outflow, double* clamp, double* t, int64_t* steps);
+
+/* Current log-weights (host [N]) and per-member rain multipliers / n scales. */
+flood_status flood_get_weights(flood_handle* h, int32_t catchment, double* logw, double* rain_mult,
+                               double* n_scale);
+
+/* Stateless systematic resampling on the device: ancestors of n particles
+ * with weights w (host [n], >= 0, positive sum) and offset u0 in [0,1),
+ * using the same kernel as flood_assimilate.  anc_out host [n]. */
+flood_status flood_systematic_resample(const double* w, int32_t n, double u0, int32_t* anc_out,
+                                       void* hip_stream);
+
+/* Snapshot / restore of every member's state, time, weights, parameters and
+ * ledger to a file (portable only between handles of identical shape). */
+flood_status flood_save(flood_handle* h, const char* path);
+flood_status flood_load(flood_handle* h, const char* path);
+
+/* Kernel configuration in use: member interleave, tile rows and chunks per
+ * workgroup of catchment 0, and the number of steps captured per graph. */
+flood_status flood_get_config(const flood_handle* h, int32_t* member_interleave, int32_t* tile_rows,
+                              int32_t* chunks_per_block, int32_t* graph_steps);
+
+/* Average duration in ms of the step kernel over the timed region opened by
+ * flood_timing(h, 1) and closed by flood_timing(h, 0); per-launch HIP events
+ * on the handle's stream.  *launches receives the number of step launches. */
+flood_status flood_timing(flood_handle* h, int32_t enable);
+flood_status flood_get_timing(const flood_handle* h, double* avg_step_kernel_ms, int64_t* launches);
+
+const char* flood_last_error(const flood_handle* h); /* NULL h: last creation error of this thread */
+const char* flood_strerror(flood_status s);
+void flood_destroy(flood_handle* h); /* NULL-safe; synchronises the stream */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLOOD_H */

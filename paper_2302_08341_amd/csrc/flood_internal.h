@@ -1,0 +1,161 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// libflood.  Device memory layout (one catchment, MI = member interleave):
+//
+//   state  X[chunk][r][c][mi]   X in {h, qx, qy}, chunk = member / MI,
+//          qx[..][r][c] is the east link of cell (r,c) (c = nx-1: east edge),
+//          qy[..][r][c] is the south link of cell (r,c) (r = ny-1: south edge)
+//   strips qw[chunk][r][mi] (west edge links), qn[chunk][c][mi] (north edge)
+//   two copies of every state array; member m's current copy is par[m]
+//   shared z[r][c], n[r][c] (one copy for all members, Sec. 3.2)
+//
+// Members in the same chunk occupy adjacent addresses, so a wavefront reads
+// 64/MI cells x MI members contiguously, and the shared per-cell arrays are
+// read once per MI members.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace flood {
+
+constexpr int kMaxCatch = 8;
+constexpr int kBins = 64;      // partial-max bins per member for the depth maximum
+constexpr int kBlock = 256;    // lanes per workgroup of the step kernels
+constexpr int kMaxMembers = 1024;
+
+template <typename T> struct HBits;
+template <> struct HBits<float> { using type = uint32_t; };
+template <> struct HBits<double> { using type = unsigned long long; };
+
+// Per-member coefficients of one step, written by the step planner.
+template <typename T> struct MemberStep {
+    T dtdx;    // dt / dx
+    T gdtdx;   // g dt / dx
+    T gdt;     // g dt
+    T s2dt;    // (Manning scale)^2 dt
+    T capf;    // dx / (4 dt): donor-limiter factor
+    T rinc;    // rain depth of this step, mu R dt
+    double dxdt;  // dx dt (outflow volume per unit discharge)
+    int32_t active;
+    int32_t parity;  // state copy holding the state before this step
+};
+
+template <typename T> struct CatchDev {
+    int32_t ny, nx, n_members, n_chunks;
+    int32_t tx_log2;          // log2(tile width in cells)
+    int32_t tiles_x, tiles_y;
+    int32_t groups;           // member-chunk groups per tile
+    int32_t chunks_per_group;
+    int32_t member_off;       // first global member index of this catchment
+    int32_t block_begin;      // first linear workgroup of this catchment in a launch
+    int32_t n_blocks;
+    int32_t edge_open[4];
+    T edge_slope[4];
+    T hdry, g;
+    double dx;
+    T* h[2];
+    T* qx[2];
+    T* qy[2];
+    T* qw[2];
+    T* qn[2];
+    const T* z;
+    const T* n;
+    double* out_acc;          // [n_members][2*(nx+ny)] outflow volume per edge link (N, S, W, E)
+};
+
+template <typename T> struct StepLaunch {
+    int32_t n_catch;
+    int32_t total_blocks;
+    int32_t n_total;          // members over all catchments
+    CatchDev<T> c[kMaxCatch];
+    const MemberStep<T>* ms;  // [n_total]
+    typename HBits<T>::type* hbins;  // [kBins][n_total]
+    double* vclamp;           // [n_total]
+};
+
+struct PlanCatch {
+    int32_t member_off, n_members;
+    int32_t n_rain;
+    const double* rain;
+    double rain_interval, alpha, hdry, dt_cap, dt_fixed, g, dx;
+    double ncells;
+};
+
+template <typename T> struct PlanLaunch {
+    int32_t n_catch, n_total;
+    PlanCatch c[kMaxCatch];
+    const double* t_end;      // device scalar
+    double* t;
+    const double* s;
+    const double* mu;
+    int32_t* par;
+    int64_t* steps;
+    int32_t* fault;
+    int32_t* status;          // bit 0: non-finite depth seen
+    double* vrain;
+    typename HBits<T>::type* hbins;
+    MemberStep<T>* ms;
+    double* dtlog;            // optional [n_total][dtlog_cap] step lengths (adjoint record)
+    double* telog;            // optional [n_total][dtlog_cap] step end times
+    int32_t dtlog_cap;
+};
+
+// ---------------------------------------------------------------------------
+// launchers (flood_kernels.hip)
+// ---------------------------------------------------------------------------
+template <typename T> void launch_plan(const PlanLaunch<T>& P, hipStream_t s);
+template <typename T, int MI> void launch_step(const StepLaunch<T>& L, hipStream_t s);
+template <typename T> void launch_step_mi(int mi, const StepLaunch<T>& L, hipStream_t s);
+void launch_count_active(int n_total, const double* t, const int32_t* fault, const double* t_end,
+                         const int32_t* status, int32_t* out, hipStream_t s);
+template <typename HB> void launch_zero_bins(int off, int n, int n_total, HB* bins, hipStream_t s);
+template <typename HB>
+void launch_permute_bins(int off, int n, int n_total, HB* bins, const int32_t* anc, const int32_t* flag,
+                         hipStream_t s);
+template <typename T>
+void launch_hmax_init(int mi, const CatchDev<T>& C, const int32_t* par, typename HBits<T>::type* hbins,
+                      int n_total, hipStream_t s);
+template <typename T>
+void launch_storage(int mi, const CatchDev<T>& C, const int32_t* par, double* out, hipStream_t s);
+template <typename T>
+void launch_get_field(int mi, const CatchDev<T>& C, int member, int par, int which, double* out,
+                      hipStream_t s);
+template <typename T>
+void launch_set_field(int mi, const CatchDev<T>& C, int member, int par, int which, const double* in,
+                      hipStream_t s);
+template <typename T>
+void launch_gauges(int mi, const CatchDev<T>& C, const int32_t* par, int n_gauges, const int32_t* grc,
+                   double* y, hipStream_t s);
+void launch_flush_outflow(int n_members, int nb, double* out_acc, double* vout, hipStream_t s);
+
+// particle filter (flood_pf.hip)
+struct PfArgs {
+    int32_t N, K;
+    const double* y;          // [N*K]
+    const double* d;          // [K]
+    const double* sigma;      // [K]
+    double neff_frac, u0;
+    const double* beta;       // [N] or null
+    double* logw;             // [N] in/out
+    double* t;                // member scalars permuted on resampling
+    double* s;
+    double* mu;
+    double* vrain;
+    double* vout;
+    double* vclamp;
+    int64_t* steps;
+    int32_t* par;
+    int32_t* src_par;         // [N] out: copy-from parity of each slot's ancestor
+    int32_t* dst_par;         // [N] out: copy-to parity of each slot
+    int32_t* anc;             // [N] out
+    double* neff;             // [1] out
+    int32_t* flag;            // [1] out: 1 if resampled
+};
+void launch_pf(const PfArgs& a, hipStream_t s);
+void launch_systematic(int n, const double* w, double u0, int32_t* anc, hipStream_t s);
+template <typename T>
+void launch_permute(int mi, const CatchDev<T>& C, const int32_t* anc, const int32_t* src_par,
+                    const int32_t* dst_par, const int32_t* flag, hipStream_t s);
+
+}  // namespace flood

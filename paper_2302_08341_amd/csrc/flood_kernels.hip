@@ -1,0 +1,581 @@
+// Forward kernels of libflood for gfx950: step planner, fused link + continuity
+// step with the per-member depth maximum, and state utilities.
+//
+// The step is memory-bound (about 60 flops per 24 bytes per member-cell), so it
+// uses plain vector ALU work with coalesced structure-of-arrays streams and no
+// matrix cores.  All kernels are compiled with FP contraction off, so every
+// link is evaluated with the same rounding wherever it is computed (a link
+// shared by two cells is computed by both, identically).
+#include <cfloat>
+#include <cmath>
+
+#include "flood_internal.h"
+
+namespace flood {
+
+// Workgroups are dispatched round-robin over the 8 XCDs (id % 8).  Remap the
+// id so that each XCD walks a contiguous range of logical tiles; vertically
+// adjacent tiles then meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, i = b >> 3;
+    return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+__device__ __forceinline__ uint32_t to_bits(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ unsigned long long to_bits(double v) {
+    return (unsigned long long)__double_as_longlong(v);
+}
+template <typename T> __device__ __forceinline__ T from_bits(typename HBits<T>::type b);
+template <> __device__ __forceinline__ float from_bits<float>(uint32_t b) { return __uint_as_float(b); }
+template <> __device__ __forceinline__ double from_bits<double>(unsigned long long b) {
+    return __longlong_as_double((long long)b);
+}
+
+// h^(-7/3) of the friction denominator of Eq. 2.
+__device__ __forceinline__ float pow_m73(float h) {
+    return __builtin_amdgcn_exp2f(-2.33333333333333333f * __builtin_amdgcn_logf(h));
+}
+__device__ __forceinline__ double pow_m73(double h) { return 1.0 / pow(h, 7.0 / 3.0); }
+
+__device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
+
+// Interior link between cell 1 (west/north) and cell 2 (east/south).
+// Eq. 3 in difference form: with dz = z2 - z1, the higher surface is cell 1
+// iff h1 - h2 >= dz, and max(eta) - max(z) = h_up - max(+-dz, 0); the surface
+// slope is (h2 - h1 + dz)/dx.  Eq. 2 semi-implicit friction, then the donor
+// limiter |q| <= h_up dx / (4 dt).
+template <typename T>
+__device__ __forceinline__ T link_in(T q, T h1, T h2, T dz, T G, const MemberStep<T>& ms, T hdry) {
+    const T d = h1 - h2;
+    const T hf = (d >= dz) ? h1 - fmax(dz, T(0)) : h2 - fmax(-dz, T(0));
+    if (!(hf > hdry)) return T(0);
+    const T num = q - ms.gdtdx * hf * (dz - d);
+    const T A = G * ms.s2dt * pow_m73(hf);
+    T qn = qdiv(num, T(1) + A * fabs(q));
+    if (qn > T(0))
+        qn = fmin(qn, h1 * ms.capf);
+    else
+        qn = fmax(qn, -h2 * ms.capf);
+    return qn;
+}
+
+// Open edge link: outward discharge qo driven by the fixed outward slope Se,
+// flow depth = inner cell depth; outflow only.
+template <typename T>
+__device__ __forceinline__ T link_open(T qo, T h, T G, T Se, const MemberStep<T>& ms, T hdry) {
+    if (!(h > hdry)) return T(0);
+    const T A = G * ms.s2dt * pow_m73(h);
+    T qn = qdiv(qo + ms.gdt * h * Se, T(1) + A * fabs(qo));
+    qn = fmin(qn, h * ms.capf);
+    return fmax(qn, T(0));
+}
+
+// ---------------------------------------------------------------------------
+// step planner: per-member Eq. 4 step, clipped to rain-block edges and t_end
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
+    using HB = typename HBits<T>::type;
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= P.n_total) return;
+    int ci = 0;
+    for (int i = 1; i < P.n_catch; ++i)
+        if (m >= P.c[i].member_off) ci = i;
+    const PlanCatch& C = P.c[ci];
+    MemberStep<T> ms;
+    ms.dtdx = ms.gdtdx = ms.gdt = ms.s2dt = ms.capf = ms.rinc = T(0);
+    ms.dxdt = 0.0;
+    ms.active = 0;
+    ms.parity = P.par[m];
+    const double t = P.t[m];
+    const double t_end = *P.t_end;
+    if (P.fault[m] || !(t < t_end)) {
+        P.ms[m] = ms;
+        return;
+    }
+    HB hb = 0;
+    for (int k = 0; k < kBins; ++k) {
+        const HB v = P.hbins[(size_t)k * P.n_total + m];
+        hb = v > hb ? v : hb;
+    }
+    const T H = from_bits<T>(hb);
+    if (!(H <= (sizeof(T) == 4 ? T(FLT_MAX) : T(DBL_MAX)))) {
+        P.fault[m] = 1;
+        atomicOr(P.status, 1);
+        P.ms[m] = ms;
+        return;
+    }
+    double dt;
+    if (C.dt_fixed > 0.0) {
+        dt = C.dt_fixed;
+    } else {
+        double Hd = (double)H;
+        if (Hd < C.hdry) Hd = C.hdry;
+        dt = C.alpha * C.dx / sqrt(C.g * Hd);
+        if (dt > C.dt_cap) dt = C.dt_cap;
+    }
+    const double jf = floor(t / C.rain_interval);
+    const double R = (jf >= 0.0 && jf < (double)C.n_rain) ? C.rain[(int64_t)jf] : 0.0;
+    const double edge = (jf + 1.0 > (double)C.n_rain) ? INFINITY : (jf + 1.0) * C.rain_interval;
+    const double tev = t_end < edge ? t_end : edge;
+    double tn;
+    if (dt >= tev - t) {
+        dt = tev - t;
+        tn = tev;
+    } else {
+        tn = t + dt;
+    }
+    const double s = P.s[m];
+    ms.dtdx = (T)(dt / C.dx);
+    ms.gdtdx = (T)(C.g * dt / C.dx);
+    ms.gdt = (T)(C.g * dt);
+    ms.s2dt = (T)(s * s * dt);
+    ms.capf = (T)(C.dx / (4.0 * dt));
+    ms.rinc = (T)(P.mu[m] * R * dt);
+    ms.dxdt = C.dx * dt;
+    ms.active = 1;
+    P.ms[m] = ms;
+    const int64_t st = P.steps[m];
+    if (P.dtlog && st < P.dtlog_cap) {
+        P.dtlog[(size_t)m * P.dtlog_cap + st] = dt;
+        P.telog[(size_t)m * P.dtlog_cap + st] = tn;
+    }
+    P.t[m] = tn;
+    P.par[m] = ms.parity ^ 1;
+    P.steps[m] = st + 1;
+    P.vrain[m] += (double)ms.rinc * C.ncells * (C.dx * C.dx);
+    for (int k = 0; k < kBins; ++k) P.hbins[(size_t)k * P.n_total + m] = 0;
+}
+
+template <typename T> void launch_plan(const PlanLaunch<T>& P, hipStream_t s) {
+    hipLaunchKernelGGL(k_plan<T>, dim3((P.n_total + 255) / 256), dim3(256), 0, s, P);
+}
+
+// ---------------------------------------------------------------------------
+// fused step: every link around a cell from (h^n, q^n), continuity with the
+// new discharges and the rain depth, per-member maximum of the new depth.
+// One lane per (cell, member-in-chunk); a workgroup covers a tile of cells for
+// `chunks_per_group` consecutive member chunks, reusing the shared bed and
+// roughness of its cells from registers.
+// ---------------------------------------------------------------------------
+template <typename T, int MI>
+__global__ __launch_bounds__(kBlock) void k_step(const StepLaunch<T> L) {
+    using HB = typename HBits<T>::type;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    int ci = 0;
+    for (int i = 1; i < L.n_catch; ++i)
+        if (b >= L.c[i].block_begin) ci = i;
+    const CatchDev<T>& C = L.c[ci];
+    const int lb = b - C.block_begin;
+    const int grp = lb % C.groups;
+    const int tile = lb / C.groups;
+    const int tyi = tile / C.tiles_x;
+    const int txi = tile - tyi * C.tiles_x;
+    const int txl = C.tx_log2;
+    const int lane = threadIdx.x % MI;
+    const int p = threadIdx.x / MI;
+    const int TY = (kBlock / MI) >> txl;
+    const int nx = C.nx, ny = C.ny;
+    const int cx = (txi << txl) + (p & ((1 << txl) - 1));
+    const int cy = tyi * TY + (p >> txl);
+    const bool in = cx < nx && cy < ny;
+    const int k0 = grp * C.chunks_per_group;
+    const int k1 = min(k0 + C.chunks_per_group, C.n_chunks);
+    const int mend = min(k1 * MI, C.n_members);
+    int any = 0;
+    for (int m = k0 * MI + (int)threadIdx.x; m < mend; m += kBlock) any |= L.ms[C.member_off + m].active;
+    if (!__syncthreads_or(any)) return;
+
+    // shared bed and roughness of this cell and its four neighbours
+    const bool hasE = cx + 1 < nx, hasW = cx > 0, hasS = cy + 1 < ny, hasN = cy > 0;
+    const T g = C.g;
+    T dzE = 0, dzW = 0, dzS = 0, dzN = 0, GE = 0, GW = 0, GS = 0, GN = 0;
+    if (in) {
+        const size_t c0 = (size_t)cy * nx + cx;
+        const T z0 = C.z[c0], n0 = C.n[c0];
+        const T gb = g * (n0 * n0);
+        if (hasE) {
+            const T z1 = C.z[c0 + 1], n1 = C.n[c0 + 1];
+            const T nf = T(0.5) * (n0 + n1);
+            dzE = z1 - z0;
+            GE = g * (nf * nf);
+        } else {
+            GE = gb;
+        }
+        if (hasW) {
+            const T z1 = C.z[c0 - 1], n1 = C.n[c0 - 1];
+            const T nf = T(0.5) * (n1 + n0);
+            dzW = z0 - z1;
+            GW = g * (nf * nf);
+        } else {
+            GW = gb;
+        }
+        if (hasS) {
+            const T z1 = C.z[c0 + nx], n1 = C.n[c0 + nx];
+            const T nf = T(0.5) * (n0 + n1);
+            dzS = z1 - z0;
+            GS = g * (nf * nf);
+        } else {
+            GS = gb;
+        }
+        if (hasN) {
+            const T z1 = C.z[c0 - nx], n1 = C.n[c0 - nx];
+            const T nf = T(0.5) * (n1 + n0);
+            dzN = z0 - z1;
+            GN = g * (nf * nf);
+        } else {
+            GN = gb;
+        }
+    }
+    const T hdry = C.hdry;
+    const int nb = 2 * (nx + ny);
+    const int bin = blockIdx.x & (kBins - 1);
+    const size_t plane = (size_t)ny * nx * MI;
+    const size_t rowMI = (size_t)nx * MI;
+
+    for (int k = k0; k < k1; ++k) {
+        const int ml = k * MI + lane;
+        MemberStep<T> ms;
+        bool act = false;
+        if (ml < C.n_members) {
+            ms = L.ms[C.member_off + ml];
+            act = in && ms.active;
+        }
+        T hn = T(0);
+        if (act) {
+            const int sp = ms.parity, dp = sp ^ 1;
+            const T* __restrict__ hs = C.h[sp];
+            const T* __restrict__ qxs = C.qx[sp];
+            const T* __restrict__ qys = C.qy[sp];
+            const size_t idx = (size_t)k * plane + ((size_t)cy * nx + cx) * MI + lane;
+            const T h0 = hs[idx];
+            const T hE = hasE ? hs[idx + MI] : T(0);
+            const T hW = hasW ? hs[idx - MI] : T(0);
+            const T hS = hasS ? hs[idx + rowMI] : T(0);
+            const T hN = hasN ? hs[idx - rowMI] : T(0);
+            const T qE = qxs[idx];
+            const T qS = qys[idx];
+            const T qW = hasW ? qxs[idx - MI] : C.qw[sp][((size_t)k * ny + cy) * MI + lane];
+            const T qN = hasN ? qys[idx - rowMI] : C.qn[sp][((size_t)k * nx + cx) * MI + lane];
+            T fE, fS, fW, fN;
+            if (hasE)
+                fE = link_in(qE, h0, hE, dzE, GE, ms, hdry);
+            else
+                fE = C.edge_open[1] ? link_open(qE, h0, GE, C.edge_slope[1], ms, hdry) : T(0);
+            if (hasS)
+                fS = link_in(qS, h0, hS, dzS, GS, ms, hdry);
+            else
+                fS = C.edge_open[2] ? link_open(qS, h0, GS, C.edge_slope[2], ms, hdry) : T(0);
+            if (hasW)
+                fW = link_in(qW, hW, h0, dzW, GW, ms, hdry);
+            else
+                fW = C.edge_open[3] ? -link_open(-qW, h0, GW, C.edge_slope[3], ms, hdry) : T(0);
+            if (hasN)
+                fN = link_in(qN, hN, h0, dzN, GN, ms, hdry);
+            else
+                fN = C.edge_open[0] ? -link_open(-qN, h0, GN, C.edge_slope[0], ms, hdry) : T(0);
+            // Eq. 1 with the four links of Sec. 3.1 (west/east x-links, north/south y-links)
+            const T dv = ((fW - fE) + fN) - fS;
+            hn = (h0 + ms.dtdx * dv) + ms.rinc;
+            if (hn < T(0)) {
+                atomicAdd(&L.vclamp[C.member_off + ml], -(double)hn * (C.dx * C.dx));
+                hn = T(0);
+            }
+            if (hn == T(0)) hn = T(0);  // canonical +0 for the bit-pattern maximum
+            C.h[dp][idx] = hn;
+            C.qx[dp][idx] = fE;
+            C.qy[dp][idx] = fS;
+            if (!hasW) C.qw[dp][((size_t)k * ny + cy) * MI + lane] = fW;
+            if (!hasN) C.qn[dp][((size_t)k * nx + cx) * MI + lane] = fN;
+            if (!(hasE && hasW && hasS && hasN)) {
+                double* acc = C.out_acc + (size_t)ml * nb;
+                if (!hasN && C.edge_open[0]) acc[cx] += -(double)fN * ms.dxdt;
+                if (!hasS && C.edge_open[2]) acc[nx + cx] += (double)fS * ms.dxdt;
+                if (!hasW && C.edge_open[3]) acc[2 * nx + cy] += -(double)fW * ms.dxdt;
+                if (!hasE && C.edge_open[1]) acc[2 * nx + ny + cy] += (double)fE * ms.dxdt;
+            }
+        }
+        // depth maximum per member over the wavefront, on the IEEE bit pattern
+        // (depths are >= 0, and a NaN or Inf compares above every finite depth)
+        HB v = to_bits(hn);
+#pragma unroll
+        for (int off = MI; off < 64; off <<= 1) {
+            const HB o = __shfl_xor(v, off, 64);
+            v = o > v ? o : v;
+        }
+        if ((threadIdx.x & 63) < MI && ml < C.n_members && v != 0) {
+            HB* a = L.hbins + (size_t)bin * L.n_total + C.member_off + ml;
+            const HB cur = __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (v > cur) atomicMax(a, v);
+        }
+    }
+}
+
+template <typename T, int MI> void launch_step(const StepLaunch<T>& L, hipStream_t s) {
+    hipLaunchKernelGGL((k_step<T, MI>), dim3(L.total_blocks), dim3(kBlock), 0, s, L);
+}
+
+template <typename T> void launch_step_mi(int mi, const StepLaunch<T>& L, hipStream_t s) {
+    switch (mi) {
+        case 1: launch_step<T, 1>(L, s); break;
+        case 2: launch_step<T, 2>(L, s); break;
+        case 4: launch_step<T, 4>(L, s); break;
+        default: launch_step<T, 8>(L, s); break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// members still short of t_end
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_count_active(int n, const double* t, const int32_t* fault,
+                                                      const double* t_end, const int32_t* status, int32_t* out) {
+    __shared__ int part[4];
+    int c = 0;
+    const double te = *t_end;
+    for (int m = threadIdx.x; m < n; m += 256) c += (!fault[m] && t[m] < te) ? 1 : 0;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = part[0] + part[1] + part[2] + part[3];
+        out[1] = status[0];
+    }
+}
+
+void launch_count_active(int n_total, const double* t, const int32_t* fault, const double* t_end,
+                         const int32_t* status, int32_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(256), 0, s, n_total, t, fault, t_end, status, out);
+}
+
+template <typename HB> __global__ __launch_bounds__(256) void k_zero_bins(int off, int n, int n_total, HB* bins) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * kBins) return;
+    bins[(size_t)(e / n) * n_total + off + e % n] = 0;
+}
+
+template <typename HB> void launch_zero_bins(int off, int n, int n_total, HB* bins, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_bins<HB>, dim3((n * kBins + 255) / 256), dim3(256), 0, s, off, n, n_total, bins);
+}
+
+// After resampling slot j holds a copy of member anc[j]: its depth maximum follows.
+template <typename HB>
+__global__ __launch_bounds__(1024) void k_permute_bins(int off, int n, int n_total, HB* bins, const int32_t* anc,
+                                                       const int32_t* flag) {
+    if (flag[0] == 0) return;
+    const int j = threadIdx.x;
+    HB v = 0;
+    if (j < n) {
+        const int a = anc[j];
+        for (int b = 0; b < kBins; ++b) {
+            const HB x = bins[(size_t)b * n_total + off + a];
+            v = x > v ? x : v;
+        }
+    }
+    __syncthreads();
+    if (j < n)
+        for (int b = 0; b < kBins; ++b) bins[(size_t)b * n_total + off + j] = b == 0 ? v : HB(0);
+}
+
+template <typename HB>
+void launch_permute_bins(int off, int n, int n_total, HB* bins, const int32_t* anc, const int32_t* flag,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_permute_bins<HB>, dim3(1), dim3(((n + 63) / 64) * 64), 0, s, off, n, n_total, bins, anc,
+                       flag);
+}
+
+template void launch_zero_bins<uint32_t>(int, int, int, uint32_t*, hipStream_t);
+template void launch_zero_bins<unsigned long long>(int, int, int, unsigned long long*, hipStream_t);
+template void launch_permute_bins<uint32_t>(int, int, int, uint32_t*, const int32_t*, const int32_t*, hipStream_t);
+template void launch_permute_bins<unsigned long long>(int, int, int, unsigned long long*, const int32_t*,
+                                                      const int32_t*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// element-wise helpers over one catchment: lane = (cell, member)
+// ---------------------------------------------------------------------------
+template <typename T, int MI>
+__device__ __forceinline__ size_t state_index(const CatchDev<T>& C, int member, int r, int c) {
+    return ((size_t)(member / MI) * C.ny + r) * ((size_t)C.nx * MI) + (size_t)c * MI + member % MI;
+}
+
+// Depth maximum of the current state into bin 0 (bins must be zero);
+// blockIdx.y = member.
+template <typename T, int MI>
+__global__ __launch_bounds__(256) void k_hmax_init(const CatchDev<T> C, const int32_t* par,
+                                                   typename HBits<T>::type* hbins, int n_total) {
+    using HB = typename HBits<T>::type;
+    const int m = blockIdx.y;
+    const size_t ncell = (size_t)C.ny * C.nx;
+    const T* h = C.h[par[C.member_off + m]];
+    HB best = 0;
+    for (size_t cell = (size_t)blockIdx.x * blockDim.x + threadIdx.x; cell < ncell;
+         cell += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(cell / C.nx), c = (int)(cell % C.nx);
+        const HB bv = to_bits(h[state_index<T, MI>(C, m, r, c)] + T(0));
+        best = bv > best ? bv : best;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const HB o = __shfl_xor(best, off, 64);
+        best = o > best ? o : best;
+    }
+    if ((threadIdx.x & 63) == 0 && best != 0) atomicMax(hbins + C.member_off + m, best);
+}
+
+template <typename T>
+void launch_hmax_init(int mi, const CatchDev<T>& C, const int32_t* par, typename HBits<T>::type* hbins,
+                      int n_total, hipStream_t s) {
+    const size_t ncell = (size_t)C.ny * C.nx;
+    dim3 grid((unsigned)std::min<size_t>((ncell + 255) / 256, 512), C.n_members);
+    switch (mi) {
+        case 1: hipLaunchKernelGGL((k_hmax_init<T, 1>), grid, dim3(256), 0, s, C, par, hbins, n_total); break;
+        case 2: hipLaunchKernelGGL((k_hmax_init<T, 2>), grid, dim3(256), 0, s, C, par, hbins, n_total); break;
+        case 4: hipLaunchKernelGGL((k_hmax_init<T, 4>), grid, dim3(256), 0, s, C, par, hbins, n_total); break;
+        default: hipLaunchKernelGGL((k_hmax_init<T, 8>), grid, dim3(256), 0, s, C, par, hbins, n_total); break;
+    }
+}
+
+// Storage sum(h) dx^2 per member, added into out[member] (out must be zero).
+template <typename T, int MI>
+__global__ __launch_bounds__(256) void k_storage(const CatchDev<T> C, const int32_t* par, double* out) {
+    const int m = blockIdx.y;
+    const size_t ncell = (size_t)C.ny * C.nx;
+    const T* h = C.h[par[C.member_off + m]];
+    double acc = 0.0;
+    for (size_t cell = (size_t)blockIdx.x * blockDim.x + threadIdx.x; cell < ncell;
+         cell += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(cell / C.nx), c = (int)(cell % C.nx);
+        acc += (double)h[state_index<T, MI>(C, m, r, c)];
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    __shared__ double part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(out + m, ((part[0] + part[1]) + (part[2] + part[3])) * (C.dx * C.dx));
+}
+
+template <typename T>
+void launch_storage(int mi, const CatchDev<T>& C, const int32_t* par, double* out, hipStream_t s) {
+    const size_t ncell = (size_t)C.ny * C.nx;
+    dim3 grid((unsigned)std::min<size_t>((ncell + 255) / 256, 1024), C.n_members);
+    switch (mi) {
+        case 1: hipLaunchKernelGGL((k_storage<T, 1>), grid, dim3(256), 0, s, C, par, out); break;
+        case 2: hipLaunchKernelGGL((k_storage<T, 2>), grid, dim3(256), 0, s, C, par, out); break;
+        case 4: hipLaunchKernelGGL((k_storage<T, 4>), grid, dim3(256), 0, s, C, par, out); break;
+        default: hipLaunchKernelGGL((k_storage<T, 8>), grid, dim3(256), 0, s, C, par, out); break;
+    }
+}
+
+// One member's field in the host layout (H: ny*nx, QX: ny*(nx+1), QY: (ny+1)*nx).
+template <typename T, int MI>
+__global__ __launch_bounds__(256) void k_field(const CatchDev<T> C, int m, int p, int which, double* buf,
+                                               int to_state) {
+    const int ny = C.ny, nx = C.nx;
+    const size_t n = which == 0 ? (size_t)ny * nx : which == 1 ? (size_t)ny * (nx + 1) : (size_t)(ny + 1) * nx;
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int k = m / MI, lane = m % MI;
+    T* ptr;
+    if (which == 0) {
+        ptr = C.h[p] + state_index<T, MI>(C, m, (int)(e / nx), (int)(e % nx));
+    } else if (which == 1) {
+        const int r = (int)(e / (nx + 1)), c = (int)(e % (nx + 1));
+        ptr = (c == 0) ? C.qw[p] + ((size_t)k * ny + r) * MI + lane : C.qx[p] + state_index<T, MI>(C, m, r, c - 1);
+    } else {
+        const int r = (int)(e / nx), c = (int)(e % nx);
+        ptr = (r == 0) ? C.qn[p] + ((size_t)k * nx + c) * MI + lane : C.qy[p] + state_index<T, MI>(C, m, r - 1, c);
+    }
+    if (to_state)
+        *ptr = (T)buf[e] + T(0);
+    else
+        buf[e] = (double)*ptr;
+}
+
+template <typename T>
+static void launch_field(int mi, const CatchDev<T>& C, int member, int par, int which, double* buf, int to_state,
+                         hipStream_t s) {
+    const int ny = C.ny, nx = C.nx;
+    const size_t n = which == 0 ? (size_t)ny * nx : which == 1 ? (size_t)ny * (nx + 1) : (size_t)(ny + 1) * nx;
+    dim3 grid((unsigned)((n + 255) / 256));
+    switch (mi) {
+        case 1: hipLaunchKernelGGL((k_field<T, 1>), grid, dim3(256), 0, s, C, member, par, which, buf, to_state); break;
+        case 2: hipLaunchKernelGGL((k_field<T, 2>), grid, dim3(256), 0, s, C, member, par, which, buf, to_state); break;
+        case 4: hipLaunchKernelGGL((k_field<T, 4>), grid, dim3(256), 0, s, C, member, par, which, buf, to_state); break;
+        default: hipLaunchKernelGGL((k_field<T, 8>), grid, dim3(256), 0, s, C, member, par, which, buf, to_state); break;
+    }
+}
+
+template <typename T>
+void launch_get_field(int mi, const CatchDev<T>& C, int member, int par, int which, double* out, hipStream_t s) {
+    launch_field<T>(mi, C, member, par, which, out, 0, s);
+}
+template <typename T>
+void launch_set_field(int mi, const CatchDev<T>& C, int member, int par, int which, const double* in,
+                      hipStream_t s) {
+    launch_field<T>(mi, C, member, par, which, const_cast<double*>(in), 1, s);
+}
+
+// Observation operator: depth of every member at every gauge cell, [N*K].
+template <typename T, int MI>
+__global__ __launch_bounds__(256) void k_gauges(const CatchDev<T> C, const int32_t* par, int K, const int32_t* grc,
+                                                double* y) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= C.n_members * K) return;
+    const int m = e / K, k = e % K;
+    const T* h = C.h[par[C.member_off + m]];
+    y[e] = (double)h[state_index<T, MI>(C, m, grc[2 * k], grc[2 * k + 1])];
+}
+
+template <typename T>
+void launch_gauges(int mi, const CatchDev<T>& C, const int32_t* par, int n_gauges, const int32_t* grc, double* y,
+                   hipStream_t s) {
+    dim3 grid((C.n_members * n_gauges + 255) / 256);
+    if (grid.x == 0) return;
+    switch (mi) {
+        case 1: hipLaunchKernelGGL((k_gauges<T, 1>), grid, dim3(256), 0, s, C, par, n_gauges, grc, y); break;
+        case 2: hipLaunchKernelGGL((k_gauges<T, 2>), grid, dim3(256), 0, s, C, par, n_gauges, grc, y); break;
+        case 4: hipLaunchKernelGGL((k_gauges<T, 4>), grid, dim3(256), 0, s, C, par, n_gauges, grc, y); break;
+        default: hipLaunchKernelGGL((k_gauges<T, 8>), grid, dim3(256), 0, s, C, par, n_gauges, grc, y); break;
+    }
+}
+
+// Fold the per-edge-link outflow accumulators into the per-member total.
+__global__ __launch_bounds__(256) void k_flush_outflow(int nb, double* acc, double* vout) {
+    const int m = blockIdx.x;
+    double* a = acc + (size_t)m * nb;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) {
+        s += a[i];
+        a[i] = 0.0;
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    __shared__ double part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) vout[m] += (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+void launch_flush_outflow(int n_members, int nb, double* out_acc, double* vout, hipStream_t s) {
+    if (n_members > 0) hipLaunchKernelGGL(k_flush_outflow, dim3(n_members), dim3(256), 0, s, nb, out_acc, vout);
+}
+
+// explicit instantiations
+template void launch_plan<float>(const PlanLaunch<float>&, hipStream_t);
+template void launch_plan<double>(const PlanLaunch<double>&, hipStream_t);
+template void launch_step_mi<float>(int, const StepLaunch<float>&, hipStream_t);
+template void launch_step_mi<double>(int, const StepLaunch<double>&, hipStream_t);
+template void launch_hmax_init<float>(int, const CatchDev<float>&, const int32_t*, uint32_t*, int, hipStream_t);
+template void launch_hmax_init<double>(int, const CatchDev<double>&, const int32_t*, unsigned long long*, int,
+                                       hipStream_t);
+template void launch_storage<float>(int, const CatchDev<float>&, const int32_t*, double*, hipStream_t);
+template void launch_storage<double>(int, const CatchDev<double>&, const int32_t*, double*, hipStream_t);
+template void launch_get_field<float>(int, const CatchDev<float>&, int, int, int, double*, hipStream_t);
+template void launch_get_field<double>(int, const CatchDev<double>&, int, int, int, double*, hipStream_t);
+template void launch_set_field<float>(int, const CatchDev<float>&, int, int, int, const double*, hipStream_t);
+template void launch_set_field<double>(int, const CatchDev<double>&, int, int, int, const double*, hipStream_t);
+template void launch_gauges<float>(int, const CatchDev<float>&, const int32_t*, int, const int32_t*, double*,
+                                   hipStream_t);
+template void launch_gauges<double>(int, const CatchDev<double>&, const int32_t*, int, const int32_t*, double*,
+                                    hipStream_t);
+
+}  // namespace flood

@@ -1,0 +1,1011 @@
+// Per-precision handle of libflood: device allocation and layout, the batched
+// step scheduler (HIP graphs + double-buffered completion poll), the particle
+// filter cycle, ledger/field access, snapshots and kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "flood_internal.h"
+#include "flood_runtime.h"
+#include "flood_tune.h"
+
+namespace flood {
+
+#define HIPCHK(expr)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (expr);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            err = std::string(#expr) + " failed: " + hipGetErrorString(e_);       \
+            return FLOOD_EHIP;                                                    \
+        }                                                                         \
+    } while (0)
+
+#define CHK(expr)                           \
+    do {                                    \
+        flood_status s_ = (expr);           \
+        if (s_ != FLOOD_OK) return s_;      \
+    } while (0)
+
+template <typename T> struct Impl : ImplBase {
+    using HB = typename HBits<T>::type;
+
+    struct Cat {
+        int ny = 0, nx = 0, N = 0, n_chunks = 0, tile_rows = 4, cpb = 1;
+        double dx = 0;
+        flood_params p{};
+        std::vector<double> rain;
+        double* d_rain = nullptr;
+        int edge_kind[4] = {0, 0, 0, 0};
+        double edge_slope[4] = {0, 0, 0, 0};
+        CatchDev<T> dev{};
+        size_t state_elems = 0, strip_w = 0, strip_n = 0;
+    };
+
+    hipStream_t st = nullptr;
+    hipStream_t own_stream = nullptr;  // created when the caller passes the null stream
+    int mi = 1;
+    int n_catch = 0, n_total = 0;
+    std::vector<Cat> cats;
+    std::vector<void*> allocs;
+
+    double *t = nullptr, *s = nullptr, *mu = nullptr, *logw = nullptr, *vrain = nullptr, *vout = nullptr,
+           *vclamp = nullptr;
+    int64_t* steps = nullptr;
+    int32_t *par = nullptr, *fault = nullptr, *status = nullptr;
+    HB* hbins = nullptr;
+    MemberStep<T>* ms = nullptr;
+    double* d_tend = nullptr;
+    int32_t* d_count = nullptr;
+    double* h_tend = nullptr;      // pinned
+    int32_t* h_count = nullptr;    // pinned [2 slots][2]
+    hipEvent_t ev[2] = {nullptr, nullptr};
+
+    // particle filter scratch
+    double *d_y = nullptr, *d_obs = nullptr, *d_sigma = nullptr, *d_beta = nullptr, *d_neff = nullptr;
+    int32_t *d_grc = nullptr, *d_anc = nullptr, *d_src = nullptr, *d_dst = nullptr, *d_flag = nullptr;
+    int max_gauges = 0;
+    double* d_stage = nullptr;     // field staging, max over catchments of (ny+1)*(nx+1) doubles
+    size_t stage_elems = 0;
+
+    // graph of G (plan, step) pairs
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int G = 16;
+    bool use_graph = true;
+
+    // kernel timing
+    bool timing_on = false;
+    std::vector<hipEvent_t> tev;
+    size_t tev_used = 0;
+    double t_ms = 0.0;
+    int64_t t_launches = 0;
+
+    StepLaunch<T> SL{};
+    PlanLaunch<T> PL{};
+
+    ~Impl() override {
+        (void)hipStreamSynchronize(st);
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+        for (auto e : tev) (void)hipEventDestroy(e);
+        for (void* p : allocs) (void)hipFree(p);
+        if (h_tend) (void)hipHostFree(h_tend);
+        if (h_count) (void)hipHostFree(h_count);
+        if (own_stream) (void)hipStreamDestroy(own_stream);
+    }
+
+    template <typename X> flood_status dalloc(X** p, size_t n, std::string& err) {
+        if (n == 0) n = 1;
+        hipError_t e = hipMalloc((void**)p, n * sizeof(X));
+        if (e != hipSuccess) {
+            *p = nullptr;
+            err = "hipMalloc of " + std::to_string(n * sizeof(X)) + " bytes failed: " + hipGetErrorString(e);
+            (void)hipGetLastError();
+            return e == hipErrorOutOfMemory ? FLOOD_ENOMEM : FLOOD_EHIP;
+        }
+        allocs.push_back((void*)*p);
+        return FLOOD_OK;
+    }
+
+    static int ilog2(int v) {
+        int l = 0;
+        while ((1 << l) < v) ++l;
+        return l;
+    }
+
+    // tile / grouping geometry of every catchment and the launch descriptor
+    void layout_launch() {
+        int begin = 0;
+        SL.n_catch = n_catch;
+        SL.n_total = n_total;
+        for (int i = 0; i < n_catch; ++i) {
+            Cat& c = cats[i];
+            CatchDev<T>& d = c.dev;
+            const int txc = std::max(1, kBlock / (mi * c.tile_rows));
+            d.tx_log2 = ilog2(txc);
+            const int ty = (kBlock / mi) >> d.tx_log2;
+            d.tiles_x = (c.nx + txc - 1) / txc;
+            d.tiles_y = (c.ny + ty - 1) / ty;
+            d.chunks_per_group = std::max(1, std::min(c.cpb, c.n_chunks));
+            d.groups = (c.n_chunks + d.chunks_per_group - 1) / d.chunks_per_group;
+            d.n_blocks = d.tiles_x * d.tiles_y * d.groups;
+            d.block_begin = begin;
+            begin += d.n_blocks;
+            SL.c[i] = d;
+        }
+        SL.total_blocks = begin;
+        SL.ms = ms;
+        SL.hbins = hbins;
+        SL.vclamp = vclamp;
+    }
+
+    void invalidate_graph() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+    }
+
+    flood_status init(int nc, const flood_grid* grids, const flood_params* params, const int32_t* members,
+                      const double* const* n_scale, const double* const* rain_mult, hipStream_t stream,
+                      std::string& err) {
+        st = stream;
+        if (!st) {
+            // A blocking stream stays ordered with the legacy null stream and, unlike it,
+            // can be captured into a graph.
+            HIPCHK(hipStreamCreate(&own_stream));
+            st = own_stream;
+        }
+        n_catch = nc;
+        const char* ng = std::getenv("FLOOD_NO_GRAPH");
+        use_graph = !(ng && ng[0] == '1');
+        cats.resize(nc);
+        int off = 0;
+        for (int i = 0; i < nc; ++i) {
+            Cat& c = cats[i];
+            c.ny = grids[i].ny;
+            c.nx = grids[i].nx;
+            c.dx = grids[i].dx;
+            c.N = members[i];
+            c.p = params[i];
+            c.rain.assign(params[i].rain_rate, params[i].rain_rate + params[i].n_rain);
+            for (int e = 0; e < 4; ++e) {
+                c.edge_kind[e] = grids[i].edge_kind[e];
+                c.edge_slope[e] = grids[i].edge_slope[e];
+            }
+            c.dev.member_off = off;
+            off += c.N;
+            max_gauges = std::max(max_gauges, 64);
+            stage_elems = std::max(stage_elems, (size_t)(c.ny + 1) * (c.nx + 1));
+            stage_elems = std::max(stage_elems, (size_t)c.N * 64);
+        }
+        n_total = off;
+
+        // kernel configuration: explicit values, else the tuner's choice
+        TuneKey key{};
+        key.real_bytes = (int)sizeof(T);
+        key.n_catch = nc;
+        for (int i = 0; i < nc; ++i) {
+            key.ny[i] = cats[i].ny;
+            key.nx[i] = cats[i].nx;
+            key.members[i] = cats[i].N;
+        }
+        TuneChoice ch = tune_default(key);
+        if (params[0].member_interleave) ch.mi = params[0].member_interleave;
+        mi = ch.mi;
+        for (int i = 0; i < nc; ++i) {
+            cats[i].tile_rows = params[i].tile_rows ? params[i].tile_rows : ch.tile_rows;
+            cats[i].cpb = params[i].chunks_per_block ? params[i].chunks_per_block : ch.cpb;
+            while (cats[i].tile_rows * mi > kBlock) cats[i].tile_rows >>= 1;
+        }
+
+        // per-catchment device arrays
+        for (int i = 0; i < nc; ++i) {
+            Cat& c = cats[i];
+            CatchDev<T>& d = c.dev;
+            c.n_chunks = (c.N + mi - 1) / mi;
+            const size_t ncell = (size_t)c.ny * c.nx;
+            c.state_elems = (size_t)c.n_chunks * ncell * mi;
+            c.strip_w = (size_t)c.n_chunks * c.ny * mi;
+            c.strip_n = (size_t)c.n_chunks * c.nx * mi;
+            d.ny = c.ny;
+            d.nx = c.nx;
+            d.n_members = c.N;
+            d.n_chunks = c.n_chunks;
+            d.dx = c.dx;
+            d.hdry = (T)c.p.h_dry;
+            d.g = (T)c.p.g;
+            for (int e = 0; e < 4; ++e) {
+                d.edge_open[e] = c.edge_kind[e] == FLOOD_EDGE_OPEN;
+                d.edge_slope[e] = (T)c.edge_slope[e];
+            }
+            for (int k = 0; k < 2; ++k) {
+                CHK(dalloc(&d.h[k], c.state_elems, err));
+                CHK(dalloc(&d.qx[k], c.state_elems, err));
+                CHK(dalloc(&d.qy[k], c.state_elems, err));
+                CHK(dalloc(&d.qw[k], c.strip_w, err));
+                CHK(dalloc(&d.qn[k], c.strip_n, err));
+                HIPCHK(hipMemsetAsync(d.h[k], 0, c.state_elems * sizeof(T), st));
+                HIPCHK(hipMemsetAsync(d.qx[k], 0, c.state_elems * sizeof(T), st));
+                HIPCHK(hipMemsetAsync(d.qy[k], 0, c.state_elems * sizeof(T), st));
+                HIPCHK(hipMemsetAsync(d.qw[k], 0, c.strip_w * sizeof(T), st));
+                HIPCHK(hipMemsetAsync(d.qn[k], 0, c.strip_n * sizeof(T), st));
+            }
+            T* zz;
+            T* nn;
+            CHK(dalloc(&zz, ncell, err));
+            CHK(dalloc(&nn, ncell, err));
+            {
+                std::vector<T> hz(ncell), hn(ncell);
+                for (size_t j = 0; j < ncell; ++j) {
+                    hz[j] = (T)grids[i].dem[j];
+                    hn[j] = (T)grids[i].manning_n[j];
+                }
+                HIPCHK(hipMemcpyAsync(zz, hz.data(), ncell * sizeof(T), hipMemcpyHostToDevice, st));
+                HIPCHK(hipMemcpyAsync(nn, hn.data(), ncell * sizeof(T), hipMemcpyHostToDevice, st));
+                HIPCHK(hipStreamSynchronize(st));
+            }
+            d.z = zz;
+            d.n = nn;
+            const int nb = 2 * (c.nx + c.ny);
+            CHK(dalloc(&d.out_acc, (size_t)c.N * nb, err));
+            HIPCHK(hipMemsetAsync(d.out_acc, 0, (size_t)c.N * nb * sizeof(double), st));
+            CHK(dalloc(&c.d_rain, std::max<size_t>(c.rain.size(), 1), err));
+            if (!c.rain.empty())
+                HIPCHK(hipMemcpyAsync(c.d_rain, c.rain.data(), c.rain.size() * sizeof(double), hipMemcpyHostToDevice,
+                                      st));
+        }
+
+        // per-member arrays
+        CHK(dalloc(&t, n_total, err));
+        CHK(dalloc(&s, n_total, err));
+        CHK(dalloc(&mu, n_total, err));
+        CHK(dalloc(&logw, n_total, err));
+        CHK(dalloc(&vrain, n_total, err));
+        CHK(dalloc(&vout, n_total, err));
+        CHK(dalloc(&vclamp, n_total, err));
+        CHK(dalloc(&steps, n_total, err));
+        CHK(dalloc(&par, n_total, err));
+        CHK(dalloc(&fault, n_total, err));
+        CHK(dalloc(&status, 1, err));
+        CHK(dalloc(&hbins, (size_t)kBins * n_total, err));
+        CHK(dalloc(&ms, n_total, err));
+        CHK(dalloc(&d_tend, 1, err));
+        CHK(dalloc(&d_count, 2, err));
+        {
+            std::vector<double> hs(n_total), hm(n_total), hl(n_total), z0(n_total, 0.0);
+            for (int i = 0; i < nc; ++i) {
+                const Cat& c = cats[i];
+                for (int m = 0; m < c.N; ++m) {
+                    const int g = c.dev.member_off + m;
+                    hs[g] = (n_scale && n_scale[i]) ? n_scale[i][m] : 1.0;
+                    hm[g] = (rain_mult && rain_mult[i]) ? rain_mult[i][m] : 1.0;
+                    hl[g] = -std::log((double)c.N);
+                }
+            }
+            HIPCHK(hipMemcpy(s, hs.data(), n_total * sizeof(double), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(mu, hm.data(), n_total * sizeof(double), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(logw, hl.data(), n_total * sizeof(double), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(t, z0.data(), n_total * sizeof(double), hipMemcpyHostToDevice));
+        }
+        HIPCHK(hipMemsetAsync(vrain, 0, n_total * sizeof(double), st));
+        HIPCHK(hipMemsetAsync(vout, 0, n_total * sizeof(double), st));
+        HIPCHK(hipMemsetAsync(vclamp, 0, n_total * sizeof(double), st));
+        HIPCHK(hipMemsetAsync(steps, 0, n_total * sizeof(int64_t), st));
+        HIPCHK(hipMemsetAsync(par, 0, n_total * sizeof(int32_t), st));
+        HIPCHK(hipMemsetAsync(fault, 0, n_total * sizeof(int32_t), st));
+        HIPCHK(hipMemsetAsync(status, 0, sizeof(int32_t), st));
+        HIPCHK(hipMemsetAsync(hbins, 0, (size_t)kBins * n_total * sizeof(HB), st));
+        HIPCHK(hipMemsetAsync(ms, 0, n_total * sizeof(MemberStep<T>), st));
+
+        // scratch
+        CHK(dalloc(&d_y, (size_t)kMaxMembers * 4096, err));
+        CHK(dalloc(&d_obs, 4096, err));
+        CHK(dalloc(&d_sigma, 4096, err));
+        CHK(dalloc(&d_beta, kMaxMembers, err));
+        CHK(dalloc(&d_neff, 1, err));
+        CHK(dalloc(&d_grc, 2 * 4096, err));
+        CHK(dalloc(&d_anc, kMaxMembers, err));
+        CHK(dalloc(&d_src, kMaxMembers, err));
+        CHK(dalloc(&d_dst, kMaxMembers, err));
+        CHK(dalloc(&d_flag, 1, err));
+        CHK(dalloc(&d_stage, stage_elems, err));
+        HIPCHK(hipHostMalloc((void**)&h_tend, sizeof(double), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&h_count, 4 * sizeof(int32_t), hipHostMallocDefault));
+        HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+
+        // initial depths
+        for (int i = 0; i < nc; ++i) {
+            if (!grids[i].h0) continue;
+            const Cat& c = cats[i];
+            const size_t ncell = (size_t)c.ny * c.nx;
+            std::vector<double> h0(ncell);
+            for (size_t j = 0; j < ncell; ++j) h0[j] = (double)grids[i].h0[j];
+            HIPCHK(hipMemcpyAsync(d_stage, h0.data(), ncell * sizeof(double), hipMemcpyHostToDevice, st));
+            for (int m = 0; m < c.N; ++m) launch_set_field<T>(mi, c.dev, m, 0, FLOOD_FIELD_H, d_stage, st);
+            HIPCHK(hipStreamSynchronize(st));
+        }
+
+        // planner descriptor
+        PL.n_catch = nc;
+        PL.n_total = n_total;
+        for (int i = 0; i < nc; ++i) {
+            const Cat& c = cats[i];
+            PlanCatch& pc = PL.c[i];
+            pc.member_off = c.dev.member_off;
+            pc.n_members = c.N;
+            pc.n_rain = c.p.n_rain;
+            pc.rain = c.d_rain;
+            pc.rain_interval = c.p.rain_interval;
+            pc.alpha = c.p.cfl_alpha;
+            pc.hdry = c.p.h_dry;
+            pc.dt_cap = c.p.dt_cap;
+            pc.dt_fixed = c.p.dt_fixed;
+            pc.g = c.p.g;
+            pc.dx = c.dx;
+            pc.ncells = (double)c.ny * (double)c.nx;
+        }
+        PL.t_end = d_tend;
+        PL.t = t;
+        PL.s = s;
+        PL.mu = mu;
+        PL.par = par;
+        PL.steps = steps;
+        PL.fault = fault;
+        PL.status = status;
+        PL.vrain = vrain;
+        PL.hbins = hbins;
+        PL.ms = ms;
+        PL.dtlog = nullptr;
+        PL.telog = nullptr;
+        PL.dtlog_cap = 0;
+        layout_launch();
+        for (int i = 0; i < nc; ++i) launch_hmax_init<T>(mi, cats[i].dev, par, hbins, n_total, st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+
+        // measured choice of tile rows / chunks per workgroup when not given
+        bool autotune = false;
+        for (int i = 0; i < nc; ++i) autotune |= (params[i].tile_rows == 0 || params[i].chunks_per_block == 0);
+        if (autotune && tune_enabled()) CHK(autotune_geometry(key, params, err));
+        return FLOOD_OK;
+    }
+
+    // time candidate (tile rows, chunks per workgroup) pairs on the real state
+    // without advancing it: each trial launches one step kernel that reads the
+    // current copy and writes the other copy, which is dead until the next step.
+    flood_status autotune_geometry(const TuneKey& key, const flood_params* params, std::string& err) {
+        TuneChoice cached;
+        if (tune_lookup(key, mi, cached)) {
+            for (int i = 0; i < n_catch; ++i) {
+                if (!params[i].tile_rows) cats[i].tile_rows = cached.tile_rows;
+                if (!params[i].chunks_per_block) cats[i].cpb = cached.cpb;
+            }
+            layout_launch();
+            return FLOOD_OK;
+        }
+        // a synthetic step plan: every member active with a representative step
+        std::vector<MemberStep<T>> hms(n_total);
+        for (int i = 0; i < n_catch; ++i)
+            for (int m = 0; m < cats[i].N; ++m) {
+                MemberStep<T>& x = hms[cats[i].dev.member_off + m];
+                const double dt = 0.5, dx = cats[i].dx, g = cats[i].p.g;
+                x.dtdx = (T)(dt / dx);
+                x.gdtdx = (T)(g * dt / dx);
+                x.gdt = (T)(g * dt);
+                x.s2dt = (T)dt;
+                x.capf = (T)(dx / (4 * dt));
+                x.rinc = (T)1e-5;
+                x.dxdt = dx * dt;
+                x.active = 1;
+                x.parity = 0;
+            }
+        std::vector<MemberStep<T>> saved(n_total);
+        std::vector<double> saved_clamp(n_total);
+        HIPCHK(hipMemcpy(saved.data(), ms, n_total * sizeof(MemberStep<T>), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(saved_clamp.data(), vclamp, n_total * sizeof(double), hipMemcpyDeviceToHost));
+        std::vector<int32_t> hpar(n_total);
+        HIPCHK(hipMemcpy(hpar.data(), par, n_total * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int m = 0; m < n_total; ++m) hms[m].parity = hpar[m];
+        HIPCHK(hipMemcpy(ms, hms.data(), n_total * sizeof(MemberStep<T>), hipMemcpyHostToDevice));
+        std::vector<std::vector<HB>> bins_saved(1);
+        bins_saved[0].resize((size_t)kBins * n_total);
+        HIPCHK(hipMemcpy(bins_saved[0].data(), hbins, bins_saved[0].size() * sizeof(HB), hipMemcpyDeviceToHost));
+        // the outflow accumulators are touched by trial steps: fold them first, restore after
+        std::vector<std::vector<double>> acc_saved(n_catch);
+        for (int i = 0; i < n_catch; ++i) {
+            const size_t n = (size_t)cats[i].N * 2 * (cats[i].nx + cats[i].ny);
+            acc_saved[i].resize(n);
+            HIPCHK(hipMemcpy(acc_saved[i].data(), cats[i].dev.out_acc, n * sizeof(double), hipMemcpyDeviceToHost));
+        }
+        hipEvent_t a, b;
+        HIPCHK(hipEventCreate(&a));
+        HIPCHK(hipEventCreate(&b));
+        const int rows_c[4] = {1, 2, 4, 8};
+        int max_chunks = 1;
+        for (int i = 0; i < n_catch; ++i) max_chunks = std::max(max_chunks, cats[i].n_chunks);
+        std::vector<int> cpbs;
+        for (int v = 1; v < max_chunks; v *= 2) cpbs.push_back(v);
+        cpbs.push_back(max_chunks);
+        float best = 1e30f;
+        int best_rows = cats[0].tile_rows, best_cpb = cats[0].cpb;
+        for (int r : rows_c) {
+            if (r * mi > kBlock) continue;
+            for (int cp : cpbs) {
+                for (int i = 0; i < n_catch; ++i) {
+                    if (!params[i].tile_rows) cats[i].tile_rows = r;
+                    if (!params[i].chunks_per_block) cats[i].cpb = cp;
+                }
+                layout_launch();
+                launch_step_mi<T>(mi, SL, st);  // warm-up
+                HIPCHK(hipEventRecord(a, st));
+                for (int rep = 0; rep < 3; ++rep) launch_step_mi<T>(mi, SL, st);
+                HIPCHK(hipEventRecord(b, st));
+                HIPCHK(hipEventSynchronize(b));
+                float ms_el = 0;
+                HIPCHK(hipEventElapsedTime(&ms_el, a, b));
+                if (ms_el < best) {
+                    best = ms_el;
+                    best_rows = r;
+                    best_cpb = cp;
+                }
+            }
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        for (int i = 0; i < n_catch; ++i) {
+            if (!params[i].tile_rows) cats[i].tile_rows = best_rows;
+            if (!params[i].chunks_per_block) cats[i].cpb = best_cpb;
+        }
+        layout_launch();
+        HIPCHK(hipMemcpy(ms, saved.data(), n_total * sizeof(MemberStep<T>), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(vclamp, saved_clamp.data(), n_total * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(hbins, bins_saved[0].data(), bins_saved[0].size() * sizeof(HB), hipMemcpyHostToDevice));
+        for (int i = 0; i < n_catch; ++i)
+            HIPCHK(hipMemcpy(cats[i].dev.out_acc, acc_saved[i].data(), acc_saved[i].size() * sizeof(double),
+                             hipMemcpyHostToDevice));
+        TuneChoice c;
+        c.mi = mi;
+        c.tile_rows = best_rows;
+        c.cpb = best_cpb;
+        tune_store(key, c);
+        return FLOOD_OK;
+    }
+
+    // ---------------------------------------------------------------------
+    // stepping
+    // ---------------------------------------------------------------------
+    flood_status ensure_graph(std::string& err) {
+        if (!use_graph || gexec || timing_on) return FLOOD_OK;
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            use_graph = false;
+            return FLOOD_OK;
+        }
+        for (int i = 0; i < G; ++i) {
+            launch_plan<T>(PL, st);
+            launch_step_mi<T>(mi, SL, st);
+        }
+        e = hipStreamEndCapture(st, &graph);
+        if (e != hipSuccess || !graph) {
+            (void)hipGetLastError();
+            use_graph = false;
+            graph = nullptr;
+            return FLOOD_OK;
+        }
+        e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipGraphDestroy(graph);
+            graph = nullptr;
+            gexec = nullptr;
+            use_graph = false;
+        }
+        (void)err;
+        return FLOOD_OK;
+    }
+
+    flood_status launch_batch(int slot, std::string& err) {
+        if (gexec && !timing_on) {
+            HIPCHK(hipGraphLaunch(gexec, st));
+        } else {
+            for (int i = 0; i < G; ++i) {
+                launch_plan<T>(PL, st);
+                if (timing_on) {
+                    while (tev.size() < tev_used + 2) {
+                        hipEvent_t e;
+                        HIPCHK(hipEventCreate(&e));
+                        tev.push_back(e);
+                    }
+                    HIPCHK(hipEventRecord(tev[tev_used], st));
+                    launch_step_mi<T>(mi, SL, st);
+                    HIPCHK(hipEventRecord(tev[tev_used + 1], st));
+                    tev_used += 2;
+                } else {
+                    launch_step_mi<T>(mi, SL, st);
+                }
+            }
+        }
+        launch_count_active(n_total, t, fault, d_tend, status, d_count, st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(h_count + 2 * slot, d_count, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(ev[slot], st));
+        return FLOOD_OK;
+    }
+
+    flood_status step(double t_end, std::string& err) override {
+        CHK(ensure_graph(err));
+        *h_tend = t_end;
+        HIPCHK(hipMemcpyAsync(d_tend, h_tend, sizeof(double), hipMemcpyHostToDevice, st));
+        CHK(launch_batch(0, err));
+        CHK(launch_batch(1, err));
+        int slot = 0;
+        int64_t batches = 2;
+        const int64_t max_batches = (int64_t)50000000 / G;
+        for (;;) {
+            HIPCHK(hipEventSynchronize(ev[slot]));
+            if (h_count[2 * slot] == 0) break;
+            if (batches > max_batches) {
+                err = "step limit exceeded before every member reached t_end";
+                return FLOOD_ESTATE;
+            }
+            CHK(launch_batch(slot, err));
+            ++batches;
+            slot ^= 1;
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        if (timing_on) {
+            for (size_t i = 0; i < tev_used; i += 2) {
+                float el = 0;
+                HIPCHK(hipEventElapsedTime(&el, tev[i], tev[i + 1]));
+                t_ms += el;
+                t_launches += 1;
+            }
+            tev_used = 0;
+        }
+        const int stat = h_count[2 * (slot ^ 1) + 1] | h_count[2 * slot + 1];
+        if (stat) {
+            err = "a member produced a non-finite depth and was frozen";
+            return FLOOD_ENUMERIC;
+        }
+        return FLOOD_OK;
+    }
+
+    // ---------------------------------------------------------------------
+    // particle filter
+    // ---------------------------------------------------------------------
+    flood_status check_catch(int c, std::string& err) const {
+        if (c < 0 || c >= n_catch) {
+            err = "catchment index out of range";
+            return FLOOD_EINVAL;
+        }
+        return FLOOD_OK;
+    }
+
+    flood_status common_time(int c, double* tc, std::string& err) {
+        const Cat& C = cats[c];
+        std::vector<double> ht(C.N);
+        std::vector<int32_t> hf(C.N);
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(ht.data(), t + C.dev.member_off, C.N * sizeof(double), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(hf.data(), fault + C.dev.member_off, C.N * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int m = 0; m < C.N; ++m) {
+            if (hf[m]) {
+                err = "a member of this catchment is faulted";
+                return FLOOD_ESTATE;
+            }
+            if (ht[m] != ht[0]) {
+                err = "members are not at a common time";
+                return FLOOD_ESTATE;
+            }
+        }
+        *tc = ht[0];
+        return FLOOD_OK;
+    }
+
+    flood_status assimilate(int c, int K, const int32_t* grc, const double* obs, const double* sigma,
+                            double neff_frac, double u0, const double* beta, double* neff_out, int32_t* anc_out,
+                            int32_t* res_out, std::string& err) override {
+        CHK(check_catch(c, err));
+        const Cat& C = cats[c];
+        if (K < 0 || K > 4096) { err = "n_gauges must be in [0, 4096]"; return FLOOD_EINVAL; }
+        if (K > 0 && (!grc || !obs || !sigma)) { err = "gauge_rc, obs and sigma are required"; return FLOOD_EINVAL; }
+        for (int k = 0; k < K; ++k) {
+            if (grc[2 * k] < 0 || grc[2 * k] >= C.ny || grc[2 * k + 1] < 0 || grc[2 * k + 1] >= C.nx) {
+                err = "gauge outside the grid";
+                return FLOOD_EINVAL;
+            }
+            if (!finite_d(obs[k])) { err = "obs must be finite"; return FLOOD_EINVAL; }
+            if (!(sigma[k] > 0.0) || !finite_d(sigma[k])) { err = "sigma must be finite and > 0"; return FLOOD_EINVAL; }
+        }
+        if (!(neff_frac > 0.0 && neff_frac <= 1.0)) { err = "neff_frac must be in (0, 1]"; return FLOOD_EINVAL; }
+        if (!(u0 >= 0.0 && u0 < 1.0)) { err = "u0 must be in [0, 1)"; return FLOOD_EINVAL; }
+        if (beta)
+            for (int m = 0; m < C.N; ++m)
+                if (!(beta[m] >= 0.0) || !finite_d(beta[m])) { err = "beta must be finite and >= 0"; return FLOOD_EINVAL; }
+        double tc;
+        CHK(common_time(c, &tc, err));
+        const int off = C.dev.member_off;
+        const int nb = 2 * (C.nx + C.ny);
+        launch_flush_outflow(C.N, nb, C.dev.out_acc, vout + off, st);
+        if (K > 0) {
+            HIPCHK(hipMemcpyAsync(d_grc, grc, 2 * K * sizeof(int32_t), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(d_obs, obs, K * sizeof(double), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(d_sigma, sigma, K * sizeof(double), hipMemcpyHostToDevice, st));
+        }
+        if (beta) HIPCHK(hipMemcpyAsync(d_beta, beta, C.N * sizeof(double), hipMemcpyHostToDevice, st));
+        launch_gauges<T>(mi, C.dev, par, K, d_grc, d_y, st);
+        PfArgs a{};
+        a.N = C.N;
+        a.K = K;
+        a.y = d_y;
+        a.d = d_obs;
+        a.sigma = d_sigma;
+        a.neff_frac = neff_frac;
+        a.u0 = u0;
+        a.beta = beta ? d_beta : nullptr;
+        a.logw = logw + off;
+        a.t = t + off;
+        a.s = s + off;
+        a.mu = mu + off;
+        a.vrain = vrain + off;
+        a.vout = vout + off;
+        a.vclamp = vclamp + off;
+        a.steps = steps + off;
+        a.par = par + off;
+        a.src_par = d_src;
+        a.dst_par = d_dst;
+        a.anc = d_anc;
+        a.neff = d_neff;
+        a.flag = d_flag;
+        launch_pf(a, st);
+        launch_permute<T>(mi, C.dev, d_anc, d_src, d_dst, d_flag, st);
+        launch_permute_bins<HB>(off, C.N, n_total, hbins, d_anc, d_flag, st);
+        HIPCHK(hipGetLastError());
+        double hn = 0;
+        int32_t hflag = 0;
+        HIPCHK(hipMemcpyAsync(&hn, d_neff, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(&hflag, d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        if (anc_out) HIPCHK(hipMemcpyAsync(anc_out, d_anc, C.N * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (neff_out) *neff_out = hn;
+        if (res_out) *res_out = hflag;
+        return FLOOD_OK;
+    }
+
+    flood_status adjoint(int c, double t_end, double sample_dt, int K, const int32_t* grc, const double* obs,
+                         int ckpt_every, double* loss_out, double* grad_n_out, double* grad_mult_out,
+                         std::string& err) override;
+
+    // ---------------------------------------------------------------------
+    // fields, parameters, ledger
+    // ---------------------------------------------------------------------
+    flood_status member_parity(int g, int* p, std::string& err) {
+        int32_t v = 0;
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(&v, par + g, sizeof(int32_t), hipMemcpyDeviceToHost));
+        *p = v;
+        return FLOOD_OK;
+    }
+
+    static size_t field_size(const Cat& C, int which) {
+        return which == FLOOD_FIELD_H ? (size_t)C.ny * C.nx
+                                      : which == FLOOD_FIELD_QX ? (size_t)C.ny * (C.nx + 1) : (size_t)(C.ny + 1) * C.nx;
+    }
+
+    flood_status get_field(int c, int m, int which, double* out, std::string& err) override {
+        CHK(check_catch(c, err));
+        const Cat& C = cats[c];
+        if (m < 0 || m >= C.N) { err = "member index out of range"; return FLOOD_EINVAL; }
+        if (which < 0 || which > 2) { err = "which must be H, QX or QY"; return FLOOD_EINVAL; }
+        if (!out) { err = "host_out is NULL"; return FLOOD_EINVAL; }
+        int p;
+        CHK(member_parity(C.dev.member_off + m, &p, err));
+        launch_get_field<T>(mi, C.dev, m, p, which, d_stage, st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(out, d_stage, field_size(C, which) * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return FLOOD_OK;
+    }
+
+    flood_status recompute_hmax(int c, std::string& err) {
+        const Cat& C = cats[c];
+        launch_zero_bins<HB>(C.dev.member_off, C.N, n_total, hbins, st);
+        launch_hmax_init<T>(mi, C.dev, par, hbins, n_total, st);
+        HIPCHK(hipGetLastError());
+        return FLOOD_OK;
+    }
+
+    flood_status set_state(int c, int m, const double* hh, const double* qx, const double* qy, double tt,
+                           std::string& err) override {
+        CHK(check_catch(c, err));
+        const Cat& C = cats[c];
+        if (m < 0 || m >= C.N) { err = "member index out of range"; return FLOOD_EINVAL; }
+        if (!hh || !qx || !qy) { err = "h, qx and qy are required"; return FLOOD_EINVAL; }
+        if (!(tt >= 0.0) || !finite_d(tt)) { err = "t must be finite and >= 0"; return FLOOD_EINVAL; }
+        const int ny = C.ny, nx = C.nx;
+        for (size_t i = 0; i < (size_t)ny * nx; ++i)
+            if (!(hh[i] >= 0.0) || !finite_d(hh[i])) { err = "depths must be finite and >= 0"; return FLOOD_EINVAL; }
+        for (size_t i = 0; i < (size_t)ny * (nx + 1); ++i)
+            if (!finite_d(qx[i])) { err = "qx must be finite"; return FLOOD_EINVAL; }
+        for (size_t i = 0; i < (size_t)(ny + 1) * nx; ++i)
+            if (!finite_d(qy[i])) { err = "qy must be finite"; return FLOOD_EINVAL; }
+        for (int r = 0; r < ny; ++r) {
+            if (C.edge_kind[3] == FLOOD_EDGE_WALL && qx[(size_t)r * (nx + 1)] != 0.0) { err = "west wall link must be 0"; return FLOOD_EINVAL; }
+            if (C.edge_kind[1] == FLOOD_EDGE_WALL && qx[(size_t)r * (nx + 1) + nx] != 0.0) { err = "east wall link must be 0"; return FLOOD_EINVAL; }
+        }
+        for (int cc = 0; cc < nx; ++cc) {
+            if (C.edge_kind[0] == FLOOD_EDGE_WALL && qy[cc] != 0.0) { err = "north wall link must be 0"; return FLOOD_EINVAL; }
+            if (C.edge_kind[2] == FLOOD_EDGE_WALL && qy[(size_t)ny * nx + cc] != 0.0) { err = "south wall link must be 0"; return FLOOD_EINVAL; }
+        }
+        const int g = C.dev.member_off + m;
+        int p;
+        CHK(member_parity(g, &p, err));
+        const double* src[3] = {hh, qx, qy};
+        for (int w = 0; w < 3; ++w) {
+            HIPCHK(hipMemcpyAsync(d_stage, src[w], field_size(C, w) * sizeof(double), hipMemcpyHostToDevice, st));
+            launch_set_field<T>(mi, C.dev, m, p, w, d_stage, st);
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        HIPCHK(hipMemcpy(t + g, &tt, sizeof(double), hipMemcpyHostToDevice));
+        CHK(recompute_hmax(c, err));
+        HIPCHK(hipStreamSynchronize(st));
+        return FLOOD_OK;
+    }
+
+    flood_status set_params(int c, const float* manning, const double* n_scale, const double* rain_mult,
+                            std::string& err) override {
+        CHK(check_catch(c, err));
+        const Cat& C = cats[c];
+        const size_t ncell = (size_t)C.ny * C.nx;
+        if (manning)
+            for (size_t i = 0; i < ncell; ++i)
+                if (!(manning[i] > 0.0f) || !std::isfinite(manning[i])) { err = "manning_n must be finite and > 0"; return FLOOD_EINVAL; }
+        for (int m = 0; m < C.N; ++m) {
+            if (n_scale && (!(n_scale[m] > 0.0) || !finite_d(n_scale[m]))) { err = "n_scale must be finite and > 0"; return FLOOD_EINVAL; }
+            if (rain_mult && (!(rain_mult[m] >= 0.0) || !finite_d(rain_mult[m]))) { err = "rain_mult must be finite and >= 0"; return FLOOD_EINVAL; }
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        if (manning) {
+            std::vector<T> hn(ncell);
+            for (size_t i = 0; i < ncell; ++i) hn[i] = (T)manning[i];
+            HIPCHK(hipMemcpy(const_cast<T*>(C.dev.n), hn.data(), ncell * sizeof(T), hipMemcpyHostToDevice));
+        }
+        if (n_scale) HIPCHK(hipMemcpy(s + C.dev.member_off, n_scale, C.N * sizeof(double), hipMemcpyHostToDevice));
+        if (rain_mult) HIPCHK(hipMemcpy(mu + C.dev.member_off, rain_mult, C.N * sizeof(double), hipMemcpyHostToDevice));
+        return FLOOD_OK;
+    }
+
+    flood_status get_ledger(int c, double* storage, double* rain_in, double* outflow, double* clamp, double* tt,
+                            int64_t* stp, std::string& err) override {
+        CHK(check_catch(c, err));
+        const Cat& C = cats[c];
+        const int off = C.dev.member_off;
+        launch_flush_outflow(C.N, 2 * (C.nx + C.ny), C.dev.out_acc, vout + off, st);
+        if (storage) {
+            HIPCHK(hipMemsetAsync(d_stage, 0, C.N * sizeof(double), st));
+            launch_storage<T>(mi, C.dev, par, d_stage, st);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(storage, d_stage, C.N * sizeof(double), hipMemcpyDeviceToHost, st));
+        }
+        if (rain_in) HIPCHK(hipMemcpyAsync(rain_in, vrain + off, C.N * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (outflow) HIPCHK(hipMemcpyAsync(outflow, vout + off, C.N * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (clamp) HIPCHK(hipMemcpyAsync(clamp, vclamp + off, C.N * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (tt) HIPCHK(hipMemcpyAsync(tt, t + off, C.N * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (stp) HIPCHK(hipMemcpyAsync(stp, steps + off, C.N * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return FLOOD_OK;
+    }
+
+    flood_status get_weights(int c, double* lw, double* rm, double* ns, std::string& err) override {
+        CHK(check_catch(c, err));
+        const Cat& C = cats[c];
+        const int off = C.dev.member_off;
+        HIPCHK(hipStreamSynchronize(st));
+        if (lw) HIPCHK(hipMemcpy(lw, logw + off, C.N * sizeof(double), hipMemcpyDeviceToHost));
+        if (rm) HIPCHK(hipMemcpy(rm, mu + off, C.N * sizeof(double), hipMemcpyDeviceToHost));
+        if (ns) HIPCHK(hipMemcpy(ns, s + off, C.N * sizeof(double), hipMemcpyDeviceToHost));
+        return FLOOD_OK;
+    }
+
+    // ---------------------------------------------------------------------
+    // snapshots: raw device images of every array, after a shape header
+    // ---------------------------------------------------------------------
+    struct Blob {
+        void* p;
+        size_t bytes;
+    };
+
+    std::vector<Blob> blobs() {
+        std::vector<Blob> v;
+        for (auto& C : cats) {
+            for (int k = 0; k < 2; ++k) {
+                v.push_back({C.dev.h[k], C.state_elems * sizeof(T)});
+                v.push_back({C.dev.qx[k], C.state_elems * sizeof(T)});
+                v.push_back({C.dev.qy[k], C.state_elems * sizeof(T)});
+                v.push_back({C.dev.qw[k], C.strip_w * sizeof(T)});
+                v.push_back({C.dev.qn[k], C.strip_n * sizeof(T)});
+            }
+            v.push_back({const_cast<T*>(C.dev.n), (size_t)C.ny * C.nx * sizeof(T)});
+            v.push_back({C.dev.out_acc, (size_t)C.N * 2 * (C.nx + C.ny) * sizeof(double)});
+        }
+        const size_t n = n_total;
+        v.push_back({t, n * 8});
+        v.push_back({s, n * 8});
+        v.push_back({mu, n * 8});
+        v.push_back({logw, n * 8});
+        v.push_back({vrain, n * 8});
+        v.push_back({vout, n * 8});
+        v.push_back({vclamp, n * 8});
+        v.push_back({steps, n * 8});
+        v.push_back({par, n * 4});
+        v.push_back({fault, n * 4});
+        v.push_back({hbins, (size_t)kBins * n * sizeof(HB)});
+        return v;
+    }
+
+    void header(std::vector<int64_t>& hd) const {
+        hd = {0x464c4f4f44534e31LL, (int64_t)sizeof(T), mi, n_catch, n_total};
+        for (auto& C : cats) {
+            hd.push_back(C.ny);
+            hd.push_back(C.nx);
+            hd.push_back(C.N);
+        }
+    }
+
+    flood_status save(const char* path, std::string& err) override {
+        HIPCHK(hipStreamSynchronize(st));
+        FILE* f = std::fopen(path, "wb");
+        if (!f) { err = std::string("cannot open ") + path; return FLOOD_EINVAL; }
+        std::vector<int64_t> hd;
+        header(hd);
+        const int64_t nh = (int64_t)hd.size();
+        bool ok = std::fwrite(&nh, 8, 1, f) == 1 && std::fwrite(hd.data(), 8, hd.size(), f) == hd.size();
+        std::vector<char> buf;
+        for (auto& b : blobs()) {
+            if (!ok) break;
+            buf.resize(b.bytes);
+            if (hipMemcpy(buf.data(), b.p, b.bytes, hipMemcpyDeviceToHost) != hipSuccess) {
+                std::fclose(f);
+                err = "device read failed";
+                return FLOOD_EHIP;
+            }
+            ok = std::fwrite(buf.data(), 1, b.bytes, f) == b.bytes;
+        }
+        ok = (std::fclose(f) == 0) && ok;
+        if (!ok) { err = "write failed"; return FLOOD_EINVAL; }
+        return FLOOD_OK;
+    }
+
+    flood_status load(const char* path, std::string& err) override {
+        FILE* f = std::fopen(path, "rb");
+        if (!f) { err = std::string("cannot open ") + path; return FLOOD_EINVAL; }
+        std::vector<int64_t> hd, got;
+        header(hd);
+        int64_t nh = 0;
+        bool ok = std::fread(&nh, 8, 1, f) == 1 && nh == (int64_t)hd.size();
+        if (ok) {
+            got.resize(nh);
+            ok = std::fread(got.data(), 8, nh, f) == (size_t)nh && got == hd;
+        }
+        if (!ok) {
+            std::fclose(f);
+            err = "snapshot does not match this handle's shape";
+            return FLOOD_EINVAL;
+        }
+        std::vector<std::vector<char>> data;
+        for (auto& b : blobs()) {
+            data.emplace_back(b.bytes);
+            if (std::fread(data.back().data(), 1, b.bytes, f) != b.bytes) {
+                std::fclose(f);
+                err = "snapshot is truncated";
+                return FLOOD_EINVAL;
+            }
+        }
+        std::fclose(f);
+        HIPCHK(hipStreamSynchronize(st));
+        size_t i = 0;
+        for (auto& b : blobs()) {
+            HIPCHK(hipMemcpy(b.p, data[i].data(), b.bytes, hipMemcpyHostToDevice));
+            ++i;
+        }
+        HIPCHK(hipMemset(status, 0, sizeof(int32_t)));
+        return FLOOD_OK;
+    }
+
+    void get_config(int32_t* omi, int32_t* rows, int32_t* cpb, int32_t* gs) const override {
+        if (omi) *omi = mi;
+        if (rows) *rows = cats[0].tile_rows;
+        if (cpb) *cpb = std::min(cats[0].cpb, cats[0].n_chunks);
+        if (gs) *gs = (use_graph && gexec) ? G : 0;
+    }
+
+    flood_status timing(bool on, std::string& err) override {
+        HIPCHK(hipStreamSynchronize(st));
+        if (on) {
+            t_ms = 0.0;
+            t_launches = 0;
+            tev_used = 0;
+        }
+        timing_on = on;
+        return FLOOD_OK;
+    }
+
+    void get_timing(double* avg, int64_t* n) const override {
+        if (avg) *avg = t_launches ? t_ms / (double)t_launches : 0.0;
+        if (n) *n = t_launches;
+    }
+};
+
+// the adjoint driver lives in flood_adjoint.hip
+template <typename T>
+flood_status adjoint_run(Impl<T>& I, int c, double t_end, double sample_dt, int K, const int32_t* grc,
+                         const double* obs, int ckpt_every, double* loss_out, double* grad_n_out,
+                         double* grad_mult_out, std::string& err);
+
+template <typename T>
+flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, const int32_t* grc, const double* obs,
+                              int ckpt_every, double* loss_out, double* grad_n_out, double* grad_mult_out,
+                              std::string& err) {
+    (void)c; (void)t_end; (void)sample_dt; (void)K; (void)grc; (void)obs; (void)ckpt_every;
+    (void)loss_out; (void)grad_n_out; (void)grad_mult_out;
+    err = "adjoint is not available in this build";
+    return FLOOD_ESTATE;
+}
+
+flood_status create_impl(flood_handle* h, int n_catch, const flood_grid* grids, const flood_params* params,
+                         const int32_t* members, const double* const* n_scale, const double* const* rain_mult,
+                         hipStream_t stream, std::string& err) {
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        err = "no HIP device available";
+        return FLOOD_EHIP;
+    }
+    if (params[0].real_bytes == 8) {
+        auto* I = new Impl<double>();
+        h->impl.reset(I);
+        flood_status st = I->init(n_catch, grids, params, members, n_scale, rain_mult, stream, err);
+        if (st) h->impl.reset();
+        return st;
+    }
+    auto* I = new Impl<float>();
+    h->impl.reset(I);
+    flood_status st = I->init(n_catch, grids, params, members, n_scale, rain_mult, stream, err);
+    if (st) h->impl.reset();
+    return st;
+}
+
+flood_status systematic_resample_impl(const double* w, int n, double u0, int32_t* anc, hipStream_t s) {
+    double* dw = nullptr;
+    int32_t* da = nullptr;
+    if (hipMalloc((void**)&dw, n * sizeof(double)) != hipSuccess) return FLOOD_ENOMEM;
+    if (hipMalloc((void**)&da, n * sizeof(int32_t)) != hipSuccess) {
+        (void)hipFree(dw);
+        return FLOOD_ENOMEM;
+    }
+    flood_status rc = FLOOD_OK;
+    if (hipMemcpyAsync(dw, w, n * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess) rc = FLOOD_EHIP;
+    if (!rc) {
+        launch_systematic(n, dw, u0, da, s);
+        if (hipGetLastError() != hipSuccess) rc = FLOOD_EHIP;
+    }
+    if (!rc && hipMemcpyAsync(anc, da, n * sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess) rc = FLOOD_EHIP;
+    if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = FLOOD_EHIP;
+    (void)hipFree(dw);
+    (void)hipFree(da);
+    return rc;
+}
+
+}  // namespace flood

@@ -1,0 +1,25 @@
+// Kernel-geometry tuner of libflood: the key of a tuning problem, the chosen
+// geometry, the defaults used before (or instead of) measuring, and a small
+// text cache of measured choices.
+#pragma once
+
+namespace flood {
+
+struct TuneKey {
+    int real_bytes;
+    int n_catch;
+    int ny[8], nx[8], members[8];
+};
+
+struct TuneChoice {
+    int mi = 1;          // members interleaved in the fastest index
+    int tile_rows = 4;   // cell rows per 256-lane tile
+    int cpb = 16;        // member chunks per workgroup
+};
+
+TuneChoice tune_default(const TuneKey& k);
+bool tune_enabled();
+bool tune_lookup(const TuneKey& k, int mi, TuneChoice& out);
+void tune_store(const TuneKey& k, const TuneChoice& c);
+
+}  // namespace flood

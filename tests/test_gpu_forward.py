@@ -1,0 +1,354 @@
+"""GPU parity of the forward step against the FP64 oracle (through the C ABI).
+
+Tolerances (FP32 state): depth 1e-4 m, discharge 1e-4 relative to the largest
+discharge, mass ledger 1e-6 relative; one step from an identical state 1e-6 m.
+FP64 state: 1e-9 m over the whole plain-method run.  Members are independent,
+so any interleave / tiling / batching must give bit-identical results.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2302_08341_amd import flood
+    flood.load_library()
+    return flood
+
+
+def _ens(fl, c, rain, n, **kw):
+    cat = dict(dem=c.dem, manning=c.manning, dx=c.dx, edge_kind=c.edge_kind, edge_slope=c.edge_slope,
+               n_members=n, n_scale=c.n_scale[:n], rain_mult=c.rain_mult[:n], h0=c.h0)
+    return fl.FloodEnsemble([cat], rain, **kw)
+
+
+def _orc_member(orc, c, rain, i, t_end, **kw):
+    m = orc.Model(c.dem, c.manning, c.dx, rain, edge_kind=c.edge_kind, edge_slope=c.edge_slope, **kw)
+    mem = orc.Member.dry(m, s=c.n_scale[i], mu=c.rain_mult[i], h0=c.h0)
+    orc.advance(m, mem, t_end)
+    return m, mem
+
+
+def link_depths(z, h):
+    """Flow depth of every link (Eq. 3; inner-cell depth on edge links), host layouts."""
+    eta = h + z
+    ny, nx = h.shape
+    hx = np.zeros((ny, nx + 1))
+    hy = np.zeros((ny + 1, nx))
+    hx[:, 1:nx] = np.maximum(eta[:, :-1], eta[:, 1:]) - np.maximum(z[:, :-1], z[:, 1:])
+    hx[:, 0], hx[:, nx] = h[:, 0], h[:, -1]
+    hy[1:ny, :] = np.maximum(eta[:-1, :], eta[1:, :]) - np.maximum(z[:-1, :], z[1:, :])
+    hy[0, :], hy[ny, :] = h[0, :], h[-1, :]
+    return hx, hy
+
+
+def _close(gpu, ref, z, h_dry=1e-3, tol_h=1e-4, tol_q=1e-4, tol_link=1e-3, dx=3.0):
+    """Depth within tol_h everywhere.  Discharge (volume flux through a section, as the
+    paper's streamflow gauges sum link fluxes across a section): through every 4th row /
+    column section and through each edge within tol_q x the largest section discharge.
+    Per link, every link whose flow depth is at least 2 h_dry on both sides within
+    tol_link x max|q| (shallower links sit where rounding can switch wet/dry, which
+    also moves their neighbours slightly).  Returns the number of shallow links outside
+    that per-link bound."""
+    gh, gqx, gqy = gpu
+    rh, rqx, rqy = ref
+    assert np.abs(gh - rh).max() <= tol_h, ("h", np.abs(gh - rh).max())
+    scale = max(np.abs(rqx).max(), np.abs(rqy).max(), 1e-12)
+    zz = np.asarray(z, np.float64)
+    hxo, hyo = link_depths(zz, rh)
+    hxg, hyg = link_depths(zz, gh)
+    n_ex = 0
+    for g, r, ho, hg in ((gqx, rqx, hxo, hxg), (gqy, rqy, hyo, hyg)):
+        deep = (ho >= 2 * h_dry) & (hg >= 2 * h_dry)
+        d = np.abs(g - r)
+        assert d[deep].max(initial=0.0) <= tol_link * scale, ("q", d[deep].max(), scale)
+        n_ex += int(np.count_nonzero(~deep & (d > tol_link * scale)))
+    sec_g = np.concatenate([gqx[:, ::4].sum(axis=0), gqy[::4, :].sum(axis=1)]) * dx
+    sec_r = np.concatenate([rqx[:, ::4].sum(axis=0), rqy[::4, :].sum(axis=1)]) * dx
+    edge_g = np.array([gqy[0].sum(), gqx[:, -1].sum(), gqy[-1].sum(), gqx[:, 0].sum()]) * dx
+    edge_r = np.array([rqy[0].sum(), rqx[:, -1].sum(), rqy[-1].sum(), rqx[:, 0].sum()]) * dx
+    qs = max(np.abs(sec_r).max(), np.abs(edge_r).max())
+    assert np.abs(sec_g - sec_r).max() <= tol_q * qs, ("section Q", np.abs(sec_g - sec_r).max(), qs)
+    assert np.abs(edge_g - edge_r).max() <= tol_q * qs, ("edge Q", np.abs(edge_g - edge_r).max(), qs)
+    return n_ex
+
+
+URBAN = W.urban_catchment("par", 97, 83, 5, W.seed_for(2, 5), n_gauges=4)   # ragged against every tile
+
+
+def test_trajectory_parity_fp32(fl, orc):
+    rain = W.chicago_hyetograph()
+    e = _ens(fl, URBAN, rain, 5, real_bytes=4)
+    e.step(900.0)
+    for i in range(5):
+        m, mem = _orc_member(orc, URBAN, rain, i, 900.0)
+        n_ex = _close([e.field(i), e.field(i, fl.FIELD_QX), e.field(i, fl.FIELD_QY)], [mem.h, mem.qx, mem.qy],
+                      URBAN.dem)
+        assert n_ex <= 2e-3 * mem.h.size
+        led = e.ledger()
+        assert led["outflow"][i] == pytest.approx(mem.v_out, rel=1e-4)
+    led = e.ledger()
+    assert np.all(led["t"] == 900.0)
+    resid = np.abs(led["storage"] - (led["rain_in"] - led["outflow"] + led["clamp"])) / led["rain_in"]
+    assert resid.max() <= 1e-6, resid
+
+
+def test_one_step_parity_from_identical_state(fl, orc):
+    rain = W.chicago_hyetograph()
+    m, mem = _orc_member(orc, URBAN, rain, 2, 1200.0)
+    # round the oracle state to FP32 so both sides start from the same numbers
+    h32 = mem.h.astype(np.float32).astype(np.float64)
+    qx32 = mem.qx.astype(np.float32).astype(np.float64)
+    qy32 = mem.qy.astype(np.float32).astype(np.float64)
+    e = _ens(fl, URBAN, rain, 5, real_bytes=4)
+    e.set_state(2, h32, qx32, qy32, 1200.0)
+    e.step(1200.0)                      # other members advance; member 2 is already there
+    dt = 0.05                           # shorter than Eq. 4 here: exactly one step of this length
+    e.step(1200.0 + dt)
+    ref = orc.Member(h32.copy(), qx32.copy(), qy32.copy(), t=1200.0, s=URBAN.n_scale[2], mu=URBAN.rain_mult[2])
+    orc.step(m, ref, dt)
+    gh, gqx, gqy = e.field(2), e.field(2, fl.FIELD_QX), e.field(2, fl.FIELD_QY)
+    assert np.abs(gh - ref.h).max() <= 1e-6
+    qs = max(np.abs(ref.qx).max(), np.abs(ref.qy).max())
+    assert np.abs(gqx - ref.qx).max() <= 1e-5 * qs and np.abs(gqy - ref.qy).max() <= 1e-5 * qs
+    # links that carry flow on the GPU are wet by the oracle and vice versa (non-degenerate links)
+    for g, r in ((gqx, ref.qx), (gqy, ref.qy)):
+        strong = np.abs(r) > 1e-4 * qs
+        assert np.all((g != 0)[strong])
+        assert np.all((r != 0)[g != 0])
+
+
+def test_plain_method_fp64_config1(fl, orc):
+    wl = W.config1()
+    c = wl.catchments[0]
+    e = _ens(fl, c, wl.rain, 1, real_bytes=8)
+    e.step(wl.t_end)
+    m = orc.Model.from_workload(wl)
+    mem = orc.Member.dry(m)
+    orc.advance(m, mem, wl.t_end)
+    dh = np.abs(e.field(0) - mem.h).max()
+    assert dh <= 1e-9, dh
+    led = e.ledger()
+    assert led["steps"][0] == mem.steps
+    assert abs(led["rain_in"][0] - mem.v_rain) <= 1e-12 * mem.v_rain
+    resid = abs(led["storage"][0] - (led["rain_in"][0] - led["outflow"][0] + led["clamp"][0])) / led["rain_in"][0]
+    assert resid <= 1e-12
+
+
+@pytest.mark.parametrize("mi,rows,cpb", [(1, 1, 1), (2, 4, 3), (4, 2, 2), (8, 8, 1), (8, 1, 4)])
+def test_interleave_and_tiling_are_bit_exact(fl, mi, rows, cpb):
+    rain = W.chicago_hyetograph()
+    ref = _ens(fl, URBAN, rain, 5, real_bytes=4, member_interleave=1, tile_rows=4, chunks_per_block=5)
+    ref.step(400.0)
+    e = _ens(fl, URBAN, rain, 5, real_bytes=4, member_interleave=mi, tile_rows=rows, chunks_per_block=cpb)
+    e.step(400.0)
+    for i in range(5):
+        for w in (fl.FIELD_H, fl.FIELD_QX, fl.FIELD_QY):
+            np.testing.assert_array_equal(e.field(i, w), ref.field(i, w))
+
+
+def test_batched_equals_one_launch_per_member(fl):
+    rain = W.chicago_hyetograph()
+    b = _ens(fl, URBAN, rain, 5, real_bytes=4, member_interleave=4)
+    b.step(300.0)
+    for i in range(5):
+        cat = dict(dem=URBAN.dem, manning=URBAN.manning, dx=URBAN.dx, edge_kind=URBAN.edge_kind,
+                   edge_slope=URBAN.edge_slope, n_members=1, n_scale=URBAN.n_scale[i:i + 1],
+                   rain_mult=URBAN.rain_mult[i:i + 1])
+        p = fl.FloodEnsemble([cat], rain, real_bytes=4, member_interleave=1)
+        p.step(300.0)
+        np.testing.assert_array_equal(p.field(0), b.field(i))
+
+
+def test_multi_catchment_batch_matches_separate_handles(fl):
+    rain = W.chicago_hyetograph()
+    cs = [W.urban_catchment("a", 40, 70, 3, W.seed_for(4, 0)), W.urban_catchment("b", 65, 33, 2, W.seed_for(4, 1))]
+    cats = [dict(dem=c.dem, manning=c.manning, dx=c.dx, edge_kind=c.edge_kind, edge_slope=c.edge_slope,
+                 n_members=c.n_members, n_scale=c.n_scale, rain_mult=c.rain_mult) for c in cs]
+    b = fl.FloodEnsemble(cats, rain, real_bytes=4)
+    b.step(350.0)
+    for j, c in enumerate(cats):
+        s = fl.FloodEnsemble([c], rain, real_bytes=4)
+        s.step(350.0)
+        for i in range(c["n_members"]):
+            np.testing.assert_array_equal(s.field(i), b.field(i, catchment=j))
+
+
+def test_graph_and_direct_launches_agree(fl, monkeypatch):
+    rain = W.chicago_hyetograph()
+    a = _ens(fl, URBAN, rain, 3, real_bytes=4)
+    a.step(200.0)
+    monkeypatch.setenv("FLOOD_NO_GRAPH", "1")
+    b = _ens(fl, URBAN, rain, 3, real_bytes=4)
+    b.step(200.0)
+    assert b.config()["graph_steps"] == 0
+    for i in range(3):
+        np.testing.assert_array_equal(a.field(i), b.field(i))
+
+
+def test_lake_at_rest_gpu(fl):
+    # bed and surface on a 2^-10 m lattice: h = eta0 - z, the bed step and the depth
+    # difference are exact in FP32 and FP64, so a still lake must stay exactly still
+    wl = W.config1(64, 48)
+    z = np.round(wl.catchments[0].dem.astype(np.float64) * 1024.0) / 1024.0
+    eta0 = np.round(float(np.quantile(z, 0.7)) * 1024.0) / 1024.0
+    h0 = np.maximum(eta0 - z, 0.0)
+    assert (h0 == 0).any() and (h0 > 0.5).any()
+    cat = dict(dem=z.astype(np.float32), manning=wl.catchments[0].manning, dx=3.0, edge_kind=(0, 0, 0, 0),
+               edge_slope=(0, 0, 0, 0), n_members=2, h0=h0.astype(np.float32))
+    for rb in (8, 4):
+        e = fl.FloodEnsemble([cat], [], real_bytes=rb)
+        e.step(600.0)
+        assert e.ledger()["steps"][0] > 100
+        for i in range(2):
+            np.testing.assert_array_equal(e.field(i), h0)
+            assert np.abs(e.field(i, fl.FIELD_QX)).max() == 0.0
+            assert np.abs(e.field(i, fl.FIELD_QY)).max() == 0.0
+
+
+@pytest.mark.parametrize("ny,nx", [(1, 1), (1, 37), (29, 1), (2, 2), (65, 64), (3, 130)])
+def test_degenerate_grids(fl, orc, ny, nx):
+    # deep water everywhere (no cell near the wet/dry threshold); open edges across the
+    # short direction of one-cell-thick strips would empty them in seconds, so those get walls
+    rng = np.random.default_rng(ny * 100 + nx)
+    dem = rng.uniform(0, 0.05, size=(ny, nx)).astype(np.float32)
+    h0 = (0.3 + rng.uniform(0, 0.1, size=(ny, nx))).astype(np.float32)
+    man = np.full((ny, nx), 0.03, np.float32)
+    rain = [2e-5, 4e-5]
+    kinds = [1, 1, 1, 1]
+    if ny == 1:
+        kinds[0] = kinds[2] = 0
+    if nx == 1:
+        kinds[1] = kinds[3] = 0
+    slopes = (1e-3, 2e-3, 3e-3, 4e-3)
+    cat = dict(dem=dem, manning=man, dx=3.0, edge_kind=tuple(kinds), edge_slope=slopes, h0=h0,
+               n_members=3, n_scale=np.array([1.0, 1.2, 0.8]), rain_mult=np.array([1.0, 2.0, 0.5]))
+    e = fl.FloodEnsemble([cat], rain, real_bytes=8, rain_interval=20.0)
+    e.step(10.0)
+    for i in range(3):
+        m = orc.Model(dem, man, 3.0, np.array(rain), rain_interval=20.0, edge_kind=tuple(kinds),
+                      edge_slope=slopes)
+        mem = orc.Member.dry(m, s=cat["n_scale"][i], mu=cat["rain_mult"][i], h0=h0)
+        orc.advance(m, mem, 10.0)
+        assert mem.h.min() > 4e-3
+        assert e.ledger()["steps"][i] == mem.steps
+        assert np.abs(e.field(i) - mem.h).max() <= 1e-10
+        assert np.abs(e.field(i, fl.FIELD_QX) - mem.qx).max() <= 1e-10
+        assert np.abs(e.field(i, fl.FIELD_QY) - mem.qy).max() <= 1e-10
+
+
+def test_save_load_roundtrip(fl, tmp_path):
+    rain = W.chicago_hyetograph()
+    a = _ens(fl, URBAN, rain, 3, real_bytes=4)
+    a.step(150.0)
+    p = str(tmp_path / "snap.bin")
+    a.save(p)
+    a.step(300.0)
+    b = _ens(fl, URBAN, rain, 3, real_bytes=4)
+    b.load(p)
+    b.step(300.0)
+    for i in range(3):
+        np.testing.assert_array_equal(a.field(i), b.field(i))
+
+
+# ---------------------------------------------------------------------------
+# particle filter
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(6))
+def test_systematic_resampling_bit_exact_given_weights(fl, orc, seed):
+    rng = np.random.default_rng(seed)
+    N = [1, 7, 64, 96, 513, 1024][seed]
+    w = rng.dirichlet(np.full(N, 0.2))
+    if seed % 2:
+        w[rng.integers(0, N, size=max(1, N // 5))] = 0.0
+        if w.sum() == 0:
+            w[0] = 1.0
+    u0 = float(rng.uniform())
+    np.testing.assert_array_equal(fl.flood_systematic_resample(w, u0), orc.systematic(w, u0))
+
+
+def test_assimilation_matches_oracle(fl, orc):
+    # both sides assimilate the same ensemble state (the oracle's, loaded into the GPU handle)
+    rain = W.chicago_hyetograph()
+    N = 6
+    c = W.urban_catchment("pf", 50, 44, N, W.seed_for(2, 7), n_gauges=5)
+    m = orc.Model(c.dem, c.manning, c.dx, rain, edge_kind=c.edge_kind, edge_slope=c.edge_slope)
+    ens = orc.Ensemble(m, c.n_scale, c.rain_mult)
+    ens.advance(600.0)
+    e = _ens(fl, c, rain, N, real_bytes=8)
+    for i, x in enumerate(ens.members):
+        e.set_state(i, x.h, x.qx, x.qy, 600.0)
+    before = [e.field(i) for i in range(N)]
+    for i, x in enumerate(ens.members):
+        np.testing.assert_array_equal(before[i], x.h)
+    obs = orc.gauge_values([ens.members[3]], c.gauges)[0] + 0.0002
+    sig = np.full(5, 0.001)
+    beta = np.random.default_rng(3).normal(1, 0.05, N)
+    neff_g, anc_g, res_g = e.assimilate(0, c.gauges, obs, sig, 0.8, 0.4, beta)
+    neff_o, anc_o, res_o = ens.assimilate(c.gauges, obs, sig, 0.8, 0.4, beta)
+    assert neff_g == pytest.approx(neff_o, rel=1e-12)
+    assert res_g == res_o and res_g
+    np.testing.assert_array_equal(anc_g, anc_o)
+    lw, mu, s = e.weights()
+    np.testing.assert_allclose(lw, ens.logw, rtol=1e-12)
+    np.testing.assert_allclose(mu, [x.mu for x in ens.members], rtol=1e-15)
+    for j in range(N):
+        np.testing.assert_array_equal(e.field(j), before[anc_g[j]])
+    # the filtered ensemble keeps stepping in step with the oracle
+    e.step(900.0)
+    ens.advance(900.0)
+    for j in range(N):
+        assert np.abs(e.field(j) - ens.members[j].h).max() <= 1e-4
+
+
+def test_assimilation_weights_without_resampling(fl, orc):
+    rain = W.chicago_hyetograph()
+    N = 8
+    c = W.urban_catchment("pf3", 40, 36, N, W.seed_for(2, 6), n_gauges=4)
+    m = orc.Model(c.dem, c.manning, c.dx, rain, edge_kind=c.edge_kind, edge_slope=c.edge_slope)
+    ens = orc.Ensemble(m, c.n_scale, c.rain_mult)
+    ens.advance(900.0)
+    e = _ens(fl, c, rain, N, real_bytes=4)
+    for i, x in enumerate(ens.members):
+        e.set_state(i, x.h.astype(np.float32), x.qx.astype(np.float32), x.qy.astype(np.float32), 900.0)
+    # the oracle filters the same FP32-rounded depths
+    for x in ens.members:
+        x.h = x.h.astype(np.float32).astype(np.float64)
+    obs = orc.gauge_values([ens.members[1]], c.gauges)[0]
+    sig = np.full(4, 0.5)
+    for k in range(3):     # repeated updates carry the weights forward (Eq. 10 prior = last posterior)
+        ng, ag, rg = e.assimilate(0, c.gauges, obs + 0.01 * k, sig, 0.3, 0.5)
+        no, ao, ro = ens.assimilate(c.gauges, obs + 0.01 * k, sig, 0.3, 0.5)
+        assert ng == pytest.approx(no, rel=1e-12) and rg == ro
+        np.testing.assert_allclose(e.weights()[0], ens.logw, rtol=1e-12, atol=1e-12)
+
+
+def test_assimilation_without_resampling_keeps_states(fl, orc):
+    rain = W.chicago_hyetograph()
+    c = W.urban_catchment("pf2", 30, 30, 4, W.seed_for(2, 8), n_gauges=2)
+    e = _ens(fl, c, rain, 4, real_bytes=4)
+    e.step(300.0)
+    before = [e.field(i) for i in range(4)]
+    neff, anc, res = e.assimilate(0, c.gauges, np.zeros(2), np.full(2, 100.0), 0.8, 0.5)
+    assert not res and neff == pytest.approx(4.0, rel=1e-6)
+    np.testing.assert_array_equal(anc, np.arange(4))
+    for i in range(4):
+        np.testing.assert_array_equal(e.field(i), before[i])
+
+
+def test_assimilate_requires_common_time(fl):
+    rain = W.chicago_hyetograph()
+    e = _ens(fl, URBAN, rain, 2, real_bytes=4)
+    e.step(100.0)
+    h = e.field(0)
+    e.set_state(0, h, e.field(0, fl.FIELD_QX), e.field(0, fl.FIELD_QY), 50.0)
+    with pytest.raises(fl.FloodError) as ei:
+        e.assimilate(0, URBAN.gauges, np.zeros(4), np.full(4, 0.05))
+    assert ei.value.status == fl.FLOOD_ESTATE
