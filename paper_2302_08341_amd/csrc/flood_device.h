@@ -1,0 +1,74 @@
+// Device-side helpers shared by the forward and adjoint kernels of libflood:
+// workgroup order, IEEE bit patterns, the Eq. 2 friction power, and the link
+// discharge functions (Eqs. 2-3 with the donor limiter and open edges).
+#pragma once
+
+#include "flood_internal.h"
+
+namespace flood {
+
+// Workgroups are dispatched round-robin over the 8 XCDs (id % 8).  Remap the
+// id so that each XCD walks a contiguous range of logical tiles; vertically
+// adjacent tiles then meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, i = b >> 3;
+    return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+__device__ __forceinline__ uint32_t to_bits(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ unsigned long long to_bits(double v) {
+    return (unsigned long long)__double_as_longlong(v);
+}
+template <typename T> __device__ __forceinline__ T from_bits(typename HBits<T>::type b);
+template <> __device__ __forceinline__ float from_bits<float>(uint32_t b) { return __uint_as_float(b); }
+template <> __device__ __forceinline__ double from_bits<double>(unsigned long long b) {
+    return __longlong_as_double((long long)b);
+}
+
+// h^(-7/3) of the friction denominator of Eq. 2.
+__device__ __forceinline__ float pow_m73(float h) {
+    return __builtin_amdgcn_exp2f(-2.33333333333333333f * __builtin_amdgcn_logf(h));
+}
+__device__ __forceinline__ double pow_m73(double h) { return 1.0 / pow(h, 7.0 / 3.0); }
+
+__device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
+
+// Interior link between cell 1 (west/north) and cell 2 (east/south).
+// Eq. 3 in difference form: with dz = z2 - z1, the higher surface is cell 1
+// iff h1 - h2 >= dz, and max(eta) - max(z) = h_up - max(+-dz, 0); the surface
+// slope is (h2 - h1 + dz)/dx.  Eq. 2 semi-implicit friction, then the donor
+// limiter |q| <= h_up dx / (4 dt).
+template <typename T>
+__device__ __forceinline__ T link_in(T q, T h1, T h2, T dz, T G, const MemberStep<T>& ms, T hdry) {
+    const T d = h1 - h2;
+    const T hf = (d >= dz) ? h1 - fmax(dz, T(0)) : h2 - fmax(-dz, T(0));
+    if (!(hf > hdry)) return T(0);
+    const T num = q - ms.gdtdx * hf * (dz - d);
+    const T A = G * ms.s2dt * pow_m73(hf);
+    T qn = qdiv(num, T(1) + A * fabs(q));
+    if (qn > T(0))
+        qn = fmin(qn, h1 * ms.capf);
+    else
+        qn = fmax(qn, -h2 * ms.capf);
+    return qn;
+}
+
+// Open edge link: outward discharge qo driven by the fixed outward slope Se,
+// flow depth = inner cell depth; outflow only.
+template <typename T>
+__device__ __forceinline__ T link_open(T qo, T h, T G, T Se, const MemberStep<T>& ms, T hdry) {
+    if (!(h > hdry)) return T(0);
+    const T A = G * ms.s2dt * pow_m73(h);
+    T qn = qdiv(qo + ms.gdt * h * Se, T(1) + A * fabs(qo));
+    qn = fmin(qn, h * ms.capf);
+    return fmax(qn, T(0));
+}
+
+template <typename T, int MI>
+__device__ __forceinline__ size_t state_index(const CatchDev<T>& C, int member, int r, int c) {
+    return ((size_t)(member / MI) * C.ny + r) * ((size_t)C.nx * MI) + (size_t)c * MI + member % MI;
+}
+
+}  // namespace flood

@@ -68,10 +68,12 @@ template <typename T> struct StepLaunch {
     int32_t n_catch;
     int32_t total_blocks;
     int32_t n_total;          // members over all catchments
+    int32_t recompute;        // 1: adjoint tape recomputation (see k_step)
     CatchDev<T> c[kMaxCatch];
-    const MemberStep<T>* ms;  // [n_total]
+    const MemberStep<T>* ms;  // indexed by global member
     typename HBits<T>::type* hbins;  // [kBins][n_total]
     double* vclamp;           // [n_total]
+    uint8_t* clamp_out;       // recompute only: 1 where the new depth was clamped at zero
 };
 
 struct PlanCatch {
@@ -96,9 +98,16 @@ template <typename T> struct PlanLaunch {
     double* vrain;
     typename HBits<T>::type* hbins;
     MemberStep<T>* ms;
-    double* dtlog;            // optional [n_total][dtlog_cap] step lengths (adjoint record)
+    double* dtlog;            // optional [n_total][dtlog_cap] step lengths
     double* telog;            // optional [n_total][dtlog_cap] step end times
     int32_t dtlog_cap;
+    int32_t m_begin, m_end;   // members planned by this launch (global indices)
+    // adjoint record of this launch (null when not recording), indexed by m - m_begin
+    MemberStep<T>* ms_log;
+    double* rdt_log;          // R dt of the step (rain depth per unit multiplier)
+    int32_t* tag_log;         // sample index completed by the step, or -1
+    int32_t* any_log;         // set to 1 when any member steps
+    int32_t tag_value;
 };
 
 // ---------------------------------------------------------------------------
@@ -128,6 +137,31 @@ template <typename T>
 void launch_gauges(int mi, const CatchDev<T>& C, const int32_t* par, int n_gauges, const int32_t* grc,
                    double* y, hipStream_t s);
 void launch_flush_outflow(int n_members, int nb, double* out_acc, double* vout, hipStream_t s);
+
+// adjoint (flood_adjoint.hip)
+template <typename T> struct AdjLaunch {
+    CatchDev<T> c;            // view of the member group; h[0].. = state before the step (tape slot)
+    T* lh[2];                 // adjoint of h: [0] after the step (in), [1] before (out)
+    T* lqx[2];
+    T* lqy[2];
+    T* lqw[2];
+    T* lqn[2];
+    const uint8_t* clamp;     // clamp flags of this step (state layout)
+    const MemberStep<T>* ms;  // [group members] coefficients of this step
+    const double* rdt;        // [group members]
+    double* nbar;             // [ny*nx] Manning-field adjoint (accumulated)
+    double* mubar_part;       // [blocks][group members] rain-multiplier adjoint partials (accumulated)
+};
+template <typename T> void launch_adjoint_step(int mi, const AdjLaunch<T>& A, hipStream_t s);
+template <typename T>
+void launch_inject(int mi, const CatchDev<T>& after, const int32_t* tags, int K, const int32_t* grc,
+                   const double* obs, T* lh, hipStream_t s);
+template <typename T>
+void launch_snapshot(int mi, const CatchDev<T>& C, const int32_t* par, const CatchDev<T>& dst, hipStream_t s);
+template <typename T>
+void launch_misfit(int mi, const CatchDev<T>& C, const int32_t* par, int K, const int32_t* grc,
+                   const double* obs, double* loss, hipStream_t s);
+void launch_sum_parts(int n_blocks, int n_members, const double* parts, double* out, hipStream_t s);
 
 // particle filter (flood_pf.hip)
 struct PfArgs {

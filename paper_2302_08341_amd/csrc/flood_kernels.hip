@@ -9,68 +9,9 @@
 #include <cfloat>
 #include <cmath>
 
-#include "flood_internal.h"
+#include "flood_device.h"
 
 namespace flood {
-
-// Workgroups are dispatched round-robin over the 8 XCDs (id % 8).  Remap the
-// id so that each XCD walks a contiguous range of logical tiles; vertically
-// adjacent tiles then meet in the same L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-    const int q = nb >> 3, r = nb & 7;
-    const int x = b & 7, i = b >> 3;
-    return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
-}
-
-__device__ __forceinline__ uint32_t to_bits(float v) { return __float_as_uint(v); }
-__device__ __forceinline__ unsigned long long to_bits(double v) {
-    return (unsigned long long)__double_as_longlong(v);
-}
-template <typename T> __device__ __forceinline__ T from_bits(typename HBits<T>::type b);
-template <> __device__ __forceinline__ float from_bits<float>(uint32_t b) { return __uint_as_float(b); }
-template <> __device__ __forceinline__ double from_bits<double>(unsigned long long b) {
-    return __longlong_as_double((long long)b);
-}
-
-// h^(-7/3) of the friction denominator of Eq. 2.
-__device__ __forceinline__ float pow_m73(float h) {
-    return __builtin_amdgcn_exp2f(-2.33333333333333333f * __builtin_amdgcn_logf(h));
-}
-__device__ __forceinline__ double pow_m73(double h) { return 1.0 / pow(h, 7.0 / 3.0); }
-
-__device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-__device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
-
-// Interior link between cell 1 (west/north) and cell 2 (east/south).
-// Eq. 3 in difference form: with dz = z2 - z1, the higher surface is cell 1
-// iff h1 - h2 >= dz, and max(eta) - max(z) = h_up - max(+-dz, 0); the surface
-// slope is (h2 - h1 + dz)/dx.  Eq. 2 semi-implicit friction, then the donor
-// limiter |q| <= h_up dx / (4 dt).
-template <typename T>
-__device__ __forceinline__ T link_in(T q, T h1, T h2, T dz, T G, const MemberStep<T>& ms, T hdry) {
-    const T d = h1 - h2;
-    const T hf = (d >= dz) ? h1 - fmax(dz, T(0)) : h2 - fmax(-dz, T(0));
-    if (!(hf > hdry)) return T(0);
-    const T num = q - ms.gdtdx * hf * (dz - d);
-    const T A = G * ms.s2dt * pow_m73(hf);
-    T qn = qdiv(num, T(1) + A * fabs(q));
-    if (qn > T(0))
-        qn = fmin(qn, h1 * ms.capf);
-    else
-        qn = fmax(qn, -h2 * ms.capf);
-    return qn;
-}
-
-// Open edge link: outward discharge qo driven by the fixed outward slope Se,
-// flow depth = inner cell depth; outflow only.
-template <typename T>
-__device__ __forceinline__ T link_open(T qo, T h, T G, T Se, const MemberStep<T>& ms, T hdry) {
-    if (!(h > hdry)) return T(0);
-    const T A = G * ms.s2dt * pow_m73(h);
-    T qn = qdiv(qo + ms.gdt * h * Se, T(1) + A * fabs(qo));
-    qn = fmin(qn, h * ms.capf);
-    return fmax(qn, T(0));
-}
 
 // ---------------------------------------------------------------------------
 // step planner: per-member Eq. 4 step, clipped to rain-block edges and t_end
@@ -78,8 +19,8 @@ __device__ __forceinline__ T link_open(T qo, T h, T G, T Se, const MemberStep<T>
 template <typename T>
 __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     using HB = typename HBits<T>::type;
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= P.n_total) return;
+    const int m = P.m_begin + blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= P.m_end) return;
     int ci = 0;
     for (int i = 1; i < P.n_catch; ++i)
         if (m >= P.c[i].member_off) ci = i;
@@ -91,8 +32,14 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     ms.parity = P.par[m];
     const double t = P.t[m];
     const double t_end = *P.t_end;
+    const int lm = m - P.m_begin;
     if (P.fault[m] || !(t < t_end)) {
         P.ms[m] = ms;
+        if (P.ms_log) {
+            P.ms_log[lm] = ms;
+            P.rdt_log[lm] = 0.0;
+            P.tag_log[lm] = -1;
+        }
         return;
     }
     HB hb = 0;
@@ -137,6 +84,12 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     ms.dxdt = C.dx * dt;
     ms.active = 1;
     P.ms[m] = ms;
+    if (P.ms_log) {
+        P.ms_log[lm] = ms;
+        P.rdt_log[lm] = R * dt;
+        P.tag_log[lm] = (tn == t_end) ? P.tag_value : -1;
+        P.any_log[0] = 1;
+    }
     const int64_t st = P.steps[m];
     if (P.dtlog && st < P.dtlog_cap) {
         P.dtlog[(size_t)m * P.dtlog_cap + st] = dt;
@@ -150,7 +103,8 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
 }
 
 template <typename T> void launch_plan(const PlanLaunch<T>& P, hipStream_t s) {
-    hipLaunchKernelGGL(k_plan<T>, dim3((P.n_total + 255) / 256), dim3(256), 0, s, P);
+    const int n = P.m_end - P.m_begin;
+    if (n > 0) hipLaunchKernelGGL(k_plan<T>, dim3((n + 255) / 256), dim3(256), 0, s, P);
 }
 
 // ---------------------------------------------------------------------------
@@ -184,8 +138,12 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepLaunch<T> L) {
     const int k0 = grp * C.chunks_per_group;
     const int k1 = min(k0 + C.chunks_per_group, C.n_chunks);
     const int mend = min(k1 * MI, C.n_members);
-    int any = 0;
-    for (int m = k0 * MI + (int)threadIdx.x; m < mend; m += kBlock) any |= L.ms[C.member_off + m].active;
+    // Recompute mode (adjoint tape): every member reads copy 0 and writes copy 1, members that
+    // do not step copy their state across, clamp flags are recorded, ledgers and the depth
+    // maximum are left alone.
+    const bool rec = L.recompute != 0;
+    int any = rec ? 1 : 0;
+    for (int m = k0 * MI + (int)threadIdx.x; m < mend && !rec; m += kBlock) any |= L.ms[C.member_off + m].active;
     if (!__syncthreads_or(any)) return;
 
     // shared bed and roughness of this cell and its four neighbours
@@ -244,8 +202,17 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepLaunch<T> L) {
             act = in && ms.active;
         }
         T hn = T(0);
+        if (rec && in && ml < C.n_members && !act) {
+            const size_t idx = (size_t)k * plane + ((size_t)cy * nx + cx) * MI + lane;
+            C.h[1][idx] = C.h[0][idx];
+            C.qx[1][idx] = C.qx[0][idx];
+            C.qy[1][idx] = C.qy[0][idx];
+            if (!hasW) C.qw[1][((size_t)k * ny + cy) * MI + lane] = C.qw[0][((size_t)k * ny + cy) * MI + lane];
+            if (!hasN) C.qn[1][((size_t)k * nx + cx) * MI + lane] = C.qn[0][((size_t)k * nx + cx) * MI + lane];
+            L.clamp_out[idx] = 0;
+        }
         if (act) {
-            const int sp = ms.parity, dp = sp ^ 1;
+            const int sp = rec ? 0 : ms.parity, dp = sp ^ 1;
             const T* __restrict__ hs = C.h[sp];
             const T* __restrict__ qxs = C.qx[sp];
             const T* __restrict__ qys = C.qy[sp];
@@ -279,17 +246,19 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepLaunch<T> L) {
             // Eq. 1 with the four links of Sec. 3.1 (west/east x-links, north/south y-links)
             const T dv = ((fW - fE) + fN) - fS;
             hn = (h0 + ms.dtdx * dv) + ms.rinc;
-            if (hn < T(0)) {
-                atomicAdd(&L.vclamp[C.member_off + ml], -(double)hn * (C.dx * C.dx));
+            const bool clamped = hn < T(0);
+            if (clamped) {
+                if (!rec) atomicAdd(&L.vclamp[C.member_off + ml], -(double)hn * (C.dx * C.dx));
                 hn = T(0);
             }
+            if (rec) L.clamp_out[idx] = clamped ? 1 : 0;
             if (hn == T(0)) hn = T(0);  // canonical +0 for the bit-pattern maximum
             C.h[dp][idx] = hn;
             C.qx[dp][idx] = fE;
             C.qy[dp][idx] = fS;
             if (!hasW) C.qw[dp][((size_t)k * ny + cy) * MI + lane] = fW;
             if (!hasN) C.qn[dp][((size_t)k * nx + cx) * MI + lane] = fN;
-            if (!(hasE && hasW && hasS && hasN)) {
+            if (!rec && !(hasE && hasW && hasS && hasN)) {
                 double* acc = C.out_acc + (size_t)ml * nb;
                 if (!hasN && C.edge_open[0]) acc[cx] += -(double)fN * ms.dxdt;
                 if (!hasS && C.edge_open[2]) acc[nx + cx] += (double)fS * ms.dxdt;
@@ -305,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepLaunch<T> L) {
             const HB o = __shfl_xor(v, off, 64);
             v = o > v ? o : v;
         }
-        if ((threadIdx.x & 63) < MI && ml < C.n_members && v != 0) {
+        if (!rec && (threadIdx.x & 63) < MI && ml < C.n_members && v != 0) {
             HB* a = L.hbins + (size_t)bin * L.n_total + C.member_off + ml;
             const HB cur = __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (v > cur) atomicMax(a, v);
@@ -394,11 +363,6 @@ template void launch_permute_bins<unsigned long long>(int, int, int, unsigned lo
 // ---------------------------------------------------------------------------
 // element-wise helpers over one catchment: lane = (cell, member)
 // ---------------------------------------------------------------------------
-template <typename T, int MI>
-__device__ __forceinline__ size_t state_index(const CatchDev<T>& C, int member, int r, int c) {
-    return ((size_t)(member / MI) * C.ny + r) * ((size_t)C.nx * MI) + (size_t)c * MI + member % MI;
-}
-
 // Depth maximum of the current state into bin 0 (bins must be zero);
 // blockIdx.y = member.
 template <typename T, int MI>

@@ -368,6 +368,15 @@ template <typename T> struct Impl : ImplBase {
         PL.dtlog = nullptr;
         PL.telog = nullptr;
         PL.dtlog_cap = 0;
+        PL.m_begin = 0;
+        PL.m_end = n_total;
+        PL.ms_log = nullptr;
+        PL.rdt_log = nullptr;
+        PL.tag_log = nullptr;
+        PL.any_log = nullptr;
+        PL.tag_value = -1;
+        SL.recompute = 0;
+        SL.clamp_out = nullptr;
         layout_launch();
         for (int i = 0; i < nc; ++i) launch_hmax_init<T>(mi, cats[i].dev, par, hbins, n_total, st);
         HIPCHK(hipGetLastError());
@@ -947,20 +956,330 @@ template <typename T> struct Impl : ImplBase {
     }
 };
 
-// the adjoint driver lives in flood_adjoint.hip
+// A view of members [g0, g0 + G) of catchment c (g0 a multiple of MI) over state
+// arrays laid out like the catchment's, with its own tile grid (one workgroup
+// per tile walking every chunk of the group).
 template <typename T>
-flood_status adjoint_run(Impl<T>& I, int c, double t_end, double sample_dt, int K, const int32_t* grc,
-                         const double* obs, int ckpt_every, double* loss_out, double* grad_n_out,
-                         double* grad_mult_out, std::string& err);
+static CatchDev<T> group_view(const CatchDev<T>& C, int mi, int g0, int G, T* const h[2], T* const qx[2],
+                              T* const qy[2], T* const qw[2], T* const qn[2]) {
+    CatchDev<T> v = C;
+    v.member_off = C.member_off + g0;
+    v.n_members = G;
+    v.n_chunks = (G + mi - 1) / mi;
+    v.groups = 1;
+    v.chunks_per_group = v.n_chunks;
+    v.n_blocks = v.tiles_x * v.tiles_y;
+    v.block_begin = 0;
+    for (int k = 0; k < 2; ++k) {
+        v.h[k] = h[k];
+        v.qx[k] = qx[k];
+        v.qy[k] = qy[k];
+        v.qw[k] = qw[k];
+        v.qn[k] = qn[k];
+    }
+    return v;
+}
 
 template <typename T>
 flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, const int32_t* grc, const double* obs,
                               int ckpt_every, double* loss_out, double* grad_n_out, double* grad_mult_out,
                               std::string& err) {
-    (void)c; (void)t_end; (void)sample_dt; (void)K; (void)grc; (void)obs; (void)ckpt_every;
-    (void)loss_out; (void)grad_n_out; (void)grad_mult_out;
-    err = "adjoint is not available in this build";
-    return FLOOD_ESTATE;
+    CHK(check_catch(c, err));
+    Cat& C = cats[c];
+    if (!(sample_dt > 0.0) || !finite_d(sample_dt)) { err = "sample_dt must be finite and > 0"; return FLOOD_EINVAL; }
+    if (!finite_d(t_end)) { err = "t_end must be finite"; return FLOOD_EINVAL; }
+    if (K < 0 || K > 4096) { err = "n_gauges must be in [0, 4096]"; return FLOOD_EINVAL; }
+    if (K > 0 && (!grc || !obs)) { err = "gauge_rc and obs are required"; return FLOOD_EINVAL; }
+    if (ckpt_every < 1) { err = "ckpt_every must be >= 1"; return FLOOD_EINVAL; }
+    for (int k = 0; k < K; ++k)
+        if (grc[2 * k] < 0 || grc[2 * k] >= C.ny || grc[2 * k + 1] < 0 || grc[2 * k + 1] >= C.nx) {
+            err = "gauge outside the grid";
+            return FLOOD_EINVAL;
+        }
+    double t0;
+    CHK(common_time(c, &t0, err));
+    const int S = (int)std::floor((t_end - t0) / sample_dt + 1e-9);
+    if (S < 1) { err = "no sample time in (t0, t_end]"; return FLOOD_EINVAL; }
+    for (size_t i = 0; i < (size_t)S * K; ++i)
+        if (!finite_d(obs[i])) { err = "obs must be finite"; return FLOOD_EINVAL; }
+
+    const size_t ncell = (size_t)C.ny * C.nx;
+    const int N = C.N;
+    // member groups sized so that the tape (ckpt_every + 1 states) fits in half the free memory
+    size_t free_b = 0, total_b = 0;
+    HIPCHK(hipMemGetInfo(&free_b, &total_b));
+    const size_t per_member_state = (3 * ncell + C.ny + C.nx) * sizeof(T);
+    const size_t per_member_slot = per_member_state + ncell;   // + clamp flags
+    size_t G = (size_t)(0.5 * (double)free_b) / ((size_t)(ckpt_every + 1) * per_member_slot + 8 * per_member_state);
+    G = std::min<size_t>(G, (size_t)N);
+    if (const char* eg = std::getenv("FLOOD_ADJ_GROUP")) {   // testing: force smaller member groups
+        const long v = std::atol(eg);
+        if (v > 0) G = std::min<size_t>(G, (size_t)v);
+    }
+    G = (G / mi) * mi;
+    if (G < (size_t)mi) { err = "adjoint tape does not fit in device memory"; return FLOOD_ENOMEM; }
+
+    // device scratch owned by this call
+    std::vector<void*> tmp;
+    auto talloc = [&](size_t bytes, void** p) -> flood_status {
+        hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 16));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            err = "hipMalloc of " + std::to_string(bytes) + " bytes failed in flood_adjoint";
+            return FLOOD_ENOMEM;
+        }
+        tmp.push_back(*p);
+        return FLOOD_OK;
+    };
+    struct Guard {
+        std::vector<void*>& v;
+        hipStream_t s;
+        ~Guard() {
+            (void)hipStreamSynchronize(s);
+            for (void* p : v) (void)hipFree(p);
+        }
+    } guard{tmp, st};
+
+    const int Gi = (int)G;
+    const int chunksG = (Gi + mi - 1) / mi;
+    const size_t elemsG = (size_t)chunksG * ncell * mi;
+    const size_t wG = (size_t)chunksG * C.ny * mi, nG = (size_t)chunksG * C.nx * mi;
+    const size_t slot_elems = 3 * elemsG + wG + nG;
+    const int max_launch = 1 << 20;
+    int32_t* d_grc2 = nullptr;
+    double *d_obs2 = nullptr, *d_loss = nullptr, *d_nbar = nullptr, *d_mubar = nullptr, *d_gm = nullptr;
+    CHK(talloc(2 * std::max(K, 1) * sizeof(int32_t), (void**)&d_grc2));
+    CHK(talloc((size_t)S * std::max(K, 1) * sizeof(double), (void**)&d_obs2));
+    CHK(talloc(sizeof(double), (void**)&d_loss));
+    CHK(talloc(ncell * sizeof(double), (void**)&d_nbar));
+    CHK(talloc((size_t)N * sizeof(double), (void**)&d_gm));
+    if (K > 0) {
+        HIPCHK(hipMemcpyAsync(d_grc2, grc, 2 * K * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(d_obs2, obs, (size_t)S * K * sizeof(double), hipMemcpyHostToDevice, st));
+    }
+    HIPCHK(hipMemsetAsync(d_loss, 0, sizeof(double), st));
+    HIPCHK(hipMemsetAsync(d_nbar, 0, ncell * sizeof(double), st));
+    // tape (ckpt_every + 1 slots), clamp flags (ckpt_every slots), adjoint ping-pong
+    T* tape = nullptr;
+    uint8_t* clamp = nullptr;
+    T* lam = nullptr;
+    CHK(talloc((size_t)(ckpt_every + 1) * slot_elems * sizeof(T), (void**)&tape));
+    CHK(talloc((size_t)ckpt_every * elemsG, (void**)&clamp));
+    CHK(talloc(2 * slot_elems * sizeof(T), (void**)&lam));
+    // per-launch record
+    MemberStep<T>* ms_log = nullptr;
+    double* rdt_log = nullptr;
+    int32_t *tag_log = nullptr, *any_log = nullptr;
+    const int nblk = C.dev.tiles_x * C.dev.tiles_y;
+    CHK(talloc((size_t)nblk * Gi * sizeof(double), (void**)&d_mubar));
+    size_t log_cap = 4096;
+    auto grow_log = [&](size_t need) -> flood_status {
+        if (need <= log_cap && ms_log) return FLOOD_OK;
+        size_t cap = std::max(log_cap, (size_t)4096);
+        while (cap < need) cap *= 2;
+        MemberStep<T>* a;
+        double* r;
+        int32_t *tg, *an;
+        CHK(talloc(cap * Gi * sizeof(MemberStep<T>), (void**)&a));
+        CHK(talloc(cap * Gi * sizeof(double), (void**)&r));
+        CHK(talloc(cap * Gi * sizeof(int32_t), (void**)&tg));
+        CHK(talloc(cap * sizeof(int32_t), (void**)&an));
+        HIPCHK(hipMemsetAsync(an, 0, cap * sizeof(int32_t), st));
+        if (ms_log) {
+            HIPCHK(hipMemcpyAsync(a, ms_log, log_cap * Gi * sizeof(MemberStep<T>), hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(r, rdt_log, log_cap * Gi * sizeof(double), hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(tg, tag_log, log_cap * Gi * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(an, any_log, log_cap * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+        }
+        ms_log = a;
+        rdt_log = r;
+        tag_log = tg;
+        any_log = an;
+        log_cap = cap;
+        return FLOOD_OK;
+    };
+
+    const int off = C.dev.member_off;
+    launch_flush_outflow(N, 2 * (C.nx + C.ny), C.dev.out_acc, vout + off, st);
+    std::vector<double> gm_host(N, 0.0);
+
+    for (int g0 = 0; g0 < N; g0 += Gi) {
+        const int Gg = std::min(Gi, N - g0);
+        const int chunk0 = g0 / mi;
+        auto at = [&](T* base) { return base + (size_t)chunk0 * ncell * mi; };
+        auto atw = [&](T* base) { return base + (size_t)chunk0 * C.ny * mi; };
+        auto atn = [&](T* base) { return base + (size_t)chunk0 * C.nx * mi; };
+        T* mh[2] = {at(C.dev.h[0]), at(C.dev.h[1])};
+        T* mqx[2] = {at(C.dev.qx[0]), at(C.dev.qx[1])};
+        T* mqy[2] = {at(C.dev.qy[0]), at(C.dev.qy[1])};
+        T* mqw[2] = {atw(C.dev.qw[0]), atw(C.dev.qw[1])};
+        T* mqn[2] = {atn(C.dev.qn[0]), atn(C.dev.qn[1])};
+        CatchDev<T> V = group_view(C.dev, mi, g0, Gg, mh, mqx, mqy, mqw, mqn);
+        V.out_acc = C.dev.out_acc + (size_t)g0 * 2 * (C.nx + C.ny);
+        // slot j of the tape as a view (copy 0 = slot j, copy 1 = slot j + 1)
+        auto slot_view = [&](T* base, int j) {
+            T* sh[2];
+            T* sx[2];
+            T* sy[2];
+            T* sw[2];
+            T* sn[2];
+            for (int k = 0; k < 2; ++k) {
+                T* b = base + (size_t)(j + k) * slot_elems;
+                sh[k] = b;
+                sx[k] = b + elemsG;
+                sy[k] = b + 2 * elemsG;
+                sw[k] = b + 3 * elemsG;
+                sn[k] = b + 3 * elemsG + wG;
+            }
+            return group_view(C.dev, mi, g0, Gg, sh, sx, sy, sw, sn);
+        };
+        StepLaunch<T> SLg = SL;
+        SLg.n_catch = 1;
+        SLg.c[0] = V;
+        SLg.c[0].groups = (V.n_chunks + std::max(1, std::min(C.cpb, V.n_chunks)) - 1) /
+                          std::max(1, std::min(C.cpb, V.n_chunks));
+        SLg.c[0].chunks_per_group = std::max(1, std::min(C.cpb, V.n_chunks));
+        SLg.c[0].n_blocks = V.tiles_x * V.tiles_y * SLg.c[0].groups;
+        SLg.total_blocks = SLg.c[0].n_blocks;
+        SLg.recompute = 0;
+        PlanLaunch<T> PLg = PL;
+        PLg.m_begin = off + g0;
+        PLg.m_end = off + g0 + Gg;
+
+        // ---------------- forward with record and checkpoints ----------------
+        std::vector<T*> ckpts;
+        int64_t L = 0;
+        CHK(grow_log(4096));
+        HIPCHK(hipMemsetAsync(any_log, 0, log_cap * sizeof(int32_t), st));
+        for (int smp = 0; smp < S; ++smp) {
+            *h_tend = t0 + (double)(smp + 1) * sample_dt;
+            HIPCHK(hipMemcpyAsync(d_tend, h_tend, sizeof(double), hipMemcpyHostToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (;;) {
+                const int B = 4;
+                CHK(grow_log((size_t)L + B + 1));
+                for (int i = 0; i < B; ++i) {
+                    if (L % ckpt_every == 0) {
+                        T* ck;
+                        CHK(talloc(slot_elems * sizeof(T), (void**)&ck));
+                        ckpts.push_back(ck);
+                        T* ch[2] = {ck, ck};
+                        T* cx[2] = {ck + elemsG, ck + elemsG};
+                        T* cyy[2] = {ck + 2 * elemsG, ck + 2 * elemsG};
+                        T* cw[2] = {ck + 3 * elemsG, ck + 3 * elemsG};
+                        T* cn[2] = {ck + 3 * elemsG + wG, ck + 3 * elemsG + wG};
+                        CatchDev<T> D = group_view(C.dev, mi, g0, Gg, ch, cx, cyy, cw, cn);
+                        launch_snapshot<T>(mi, V, par, D, st);
+                    }
+                    PLg.ms_log = ms_log + (size_t)L * Gi;
+                    PLg.rdt_log = rdt_log + (size_t)L * Gi;
+                    PLg.tag_log = tag_log + (size_t)L * Gi;
+                    PLg.any_log = any_log + L;
+                    PLg.tag_value = smp;
+                    launch_plan<T>(PLg, st);
+                    launch_step_mi<T>(mi, SLg, st);
+                    ++L;
+                }
+                launch_count_active(Gg, t + off + g0, fault + off + g0, d_tend, status, d_count, st);
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipMemcpyAsync(h_count, d_count, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                if (h_count[1]) {
+                    err = "a member produced a non-finite depth during the adjoint forward";
+                    return FLOOD_ENUMERIC;
+                }
+                if (h_count[0] == 0) break;
+                if (L > max_launch) {
+                    err = "adjoint forward exceeded the launch limit";
+                    return FLOOD_ESTATE;
+                }
+            }
+            launch_misfit<T>(mi, V, par, K, d_grc2, d_obs2 + (size_t)smp * K, d_loss, st);
+        }
+        std::vector<int32_t> any_h(L);
+        HIPCHK(hipMemcpyAsync(any_h.data(), any_log, L * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+
+        // ---------------- reverse sweep ----------------
+        HIPCHK(hipMemsetAsync(lam, 0, 2 * slot_elems * sizeof(T), st));
+        HIPCHK(hipMemsetAsync(d_mubar, 0, (size_t)nblk * Gi * sizeof(double), st));
+        int cur = 0;
+        auto lam_view = [&](int which, T** lh, T** lqx, T** lqy, T** lqw, T** lqn) {
+            T* b = lam + (size_t)which * slot_elems;
+            *lh = b;
+            *lqx = b + elemsG;
+            *lqy = b + 2 * elemsG;
+            *lqw = b + 3 * elemsG;
+            *lqn = b + 3 * elemsG + wG;
+        };
+        const int n_ck = (int)ckpts.size();
+        for (int ck = n_ck - 1; ck >= 0; --ck) {
+            const int64_t L0 = (int64_t)ck * ckpt_every;
+            const int64_t L1 = std::min<int64_t>(L0 + ckpt_every, L);
+            std::vector<int64_t> useful;
+            for (int64_t l = L0; l < L1; ++l)
+                if (any_h[l]) useful.push_back(l);
+            if (useful.empty()) continue;
+            HIPCHK(hipMemcpyAsync(tape, ckpts[ck], slot_elems * sizeof(T), hipMemcpyDeviceToDevice, st));
+            const int n = (int)useful.size();
+            for (int j = 0; j < n; ++j) {
+                StepLaunch<T> R = SLg;
+                R.recompute = 1;
+                R.c[0] = slot_view(tape, j);
+                R.c[0].groups = 1;
+                R.c[0].chunks_per_group = R.c[0].n_chunks;
+                R.c[0].n_blocks = R.c[0].tiles_x * R.c[0].tiles_y;
+                R.total_blocks = R.c[0].n_blocks;
+                R.ms = ms_log + (size_t)useful[j] * Gi - (off + g0);
+                R.clamp_out = clamp + (size_t)j * elemsG;
+                launch_step_mi<T>(mi, R, st);
+            }
+            for (int j = n - 1; j >= 0; --j) {
+                const int64_t l = useful[j];
+                CatchDev<T> after = slot_view(tape, j + 1);
+                T *lh0, *lqx0, *lqy0, *lqw0, *lqn0, *lh1, *lqx1, *lqy1, *lqw1, *lqn1;
+                lam_view(cur, &lh0, &lqx0, &lqy0, &lqw0, &lqn0);
+                lam_view(cur ^ 1, &lh1, &lqx1, &lqy1, &lqw1, &lqn1);
+                launch_inject<T>(mi, after, tag_log + (size_t)l * Gi, K, d_grc2, d_obs2, lh0, st);
+                AdjLaunch<T> A{};
+                A.c = slot_view(tape, j);
+                A.lh[0] = lh0;
+                A.lh[1] = lh1;
+                A.lqx[0] = lqx0;
+                A.lqx[1] = lqx1;
+                A.lqy[0] = lqy0;
+                A.lqy[1] = lqy1;
+                A.lqw[0] = lqw0;
+                A.lqw[1] = lqw1;
+                A.lqn[0] = lqn0;
+                A.lqn[1] = lqn1;
+                A.clamp = clamp + (size_t)j * elemsG;
+                A.ms = ms_log + (size_t)l * Gi;
+                A.rdt = rdt_log + (size_t)l * Gi;
+                A.nbar = d_nbar;
+                A.mubar_part = d_mubar;
+                launch_adjoint_step<T>(mi, A, st);
+                cur ^= 1;
+            }
+            HIPCHK(hipGetLastError());
+        }
+        launch_sum_parts(nblk, Gg, d_mubar, d_gm + g0, st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        for (T* p : ckpts) {
+            auto it = std::find(tmp.begin(), tmp.end(), (void*)p);
+            if (it != tmp.end()) tmp.erase(it);
+            (void)hipFree(p);
+        }
+    }
+    double loss_h = 0.0;
+    HIPCHK(hipMemcpyAsync(&loss_h, d_loss, sizeof(double), hipMemcpyDeviceToHost, st));
+    if (grad_n_out) HIPCHK(hipMemcpyAsync(grad_n_out, d_nbar, ncell * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (grad_mult_out) HIPCHK(hipMemcpyAsync(grad_mult_out, d_gm, N * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (loss_out) *loss_out = loss_h;
+    (void)gm_host;
+    return FLOOD_OK;
 }
 
 flood_status create_impl(flood_handle* h, int n_catch, const flood_grid* grids, const flood_params* params,

@@ -1,0 +1,185 @@
+"""GPU discrete adjoint (flood_adjoint) against the FP64 oracle's adjoint and
+central finite differences.
+
+Bars: FP64 handle vs oracle adjoint 1e-8 relative; FP32 handle vs oracle
+adjoint 1e-3 relative (rain-multiplier gradient per member, Manning-field
+gradient in the 2-norm); central differences of the FP64 GPU loss (1e-3
+relative perturbation, fixed step so the step sequence does not move) within
+1e-3 for the FP32 adjoint and 1e-4 for the FP64 adjoint.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2302_08341_amd import flood
+    flood.load_library()
+    return flood
+
+
+def _smooth(ny=24, nx=20, n_members=3, seed=4):
+    rng = np.random.default_rng(seed)
+    r = np.arange(ny)[:, None]
+    c = np.arange(nx)[None, :]
+    z = (0.02 * (r + 0.7 * c) + rng.uniform(0.0, 0.003, size=(ny, nx))).astype(np.float32)
+    n = rng.uniform(0.02, 0.05, size=(ny, nx)).astype(np.float32)
+    h0 = (0.4 + rng.uniform(0.0, 0.01, size=(ny, nx))).astype(np.float32)
+    s = np.array([1.05, 0.9, 1.2, 1.0][:n_members])
+    mu = np.array([1.3, 0.7, 1.0, 1.1][:n_members])
+    g = np.array([[3, 4], [9, 2], [12, 9], [20, 15]], dtype=np.int32)
+    return z, n, h0, s, mu, g
+
+
+def _oracle_adjoint(orc, z, n, rain, ri, edges, slopes, s, mu, h0, t0_state, t_end, sdt, g, obs, ckpt,
+                    **model_kw):
+    m = orc.Model(z, n, 3.0, np.asarray(rain), rain_interval=ri, edge_kind=edges, edge_slope=slopes, **model_kw)
+    L = 0.0
+    gn = np.zeros(z.shape)
+    gm = []
+    for i in range(len(s)):
+        if t0_state is None:
+            mem = orc.Member.dry(m, s=s[i], mu=mu[i], h0=h0)
+        else:
+            hh, qx, qy, t0 = t0_state[i]
+            mem = orc.Member(hh.copy(), qx.copy(), qy.copy(), t=t0, s=s[i], mu=mu[i])
+        Li, gni, gmi, _ = orc.adjoint(m, mem, t_end, sdt, g, obs, ckpt_every=ckpt)
+        L += Li
+        gn += gni
+        gm.append(gmi)
+    return L, gn, np.array(gm)
+
+
+def _ens(fl, z, n, h0, s, mu, rain, ri, edges, slopes, **kw):
+    cat = dict(dem=z, manning=n, dx=3.0, edge_kind=edges, edge_slope=slopes, n_members=len(s), n_scale=s,
+               rain_mult=mu, h0=h0)
+    return fl.FloodEnsemble([cat], rain, rain_interval=ri, **kw)
+
+
+EDGES = (1, 1, 1, 1)
+SLOPES = (1e-3, 2e-3, 3e-3, 1.5e-3)
+
+
+def test_adjoint_fp64_matches_oracle(fl, orc):
+    z, n, h0, s, mu, g = _smooth()
+    rain = [2e-4, 1e-4]
+    obs = np.random.default_rng(0).uniform(0.3, 0.5, size=(4, len(g)))
+    e = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, real_bytes=8, cfl_alpha=0.5, dt_cap=5.0)
+    L, gn, gm = e.adjoint(0, 40.0, 10.0, g, obs, ckpt_every=7)
+    Lo, gno, gmo = _oracle_adjoint(orc, z, n, rain, 20.0, EDGES, SLOPES, s, mu, h0, None, 40.0, 10.0, g, obs, 7,
+                                   alpha=0.5, dt_cap=5.0)
+    assert L == pytest.approx(Lo, rel=1e-10)
+    np.testing.assert_allclose(gm, gmo, rtol=1e-8)
+    assert np.linalg.norm(gn - gno) <= 1e-8 * np.linalg.norm(gno)
+    assert e.ledger()["t"][0] == 40.0
+
+
+def test_adjoint_fp32_matches_oracle_on_wet_urban_state(fl, orc):
+    N = 3
+    c = W.urban_catchment("adj", 64, 56, N, W.seed_for(3, 1), n_gauges=6)
+    rain = W.chicago_hyetograph()
+    m = orc.Model(c.dem, c.manning, c.dx, rain, edge_kind=c.edge_kind, edge_slope=c.edge_slope)
+    states = []
+    for i in range(N):
+        mem = orc.Member.dry(m, s=c.n_scale[i], mu=c.rain_mult[i])
+        orc.advance(m, mem, 1200.0)
+        states.append(tuple(a.astype(np.float32).astype(np.float64) for a in (mem.h, mem.qx, mem.qy)) + (1200.0,))
+    obs = np.random.default_rng(2).uniform(0.0, 0.05, size=(30, 6))
+    e = _ens(fl, c.dem, c.manning, None, c.n_scale, c.rain_mult, rain, 300.0, c.edge_kind, c.edge_slope,
+             real_bytes=4)
+    for i in range(N):
+        e.set_state(i, *states[i])
+    L, gn, gm = e.adjoint(0, 1500.0, 10.0, c.gauges, obs, ckpt_every=50)
+    Lo, gno, gmo = _oracle_adjoint(orc, c.dem, c.manning, rain, 300.0, c.edge_kind, c.edge_slope, c.n_scale,
+                                   c.rain_mult, None, states, 1500.0, 10.0, c.gauges, obs, 50)
+    assert L == pytest.approx(Lo, rel=1e-4)
+    np.testing.assert_allclose(gm, gmo, rtol=1e-3)
+    assert np.linalg.norm(gn - gno) <= 1e-3 * np.linalg.norm(gno)
+
+
+def _adj_fixed(fl, z, n, h0, s, mu, g, obs, rain, rb):
+    e = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, real_bytes=rb, dt_fixed=0.25)
+    return e.adjoint(0, 40.0, 10.0, g, obs, ckpt_every=25)
+
+
+@pytest.mark.parametrize("rb,tol", [(8, 1e-4), (4, 1e-3)])
+def test_adjoint_central_differences(fl, rb, tol):
+    # fixed step, so perturbed runs keep the step sequence; central differences of the
+    # FP64 GPU forward loss with a 1e-3 relative perturbation (truncation error of the
+    # central difference is O(eps^2) relative to the curvature, a few 1e-5 here)
+    z, n, h0, s, mu, g = _smooth()
+    rain = [1e-3, 5e-4]
+    obs = np.random.default_rng(0).uniform(0.3, 0.5, size=(4, len(g)))
+    L, gn, gm = _adj_fixed(fl, z, n, h0, s, mu, g, obs, rain, rb)
+    eps = 1e-3
+    for i in range(len(s)):
+        mp, mm = mu.copy(), mu.copy()
+        mp[i] *= 1 + eps
+        mm[i] *= 1 - eps
+        fd = (_adj_fixed(fl, z, n, h0, s, mp, g, obs, rain, 8)[0]
+              - _adj_fixed(fl, z, n, h0, s, mm, g, obs, rain, 8)[0]) / (2 * eps * mu[i])
+        assert gm[i] == pytest.approx(fd, rel=tol)
+    v = np.random.default_rng(5).standard_normal(n.shape)
+    dn = 1e-3 * n.astype(np.float64) * v
+    n_p = (n.astype(np.float64) + dn).astype(np.float32)    # the library takes the field in FP32
+    n_m = (n.astype(np.float64) - dn).astype(np.float32)
+    dn_eff = (n_p.astype(np.float64) - n_m.astype(np.float64)) / 2.0
+    fd = (_adj_fixed(fl, z, n_p, h0, s, mu, g, obs, rain, 8)[0] - _adj_fixed(fl, z, n_m, h0, s, mu, g, obs, rain, 8)[0]) / 2.0
+    assert float(np.sum(gn * dn_eff)) == pytest.approx(fd, rel=tol)
+
+
+def test_adjoint_checkpoint_interval_and_groups_are_consistent(fl, monkeypatch):
+    z, n, h0, s, mu, g = _smooth(n_members=4)
+    rain = [2e-4, 1e-4]
+    obs = np.random.default_rng(0).uniform(0.3, 0.5, size=(4, len(g)))
+    ref = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, real_bytes=4).adjoint(0, 40.0, 10.0, g, obs, 1000)
+    other = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, real_bytes=4).adjoint(0, 40.0, 10.0, g, obs, 3)
+    assert other[0] == ref[0]
+    np.testing.assert_array_equal(other[2], ref[2])
+    np.testing.assert_array_equal(other[1], ref[1])
+    monkeypatch.setenv("FLOOD_ADJ_GROUP", "1")
+    grp = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, real_bytes=4, member_interleave=1).adjoint(
+        0, 40.0, 10.0, g, obs, 5)
+    assert grp[0] == pytest.approx(ref[0], rel=1e-12)
+    np.testing.assert_array_equal(grp[2], ref[2])
+    assert np.linalg.norm(grp[1] - ref[1]) <= 1e-6 * np.linalg.norm(ref[1])
+
+
+def test_adjoint_interleave_variants_agree(fl):
+    z, n, h0, s, mu, g = _smooth(n_members=4)
+    rain = [2e-4, 1e-4]
+    obs = np.random.default_rng(0).uniform(0.3, 0.5, size=(4, len(g)))
+    res = [_ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, real_bytes=4, member_interleave=mi).adjoint(
+        0, 40.0, 10.0, g, obs, 10) for mi in (1, 2, 4)]
+    for r in res[1:]:
+        assert r[0] == res[0][0]
+        # per-workgroup partial sums group cells differently for each interleave
+        np.testing.assert_allclose(r[2], res[0][2], rtol=1e-6)
+        assert np.linalg.norm(r[1] - res[0][1]) <= 1e-6 * np.linalg.norm(res[0][1])
+
+
+def test_autograd_function(fl):
+    import torch
+    from paper_2302_08341_amd.autograd import FloodAdjointFn
+    z, n, h0, s, mu, g = _smooth()
+    rain = [2e-4, 1e-4]
+    obs = np.random.default_rng(0).uniform(0.3, 0.5, size=(4, len(g)))
+    e = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, real_bytes=4)
+    before = e.field(1)
+    nt = torch.tensor(n, dtype=torch.float64, requires_grad=True)
+    mt = torch.tensor(mu, dtype=torch.float64, requires_grad=True)
+    spec = dict(t_end=40.0, sample_dt=10.0, gauges=g, obs=obs, ckpt_every=10)
+    loss = FloodAdjointFn.apply(nt, mt, e, spec)
+    (2.0 * loss).backward()
+    np.testing.assert_array_equal(e.field(1), before)       # state restored
+    ref = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, real_bytes=4).adjoint(0, 40.0, 10.0, g, obs, 10)
+    assert float(loss) == ref[0]
+    np.testing.assert_allclose(nt.grad.numpy(), 2.0 * ref[1], rtol=1e-6)
+    np.testing.assert_allclose(mt.grad.numpy(), 2.0 * ref[2], rtol=1e-6)
