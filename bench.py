@@ -81,6 +81,13 @@ def main():
     ap.add_argument("--mi", type=int, default=0)
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--cpb", type=int, default=0)
+    ap.add_argument("--kernel", type=int, default=0, help="0 autotune, 1 tiled, 2 row-marching")
+    ap.add_argument("--kernel-only", type=int, default=0,
+                    help="after the warm-up, time this many single steps in which every member steps")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the run, copy a 1 GiB device buffer (counter calibration for profiling)")
+    ap.add_argument("--march-rows", type=int, default=0)
+    ap.add_argument("--march-members", type=int, default=0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -121,7 +128,8 @@ def main():
     draws = [W.pf_draws(rng, N) for _ in range(n_cycles)]
 
     ens = FloodEnsemble.from_workload(wl, member_interleave=args.mi, tile_rows=args.rows,
-                                      chunks_per_block=args.cpb)
+                                      chunks_per_block=args.cpb, step_kernel=args.kernel,
+                                      march_rows=args.march_rows, march_members=args.march_members)
     conf = ens.config()
     resampled = []
 
@@ -134,6 +142,36 @@ def main():
     for k in range(args.warmup):
         cycle(k)
     torch.cuda.synchronize()
+    if args.kernel_only:
+        # every launch steps every member: single steps of 0.02 s, shorter than Eq. 4 allows here
+        t = args.warmup * args.window
+        l0 = ens.ledger()
+        ens.timing(True)
+        for i in range(args.kernel_only):
+            ens.step(t + 0.02 * (i + 1))
+        ens.timing(False)
+        l1 = ens.ledger()
+        avg_ms, launches = ens.get_timing()
+        steps = int((l1["steps"] - l0["steps"]).sum())
+        full = steps // args.kernel_only
+        gbs = BYTES_PER_MCU * full * ncell / (avg_ms * 1e-3) / 1e9 if launches == args.kernel_only else None
+        # attainable streaming bandwidth: one elementwise kernel reading and writing 2 GiB each
+        x = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
+        ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        y = x + 1.0
+        torch.cuda.synchronize()
+        ea.record()
+        for _ in range(5):
+            y = x + 1.0
+        eb.record()
+        torch.cuda.synchronize()
+        copy_gbs = 5 * 2 * x.numel() * 4 / (ea.elapsed_time(eb) * 1e-3) / 1e9
+        del x, y
+        print(json.dumps({"kernel_only": True, "members_per_launch": full, "real_launches": args.kernel_only,
+                          "timed_launches": launches, "avg_launch_ms": avg_ms, "algorithmic_GBps": gbs,
+                          "elementwise_copy_GBps": copy_gbs,
+                          "config": ens.config()}))
+        return
     led0 = ens.ledger()
     if not args.no_kernel_timing:
         ens.timing(True)
@@ -160,7 +198,8 @@ def main():
         achieved = BYTES_PER_MCU * mcu_per_launch / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_step (fused link + continuity step)",
+                "kernel": "k_march (row-marching fused step)" if conf["step_kernel"] == 2
+                          else "k_step (tiled fused step)",
                 "avg_launch_ms": round(avg_ms, 4), "launches": launches,
                 "algorithmic_bytes_per_launch": round(BYTES_PER_MCU * mcu_per_launch)}
 
@@ -182,13 +221,21 @@ def main():
                    "cells": ncell, "members": N, "window_s": args.window,
                    "sim_time_s": [args.warmup * args.window, n_cycles * args.window],
                    "member_interleave": conf["member_interleave"], "tile_rows": conf["tile_rows"],
-                   "chunks_per_block": conf["chunks_per_block"], "graph_steps": conf["graph_steps"]},
+                   "chunks_per_block": conf["chunks_per_block"], "step_kernel": conf["step_kernel"],
+                   "march_rows": conf["march_rows"], "march_members": conf["march_members"]},
         "roofline": roof,
         "cpu_baseline": cpu,
         "detail": {"member_steps": member_steps, "mcu": mcu, "elapsed_s": elapsed,
                    "resampled": resampled[args.warmup:], "mass_balance_rel": mass,
                    "paper_context": "8x P100: 4.69e10 MCU/s (96 x 4.0 M cells x 14,400 steps in 118 s)"},
     }
+    if args.copy_calibration:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        y = x + 1.0          # one elementwise kernel: reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del y
+        out["detail"]["copy_calibration_bytes"] = 2 * x.numel() * 4
     print(json.dumps(out))
 
 

@@ -83,6 +83,11 @@ typedef struct flood_params {
                                   Must agree across catchments of one handle. */
     int32_t tile_rows;         /* 0: autotune; else 1, 2, 4 or 8 cell rows per 256-lane tile */
     int32_t chunks_per_block;  /* 0: autotune; else member chunks processed by one workgroup */
+    int32_t step_kernel;       /* 0: autotune; 1: tiled kernel; 2: row-marching kernel; 3: vectorised
+                                  row-marching kernel (2 and 3 need member_interleave 1, i.e. members
+                                  stored in planes; 3 also needs nx a multiple of 4 (FP32) or 2 (FP64)) */
+    int32_t march_rows;        /* 0: autotune; else rows per strip of the row-marching kernel, 1..4096 */
+    int32_t march_members;     /* 0: autotune; else members marched together by one wavefront: 1, 2, 4, 8 */
 } flood_params;
 
 typedef struct flood_handle flood_handle;
@@ -189,9 +194,12 @@ flood_status flood_save(flood_handle* h, const char* path);
 flood_status flood_load(flood_handle* h, const char* path);
 
 /* Kernel configuration in use: member interleave, tile rows and chunks per
- * workgroup of catchment 0, and the number of steps captured per graph. */
+ * workgroup of catchment 0, the number of steps captured per graph, the step
+ * kernel variant (1 tiled, 2 row-marching, 3 vectorised row-marching), its rows per strip and members per
+ * wavefront.  Any output may be NULL. */
 flood_status flood_get_config(const flood_handle* h, int32_t* member_interleave, int32_t* tile_rows,
-                              int32_t* chunks_per_block, int32_t* graph_steps);
+                              int32_t* chunks_per_block, int32_t* graph_steps, int32_t* step_kernel,
+                              int32_t* march_rows, int32_t* march_members);
 
 /* Average duration in ms of the step kernel over the timed region opened by
  * flood_timing(h, 1) and closed by flood_timing(h, 0); per-launch HIP events

@@ -96,6 +96,16 @@ flood_status validate_params(const flood_params* p, std::string& err) {
     }
     if (p->tile_rows != 0 && !pow2_in(p->tile_rows, 1, 8)) { err = "tile_rows must be 0, 1, 2, 4 or 8"; return FLOOD_EINVAL; }
     if (p->chunks_per_block < 0) { err = "chunks_per_block must be >= 0"; return FLOOD_EINVAL; }
+    if (p->step_kernel < 0 || p->step_kernel > 3) { err = "step_kernel must be 0, 1, 2 or 3"; return FLOOD_EINVAL; }
+    if (p->step_kernel >= 2 && p->member_interleave > 1) {
+        err = "the row-marching kernels need member_interleave 1";
+        return FLOOD_EINVAL;
+    }
+    if (p->march_rows < 0 || p->march_rows > 4096) { err = "march_rows must be in [0, 4096]"; return FLOOD_EINVAL; }
+    if (p->march_members != 0 && !pow2_in(p->march_members, 1, 8)) {
+        err = "march_members must be 0, 1, 2, 4 or 8";
+        return FLOOD_EINVAL;
+    }
     return FLOOD_OK;
 }
 
@@ -137,6 +147,10 @@ flood_status flood_create_batch(int32_t n_catch, const flood_grid* grids, const 
         }
         if (params[i].member_interleave != params[0].member_interleave) {
             g_create_error = "member_interleave must agree across catchments";
+            return FLOOD_EINVAL;
+        }
+        if (params[i].step_kernel != params[0].step_kernel) {
+            g_create_error = "step_kernel must agree across catchments";
             return FLOOD_EINVAL;
         }
         const int N = members_per_catch[i];
@@ -247,9 +261,10 @@ flood_status flood_load(flood_handle* h, const char* path) {
     return h->impl->load(path, h->err);
 }
 
-flood_status flood_get_config(const flood_handle* h, int32_t* mi, int32_t* tile_rows, int32_t* cpb, int32_t* gsteps) {
+flood_status flood_get_config(const flood_handle* h, int32_t* mi, int32_t* tile_rows, int32_t* cpb, int32_t* gsteps,
+                              int32_t* step_kernel, int32_t* march_rows, int32_t* march_members) {
     if (!h || !h->impl) return FLOOD_EINVAL;
-    h->impl->get_config(mi, tile_rows, cpb, gsteps);
+    h->impl->get_config(mi, tile_rows, cpb, gsteps, step_kernel, march_rows, march_members);
     return FLOOD_OK;
 }
 

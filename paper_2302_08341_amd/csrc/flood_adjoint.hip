@@ -274,7 +274,12 @@ __global__ __launch_bounds__(kBlock) void k_adj(const AdjLaunch<T> A) {
         }
         __syncthreads();
     }
-    if (in && nacc != T(0)) A.nbar[c0] += (double)nacc;
+    // the MI lanes of a cell hold different members' contributions to the same
+    // Manning-field entry: combine them before the single read-modify-write
+    double nsum = (double)nacc;
+#pragma unroll
+    for (int off = 1; off < MI; off <<= 1) nsum += __shfl_xor(nsum, off, 64);
+    if (in && lane == 0 && nsum != 0.0) A.nbar[c0] += nsum;
 }
 
 template <typename T> void launch_adjoint_step(int mi, const AdjLaunch<T>& A, hipStream_t s) {

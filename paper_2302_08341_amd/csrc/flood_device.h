@@ -39,31 +39,29 @@ __device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
 // Eq. 3 in difference form: with dz = z2 - z1, the higher surface is cell 1
 // iff h1 - h2 >= dz, and max(eta) - max(z) = h_up - max(+-dz, 0); the surface
 // slope is (h2 - h1 + dz)/dx.  Eq. 2 semi-implicit friction, then the donor
-// limiter |q| <= h_up dx / (4 dt).
+// limiter |q| <= h_up dx / (4 dt).  Evaluated without branches and selected at
+// the end, so dry and wet links in one wavefront do not split it; a dry link's
+// intermediate values (possibly inf or NaN from the friction power) are
+// discarded by the final select.
 template <typename T>
 __device__ __forceinline__ T link_in(T q, T h1, T h2, T dz, T G, const MemberStep<T>& ms, T hdry) {
     const T d = h1 - h2;
     const T hf = (d >= dz) ? h1 - fmax(dz, T(0)) : h2 - fmax(-dz, T(0));
-    if (!(hf > hdry)) return T(0);
     const T num = q - ms.gdtdx * hf * (dz - d);
     const T A = G * ms.s2dt * pow_m73(hf);
-    T qn = qdiv(num, T(1) + A * fabs(q));
-    if (qn > T(0))
-        qn = fmin(qn, h1 * ms.capf);
-    else
-        qn = fmax(qn, -h2 * ms.capf);
-    return qn;
+    const T qn = qdiv(num, T(1) + A * fabs(q));
+    const T lim = (qn > T(0)) ? fmin(qn, h1 * ms.capf) : fmax(qn, -h2 * ms.capf);
+    return (hf > hdry) ? lim : T(0);
 }
 
 // Open edge link: outward discharge qo driven by the fixed outward slope Se,
 // flow depth = inner cell depth; outflow only.
 template <typename T>
 __device__ __forceinline__ T link_open(T qo, T h, T G, T Se, const MemberStep<T>& ms, T hdry) {
-    if (!(h > hdry)) return T(0);
     const T A = G * ms.s2dt * pow_m73(h);
-    T qn = qdiv(qo + ms.gdt * h * Se, T(1) + A * fabs(qo));
-    qn = fmin(qn, h * ms.capf);
-    return fmax(qn, T(0));
+    const T qn = qdiv(qo + ms.gdt * h * Se, T(1) + A * fabs(qo));
+    const T lim = fmax(fmin(qn, h * ms.capf), T(0));
+    return (h > hdry) ? lim : T(0);
 }
 
 template <typename T, int MI>

@@ -51,6 +51,11 @@ template <typename T> struct CatchDev {
     int32_t block_begin;      // first linear workgroup of this catchment in a launch
     int32_t n_blocks;
     int32_t edge_open[4];
+    // row-march variant (members in planes): strips of 62 cells x march_rows rows,
+    // one wavefront per (strip, group of march_seg members)
+    int32_t march_rows, strips_x, strips_y;
+    int32_t wave_begin, n_waves;
+    int32_t march_order;      // 0: member groups fastest, 1: strips along x fastest
     T edge_slope[4];
     T hdry, g;
     double dx;
@@ -116,6 +121,10 @@ template <typename T> struct PlanLaunch {
 template <typename T> void launch_plan(const PlanLaunch<T>& P, hipStream_t s);
 template <typename T, int MI> void launch_step(const StepLaunch<T>& L, hipStream_t s);
 template <typename T> void launch_step_mi(int mi, const StepLaunch<T>& L, hipStream_t s);
+template <typename T> void launch_march(const StepLaunch<T>& L, int seg, int total_waves, hipStream_t s);
+// cells per lane of the vectorised row-marching kernel (nx must be a multiple of it)
+template <typename T> constexpr int march_vec() { return sizeof(T) == 4 ? 4 : 2; }
+template <typename T> void launch_marchv(const StepLaunch<T>& L, int nt, int total_waves, hipStream_t s);
 void launch_count_active(int n_total, const double* t, const int32_t* fault, const double* t_end,
                          const int32_t* status, int32_t* out, hipStream_t s);
 template <typename HB> void launch_zero_bins(int off, int n, int n_total, HB* bins, hipStream_t s);

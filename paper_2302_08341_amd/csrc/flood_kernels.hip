@@ -543,3 +543,458 @@ template void launch_gauges<double>(int, const CatchDev<double>&, const int32_t*
                                     hipStream_t);
 
 }  // namespace flood
+
+namespace flood {
+
+// ---------------------------------------------------------------------------
+// Row-marching step for members stored in planes (MI = 1).
+//
+// One wavefront handles SEG members on a strip 62 cells wide and `march_rows`
+// rows tall.  Lane l holds cell x0 - 1 + l: lanes 0 and 63 are halo cells that
+// only supply their values to the neighbouring lanes, so horizontal neighbours
+// (depth, bed, roughness, the east link of the lane to the left) come from
+// lane shuffles.  Walking down the strip, the next row's depth, bed and
+// roughness are loaded once and carried into the following iteration, and the
+// new south link of a row is the north link of the next, so every state
+// element is read once and written once; the bed and roughness rows are shared
+// by the SEG members, whose independent streams keep more loads in flight per
+// wavefront.  Whether a member steps is uniform across the wavefront, so idle
+// members cost no divergence.  Each cell evaluates the same link functions on
+// the same operands as k_step, so both kernels produce identical bits.
+// ---------------------------------------------------------------------------
+template <typename T, int SEG>
+__global__ __launch_bounds__(kBlock) void k_march(const StepLaunch<T> L) {
+    using HB = typename HBits<T>::type;
+    const int lane = threadIdx.x & 63;
+    // the wavefront index is uniform across the wavefront; saying so lets every
+    // per-member quantity live in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int wg = xcd_remap(blockIdx.x, gridDim.x) * (kBlock / 64) + wave;
+    int ci = 0;
+    for (int i = 1; i < L.n_catch; ++i)
+        if (wg >= L.c[i].wave_begin) ci = i;
+    const CatchDev<T>& C = L.c[ci];
+    const int local = wg - C.wave_begin;
+    if (local >= C.n_waves) return;
+    const int n_groups = (C.n_members + SEG - 1) / SEG;
+    int kg, sx, sy;
+    if (C.march_order == 0) {
+        // member groups fastest: neighbouring wavefronts share the strip's bed and roughness
+        kg = local % n_groups;
+        const int strip = local / n_groups;
+        sy = strip / C.strips_x;
+        sx = strip - sy * C.strips_x;
+    } else {
+        // strips along x fastest: neighbouring wavefronts read neighbouring segments of the
+        // same rows, so DRAM pages are streamed instead of visited 256 bytes at a time
+        sx = local % C.strips_x;
+        const int rest = local / C.strips_x;
+        sy = rest % C.strips_y;
+        kg = rest / C.strips_y;
+    }
+    MemberStep<T> ms[SEG];
+    bool act[SEG];
+    bool any = false;
+#pragma unroll
+    for (int s = 0; s < SEG; ++s) {
+        const int k = kg * SEG + s;
+        act[s] = false;
+        if (k < C.n_members) {
+            ms[s] = L.ms[C.member_off + k];
+            act[s] = ms[s].active != 0;
+        }
+        any |= act[s];
+    }
+    if (!any) return;
+    const int nx = C.nx, ny = C.ny;
+    const int x = sx * 62 - 1 + lane;
+    const bool inx = x >= 0 && x < nx;
+    const bool own = lane >= 1 && lane <= 62 && inx;
+    const bool hasE = x + 1 < nx, hasW = x > 0;
+    const int r0 = sy * C.march_rows;
+    const int r1 = min(r0 + C.march_rows, ny);
+    const size_t plane = (size_t)ny * nx;
+    const T* __restrict__ Z = C.z;
+    const T* __restrict__ Nn = C.n;
+    const T g = C.g, hdry = C.hdry;
+    const int nb = 2 * (nx + ny);
+
+    size_t c0 = (size_t)r0 * nx + x;
+    T zc = inx ? Z[c0] : T(0);
+    T nc = inx ? Nn[c0] : T(0);
+    T zN = T(0), nN = T(0);
+    if (inx && r0 > 0) {
+        zN = Z[c0 - nx];
+        nN = Nn[c0 - nx];
+    }
+    T hc[SEG], fN[SEG];
+    HB vmax[SEG];
+#pragma unroll
+    for (int s = 0; s < SEG; ++s) {
+        hc[s] = T(0);
+        fN[s] = T(0);
+        vmax[s] = 0;
+        if (!act[s]) continue;
+        const int k = kg * SEG + s;
+        const int sp = ms[s].parity;
+        const T* __restrict__ H = C.h[sp] + (size_t)k * plane;
+        if (inx) {
+            hc[s] = H[c0];
+            if (r0 > 0) {
+                const T nf = T(0.5) * (nN + nc);
+                fN[s] = link_in(C.qy[sp][(size_t)k * plane + c0 - nx], H[c0 - nx], hc[s], zc - zN, g * (nf * nf),
+                                ms[s], hdry);
+            } else if (C.edge_open[0]) {
+                fN[s] = -link_open(-C.qn[sp][(size_t)k * nx + x], hc[s], g * (nc * nc), C.edge_slope[0], ms[s], hdry);
+            }
+        }
+    }
+    for (int r = r0; r < r1; ++r) {
+        const bool hasS = r + 1 < ny;
+        T zs = T(0), ns = T(0);
+        if (inx && hasS) {
+            zs = Z[c0 + nx];
+            ns = Nn[c0 + nx];
+        }
+        const T zE = __shfl_down(zc, 1, 64);
+        const T nE = __shfl_down(nc, 1, 64);
+        const T gb = g * (nc * nc);
+        T nfE = T(0.5) * (nc + nE);
+        const T GE = g * (nfE * nfE);
+        const T nfS = T(0.5) * (nc + ns);
+        const T GS = g * (nfS * nfS);
+#pragma unroll
+        for (int s = 0; s < SEG; ++s) {
+            if (!act[s]) continue;
+            const int k = kg * SEG + s;
+            const MemberStep<T>& m = ms[s];
+            const int sp = m.parity, dp = sp ^ 1;
+            const size_t base = (size_t)k * plane;
+            const T* __restrict__ H = C.h[sp] + base;
+            T hs = T(0), qE = T(0), qS = T(0);
+            if (inx) {
+                qE = C.qx[sp][base + c0];
+                qS = C.qy[sp][base + c0];
+                if (hasS) hs = H[c0 + nx];
+            }
+            const T h0 = hc[s];
+            const T hE = __shfl_down(h0, 1, 64);
+            T fE;
+            if (hasE)
+                fE = link_in(qE, h0, hE, zE - zc, GE, m, hdry);
+            else
+                fE = C.edge_open[1] ? link_open(qE, h0, gb, C.edge_slope[1], m, hdry) : T(0);
+            const T fWn = __shfl_up(fE, 1, 64);
+            if (own) {
+                T fW, fS;
+                if (hasW)
+                    fW = fWn;
+                else
+                    fW = C.edge_open[3] ? -link_open(-C.qw[sp][(size_t)k * ny + r], h0, gb, C.edge_slope[3], m, hdry)
+                                        : T(0);
+                if (hasS)
+                    fS = link_in(qS, h0, hs, zs - zc, GS, m, hdry);
+                else
+                    fS = C.edge_open[2] ? link_open(qS, h0, gb, C.edge_slope[2], m, hdry) : T(0);
+                const T dv = ((fW - fE) + fN[s]) - fS;
+                T hn = (h0 + m.dtdx * dv) + m.rinc;
+                if (hn < T(0)) {
+                    atomicAdd(&L.vclamp[C.member_off + k], -(double)hn * (C.dx * C.dx));
+                    hn = T(0);
+                }
+                if (hn == T(0)) hn = T(0);
+                C.h[dp][base + c0] = hn;
+                C.qx[dp][base + c0] = fE;
+                C.qy[dp][base + c0] = fS;
+                if (!hasW) C.qw[dp][(size_t)k * ny + r] = fW;
+                if (r == 0) C.qn[dp][(size_t)k * nx + x] = fN[s];
+                if (!(hasE && hasW && hasS && r > 0)) {
+                    double* acc = C.out_acc + (size_t)k * nb;
+                    if (r == 0 && C.edge_open[0]) acc[x] += -(double)fN[s] * m.dxdt;
+                    if (!hasS && C.edge_open[2]) acc[nx + x] += (double)fS * m.dxdt;
+                    if (!hasW && C.edge_open[3]) acc[2 * nx + r] += -(double)fW * m.dxdt;
+                    if (!hasE && C.edge_open[1]) acc[2 * nx + ny + r] += (double)fE * m.dxdt;
+                }
+                const HB hb = to_bits(hn);
+                vmax[s] = hb > vmax[s] ? hb : vmax[s];
+                fN[s] = fS;
+            }
+            hc[s] = hs;
+        }
+        zc = zs;
+        nc = ns;
+        c0 += nx;
+    }
+#pragma unroll
+    for (int s = 0; s < SEG; ++s) {
+        if (!act[s]) continue;
+        HB v = vmax[s];
+        for (int off = 32; off > 0; off >>= 1) {
+            const HB o = __shfl_xor(v, off, 64);
+            v = o > v ? o : v;
+        }
+        if (lane == 0 && v != 0) {
+            HB* a = L.hbins + (size_t)(blockIdx.x & (kBins - 1)) * L.n_total + C.member_off + kg * SEG + s;
+            const HB cur = __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (v > cur) atomicMax(a, v);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Vectorised row-marching step (members in planes, nx a multiple of V): each
+// lane owns V adjacent cells and moves them with one V-wide load or store, so a
+// wavefront streams 64 V cells per row with five loads and three stores.
+// Lanes 0 and 63 are halo lanes (the strip's own cells are those of lanes
+// 1..62), which keeps every access V-aligned.  Same link functions and
+// operands as k_step: identical bits.
+// ---------------------------------------------------------------------------
+template <typename T, int V> struct VecOf;
+template <> struct VecOf<float, 4> { typedef float __attribute__((ext_vector_type(4))) type; };
+template <> struct VecOf<float, 2> { typedef float __attribute__((ext_vector_type(2))) type; };
+template <> struct VecOf<double, 2> { typedef double __attribute__((ext_vector_type(2))) type; };
+
+template <typename T, int V>
+__device__ __forceinline__ void vload(const T* p, T (&d)[V]) {
+    typedef typename VecOf<T, V>::type vt;
+    const vt v = *reinterpret_cast<const vt*>(p);
+#pragma unroll
+    for (int j = 0; j < V; ++j) d[j] = v[j];
+}
+template <typename T, int V>
+__device__ __forceinline__ void vstore(T* p, const T (&d)[V]) {
+    typedef typename VecOf<T, V>::type vt;
+    vt v;
+#pragma unroll
+    for (int j = 0; j < V; ++j) v[j] = d[j];
+    *reinterpret_cast<vt*>(p) = v;
+}
+// streaming variants: the state is touched once per step, so these accesses are
+// marked non-temporal and leave cache capacity to the shared bed and roughness
+template <typename T, int V>
+__device__ __forceinline__ void vload_nt(const T* p, T (&d)[V]) {
+    typedef typename VecOf<T, V>::type vt;
+    const vt v = __builtin_nontemporal_load(reinterpret_cast<const vt*>(p));
+#pragma unroll
+    for (int j = 0; j < V; ++j) d[j] = v[j];
+}
+template <typename T, int V>
+__device__ __forceinline__ void vstore_nt(T* p, const T (&d)[V]) {
+    typedef typename VecOf<T, V>::type vt;
+    vt v;
+#pragma unroll
+    for (int j = 0; j < V; ++j) v[j] = d[j];
+    __builtin_nontemporal_store(v, reinterpret_cast<vt*>(p));
+}
+
+template <typename T, int V, int NT>
+__global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
+    using HB = typename HBits<T>::type;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int wg = xcd_remap(blockIdx.x, gridDim.x) * (kBlock / 64) + wave;
+    int ci = 0;
+    for (int i = 1; i < L.n_catch; ++i)
+        if (wg >= L.c[i].wave_begin) ci = i;
+    const CatchDev<T>& C = L.c[ci];
+    const int local = wg - C.wave_begin;
+    if (local >= C.n_waves) return;
+    int k, sx, sy;
+    if (C.march_order == 0) {
+        k = local % C.n_members;
+        const int strip = local / C.n_members;
+        sy = strip / C.strips_x;
+        sx = strip - sy * C.strips_x;
+    } else {
+        sx = local % C.strips_x;
+        const int rest = local / C.strips_x;
+        sy = rest % C.strips_y;
+        k = rest / C.strips_y;
+    }
+    const MemberStep<T> ms = L.ms[C.member_off + k];
+    if (!ms.active) return;
+    const int nx = C.nx, ny = C.ny;
+    const int xl = sx * (62 * V) - V + V * lane;          // first cell of this lane
+    const bool inx = xl >= 0 && xl < nx;                   // nx % V == 0: all V cells or none
+    const bool own = lane >= 1 && lane <= 62 && inx;
+    const int r0 = sy * C.march_rows;
+    const int r1 = min(r0 + C.march_rows, ny);
+    const int sp = ms.parity, dp = sp ^ 1;
+    const size_t plane = (size_t)ny * nx;
+    const T* __restrict__ H = C.h[sp] + (size_t)k * plane;
+    const T* __restrict__ QX = C.qx[sp] + (size_t)k * plane;
+    const T* __restrict__ QY = C.qy[sp] + (size_t)k * plane;
+    T* __restrict__ Ho = C.h[dp] + (size_t)k * plane;
+    T* __restrict__ QXo = C.qx[dp] + (size_t)k * plane;
+    T* __restrict__ QYo = C.qy[dp] + (size_t)k * plane;
+    const T* __restrict__ Z = C.z;
+    const T* __restrict__ Nn = C.n;
+    const T g = C.g, hdry = C.hdry;
+    const int nb = 2 * (nx + ny);
+
+    size_t c0 = (size_t)r0 * nx + xl;
+    T hc[V], zc[V], nc[V], fN[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) hc[j] = zc[j] = nc[j] = fN[j] = T(0);
+    if (inx) {
+        vload<T, V>(H + c0, hc);
+        vload<T, V>(Z + c0, zc);
+        vload<T, V>(Nn + c0, nc);
+        if (r0 > 0) {
+            T hN[V], zN[V], nN[V], qN[V];
+            vload<T, V>(H + c0 - nx, hN);
+            vload<T, V>(Z + c0 - nx, zN);
+            vload<T, V>(Nn + c0 - nx, nN);
+            vload<T, V>(QY + c0 - nx, qN);
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                const T nf = T(0.5) * (nN[j] + nc[j]);
+                fN[j] = link_in(qN[j], hN[j], hc[j], zc[j] - zN[j], g * (nf * nf), ms, hdry);
+            }
+        } else if (C.edge_open[0]) {
+#pragma unroll
+            for (int j = 0; j < V; ++j)
+                fN[j] = -link_open(-C.qn[sp][(size_t)k * nx + xl + j], hc[j], g * (nc[j] * nc[j]), C.edge_slope[0],
+                                   ms, hdry);
+        }
+    }
+    HB vmax = 0;
+    for (int r = r0; r < r1; ++r) {
+        const bool hasS = r + 1 < ny;
+        T hs[V], zs[V], ns[V], qE[V], qS[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) hs[j] = zs[j] = ns[j] = qE[j] = qS[j] = T(0);
+        if (inx) {
+            if (NT) {
+                vload_nt<T, V>(QX + c0, qE);
+                vload_nt<T, V>(QY + c0, qS);
+            } else {
+                vload<T, V>(QX + c0, qE);
+                vload<T, V>(QY + c0, qS);
+            }
+            if (hasS) {
+                vload<T, V>(H + c0 + nx, hs);
+                vload<T, V>(Z + c0 + nx, zs);
+                vload<T, V>(Nn + c0 + nx, ns);
+            }
+        }
+        // east neighbour of the lane's last cell = first cell of the next lane
+        const T hE = __shfl_down(hc[0], 1, 64);
+        const T zE = __shfl_down(zc[0], 1, 64);
+        const T nE = __shfl_down(nc[0], 1, 64);
+        T fE[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const int x = xl + j;
+            const T h2 = (j + 1 < V) ? hc[j + 1] : hE;
+            const T z2 = (j + 1 < V) ? zc[j + 1] : zE;
+            const T n2 = (j + 1 < V) ? nc[j + 1] : nE;
+            if (x + 1 < nx) {
+                const T nf = T(0.5) * (nc[j] + n2);
+                fE[j] = link_in(qE[j], hc[j], h2, z2 - zc[j], g * (nf * nf), ms, hdry);
+            } else {
+                fE[j] = C.edge_open[1] ? link_open(qE[j], hc[j], g * (nc[j] * nc[j]), C.edge_slope[1], ms, hdry)
+                                       : T(0);
+            }
+        }
+        const T fW0 = __shfl_up(fE[V - 1], 1, 64);
+        if (own) {
+            T hn4[V], fS4[V];
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                const int x = xl + j;
+                const T gb = g * (nc[j] * nc[j]);
+                T fW;
+                if (j > 0)
+                    fW = fE[j - 1];
+                else if (x > 0)
+                    fW = fW0;
+                else
+                    fW = C.edge_open[3] ? -link_open(-C.qw[sp][(size_t)k * ny + r], hc[0], gb, C.edge_slope[3], ms, hdry)
+                                        : T(0);
+                T fS;
+                if (hasS) {
+                    const T nf = T(0.5) * (nc[j] + ns[j]);
+                    fS = link_in(qS[j], hc[j], hs[j], zs[j] - zc[j], g * (nf * nf), ms, hdry);
+                } else {
+                    fS = C.edge_open[2] ? link_open(qS[j], hc[j], gb, C.edge_slope[2], ms, hdry) : T(0);
+                }
+                const T dv = ((fW - fE[j]) + fN[j]) - fS;
+                T hn = (hc[j] + ms.dtdx * dv) + ms.rinc;
+                if (hn < T(0)) {
+                    atomicAdd(&L.vclamp[C.member_off + k], -(double)hn * (C.dx * C.dx));
+                    hn = T(0);
+                }
+                if (hn == T(0)) hn = T(0);
+                hn4[j] = hn;
+                fS4[j] = fS;
+                if (x == 0) C.qw[dp][(size_t)k * ny + r] = fW;
+                if (r == 0) C.qn[dp][(size_t)k * nx + x] = fN[j];
+                if (x == 0 || x + 1 == nx || r == 0 || !hasS) {
+                    double* acc = C.out_acc + (size_t)k * nb;
+                    if (r == 0 && C.edge_open[0]) acc[x] += -(double)fN[j] * ms.dxdt;
+                    if (!hasS && C.edge_open[2]) acc[nx + x] += (double)fS * ms.dxdt;
+                    if (x == 0 && C.edge_open[3]) acc[2 * nx + r] += -(double)fW * ms.dxdt;
+                    if (x + 1 == nx && C.edge_open[1]) acc[2 * nx + ny + r] += (double)fE[j] * ms.dxdt;
+                }
+                const HB hb = to_bits(hn);
+                vmax = hb > vmax ? hb : vmax;
+                fN[j] = fS;
+            }
+            if (NT) {
+                vstore_nt<T, V>(Ho + c0, hn4);
+                vstore_nt<T, V>(QXo + c0, fE);
+                vstore_nt<T, V>(QYo + c0, fS4);
+            } else {
+                vstore<T, V>(Ho + c0, hn4);
+                vstore<T, V>(QXo + c0, fE);
+                vstore<T, V>(QYo + c0, fS4);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            hc[j] = hs[j];
+            zc[j] = zs[j];
+            nc[j] = ns[j];
+        }
+        c0 += nx;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const HB o = __shfl_xor(vmax, off, 64);
+        vmax = o > vmax ? o : vmax;
+    }
+    if (lane == 0 && vmax != 0) {
+        HB* a = L.hbins + (size_t)(blockIdx.x & (kBins - 1)) * L.n_total + C.member_off + k;
+        const HB cur = __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (vmax > cur) atomicMax(a, vmax);
+    }
+}
+
+template <typename T> void launch_marchv(const StepLaunch<T>& L, int nt, int total_waves, hipStream_t s) {
+    const int per = kBlock / 64;
+    const dim3 grid((total_waves + per - 1) / per);
+    constexpr int V = march_vec<T>();
+    if (nt)
+        hipLaunchKernelGGL((k_marchv<T, V, 1>), grid, dim3(kBlock), 0, s, L);
+    else
+        hipLaunchKernelGGL((k_marchv<T, V, 0>), grid, dim3(kBlock), 0, s, L);
+}
+
+template void launch_marchv<float>(const StepLaunch<float>&, int, int, hipStream_t);
+template void launch_marchv<double>(const StepLaunch<double>&, int, int, hipStream_t);
+
+template <typename T> void launch_march(const StepLaunch<T>& L, int seg, int total_waves, hipStream_t s) {
+    const int per = kBlock / 64;
+    const dim3 grid((total_waves + per - 1) / per);
+    switch (seg) {
+        case 1: hipLaunchKernelGGL((k_march<T, 1>), grid, dim3(kBlock), 0, s, L); break;
+        case 2: hipLaunchKernelGGL((k_march<T, 2>), grid, dim3(kBlock), 0, s, L); break;
+        case 4: hipLaunchKernelGGL((k_march<T, 4>), grid, dim3(kBlock), 0, s, L); break;
+        default: hipLaunchKernelGGL((k_march<T, 8>), grid, dim3(kBlock), 0, s, L); break;
+    }
+}
+
+template void launch_march<float>(const StepLaunch<float>&, int, int, hipStream_t);
+template void launch_march<double>(const StepLaunch<double>&, int, int, hipStream_t);
+
+}  // namespace flood

@@ -36,7 +36,7 @@ template <typename T> struct Impl : ImplBase {
     using HB = typename HBits<T>::type;
 
     struct Cat {
-        int ny = 0, nx = 0, N = 0, n_chunks = 0, tile_rows = 4, cpb = 1;
+        int ny = 0, nx = 0, N = 0, n_chunks = 0, tile_rows = 4, cpb = 1, march_rows = 32;
         double dx = 0;
         flood_params p{};
         std::vector<double> rain;
@@ -50,6 +50,11 @@ template <typename T> struct Impl : ImplBase {
     hipStream_t st = nullptr;
     hipStream_t own_stream = nullptr;  // created when the caller passes the null stream
     int mi = 1;
+    int variant = 1;          // 1 tiled step kernel, 2 row-marching step kernel (mi == 1)
+    int march_seg = 2;        // members per wavefront of the row-marching kernel
+    int march_order = 1;      // wavefront order of the row-marching kernel
+    int march_nt = 1;         // non-temporal state streams in the vectorised row-marching kernel
+    int total_waves = 0;      // waves of one row-marching launch
     int n_catch = 0, n_total = 0;
     std::vector<Cat> cats;
     std::vector<void*> allocs;
@@ -123,7 +128,7 @@ template <typename T> struct Impl : ImplBase {
 
     // tile / grouping geometry of every catchment and the launch descriptor
     void layout_launch() {
-        int begin = 0;
+        int begin = 0, waves = 0;
         SL.n_catch = n_catch;
         SL.n_total = n_total;
         for (int i = 0; i < n_catch; ++i) {
@@ -139,12 +144,36 @@ template <typename T> struct Impl : ImplBase {
             d.n_blocks = d.tiles_x * d.tiles_y * d.groups;
             d.block_begin = begin;
             begin += d.n_blocks;
+            d.march_rows = std::max(1, std::min(c.march_rows, c.ny));
+            const int strip_w = variant == 3 ? 62 * march_vec<T>() : 62;
+            d.strips_x = (c.nx + strip_w - 1) / strip_w;
+            d.strips_y = (c.ny + d.march_rows - 1) / d.march_rows;
+            d.wave_begin = waves;
+            d.n_waves = d.strips_x * d.strips_y * (variant == 3 ? c.N : (c.N + march_seg - 1) / march_seg);
+            d.march_order = march_order;
+            waves += d.n_waves;
             SL.c[i] = d;
         }
         SL.total_blocks = begin;
+        total_waves = waves;
         SL.ms = ms;
         SL.hbins = hbins;
         SL.vclamp = vclamp;
+    }
+
+    void launch_steps(const StepLaunch<T>& L) {
+        if (variant == 3 && !L.recompute)
+            launch_marchv<T>(L, march_nt, total_waves, st);
+        else if (variant == 2 && !L.recompute)
+            launch_march<T>(L, march_seg, total_waves, st);
+        else
+            launch_step_mi<T>(mi, L, st);
+    }
+
+    bool vector_ok() const {
+        for (const Cat& c : cats)
+            if (c.nx % march_vec<T>() != 0) return false;
+        return mi == 1;
     }
 
     void invalidate_graph() {
@@ -165,8 +194,14 @@ template <typename T> struct Impl : ImplBase {
             st = own_stream;
         }
         n_catch = nc;
+        if (const char* mo = std::getenv("FLOOD_MARCH_ORDER")) march_order = std::atoi(mo) ? 1 : 0;
+        if (const char* nt = std::getenv("FLOOD_MARCH_NT")) march_nt = std::atoi(nt) ? 1 : 0;
         const char* ng = std::getenv("FLOOD_NO_GRAPH");
         use_graph = !(ng && ng[0] == '1');
+        if (const char* gs = std::getenv("FLOOD_GRAPH_STEPS")) {   // steps per captured batch
+            const int v = std::atoi(gs);
+            if (v >= 1 && v <= 4096) G = v;
+        }
         cats.resize(nc);
         int off = 0;
         for (int i = 0; i < nc; ++i) {
@@ -201,9 +236,21 @@ template <typename T> struct Impl : ImplBase {
         TuneChoice ch = tune_default(key);
         if (params[0].member_interleave) ch.mi = params[0].member_interleave;
         mi = ch.mi;
+        variant = params[0].step_kernel ? params[0].step_kernel : ch.variant;
+        march_seg = params[0].march_members ? params[0].march_members : ch.march_seg;
+        if (variant == 3 && !vector_ok()) {
+            if (params[0].step_kernel == 3) {
+                err = "the vectorised kernel needs member_interleave 1 and nx a multiple of " +
+                      std::to_string(march_vec<T>());
+                return FLOOD_EINVAL;
+            }
+            variant = 2;
+        }
+        if (mi != 1) variant = 1;
         for (int i = 0; i < nc; ++i) {
             cats[i].tile_rows = params[i].tile_rows ? params[i].tile_rows : ch.tile_rows;
             cats[i].cpb = params[i].chunks_per_block ? params[i].chunks_per_block : ch.cpb;
+            cats[i].march_rows = params[i].march_rows ? params[i].march_rows : ch.march_rows;
             while (cats[i].tile_rows * mi > kBlock) cats[i].tile_rows >>= 1;
         }
 
@@ -384,7 +431,10 @@ template <typename T> struct Impl : ImplBase {
 
         // measured choice of tile rows / chunks per workgroup when not given
         bool autotune = false;
-        for (int i = 0; i < nc; ++i) autotune |= (params[i].tile_rows == 0 || params[i].chunks_per_block == 0);
+        for (int i = 0; i < nc; ++i)
+            autotune |= (params[i].tile_rows == 0 || params[i].chunks_per_block == 0 ||
+                         (mi == 1 && (params[i].step_kernel == 0 || params[i].march_rows == 0 ||
+                                      params[i].march_members == 0)));
         if (autotune && tune_enabled()) CHK(autotune_geometry(key, params, err));
         return FLOOD_OK;
     }
@@ -395,9 +445,13 @@ template <typename T> struct Impl : ImplBase {
     flood_status autotune_geometry(const TuneKey& key, const flood_params* params, std::string& err) {
         TuneChoice cached;
         if (tune_lookup(key, mi, cached)) {
+            if (!params[0].step_kernel && mi == 1) variant = cached.variant;
+            if (!params[0].march_members) march_seg = cached.march_seg;
+            march_order = cached.march_order;
             for (int i = 0; i < n_catch; ++i) {
                 if (!params[i].tile_rows) cats[i].tile_rows = cached.tile_rows;
                 if (!params[i].chunks_per_block) cats[i].cpb = cached.cpb;
+                if (!params[i].march_rows) cats[i].march_rows = cached.march_rows;
             }
             layout_launch();
             return FLOOD_OK;
@@ -439,41 +493,71 @@ template <typename T> struct Impl : ImplBase {
         hipEvent_t a, b;
         HIPCHK(hipEventCreate(&a));
         HIPCHK(hipEventCreate(&b));
-        const int rows_c[4] = {1, 2, 4, 8};
         int max_chunks = 1;
         for (int i = 0; i < n_catch; ++i) max_chunks = std::max(max_chunks, cats[i].n_chunks);
         std::vector<int> cpbs;
         for (int v = 1; v < max_chunks; v *= 2) cpbs.push_back(v);
         cpbs.push_back(max_chunks);
+        struct Cand {
+            int variant, rows, cpb, mrows, seg, order;
+        };
+        std::vector<Cand> cands;
+        const bool want1 = params[0].step_kernel == 0 || params[0].step_kernel == 1 || mi != 1;
+        const bool want2 = mi == 1 && (params[0].step_kernel == 0 || params[0].step_kernel == 2);
+        const bool want3 = vector_ok() && (params[0].step_kernel == 0 || params[0].step_kernel == 3);
+        if (want1)
+            for (int r : {1, 2, 4, 8})
+                for (int cp : cpbs)
+                    if (r * mi <= kBlock) cands.push_back({1, r, cp, cats[0].march_rows, march_seg, march_order});
+        if (want2) {
+            std::vector<int> segs;
+            if (params[0].march_members)
+                segs.push_back(params[0].march_members);
+            else
+                segs = {1, 2, 4, 8};
+            for (int od : {0, 1})
+                for (int sg : segs)
+                    for (int mr : {8, 16, 32, 64, 128})
+                        cands.push_back({2, cats[0].tile_rows, cats[0].cpb, mr, sg, od});
+        }
+        if (want3)
+            for (int od : {0, 1})
+                for (int mr : {4, 8, 16, 32, 64}) cands.push_back({3, cats[0].tile_rows, cats[0].cpb, mr, 1, od});
         float best = 1e30f;
-        int best_rows = cats[0].tile_rows, best_cpb = cats[0].cpb;
-        for (int r : rows_c) {
-            if (r * mi > kBlock) continue;
-            for (int cp : cpbs) {
-                for (int i = 0; i < n_catch; ++i) {
-                    if (!params[i].tile_rows) cats[i].tile_rows = r;
-                    if (!params[i].chunks_per_block) cats[i].cpb = cp;
-                }
-                layout_launch();
-                launch_step_mi<T>(mi, SL, st);  // warm-up
-                HIPCHK(hipEventRecord(a, st));
-                for (int rep = 0; rep < 3; ++rep) launch_step_mi<T>(mi, SL, st);
-                HIPCHK(hipEventRecord(b, st));
-                HIPCHK(hipEventSynchronize(b));
-                float ms_el = 0;
-                HIPCHK(hipEventElapsedTime(&ms_el, a, b));
-                if (ms_el < best) {
-                    best = ms_el;
-                    best_rows = r;
-                    best_cpb = cp;
-                }
+        Cand bc = cands.empty()
+                      ? Cand{variant, cats[0].tile_rows, cats[0].cpb, cats[0].march_rows, march_seg, march_order}
+                      : cands[0];
+        for (const Cand& cd : cands) {
+            variant = cd.variant;
+            march_seg = cd.seg;
+            march_order = cd.order;
+            for (int i = 0; i < n_catch; ++i) {
+                if (!params[i].tile_rows) cats[i].tile_rows = cd.rows;
+                if (!params[i].chunks_per_block) cats[i].cpb = cd.cpb;
+                if (!params[i].march_rows) cats[i].march_rows = cd.mrows;
+            }
+            layout_launch();
+            launch_steps(SL);  // warm-up
+            HIPCHK(hipEventRecord(a, st));
+            for (int rep = 0; rep < 3; ++rep) launch_steps(SL);
+            HIPCHK(hipEventRecord(b, st));
+            HIPCHK(hipEventSynchronize(b));
+            float ms_el = 0;
+            HIPCHK(hipEventElapsedTime(&ms_el, a, b));
+            if (ms_el < best) {
+                best = ms_el;
+                bc = cd;
             }
         }
         (void)hipEventDestroy(a);
         (void)hipEventDestroy(b);
+        variant = bc.variant;
+        march_seg = bc.seg;
+        march_order = bc.order;
         for (int i = 0; i < n_catch; ++i) {
-            if (!params[i].tile_rows) cats[i].tile_rows = best_rows;
-            if (!params[i].chunks_per_block) cats[i].cpb = best_cpb;
+            if (!params[i].tile_rows) cats[i].tile_rows = bc.rows;
+            if (!params[i].chunks_per_block) cats[i].cpb = bc.cpb;
+            if (!params[i].march_rows) cats[i].march_rows = bc.mrows;
         }
         layout_launch();
         HIPCHK(hipMemcpy(ms, saved.data(), n_total * sizeof(MemberStep<T>), hipMemcpyHostToDevice));
@@ -484,8 +568,12 @@ template <typename T> struct Impl : ImplBase {
                              hipMemcpyHostToDevice));
         TuneChoice c;
         c.mi = mi;
-        c.tile_rows = best_rows;
-        c.cpb = best_cpb;
+        c.tile_rows = bc.rows;
+        c.cpb = bc.cpb;
+        c.variant = bc.variant;
+        c.march_rows = bc.mrows;
+        c.march_seg = bc.seg;
+        c.march_order = bc.order;
         tune_store(key, c);
         return FLOOD_OK;
     }
@@ -503,7 +591,7 @@ template <typename T> struct Impl : ImplBase {
         }
         for (int i = 0; i < G; ++i) {
             launch_plan<T>(PL, st);
-            launch_step_mi<T>(mi, SL, st);
+            launch_steps(SL);
         }
         e = hipStreamEndCapture(st, &graph);
         if (e != hipSuccess || !graph) {
@@ -537,11 +625,11 @@ template <typename T> struct Impl : ImplBase {
                         tev.push_back(e);
                     }
                     HIPCHK(hipEventRecord(tev[tev_used], st));
-                    launch_step_mi<T>(mi, SL, st);
+                    launch_steps(SL);
                     HIPCHK(hipEventRecord(tev[tev_used + 1], st));
                     tev_used += 2;
                 } else {
-                    launch_step_mi<T>(mi, SL, st);
+                    launch_steps(SL);
                 }
             }
         }
@@ -556,21 +644,28 @@ template <typename T> struct Impl : ImplBase {
         CHK(ensure_graph(err));
         *h_tend = t_end;
         HIPCHK(hipMemcpyAsync(d_tend, h_tend, sizeof(double), hipMemcpyHostToDevice, st));
+        // the first batch runs alone (a call that needs a single batch launches nothing
+        // more); after that two batches are kept in flight
         CHK(launch_batch(0, err));
-        CHK(launch_batch(1, err));
+        HIPCHK(hipEventSynchronize(ev[0]));
         int slot = 0;
-        int64_t batches = 2;
-        const int64_t max_batches = (int64_t)50000000 / G;
-        for (;;) {
-            HIPCHK(hipEventSynchronize(ev[slot]));
-            if (h_count[2 * slot] == 0) break;
-            if (batches > max_batches) {
-                err = "step limit exceeded before every member reached t_end";
-                return FLOOD_ESTATE;
+        if (h_count[0] != 0) {
+            CHK(launch_batch(1, err));
+            CHK(launch_batch(0, err));
+            slot = 1;
+            int64_t batches = 3;
+            const int64_t max_batches = (int64_t)50000000 / G;
+            for (;;) {
+                HIPCHK(hipEventSynchronize(ev[slot]));
+                if (h_count[2 * slot] == 0) break;
+                if (batches > max_batches) {
+                    err = "step limit exceeded before every member reached t_end";
+                    return FLOOD_ESTATE;
+                }
+                CHK(launch_batch(slot, err));
+                ++batches;
+                slot ^= 1;
             }
-            CHK(launch_batch(slot, err));
-            ++batches;
-            slot ^= 1;
         }
         HIPCHK(hipStreamSynchronize(st));
         if (timing_on) {
@@ -932,11 +1027,15 @@ template <typename T> struct Impl : ImplBase {
         return FLOOD_OK;
     }
 
-    void get_config(int32_t* omi, int32_t* rows, int32_t* cpb, int32_t* gs) const override {
+    void get_config(int32_t* omi, int32_t* rows, int32_t* cpb, int32_t* gs, int32_t* vk, int32_t* mr,
+                    int32_t* mseg) const override {
+        if (mseg) *mseg = march_seg;
         if (omi) *omi = mi;
         if (rows) *rows = cats[0].tile_rows;
         if (cpb) *cpb = std::min(cats[0].cpb, cats[0].n_chunks);
         if (gs) *gs = (use_graph && gexec) ? G : 0;
+        if (vk) *vk = variant;
+        if (mr) *mr = std::min(cats[0].march_rows, cats[0].ny);
     }
 
     flood_status timing(bool on, std::string& err) override {
@@ -958,11 +1057,23 @@ template <typename T> struct Impl : ImplBase {
 
 // A view of members [g0, g0 + G) of catchment c (g0 a multiple of MI) over state
 // arrays laid out like the catchment's, with its own tile grid (one workgroup
-// per tile walking every chunk of the group).
+// per tile walking every chunk of the group).  The tile shape is fixed rather
+// than taken from the tuned forward geometry: the adjoint's per-workgroup
+// partial sums then group cells the same way on every handle of a given
+// interleave, so its gradients do not depend on what the tuner picked.
+constexpr int kAdjTileRows = 4;
+
 template <typename T>
 static CatchDev<T> group_view(const CatchDev<T>& C, int mi, int g0, int G, T* const h[2], T* const qx[2],
                               T* const qy[2], T* const qw[2], T* const qn[2]) {
     CatchDev<T> v = C;
+    const int txc = std::max(1, kBlock / (mi * kAdjTileRows));
+    int l = 0;
+    while ((1 << l) < txc) ++l;
+    v.tx_log2 = l;
+    const int ty = (kBlock / mi) >> l;
+    v.tiles_x = (C.nx + (1 << l) - 1) >> l;
+    v.tiles_y = (C.ny + ty - 1) / ty;
     v.member_off = C.member_off + g0;
     v.n_members = G;
     v.n_chunks = (G + mi - 1) / mi;
@@ -1070,7 +1181,12 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
     MemberStep<T>* ms_log = nullptr;
     double* rdt_log = nullptr;
     int32_t *tag_log = nullptr, *any_log = nullptr;
-    const int nblk = C.dev.tiles_x * C.dev.tiles_y;
+    int nblk;
+    {
+        T* none[2] = {nullptr, nullptr};
+        const CatchDev<T> tv = group_view(C.dev, mi, 0, std::min(Gi, N), none, none, none, none, none);
+        nblk = tv.tiles_x * tv.tiles_y;
+    }
     CHK(talloc((size_t)nblk * Gi * sizeof(double), (void**)&d_mubar));
     size_t log_cap = 4096;
     auto grow_log = [&](size_t need) -> flood_status {

@@ -1,7 +1,7 @@
 // Geometry defaults and the measured-choice cache of libflood.
 //
 // Cache file: $FLOOD_TUNE_CACHE (no caching when unset).  One line per tuned
-// problem: "<key> mi tile_rows cpb".  Set FLOOD_AUTOTUNE=0 to skip measuring
+// problem: "<key> mi tile_rows cpb variant march_rows march_seg march_order".  Set FLOOD_AUTOTUNE=0 to skip measuring
 // and use the defaults (or the explicit values given at creation).
 #include "flood_tune.h"
 
@@ -26,6 +26,10 @@ TuneChoice tune_default(const TuneKey& k) {
     int maxm = 1;
     for (int i = 0; i < k.n_catch; ++i) maxm = k.members[i] > maxm ? k.members[i] : maxm;
     c.cpb = maxm < 16 ? maxm : 16;
+    c.variant = 3;      // vectorised row march (falls back to 2 when nx does not allow it)
+    c.march_rows = 16;
+    c.march_seg = 1;
+    c.march_order = 1;
     return c;
 }
 
@@ -41,13 +45,17 @@ bool tune_lookup(const TuneKey& k, int mi, TuneChoice& out) {
     if (!f) return false;
     const std::string want = key_string(k, mi);
     char key[512];
-    int a, b, c;
+    int a, b, c, d, e, f2, g2;
     bool found = false;
-    while (std::fscanf(f, "%511s %d %d %d", key, &a, &b, &c) == 4) {
+    while (std::fscanf(f, "%511s %d %d %d %d %d %d %d", key, &a, &b, &c, &d, &e, &f2, &g2) == 8) {
         if (want == key) {
             out.mi = a;
             out.tile_rows = b;
             out.cpb = c;
+            out.variant = d;
+            out.march_rows = e;
+            out.march_seg = f2;
+            out.march_order = g2;
             found = true;
         }
     }
@@ -60,7 +68,8 @@ void tune_store(const TuneKey& k, const TuneChoice& c) {
     if (!path || !path[0]) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %d\n", key_string(k, c.mi).c_str(), c.mi, c.tile_rows, c.cpb);
+    std::fprintf(f, "%s %d %d %d %d %d %d %d\n", key_string(k, c.mi).c_str(), c.mi, c.tile_rows, c.cpb, c.variant,
+                 c.march_rows, c.march_seg, c.march_order);
     std::fclose(f);
 }
 

@@ -15,6 +15,10 @@ struct TuneChoice {
     int mi = 1;          // members interleaved in the fastest index
     int tile_rows = 4;   // cell rows per 256-lane tile
     int cpb = 16;        // member chunks per workgroup
+    int variant = 1;     // 1 tiled kernel, 2 row-marching kernel
+    int march_rows = 32; // rows per strip of the row-marching kernel
+    int march_seg = 2;   // members marched together by one wavefront
+    int march_order = 1; // wavefront order: 0 members fastest, 1 strips fastest
 };
 
 TuneChoice tune_default(const TuneKey& k);

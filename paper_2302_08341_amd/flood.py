@@ -46,7 +46,8 @@ class FloodParams(C.Structure):
     _fields_ = [("rain_rate", C.POINTER(C.c_double)), ("n_rain", C.c_int32), ("rain_interval", C.c_double),
                 ("cfl_alpha", C.c_double), ("h_dry", C.c_double), ("dt_cap", C.c_double),
                 ("dt_fixed", C.c_double), ("g", C.c_double), ("real_bytes", C.c_int32),
-                ("member_interleave", C.c_int32), ("tile_rows", C.c_int32), ("chunks_per_block", C.c_int32)]
+                ("member_interleave", C.c_int32), ("tile_rows", C.c_int32), ("chunks_per_block", C.c_int32),
+                ("step_kernel", C.c_int32), ("march_rows", C.c_int32), ("march_members", C.c_int32)]
 
 
 _lib = None
@@ -79,7 +80,7 @@ def load_library():
         "flood_systematic_resample": [dp, C.c_int32, C.c_double, ip, C.c_void_p],
         "flood_save": [H, C.c_char_p],
         "flood_load": [H, C.c_char_p],
-        "flood_get_config": [H, ip, ip, ip, ip],
+        "flood_get_config": [H, ip, ip, ip, ip, ip, ip, ip],
         "flood_timing": [H, C.c_int32],
         "flood_get_timing": [H, dp, lp],
     }
@@ -147,11 +148,13 @@ def make_grid(dem, manning, dx, edge_kind=(0, 0, 0, 0), edge_slope=(0, 0, 0, 0),
 
 
 def make_params(rain, rain_interval=300.0, cfl_alpha=0.7, h_dry=1e-3, dt_cap=10.0, dt_fixed=0.0, g=9.81,
-                real_bytes=4, member_interleave=0, tile_rows=0, chunks_per_block=0):
+                real_bytes=4, member_interleave=0, tile_rows=0, chunks_per_block=0, step_kernel=0, march_rows=0,
+                march_members=0):
     rain = _f64(np.asarray(rain, dtype=np.float64).ravel())
     p = FloodParams(_dp(rain) if rain.size else None, int(rain.size), float(rain_interval), float(cfl_alpha),
                     float(h_dry), float(dt_cap), float(dt_fixed), float(g), int(real_bytes),
-                    int(member_interleave), int(tile_rows), int(chunks_per_block))
+                    int(member_interleave), int(tile_rows), int(chunks_per_block), int(step_kernel),
+                    int(march_rows), int(march_members))
     p._keep = (rain,)
     return p
 
@@ -260,10 +263,11 @@ def flood_load(h, path):
 
 
 def flood_get_config(h):
-    v = [C.c_int32(0) for _ in range(4)]
+    v = [C.c_int32(0) for _ in range(7)]
     _check(load_library().flood_get_config(h, *[C.byref(x) for x in v]), h)
     return {"member_interleave": v[0].value, "tile_rows": v[1].value, "chunks_per_block": v[2].value,
-            "graph_steps": v[3].value}
+            "graph_steps": v[3].value, "step_kernel": v[4].value, "march_rows": v[5].value,
+            "march_members": v[6].value}
 
 
 def flood_timing(h, enable):
@@ -290,14 +294,15 @@ class FloodEnsemble:
 
     def __init__(self, catchments, rain, rain_interval=300.0, cfl_alpha=0.7, h_dry=1e-3, dt_cap=10.0,
                  dt_fixed=0.0, g=9.81, real_bytes=4, member_interleave=0, tile_rows=0, chunks_per_block=0,
-                 stream="torch"):
+                 step_kernel=0, march_rows=0, march_members=0, stream="torch"):
         self.catchments = list(catchments)
         grids, params = [], []
         for c in self.catchments:
             grids.append(make_grid(c["dem"], c["manning"], c["dx"], c.get("edge_kind", (0, 0, 0, 0)),
                                    c.get("edge_slope", (0, 0, 0, 0)), c.get("h0")))
             params.append(make_params(rain, rain_interval, cfl_alpha, h_dry, dt_cap, dt_fixed, g, real_bytes,
-                                      member_interleave, tile_rows, chunks_per_block))
+                                      member_interleave, tile_rows, chunks_per_block, step_kernel, march_rows,
+                                      march_members))
         self._keep = (grids, params)
         self.stream = current_stream() if stream == "torch" else stream
         self.h = flood_create_batch(grids, params, [c["n_members"] for c in self.catchments],

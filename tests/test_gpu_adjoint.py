@@ -5,7 +5,8 @@ Bars: FP64 handle vs oracle adjoint 1e-8 relative; FP32 handle vs oracle
 adjoint 1e-3 relative (rain-multiplier gradient per member, Manning-field
 gradient in the 2-norm); central differences of the FP64 GPU loss (1e-3
 relative perturbation, fixed step so the step sequence does not move) within
-1e-3 for the FP32 adjoint and 1e-4 for the FP64 adjoint.
+1e-3 for the FP32 adjoint and 1e-4 for the FP64 adjoint (1e-4 relative
+perturbation in the Manning direction).
 """
 import numpy as np
 import pytest
@@ -126,8 +127,12 @@ def test_adjoint_central_differences(fl, rb, tol):
         fd = (_adj_fixed(fl, z, n, h0, s, mp, g, obs, rain, 8)[0]
               - _adj_fixed(fl, z, n, h0, s, mm, g, obs, rain, 8)[0]) / (2 * eps * mu[i])
         assert gm[i] == pytest.approx(fd, rel=tol)
+    # Manning direction: the gap between the frozen-branch adjoint and central
+    # differences shrinks linearly with the step here (a branch kink lies within
+    # the perturbation; the FP64 oracle shows the same 4.4e-4 at 1e-3 and 4e-5 at
+    # 1e-4), so this direction takes the smaller step
     v = np.random.default_rng(5).standard_normal(n.shape)
-    dn = 1e-3 * n.astype(np.float64) * v
+    dn = 1e-4 * n.astype(np.float64) * v
     n_p = (n.astype(np.float64) + dn).astype(np.float32)    # the library takes the field in FP32
     n_m = (n.astype(np.float64) - dn).astype(np.float32)
     dn_eff = (n_p.astype(np.float64) - n_m.astype(np.float64)) / 2.0
@@ -180,6 +185,6 @@ def test_autograd_function(fl):
     (2.0 * loss).backward()
     np.testing.assert_array_equal(e.field(1), before)       # state restored
     ref = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, real_bytes=4).adjoint(0, 40.0, 10.0, g, obs, 10)
-    assert float(loss) == ref[0]
+    assert loss.item() == ref[0]
     np.testing.assert_allclose(nt.grad.numpy(), 2.0 * ref[1], rtol=1e-6)
     np.testing.assert_allclose(mt.grad.numpy(), 2.0 * ref[2], rtol=1e-6)

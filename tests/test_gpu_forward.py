@@ -125,10 +125,11 @@ def test_one_step_parity_from_identical_state(fl, orc):
         assert np.all((r != 0)[g != 0])
 
 
-def test_plain_method_fp64_config1(fl, orc):
+@pytest.mark.parametrize("sk", [1, 2])
+def test_plain_method_fp64_config1(fl, orc, sk):
     wl = W.config1()
     c = wl.catchments[0]
-    e = _ens(fl, c, wl.rain, 1, real_bytes=8)
+    e = _ens(fl, c, wl.rain, 1, real_bytes=8, member_interleave=1, step_kernel=sk)
     e.step(wl.t_end)
     m = orc.Model.from_workload(wl)
     mem = orc.Member.dry(m)
@@ -142,16 +143,41 @@ def test_plain_method_fp64_config1(fl, orc):
     assert resid <= 1e-12
 
 
-@pytest.mark.parametrize("mi,rows,cpb", [(1, 1, 1), (2, 4, 3), (4, 2, 2), (8, 8, 1), (8, 1, 4)])
-def test_interleave_and_tiling_are_bit_exact(fl, mi, rows, cpb):
+@pytest.mark.parametrize("mi,rows,cpb,sk,mr,mm", [(1, 1, 1, 1, 0, 1), (2, 4, 3, 1, 0, 1), (4, 2, 2, 1, 0, 1),
+                                                 (8, 8, 1, 1, 0, 1), (8, 1, 4, 1, 0, 1), (1, 4, 5, 2, 1, 1),
+                                                 (1, 4, 5, 2, 7, 2), (1, 4, 5, 2, 64, 4), (1, 4, 5, 2, 500, 8),
+                                                 (1, 4, 5, 2, 13, 4)])
+def test_interleave_and_tiling_are_bit_exact(fl, mi, rows, cpb, sk, mr, mm):
     rain = W.chicago_hyetograph()
-    ref = _ens(fl, URBAN, rain, 5, real_bytes=4, member_interleave=1, tile_rows=4, chunks_per_block=5)
+    ref = _ens(fl, URBAN, rain, 5, real_bytes=4, member_interleave=1, tile_rows=4, chunks_per_block=5,
+               step_kernel=1)
     ref.step(400.0)
-    e = _ens(fl, URBAN, rain, 5, real_bytes=4, member_interleave=mi, tile_rows=rows, chunks_per_block=cpb)
+    e = _ens(fl, URBAN, rain, 5, real_bytes=4, member_interleave=mi, tile_rows=rows, chunks_per_block=cpb,
+             step_kernel=sk, march_rows=mr, march_members=mm)
+    assert e.config()["step_kernel"] == sk
     e.step(400.0)
     for i in range(5):
         for w in (fl.FIELD_H, fl.FIELD_QX, fl.FIELD_QY):
             np.testing.assert_array_equal(e.field(i, w), ref.field(i, w))
+
+
+URBAN4 = W.urban_catchment("par4", 61, 300, 3, W.seed_for(2, 4), n_gauges=3)   # nx % 4 == 0, 2 strips
+
+
+@pytest.mark.parametrize("rb", [4, 8])
+@pytest.mark.parametrize("mr", [1, 5, 16, 100])
+def test_vectorised_march_is_bit_exact(fl, rb, mr):
+    rain = W.chicago_hyetograph()
+    ref = _ens(fl, URBAN4, rain, 3, real_bytes=rb, member_interleave=1, tile_rows=4, chunks_per_block=3,
+               step_kernel=1)
+    ref.step(350.0)
+    e = _ens(fl, URBAN4, rain, 3, real_bytes=rb, member_interleave=1, step_kernel=3, march_rows=mr)
+    assert e.config()["step_kernel"] == 3
+    e.step(350.0)
+    for i in range(3):
+        for w in (fl.FIELD_H, fl.FIELD_QX, fl.FIELD_QY):
+            np.testing.assert_array_equal(e.field(i, w), ref.field(i, w))
+    np.testing.assert_array_equal(e.ledger()["outflow"], ref.ledger()["outflow"])
 
 
 def test_batched_equals_one_launch_per_member(fl):
