@@ -11,14 +11,29 @@ all members) followed by the filter update (gauge gather, weights, N_eff,
 systematic resampling and member copy when N_eff < 0.8 N).  Observations
 come from a hidden truth member run beforehand plus N(0, 0.05^2) noise.
 
-Metric: member-cell-updates per second (MCU/s) over the timed steps,
-counted from the per-member step counters.  The JSON line also carries the
-roofline of the step kernel (HIP-event durations of every step launch in the
-timed region) and the FP64 oracle timed on the host cores.
+`value` is member-cell-updates per second (MCU/s) over the timed cycles,
+counted from the per-member step counters, filter updates included.  The JSON
+line also carries the roofline of the step kernel (HIP-event durations of
+every step launch in the timed region), the FP64 oracle timed on the host
+cores, and in `detail` the other parts of the metric, each outside the timed
+region:
+  * step kernels alone (MCU over summed kernel time);
+  * forward + adjoint over the first 900 s of the same ensemble (Manning-field
+    and rain-multiplier gradients of a 10-s gauge misfit, checkpoints every
+    100 steps) against the forward alone over the same window;
+  * batched against plain (one handle and one launch per member) on this
+    workload over its first window, and on the four-catchment batch
+    (512^2, 768x1536, 1024^2, 2000^2, 24 members each) over its first 300 s;
+  * the streaming ceiling of one elementwise kernel (2 GiB in, 2 GiB out).
+
+The timed cycles run last among full-size launches of the step kernel, so
+that a kernel trace of this command can isolate them (the last `launches`
+dispatches of that kernel with the full ensemble's grid).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import multiprocessing as mp
 import os
@@ -32,6 +47,15 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_MCU = 24.0    # h, qx, qy read + written once per member-cell-step (FP32)
+KERNEL_NAMES = {1: "k_step", 2: "k_march", 3: "k_marchv"}
+KERNEL_TITLES = {1: "k_step (tiled fused step)", 2: "k_march (row-march fused step)",
+                 3: "k_marchv (vectorised row-march fused step)"}
+KERNEL_SOURCES = ("paper_2302_08341_amd/csrc/flood_kernels.hip", "paper_2302_08341_amd/csrc/flood_device.h",
+                  "paper_2302_08341_amd/csrc/flood_internal.h")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
 def _cpu_worker(args):
@@ -64,6 +88,141 @@ def cpu_baseline(cfg, cores, n_steps):
                       "process, %.1f s wall incl. start-up)" % (n_steps, cores, busy, wall)}
 
 
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload_tag):
+    """HBM bytes per launch from the committed counter summary of this kernel and
+    workload, if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.md" % (kernel, workload_tag))
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_sources_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def ensemble_args(c, members, n_scale=None, rain_mult=None):
+    return dict(dem=c.dem, manning=c.manning, dx=c.dx, edge_kind=c.edge_kind, edge_slope=c.edge_slope,
+                n_members=len(members) if n_scale is None else len(n_scale),
+                n_scale=c.n_scale[members] if n_scale is None else n_scale,
+                rain_mult=c.rain_mult[members] if rain_mult is None else rain_mult)
+
+
+def truth_observations(FloodEnsemble, W, wl, times, rng):
+    """Gauge depths of a hidden truth member (drawn from the same prior) at the
+    given times plus N(0, sigma^2) noise.  Runs on the tiled kernel so that the
+    step kernel measured below sees only ensemble launches."""
+    c = wl.catchments[0]
+    truth = FloodEnsemble([ensemble_args(c, None, [c.truth_n_scale], [c.truth_rain_mult])], wl.rain,
+                          rain_interval=wl.rain_interval, real_bytes=wl.real_bytes, step_kernel=1,
+                          tile_rows=4, chunks_per_block=1, march_rows=8, march_members=1)
+    out = {}
+    for t in sorted(times):
+        truth.step(t)
+        hv = truth.field(0)[c.gauges[:, 0], c.gauges[:, 1]]
+        out[t] = W.obs_noise(rng, hv, wl.obs_sigma)
+    truth.close()
+    return out
+
+
+def elementwise_ceiling(torch):
+    """One elementwise kernel reading and writing 2 GiB each: the attainable
+    streaming rate, and the known-size kernel for scaling the memory counters."""
+    x = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
+    ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    y = x + 1.0
+    torch.cuda.synchronize()
+    ea.record()
+    for _ in range(5):
+        y = x + 1.0
+    eb.record()
+    torch.cuda.synchronize()
+    gbs = 5 * 2 * x.numel() * 4 / (ea.elapsed_time(eb) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def leg_adjoint(FloodEnsemble, wl, obs_adj, window, sample_dt, ckpt):
+    """Forward + adjoint over [0, window] of the full ensemble, against the forward alone."""
+    c = wl.catchments[0]
+    ncell = c.ny * c.nx
+    ens = FloodEnsemble.from_workload(wl)
+    t0 = time.perf_counter()
+    ens.step(window)
+    t_fwd = time.perf_counter() - t0
+    steps_fwd = int(ens.ledger()["steps"].sum())
+    ens.close()
+    log("adjoint leg: forward alone %.2f s" % t_fwd)
+    ens = FloodEnsemble.from_workload(wl)
+    obs = np.stack([obs_adj[t] for t in sorted(obs_adj)])
+    t0 = time.perf_counter()
+    loss, gn, gm = ens.adjoint(0, window, sample_dt, c.gauges, obs, ckpt_every=ckpt)
+    t_adj = time.perf_counter() - t0
+    steps_adj = int(ens.ledger()["steps"].sum())
+    ens.close()
+    log("adjoint leg: forward + adjoint %.2f s" % t_adj)
+    return {"workload": "first %.0f s of the same ensemble (%d x %d cells x %d members), loss = squared misfit "
+                        "at %d gauges every %.0f s, checkpoints every %d steps" % (
+                            window, c.ny, c.nx, c.n_members, c.gauges.shape[0], sample_dt, ckpt),
+            "fwd_adj_MCUps": steps_adj * ncell / t_adj, "fwd_MCUps": steps_fwd * ncell / t_fwd,
+            "member_steps": steps_adj, "fwd_s": t_fwd, "fwd_adj_s": t_adj, "adj_over_fwd": t_adj / t_fwd,
+            "loss": float(loss), "grad_n_norm": float(np.linalg.norm(gn)),
+            "grad_mult_mean_abs": float(np.mean(np.abs(gm)))}
+
+
+def leg_c4(FloodEnsemble, W, window, per_catch):
+    """Four uneven catchments in one batched handle against one handle per member."""
+    wl = W.config4()
+    ens = FloodEnsemble.from_workload(wl)
+    t0 = time.perf_counter()
+    ens.step(window)
+    t_b = time.perf_counter() - t0
+    conf = ens.config()
+    steps = [ens.ledger(i)["steps"] for i in range(len(wl.catchments))]
+    ens.close()
+    mcu = sum(int(s.sum()) * c.ny * c.nx for s, c in zip(steps, wl.catchments))
+    # plain: a sample of members per catchment, each alone; the full job's plain
+    # time is the per-member mean times the member count, catchment by catchment
+    plain_time = 0.0
+    sampled = []
+    for j, c in enumerate(wl.catchments):
+        ts = []
+        for m in range(per_catch):
+            e = FloodEnsemble([ensemble_args(c, [m])], wl.rain, rain_interval=wl.rain_interval,
+                              real_bytes=wl.real_bytes)
+            t0 = time.perf_counter()
+            e.step(window)
+            ts.append(time.perf_counter() - t0)
+            if int(e.ledger()["steps"][0]) != int(steps[j][m]):
+                raise RuntimeError("plain and batched member step counts differ")
+            e.close()
+        plain_time += c.n_members * float(np.mean(ts))
+        sampled.append(float(np.mean(ts)))
+    log("four-catchment leg: batched %.2f s, plain (estimated) %.2f s" % (t_b, plain_time))
+    return {"workload": "512^2, 768x1536, 1024^2, 2000^2 cells x 24 members each, first %.0f s" % window,
+            "batched_MCUps": mcu / t_b, "plain_MCUps": mcu / plain_time, "speedup": plain_time / t_b,
+            "batched_s": t_b, "plain_s_estimated": plain_time,
+            "plain_sample": "%d members per catchment run alone; mean seconds per member %s" % (
+                per_catch, [round(x, 4) for x in sampled]),
+            "batched_config": conf}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,16 +237,24 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--cpu-cores", type=int, default=0)
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adj-window", type=float, default=900.0)
+    ap.add_argument("--adj-sample", type=float, default=10.0)
+    ap.add_argument("--adj-ckpt", type=int, default=100)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--plain-members", type=int, default=8)
+    ap.add_argument("--no-c4", action="store_true")
+    ap.add_argument("--c4-window", type=float, default=300.0)
+    ap.add_argument("--c4-plain-members", type=int, default=2)
     ap.add_argument("--mi", type=int, default=0)
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--cpb", type=int, default=0)
-    ap.add_argument("--kernel", type=int, default=0, help="0 autotune, 1 tiled, 2 row-marching")
-    ap.add_argument("--kernel-only", type=int, default=0,
-                    help="after the warm-up, time this many single steps in which every member steps")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="after the run, copy a 1 GiB device buffer (counter calibration for profiling)")
+    ap.add_argument("--kernel", type=int, default=0, help="0 autotune, 1 tiled, 2 row-march, 3 vectorised")
     ap.add_argument("--march-rows", type=int, default=0)
     ap.add_argument("--march-members", type=int, default=0)
+    ap.add_argument("--kernel-only", type=int, default=0,
+                    help="after the warm-up, time this many single steps in which every member steps "
+                         "and print their average instead of the benchmark line")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -97,9 +264,11 @@ def main():
 
     cfg = {"config": args.config, "ny": args.ny, "nx": args.nx, "members": args.members}
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and not args.kernel_only:
         cores = args.cpu_cores or min(16, os.cpu_count() or 1)
+        log("oracle baseline on %d cores" % cores)
         cpu = cpu_baseline(cfg, cores, args.cpu_steps)
+        log("oracle baseline %.3e MCU/s" % cpu["value"])
 
     import torch
     import workloads as W
@@ -114,34 +283,51 @@ def main():
     sigma = np.full(K, wl.obs_sigma)
     n_cycles = args.warmup + args.steps
     rng = np.random.default_rng(wl.seed + 7)
-
-    # observations: hidden truth member drawn from the same prior
-    truth = FloodEnsemble([dict(dem=c.dem, manning=c.manning, dx=c.dx, edge_kind=c.edge_kind,
-                                edge_slope=c.edge_slope, n_members=1, n_scale=[c.truth_n_scale],
-                                rain_mult=[c.truth_rain_mult])], wl.rain, real_bytes=wl.real_bytes)
-    obs = []
-    for k in range(n_cycles):
-        truth.step((k + 1) * args.window)
-        hv = truth.field(0)[c.gauges[:, 0], c.gauges[:, 1]]
-        obs.append(W.obs_noise(rng, hv, wl.obs_sigma))
-    truth.close()
+    win_times = [(k + 1) * args.window for k in range(n_cycles)]
+    n_adj = int(round(args.adj_window / args.adj_sample))
+    adj_times = [(i + 1) * args.adj_sample for i in range(n_adj)] if not args.no_adjoint else []
+    log("workload ready: %d x %d cells x %d members" % (c.ny, c.nx, N))
+    obs_all = truth_observations(FloodEnsemble, W, wl, set(win_times) | set(adj_times), rng)
     draws = [W.pf_draws(rng, N) for _ in range(n_cycles)]
+    log("truth observations done")
+    detail = {}
+
+    # forward + adjoint first: the timed cycles below are then the last full-size step launches
+    if adj_times and not args.kernel_only:
+        detail["fwd_adj"] = leg_adjoint(FloodEnsemble, wl, {t: obs_all[t] for t in adj_times},
+                                        args.adj_window, args.adj_sample, args.adj_ckpt)
+    if not args.no_c4 and not args.kernel_only:
+        detail["batched_vs_plain_c4"] = leg_c4(FloodEnsemble, W, args.c4_window, args.c4_plain_members)
 
     ens = FloodEnsemble.from_workload(wl, member_interleave=args.mi, tile_rows=args.rows,
                                       chunks_per_block=args.cpb, step_kernel=args.kernel,
                                       march_rows=args.march_rows, march_members=args.march_members)
     conf = ens.config()
+    log("ensemble ready, step kernel %d" % conf["step_kernel"])
     resampled = []
+    cycle_log = []
+    n_plain = 0 if (args.no_plain or args.kernel_only) else min(args.plain_members, N)
+    snap = {}
 
     def cycle(k):
-        ens.step((k + 1) * args.window)
+        s0 = int(ens.ledger()["steps"].sum())
+        t0 = time.perf_counter()
+        ens.step(win_times[k])
+        t1 = time.perf_counter()
+        s1 = int(ens.ledger()["steps"].sum())
+        if k == 0:
+            for m in range(n_plain):
+                snap[m] = ens.field(m)
         u0, beta = draws[k]
-        neff, anc, res = ens.assimilate(0, c.gauges, obs[k], sigma, 0.8, u0, beta)
+        neff, anc, res = ens.assimilate(0, c.gauges, obs_all[win_times[k]], sigma, 0.8, u0, beta)
+        t2 = time.perf_counter()
         resampled.append(bool(res))
+        cycle_log.append({"step_s": t1 - t0, "filter_s": t2 - t1, "member_steps": s1 - s0, "neff": float(neff)})
 
     for k in range(args.warmup):
         cycle(k)
     torch.cuda.synchronize()
+    log("warm-up done")
     if args.kernel_only:
         # every launch steps every member: single steps of 0.02 s, shorter than Eq. 4 allows here
         t = args.warmup * args.window
@@ -155,23 +341,11 @@ def main():
         steps = int((l1["steps"] - l0["steps"]).sum())
         full = steps // args.kernel_only
         gbs = BYTES_PER_MCU * full * ncell / (avg_ms * 1e-3) / 1e9 if launches == args.kernel_only else None
-        # attainable streaming bandwidth: one elementwise kernel reading and writing 2 GiB each
-        x = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
-        ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        y = x + 1.0
-        torch.cuda.synchronize()
-        ea.record()
-        for _ in range(5):
-            y = x + 1.0
-        eb.record()
-        torch.cuda.synchronize()
-        copy_gbs = 5 * 2 * x.numel() * 4 / (ea.elapsed_time(eb) * 1e-3) / 1e9
-        del x, y
         print(json.dumps({"kernel_only": True, "members_per_launch": full, "real_launches": args.kernel_only,
                           "timed_launches": launches, "avg_launch_ms": avg_ms, "algorithmic_GBps": gbs,
-                          "elementwise_copy_GBps": copy_gbs,
-                          "config": ens.config()}))
+                          "elementwise_copy_GBps": elementwise_ceiling(torch), "config": ens.config()}))
         return
+
     led0 = ens.ledger()
     if not args.no_kernel_timing:
         ens.timing(True)
@@ -185,23 +359,59 @@ def main():
         ens.timing(False)
     led1 = ens.ledger()
     avg_ms, launches = ens.get_timing()
+    log("timed cycles done: %.2f s" % elapsed)
 
     member_steps = int((led1["steps"] - led0["steps"]).sum())
     mcu = member_steps * ncell
     value = mcu / elapsed
     mass = float(np.max(np.abs(led1["storage"] - (led1["rain_in"] - led1["outflow"] + led1["clamp"]))
                         / np.maximum(led1["rain_in"], 1e-30)))
+    ens.close()
 
+    workload_tag = "urban%dx%dx%d" % (c.ny, c.nx, N)
+    kname = KERNEL_NAMES.get(conf["step_kernel"], "k_step")
     roof = None
     if launches:
         mcu_per_launch = mcu / launches
-        achieved = BYTES_PER_MCU * mcu_per_launch / (avg_ms * 1e-3) / 1e9
+        alg_bytes = BYTES_PER_MCU * mcu_per_launch
+        achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+        traffic = measured_traffic(kname, workload_tag)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_march (row-marching fused step)" if conf["step_kernel"] == 2
-                          else "k_step (tiled fused step)",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": KERNEL_TITLES.get(conf["step_kernel"], kname),
                 "avg_launch_ms": round(avg_ms, 4), "launches": launches,
-                "algorithmic_bytes_per_launch": round(BYTES_PER_MCU * mcu_per_launch)}
+                "algorithmic_bytes_per_launch": round(alg_bytes),
+                "traffic_over_algorithmic": round(traffic / alg_bytes, 3) if traffic else None,
+                "kernel_sources_sha256": kernel_source_hash()}
+        detail["kernel_only_MCUps"] = mcu / (launches * avg_ms * 1e-3)
+
+    if n_plain:
+        # plain: one handle and one launch per member over the first window
+        c0 = cycle_log[0]
+        t_plain, s_plain = 0.0, 0
+        exact = True
+        for m in range(n_plain):
+            e = FloodEnsemble([ensemble_args(c, [m])], wl.rain, rain_interval=wl.rain_interval,
+                              real_bytes=wl.real_bytes)
+            ta = time.perf_counter()
+            e.step(win_times[0])
+            t_plain += time.perf_counter() - ta
+            s_plain += int(e.ledger()["steps"][0])
+            exact &= bool(np.array_equal(e.field(0), snap[m]))
+            e.close()
+        plain_rate = s_plain * ncell / t_plain
+        batched_rate = c0["member_steps"] * ncell / c0["step_s"]
+        detail["batched_vs_plain"] = {
+            "workload": "first %.0f s of this ensemble from the dry start" % args.window,
+            "batched_MCUps": batched_rate, "plain_MCUps": plain_rate, "speedup": batched_rate / plain_rate,
+            "plain_sample": "%d members each run alone in its own handle" % n_plain,
+            "plain_bit_identical": exact}
+        log("plain leg done")
+
+    detail["copy_ceiling_GBps"] = elementwise_ceiling(torch)
+    detail.update({"member_steps": member_steps, "mcu": mcu, "elapsed_s": elapsed, "cycles": cycle_log[args.warmup:],
+                   "resampled": resampled[args.warmup:], "mass_balance_rel": mass,
+                   "paper_context": "8x P100: 4.69e10 MCU/s (96 x 4.0 M cells x 14,400 steps in 118 s)"})
 
     out = {
         "metric": "member-cell-updates/s fwd & fwd+adj; % HBM peak; batched vs plain, 96x4M",
@@ -225,18 +435,9 @@ def main():
                    "march_rows": conf["march_rows"], "march_members": conf["march_members"]},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "detail": {"member_steps": member_steps, "mcu": mcu, "elapsed_s": elapsed,
-                   "resampled": resampled[args.warmup:], "mass_balance_rel": mass,
-                   "paper_context": "8x P100: 4.69e10 MCU/s (96 x 4.0 M cells x 14,400 steps in 118 s)"},
+        "detail": detail,
     }
-    if args.copy_calibration:
-        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-        torch.cuda.synchronize()
-        y = x + 1.0          # one elementwise kernel: reads 1 GiB, writes 1 GiB
-        torch.cuda.synchronize()
-        del y
-        out["detail"]["copy_calibration_bytes"] = 2 * x.numel() * 4
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

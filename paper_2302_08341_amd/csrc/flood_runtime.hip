@@ -574,7 +574,15 @@ template <typename T> struct Impl : ImplBase {
         c.march_rows = bc.mrows;
         c.march_seg = bc.seg;
         c.march_order = bc.order;
-        tune_store(key, c);
+        // only a search over the full candidate set is remembered: a handle that
+        // pinned part of the geometry measured a subset, whose best need not be
+        // the best for a later handle of the same shape
+        bool free_search = true;
+        for (int i = 0; i < n_catch; ++i)
+            free_search &= params[i].tile_rows == 0 && params[i].chunks_per_block == 0 &&
+                           params[i].step_kernel == 0 && params[i].march_rows == 0 &&
+                           params[i].march_members == 0;
+        if (free_search) tune_store(key, c);
         return FLOOD_OK;
     }
 

@@ -1,13 +1,18 @@
 // Geometry defaults and the measured-choice cache of libflood.
 //
-// Cache file: $FLOOD_TUNE_CACHE (no caching when unset).  One line per tuned
-// problem: "<key> mi tile_rows cpb variant march_rows march_seg march_order".  Set FLOOD_AUTOTUNE=0 to skip measuring
-// and use the defaults (or the explicit values given at creation).
+// Measured choices are remembered for the life of the process, so handles of
+// one problem shape after the first do not measure again, and optionally in a
+// file: $FLOOD_TUNE_CACHE, one line per tuned problem,
+// "<key> mi tile_rows cpb variant march_rows march_seg march_order".  Set
+// FLOOD_AUTOTUNE=0 to skip measuring and use the defaults (or the explicit
+// values given at creation).
 #include "flood_tune.h"
 
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 
 namespace flood {
@@ -38,7 +43,21 @@ bool tune_enabled() {
     return !(e && e[0] == '0');
 }
 
+static std::mutex memo_mu;
+static std::map<std::string, TuneChoice>& memo() {
+    static std::map<std::string, TuneChoice> m;
+    return m;
+}
+
 bool tune_lookup(const TuneKey& k, int mi, TuneChoice& out) {
+    {
+        std::lock_guard<std::mutex> lock(memo_mu);
+        auto it = memo().find(key_string(k, mi));
+        if (it != memo().end()) {
+            out = it->second;
+            return true;
+        }
+    }
     const char* path = std::getenv("FLOOD_TUNE_CACHE");
     if (!path || !path[0]) return false;
     FILE* f = std::fopen(path, "r");
@@ -64,6 +83,10 @@ bool tune_lookup(const TuneKey& k, int mi, TuneChoice& out) {
 }
 
 void tune_store(const TuneKey& k, const TuneChoice& c) {
+    {
+        std::lock_guard<std::mutex> lock(memo_mu);
+        memo()[key_string(k, c.mi)] = c;
+    }
     const char* path = std::getenv("FLOOD_TUNE_CACHE");
     if (!path || !path[0]) return;
     FILE* f = std::fopen(path, "a");
