@@ -292,6 +292,298 @@ template <typename T> void launch_adjoint_step(int mi, const AdjLaunch<T>& A, hi
     }
 }
 
+// Adjoint of the new depths after the clamp branch: zero where the forward
+// clamped the depth at zero, the stored adjoint elsewhere.
+template <typename T, int V>
+__device__ __forceinline__ void le_load(const T* lh, const uint8_t* cl, T (&d)[V]) {
+    T v[V];
+    vload<T, V>(lh, v);
+    uint32_t f;
+    if constexpr (V == 4)
+        f = *reinterpret_cast<const uint32_t*>(cl);
+    else
+        f = *reinterpret_cast<const uint16_t*>(cl);
+#pragma unroll
+    for (int j = 0; j < V; ++j) d[j] = ((f >> (8 * j)) & 0xffu) ? T(0) : v[j];
+}
+
+// Reverse step in row-march form.  Geometry as the forward row march: one
+// wavefront per (strip of 62 V cells, member), marching down the strip's rows;
+// lanes 0 and 63 are halo lanes.  Per row each lane evaluates the derivatives
+// of the east and south links of its V cells once; the west link of its first
+// cell comes from the neighbouring lane and the north link from the previous
+// row, so every link is differentiated once per step.  Contributions to a
+// cell's depth adjoint are added in the order east, south, west, north (as in
+// k_adj).  The Manning-field adjoint of each cell is accumulated per member
+// (no atomics) and the rain-multiplier adjoint per (strip, member).
+template <typename T, int V>
+__global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
+    const CatchDev<T>& C = A.c;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int wg = xcd_remap(blockIdx.x, gridDim.x) * (kBlock / 64) + wave;
+    if (wg >= C.n_waves) return;
+    int k, sx, sy;
+    if (C.march_order == 0) {
+        k = wg % C.n_members;
+        const int strip = wg / C.n_members;
+        sy = strip / C.strips_x;
+        sx = strip - sy * C.strips_x;
+    } else {
+        sx = wg % C.strips_x;
+        const int rest = wg / C.strips_x;
+        sy = rest % C.strips_y;
+        k = rest / C.strips_y;
+    }
+    const MemberStep<T> ms = A.ms[k];
+    if (!ms.active) return;
+    const int nx = C.nx, ny = C.ny;
+    const int xl = sx * (62 * V) - V + V * lane;
+    const bool inx = xl >= 0 && xl < nx;
+    const bool own = lane >= 1 && lane <= 62 && inx;
+    const int r0 = sy * C.march_rows;
+    const int r1 = min(r0 + C.march_rows, ny);
+    const size_t plane = (size_t)ny * nx;
+    const size_t so = (size_t)ms.slot * A.slot_stride;
+    const T* __restrict__ H = C.h[0] + so + (size_t)k * plane;
+    const T* __restrict__ QX = C.qx[0] + so + (size_t)k * plane;
+    const T* __restrict__ QY = C.qy[0] + so + (size_t)k * plane;
+    const T* __restrict__ QWs = C.qw[0] + so + (size_t)k * ny;
+    const T* __restrict__ QNs = C.qn[0] + so + (size_t)k * nx;
+    const uint8_t* __restrict__ CL = A.clamp + (size_t)ms.slot * A.clamp_stride + (size_t)k * plane;
+    const int lp = A.lpar[k];
+    const T* __restrict__ LH = A.lh[lp] + (size_t)k * plane;
+    const T* __restrict__ LQX = A.lqx[lp] + (size_t)k * plane;
+    const T* __restrict__ LQY = A.lqy[lp] + (size_t)k * plane;
+    const T* __restrict__ LQWs = A.lqw[lp] + (size_t)k * ny;
+    const T* __restrict__ LQNs = A.lqn[lp] + (size_t)k * nx;
+    T* __restrict__ LHo = A.lh[lp ^ 1] + (size_t)k * plane;
+    T* __restrict__ LQXo = A.lqx[lp ^ 1] + (size_t)k * plane;
+    T* __restrict__ LQYo = A.lqy[lp ^ 1] + (size_t)k * plane;
+    T* __restrict__ LQWo = A.lqw[lp ^ 1] + (size_t)k * ny;
+    T* __restrict__ LQNo = A.lqn[lp ^ 1] + (size_t)k * nx;
+    T* __restrict__ NA = A.nacc + (size_t)k * plane;
+    const T* __restrict__ Z = C.z;
+    const T* __restrict__ Nn = C.n;
+    const T g = C.g, hdry = C.hdry, kk = ms.dtdx;
+
+    size_t c0 = (size_t)r0 * nx + xl;
+    T hc[V], zc[V], nc[V], lec[V], pNh[V], pNn[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) hc[j] = zc[j] = nc[j] = lec[j] = pNh[j] = pNn[j] = T(0);
+    if (inx) {
+        vload<T, V>(H + c0, hc);
+        vload<T, V>(Z + c0, zc);
+        vload<T, V>(Nn + c0, nc);
+        le_load<T, V>(LH + c0, CL + c0, lec);
+        if (r0 > 0) {
+            // the south links of the row above the strip feed its first row's north links
+            T hN[V], zN[V], nN[V], qN[V], lqN[V], leN[V];
+            vload<T, V>(H + c0 - nx, hN);
+            vload<T, V>(Z + c0 - nx, zN);
+            vload<T, V>(Nn + c0 - nx, nN);
+            vload<T, V>(QY + c0 - nx, qN);
+            vload<T, V>(LQY + c0 - nx, lqN);
+            le_load<T, V>(LH + c0 - nx, CL + c0 - nx, leN);
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                const T nf = T(0.5) * (nN[j] + nc[j]);
+                T dq, d1, d2, cn;
+                link_in_d(qN[j], hN[j], hc[j], zc[j] - zN[j], g * (nf * nf), g * nf, ms, hdry, dq, d1, d2, cn);
+                const T lt = lqN[j] + kk * (lec[j] - leN[j]);
+                pNh[j] = lt * d2;
+                pNn[j] = lt * cn;
+            }
+        }
+    }
+    double lsum = 0.0;
+    for (int r = r0; r < r1; ++r) {
+        const bool hasS = r + 1 < ny;
+        T qE[V], qS[V], lqE[V], lqS[V], hs[V], zs[V], ns[V], les[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) qE[j] = qS[j] = lqE[j] = lqS[j] = hs[j] = zs[j] = ns[j] = les[j] = T(0);
+        if (inx) {
+            vload<T, V>(QX + c0, qE);
+            vload<T, V>(QY + c0, qS);
+            vload<T, V>(LQX + c0, lqE);
+            vload<T, V>(LQY + c0, lqS);
+            if (hasS) {
+                vload<T, V>(H + c0 + nx, hs);
+                vload<T, V>(Z + c0 + nx, zs);
+                vload<T, V>(Nn + c0 + nx, ns);
+                le_load<T, V>(LH + c0 + nx, CL + c0 + nx, les);
+            }
+        }
+        // east neighbour of the lane's last cell = first cell of the next lane
+        const T hE = __shfl_down(hc[0], 1, 64);
+        const T zE = __shfl_down(zc[0], 1, 64);
+        const T nE = __shfl_down(nc[0], 1, 64);
+        const T leE = __shfl_down(lec[0], 1, 64);
+        T ltE[V], dqE[V], d1E[V], d2E[V], cnE[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const int x = xl + j;
+            const T h2 = (j + 1 < V) ? hc[j + 1] : hE;
+            const T z2 = (j + 1 < V) ? zc[j + 1] : zE;
+            const T n2 = (j + 1 < V) ? nc[j + 1] : nE;
+            const T le2 = (j + 1 < V) ? lec[j + 1] : leE;
+            if (x + 1 < nx) {
+                const T nf = T(0.5) * (nc[j] + n2);
+                link_in_d(qE[j], hc[j], h2, z2 - zc[j], g * (nf * nf), g * nf, ms, hdry, dqE[j], d1E[j], d2E[j],
+                          cnE[j]);
+                ltE[j] = lqE[j] + kk * (le2 - lec[j]);
+            } else if (C.edge_open[1]) {
+                link_open_d(qE[j], hc[j], g * (nc[j] * nc[j]), T(2) * g * nc[j], C.edge_slope[1], ms, hdry, dqE[j],
+                            d1E[j], cnE[j]);
+                d2E[j] = T(0);
+                ltE[j] = lqE[j] - kk * lec[j];
+            } else {
+                dqE[j] = d1E[j] = d2E[j] = cnE[j] = ltE[j] = T(0);
+            }
+        }
+        // west link of the first cell: the previous lane's last east link
+        const T wH = __shfl_up(ltE[V - 1] * d2E[V - 1], 1, 64);
+        const T wN = __shfl_up(ltE[V - 1] * cnE[V - 1], 1, 64);
+        if (own) {
+            T nh4[V], oqx4[V], oqy4[V], na4[V];
+            vload<T, V>(NA + c0, na4);
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                const int x = xl + j;
+                const T gb = g * (nc[j] * nc[j]), nb = T(2) * g * nc[j];
+                const T le_c = lec[j];
+                T nh = le_c;
+                T nac = T(0);
+                // east (this cell is cell 1)
+                nh += ltE[j] * d1E[j];
+                nac += ltE[j] * cnE[j];
+                // south (this cell is cell 1)
+                T ltS = T(0), dqS = T(0), d1S = T(0), d2S = T(0), cnS = T(0);
+                if (hasS) {
+                    const T nf = T(0.5) * (nc[j] + ns[j]);
+                    link_in_d(qS[j], hc[j], hs[j], zs[j] - zc[j], g * (nf * nf), g * nf, ms, hdry, dqS, d1S, d2S,
+                              cnS);
+                    ltS = lqS[j] + kk * (les[j] - le_c);
+                } else if (C.edge_open[2]) {
+                    link_open_d(qS[j], hc[j], gb, nb, C.edge_slope[2], ms, hdry, dqS, d1S, cnS);
+                    ltS = lqS[j] - kk * le_c;
+                }
+                nh += ltS * d1S;
+                nac += ltS * cnS;
+                // west (this cell is cell 2); the edge strip holds -qo
+                if (x > 0) {
+                    nh += (j > 0) ? ltE[j - 1] * d2E[j - 1] : wH;
+                    nac += (j > 0) ? ltE[j - 1] * cnE[j - 1] : wN;
+                } else {
+                    T oqw = T(0);
+                    if (C.edge_open[3]) {
+                        T dq, d1, cn;
+                        link_open_d(-QWs[r], hc[j], gb, nb, C.edge_slope[3], ms, hdry, dq, d1, cn);
+                        const T lt = LQWs[r] + kk * le_c;
+                        oqw = lt * dq;
+                        nh -= lt * d1;
+                        nac -= lt * cn;
+                    }
+                    LQWo[r] = oqw;
+                }
+                // north (this cell is cell 2)
+                if (r > 0) {
+                    nh += pNh[j];
+                    nac += pNn[j];
+                } else {
+                    T oqn = T(0);
+                    if (C.edge_open[0]) {
+                        T dq, d1, cn;
+                        link_open_d(-QNs[x], hc[j], gb, nb, C.edge_slope[0], ms, hdry, dq, d1, cn);
+                        const T lt = LQNs[x] + kk * le_c;
+                        oqn = lt * dq;
+                        nh -= lt * d1;
+                        nac -= lt * cn;
+                    }
+                    LQNo[x] = oqn;
+                }
+                nh4[j] = nh;
+                oqx4[j] = ltE[j] * dqE[j];
+                oqy4[j] = ltS * dqS;
+                na4[j] += nac;
+                lsum += (double)le_c;
+                pNh[j] = ltS * d2S;
+                pNn[j] = ltS * cnS;
+            }
+            vstore<T, V>(LHo + c0, nh4);
+            vstore<T, V>(LQXo + c0, oqx4);
+            vstore<T, V>(LQYo + c0, oqy4);
+            vstore<T, V>(NA + c0, na4);
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            hc[j] = hs[j];
+            zc[j] = zs[j];
+            nc[j] = ns[j];
+            lec[j] = les[j];
+        }
+        c0 += nx;
+    }
+    // rain-multiplier adjoint: the depth adjoint after the step summed over the
+    // strip's cells, times R dt of the member's step
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+    if (lane == 0) A.mubar_part[(size_t)(sy * C.strips_x + sx) * C.n_members + k] += lsum * A.rdt[k];
+}
+
+template <typename T> void launch_adjoint_march(const AdjvLaunch<T>& A, int total_waves, hipStream_t s) {
+    const int per = kBlock / 64;
+    const dim3 grid((total_waves + per - 1) / per);
+    hipLaunchKernelGGL((k_adjv<T, march_vec<T>()>), grid, dim3(kBlock), 0, s, A);
+}
+
+// One lane per member of the group.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_pre(int G, const MemberStep<T>* ms_prev, const MemberStep<T>* ms_cur,
+                                                 const int32_t* tags, int K, const int32_t* grc, const double* obs,
+                                                 const T* tape_h, size_t slot_stride, size_t plane, int nx,
+                                                 int32_t* lpar, T* lh0, T* lh1) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= G) return;
+    int p = lpar[m];
+    if (ms_prev && ms_prev[m].active) {
+        p ^= 1;
+        lpar[m] = p;
+    }
+    if (K == 0 || !ms_cur[m].active) return;
+    const int s = tags[m];
+    if (s < 0) return;
+    const T* h = tape_h + (size_t)(ms_cur[m].slot + 1) * slot_stride + (size_t)m * plane;
+    T* lh = (p ? lh1 : lh0) + (size_t)m * plane;
+    for (int q = 0; q < K; ++q) {
+        const size_t cell = (size_t)grc[2 * q] * nx + grc[2 * q + 1];
+        lh[cell] += (T)(2.0 * ((double)h[cell] - obs[(size_t)s * K + q]));
+    }
+}
+
+template <typename T>
+void launch_adj_pre(int G, const MemberStep<T>* ms_prev, const MemberStep<T>* ms_cur, const int32_t* tags, int K,
+                    const int32_t* grc, const double* obs, const CatchDev<T>& tape, size_t slot_stride,
+                    int32_t* lpar, T* lh0, T* lh1, hipStream_t s) {
+    const size_t plane = (size_t)tape.ny * tape.nx;
+    hipLaunchKernelGGL((k_adj_pre<T>), dim3((G + 255) / 256), dim3(256), 0, s, G, ms_prev, ms_cur, tags, K, grc, obs,
+                       (const T*)tape.h[0], slot_stride, plane, tape.nx, lpar, lh0, lh1);
+}
+
+// nbar[c] += sum over the group's members of their Manning-field adjoint
+template <typename T>
+__global__ __launch_bounds__(256) void k_nacc_reduce(int G, size_t ncell, const T* nacc, double* nbar) {
+    const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    double acc = 0.0;
+    for (int m = 0; m < G; ++m) acc += (double)nacc[(size_t)m * ncell + c];
+    nbar[c] += acc;
+}
+
+template <typename T> void launch_nacc_reduce(int G, size_t ncell, const T* nacc, double* nbar, hipStream_t s) {
+    hipLaunchKernelGGL((k_nacc_reduce<T>), dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s, G, ncell, nacc,
+                       nbar);
+}
+
 // Gauge misfit seeds the adjoint: d/dh of (h - d)^2 at every gauge of every
 // member whose step just completed a sample.  One lane per member.
 template <typename T, int MI>
@@ -399,6 +691,16 @@ void launch_sum_parts(int n_blocks, int n_members, const double* parts, double* 
     hipLaunchKernelGGL(k_sum_parts, dim3(n_members), dim3(256), 0, s, n_blocks, n_members, parts, out);
 }
 
+template void launch_adjoint_march<float>(const AdjvLaunch<float>&, int, hipStream_t);
+template void launch_adjoint_march<double>(const AdjvLaunch<double>&, int, hipStream_t);
+template void launch_adj_pre<float>(int, const MemberStep<float>*, const MemberStep<float>*, const int32_t*, int,
+                                    const int32_t*, const double*, const CatchDev<float>&, size_t, int32_t*, float*,
+                                    float*, hipStream_t);
+template void launch_adj_pre<double>(int, const MemberStep<double>*, const MemberStep<double>*, const int32_t*, int,
+                                     const int32_t*, const double*, const CatchDev<double>&, size_t, int32_t*,
+                                     double*, double*, hipStream_t);
+template void launch_nacc_reduce<float>(int, size_t, const float*, double*, hipStream_t);
+template void launch_nacc_reduce<double>(int, size_t, const double*, double*, hipStream_t);
 template void launch_adjoint_step<float>(int, const AdjLaunch<float>&, hipStream_t);
 template void launch_adjoint_step<double>(int, const AdjLaunch<double>&, hipStream_t);
 template void launch_inject<float>(int, const CatchDev<float>&, const int32_t*, int, const int32_t*, const double*,

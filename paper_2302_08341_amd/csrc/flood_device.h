@@ -69,4 +69,43 @@ __device__ __forceinline__ size_t state_index(const CatchDev<T>& C, int member, 
     return ((size_t)(member / MI) * C.ny + r) * ((size_t)C.nx * MI) + (size_t)c * MI + member % MI;
 }
 
+// V adjacent cells moved with one V-wide access (p must be V-element aligned)
+template <typename T, int V> struct VecOf;
+template <> struct VecOf<float, 4> { typedef float __attribute__((ext_vector_type(4))) type; };
+template <> struct VecOf<float, 2> { typedef float __attribute__((ext_vector_type(2))) type; };
+template <> struct VecOf<double, 2> { typedef double __attribute__((ext_vector_type(2))) type; };
+
+template <typename T, int V>
+__device__ __forceinline__ void vload(const T* p, T (&d)[V]) {
+    typedef typename VecOf<T, V>::type vt;
+    const vt v = *reinterpret_cast<const vt*>(p);
+#pragma unroll
+    for (int j = 0; j < V; ++j) d[j] = v[j];
+}
+template <typename T, int V>
+__device__ __forceinline__ void vstore(T* p, const T (&d)[V]) {
+    typedef typename VecOf<T, V>::type vt;
+    vt v;
+#pragma unroll
+    for (int j = 0; j < V; ++j) v[j] = d[j];
+    *reinterpret_cast<vt*>(p) = v;
+}
+// streaming variants: the state is touched once per step, so these accesses are
+// marked non-temporal and leave cache capacity to the shared bed and roughness
+template <typename T, int V>
+__device__ __forceinline__ void vload_nt(const T* p, T (&d)[V]) {
+    typedef typename VecOf<T, V>::type vt;
+    const vt v = __builtin_nontemporal_load(reinterpret_cast<const vt*>(p));
+#pragma unroll
+    for (int j = 0; j < V; ++j) d[j] = v[j];
+}
+template <typename T, int V>
+__device__ __forceinline__ void vstore_nt(T* p, const T (&d)[V]) {
+    typedef typename VecOf<T, V>::type vt;
+    vt v;
+#pragma unroll
+    for (int j = 0; j < V; ++j) v[j] = d[j];
+    __builtin_nontemporal_store(v, reinterpret_cast<vt*>(p));
+}
+
 }  // namespace flood

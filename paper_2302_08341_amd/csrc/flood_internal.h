@@ -39,6 +39,7 @@ template <typename T> struct MemberStep {
     double dxdt;  // dx dt (outflow volume per unit discharge)
     int32_t active;
     int32_t parity;  // state copy holding the state before this step
+    int32_t slot;    // adjoint record: the member's step index within the tape segment
 };
 
 template <typename T> struct CatchDev {
@@ -79,6 +80,11 @@ template <typename T> struct StepLaunch {
     typename HBits<T>::type* hbins;  // [kBins][n_total]
     double* vclamp;           // [n_total]
     uint8_t* clamp_out;       // recompute only: 1 where the new depth was clamped at zero
+    // tape recomputation by the row-march kernel: c[0]'s copy-0 arrays are tape
+    // slot 0; a member reads slot ms.slot and writes slot ms.slot + 1, and its
+    // clamp flags go to clamp_out + ms.slot * clamp_stride
+    size_t slot_stride;
+    size_t clamp_stride;
 };
 
 struct PlanCatch {
@@ -113,6 +119,7 @@ template <typename T> struct PlanLaunch {
     int32_t* tag_log;         // sample index completed by the step, or -1
     int32_t* any_log;         // set to 1 when any member steps
     int32_t tag_value;
+    int32_t* seg_cnt;         // optional, by m - m_begin: steps taken since the last checkpoint
 };
 
 // ---------------------------------------------------------------------------
@@ -162,6 +169,37 @@ template <typename T> struct AdjLaunch {
     double* mubar_part;       // [blocks][group members] rain-multiplier adjoint partials (accumulated)
 };
 template <typename T> void launch_adjoint_step(int mi, const AdjLaunch<T>& A, hipStream_t s);
+
+// Reverse step in row-march form (members in planes, nx a multiple of the
+// vector width).  The tape holds per-member slots: a member active in this
+// launch reads its state before the step from slot ms.slot; members that did
+// not step are skipped and keep their adjoint in place.
+template <typename T> struct AdjvLaunch {
+    CatchDev<T> c;            // group view: copy-0 arrays are tape slot 0; strip / wave geometry
+    size_t slot_stride;       // elements between tape slots
+    const uint8_t* clamp;     // [slot][member][cell] clamp flags of the recomputed steps
+    size_t clamp_stride;
+    T* lh[2];                 // two copies of the adjoint state, [member][...]
+    T* lqx[2];
+    T* lqy[2];
+    T* lqw[2];
+    T* lqn[2];
+    const int32_t* lpar;      // [group members] copy holding the adjoint after the step
+    const MemberStep<T>* ms;  // [group members] record of this launch
+    const double* rdt;        // [group members]
+    T* nacc;                  // [group members][cell] Manning-field adjoint per member (accumulated)
+    double* mubar_part;       // [strips][group members] rain-multiplier adjoint partials (accumulated)
+};
+template <typename T> void launch_adjoint_march(const AdjvLaunch<T>& A, int total_waves, hipStream_t s);
+// before each reverse launch: flip the adjoint copy of members that stepped in
+// the previously reversed launch, then seed the gauge misfit of this launch
+template <typename T>
+void launch_adj_pre(int G, const MemberStep<T>* ms_prev, const MemberStep<T>* ms_cur, const int32_t* tags, int K,
+                    const int32_t* grc, const double* obs, const CatchDev<T>& tape, size_t slot_stride,
+                    int32_t* lpar, T* lh0, T* lh1, hipStream_t s);
+template <typename T>
+void launch_nacc_reduce(int G, size_t ncell, const T* nacc, double* nbar, hipStream_t s);
+template <typename T> void launch_marchv_rec(const StepLaunch<T>& L, int total_waves, hipStream_t s);
 template <typename T>
 void launch_inject(int mi, const CatchDev<T>& after, const int32_t* tags, int K, const int32_t* grc,
                    const double* obs, T* lh, hipStream_t s);

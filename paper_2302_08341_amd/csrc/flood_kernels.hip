@@ -30,6 +30,7 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     ms.dxdt = 0.0;
     ms.active = 0;
     ms.parity = P.par[m];
+    ms.slot = -1;
     const double t = P.t[m];
     const double t_end = *P.t_end;
     const int lm = m - P.m_begin;
@@ -52,6 +53,11 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
         P.fault[m] = 1;
         atomicOr(P.status, 1);
         P.ms[m] = ms;
+        if (P.ms_log) {
+            P.ms_log[lm] = ms;
+            P.rdt_log[lm] = 0.0;
+            P.tag_log[lm] = -1;
+        }
         return;
     }
     double dt;
@@ -83,6 +89,7 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     ms.rinc = (T)(P.mu[m] * R * dt);
     ms.dxdt = C.dx * dt;
     ms.active = 1;
+    if (P.seg_cnt) ms.slot = P.seg_cnt[lm]++;
     P.ms[m] = ms;
     if (P.ms_log) {
         P.ms_log[lm] = ms;
@@ -749,45 +756,7 @@ __global__ __launch_bounds__(kBlock) void k_march(const StepLaunch<T> L) {
 // 1..62), which keeps every access V-aligned.  Same link functions and
 // operands as k_step: identical bits.
 // ---------------------------------------------------------------------------
-template <typename T, int V> struct VecOf;
-template <> struct VecOf<float, 4> { typedef float __attribute__((ext_vector_type(4))) type; };
-template <> struct VecOf<float, 2> { typedef float __attribute__((ext_vector_type(2))) type; };
-template <> struct VecOf<double, 2> { typedef double __attribute__((ext_vector_type(2))) type; };
-
-template <typename T, int V>
-__device__ __forceinline__ void vload(const T* p, T (&d)[V]) {
-    typedef typename VecOf<T, V>::type vt;
-    const vt v = *reinterpret_cast<const vt*>(p);
-#pragma unroll
-    for (int j = 0; j < V; ++j) d[j] = v[j];
-}
-template <typename T, int V>
-__device__ __forceinline__ void vstore(T* p, const T (&d)[V]) {
-    typedef typename VecOf<T, V>::type vt;
-    vt v;
-#pragma unroll
-    for (int j = 0; j < V; ++j) v[j] = d[j];
-    *reinterpret_cast<vt*>(p) = v;
-}
-// streaming variants: the state is touched once per step, so these accesses are
-// marked non-temporal and leave cache capacity to the shared bed and roughness
-template <typename T, int V>
-__device__ __forceinline__ void vload_nt(const T* p, T (&d)[V]) {
-    typedef typename VecOf<T, V>::type vt;
-    const vt v = __builtin_nontemporal_load(reinterpret_cast<const vt*>(p));
-#pragma unroll
-    for (int j = 0; j < V; ++j) d[j] = v[j];
-}
-template <typename T, int V>
-__device__ __forceinline__ void vstore_nt(T* p, const T (&d)[V]) {
-    typedef typename VecOf<T, V>::type vt;
-    vt v;
-#pragma unroll
-    for (int j = 0; j < V; ++j) v[j] = d[j];
-    __builtin_nontemporal_store(v, reinterpret_cast<vt*>(p));
-}
-
-template <typename T, int V, int NT>
+template <typename T, int V, int NT, int REC>
 __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
     using HB = typename HBits<T>::type;
     const int lane = threadIdx.x & 63;
@@ -819,14 +788,45 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
     const bool own = lane >= 1 && lane <= 62 && inx;
     const int r0 = sy * C.march_rows;
     const int r1 = min(r0 + C.march_rows, ny);
-    const int sp = ms.parity, dp = sp ^ 1;
     const size_t plane = (size_t)ny * nx;
-    const T* __restrict__ H = C.h[sp] + (size_t)k * plane;
-    const T* __restrict__ QX = C.qx[sp] + (size_t)k * plane;
-    const T* __restrict__ QY = C.qy[sp] + (size_t)k * plane;
-    T* __restrict__ Ho = C.h[dp] + (size_t)k * plane;
-    T* __restrict__ QXo = C.qx[dp] + (size_t)k * plane;
-    T* __restrict__ QYo = C.qy[dp] + (size_t)k * plane;
+    // source and destination of this member's state: the two copies, or (tape
+    // recomputation) the member's tape slot and the next one
+    const T* __restrict__ H;
+    const T* __restrict__ QX;
+    const T* __restrict__ QY;
+    T* __restrict__ Ho;
+    T* __restrict__ QXo;
+    T* __restrict__ QYo;
+    const T* QWs;
+    const T* QNs;
+    T* QWo;
+    T* QNo;
+    if constexpr (REC) {
+        const size_t so = (size_t)ms.slot * L.slot_stride;
+        const size_t sd = so + L.slot_stride;
+        H = C.h[0] + so + (size_t)k * plane;
+        QX = C.qx[0] + so + (size_t)k * plane;
+        QY = C.qy[0] + so + (size_t)k * plane;
+        Ho = C.h[0] + sd + (size_t)k * plane;
+        QXo = C.qx[0] + sd + (size_t)k * plane;
+        QYo = C.qy[0] + sd + (size_t)k * plane;
+        QWs = C.qw[0] + so + (size_t)k * ny;
+        QWo = C.qw[0] + sd + (size_t)k * ny;
+        QNs = C.qn[0] + so + (size_t)k * nx;
+        QNo = C.qn[0] + sd + (size_t)k * nx;
+    } else {
+        const int sp = ms.parity, dp = sp ^ 1;
+        H = C.h[sp] + (size_t)k * plane;
+        QX = C.qx[sp] + (size_t)k * plane;
+        QY = C.qy[sp] + (size_t)k * plane;
+        Ho = C.h[dp] + (size_t)k * plane;
+        QXo = C.qx[dp] + (size_t)k * plane;
+        QYo = C.qy[dp] + (size_t)k * plane;
+        QWs = C.qw[sp] + (size_t)k * ny;
+        QWo = C.qw[dp] + (size_t)k * ny;
+        QNs = C.qn[sp] + (size_t)k * nx;
+        QNo = C.qn[dp] + (size_t)k * nx;
+    }
     const T* __restrict__ Z = C.z;
     const T* __restrict__ Nn = C.n;
     const T g = C.g, hdry = C.hdry;
@@ -854,8 +854,7 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
         } else if (C.edge_open[0]) {
 #pragma unroll
             for (int j = 0; j < V; ++j)
-                fN[j] = -link_open(-C.qn[sp][(size_t)k * nx + xl + j], hc[j], g * (nc[j] * nc[j]), C.edge_slope[0],
-                                   ms, hdry);
+                fN[j] = -link_open(-QNs[xl + j], hc[j], g * (nc[j] * nc[j]), C.edge_slope[0], ms, hdry);
         }
     }
     HB vmax = 0;
@@ -900,6 +899,7 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
         const T fW0 = __shfl_up(fE[V - 1], 1, 64);
         if (own) {
             T hn4[V], fS4[V];
+            uint8_t cf[V];
 #pragma unroll
             for (int j = 0; j < V; ++j) {
                 const int x = xl + j;
@@ -910,8 +910,7 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
                 else if (x > 0)
                     fW = fW0;
                 else
-                    fW = C.edge_open[3] ? -link_open(-C.qw[sp][(size_t)k * ny + r], hc[0], gb, C.edge_slope[3], ms, hdry)
-                                        : T(0);
+                    fW = C.edge_open[3] ? -link_open(-QWs[r], hc[0], gb, C.edge_slope[3], ms, hdry) : T(0);
                 T fS;
                 if (hasS) {
                     const T nf = T(0.5) * (nc[j] + ns[j]);
@@ -921,16 +920,17 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
                 }
                 const T dv = ((fW - fE[j]) + fN[j]) - fS;
                 T hn = (hc[j] + ms.dtdx * dv) + ms.rinc;
+                cf[j] = hn < T(0);
                 if (hn < T(0)) {
-                    atomicAdd(&L.vclamp[C.member_off + k], -(double)hn * (C.dx * C.dx));
+                    if constexpr (!REC) atomicAdd(&L.vclamp[C.member_off + k], -(double)hn * (C.dx * C.dx));
                     hn = T(0);
                 }
                 if (hn == T(0)) hn = T(0);
                 hn4[j] = hn;
                 fS4[j] = fS;
-                if (x == 0) C.qw[dp][(size_t)k * ny + r] = fW;
-                if (r == 0) C.qn[dp][(size_t)k * nx + x] = fN[j];
-                if (x == 0 || x + 1 == nx || r == 0 || !hasS) {
+                if (x == 0) QWo[r] = fW;
+                if (r == 0) QNo[x] = fN[j];
+                if (!REC && (x == 0 || x + 1 == nx || r == 0 || !hasS)) {
                     double* acc = C.out_acc + (size_t)k * nb;
                     if (r == 0 && C.edge_open[0]) acc[x] += -(double)fN[j] * ms.dxdt;
                     if (!hasS && C.edge_open[2]) acc[nx + x] += (double)fS * ms.dxdt;
@@ -950,6 +950,15 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
                 vstore<T, V>(QXo + c0, fE);
                 vstore<T, V>(QYo + c0, fS4);
             }
+            if constexpr (REC) {
+                uint8_t* cl = L.clamp_out + (size_t)ms.slot * L.clamp_stride + (size_t)k * plane + c0;
+                if constexpr (V == 4) {
+                    *reinterpret_cast<uint32_t*>(cl) = (uint32_t)cf[0] | ((uint32_t)cf[1] << 8) |
+                                                       ((uint32_t)cf[2] << 16) | ((uint32_t)cf[3] << 24);
+                } else {
+                    *reinterpret_cast<uint16_t*>(cl) = (uint16_t)(cf[0] | (cf[1] << 8));
+                }
+            }
         }
 #pragma unroll
         for (int j = 0; j < V; ++j) {
@@ -959,14 +968,16 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
         }
         c0 += nx;
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        const HB o = __shfl_xor(vmax, off, 64);
-        vmax = o > vmax ? o : vmax;
-    }
-    if (lane == 0 && vmax != 0) {
-        HB* a = L.hbins + (size_t)(blockIdx.x & (kBins - 1)) * L.n_total + C.member_off + k;
-        const HB cur = __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (vmax > cur) atomicMax(a, vmax);
+    if constexpr (!REC) {
+        for (int off = 32; off > 0; off >>= 1) {
+            const HB o = __shfl_xor(vmax, off, 64);
+            vmax = o > vmax ? o : vmax;
+        }
+        if (lane == 0 && vmax != 0) {
+            HB* a = L.hbins + (size_t)(blockIdx.x & (kBins - 1)) * L.n_total + C.member_off + k;
+            const HB cur = __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (vmax > cur) atomicMax(a, vmax);
+        }
     }
 }
 
@@ -975,13 +986,26 @@ template <typename T> void launch_marchv(const StepLaunch<T>& L, int nt, int tot
     const dim3 grid((total_waves + per - 1) / per);
     constexpr int V = march_vec<T>();
     if (nt)
-        hipLaunchKernelGGL((k_marchv<T, V, 1>), grid, dim3(kBlock), 0, s, L);
+        hipLaunchKernelGGL((k_marchv<T, V, 1, 0>), grid, dim3(kBlock), 0, s, L);
     else
-        hipLaunchKernelGGL((k_marchv<T, V, 0>), grid, dim3(kBlock), 0, s, L);
+        hipLaunchKernelGGL((k_marchv<T, V, 0, 0>), grid, dim3(kBlock), 0, s, L);
+}
+
+// Tape recomputation of the adjoint: the same step, reading and writing tape
+// slots, recording clamp flags, leaving the ledger, the outflow accumulators and
+// the depth maximum alone; members that did not step in the recorded launch are
+// skipped (their slots are not advanced).
+template <typename T> void launch_marchv_rec(const StepLaunch<T>& L, int total_waves, hipStream_t s) {
+    const int per = kBlock / 64;
+    const dim3 grid((total_waves + per - 1) / per);
+    constexpr int V = march_vec<T>();
+    hipLaunchKernelGGL((k_marchv<T, V, 0, 1>), grid, dim3(kBlock), 0, s, L);
 }
 
 template void launch_marchv<float>(const StepLaunch<float>&, int, int, hipStream_t);
 template void launch_marchv<double>(const StepLaunch<double>&, int, int, hipStream_t);
+template void launch_marchv_rec<float>(const StepLaunch<float>&, int, hipStream_t);
+template void launch_marchv_rec<double>(const StepLaunch<double>&, int, hipStream_t);
 
 template <typename T> void launch_march(const StepLaunch<T>& L, int seg, int total_waves, hipStream_t s) {
     const int per = kBlock / 64;

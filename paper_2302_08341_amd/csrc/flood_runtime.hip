@@ -1070,6 +1070,7 @@ template <typename T> struct Impl : ImplBase {
 // partial sums then group cells the same way on every handle of a given
 // interleave, so its gradients do not depend on what the tuner picked.
 constexpr int kAdjTileRows = 4;
+constexpr int kAdjMarchRows = 8;
 
 template <typename T>
 static CatchDev<T> group_view(const CatchDev<T>& C, int mi, int g0, int G, T* const h[2], T* const qx[2],
@@ -1082,6 +1083,14 @@ static CatchDev<T> group_view(const CatchDev<T>& C, int mi, int g0, int G, T* co
     const int ty = (kBlock / mi) >> l;
     v.tiles_x = (C.nx + (1 << l) - 1) >> l;
     v.tiles_y = (C.ny + ty - 1) / ty;
+    // row-march geometry (members in planes), likewise fixed
+    const int strip_w = 62 * march_vec<T>();
+    v.march_rows = std::min(kAdjMarchRows, C.ny);
+    v.strips_x = (C.nx + strip_w - 1) / strip_w;
+    v.strips_y = (C.ny + v.march_rows - 1) / v.march_rows;
+    v.wave_begin = 0;
+    v.n_waves = v.strips_x * v.strips_y * G;
+    v.march_order = 1;
     v.member_off = C.member_off + g0;
     v.n_members = G;
     v.n_chunks = (G + mi - 1) / mi;
@@ -1159,6 +1168,10 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
         }
     } guard{tmp, st};
 
+    // members in planes with a vectorisable row length: the adjoint runs in
+    // row-march form (forward, tape recomputation and reverse step), otherwise
+    // in the tiled form that also serves interleaved members
+    const bool march_adj = mi == 1 && variant == 3;
     const int Gi = (int)G;
     const int chunksG = (Gi + mi - 1) / mi;
     const size_t elemsG = (size_t)chunksG * ncell * mi;
@@ -1194,8 +1207,18 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
         T* none[2] = {nullptr, nullptr};
         const CatchDev<T> tv = group_view(C.dev, mi, 0, std::min(Gi, N), none, none, none, none, none);
         nblk = tv.tiles_x * tv.tiles_y;
+        if (march_adj) nblk = tv.strips_x * tv.strips_y;
     }
     CHK(talloc((size_t)nblk * Gi * sizeof(double), (void**)&d_mubar));
+    // row-march form: per-member adjoint copy index and Manning-field accumulators
+    int32_t* d_lpar = nullptr;
+    int32_t* d_segcnt = nullptr;
+    T* d_nacc = nullptr;
+    if (march_adj) {
+        CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_lpar));
+        CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_segcnt));
+        CHK(talloc(elemsG * sizeof(T), (void**)&d_nacc));
+    }
     size_t log_cap = 4096;
     auto grow_log = [&](size_t need) -> flood_status {
         if (need <= log_cap && ms_log) return FLOOD_OK;
@@ -1269,6 +1292,138 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
         PlanLaunch<T> PLg = PL;
         PLg.m_begin = off + g0;
         PLg.m_end = off + g0 + Gg;
+        if (march_adj) {
+            // ---------------- row-march form ----------------
+            // Forward: the step kernel of flood_step on the group, with the planner
+            // recording every launch and numbering each member's steps within the
+            // current tape segment (ckpt_every launches, checkpoint at its start).
+            const int tw = V.n_waves;
+            StepLaunch<T> SLm = SL;
+            SLm.n_catch = 1;
+            SLm.c[0] = V;
+            SLm.total_blocks = 0;
+            SLm.recompute = 0;
+            PLg.seg_cnt = d_segcnt;
+            std::vector<T*> ckpts;
+            int64_t L = 0;
+            CHK(grow_log(4096));
+            HIPCHK(hipMemsetAsync(any_log, 0, log_cap * sizeof(int32_t), st));
+            for (int smp = 0; smp < S; ++smp) {
+                *h_tend = t0 + (double)(smp + 1) * sample_dt;
+                HIPCHK(hipMemcpyAsync(d_tend, h_tend, sizeof(double), hipMemcpyHostToDevice, st));
+                HIPCHK(hipStreamSynchronize(st));
+                for (;;) {
+                    const int B = 8;
+                    CHK(grow_log((size_t)L + B + 1));
+                    for (int i = 0; i < B; ++i) {
+                        if (L % ckpt_every == 0) {
+                            T* ck;
+                            CHK(talloc(slot_elems * sizeof(T), (void**)&ck));
+                            ckpts.push_back(ck);
+                            T* ch[2] = {ck, ck};
+                            T* cx[2] = {ck + elemsG, ck + elemsG};
+                            T* cyy[2] = {ck + 2 * elemsG, ck + 2 * elemsG};
+                            T* cw[2] = {ck + 3 * elemsG, ck + 3 * elemsG};
+                            T* cn[2] = {ck + 3 * elemsG + wG, ck + 3 * elemsG + wG};
+                            CatchDev<T> D = group_view(C.dev, mi, g0, Gg, ch, cx, cyy, cw, cn);
+                            launch_snapshot<T>(mi, V, par, D, st);
+                            HIPCHK(hipMemsetAsync(d_segcnt, 0, (size_t)Gi * sizeof(int32_t), st));
+                        }
+                        PLg.ms_log = ms_log + (size_t)L * Gi;
+                        PLg.rdt_log = rdt_log + (size_t)L * Gi;
+                        PLg.tag_log = tag_log + (size_t)L * Gi;
+                        PLg.any_log = any_log + L;
+                        PLg.tag_value = smp;
+                        launch_plan<T>(PLg, st);
+                        launch_marchv<T>(SLm, march_nt, tw, st);
+                        ++L;
+                    }
+                    launch_count_active(Gg, t + off + g0, fault + off + g0, d_tend, status, d_count, st);
+                    HIPCHK(hipGetLastError());
+                    HIPCHK(hipMemcpyAsync(h_count, d_count, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+                    HIPCHK(hipStreamSynchronize(st));
+                    if (h_count[1]) {
+                        err = "a member produced a non-finite depth during the adjoint forward";
+                        return FLOOD_ENUMERIC;
+                    }
+                    if (h_count[0] == 0) break;
+                    if (L > max_launch) {
+                        err = "adjoint forward exceeded the launch limit";
+                        return FLOOD_ESTATE;
+                    }
+                }
+                launch_misfit<T>(mi, V, par, K, d_grc2, d_obs2 + (size_t)smp * K, d_loss, st);
+            }
+            std::vector<int32_t> any_h(L);
+            HIPCHK(hipMemcpyAsync(any_h.data(), any_log, L * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+
+            // Reverse, segment by segment from the last: recompute the segment's
+            // launches into per-member tape slots, then apply the reverse steps in
+            // reverse launch order.  A member that did not step in a launch keeps
+            // its slot, its adjoint copy and its accumulators untouched.
+            HIPCHK(hipMemsetAsync(lam, 0, 2 * slot_elems * sizeof(T), st));
+            HIPCHK(hipMemsetAsync(d_mubar, 0, (size_t)nblk * Gi * sizeof(double), st));
+            HIPCHK(hipMemsetAsync(d_lpar, 0, (size_t)Gi * sizeof(int32_t), st));
+            HIPCHK(hipMemsetAsync(d_nacc, 0, elemsG * sizeof(T), st));
+            const CatchDev<T> TV = slot_view(tape, 0);
+            T* lb[2] = {lam, lam + slot_elems};
+            int64_t l_prev = -1;
+            for (int ck = (int)ckpts.size() - 1; ck >= 0; --ck) {
+                const int64_t L0 = (int64_t)ck * ckpt_every;
+                const int64_t L1 = std::min<int64_t>(L0 + ckpt_every, L);
+                std::vector<int64_t> useful;
+                for (int64_t l = L0; l < L1; ++l)
+                    if (any_h[l]) useful.push_back(l);
+                if (useful.empty()) continue;
+                HIPCHK(hipMemcpyAsync(tape, ckpts[ck], slot_elems * sizeof(T), hipMemcpyDeviceToDevice, st));
+                for (int64_t l : useful) {
+                    StepLaunch<T> R = SLm;
+                    R.c[0] = TV;
+                    R.ms = ms_log + (size_t)l * Gi - (off + g0);
+                    R.clamp_out = clamp;
+                    R.slot_stride = slot_elems;
+                    R.clamp_stride = elemsG;
+                    launch_marchv_rec<T>(R, tw, st);
+                }
+                for (int j = (int)useful.size() - 1; j >= 0; --j) {
+                    const int64_t l = useful[j];
+                    launch_adj_pre<T>(Gg, l_prev >= 0 ? ms_log + (size_t)l_prev * Gi : nullptr, ms_log + (size_t)l * Gi,
+                                      tag_log + (size_t)l * Gi, K, d_grc2, d_obs2, TV, slot_elems, d_lpar, lb[0], lb[1],
+                                      st);
+                    AdjvLaunch<T> A{};
+                    A.c = TV;
+                    A.slot_stride = slot_elems;
+                    A.clamp = clamp;
+                    A.clamp_stride = elemsG;
+                    for (int w = 0; w < 2; ++w) {
+                        A.lh[w] = lb[w];
+                        A.lqx[w] = lb[w] + elemsG;
+                        A.lqy[w] = lb[w] + 2 * elemsG;
+                        A.lqw[w] = lb[w] + 3 * elemsG;
+                        A.lqn[w] = lb[w] + 3 * elemsG + wG;
+                    }
+                    A.lpar = d_lpar;
+                    A.ms = ms_log + (size_t)l * Gi;
+                    A.rdt = rdt_log + (size_t)l * Gi;
+                    A.nacc = d_nacc;
+                    A.mubar_part = d_mubar;
+                    launch_adjoint_march<T>(A, tw, st);
+                    l_prev = l;
+                }
+                HIPCHK(hipGetLastError());
+            }
+            launch_nacc_reduce<T>(Gg, ncell, d_nacc, d_nbar, st);
+            launch_sum_parts(V.strips_x * V.strips_y, Gg, d_mubar, d_gm + g0, st);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipStreamSynchronize(st));
+            for (T* p : ckpts) {
+                auto it = std::find(tmp.begin(), tmp.end(), (void*)p);
+                if (it != tmp.end()) tmp.erase(it);
+                (void)hipFree(p);
+            }
+            continue;
+        }
 
         // ---------------- forward with record and checkpoints ----------------
         std::vector<T*> ckpts;

@@ -1,6 +1,10 @@
 """GPU discrete adjoint (flood_adjoint) against the FP64 oracle's adjoint and
 central finite differences.
 
+Both forms of the adjoint are exercised: the tiled form (step_kernel 1, also
+used for interleaved members) and the row-march form (step_kernel 3: per-member
+tape slots, per-member adjoint copies).
+
 Bars: FP64 handle vs oracle adjoint 1e-8 relative; FP32 handle vs oracle
 adjoint 1e-3 relative (rain-multiplier gradient per member, Manning-field
 gradient in the 2-norm); central differences of the FP64 GPU loss (1e-3
@@ -68,11 +72,16 @@ EDGES = (1, 1, 1, 1)
 SLOPES = (1e-3, 2e-3, 3e-3, 1.5e-3)
 
 
-def test_adjoint_fp64_matches_oracle(fl, orc):
+SK = pytest.mark.parametrize("sk", [1, 3])
+
+
+@SK
+def test_adjoint_fp64_matches_oracle(fl, orc, sk):
     z, n, h0, s, mu, g = _smooth()
     rain = [2e-4, 1e-4]
     obs = np.random.default_rng(0).uniform(0.3, 0.5, size=(4, len(g)))
-    e = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, real_bytes=8, cfl_alpha=0.5, dt_cap=5.0)
+    e = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, real_bytes=8, cfl_alpha=0.5, dt_cap=5.0,
+             step_kernel=sk)
     L, gn, gm = e.adjoint(0, 40.0, 10.0, g, obs, ckpt_every=7)
     Lo, gno, gmo = _oracle_adjoint(orc, z, n, rain, 20.0, EDGES, SLOPES, s, mu, h0, None, 40.0, 10.0, g, obs, 7,
                                    alpha=0.5, dt_cap=5.0)
@@ -82,7 +91,8 @@ def test_adjoint_fp64_matches_oracle(fl, orc):
     assert e.ledger()["t"][0] == 40.0
 
 
-def test_adjoint_fp32_matches_oracle_on_wet_urban_state(fl, orc):
+@SK
+def test_adjoint_fp32_matches_oracle_on_wet_urban_state(fl, orc, sk):
     N = 3
     c = W.urban_catchment("adj", 64, 56, N, W.seed_for(3, 1), n_gauges=6)
     rain = W.chicago_hyetograph()
@@ -94,7 +104,7 @@ def test_adjoint_fp32_matches_oracle_on_wet_urban_state(fl, orc):
         states.append(tuple(a.astype(np.float32).astype(np.float64) for a in (mem.h, mem.qx, mem.qy)) + (1200.0,))
     obs = np.random.default_rng(2).uniform(0.0, 0.05, size=(30, 6))
     e = _ens(fl, c.dem, c.manning, None, c.n_scale, c.rain_mult, rain, 300.0, c.edge_kind, c.edge_slope,
-             real_bytes=4)
+             real_bytes=4, step_kernel=sk)
     for i in range(N):
         e.set_state(i, *states[i])
     L, gn, gm = e.adjoint(0, 1500.0, 10.0, c.gauges, obs, ckpt_every=50)
@@ -105,20 +115,21 @@ def test_adjoint_fp32_matches_oracle_on_wet_urban_state(fl, orc):
     assert np.linalg.norm(gn - gno) <= 1e-3 * np.linalg.norm(gno)
 
 
-def _adj_fixed(fl, z, n, h0, s, mu, g, obs, rain, rb):
-    e = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, real_bytes=rb, dt_fixed=0.25)
+def _adj_fixed(fl, z, n, h0, s, mu, g, obs, rain, rb, sk=1):
+    e = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, real_bytes=rb, dt_fixed=0.25, step_kernel=sk)
     return e.adjoint(0, 40.0, 10.0, g, obs, ckpt_every=25)
 
 
+@SK
 @pytest.mark.parametrize("rb,tol", [(8, 1e-4), (4, 1e-3)])
-def test_adjoint_central_differences(fl, rb, tol):
+def test_adjoint_central_differences(fl, rb, tol, sk):
     # fixed step, so perturbed runs keep the step sequence; central differences of the
     # FP64 GPU forward loss with a 1e-3 relative perturbation (truncation error of the
     # central difference is O(eps^2) relative to the curvature, a few 1e-5 here)
     z, n, h0, s, mu, g = _smooth()
     rain = [1e-3, 5e-4]
     obs = np.random.default_rng(0).uniform(0.3, 0.5, size=(4, len(g)))
-    L, gn, gm = _adj_fixed(fl, z, n, h0, s, mu, g, obs, rain, rb)
+    L, gn, gm = _adj_fixed(fl, z, n, h0, s, mu, g, obs, rain, rb, sk)
     eps = 1e-3
     for i in range(len(s)):
         mp, mm = mu.copy(), mu.copy()
@@ -140,17 +151,20 @@ def test_adjoint_central_differences(fl, rb, tol):
     assert float(np.sum(gn * dn_eff)) == pytest.approx(fd, rel=tol)
 
 
-def test_adjoint_checkpoint_interval_and_groups_are_consistent(fl, monkeypatch):
+@SK
+def test_adjoint_checkpoint_interval_and_groups_are_consistent(fl, monkeypatch, sk):
+    # adaptive steps: members take different numbers of steps in each tape segment
     z, n, h0, s, mu, g = _smooth(n_members=4)
     rain = [2e-4, 1e-4]
     obs = np.random.default_rng(0).uniform(0.3, 0.5, size=(4, len(g)))
-    ref = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, real_bytes=4).adjoint(0, 40.0, 10.0, g, obs, 1000)
-    other = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, real_bytes=4).adjoint(0, 40.0, 10.0, g, obs, 3)
+    kw = dict(real_bytes=4, step_kernel=sk)
+    ref = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, **kw).adjoint(0, 40.0, 10.0, g, obs, 1000)
+    other = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, **kw).adjoint(0, 40.0, 10.0, g, obs, 3)
     assert other[0] == ref[0]
     np.testing.assert_array_equal(other[2], ref[2])
     np.testing.assert_array_equal(other[1], ref[1])
     monkeypatch.setenv("FLOOD_ADJ_GROUP", "1")
-    grp = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, real_bytes=4, member_interleave=1).adjoint(
+    grp = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, member_interleave=1, **kw).adjoint(
         0, 40.0, 10.0, g, obs, 5)
     assert grp[0] == pytest.approx(ref[0], rel=1e-12)
     np.testing.assert_array_equal(grp[2], ref[2])
@@ -168,6 +182,20 @@ def test_adjoint_interleave_variants_agree(fl):
         # per-workgroup partial sums group cells differently for each interleave
         np.testing.assert_allclose(r[2], res[0][2], rtol=1e-6)
         assert np.linalg.norm(r[1] - res[0][1]) <= 1e-6 * np.linalg.norm(res[0][1])
+
+
+@pytest.mark.parametrize("rb,tol", [(8, 1e-12), (4, 1e-5)])
+def test_adjoint_forms_agree(fl, rb, tol):
+    # tiled and row-march forms: the same recorded forward, the same derivative
+    # per link; only summation order differs
+    z, n, h0, s, mu, g = _smooth(n_members=4)
+    rain = [2e-4, 1e-4]
+    obs = np.random.default_rng(0).uniform(0.3, 0.5, size=(4, len(g)))
+    res = [_ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, real_bytes=rb, step_kernel=sk, cfl_alpha=0.5).adjoint(
+        0, 40.0, 10.0, g, obs, 6) for sk in (1, 3)]
+    assert res[1][0] == res[0][0]
+    np.testing.assert_allclose(res[1][2], res[0][2], rtol=tol)
+    assert np.linalg.norm(res[1][1] - res[0][1]) <= tol * np.linalg.norm(res[0][1])
 
 
 def test_autograd_function(fl):
