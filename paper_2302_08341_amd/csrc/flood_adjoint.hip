@@ -324,17 +324,7 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
     const int wg = xcd_remap(blockIdx.x, gridDim.x) * (kBlock / 64) + wave;
     if (wg >= C.n_waves) return;
     int k, sx, sy;
-    if (C.march_order == 0) {
-        k = wg % C.n_members;
-        const int strip = wg / C.n_members;
-        sy = strip / C.strips_x;
-        sx = strip - sy * C.strips_x;
-    } else {
-        sx = wg % C.strips_x;
-        const int rest = wg / C.strips_x;
-        sy = rest % C.strips_y;
-        k = rest / C.strips_y;
-    }
+    if (!march_wave(C, wg, C.n_members, k, sx, sy)) return;
     const MemberStep<T> ms = A.ms[k];
     if (!ms.active) return;
     const int nx = C.nx, ny = C.ny;

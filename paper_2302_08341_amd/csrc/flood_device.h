@@ -50,7 +50,9 @@ __device__ __forceinline__ T link_in(T q, T h1, T h2, T dz, T G, const MemberSte
     const T num = q - ms.gdtdx * hf * (dz - d);
     const T A = G * ms.s2dt * pow_m73(hf);
     const T qn = qdiv(num, T(1) + A * fabs(q));
-    const T lim = (qn > T(0)) ? fmin(qn, h1 * ms.capf) : fmax(qn, -h2 * ms.capf);
+    // donor limiter, branch-free: the lower bound only binds when qn < 0 and the
+    // upper bound only when qn > 0 (both bounds straddle zero)
+    const T lim = fmin(fmax(qn, -h2 * ms.capf), h1 * ms.capf);
     return (hf > hdry) ? lim : T(0);
 }
 
@@ -67,6 +69,40 @@ __device__ __forceinline__ T link_open(T qo, T h, T G, T Se, const MemberStep<T>
 template <typename T, int MI>
 __device__ __forceinline__ size_t state_index(const CatchDev<T>& C, int member, int r, int c) {
     return ((size_t)(member / MI) * C.ny + r) * ((size_t)C.nx * MI) + (size_t)c * MI + member % MI;
+}
+
+// Wavefront -> (member unit, strip) of the row-march kernels.  A member unit is
+// one member, or a group of members marched together.  Orders:
+//   0  units fastest (neighbouring wavefronts share the strip's bed and roughness)
+//   1  strips along x fastest, then rows of strips, then units (neighbouring
+//      wavefronts stream neighbouring segments of the same rows of one member)
+//   2  quads of units fastest, then strips as in 1, then quads: the four
+//      wavefronts of a workgroup march the same strip for four units, so the
+//      shared arrays are fetched once per workgroup and each member's rows are
+//      still streamed strip after strip
+// Order 2 pads the unit count to a multiple of four; padding wavefronts get
+// false.
+template <typename T>
+__device__ __forceinline__ bool march_wave(const CatchDev<T>& C, int local, int units, int& k, int& sx, int& sy) {
+    if (C.march_order == 0) {
+        k = local % units;
+        const int strip = local / units;
+        sy = strip / C.strips_x;
+        sx = strip - sy * C.strips_x;
+    } else if (C.march_order == 1) {
+        sx = local % C.strips_x;
+        const int rest = local / C.strips_x;
+        sy = rest % C.strips_y;
+        k = rest / C.strips_y;
+    } else {
+        const int q = local & 3;
+        const int rest = local >> 2;
+        sx = rest % C.strips_x;
+        const int rest2 = rest / C.strips_x;
+        sy = rest2 % C.strips_y;
+        k = (rest2 / C.strips_y) * 4 + q;
+    }
+    return k < units;
 }
 
 // V adjacent cells moved with one V-wide access (p must be V-element aligned)

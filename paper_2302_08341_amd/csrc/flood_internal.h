@@ -56,7 +56,7 @@ template <typename T> struct CatchDev {
     // one wavefront per (strip, group of march_seg members)
     int32_t march_rows, strips_x, strips_y;
     int32_t wave_begin, n_waves;
-    int32_t march_order;      // 0: member groups fastest, 1: strips along x fastest
+    int32_t march_order;      // wavefront order, see march_wave
     T edge_slope[4];
     T hdry, g;
     double dx;
@@ -131,7 +131,10 @@ template <typename T> void launch_step_mi(int mi, const StepLaunch<T>& L, hipStr
 template <typename T> void launch_march(const StepLaunch<T>& L, int seg, int total_waves, hipStream_t s);
 // cells per lane of the vectorised row-marching kernel (nx must be a multiple of it)
 template <typename T> constexpr int march_vec() { return sizeof(T) == 4 ? 4 : 2; }
-template <typename T> void launch_marchv(const StepLaunch<T>& L, int nt, int total_waves, hipStream_t s);
+template <typename T> void launch_marchv(const StepLaunch<T>& L, int nt, int pf, int total_waves, hipStream_t s);
+// wavefronts of a row-march launch over one catchment: strips x member units,
+// units padded to a multiple of four in wavefront order 2
+inline int march_waves(int strips, int units, int order) { return strips * (order == 2 ? (units + 3) / 4 * 4 : units); }
 void launch_count_active(int n_total, const double* t, const int32_t* fault, const double* t_end,
                          const int32_t* status, int32_t* out, hipStream_t s);
 template <typename HB> void launch_zero_bins(int off, int n, int n_total, HB* bins, hipStream_t s);
@@ -199,7 +202,7 @@ void launch_adj_pre(int G, const MemberStep<T>* ms_prev, const MemberStep<T>* ms
                     int32_t* lpar, T* lh0, T* lh1, hipStream_t s);
 template <typename T>
 void launch_nacc_reduce(int G, size_t ncell, const T* nacc, double* nbar, hipStream_t s);
-template <typename T> void launch_marchv_rec(const StepLaunch<T>& L, int total_waves, hipStream_t s);
+template <typename T> void launch_marchv_rec(const StepLaunch<T>& L, int pf, int total_waves, hipStream_t s);
 template <typename T>
 void launch_inject(int mi, const CatchDev<T>& after, const int32_t* tags, int K, const int32_t* grc,
                    const double* obs, T* lh, hipStream_t s);

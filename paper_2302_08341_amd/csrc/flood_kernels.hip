@@ -585,20 +585,7 @@ __global__ __launch_bounds__(kBlock) void k_march(const StepLaunch<T> L) {
     if (local >= C.n_waves) return;
     const int n_groups = (C.n_members + SEG - 1) / SEG;
     int kg, sx, sy;
-    if (C.march_order == 0) {
-        // member groups fastest: neighbouring wavefronts share the strip's bed and roughness
-        kg = local % n_groups;
-        const int strip = local / n_groups;
-        sy = strip / C.strips_x;
-        sx = strip - sy * C.strips_x;
-    } else {
-        // strips along x fastest: neighbouring wavefronts read neighbouring segments of the
-        // same rows, so DRAM pages are streamed instead of visited 256 bytes at a time
-        sx = local % C.strips_x;
-        const int rest = local / C.strips_x;
-        sy = rest % C.strips_y;
-        kg = rest / C.strips_y;
-    }
+    if (!march_wave(C, local, n_groups, kg, sx, sy)) return;
     MemberStep<T> ms[SEG];
     bool act[SEG];
     bool any = false;
@@ -756,7 +743,12 @@ __global__ __launch_bounds__(kBlock) void k_march(const StepLaunch<T> L) {
 // 1..62), which keeps every access V-aligned.  Same link functions and
 // operands as k_step: identical bits.
 // ---------------------------------------------------------------------------
-template <typename T, int V, int NT, int REC>
+// PF = 1 issues the next row's loads before computing the current row (one row
+// of lookahead), so each wavefront keeps its own loads in flight while it
+// computes.  Loads use a column clamped into the grid and a row clamped to the
+// last row, so no lane needs a branch or a zero fill around them: values of
+// lanes outside the grid and of the row below the last are read but never used.
+template <typename T, int V, int NT, int REC, int PF>
 __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
     using HB = typename HBits<T>::type;
     const int lane = threadIdx.x & 63;
@@ -769,23 +761,16 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
     const int local = wg - C.wave_begin;
     if (local >= C.n_waves) return;
     int k, sx, sy;
-    if (C.march_order == 0) {
-        k = local % C.n_members;
-        const int strip = local / C.n_members;
-        sy = strip / C.strips_x;
-        sx = strip - sy * C.strips_x;
-    } else {
-        sx = local % C.strips_x;
-        const int rest = local / C.strips_x;
-        sy = rest % C.strips_y;
-        k = rest / C.strips_y;
-    }
+    if (!march_wave(C, local, C.n_members, k, sx, sy)) return;
     const MemberStep<T> ms = L.ms[C.member_off + k];
     if (!ms.active) return;
     const int nx = C.nx, ny = C.ny;
     const int xl = sx * (62 * V) - V + V * lane;          // first cell of this lane
     const bool inx = xl >= 0 && xl < nx;                   // nx % V == 0: all V cells or none
     const bool own = lane >= 1 && lane <= 62 && inx;
+    const bool westw = sx == 0;                            // wavefront-uniform edge tests
+    const bool eastw = sx == C.strips_x - 1;
+    const int xa = min(max(xl, 0), nx - V);                // load column
     const int r0 = sy * C.march_rows;
     const int r1 = min(r0 + C.march_rows, ny);
     const size_t plane = (size_t)ny * nx;
@@ -832,50 +817,55 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
     const T g = C.g, hdry = C.hdry;
     const int nb = 2 * (nx + ny);
 
-    size_t c0 = (size_t)r0 * nx + xl;
+    size_t ca = (size_t)r0 * nx + xa;
     T hc[V], zc[V], nc[V], fN[V];
+    vload<T, V>(H + ca, hc);
+    vload<T, V>(Z + ca, zc);
+    vload<T, V>(Nn + ca, nc);
+    if (r0 > 0) {
+        T hN[V], zN[V], nN[V], qN[V];
+        vload<T, V>(H + ca - nx, hN);
+        vload<T, V>(Z + ca - nx, zN);
+        vload<T, V>(Nn + ca - nx, nN);
+        vload<T, V>(QY + ca - nx, qN);
 #pragma unroll
-    for (int j = 0; j < V; ++j) hc[j] = zc[j] = nc[j] = fN[j] = T(0);
-    if (inx) {
-        vload<T, V>(H + c0, hc);
-        vload<T, V>(Z + c0, zc);
-        vload<T, V>(Nn + c0, nc);
-        if (r0 > 0) {
-            T hN[V], zN[V], nN[V], qN[V];
-            vload<T, V>(H + c0 - nx, hN);
-            vload<T, V>(Z + c0 - nx, zN);
-            vload<T, V>(Nn + c0 - nx, nN);
-            vload<T, V>(QY + c0 - nx, qN);
-#pragma unroll
-            for (int j = 0; j < V; ++j) {
-                const T nf = T(0.5) * (nN[j] + nc[j]);
-                fN[j] = link_in(qN[j], hN[j], hc[j], zc[j] - zN[j], g * (nf * nf), ms, hdry);
-            }
-        } else if (C.edge_open[0]) {
-#pragma unroll
-            for (int j = 0; j < V; ++j)
-                fN[j] = -link_open(-QNs[xl + j], hc[j], g * (nc[j] * nc[j]), C.edge_slope[0], ms, hdry);
+        for (int j = 0; j < V; ++j) {
+            const T nf = T(0.5) * (nN[j] + nc[j]);
+            fN[j] = link_in(qN[j], hN[j], hc[j], zc[j] - zN[j], g * (nf * nf), ms, hdry);
         }
+    } else if (C.edge_open[0]) {
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+            fN[j] = -link_open(-QNs[xa + j], hc[j], g * (nc[j] * nc[j]), C.edge_slope[0], ms, hdry);
+    } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j) fN[j] = T(0);
     }
+    // current row's links (qE, qS) and the row below (hs, zs, ns)
+    T hs[V], zs[V], ns[V], qE[V], qS[V];
+    auto load_row = [&](size_t c, bool below, T (&qe)[V], T (&qs)[V], T (&h2)[V], T (&z2)[V], T (&n2)[V]) {
+        const size_t cb = below ? c + nx : c;
+        if (NT) {
+            vload_nt<T, V>(QX + c, qe);
+            vload_nt<T, V>(QY + c, qs);
+        } else {
+            vload<T, V>(QX + c, qe);
+            vload<T, V>(QY + c, qs);
+        }
+        vload<T, V>(H + cb, h2);
+        vload<T, V>(Z + cb, z2);
+        vload<T, V>(Nn + cb, n2);
+    };
+    if (PF) load_row(ca, r0 + 1 < ny, qE, qS, hs, zs, ns);
     HB vmax = 0;
+    T vcl = T(0);
     for (int r = r0; r < r1; ++r) {
         const bool hasS = r + 1 < ny;
-        T hs[V], zs[V], ns[V], qE[V], qS[V];
-#pragma unroll
-        for (int j = 0; j < V; ++j) hs[j] = zs[j] = ns[j] = qE[j] = qS[j] = T(0);
-        if (inx) {
-            if (NT) {
-                vload_nt<T, V>(QX + c0, qE);
-                vload_nt<T, V>(QY + c0, qS);
-            } else {
-                vload<T, V>(QX + c0, qE);
-                vload<T, V>(QY + c0, qS);
-            }
-            if (hasS) {
-                vload<T, V>(H + c0 + nx, hs);
-                vload<T, V>(Z + c0 + nx, zs);
-                vload<T, V>(Nn + c0 + nx, ns);
-            }
+        T hs2[V], zs2[V], ns2[V], qE2[V], qS2[V];
+        if (PF) {
+            if (r + 1 < r1) load_row(ca + nx, r + 2 < ny, qE2, qS2, hs2, zs2, ns2);
+        } else {
+            load_row(ca, hasS, qE, qS, hs, zs, ns);
         }
         // east neighbour of the lane's last cell = first cell of the next lane
         const T hE = __shfl_down(hc[0], 1, 64);
@@ -884,74 +874,67 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
         T fE[V];
 #pragma unroll
         for (int j = 0; j < V; ++j) {
-            const int x = xl + j;
             const T h2 = (j + 1 < V) ? hc[j + 1] : hE;
             const T z2 = (j + 1 < V) ? zc[j + 1] : zE;
             const T n2 = (j + 1 < V) ? nc[j + 1] : nE;
-            if (x + 1 < nx) {
-                const T nf = T(0.5) * (nc[j] + n2);
-                fE[j] = link_in(qE[j], hc[j], h2, z2 - zc[j], g * (nf * nf), ms, hdry);
-            } else {
-                fE[j] = C.edge_open[1] ? link_open(qE[j], hc[j], g * (nc[j] * nc[j]), C.edge_slope[1], ms, hdry)
-                                       : T(0);
-            }
+            const T nf = T(0.5) * (nc[j] + n2);
+            fE[j] = link_in(qE[j], hc[j], h2, z2 - zc[j], g * (nf * nf), ms, hdry);
         }
-        const T fW0 = __shfl_up(fE[V - 1], 1, 64);
-        if (own) {
-            T hn4[V], fS4[V];
-            uint8_t cf[V];
+        if (eastw) {
+#pragma unroll
+            for (int j = 0; j < V; ++j)
+                if (xl + j + 1 == nx)
+                    fE[j] = C.edge_open[1] ? link_open(qE[j], hc[j], g * (nc[j] * nc[j]), C.edge_slope[1], ms, hdry)
+                                           : T(0);
+        }
+        T fW[V];
+        fW[0] = __shfl_up(fE[V - 1], 1, 64);
+#pragma unroll
+        for (int j = 1; j < V; ++j) fW[j] = fE[j - 1];
+        if (westw && xl == 0)
+            fW[0] = C.edge_open[3] ? -link_open(-QWs[r], hc[0], g * (nc[0] * nc[0]), C.edge_slope[3], ms, hdry)
+                                   : T(0);
+        T fS[V];
+        if (hasS) {
 #pragma unroll
             for (int j = 0; j < V; ++j) {
-                const int x = xl + j;
-                const T gb = g * (nc[j] * nc[j]);
-                T fW;
-                if (j > 0)
-                    fW = fE[j - 1];
-                else if (x > 0)
-                    fW = fW0;
-                else
-                    fW = C.edge_open[3] ? -link_open(-QWs[r], hc[0], gb, C.edge_slope[3], ms, hdry) : T(0);
-                T fS;
-                if (hasS) {
-                    const T nf = T(0.5) * (nc[j] + ns[j]);
-                    fS = link_in(qS[j], hc[j], hs[j], zs[j] - zc[j], g * (nf * nf), ms, hdry);
-                } else {
-                    fS = C.edge_open[2] ? link_open(qS[j], hc[j], gb, C.edge_slope[2], ms, hdry) : T(0);
-                }
-                const T dv = ((fW - fE[j]) + fN[j]) - fS;
-                T hn = (hc[j] + ms.dtdx * dv) + ms.rinc;
-                cf[j] = hn < T(0);
-                if (hn < T(0)) {
-                    if constexpr (!REC) atomicAdd(&L.vclamp[C.member_off + k], -(double)hn * (C.dx * C.dx));
-                    hn = T(0);
-                }
-                if (hn == T(0)) hn = T(0);
-                hn4[j] = hn;
-                fS4[j] = fS;
-                if (x == 0) QWo[r] = fW;
-                if (r == 0) QNo[x] = fN[j];
-                if (!REC && (x == 0 || x + 1 == nx || r == 0 || !hasS)) {
-                    double* acc = C.out_acc + (size_t)k * nb;
-                    if (r == 0 && C.edge_open[0]) acc[x] += -(double)fN[j] * ms.dxdt;
-                    if (!hasS && C.edge_open[2]) acc[nx + x] += (double)fS * ms.dxdt;
-                    if (x == 0 && C.edge_open[3]) acc[2 * nx + r] += -(double)fW * ms.dxdt;
-                    if (x + 1 == nx && C.edge_open[1]) acc[2 * nx + ny + r] += (double)fE[j] * ms.dxdt;
-                }
-                const HB hb = to_bits(hn);
-                vmax = hb > vmax ? hb : vmax;
-                fN[j] = fS;
+                const T nf = T(0.5) * (nc[j] + ns[j]);
+                fS[j] = link_in(qS[j], hc[j], hs[j], zs[j] - zc[j], g * (nf * nf), ms, hdry);
             }
+        } else if (C.edge_open[2]) {
+#pragma unroll
+            for (int j = 0; j < V; ++j)
+                fS[j] = link_open(qS[j], hc[j], g * (nc[j] * nc[j]), C.edge_slope[2], ms, hdry);
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) fS[j] = T(0);
+        }
+        T hn4[V];
+        uint8_t cf[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const T dv = ((fW[j] - fE[j]) + fN[j]) - fS[j];
+            T hn = (hc[j] + ms.dtdx * dv) + ms.rinc;
+            cf[j] = hn < T(0);
+            vcl += (own && hn < T(0)) ? -hn : T(0);
+            hn = (hn < T(0)) ? T(0) : hn;
+            hn = (hn == T(0)) ? T(0) : hn;
+            hn4[j] = hn;
+            const HB hb = to_bits(hn);
+            vmax = (own && hb > vmax) ? hb : vmax;
+        }
+        if (own) {
             if (NT) {
-                vstore_nt<T, V>(Ho + c0, hn4);
-                vstore_nt<T, V>(QXo + c0, fE);
-                vstore_nt<T, V>(QYo + c0, fS4);
+                vstore_nt<T, V>(Ho + ca, hn4);
+                vstore_nt<T, V>(QXo + ca, fE);
+                vstore_nt<T, V>(QYo + ca, fS);
             } else {
-                vstore<T, V>(Ho + c0, hn4);
-                vstore<T, V>(QXo + c0, fE);
-                vstore<T, V>(QYo + c0, fS4);
+                vstore<T, V>(Ho + ca, hn4);
+                vstore<T, V>(QXo + ca, fE);
+                vstore<T, V>(QYo + ca, fS);
             }
             if constexpr (REC) {
-                uint8_t* cl = L.clamp_out + (size_t)ms.slot * L.clamp_stride + (size_t)k * plane + c0;
+                uint8_t* cl = L.clamp_out + (size_t)ms.slot * L.clamp_stride + (size_t)k * plane + ca;
                 if constexpr (V == 4) {
                     *reinterpret_cast<uint32_t*>(cl) = (uint32_t)cf[0] | ((uint32_t)cf[1] << 8) |
                                                        ((uint32_t)cf[2] << 16) | ((uint32_t)cf[3] << 24);
@@ -959,53 +942,93 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
                     *reinterpret_cast<uint16_t*>(cl) = (uint16_t)(cf[0] | (cf[1] << 8));
                 }
             }
+            if (westw && xl == 0) QWo[r] = fW[0];
+            if (r == 0) {
+#pragma unroll
+                for (int j = 0; j < V; ++j) QNo[xl + j] = fN[j];
+            }
+            // outflow through open edges (FP64 per member and edge link)
+            if (!REC && (westw || eastw || r == 0 || !hasS)) {
+                double* acc = C.out_acc + (size_t)k * nb;
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    const int x = xl + j;
+                    if (r == 0 && C.edge_open[0]) acc[x] += -(double)fN[j] * ms.dxdt;
+                    if (!hasS && C.edge_open[2]) acc[nx + x] += (double)fS[j] * ms.dxdt;
+                    if (x == 0 && C.edge_open[3]) acc[2 * nx + r] += -(double)fW[j] * ms.dxdt;
+                    if (x + 1 == nx && C.edge_open[1]) acc[2 * nx + ny + r] += (double)fE[j] * ms.dxdt;
+                }
+            }
         }
 #pragma unroll
         for (int j = 0; j < V; ++j) {
+            fN[j] = fS[j];
             hc[j] = hs[j];
             zc[j] = zs[j];
             nc[j] = ns[j];
         }
-        c0 += nx;
+        if (PF) {
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                qE[j] = qE2[j];
+                qS[j] = qS2[j];
+                hs[j] = hs2[j];
+                zs[j] = zs2[j];
+                ns[j] = ns2[j];
+            }
+        }
+        ca += nx;
     }
     if constexpr (!REC) {
         for (int off = 32; off > 0; off >>= 1) {
             const HB o = __shfl_xor(vmax, off, 64);
             vmax = o > vmax ? o : vmax;
         }
-        if (lane == 0 && vmax != 0) {
-            HB* a = L.hbins + (size_t)(blockIdx.x & (kBins - 1)) * L.n_total + C.member_off + k;
-            const HB cur = __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (vmax > cur) atomicMax(a, vmax);
+        double cl = (double)vcl;
+        for (int off = 32; off > 0; off >>= 1) cl += __shfl_xor(cl, off, 64);
+        if (lane == 0) {
+            if (vmax != 0) {
+                HB* a = L.hbins + (size_t)(blockIdx.x & (kBins - 1)) * L.n_total + C.member_off + k;
+                const HB cur = __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (vmax > cur) atomicMax(a, vmax);
+            }
+            if (cl != 0.0) atomicAdd(&L.vclamp[C.member_off + k], cl * (C.dx * C.dx));
         }
     }
 }
 
-template <typename T> void launch_marchv(const StepLaunch<T>& L, int nt, int total_waves, hipStream_t s) {
+template <typename T> void launch_marchv(const StepLaunch<T>& L, int nt, int pf, int total_waves, hipStream_t s) {
     const int per = kBlock / 64;
     const dim3 grid((total_waves + per - 1) / per);
     constexpr int V = march_vec<T>();
-    if (nt)
-        hipLaunchKernelGGL((k_marchv<T, V, 1, 0>), grid, dim3(kBlock), 0, s, L);
+    if (nt && pf)
+        hipLaunchKernelGGL((k_marchv<T, V, 1, 0, 1>), grid, dim3(kBlock), 0, s, L);
+    else if (nt)
+        hipLaunchKernelGGL((k_marchv<T, V, 1, 0, 0>), grid, dim3(kBlock), 0, s, L);
+    else if (pf)
+        hipLaunchKernelGGL((k_marchv<T, V, 0, 0, 1>), grid, dim3(kBlock), 0, s, L);
     else
-        hipLaunchKernelGGL((k_marchv<T, V, 0, 0>), grid, dim3(kBlock), 0, s, L);
+        hipLaunchKernelGGL((k_marchv<T, V, 0, 0, 0>), grid, dim3(kBlock), 0, s, L);
 }
 
 // Tape recomputation of the adjoint: the same step, reading and writing tape
 // slots, recording clamp flags, leaving the ledger, the outflow accumulators and
 // the depth maximum alone; members that did not step in the recorded launch are
 // skipped (their slots are not advanced).
-template <typename T> void launch_marchv_rec(const StepLaunch<T>& L, int total_waves, hipStream_t s) {
+template <typename T> void launch_marchv_rec(const StepLaunch<T>& L, int pf, int total_waves, hipStream_t s) {
     const int per = kBlock / 64;
     const dim3 grid((total_waves + per - 1) / per);
     constexpr int V = march_vec<T>();
-    hipLaunchKernelGGL((k_marchv<T, V, 0, 1>), grid, dim3(kBlock), 0, s, L);
+    if (pf)
+        hipLaunchKernelGGL((k_marchv<T, V, 0, 1, 1>), grid, dim3(kBlock), 0, s, L);
+    else
+        hipLaunchKernelGGL((k_marchv<T, V, 0, 1, 0>), grid, dim3(kBlock), 0, s, L);
 }
 
-template void launch_marchv<float>(const StepLaunch<float>&, int, int, hipStream_t);
-template void launch_marchv<double>(const StepLaunch<double>&, int, int, hipStream_t);
-template void launch_marchv_rec<float>(const StepLaunch<float>&, int, hipStream_t);
-template void launch_marchv_rec<double>(const StepLaunch<double>&, int, hipStream_t);
+template void launch_marchv<float>(const StepLaunch<float>&, int, int, int, hipStream_t);
+template void launch_marchv<double>(const StepLaunch<double>&, int, int, int, hipStream_t);
+template void launch_marchv_rec<float>(const StepLaunch<float>&, int, int, hipStream_t);
+template void launch_marchv_rec<double>(const StepLaunch<double>&, int, int, hipStream_t);
 
 template <typename T> void launch_march(const StepLaunch<T>& L, int seg, int total_waves, hipStream_t s) {
     const int per = kBlock / 64;

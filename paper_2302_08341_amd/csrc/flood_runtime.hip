@@ -54,6 +54,7 @@ template <typename T> struct Impl : ImplBase {
     int march_seg = 2;        // members per wavefront of the row-marching kernel
     int march_order = 1;      // wavefront order of the row-marching kernel
     int march_nt = 1;         // non-temporal state streams in the vectorised row-marching kernel
+    int march_pf = 1;         // one row of load lookahead in the vectorised row-marching kernel
     int total_waves = 0;      // waves of one row-marching launch
     int n_catch = 0, n_total = 0;
     std::vector<Cat> cats;
@@ -149,7 +150,8 @@ template <typename T> struct Impl : ImplBase {
             d.strips_x = (c.nx + strip_w - 1) / strip_w;
             d.strips_y = (c.ny + d.march_rows - 1) / d.march_rows;
             d.wave_begin = waves;
-            d.n_waves = d.strips_x * d.strips_y * (variant == 3 ? c.N : (c.N + march_seg - 1) / march_seg);
+            d.n_waves = march_waves(d.strips_x * d.strips_y, variant == 3 ? c.N : (c.N + march_seg - 1) / march_seg,
+                                    march_order);
             d.march_order = march_order;
             waves += d.n_waves;
             SL.c[i] = d;
@@ -163,7 +165,7 @@ template <typename T> struct Impl : ImplBase {
 
     void launch_steps(const StepLaunch<T>& L) {
         if (variant == 3 && !L.recompute)
-            launch_marchv<T>(L, march_nt, total_waves, st);
+            launch_marchv<T>(L, march_nt, march_pf, total_waves, st);
         else if (variant == 2 && !L.recompute)
             launch_march<T>(L, march_seg, total_waves, st);
         else
@@ -194,8 +196,9 @@ template <typename T> struct Impl : ImplBase {
             st = own_stream;
         }
         n_catch = nc;
-        if (const char* mo = std::getenv("FLOOD_MARCH_ORDER")) march_order = std::atoi(mo) ? 1 : 0;
+        if (const char* mo = std::getenv("FLOOD_MARCH_ORDER")) march_order = std::min(2, std::max(0, std::atoi(mo)));
         if (const char* nt = std::getenv("FLOOD_MARCH_NT")) march_nt = std::atoi(nt) ? 1 : 0;
+        if (const char* pf = std::getenv("FLOOD_MARCH_PF")) march_pf = std::atoi(pf) ? 1 : 0;
         const char* ng = std::getenv("FLOOD_NO_GRAPH");
         use_graph = !(ng && ng[0] == '1');
         if (const char* gs = std::getenv("FLOOD_GRAPH_STEPS")) {   // steps per captured batch
@@ -515,13 +518,13 @@ template <typename T> struct Impl : ImplBase {
                 segs.push_back(params[0].march_members);
             else
                 segs = {1, 2, 4, 8};
-            for (int od : {0, 1})
+            for (int od : {0, 1, 2})
                 for (int sg : segs)
                     for (int mr : {8, 16, 32, 64, 128})
                         cands.push_back({2, cats[0].tile_rows, cats[0].cpb, mr, sg, od});
         }
         if (want3)
-            for (int od : {0, 1})
+            for (int od : {0, 1, 2})
                 for (int mr : {4, 8, 16, 32, 64}) cands.push_back({3, cats[0].tile_rows, cats[0].cpb, mr, 1, od});
         float best = 1e30f;
         Cand bc = cands.empty()
@@ -1071,6 +1074,7 @@ template <typename T> struct Impl : ImplBase {
 // interleave, so its gradients do not depend on what the tuner picked.
 constexpr int kAdjTileRows = 4;
 constexpr int kAdjMarchRows = 8;
+constexpr int kAdjMarchOrder = 1;
 
 template <typename T>
 static CatchDev<T> group_view(const CatchDev<T>& C, int mi, int g0, int G, T* const h[2], T* const qx[2],
@@ -1089,8 +1093,8 @@ static CatchDev<T> group_view(const CatchDev<T>& C, int mi, int g0, int G, T* co
     v.strips_x = (C.nx + strip_w - 1) / strip_w;
     v.strips_y = (C.ny + v.march_rows - 1) / v.march_rows;
     v.wave_begin = 0;
-    v.n_waves = v.strips_x * v.strips_y * G;
-    v.march_order = 1;
+    v.march_order = kAdjMarchOrder;
+    v.n_waves = march_waves(v.strips_x * v.strips_y, G, v.march_order);
     v.member_off = C.member_off + g0;
     v.n_members = G;
     v.n_chunks = (G + mi - 1) / mi;
@@ -1335,7 +1339,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                         PLg.any_log = any_log + L;
                         PLg.tag_value = smp;
                         launch_plan<T>(PLg, st);
-                        launch_marchv<T>(SLm, march_nt, tw, st);
+                        launch_marchv<T>(SLm, march_nt, march_pf, tw, st);
                         ++L;
                     }
                     launch_count_active(Gg, t + off + g0, fault + off + g0, d_tend, status, d_count, st);
@@ -1384,7 +1388,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                     R.clamp_out = clamp;
                     R.slot_stride = slot_elems;
                     R.clamp_stride = elemsG;
-                    launch_marchv_rec<T>(R, tw, st);
+                    launch_marchv_rec<T>(R, march_pf, tw, st);
                 }
                 for (int j = (int)useful.size() - 1; j >= 0; --j) {
                     const int64_t l = useful[j];

@@ -18,7 +18,7 @@ struct TuneChoice {
     int variant = 1;     // 1 tiled kernel, 2 row-marching kernel
     int march_rows = 32; // rows per strip of the row-marching kernel
     int march_seg = 2;   // members marched together by one wavefront
-    int march_order = 1; // wavefront order: 0 members fastest, 1 strips fastest
+    int march_order = 1; // wavefront order of the row-march kernels (0, 1 or 2)
 };
 
 TuneChoice tune_default(const TuneKey& k);

@@ -166,11 +166,14 @@ URBAN4 = W.urban_catchment("par4", 61, 300, 3, W.seed_for(2, 4), n_gauges=3)   #
 
 @pytest.mark.parametrize("rb", [4, 8])
 @pytest.mark.parametrize("mr", [1, 5, 16, 100])
-def test_vectorised_march_is_bit_exact(fl, rb, mr):
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_vectorised_march_is_bit_exact(fl, rb, mr, order, monkeypatch):
+    # wavefront orders: 2 takes the members in quads and pads 3 members to 4
     rain = W.chicago_hyetograph()
     ref = _ens(fl, URBAN4, rain, 3, real_bytes=rb, member_interleave=1, tile_rows=4, chunks_per_block=3,
                step_kernel=1)
     ref.step(350.0)
+    monkeypatch.setenv("FLOOD_MARCH_ORDER", str(order))
     e = _ens(fl, URBAN4, rain, 3, real_bytes=rb, member_interleave=1, step_kernel=3, march_rows=mr)
     assert e.config()["step_kernel"] == 3
     e.step(350.0)
@@ -178,6 +181,21 @@ def test_vectorised_march_is_bit_exact(fl, rb, mr):
         for w in (fl.FIELD_H, fl.FIELD_QX, fl.FIELD_QY):
             np.testing.assert_array_equal(e.field(i, w), ref.field(i, w))
     np.testing.assert_array_equal(e.ledger()["outflow"], ref.ledger()["outflow"])
+
+
+@pytest.mark.parametrize("order", [0, 2])
+@pytest.mark.parametrize("mm", [1, 2])
+def test_row_march_orders_are_bit_exact(fl, order, mm, monkeypatch):
+    rain = W.chicago_hyetograph()
+    ref = _ens(fl, URBAN, rain, 5, real_bytes=4, member_interleave=1, tile_rows=4, chunks_per_block=5,
+               step_kernel=1)
+    ref.step(330.0)
+    monkeypatch.setenv("FLOOD_MARCH_ORDER", str(order))
+    e = _ens(fl, URBAN, rain, 5, real_bytes=4, member_interleave=1, step_kernel=2, march_rows=7, march_members=mm)
+    e.step(330.0)
+    for i in range(5):
+        np.testing.assert_array_equal(e.field(i), ref.field(i))
+        np.testing.assert_array_equal(e.field(i, fl.FIELD_QY), ref.field(i, fl.FIELD_QY))
 
 
 def test_batched_equals_one_launch_per_member(fl):
