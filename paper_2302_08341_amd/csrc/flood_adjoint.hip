@@ -331,6 +331,9 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
     const int xl = sx * (62 * V) - V + V * lane;
     const bool inx = xl >= 0 && xl < nx;
     const bool own = lane >= 1 && lane <= 62 && inx;
+    const bool westw = sx == 0;                        // wavefront-uniform edge tests
+    const bool eastw = sx == C.strips_x - 1;
+    const int xa = min(max(xl, 0), nx - V);            // load column (lanes outside the grid read, never use)
     const int r0 = sy * C.march_rows;
     const int r1 = min(r0 + C.march_rows, ny);
     const size_t plane = (size_t)ny * nx;
@@ -357,53 +360,47 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
     const T* __restrict__ Nn = C.n;
     const T g = C.g, hdry = C.hdry, kk = ms.dtdx;
 
-    size_t c0 = (size_t)r0 * nx + xl;
+    size_t ca = (size_t)r0 * nx + xa;
     T hc[V], zc[V], nc[V], lec[V], pNh[V], pNn[V];
+    vload<T, V>(H + ca, hc);
+    vload<T, V>(Z + ca, zc);
+    vload<T, V>(Nn + ca, nc);
+    le_load<T, V>(LH + ca, CL + ca, lec);
+    if (r0 > 0) {
+        // the south links of the row above the strip feed its first row's north links
+        T hN[V], zN[V], nN[V], qN[V], lqN[V], leN[V];
+        vload<T, V>(H + ca - nx, hN);
+        vload<T, V>(Z + ca - nx, zN);
+        vload<T, V>(Nn + ca - nx, nN);
+        vload<T, V>(QY + ca - nx, qN);
+        vload<T, V>(LQY + ca - nx, lqN);
+        le_load<T, V>(LH + ca - nx, CL + ca - nx, leN);
 #pragma unroll
-    for (int j = 0; j < V; ++j) hc[j] = zc[j] = nc[j] = lec[j] = pNh[j] = pNn[j] = T(0);
-    if (inx) {
-        vload<T, V>(H + c0, hc);
-        vload<T, V>(Z + c0, zc);
-        vload<T, V>(Nn + c0, nc);
-        le_load<T, V>(LH + c0, CL + c0, lec);
-        if (r0 > 0) {
-            // the south links of the row above the strip feed its first row's north links
-            T hN[V], zN[V], nN[V], qN[V], lqN[V], leN[V];
-            vload<T, V>(H + c0 - nx, hN);
-            vload<T, V>(Z + c0 - nx, zN);
-            vload<T, V>(Nn + c0 - nx, nN);
-            vload<T, V>(QY + c0 - nx, qN);
-            vload<T, V>(LQY + c0 - nx, lqN);
-            le_load<T, V>(LH + c0 - nx, CL + c0 - nx, leN);
-#pragma unroll
-            for (int j = 0; j < V; ++j) {
-                const T nf = T(0.5) * (nN[j] + nc[j]);
-                T dq, d1, d2, cn;
-                link_in_d(qN[j], hN[j], hc[j], zc[j] - zN[j], g * (nf * nf), g * nf, ms, hdry, dq, d1, d2, cn);
-                const T lt = lqN[j] + kk * (lec[j] - leN[j]);
-                pNh[j] = lt * d2;
-                pNn[j] = lt * cn;
-            }
+        for (int j = 0; j < V; ++j) {
+            const T nf = T(0.5) * (nN[j] + nc[j]);
+            T dq, d1, d2, cn;
+            link_in_d(qN[j], hN[j], hc[j], zc[j] - zN[j], g * (nf * nf), g * nf, ms, hdry, dq, d1, d2, cn);
+            const T lt = lqN[j] + kk * (lec[j] - leN[j]);
+            pNh[j] = lt * d2;
+            pNn[j] = lt * cn;
         }
+    } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j) pNh[j] = pNn[j] = T(0);
     }
     double lsum = 0.0;
     for (int r = r0; r < r1; ++r) {
         const bool hasS = r + 1 < ny;
+        const size_t cs = hasS ? ca + nx : ca;
         T qE[V], qS[V], lqE[V], lqS[V], hs[V], zs[V], ns[V], les[V];
-#pragma unroll
-        for (int j = 0; j < V; ++j) qE[j] = qS[j] = lqE[j] = lqS[j] = hs[j] = zs[j] = ns[j] = les[j] = T(0);
-        if (inx) {
-            vload<T, V>(QX + c0, qE);
-            vload<T, V>(QY + c0, qS);
-            vload<T, V>(LQX + c0, lqE);
-            vload<T, V>(LQY + c0, lqS);
-            if (hasS) {
-                vload<T, V>(H + c0 + nx, hs);
-                vload<T, V>(Z + c0 + nx, zs);
-                vload<T, V>(Nn + c0 + nx, ns);
-                le_load<T, V>(LH + c0 + nx, CL + c0 + nx, les);
-            }
-        }
+        vload<T, V>(QX + ca, qE);
+        vload<T, V>(QY + ca, qS);
+        vload<T, V>(LQX + ca, lqE);
+        vload<T, V>(LQY + ca, lqS);
+        vload<T, V>(H + cs, hs);
+        vload<T, V>(Z + cs, zs);
+        vload<T, V>(Nn + cs, ns);
+        le_load<T, V>(LH + cs, CL + cs, les);
         // east neighbour of the lane's last cell = first cell of the next lane
         const T hE = __shfl_down(hc[0], 1, 64);
         const T zE = __shfl_down(zc[0], 1, 64);
@@ -412,79 +409,95 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
         T ltE[V], dqE[V], d1E[V], d2E[V], cnE[V];
 #pragma unroll
         for (int j = 0; j < V; ++j) {
-            const int x = xl + j;
             const T h2 = (j + 1 < V) ? hc[j + 1] : hE;
             const T z2 = (j + 1 < V) ? zc[j + 1] : zE;
             const T n2 = (j + 1 < V) ? nc[j + 1] : nE;
             const T le2 = (j + 1 < V) ? lec[j + 1] : leE;
-            if (x + 1 < nx) {
-                const T nf = T(0.5) * (nc[j] + n2);
-                link_in_d(qE[j], hc[j], h2, z2 - zc[j], g * (nf * nf), g * nf, ms, hdry, dqE[j], d1E[j], d2E[j],
-                          cnE[j]);
-                ltE[j] = lqE[j] + kk * (le2 - lec[j]);
-            } else if (C.edge_open[1]) {
-                link_open_d(qE[j], hc[j], g * (nc[j] * nc[j]), T(2) * g * nc[j], C.edge_slope[1], ms, hdry, dqE[j],
-                            d1E[j], cnE[j]);
+            const T nf = T(0.5) * (nc[j] + n2);
+            link_in_d(qE[j], hc[j], h2, z2 - zc[j], g * (nf * nf), g * nf, ms, hdry, dqE[j], d1E[j], d2E[j], cnE[j]);
+            ltE[j] = lqE[j] + kk * (le2 - lec[j]);
+        }
+        if (eastw) {
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                if (xl + j + 1 != nx) continue;
                 d2E[j] = T(0);
-                ltE[j] = lqE[j] - kk * lec[j];
-            } else {
-                dqE[j] = d1E[j] = d2E[j] = cnE[j] = ltE[j] = T(0);
+                if (C.edge_open[1]) {
+                    link_open_d(qE[j], hc[j], g * (nc[j] * nc[j]), T(2) * g * nc[j], C.edge_slope[1], ms, hdry,
+                                dqE[j], d1E[j], cnE[j]);
+                    ltE[j] = lqE[j] - kk * lec[j];
+                } else {
+                    dqE[j] = d1E[j] = cnE[j] = ltE[j] = T(0);
+                }
             }
         }
         // west link of the first cell: the previous lane's last east link
         const T wH = __shfl_up(ltE[V - 1] * d2E[V - 1], 1, 64);
         const T wN = __shfl_up(ltE[V - 1] * cnE[V - 1], 1, 64);
+        // south links
+        T ltS[V], dqS[V], d1S[V], d2S[V], cnS[V];
+        if (hasS) {
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                const T nf = T(0.5) * (nc[j] + ns[j]);
+                link_in_d(qS[j], hc[j], hs[j], zs[j] - zc[j], g * (nf * nf), g * nf, ms, hdry, dqS[j], d1S[j],
+                          d2S[j], cnS[j]);
+                ltS[j] = lqS[j] + kk * (les[j] - lec[j]);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                d2S[j] = T(0);
+                if (C.edge_open[2]) {
+                    link_open_d(qS[j], hc[j], g * (nc[j] * nc[j]), T(2) * g * nc[j], C.edge_slope[2], ms, hdry,
+                                dqS[j], d1S[j], cnS[j]);
+                    ltS[j] = lqS[j] - kk * lec[j];
+                } else {
+                    dqS[j] = d1S[j] = cnS[j] = ltS[j] = T(0);
+                }
+            }
+        }
         if (own) {
             T nh4[V], oqx4[V], oqy4[V], na4[V];
-            vload<T, V>(NA + c0, na4);
+            vload<T, V>(NA + ca, na4);
 #pragma unroll
             for (int j = 0; j < V; ++j) {
                 const int x = xl + j;
-                const T gb = g * (nc[j] * nc[j]), nb = T(2) * g * nc[j];
                 const T le_c = lec[j];
+                // east, south (this cell is cell 1), west, north (cell 2), as in k_adj
                 T nh = le_c;
                 T nac = T(0);
-                // east (this cell is cell 1)
                 nh += ltE[j] * d1E[j];
                 nac += ltE[j] * cnE[j];
-                // south (this cell is cell 1)
-                T ltS = T(0), dqS = T(0), d1S = T(0), d2S = T(0), cnS = T(0);
-                if (hasS) {
-                    const T nf = T(0.5) * (nc[j] + ns[j]);
-                    link_in_d(qS[j], hc[j], hs[j], zs[j] - zc[j], g * (nf * nf), g * nf, ms, hdry, dqS, d1S, d2S,
-                              cnS);
-                    ltS = lqS[j] + kk * (les[j] - le_c);
-                } else if (C.edge_open[2]) {
-                    link_open_d(qS[j], hc[j], gb, nb, C.edge_slope[2], ms, hdry, dqS, d1S, cnS);
-                    ltS = lqS[j] - kk * le_c;
-                }
-                nh += ltS * d1S;
-                nac += ltS * cnS;
-                // west (this cell is cell 2); the edge strip holds -qo
-                if (x > 0) {
-                    nh += (j > 0) ? ltE[j - 1] * d2E[j - 1] : wH;
-                    nac += (j > 0) ? ltE[j - 1] * cnE[j - 1] : wN;
-                } else {
+                nh += ltS[j] * d1S[j];
+                nac += ltS[j] * cnS[j];
+                if (j == 0 && westw && x == 0) {
+                    // west edge link; its strip holds -qo
                     T oqw = T(0);
                     if (C.edge_open[3]) {
                         T dq, d1, cn;
-                        link_open_d(-QWs[r], hc[j], gb, nb, C.edge_slope[3], ms, hdry, dq, d1, cn);
+                        link_open_d(-QWs[r], hc[0], g * (nc[0] * nc[0]), T(2) * g * nc[0], C.edge_slope[3], ms,
+                                    hdry, dq, d1, cn);
                         const T lt = LQWs[r] + kk * le_c;
                         oqw = lt * dq;
                         nh -= lt * d1;
                         nac -= lt * cn;
                     }
                     LQWo[r] = oqw;
+                } else {
+                    nh += (j > 0) ? ltE[j - 1] * d2E[j - 1] : wH;
+                    nac += (j > 0) ? ltE[j - 1] * cnE[j - 1] : wN;
                 }
-                // north (this cell is cell 2)
                 if (r > 0) {
                     nh += pNh[j];
                     nac += pNn[j];
                 } else {
+                    // north edge link; its strip holds -qo
                     T oqn = T(0);
                     if (C.edge_open[0]) {
                         T dq, d1, cn;
-                        link_open_d(-QNs[x], hc[j], gb, nb, C.edge_slope[0], ms, hdry, dq, d1, cn);
+                        link_open_d(-QNs[x], hc[j], g * (nc[j] * nc[j]), T(2) * g * nc[j], C.edge_slope[0], ms,
+                                    hdry, dq, d1, cn);
                         const T lt = LQNs[x] + kk * le_c;
                         oqn = lt * dq;
                         nh -= lt * d1;
@@ -494,16 +507,14 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
                 }
                 nh4[j] = nh;
                 oqx4[j] = ltE[j] * dqE[j];
-                oqy4[j] = ltS * dqS;
+                oqy4[j] = ltS[j] * dqS[j];
                 na4[j] += nac;
                 lsum += (double)le_c;
-                pNh[j] = ltS * d2S;
-                pNn[j] = ltS * cnS;
             }
-            vstore<T, V>(LHo + c0, nh4);
-            vstore<T, V>(LQXo + c0, oqx4);
-            vstore<T, V>(LQYo + c0, oqy4);
-            vstore<T, V>(NA + c0, na4);
+            vstore<T, V>(LHo + ca, nh4);
+            vstore<T, V>(LQXo + ca, oqx4);
+            vstore<T, V>(LQYo + ca, oqy4);
+            vstore<T, V>(NA + ca, na4);
         }
 #pragma unroll
         for (int j = 0; j < V; ++j) {
@@ -511,8 +522,10 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
             zc[j] = zs[j];
             nc[j] = ns[j];
             lec[j] = les[j];
+            pNh[j] = ltS[j] * d2S[j];
+            pNn[j] = ltS[j] * cnS[j];
         }
-        c0 += nx;
+        ca += nx;
     }
     // rain-multiplier adjoint: the depth adjoint after the step summed over the
     // strip's cells, times R dt of the member's step
