@@ -42,7 +42,7 @@ class _Model(C.Structure):
                 ("edge_kind", C.c_int32 * 4), ("edge_slope", C.c_double * 4),
                 ("rain", C.POINTER(C.c_double)), ("n_rain", C.c_int32), ("rain_interval", C.c_double),
                 ("alpha", C.c_double), ("h_dry", C.c_double), ("dt_cap", C.c_double),
-                ("dt_fixed", C.c_double), ("g", C.c_double)]
+                ("dt_fixed", C.c_double), ("g", C.c_double), ("wet_fp32", C.c_int32)]
 
 
 class _Member(C.Structure):
@@ -100,7 +100,11 @@ class Model:
     """Static description of one catchment: grid, bed, roughness, edges, rain, step policy."""
 
     def __init__(self, dem, manning, dx, rain, rain_interval=300.0, edge_kind=(0, 0, 0, 0),
-                 edge_slope=(0.0, 0.0, 0.0, 0.0), alpha=0.7, h_dry=1e-3, dt_cap=10.0, dt_fixed=0.0, g=9.81):
+                 edge_slope=(0.0, 0.0, 0.0, 0.0), alpha=0.7, h_dry=1e-3, dt_cap=10.0, dt_fixed=0.0, g=9.81,
+                 wet_fp32=False):
+        """wet_fp32: take each link's wet/dry decision in single precision (flow depth
+        in difference form, rounded to float, against h_dry rounded to float), as a
+        single-precision model does; for comparisons from the same float state."""
         self.z = _f64(dem)
         self.n = _f64(manning)
         self.ny, self.nx = self.z.shape
@@ -114,7 +118,7 @@ class Model:
         self._m = _Model(self.ny, self.nx, self.dx, _dp(self.z), _dp(self.n),
                          (C.c_int32 * 4)(*edge_kind), (C.c_double * 4)(*edge_slope),
                          _dp(self.rain), n_rain, float(rain_interval), float(alpha), float(h_dry),
-                         float(dt_cap), float(dt_fixed), float(g))
+                         float(dt_cap), float(dt_fixed), float(g), int(bool(wet_fp32)))
         self.edge_kind = tuple(edge_kind)
         self.edge_slope = tuple(edge_slope)
         self.h_dry = h_dry

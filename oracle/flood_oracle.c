@@ -10,7 +10,9 @@
  * Everything is plain IEEE double arithmetic in the order the formulas are
  * written in the paper, one member at a time, one cell or link at a time.
  * Compile with contraction off (-ffp-contract=off) so that every operation is
- * rounded as written.
+ * rounded as written.  One option (wet_fp32) takes the links' wet/dry decision
+ * in single precision, for comparisons with a single-precision model from the
+ * same float state, where the decision is the model's own (see wet_link_f32).
  *
  * Grid and link convention (Sec. 3.1, the link/cell indexing around Fig. 2):
  * cells are row-major h[r*nx + c], r = 0 is the north edge.  x-links are
@@ -46,6 +48,7 @@ typedef struct {
     double dt_cap;             /* upper bound on the adaptive step */
     double dt_fixed;           /* > 0: fixed step instead of Eq. 4 */
     double g;
+    int32_t wet_fp32;          /* 1: take the wet/dry decision of each link in single precision */
 } orc_model;
 
 typedef struct {
@@ -92,6 +95,24 @@ double orc_dt_cfl(const orc_model* m, const double* h) {
 /* ------------------------------------------------------------------------ */
 /* link discharge: Eq. 3 flow depth, Eq. 2 semi-implicit friction update    */
 /* ------------------------------------------------------------------------ */
+/* Wet/dry decision of a link in single precision.  A single-precision model
+ * decides whether a link carries flow from its own float numbers, so a
+ * comparison with it from the same float state takes that decision the same
+ * way: Eq. 3's flow depth written as the depth of the higher water surface's
+ * cell minus the positive part of the bed step towards the other cell
+ * (dz = z2 - z1), every operation rounded to float, compared with h_dry rounded
+ * to float.  Only the decision is taken in float; the discharge stays in
+ * double.  Edge links compare the inner depth. */
+static int wet_link_f32(const orc_model* m, double h1, double z1, double h2, double z2) {
+    const float fh1 = (float)h1, fh2 = (float)h2;
+    const float dz = (float)z2 - (float)z1;
+    const float d = fh1 - fh2;
+    const float hf = (d >= dz) ? fh1 - fmaxf(dz, 0.0f) : fh2 - fmaxf(-dz, 0.0f);
+    return hf > (float)m->h_dry;
+}
+
+static int wet_edge_f32(const orc_model* m, double h) { return (float)h > (float)m->h_dry; }
+
 /* Interior link between cell 1 (west or north) and cell 2 (east or south).
  * The donor limiter keeps each link from draining more than a quarter of its
  * upwind cell in one step. */
@@ -100,7 +121,7 @@ static double link_interior(const orc_model* m, double s, double q, double h1, d
     double eta1 = h1 + z1;
     double eta2 = h2 + z2;
     double hf = fmax(eta1, eta2) - fmax(z1, z2);
-    if (!(hf > m->h_dry)) return 0.0;
+    if (m->wet_fp32 ? !wet_link_f32(m, h1, z1, h2, z2) : !(hf > m->h_dry)) return 0.0;
     double S = (eta2 - eta1) / m->dx;
     double nf = s * 0.5 * (n1 + n2);
     double qn = (q - m->g * hf * dt * S) / (1.0 + m->g * nf * nf * fabs(q) * dt / pow(hf, 7.0 / 3.0));
@@ -116,7 +137,7 @@ static double link_interior(const orc_model* m, double s, double q, double h1, d
 static double link_open(const orc_model* m, double s, double qo, double hi, double ni, double Se,
                         double dt) {
     double hf = hi;
-    if (!(hf > m->h_dry)) return 0.0;
+    if (m->wet_fp32 ? !wet_edge_f32(m, hi) : !(hf > m->h_dry)) return 0.0;
     double nf = s * ni;
     double qn = (qo + m->g * hf * dt * Se) / (1.0 + m->g * nf * nf * fabs(qo) * dt / pow(hf, 7.0 / 3.0));
     qn = fmin(qn, hi * m->dx / (4.0 * dt));
@@ -408,7 +429,7 @@ static double link_interior_d(const orc_model* m, double s, double q, double h1,
     double eta2 = h2 + z2;
     int up1 = eta1 >= eta2;
     double hf = (up1 ? eta1 : eta2) - fmax(z1, z2);
-    if (!(hf > m->h_dry)) return 0.0;
+    if (m->wet_fp32 ? !wet_link_f32(m, h1, z1, h2, z2) : !(hf > m->h_dry)) return 0.0;
     const double g = m->g, dx = m->dx;
     double S = (eta2 - eta1) / dx;
     double nf = s * 0.5 * (n1 + n2);
@@ -446,7 +467,7 @@ static double link_open_d(const orc_model* m, double s, double qo, double hi, do
                           double dt, double* dq, double* dh, double* dnf) {
     *dq = *dh = *dnf = 0.0;
     double hf = hi;
-    if (!(hf > m->h_dry)) return 0.0;
+    if (m->wet_fp32 ? !wet_edge_f32(m, hi) : !(hf > m->h_dry)) return 0.0;
     const double g = m->g, dx = m->dx;
     double nf = s * ni;
     double P = pow(hf, 7.0 / 3.0);

@@ -113,7 +113,10 @@ def test_one_step_parity_from_identical_state(fl, orc):
     dt = 0.05                           # shorter than Eq. 4 here: exactly one step of this length
     e.step(1200.0 + dt)
     ref = orc.Member(h32.copy(), qx32.copy(), qy32.copy(), t=1200.0, s=URBAN.n_scale[2], mu=URBAN.rain_mult[2])
-    orc.step(m, ref, dt)
+    # from the same float state the links' wet/dry decision is the float model's own
+    m32 = orc.Model(URBAN.dem, URBAN.manning, URBAN.dx, rain, edge_kind=URBAN.edge_kind,
+                    edge_slope=URBAN.edge_slope, wet_fp32=True)
+    orc.step(m32, ref, dt)
     gh, gqx, gqy = e.field(2), e.field(2, fl.FIELD_QX), e.field(2, fl.FIELD_QY)
     assert np.abs(gh - ref.h).max() <= 1e-6
     qs = max(np.abs(ref.qx).max(), np.abs(ref.qy).max())

@@ -1,0 +1,141 @@
+"""Parity at the benchmark's full size: 2000 x 2000 cells x 96 members, FP32, the
+urban workload and the launch configuration bench.py times (geometry chosen by
+the tuner).  The oracle cannot run the whole ensemble, so it checks sampled
+outputs one by one (one step of sampled members from the GPU's own state, the
+filter weights and ancestors from the GPU's gauge values, the adjoint of a
+sampled member), and the rest is checked through properties that hold at any
+size (mass ledger of every member, batched = one handle per member).
+
+Bars as in the small-size tests: one step 1e-6 m + 4 FP32 ulp of the depth
+(deep ponds) and 1e-5 of the largest discharge; weights 1e-12; ancestors bit-exact given the weights; mass
+ledger 1e-6; adjoint 1e-3 (FP32 state against the FP64 oracle).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+T0 = 600.0
+SAMPLED = (0, 47, 95)
+
+
+@pytest.fixture(scope="module")
+def fl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2302_08341_amd import flood
+    flood.load_library()
+    return flood
+
+
+@pytest.fixture(scope="module")
+def c5(fl):
+    wl = W.config5()
+    ens = fl.FloodEnsemble.from_workload(wl)
+    ens.step(T0)
+    saved = {i: (ens.field(i), ens.field(i, fl.FIELD_QX), ens.field(i, fl.FIELD_QY)) for i in SAMPLED}
+    yield wl, ens, saved
+    ens.close()
+
+
+def test_fullsize_runs_in_the_benchmark_configuration(c5):
+    wl, ens, _ = c5
+    conf = ens.config()
+    print("full-size configuration", conf)
+    assert conf["member_interleave"] >= 1
+    led = ens.ledger()
+    assert np.all(led["t"] == T0)
+    assert np.all(led["steps"] > 0)
+
+
+def test_fullsize_mass_ledger_every_member(c5):
+    wl, ens, _ = c5
+    led = ens.ledger()
+    resid = np.abs(led["storage"] - (led["rain_in"] - led["outflow"] + led["clamp"])) / led["rain_in"]
+    assert resid.max() <= 1e-6, resid.max()
+
+
+def test_fullsize_batched_equals_one_handle_for_a_sampled_member(fl, c5):
+    wl, ens, saved = c5
+    c = wl.catchments[0]
+    i = SAMPLED[1]
+    cat = dict(dem=c.dem, manning=c.manning, dx=c.dx, edge_kind=c.edge_kind, edge_slope=c.edge_slope,
+               n_members=1, n_scale=c.n_scale[i:i + 1], rain_mult=c.rain_mult[i:i + 1])
+    p = fl.FloodEnsemble([cat], wl.rain, rain_interval=wl.rain_interval, real_bytes=wl.real_bytes)
+    p.step(T0)
+    for w, ref in zip((fl.FIELD_H, fl.FIELD_QX, fl.FIELD_QY), saved[i]):
+        np.testing.assert_array_equal(p.field(0, w), ref)
+    p.close()
+
+
+def test_fullsize_one_step_of_sampled_members(fl, orc, c5):
+    wl, ens, saved = c5
+    c = wl.catchments[0]
+    m = orc.Model.from_workload(wl, wet_fp32=True)   # from the same float state: the float model's decisions
+    dt = 0.05                                    # shorter than Eq. 4 allows here: one step of this length
+    ens.step(T0 + dt)
+    for i in SAMPLED:
+        h, qx, qy = saved[i]
+        ref = orc.Member(h.copy(), qx.copy(), qy.copy(), t=T0, s=c.n_scale[i], mu=c.rain_mult[i])
+        orc.step(m, ref, dt)
+        gh, gqx, gqy = ens.field(i), ens.field(i, fl.FIELD_QX), ens.field(i, fl.FIELD_QY)
+        # the FP32 update h' = (h + dt/dx sum q) + rain rounds twice at the scale of h'
+        # and carries the links' FP32 rounding: 4 ulp of the depth on top of 1e-6 m
+        # (ponds here are metres deep, where one ulp is about 1e-6 m)
+        tol = 1e-6 + 4.0 * np.spacing(np.abs(ref.h).astype(np.float32)).astype(np.float64)
+        d = np.abs(gh - ref.h)
+        at = np.unravel_index(np.argmax(d - tol), d.shape)
+        print("member", i, "max |dh|", d.max(), "worst cell", at, "h", ref.h[at], "h before", h[at])
+        assert np.all(d <= tol)
+        qs = max(np.abs(ref.qx).max(), np.abs(ref.qy).max())
+        assert np.abs(gqx - ref.qx).max() <= 1e-5 * qs
+        assert np.abs(gqy - ref.qy).max() <= 1e-5 * qs
+
+
+def test_fullsize_filter_weights_and_ancestors(fl, orc, c5):
+    wl, ens, _ = c5
+    c = wl.catchments[0]
+    N = c.n_members
+    K = c.gauges.shape[0]
+    rng = np.random.default_rng(W.seed_for(5, 0, 3))
+    obs = rng.uniform(0.0, 0.05, size=K)
+    sigma = np.full(K, wl.obs_sigma)
+    y = np.array([ens.field(i)[c.gauges[:, 0], c.gauges[:, 1]] for i in range(N)])
+    logw0 = ens.weights()[0]
+    # a threshold no N_eff (>= 1) falls below: the posterior log-weights stay readable
+    neff, _, res = ens.assimilate(0, c.gauges, obs, sigma, 1e-9, 0.5, None)
+    assert not res
+    _, w_ref, neff_ref = orc.pf_weights(y, obs, sigma, logw0)
+    w_gpu = np.exp(ens.weights()[0])
+    np.testing.assert_allclose(w_gpu, w_ref, rtol=1e-12, atol=1e-300)
+    assert neff == pytest.approx(neff_ref, rel=1e-12)
+    # ancestors from identical weights
+    for u0 in (0.0, 0.37, 0.999):
+        anc = fl.flood_systematic_resample(w_gpu, u0)
+        np.testing.assert_array_equal(anc, orc.systematic(w_gpu, u0))
+
+
+def test_fullsize_adjoint_of_a_sampled_member(fl, orc, c5):
+    wl, ens, saved = c5
+    c = wl.catchments[0]
+    i = SAMPLED[1]
+    h, qx, qy = saved[i]
+    t1, sdt = T0 + 10.0, 5.0
+    K = c.gauges.shape[0]
+    obs = np.random.default_rng(W.seed_for(5, 0, 4)).uniform(0.0, 0.05, size=(2, K))
+    # one member on the full grid, tuned like the benchmark, from the GPU's own state
+    cat = dict(dem=c.dem, manning=c.manning, dx=c.dx, edge_kind=c.edge_kind, edge_slope=c.edge_slope,
+               n_members=1, n_scale=c.n_scale[i:i + 1], rain_mult=c.rain_mult[i:i + 1])
+    p = fl.FloodEnsemble([cat], wl.rain, rain_interval=wl.rain_interval, real_bytes=wl.real_bytes)
+    p.set_state(0, h, qx, qy, T0)
+    L, gn, gm = p.adjoint(0, t1, sdt, c.gauges, obs, ckpt_every=8)
+    p.close()
+    m = orc.Model.from_workload(wl)
+    mem = orc.Member(h.copy(), qx.copy(), qy.copy(), t=T0, s=c.n_scale[i], mu=c.rain_mult[i])
+    Lo, gno, gmo, _ = orc.adjoint(m, mem, t1, sdt, c.gauges, obs, ckpt_every=8)
+    assert L == pytest.approx(Lo, rel=1e-4)
+    assert gm[0] == pytest.approx(gmo, rel=1e-3)
+    assert np.linalg.norm(gn - gno) <= 1e-3 * np.linalg.norm(gno)

@@ -110,6 +110,52 @@ def test_wet_dry_threshold_is_strict(orc):
     assert mem.qx[0, 1] > 0.0
 
 
+def test_single_precision_wet_decision_at_the_float_threshold(orc):
+    # h_dry = 1e-3 is not a float; its float rounding lies above it.  A flow depth
+    # equal to that float exceeds 1e-3 (wet in double) but is not strictly above
+    # the float threshold (dry when decided in float, as a float model decides it)
+    dx, dt = 3.0, 0.05
+    hf = float(np.float32(1e-3))
+    assert hf > 1e-3
+    for wet32, expect_flow in ((False, True), (True, False)):
+        m = _model(orc, np.zeros((1, 2)), dx=dx, h_dry=1e-3, wet_fp32=wet32)
+        mem = orc.Member.dry(m, h0=np.array([[hf, 0.0]]))
+        orc.step(m, mem, dt)
+        assert (mem.qx[0, 1] > 0.0) == expect_flow
+    # the next float up is wet either way; so is an open edge's inner depth
+    up = float(np.nextafter(np.float32(hf), np.float32(1.0)))
+    m = _model(orc, np.zeros((1, 2)), dx=dx, h_dry=1e-3, wet_fp32=True)
+    mem = orc.Member.dry(m, h0=np.array([[up, 0.0]]))
+    orc.step(m, mem, dt)
+    assert mem.qx[0, 1] > 0.0
+    for h0, expect in ((hf, False), (up, True)):
+        m = _model(orc, np.zeros((1, 1)), dx=dx, h_dry=1e-3, edges=(0, 1, 0, 0), slopes=(0, 1e-3, 0, 0),
+                   wet_fp32=True)
+        mem = orc.Member.dry(m, h0=np.array([[h0]]))
+        orc.step(m, mem, dt)
+        assert (mem.qx[0, 1] > 0.0) == expect
+
+
+def test_single_precision_wet_decision_changes_nothing_where_floats_are_exact(orc):
+    # beds and depths on a 2^-10 lattice below 16 m with h_dry on the lattice: every
+    # float operation of the flow depth is exact, so deciding in float or double
+    # gives the same links and a bit-identical step
+    rng = np.random.default_rng(11)
+    ny, nx = 40, 37
+    z = rng.integers(0, 4096, size=(ny, nx)) / 1024.0
+    h0 = rng.integers(0, 3, size=(ny, nx)) / 1024.0 + rng.integers(0, 2, size=(ny, nx)) * rng.integers(
+        0, 600, size=(ny, nx)) / 1024.0
+    out = []
+    for wet32 in (False, True):
+        m = _model(orc, z, dx=3.0, h_dry=1.0 / 1024.0, edges=(1, 1, 1, 1), slopes=(1e-3,) * 4, wet_fp32=wet32)
+        mem = orc.Member.dry(m, h0=h0)
+        orc.step(m, mem, 0.02)
+        out.append((mem.h.copy(), mem.qx.copy(), mem.qy.copy()))
+    for a, b in zip(*out):
+        np.testing.assert_array_equal(a, b)
+    assert np.count_nonzero(out[0][1]) > 50     # the step moved water over many links
+
+
 def test_donor_limiter_closed_form(orc):
     # single wet cell surrounded by dry cells, long step: every link hits the
     # quarter-cell cap h dx/(4 dt) and the centre cell empties exactly
