@@ -16,6 +16,7 @@ import ctypes as C
 import os
 import subprocess
 from dataclasses import dataclass, field
+from typing import Optional
 
 import numpy as np
 
@@ -49,7 +50,7 @@ class _Member(C.Structure):
     _fields_ = [("h", C.POINTER(C.c_double)), ("qx", C.POINTER(C.c_double)), ("qy", C.POINTER(C.c_double)),
                 ("t", C.c_double), ("s", C.c_double), ("mu", C.c_double),
                 ("v_rain", C.c_double), ("v_out", C.c_double), ("v_clamp", C.c_double),
-                ("steps", C.c_int64)]
+                ("steps", C.c_int64), ("hmax", C.POINTER(C.c_double))]
 
 
 _lib = None
@@ -150,22 +151,27 @@ class Member:
     v_clamp: float = 0.0
     steps: int = 0
     dt_log: list = field(default_factory=list)
+    hmax: Optional[np.ndarray] = None     # running maximum depth, when tracked
 
     @classmethod
-    def dry(cls, model: Model, s=1.0, mu=1.0, h0=None):
+    def dry(cls, model: Model, s=1.0, mu=1.0, h0=None, track_max=False):
         h = np.zeros((model.ny, model.nx)) if h0 is None else _f64(h0).copy()
         return cls(h=h, qx=np.zeros((model.ny, model.nx + 1)), qy=np.zeros((model.ny + 1, model.nx)),
-                   s=float(s), mu=float(mu))
+                   s=float(s), mu=float(mu), hmax=h.copy() if track_max else None)
 
     def copy(self):
         return Member(self.h.copy(), self.qx.copy(), self.qy.copy(), self.t, self.s, self.mu, self.v_rain,
-                      self.v_out, self.v_clamp, self.steps, list(self.dt_log))
+                      self.v_out, self.v_clamp, self.steps, list(self.dt_log),
+                      None if self.hmax is None else self.hmax.copy())
 
     def _c(self):
         for a in (self.h, self.qx, self.qy):
             assert a.flags.c_contiguous and a.dtype == np.float64
+        if self.hmax is not None:
+            assert self.hmax.flags.c_contiguous and self.hmax.dtype == np.float64 and self.hmax.shape == self.h.shape
+        hm = _dp(self.hmax) if self.hmax is not None else C.POINTER(C.c_double)()
         return _Member(_dp(self.h), _dp(self.qx), _dp(self.qy), self.t, self.s, self.mu, self.v_rain,
-                       self.v_out, self.v_clamp, self.steps)
+                       self.v_out, self.v_clamp, self.steps, hm)
 
     def _back(self, cm):
         self.t, self.v_rain, self.v_out, self.v_clamp, self.steps = cm.t, cm.v_rain, cm.v_out, cm.v_clamp, cm.steps
@@ -327,3 +333,35 @@ def adj_step(model: Model, mem: Member, dt, lh, lqx, lqy):
     if rc:
         raise ValueError("orc_adj_step failed: %d" % rc)
     return lh, lqx, lqy, gn, gmu.value
+
+
+def ensemble_products(hmax, threshold, pcts=(), weights=None):
+    """Ensemble products of the maximum depth (Sec. 4.4, Figs. 15-16).
+
+    hmax: [N, ...] running maximum depth of each member (any cell shape after the
+    member axis).  weights: non-negative member weights (None: equal).  With
+    W = sum of the weights:
+      prob[c]   = (sum of w_m over members with hmax_m[c] >= threshold) / W
+      pct_p[c]  = min{ hmax_k[c] : sum of w_m over members with hmax_m[c] <= hmax_k[c]
+                                   >= p W }         (inverted distribution function)
+    Every weight sum runs over members in index order in FP64, as written.
+    Returns (prob, [pct for each p])."""
+    v = np.asarray(hmax, dtype=np.float64)
+    N = v.shape[0]
+    w = np.ones(N) if weights is None else np.asarray(weights, dtype=np.float64)
+    W = 0.0
+    for m in range(N):
+        W += w[m]
+    hit = np.zeros(v.shape[1:])
+    for m in range(N):
+        hit = hit + np.where(v[m] >= threshold, w[m], 0.0)
+    prob = hit / W
+    best = [np.full(v.shape[1:], np.inf) for _ in pcts]
+    for k in range(N):
+        cum = np.zeros(v.shape[1:])
+        for m in range(N):
+            cum = cum + np.where(v[m] <= v[k], w[m], 0.0)
+        for i, p in enumerate(pcts):
+            take = (cum >= p * W) & (v[k] < best[i])
+            best[i] = np.where(take, v[k], best[i])
+    return prob, best

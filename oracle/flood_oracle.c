@@ -60,6 +60,7 @@ typedef struct {
     double mu;                 /* member multiplier on the rain series */
     double v_rain, v_out, v_clamp;
     int64_t steps;
+    double* hmax;              /* optional [ny*nx]: running maximum of the depth (Sec. 4.4, Figs. 15-16) */
 } orc_member;
 
 /* ------------------------------------------------------------------------ */
@@ -255,6 +256,7 @@ static void step_core(const orc_model* m, orc_member* st, double dt, orc_scratch
             hn = 0.0;
         }
         st->h[i] = hn;
+        if (st->hmax && hn > st->hmax[i]) st->hmax[i] = hn;
     }
     st->v_rain += rain_depth * (double)nc * area;
     memcpy(st->qx, w->qxn, sizeof(double) * (size_t)(m->ny * (int64_t)(m->nx + 1)));
@@ -755,6 +757,7 @@ int orc_adjoint(const orc_model* m, orc_member* st, double t_end, double sample_
     const int32_t S = n_samples(t0, t_end, sample_dt);
     if (rc == ORC_OK) {
         orc_member tm = *st;
+        tm.hmax = NULL;    /* recomputation replays steps already taken */
         for (int64_t c = n_ckpt - 1; c >= 0; --c) {
             int64_t n0 = c * ckpt_every;
             int64_t n1 = n0 + ckpt_every;
