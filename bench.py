@@ -24,6 +24,8 @@ region:
   * batched against plain (one handle and one launch per member) on this
     workload over its first window, and on the four-catchment batch
     (512^2, 768x1536, 1024^2, 2000^2, 24 members each) over its first 300 s;
+  * the running maximum depth tracked through the first window (its cost) and
+    the ensemble products of every cell (Sec. 4.4, Figs. 15-16);
   * the streaming ceiling of one elementwise kernel (2 GiB in, 2 GiB out).
 
 The timed cycles run last among full-size launches of the step kernel, so
@@ -223,6 +225,29 @@ def leg_c4(FloodEnsemble, W, window, per_catch):
             "batched_config": conf}
 
 
+def leg_products(FloodEnsemble, wl, window):
+    """Running maximum depth tracked through the first window, then the ensemble
+    products of every cell (probability of reaching 0.2 m, 10/50/90 % maxima)."""
+    import torch
+    c = wl.catchments[0]
+    ncell = c.ny * c.nx
+    ens = FloodEnsemble.from_workload(wl, track_peak=True)
+    t0 = time.perf_counter()
+    ens.step(window)
+    t_step = time.perf_counter() - t0
+    steps = int(ens.ledger()["steps"].sum())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob, pc = ens.products(0.2, (0.1, 0.5, 0.9))
+    t_prod = time.perf_counter() - t0
+    ens.close()
+    log("products leg: %.2f s stepping with running maxima, %.3f s products" % (t_step, t_prod))
+    return {"workload": "first %.0f s of this ensemble with running maxima; products of every cell" % window,
+            "tracked_MCUps": steps * ncell / t_step, "products_s": t_prod,
+            "products": "P(max depth >= 0.2 m) and 10/50/90 %% maxima, %d cells x %d members" % (ncell, c.n_members),
+            "cells_reaching_0.2m_in_any_member": int(np.count_nonzero(prob > 0))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,6 +269,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-members", type=int, default=8)
     ap.add_argument("--no-c4", action="store_true")
+    ap.add_argument("--no-products", action="store_true")
     ap.add_argument("--c4-window", type=float, default=300.0)
     ap.add_argument("--c4-plain-members", type=int, default=2)
     ap.add_argument("--mi", type=int, default=0)
@@ -282,22 +308,28 @@ def main():
     K = c.gauges.shape[0]
     sigma = np.full(K, wl.obs_sigma)
     n_cycles = args.warmup + args.steps
-    rng = np.random.default_rng(wl.seed + 7)
     win_times = [(k + 1) * args.window for k in range(n_cycles)]
     n_adj = int(round(args.adj_window / args.adj_sample))
     adj_times = [(i + 1) * args.adj_sample for i in range(n_adj)] if not args.no_adjoint else []
     log("workload ready: %d x %d cells x %d members" % (c.ny, c.nx, N))
-    obs_all = truth_observations(FloodEnsemble, W, wl, set(win_times) | set(adj_times), rng)
+    # the filter's observations and draws have their own truth run and random stream,
+    # so the timed cycles are the same whichever other legs run
+    rng = np.random.default_rng(wl.seed + 7)
+    obs_all = truth_observations(FloodEnsemble, W, wl, win_times, rng)
     draws = [W.pf_draws(rng, N) for _ in range(n_cycles)]
+    obs_adj = (truth_observations(FloodEnsemble, W, wl, adj_times, np.random.default_rng(wl.seed + 8))
+               if adj_times else {})
     log("truth observations done")
     detail = {}
 
     # forward + adjoint first: the timed cycles below are then the last full-size step launches
     if adj_times and not args.kernel_only:
-        detail["fwd_adj"] = leg_adjoint(FloodEnsemble, wl, {t: obs_all[t] for t in adj_times},
+        detail["fwd_adj"] = leg_adjoint(FloodEnsemble, wl, obs_adj,
                                         args.adj_window, args.adj_sample, args.adj_ckpt)
     if not args.no_c4 and not args.kernel_only:
         detail["batched_vs_plain_c4"] = leg_c4(FloodEnsemble, W, args.c4_window, args.c4_plain_members)
+    if not args.no_products and not args.kernel_only:
+        detail["ensemble_products"] = leg_products(FloodEnsemble, wl, args.window)
 
     ens = FloodEnsemble.from_workload(wl, member_interleave=args.mi, tile_rows=args.rows,
                                       chunks_per_block=args.cpb, step_kernel=args.kernel,

@@ -52,6 +52,7 @@ typedef int32_t flood_status;
 #define FLOOD_FIELD_H 0
 #define FLOOD_FIELD_QX 1
 #define FLOOD_FIELD_QY 2
+#define FLOOD_FIELD_PEAK 3 /* running maximum depth (handles created with track_peak = 1) */
 
 #define FLOOD_MAX_CATCHMENTS 8
 #define FLOOD_MAX_MEMBERS 1024 /* per catchment (one workgroup runs the filter) */
@@ -88,6 +89,9 @@ typedef struct flood_params {
                                   stored in planes; 3 also needs nx a multiple of 4 (FP32) or 2 (FP64)) */
     int32_t march_rows;        /* 0: autotune; else rows per strip of the row-marching kernel, 1..4096 */
     int32_t march_members;     /* 0: autotune; else members marched together by one wavefront: 1, 2, 4, 8 */
+    int32_t track_peak;        /* 1: keep each member's running maximum depth (ensemble products, Sec. 4.4,
+                                  Figs. 15-16); costs a read and a write of one value per member-cell-step;
+                                  excludes step_kernel 2.  0: off */
 } flood_params;
 
 typedef struct flood_handle flood_handle;
@@ -155,13 +159,16 @@ flood_status flood_adjoint(flood_handle* h, int32_t catchment, double t_end, dou
                            double* loss_out, double* grad_n_out, double* grad_mult_out);
 
 /* Copy one member's field to host memory in the host layout described above
- * (H: ny*nx, QX: ny*(nx+1), QY: (ny+1)*nx), converted to double. */
+ * (H: ny*nx, QX: ny*(nx+1), QY: (ny+1)*nx, PEAK: ny*nx), converted to double.
+ * PEAK, the member's running maximum depth since creation (or its last
+ * flood_set_state), needs a handle created with track_peak = 1 (else ESTATE). */
 flood_status flood_get_field(flood_handle* h, int32_t catchment, int32_t member, int32_t which,
                              double* host_out);
 
 /* Overwrite one member's state (h: ny*nx, qx: ny*(nx+1), qy: (ny+1)*nx, all
  * host doubles, rounded to the handle's precision) and its time t.  Depths
- * must be >= 0 and finite.  Wall links must be zero. */
+ * must be >= 0 and finite.  Wall links must be zero.  A tracked running maximum
+ * restarts from the new depths. */
 flood_status flood_set_state(flood_handle* h, int32_t catchment, int32_t member, const double* hh,
                              const double* qx, const double* qy, double t);
 
@@ -187,6 +194,22 @@ flood_status flood_get_weights(flood_handle* h, int32_t catchment, double* logw,
  * using the same kernel as flood_assimilate.  anc_out host [n]. */
 flood_status flood_systematic_resample(const double* w, int32_t n, double u0, int32_t* anc_out,
                                        void* hip_stream);
+
+/* Ensemble products of the running maximum depth (Sec. 4.4, Figs. 15-16) of
+ * one catchment, per cell, with member weights w (host [N], finite, >= 0,
+ * positive sum; NULL: equal weights) and W = sum of w in member order:
+ *   prob_out[c]         = (sum of w_m over members whose maximum at c >= threshold) / W
+ *   pct_out[i*ny*nx+c]  = min over members k of their maximum v_k at c such that the
+ *                         sum of w_m over members with v_m <= v_k is >= pct[i] W
+ *                         (inverted distribution function)
+ * All sums run over members in index order in FP64.  pct host [n_pct], each
+ * in (0, 1], 0 <= n_pct <= 16; prob_out host [ny*nx] and pct_out host
+ * [n_pct*ny*nx], row-major cells, either may be NULL.  Needs track_peak = 1.
+ * Errors: EINVAL (validation, before any HIP call), ESTATE (not tracked),
+ * ENOMEM, EHIP.  Synchronises the stream. */
+flood_status flood_ensemble_products(flood_handle* h, int32_t catchment, double threshold, int32_t n_pct,
+                                     const double* pct, const double* weights, double* prob_out,
+                                     double* pct_out);
 
 /* Snapshot / restore of every member's state, time, weights, parameters and
  * ledger to a file (portable only between handles of identical shape). */

@@ -106,6 +106,7 @@ flood_status validate_params(const flood_params* p, std::string& err) {
         err = "march_members must be 0, 1, 2, 4 or 8";
         return FLOOD_EINVAL;
     }
+    if (p->track_peak != 0 && p->track_peak != 1) { err = "track_peak must be 0 or 1"; return FLOOD_EINVAL; }
     return FLOOD_OK;
 }
 
@@ -247,6 +248,12 @@ flood_status flood_systematic_resample(const double* w, int32_t n, double u0, in
     }
     if (!(tot > 0.0) || !finite_d(tot)) return FLOOD_EINVAL;
     return systematic_resample_impl(w, n, u0, anc_out, (hipStream_t)hip_stream);
+}
+
+flood_status flood_ensemble_products(flood_handle* h, int32_t catchment, double threshold, int32_t n_pct,
+                                     const double* pct, const double* weights, double* prob_out, double* pct_out) {
+    FLOOD_NEED_HANDLE(h);
+    return h->impl->products(catchment, threshold, n_pct, pct, weights, prob_out, pct_out, h->err);
 }
 
 flood_status flood_save(flood_handle* h, const char* path) {

@@ -68,6 +68,7 @@ template <typename T> struct CatchDev {
     const T* z;
     const T* n;
     double* out_acc;          // [n_members][2*(nx+ny)] outflow volume per edge link (N, S, W, E)
+    T* peak;                  // running maximum depth, state layout, one copy; null when not tracked
 };
 
 template <typename T> struct StepLaunch {
@@ -156,6 +157,10 @@ template <typename T>
 void launch_gauges(int mi, const CatchDev<T>& C, const int32_t* par, int n_gauges, const int32_t* grc,
                    double* y, hipStream_t s);
 void launch_flush_outflow(int n_members, int nb, double* out_acc, double* vout, hipStream_t s);
+// ensemble products of the running maximum depth: prob [ny*nx], pct [n_pct][ny*nx]
+template <typename T>
+void launch_products(int mi, const CatchDev<T>& C, double threshold, int n_pct, const double* pct, const double* w,
+                     double W, double* prob, double* pct_out, hipStream_t s);
 
 // adjoint (flood_adjoint.hip)
 template <typename T> struct AdjLaunch {
@@ -237,6 +242,10 @@ struct PfArgs {
     int32_t* flag;            // [1] out: 1 if resampled
 };
 void launch_pf(const PfArgs& a, hipStream_t s);
+// running maxima follow their members on resampling: gather into tmp, then commit
+template <typename T>
+void launch_permute_peak(int mi, const CatchDev<T>& C, const int32_t* anc, const int32_t* flag, T* tmp,
+                         hipStream_t s);
 void launch_systematic(int n, const double* w, double u0, int32_t* anc, hipStream_t s);
 template <typename T>
 void launch_permute(int mi, const CatchDev<T>& C, const int32_t* anc, const int32_t* src_par,

@@ -261,6 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepLaunch<T> L) {
             if (rec) L.clamp_out[idx] = clamped ? 1 : 0;
             if (hn == T(0)) hn = T(0);  // canonical +0 for the bit-pattern maximum
             C.h[dp][idx] = hn;
+            if (!rec && C.peak) C.peak[idx] = fmax(C.peak[idx], hn);
             C.qx[dp][idx] = fE;
             C.qy[dp][idx] = fS;
             if (!hasW) C.qw[dp][((size_t)k * ny + cy) * MI + lane] = fW;
@@ -442,12 +443,16 @@ template <typename T, int MI>
 __global__ __launch_bounds__(256) void k_field(const CatchDev<T> C, int m, int p, int which, double* buf,
                                                int to_state) {
     const int ny = C.ny, nx = C.nx;
-    const size_t n = which == 0 ? (size_t)ny * nx : which == 1 ? (size_t)ny * (nx + 1) : (size_t)(ny + 1) * nx;
+    const size_t n = (which == 0 || which == 3) ? (size_t)ny * nx
+                     : which == 1               ? (size_t)ny * (nx + 1)
+                                                : (size_t)(ny + 1) * nx;
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
     const int k = m / MI, lane = m % MI;
     T* ptr;
-    if (which == 0) {
+    if (which == 3) {
+        ptr = C.peak + state_index<T, MI>(C, m, (int)(e / nx), (int)(e % nx));
+    } else if (which == 0) {
         ptr = C.h[p] + state_index<T, MI>(C, m, (int)(e / nx), (int)(e % nx));
     } else if (which == 1) {
         const int r = (int)(e / (nx + 1)), c = (int)(e % (nx + 1));
@@ -466,7 +471,9 @@ template <typename T>
 static void launch_field(int mi, const CatchDev<T>& C, int member, int par, int which, double* buf, int to_state,
                          hipStream_t s) {
     const int ny = C.ny, nx = C.nx;
-    const size_t n = which == 0 ? (size_t)ny * nx : which == 1 ? (size_t)ny * (nx + 1) : (size_t)(ny + 1) * nx;
+    const size_t n = (which == 0 || which == 3) ? (size_t)ny * nx
+                     : which == 1               ? (size_t)ny * (nx + 1)
+                                                : (size_t)(ny + 1) * nx;
     dim3 grid((unsigned)((n + 255) / 256));
     switch (mi) {
         case 1: hipLaunchKernelGGL((k_field<T, 1>), grid, dim3(256), 0, s, C, member, par, which, buf, to_state); break;
@@ -698,6 +705,7 @@ __global__ __launch_bounds__(kBlock) void k_march(const StepLaunch<T> L) {
                 }
                 if (hn == T(0)) hn = T(0);
                 C.h[dp][base + c0] = hn;
+                if (C.peak) C.peak[base + c0] = fmax(C.peak[base + c0], hn);
                 C.qx[dp][base + c0] = fE;
                 C.qy[dp][base + c0] = fS;
                 if (!hasW) C.qw[dp][(size_t)k * ny + r] = fW;
@@ -942,6 +950,16 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
                     *reinterpret_cast<uint16_t*>(cl) = (uint16_t)(cf[0] | (cf[1] << 8));
                 }
             }
+            if constexpr (!REC) {
+                if (C.peak) {
+                    T* PK = C.peak + (size_t)k * plane + ca;
+                    T pk4[V];
+                    vload<T, V>(PK, pk4);
+#pragma unroll
+                    for (int j = 0; j < V; ++j) pk4[j] = fmax(pk4[j], hn4[j]);
+                    vstore<T, V>(PK, pk4);
+                }
+            }
             if (westw && xl == 0) QWo[r] = fW[0];
             if (r == 0) {
 #pragma unroll
@@ -1043,5 +1061,89 @@ template <typename T> void launch_march(const StepLaunch<T>& L, int seg, int tot
 
 template void launch_march<float>(const StepLaunch<float>&, int, int, hipStream_t);
 template void launch_march<double>(const StepLaunch<double>&, int, int, hipStream_t);
+
+
+// ---------------------------------------------------------------------------
+// Ensemble products of the running maximum depth (Sec. 4.4, Figs. 15-16).  One
+// lane per cell; a workgroup of 64 cells stages its cells' member values in
+// LDS (member-major, so the staging loads are contiguous in every member's
+// plane), then each lane forms, in member order and FP64, the weight of the
+// members at or above the threshold and, for every member k, the weight of the
+// members at or below member k's value; the smallest value whose weight
+// reaches p W is the p-quantile (inverted distribution function).
+// ---------------------------------------------------------------------------
+constexpr int kProdCells = 64;
+constexpr int kProdMaxPct = 16;
+
+template <typename T, int MI, bool LDS>
+__global__ __launch_bounds__(kProdCells) void k_products(const CatchDev<T> C, double thr, int n_pct,
+                                                         const double* __restrict__ pct,
+                                                         const double* __restrict__ w, double W,
+                                                         double* __restrict__ prob, double* __restrict__ pout) {
+    extern __shared__ unsigned char smem[];
+    T* vals = reinterpret_cast<T*>(smem);
+    const int N = C.n_members;
+    const size_t ncell = (size_t)C.ny * C.nx;
+    const size_t cell = (size_t)blockIdx.x * kProdCells + threadIdx.x;
+    const bool in = cell < ncell;
+    const int r = in ? (int)(cell / C.nx) : 0, c = in ? (int)(cell % C.nx) : 0;
+    auto value = [&](int m) -> T {
+        if constexpr (LDS) return vals[(size_t)m * kProdCells + threadIdx.x];
+        else return C.peak[state_index<T, MI>(C, m, r, c)];
+    };
+    if constexpr (LDS) {
+        for (int m = 0; m < N; ++m) vals[(size_t)m * kProdCells + threadIdx.x] = in ? C.peak[state_index<T, MI>(C, m, r, c)] : T(0);
+        __syncthreads();
+    }
+    if (!in) return;
+    double hit = 0.0;
+    for (int m = 0; m < N; ++m) hit += ((double)value(m) >= thr) ? w[m] : 0.0;
+    if (prob) prob[cell] = hit / W;
+    if (n_pct == 0 || !pout) return;
+    double best[kProdMaxPct];
+    double lim[kProdMaxPct];
+    for (int i = 0; i < n_pct; ++i) {
+        best[i] = INFINITY;
+        lim[i] = pct[i] * W;
+    }
+    for (int k = 0; k < N; ++k) {
+        const T vk = value(k);
+        double cum = 0.0;
+        for (int m = 0; m < N; ++m) cum += (value(m) <= vk) ? w[m] : 0.0;
+        for (int i = 0; i < n_pct; ++i)
+            if (cum >= lim[i] && (double)vk < best[i]) best[i] = (double)vk;
+    }
+    for (int i = 0; i < n_pct; ++i) pout[(size_t)i * ncell + cell] = best[i];
+}
+
+template <typename T, int MI>
+static void launch_products_mi(const CatchDev<T>& C, double thr, int n_pct, const double* pct, const double* w,
+                               double W, double* prob, double* pout, hipStream_t s) {
+    const size_t ncell = (size_t)C.ny * C.nx;
+    const dim3 grid((unsigned)((ncell + kProdCells - 1) / kProdCells));
+    const size_t lds = (size_t)C.n_members * kProdCells * sizeof(T);
+    if (lds <= 48 * 1024)
+        hipLaunchKernelGGL((k_products<T, MI, true>), grid, dim3(kProdCells), lds, s, C, thr, n_pct, pct, w, W, prob,
+                           pout);
+    else
+        hipLaunchKernelGGL((k_products<T, MI, false>), grid, dim3(kProdCells), 0, s, C, thr, n_pct, pct, w, W, prob,
+                           pout);
+}
+
+template <typename T>
+void launch_products(int mi, const CatchDev<T>& C, double thr, int n_pct, const double* pct, const double* w,
+                     double W, double* prob, double* pout, hipStream_t s) {
+    switch (mi) {
+        case 1: launch_products_mi<T, 1>(C, thr, n_pct, pct, w, W, prob, pout, s); break;
+        case 2: launch_products_mi<T, 2>(C, thr, n_pct, pct, w, W, prob, pout, s); break;
+        case 4: launch_products_mi<T, 4>(C, thr, n_pct, pct, w, W, prob, pout, s); break;
+        default: launch_products_mi<T, 8>(C, thr, n_pct, pct, w, W, prob, pout, s); break;
+    }
+}
+
+template void launch_products<float>(int, const CatchDev<float>&, double, int, const double*, const double*, double,
+                                     double*, double*, hipStream_t);
+template void launch_products<double>(int, const CatchDev<double>&, double, int, const double*, const double*, double,
+                                      double*, double*, hipStream_t);
 
 }  // namespace flood

@@ -206,4 +206,71 @@ template void launch_permute<float>(int, const CatchDev<float>&, const int32_t*,
 template void launch_permute<double>(int, const CatchDev<double>&, const int32_t*, const int32_t*, const int32_t*,
                                      const int32_t*, hipStream_t);
 
+
+// Running maxima follow their members on resampling.  There is one copy of
+// the array, so the slots that change are gathered into tmp first (reading only
+// the old maxima) and committed in a second pass.
+template <typename T, int MI>
+__global__ __launch_bounds__(256) void k_peak_gather(const CatchDev<T> C, const int32_t* anc, const int32_t* flag,
+                                                     T* tmp) {
+    if (flag[0] == 0) return;
+    const int k = blockIdx.y;
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t ncell = (size_t)C.ny * C.nx;
+    if (e >= ncell * MI) return;
+    const int lane = (int)(e % MI);
+    const size_t cell = e / MI;
+    const int j = k * MI + lane;
+    if (j >= C.n_members) return;
+    const int a = anc[j];
+    if (a == j) return;
+    const size_t plane = ncell * MI;
+    tmp[(size_t)k * plane + cell * MI + lane] = C.peak[(size_t)(a / MI) * plane + cell * MI + (a % MI)];
+}
+
+template <typename T, int MI>
+__global__ __launch_bounds__(256) void k_peak_commit(const CatchDev<T> C, const int32_t* anc, const int32_t* flag,
+                                                     const T* tmp) {
+    if (flag[0] == 0) return;
+    const int k = blockIdx.y;
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t ncell = (size_t)C.ny * C.nx;
+    if (e >= ncell * MI) return;
+    const int lane = (int)(e % MI);
+    const int j = k * MI + lane;
+    if (j >= C.n_members || anc[j] == j) return;
+    const size_t i = (size_t)k * ncell * MI + (e / MI) * MI + lane;
+    C.peak[i] = tmp[i];
+}
+
+template <typename T>
+void launch_permute_peak(int mi, const CatchDev<T>& C, const int32_t* anc, const int32_t* flag, T* tmp,
+                         hipStream_t s) {
+    const size_t ncell = (size_t)C.ny * C.nx;
+    dim3 grid((unsigned)((ncell * mi + 255) / 256), C.n_chunks);
+    switch (mi) {
+        case 1:
+            hipLaunchKernelGGL((k_peak_gather<T, 1>), grid, dim3(256), 0, s, C, anc, flag, tmp);
+            hipLaunchKernelGGL((k_peak_commit<T, 1>), grid, dim3(256), 0, s, C, anc, flag, tmp);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_peak_gather<T, 2>), grid, dim3(256), 0, s, C, anc, flag, tmp);
+            hipLaunchKernelGGL((k_peak_commit<T, 2>), grid, dim3(256), 0, s, C, anc, flag, tmp);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_peak_gather<T, 4>), grid, dim3(256), 0, s, C, anc, flag, tmp);
+            hipLaunchKernelGGL((k_peak_commit<T, 4>), grid, dim3(256), 0, s, C, anc, flag, tmp);
+            break;
+        default:
+            hipLaunchKernelGGL((k_peak_gather<T, 8>), grid, dim3(256), 0, s, C, anc, flag, tmp);
+            hipLaunchKernelGGL((k_peak_commit<T, 8>), grid, dim3(256), 0, s, C, anc, flag, tmp);
+            break;
+    }
+}
+
+template void launch_permute_peak<float>(int, const CatchDev<float>&, const int32_t*, const int32_t*, float*,
+                                         hipStream_t);
+template void launch_permute_peak<double>(int, const CatchDev<double>&, const int32_t*, const int32_t*, double*,
+                                          hipStream_t);
+
 }  // namespace flood

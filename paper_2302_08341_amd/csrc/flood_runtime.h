@@ -29,6 +29,8 @@ struct ImplBase {
                                     double* t, int64_t* steps, std::string& err) = 0;
     virtual flood_status get_weights(int c, double* logw, double* rain_mult, double* n_scale,
                                      std::string& err) = 0;
+    virtual flood_status products(int c, double threshold, int n_pct, const double* pct, const double* weights,
+                                  double* prob_out, double* pct_out, std::string& err) = 0;
     virtual flood_status save(const char* path, std::string& err) = 0;
     virtual flood_status load(const char* path, std::string& err) = 0;
     virtual void get_config(int32_t* mi, int32_t* tile_rows, int32_t* cpb, int32_t* gsteps, int32_t* step_kernel,

@@ -45,6 +45,7 @@ template <typename T> struct Impl : ImplBase {
         double edge_slope[4] = {0, 0, 0, 0};
         CatchDev<T> dev{};
         size_t state_elems = 0, strip_w = 0, strip_n = 0;
+        T* peak_tmp = nullptr;    // resampling scratch of the running maximum
     };
 
     hipStream_t st = nullptr;
@@ -305,6 +306,13 @@ template <typename T> struct Impl : ImplBase {
             }
             d.z = zz;
             d.n = nn;
+            if (c.p.track_peak) {
+                CHK(dalloc(&d.peak, c.state_elems, err));
+                CHK(dalloc(&c.peak_tmp, c.state_elems, err));
+                HIPCHK(hipMemsetAsync(d.peak, 0, c.state_elems * sizeof(T), st));
+            } else {
+                d.peak = nullptr;
+            }
             const int nb = 2 * (c.nx + c.ny);
             CHK(dalloc(&d.out_acc, (size_t)c.N * nb, err));
             HIPCHK(hipMemsetAsync(d.out_acc, 0, (size_t)c.N * nb * sizeof(double), st));
@@ -381,7 +389,10 @@ template <typename T> struct Impl : ImplBase {
             std::vector<double> h0(ncell);
             for (size_t j = 0; j < ncell; ++j) h0[j] = (double)grids[i].h0[j];
             HIPCHK(hipMemcpyAsync(d_stage, h0.data(), ncell * sizeof(double), hipMemcpyHostToDevice, st));
-            for (int m = 0; m < c.N; ++m) launch_set_field<T>(mi, c.dev, m, 0, FLOOD_FIELD_H, d_stage, st);
+            for (int m = 0; m < c.N; ++m) {
+                launch_set_field<T>(mi, c.dev, m, 0, FLOOD_FIELD_H, d_stage, st);
+                if (c.dev.peak) launch_set_field<T>(mi, c.dev, m, 0, FLOOD_FIELD_PEAK, d_stage, st);
+            }
             HIPCHK(hipStreamSynchronize(st));
         }
 
@@ -493,6 +504,12 @@ template <typename T> struct Impl : ImplBase {
             acc_saved[i].resize(n);
             HIPCHK(hipMemcpy(acc_saved[i].data(), cats[i].dev.out_acc, n * sizeof(double), hipMemcpyDeviceToHost));
         }
+        // trial launches must not touch the running maxima
+        std::vector<T*> peaks(n_catch);
+        for (int i = 0; i < n_catch; ++i) {
+            peaks[i] = cats[i].dev.peak;
+            cats[i].dev.peak = nullptr;
+        }
         hipEvent_t a, b;
         HIPCHK(hipEventCreate(&a));
         HIPCHK(hipEventCreate(&b));
@@ -574,6 +591,7 @@ template <typename T> struct Impl : ImplBase {
         }
         (void)hipEventDestroy(a);
         (void)hipEventDestroy(b);
+        for (int i = 0; i < n_catch; ++i) cats[i].dev.peak = peaks[i];
         variant = bc.variant;
         march_seg = bc.seg;
         march_order = bc.order;
@@ -805,6 +823,7 @@ template <typename T> struct Impl : ImplBase {
         a.flag = d_flag;
         launch_pf(a, st);
         launch_permute<T>(mi, C.dev, d_anc, d_src, d_dst, d_flag, st);
+        if (C.dev.peak) launch_permute_peak<T>(mi, C.dev, d_anc, d_flag, C.peak_tmp, st);
         launch_permute_bins<HB>(off, C.N, n_total, hbins, d_anc, d_flag, st);
         HIPCHK(hipGetLastError());
         double hn = 0;
@@ -834,16 +853,21 @@ template <typename T> struct Impl : ImplBase {
     }
 
     static size_t field_size(const Cat& C, int which) {
-        return which == FLOOD_FIELD_H ? (size_t)C.ny * C.nx
-                                      : which == FLOOD_FIELD_QX ? (size_t)C.ny * (C.nx + 1) : (size_t)(C.ny + 1) * C.nx;
+        return (which == FLOOD_FIELD_H || which == FLOOD_FIELD_PEAK) ? (size_t)C.ny * C.nx
+               : which == FLOOD_FIELD_QX                             ? (size_t)C.ny * (C.nx + 1)
+                                                                     : (size_t)(C.ny + 1) * C.nx;
     }
 
     flood_status get_field(int c, int m, int which, double* out, std::string& err) override {
         CHK(check_catch(c, err));
         const Cat& C = cats[c];
         if (m < 0 || m >= C.N) { err = "member index out of range"; return FLOOD_EINVAL; }
-        if (which < 0 || which > 2) { err = "which must be H, QX or QY"; return FLOOD_EINVAL; }
+        if (which < 0 || which > 3) { err = "which must be H, QX, QY or PEAK"; return FLOOD_EINVAL; }
         if (!out) { err = "host_out is NULL"; return FLOOD_EINVAL; }
+        if (which == FLOOD_FIELD_PEAK && !C.dev.peak) {
+            err = "the running maximum is kept only by handles created with track_peak = 1";
+            return FLOOD_ESTATE;
+        }
         int p;
         CHK(member_parity(C.dev.member_off + m, &p, err));
         launch_get_field<T>(mi, C.dev, m, p, which, d_stage, st);
@@ -890,6 +914,7 @@ template <typename T> struct Impl : ImplBase {
         for (int w = 0; w < 3; ++w) {
             HIPCHK(hipMemcpyAsync(d_stage, src[w], field_size(C, w) * sizeof(double), hipMemcpyHostToDevice, st));
             launch_set_field<T>(mi, C.dev, m, p, w, d_stage, st);
+            if (w == FLOOD_FIELD_H && C.dev.peak) launch_set_field<T>(mi, C.dev, m, p, FLOOD_FIELD_PEAK, d_stage, st);
             HIPCHK(hipStreamSynchronize(st));
         }
         HIPCHK(hipMemcpy(t + g, &tt, sizeof(double), hipMemcpyHostToDevice));
@@ -973,6 +998,7 @@ template <typename T> struct Impl : ImplBase {
             }
             v.push_back({const_cast<T*>(C.dev.n), (size_t)C.ny * C.nx * sizeof(T)});
             v.push_back({C.dev.out_acc, (size_t)C.N * 2 * (C.nx + C.ny) * sizeof(double)});
+            if (C.dev.peak) v.push_back({C.dev.peak, C.state_elems * sizeof(T)});
         }
         const size_t n = n_total;
         v.push_back({t, n * 8});
@@ -995,7 +1021,69 @@ template <typename T> struct Impl : ImplBase {
             hd.push_back(C.ny);
             hd.push_back(C.nx);
             hd.push_back(C.N);
+            hd.push_back(C.dev.peak ? 1 : 0);
         }
+    }
+
+    // ensemble products of the running maximum depth (Sec. 4.4, Figs. 15-16)
+    flood_status products(int c, double threshold, int n_pct, const double* pct, const double* weights,
+                          double* prob_out, double* pct_out, std::string& err) override {
+        CHK(check_catch(c, err));
+        const Cat& C = cats[c];
+        if (!finite_d(threshold)) { err = "threshold must be finite"; return FLOOD_EINVAL; }
+        if (n_pct < 0 || n_pct > 16) { err = "n_pct must be in [0, 16]"; return FLOOD_EINVAL; }
+        if (n_pct > 0 && !pct) { err = "pct is NULL"; return FLOOD_EINVAL; }
+        for (int i = 0; i < n_pct; ++i)
+            if (!(pct[i] > 0.0 && pct[i] <= 1.0)) { err = "percentiles must be in (0, 1]"; return FLOOD_EINVAL; }
+        std::vector<double> w(C.N, 1.0);
+        double W = 0.0;
+        if (weights)
+            for (int m = 0; m < C.N; ++m) {
+                if (!(weights[m] >= 0.0) || !finite_d(weights[m])) {
+                    err = "weights must be finite and >= 0";
+                    return FLOOD_EINVAL;
+                }
+                w[m] = weights[m];
+            }
+        for (int m = 0; m < C.N; ++m) W += w[m];   // member order, as the kernel's sums
+        if (!(W > 0.0) || !finite_d(W)) { err = "weights must have a positive finite sum"; return FLOOD_EINVAL; }
+        if (!C.dev.peak) {
+            err = "the running maximum is kept only by handles created with track_peak = 1";
+            return FLOOD_ESTATE;
+        }
+        const size_t ncell = (size_t)C.ny * C.nx;
+        std::vector<void*> tmp;
+        struct Guard {
+            std::vector<void*>& v;
+            hipStream_t s;
+            ~Guard() {
+                (void)hipStreamSynchronize(s);
+                for (void* p : v) (void)hipFree(p);
+            }
+        } guard{tmp, st};
+        auto talloc = [&](size_t bytes, void** p) -> flood_status {
+            if (hipMalloc(p, std::max<size_t>(bytes, 16)) != hipSuccess) {
+                (void)hipGetLastError();
+                err = "hipMalloc failed in flood_ensemble_products";
+                return FLOOD_ENOMEM;
+            }
+            tmp.push_back(*p);
+            return FLOOD_OK;
+        };
+        double *d_w, *d_p, *d_prob = nullptr, *d_out = nullptr;
+        CHK(talloc(C.N * sizeof(double), (void**)&d_w));
+        CHK(talloc(16 * sizeof(double), (void**)&d_p));
+        if (prob_out) CHK(talloc(ncell * sizeof(double), (void**)&d_prob));
+        if (pct_out && n_pct > 0) CHK(talloc((size_t)n_pct * ncell * sizeof(double), (void**)&d_out));
+        HIPCHK(hipMemcpyAsync(d_w, w.data(), C.N * sizeof(double), hipMemcpyHostToDevice, st));
+        if (n_pct > 0) HIPCHK(hipMemcpyAsync(d_p, pct, n_pct * sizeof(double), hipMemcpyHostToDevice, st));
+        launch_products<T>(mi, C.dev, threshold, d_out ? n_pct : 0, d_p, d_w, W, d_prob, d_out, st);
+        HIPCHK(hipGetLastError());
+        if (d_prob) HIPCHK(hipMemcpyAsync(prob_out, d_prob, ncell * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (d_out)
+            HIPCHK(hipMemcpyAsync(pct_out, d_out, (size_t)n_pct * ncell * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return FLOOD_OK;
     }
 
     flood_status save(const char* path, std::string& err) override {
@@ -1100,6 +1188,7 @@ template <typename T>
 static CatchDev<T> group_view(const CatchDev<T>& C, int mi, int g0, int G, T* const h[2], T* const qx[2],
                               T* const qy[2], T* const qw[2], T* const qn[2]) {
     CatchDev<T> v = C;
+    v.peak = nullptr;   // tape, checkpoint and adjoint views; the recorded forward sets its own
     const int txc = std::max(1, kBlock / (mi * kAdjTileRows));
     int l = 0;
     while ((1 << l) < txc) ++l;
@@ -1287,6 +1376,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
         T* mqn[2] = {atn(C.dev.qn[0]), atn(C.dev.qn[1])};
         CatchDev<T> V = group_view(C.dev, mi, g0, Gg, mh, mqx, mqy, mqw, mqn);
         V.out_acc = C.dev.out_acc + (size_t)g0 * 2 * (C.nx + C.ny);
+        V.peak = C.dev.peak ? at(C.dev.peak) : nullptr;   // the recorded forward advances the members
         // slot j of the tape as a view (copy 0 = slot j, copy 1 = slot j + 1)
         auto slot_view = [&](T* base, int j) {
             T* sh[2];

@@ -19,11 +19,12 @@ LIB_PATH = os.path.join(HERE, "libflood.so")
 
 FLOOD_OK, FLOOD_EINVAL, FLOOD_ENOMEM, FLOOD_EHIP, FLOOD_ESTATE, FLOOD_ENUMERIC = 0, -1, -2, -3, -4, -5
 EDGE_WALL, EDGE_OPEN = 0, 1
-FIELD_H, FIELD_QX, FIELD_QY = 0, 1, 2
+FIELD_H, FIELD_QX, FIELD_QY, FIELD_PEAK = 0, 1, 2, 3
 EXPORTED = ["flood_create", "flood_create_batch", "flood_step", "flood_assimilate", "flood_adjoint",
             "flood_get_field", "flood_set_state", "flood_set_params", "flood_get_ledger", "flood_get_weights",
-            "flood_systematic_resample", "flood_save", "flood_load", "flood_get_config", "flood_timing",
-            "flood_get_timing", "flood_last_error", "flood_strerror", "flood_destroy"]
+            "flood_systematic_resample", "flood_ensemble_products", "flood_save", "flood_load",
+            "flood_get_config", "flood_timing", "flood_get_timing", "flood_last_error", "flood_strerror",
+            "flood_destroy"]
 
 
 class FloodError(RuntimeError):
@@ -47,7 +48,8 @@ class FloodParams(C.Structure):
                 ("cfl_alpha", C.c_double), ("h_dry", C.c_double), ("dt_cap", C.c_double),
                 ("dt_fixed", C.c_double), ("g", C.c_double), ("real_bytes", C.c_int32),
                 ("member_interleave", C.c_int32), ("tile_rows", C.c_int32), ("chunks_per_block", C.c_int32),
-                ("step_kernel", C.c_int32), ("march_rows", C.c_int32), ("march_members", C.c_int32)]
+                ("step_kernel", C.c_int32), ("march_rows", C.c_int32), ("march_members", C.c_int32),
+                ("track_peak", C.c_int32)]
 
 
 _lib = None
@@ -78,6 +80,7 @@ def load_library():
         "flood_get_ledger": [H, C.c_int32, dp, dp, dp, dp, dp, lp],
         "flood_get_weights": [H, C.c_int32, dp, dp, dp],
         "flood_systematic_resample": [dp, C.c_int32, C.c_double, ip, C.c_void_p],
+        "flood_ensemble_products": [H, C.c_int32, C.c_double, C.c_int32, dp, dp, dp, dp],
         "flood_save": [H, C.c_char_p],
         "flood_load": [H, C.c_char_p],
         "flood_get_config": [H, ip, ip, ip, ip, ip, ip, ip],
@@ -149,12 +152,12 @@ def make_grid(dem, manning, dx, edge_kind=(0, 0, 0, 0), edge_slope=(0, 0, 0, 0),
 
 def make_params(rain, rain_interval=300.0, cfl_alpha=0.7, h_dry=1e-3, dt_cap=10.0, dt_fixed=0.0, g=9.81,
                 real_bytes=4, member_interleave=0, tile_rows=0, chunks_per_block=0, step_kernel=0, march_rows=0,
-                march_members=0):
+                march_members=0, track_peak=0):
     rain = _f64(np.asarray(rain, dtype=np.float64).ravel())
     p = FloodParams(_dp(rain) if rain.size else None, int(rain.size), float(rain_interval), float(cfl_alpha),
                     float(h_dry), float(dt_cap), float(dt_fixed), float(g), int(real_bytes),
                     int(member_interleave), int(tile_rows), int(chunks_per_block), int(step_kernel),
-                    int(march_rows), int(march_members))
+                    int(march_rows), int(march_members), int(bool(track_peak)))
     p._keep = (rain,)
     return p
 
@@ -218,6 +221,19 @@ def flood_get_field(h, catchment, member, which, shape):
     out = np.zeros(shape, dtype=np.float64)
     _check(load_library().flood_get_field(h, int(catchment), int(member), int(which), _dp(out)), h)
     return out
+
+
+def flood_ensemble_products(h, catchment, threshold, pct, weights, ny, nx, n_members):
+    pct = _f64(np.asarray(pct, dtype=np.float64).ravel())
+    w = None if weights is None else _f64(weights)
+    if w is not None and w.size != n_members:
+        raise ValueError("weights must have one entry per member")
+    prob = np.zeros(ny * nx)
+    out = np.zeros(max(pct.size, 1) * ny * nx)
+    _check(load_library().flood_ensemble_products(h, int(catchment), float(threshold), int(pct.size),
+                                                  _dp(pct) if pct.size else None,
+                                                  _dp(w) if w is not None else None, _dp(prob), _dp(out)), h)
+    return prob.reshape(ny, nx), out[:pct.size * ny * nx].reshape(pct.size, ny, nx)
 
 
 def flood_set_state(h, catchment, member, hh, qx, qy, t):
@@ -294,7 +310,7 @@ class FloodEnsemble:
 
     def __init__(self, catchments, rain, rain_interval=300.0, cfl_alpha=0.7, h_dry=1e-3, dt_cap=10.0,
                  dt_fixed=0.0, g=9.81, real_bytes=4, member_interleave=0, tile_rows=0, chunks_per_block=0,
-                 step_kernel=0, march_rows=0, march_members=0, stream="torch"):
+                 step_kernel=0, march_rows=0, march_members=0, track_peak=False, stream="torch"):
         self.catchments = list(catchments)
         grids, params = [], []
         for c in self.catchments:
@@ -302,7 +318,7 @@ class FloodEnsemble:
                                    c.get("edge_slope", (0, 0, 0, 0)), c.get("h0")))
             params.append(make_params(rain, rain_interval, cfl_alpha, h_dry, dt_cap, dt_fixed, g, real_bytes,
                                       member_interleave, tile_rows, chunks_per_block, step_kernel, march_rows,
-                                      march_members))
+                                      march_members, track_peak))
         self._keep = (grids, params)
         self.stream = current_stream() if stream == "torch" else stream
         self.h = flood_create_batch(grids, params, [c["n_members"] for c in self.catchments],
@@ -344,8 +360,15 @@ class FloodEnsemble:
 
     def field(self, member, which=FIELD_H, catchment=0):
         ny, nx = self.shape(catchment)
-        shape = {FIELD_H: (ny, nx), FIELD_QX: (ny, nx + 1), FIELD_QY: (ny + 1, nx)}[which]
+        shape = {FIELD_H: (ny, nx), FIELD_QX: (ny, nx + 1), FIELD_QY: (ny + 1, nx), FIELD_PEAK: (ny, nx)}[which]
         return flood_get_field(self.h, catchment, member, which, shape)
+
+    def products(self, threshold, pct=(), weights=None, catchment=0):
+        """(probability map [ny, nx], percentile maps [len(pct), ny, nx]) of the running
+        maximum depth; needs track_peak=True."""
+        ny, nx = self.shape(catchment)
+        return flood_ensemble_products(self.h, catchment, threshold, pct, weights, ny, nx,
+                                       self.n_members(catchment))
 
     def set_state(self, member, h, qx, qy, t, catchment=0):
         flood_set_state(self.h, catchment, member, h, qx, qy, t)

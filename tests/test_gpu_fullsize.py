@@ -139,3 +139,24 @@ def test_fullsize_adjoint_of_a_sampled_member(fl, orc, c5):
     assert L == pytest.approx(Lo, rel=1e-4)
     assert gm[0] == pytest.approx(gmo, rel=1e-3)
     assert np.linalg.norm(gn - gno) <= 1e-3 * np.linalg.norm(gno)
+
+
+def test_fullsize_ensemble_products_on_sampled_cells(fl, orc):
+    # the benchmark ensemble with running maxima, first 900 s; products of every
+    # cell on the GPU, the oracle on a sample of cells from the same maxima
+    wl = W.config5()
+    c = wl.catchments[0]
+    ens = fl.FloodEnsemble.from_workload(wl, track_peak=True)
+    ens.step(900.0)
+    pct = (0.1, 0.5, 0.9)
+    prob, pc = ens.products(0.2, pct)
+    rng = np.random.default_rng(W.seed_for(5, 0, 5))
+    cells = rng.choice(c.ny * c.nx, size=4000, replace=False)
+    peaks = np.array([ens.field(i, fl.FIELD_PEAK).ravel()[cells] for i in range(c.n_members)])
+    w = np.exp(ens.weights()[0])
+    rp, rpc = orc.ensemble_products(peaks, 0.2, pct)
+    np.testing.assert_array_equal(prob.ravel()[cells], rp)
+    for i in range(len(pct)):
+        np.testing.assert_array_equal(pc[i].ravel()[cells], rpc[i])
+    assert np.all(w == w[0])          # equal weights before any filter update
+    ens.close()

@@ -1,0 +1,142 @@
+"""GPU running maximum depth and ensemble products (Sec. 4.4, Figs. 15-16)
+against the oracle, through the C ABI.
+
+Bars: the running maximum follows the depth's bars (FP64 1e-9 m over the run,
+FP32 1e-4 m), is bit-identical across step kernels and unaffected by tracking;
+it follows its member through resampling, set_state and save/load exactly.
+Products from the same maxima and weights are bit-exact (the same FP64 sums in
+member order on both sides; percentiles are members' values).
+"""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2302_08341_amd import flood
+    flood.load_library()
+    return flood
+
+
+CAT = W.urban_catchment("pk", 45, 64, 5, W.seed_for(2, 21), n_gauges=4)   # nx % 4 == 0
+RAIN = W.chicago_hyetograph()
+
+
+def _ens(fl, n=5, **kw):
+    c = CAT
+    cat = dict(dem=c.dem, manning=c.manning, dx=c.dx, edge_kind=c.edge_kind, edge_slope=c.edge_slope,
+               n_members=n, n_scale=c.n_scale[:n], rain_mult=c.rain_mult[:n])
+    return fl.FloodEnsemble([cat], RAIN, **kw)
+
+
+def _oracle_peaks(orc, t_end, n=5):
+    c = CAT
+    m = orc.Model(c.dem, c.manning, c.dx, RAIN, edge_kind=c.edge_kind, edge_slope=c.edge_slope)
+    out = []
+    for i in range(n):
+        mem = orc.Member.dry(m, s=c.n_scale[i], mu=c.rain_mult[i], track_max=True)
+        orc.advance(m, mem, t_end)
+        out.append(mem.hmax)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("rb,tol", [(8, 1e-9), (4, 1e-4)])
+def test_running_maximum_matches_oracle(fl, orc, rb, tol):
+    e = _ens(fl, real_bytes=rb, track_peak=True)
+    e.step(1500.0)
+    ref = _oracle_peaks(orc, 1500.0)
+    for i in range(5):
+        got = e.field(i, fl.FIELD_PEAK)
+        assert np.abs(got - ref[i]).max() <= tol
+        assert np.all(got >= e.field(i))
+    assert np.any(ref > 0.05)
+
+
+@pytest.mark.parametrize("sk,mi", [(1, 1), (1, 4), (2, 1), (3, 1)])
+def test_running_maximum_is_bit_exact_across_kernels_and_free_of_side_effects(fl, sk, mi):
+    ref = _ens(fl, real_bytes=4, member_interleave=1, tile_rows=4, chunks_per_block=5, step_kernel=1,
+               track_peak=True)
+    ref.step(1300.0)
+    e = _ens(fl, real_bytes=4, member_interleave=mi, step_kernel=sk, track_peak=True)
+    e.step(1300.0)
+    plain = _ens(fl, real_bytes=4, member_interleave=mi, step_kernel=sk)
+    plain.step(1300.0)
+    for i in range(5):
+        np.testing.assert_array_equal(e.field(i, fl.FIELD_PEAK), ref.field(i, fl.FIELD_PEAK))
+        np.testing.assert_array_equal(e.field(i), plain.field(i))
+    with pytest.raises(fl.FloodError):
+        plain.field(0, fl.FIELD_PEAK)
+
+
+def test_running_maximum_follows_resampling_set_state_and_snapshots(fl):
+    e = _ens(fl, real_bytes=4, track_peak=True)
+    e.step(1200.0)
+    before = np.array([e.field(i, fl.FIELD_PEAK) for i in range(5)])
+    obs = e.field(3)[CAT.gauges[:, 0], CAT.gauges[:, 1]]
+    neff, anc, res = e.assimilate(0, CAT.gauges, obs, np.full(4, 1e-5), 1.0, 0.3)
+    assert res and len(set(anc.tolist())) < 5
+    for j in range(5):
+        np.testing.assert_array_equal(e.field(j, fl.FIELD_PEAK), before[anc[j]])
+    path = os.path.join(tempfile.mkdtemp(), "snap.bin")
+    e.save(path)
+    e.step(1500.0)
+    moved = e.field(0, fl.FIELD_PEAK)
+    e.load(path)
+    np.testing.assert_array_equal(e.field(0, fl.FIELD_PEAK), before[anc[0]])
+    assert not np.array_equal(moved, before[anc[0]])
+    h = e.field(2) * 0.5
+    e.set_state(2, h, e.field(2, fl.FIELD_QX), e.field(2, fl.FIELD_QY), 1200.0)
+    np.testing.assert_array_equal(e.field(2, fl.FIELD_PEAK), h.astype(np.float32).astype(np.float64))
+
+
+def test_recorded_adjoint_forward_advances_the_running_maximum(fl):
+    obs = np.zeros((3, 4))
+    a = _ens(fl, real_bytes=4, track_peak=True, step_kernel=3)
+    a.step(1200.0)
+    a.adjoint(0, 1230.0, 10.0, CAT.gauges, obs, ckpt_every=7)
+    b = _ens(fl, real_bytes=4, track_peak=True, step_kernel=3)
+    for t in (1200.0, 1210.0, 1220.0, 1230.0):     # the recorded forward ends a step at every sample time
+        b.step(t)
+    for i in range(5):
+        np.testing.assert_array_equal(a.field(i, fl.FIELD_PEAK), b.field(i, fl.FIELD_PEAK))
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_products_match_oracle(fl, orc, weighted):
+    e = _ens(fl, real_bytes=4, track_peak=True)
+    e.step(1800.0)
+    peaks = np.array([e.field(i, fl.FIELD_PEAK) for i in range(5)])
+    w = np.random.default_rng(5).uniform(0.0, 2.0, size=5) if weighted else None
+    if weighted:
+        w[1] = 0.0
+    pct = (0.1, 0.5, 0.9, 1.0)
+    prob, pc = e.products(0.05, pct, weights=w)
+    rp, rpc = orc.ensemble_products(peaks, 0.05, pct, weights=w)
+    np.testing.assert_array_equal(prob, rp)
+    for i in range(len(pct)):
+        np.testing.assert_array_equal(pc[i], rpc[i])
+    assert 0.0 < prob.mean() < 1.0
+    np.testing.assert_array_equal(pc[-1], peaks.max(axis=0) if not weighted else rpc[-1])
+
+
+def test_products_validation(fl):
+    e = _ens(fl, real_bytes=4)
+    with pytest.raises(fl.FloodError) as ex:
+        e.products(0.2, (0.5,))
+    assert ex.value.status == fl.FLOOD_ESTATE
+    t = _ens(fl, real_bytes=4, track_peak=True)
+    for bad in (dict(pct=(0.0,)), dict(pct=(1.5,)), dict(pct=tuple([0.5] * 17)),
+                dict(weights=np.zeros(5)), dict(weights=-np.ones(5))):
+        with pytest.raises(fl.FloodError) as ex:
+            t.products(0.2, **bad)
+        assert ex.value.status == fl.FLOOD_EINVAL
