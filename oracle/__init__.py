@@ -43,14 +43,17 @@ class _Model(C.Structure):
                 ("edge_kind", C.c_int32 * 4), ("edge_slope", C.c_double * 4),
                 ("rain", C.POINTER(C.c_double)), ("n_rain", C.c_int32), ("rain_interval", C.c_double),
                 ("alpha", C.c_double), ("h_dry", C.c_double), ("dt_cap", C.c_double),
-                ("dt_fixed", C.c_double), ("g", C.c_double), ("wet_fp32", C.c_int32)]
+                ("dt_fixed", C.c_double), ("g", C.c_double), ("wet_fp32", C.c_int32),
+                ("cls", C.POINTER(C.c_uint8)), ("n_classes", C.c_int32),
+                ("class_runoff", C.POINTER(C.c_double)), ("class_drain", C.POINTER(C.c_int32))]
 
 
 class _Member(C.Structure):
     _fields_ = [("h", C.POINTER(C.c_double)), ("qx", C.POINTER(C.c_double)), ("qy", C.POINTER(C.c_double)),
                 ("t", C.c_double), ("s", C.c_double), ("mu", C.c_double),
                 ("v_rain", C.c_double), ("v_out", C.c_double), ("v_clamp", C.c_double),
-                ("steps", C.c_int64), ("hmax", C.POINTER(C.c_double))]
+                ("steps", C.c_int64), ("hmax", C.POINTER(C.c_double)),
+                ("class_n", C.POINTER(C.c_double)), ("drain_rate", C.c_double), ("v_drain", C.c_double)]
 
 
 _lib = None
@@ -102,10 +105,16 @@ class Model:
 
     def __init__(self, dem, manning, dx, rain, rain_interval=300.0, edge_kind=(0, 0, 0, 0),
                  edge_slope=(0.0, 0.0, 0.0, 0.0), alpha=0.7, h_dry=1e-3, dt_cap=10.0, dt_fixed=0.0, g=9.81,
-                 wet_fp32=False):
+                 wet_fp32=False, land_class=None, class_runoff=None, class_drain=None):
         """wet_fp32: take each link's wet/dry decision in single precision (flow depth
         in difference form, rounded to float, against h_dry rounded to float), as a
-        single-precision model does; for comparisons from the same float state."""
+        single-precision model does; for comparisons from the same float state.
+
+        land_class [ny, nx] (uint8 < n_classes), class_runoff [n_classes] and
+        class_drain [n_classes] switch on land cover (Sec. 4.1, Table 1): each member
+        then carries its own Manning n per class and a drainage rate (Member.class_n,
+        Member.drain_rate), rain is scaled by the cell's runoff coefficient, and
+        draining classes lose water at the member's rate, up to what they hold."""
         self.z = _f64(dem)
         self.n = _f64(manning)
         self.ny, self.nx = self.z.shape
@@ -116,10 +125,24 @@ class Model:
             n_rain = 0
         else:
             n_rain = self.rain.size
+        if land_class is not None:
+            self.cls = np.ascontiguousarray(np.asarray(land_class, dtype=np.uint8))
+            assert self.cls.shape == self.z.shape
+            self.class_runoff = _f64(class_runoff).ravel()
+            self.class_drain = np.ascontiguousarray(np.asarray(class_drain, dtype=np.int32).ravel())
+            self.n_classes = self.class_runoff.size
+            assert self.class_drain.size == self.n_classes and int(self.cls.max()) < self.n_classes
+            cls_p = self.cls.ctypes.data_as(C.POINTER(C.c_uint8))
+            rc_p, dr_p = _dp(self.class_runoff), self.class_drain.ctypes.data_as(C.POINTER(C.c_int32))
+        else:
+            self.cls = None
+            self.n_classes = 0
+            cls_p, rc_p, dr_p = C.POINTER(C.c_uint8)(), C.POINTER(C.c_double)(), C.POINTER(C.c_int32)()
         self._m = _Model(self.ny, self.nx, self.dx, _dp(self.z), _dp(self.n),
                          (C.c_int32 * 4)(*edge_kind), (C.c_double * 4)(*edge_slope),
                          _dp(self.rain), n_rain, float(rain_interval), float(alpha), float(h_dry),
-                         float(dt_cap), float(dt_fixed), float(g), int(bool(wet_fp32)))
+                         float(dt_cap), float(dt_fixed), float(g), int(bool(wet_fp32)),
+                         cls_p, int(self.n_classes), rc_p, dr_p)
         self.edge_kind = tuple(edge_kind)
         self.edge_slope = tuple(edge_slope)
         self.h_dry = h_dry
@@ -130,6 +153,8 @@ class Model:
         c = wl.catchments[catchment]
         kw = dict(rain_interval=wl.rain_interval, edge_kind=c.edge_kind, edge_slope=c.edge_slope,
                   alpha=wl.cfl_alpha, h_dry=wl.h_dry, dt_cap=wl.dt_cap, dt_fixed=wl.dt_fixed, g=wl.g)
+        if getattr(c, "land_class", None) is not None:
+            kw.update(land_class=c.land_class, class_runoff=c.class_runoff, class_drain=c.class_drain)
         kw.update(over)
         return cls(c.dem, c.manning, c.dx, wl.rain, **kw)
 
@@ -152,17 +177,23 @@ class Member:
     steps: int = 0
     dt_log: list = field(default_factory=list)
     hmax: Optional[np.ndarray] = None     # running maximum depth, when tracked
+    class_n: Optional[np.ndarray] = None  # land cover: this member's Manning n per class
+    drain_rate: float = 0.0               # land cover: drainage rate, m/s
+    v_drain: float = 0.0
 
     @classmethod
-    def dry(cls, model: Model, s=1.0, mu=1.0, h0=None, track_max=False):
+    def dry(cls, model: Model, s=1.0, mu=1.0, h0=None, track_max=False, class_n=None, drain_rate=0.0):
         h = np.zeros((model.ny, model.nx)) if h0 is None else _f64(h0).copy()
         return cls(h=h, qx=np.zeros((model.ny, model.nx + 1)), qy=np.zeros((model.ny + 1, model.nx)),
-                   s=float(s), mu=float(mu), hmax=h.copy() if track_max else None)
+                   s=float(s), mu=float(mu), hmax=h.copy() if track_max else None,
+                   class_n=None if class_n is None else _f64(class_n).ravel().copy(),
+                   drain_rate=float(drain_rate))
 
     def copy(self):
         return Member(self.h.copy(), self.qx.copy(), self.qy.copy(), self.t, self.s, self.mu, self.v_rain,
                       self.v_out, self.v_clamp, self.steps, list(self.dt_log),
-                      None if self.hmax is None else self.hmax.copy())
+                      None if self.hmax is None else self.hmax.copy(),
+                      None if self.class_n is None else self.class_n.copy(), self.drain_rate, self.v_drain)
 
     def _c(self):
         for a in (self.h, self.qx, self.qy):
@@ -170,11 +201,13 @@ class Member:
         if self.hmax is not None:
             assert self.hmax.flags.c_contiguous and self.hmax.dtype == np.float64 and self.hmax.shape == self.h.shape
         hm = _dp(self.hmax) if self.hmax is not None else C.POINTER(C.c_double)()
+        cn = _dp(self.class_n) if self.class_n is not None else C.POINTER(C.c_double)()
         return _Member(_dp(self.h), _dp(self.qx), _dp(self.qy), self.t, self.s, self.mu, self.v_rain,
-                       self.v_out, self.v_clamp, self.steps, hm)
+                       self.v_out, self.v_clamp, self.steps, hm, cn, float(self.drain_rate), self.v_drain)
 
     def _back(self, cm):
         self.t, self.v_rain, self.v_out, self.v_clamp, self.steps = cm.t, cm.v_rain, cm.v_out, cm.v_clamp, cm.steps
+        self.v_drain = cm.v_drain
 
 
 def dt_cfl(model: Model, h) -> float:
@@ -259,9 +292,11 @@ def gauge_values(members, gauges) -> np.ndarray:
 class Ensemble:
     """Members of one catchment plus their log-weights (equal at start)."""
 
-    def __init__(self, model: Model, s, mu, h0=None):
+    def __init__(self, model: Model, s, mu, h0=None, class_n=None, drain=None):
         self.model = model
-        self.members = [Member.dry(model, s[i], mu[i], h0) for i in range(len(s))]
+        self.members = [Member.dry(model, s[i], mu[i], h0,
+                                   class_n=None if class_n is None else class_n[i],
+                                   drain_rate=0.0 if drain is None else drain[i]) for i in range(len(s))]
         self.logw = np.full(len(s), -np.log(len(s)))
 
     def advance(self, t_end: float, log_dt=False):

@@ -49,6 +49,11 @@ typedef struct {
     double dt_fixed;           /* > 0: fixed step instead of Eq. 4 */
     double g;
     int32_t wet_fp32;          /* 1: take the wet/dry decision of each link in single precision */
+    /* land cover (Sec. 4.1, Table 1); cls NULL: no classes (shared field, member scale) */
+    const uint8_t* cls;        /* [ny*nx] class of each cell, < n_classes */
+    int32_t n_classes;
+    const double* class_runoff; /* [n_classes] fraction of the rain that stays on the surface */
+    const int32_t* class_drain; /* [n_classes] 1: the member's drainage rate applies to the class */
 } orc_model;
 
 typedef struct {
@@ -61,6 +66,9 @@ typedef struct {
     double v_rain, v_out, v_clamp;
     int64_t steps;
     double* hmax;              /* optional [ny*nx]: running maximum of the depth (Sec. 4.4, Figs. 15-16) */
+    const double* class_n;     /* land cover: [n_classes] this member's Manning n of each class */
+    double drain_rate;         /* land cover: drainage rate of draining classes, m/s */
+    double v_drain;            /* drained volume */
 } orc_member;
 
 /* ------------------------------------------------------------------------ */
@@ -147,8 +155,16 @@ static double link_open(const orc_model* m, double s, double qo, double hi, doub
 
 /* All new link discharges from the old state (h, qx, qy).  Returns the
  * outflow volume leaving through open edges during dt. */
-static double links_all(const orc_model* m, double s, const double* h, const double* qx,
+/* Manning n of cell i for one member: the shared field (scaled at the link by
+ * the member's factor s) or, with land-cover classes, the member's value for
+ * the cell's class (Table 1), unscaled. */
+static double cell_rough(const orc_model* m, const double* class_n, int64_t i) {
+    return m->cls ? class_n[m->cls[i]] : m->n[i];
+}
+
+static double links_all(const orc_model* m, double s, const double* class_n, const double* h, const double* qx,
                         const double* qy, double dt, double* qxn, double* qyn) {
+    if (m->cls) s = 1.0;
     const int ny = m->ny, nx = m->nx;
     const double dx = m->dx;
     double vout = 0.0;
@@ -159,20 +175,20 @@ static double links_all(const orc_model* m, double s, const double* h, const dou
                 int64_t i = (int64_t)r * nx;
                 double qo = 0.0;
                 if (m->edge_kind[EDGE_W] == EDGE_OPEN)
-                    qo = link_open(m, s, -qx[li], h[i], m->n[i], m->edge_slope[EDGE_W], dt);
+                    qo = link_open(m, s, -qx[li], h[i], cell_rough(m, class_n, i), m->edge_slope[EDGE_W], dt);
                 qxn[li] = -qo;
                 vout += qo * dx * dt;
             } else if (c == nx) {
                 int64_t i = (int64_t)r * nx + nx - 1;
                 double qo = 0.0;
                 if (m->edge_kind[EDGE_E] == EDGE_OPEN)
-                    qo = link_open(m, s, qx[li], h[i], m->n[i], m->edge_slope[EDGE_E], dt);
+                    qo = link_open(m, s, qx[li], h[i], cell_rough(m, class_n, i), m->edge_slope[EDGE_E], dt);
                 qxn[li] = qo;
                 vout += qo * dx * dt;
             } else {
                 int64_t i1 = (int64_t)r * nx + c - 1, i2 = i1 + 1;
-                qxn[li] = link_interior(m, s, qx[li], h[i1], m->z[i1], m->n[i1], h[i2], m->z[i2],
-                                        m->n[i2], dt);
+                qxn[li] = link_interior(m, s, qx[li], h[i1], m->z[i1], cell_rough(m, class_n, i1), h[i2], m->z[i2],
+                                        cell_rough(m, class_n, i2), dt);
             }
         }
     }
@@ -183,20 +199,20 @@ static double links_all(const orc_model* m, double s, const double* h, const dou
                 int64_t i = c;
                 double qo = 0.0;
                 if (m->edge_kind[EDGE_N] == EDGE_OPEN)
-                    qo = link_open(m, s, -qy[li], h[i], m->n[i], m->edge_slope[EDGE_N], dt);
+                    qo = link_open(m, s, -qy[li], h[i], cell_rough(m, class_n, i), m->edge_slope[EDGE_N], dt);
                 qyn[li] = -qo;
                 vout += qo * dx * dt;
             } else if (r == ny) {
                 int64_t i = (int64_t)(ny - 1) * nx + c;
                 double qo = 0.0;
                 if (m->edge_kind[EDGE_S] == EDGE_OPEN)
-                    qo = link_open(m, s, qy[li], h[i], m->n[i], m->edge_slope[EDGE_S], dt);
+                    qo = link_open(m, s, qy[li], h[i], cell_rough(m, class_n, i), m->edge_slope[EDGE_S], dt);
                 qyn[li] = qo;
                 vout += qo * dx * dt;
             } else {
                 int64_t i1 = (int64_t)(r - 1) * nx + c, i2 = i1 + nx;
-                qyn[li] = link_interior(m, s, qy[li], h[i1], m->z[i1], m->n[i1], h[i2], m->z[i2],
-                                        m->n[i2], dt);
+                qyn[li] = link_interior(m, s, qy[li], h[i1], m->z[i1], cell_rough(m, class_n, i1), h[i2], m->z[i2],
+                                        cell_rough(m, class_n, i2), dt);
             }
         }
     }
@@ -207,6 +223,13 @@ static double links_all(const orc_model* m, double s, const double* h, const dou
  * cell as indexed in Sec. 3.1 (west/east x-links, north/south y-links), using
  * the new discharges, plus the rain depth of this step.  Writes the unclamped
  * depth to hu (may alias nothing). */
+/* Rain reaching the surface of cell i: the member's rain depth of the step,
+ * times the runoff coefficient of the cell's land-cover class (Sec. 4.1: green
+ * land keeps 0.9 of the rain). */
+static double cell_rain(const orc_model* m, double rain_depth, int64_t i) {
+    return m->cls ? rain_depth * m->class_runoff[m->cls[i]] : rain_depth;
+}
+
 static void continuity_unclamped(const orc_model* m, const double* h, const double* qxn,
                                  const double* qyn, double dt, double rain_depth, double* hu) {
     const int ny = m->ny, nx = m->nx;
@@ -216,7 +239,7 @@ static void continuity_unclamped(const orc_model* m, const double* h, const doub
             int64_t lx = (int64_t)r * (nx + 1) + c;
             int64_t ly = (int64_t)r * nx + c;
             double dv = qxn[lx] - qxn[lx + 1] + qyn[ly] - qyn[ly + nx];
-            hu[i] = h[i] + dt / m->dx * dv + rain_depth;
+            hu[i] = h[i] + dt / m->dx * dv + cell_rain(m, rain_depth, i);
         }
 }
 
@@ -246,19 +269,28 @@ static void scratch_free(orc_scratch* w) {
 static void step_core(const orc_model* m, orc_member* st, double dt, orc_scratch* w) {
     const int64_t nc = (int64_t)m->ny * m->nx;
     const double area = m->dx * m->dx;
-    st->v_out += links_all(m, st->s, st->h, st->qx, st->qy, dt, w->qxn, w->qyn);
+    st->v_out += links_all(m, st->s, st->class_n, st->h, st->qx, st->qy, dt, w->qxn, w->qyn);
     double rain_depth = st->mu * rain_at(m, st->t) * dt;
     continuity_unclamped(m, st->h, w->qxn, w->qyn, dt, rain_depth, w->hu);
+    double rain_cells = 0.0;
     for (int64_t i = 0; i < nc; ++i) {
         double hn = w->hu[i];
         if (hn < 0.0) {
             st->v_clamp += -hn * area;
             hn = 0.0;
         }
+        /* drainage of the pipe network (Sec. 4.1): a fixed rate on draining
+         * classes, limited by the water the cell holds after the step */
+        if (m->cls && m->class_drain[m->cls[i]]) {
+            double loss = fmin(st->drain_rate * dt, hn);
+            hn -= loss;
+            st->v_drain += loss * area;
+        }
         st->h[i] = hn;
         if (st->hmax && hn > st->hmax[i]) st->hmax[i] = hn;
+        rain_cells += m->cls ? m->class_runoff[m->cls[i]] : 1.0;
     }
-    st->v_rain += rain_depth * (double)nc * area;
+    st->v_rain += rain_depth * rain_cells * area;
     memcpy(st->qx, w->qxn, sizeof(double) * (size_t)(m->ny * (int64_t)(m->nx + 1)));
     memcpy(st->qy, w->qyn, sizeof(double) * (size_t)((m->ny + 1) * (int64_t)m->nx));
     st->steps += 1;
@@ -269,12 +301,13 @@ static int model_valid(const orc_model* m) {
     if (!(m->g > 0.0) || !(m->h_dry >= 0.0) || !(m->rain_interval > 0.0)) return 0;
     if (m->n_rain < 0 || (m->n_rain > 0 && !m->rain)) return 0;
     if (!(m->dt_fixed > 0.0) && (!(m->alpha > 0.0) || !(m->dt_cap > 0.0))) return 0;
+    if (m->cls && (m->n_classes < 1 || m->n_classes > 8 || !m->class_runoff || !m->class_drain)) return 0;
     return 1;
 }
 
 /* Single step with a caller-chosen dt (time advances by dt). */
 int orc_step(const orc_model* m, orc_member* st, double dt) {
-    if (!model_valid(m) || !st || !(dt > 0.0)) return ORC_EINVAL;
+    if (!model_valid(m) || !st || !(dt > 0.0) || (m->cls && !st->class_n)) return ORC_EINVAL;
     orc_scratch w;
     if (scratch_alloc(m, &w)) return ORC_ENOMEM;
     step_core(m, st, dt, &w);
@@ -302,7 +335,7 @@ static double plan_step(const orc_model* m, const double* h, double t, double t_
 /* Advance one member to t_end.  Optionally logs the step sizes. */
 int orc_advance(const orc_model* m, orc_member* st, double t_end, int64_t max_steps, double* dt_log,
                 int64_t dt_log_cap, int64_t* n_steps_out) {
-    if (!model_valid(m) || !st) return ORC_EINVAL;
+    if (!model_valid(m) || !st || (m->cls && !st->class_n)) return ORC_EINVAL;
     orc_scratch w;
     if (scratch_alloc(m, &w)) return ORC_ENOMEM;
     int64_t k = 0;
@@ -511,7 +544,7 @@ static void adj_step(const orc_model* m, double s, double mu, const double* h, c
     const int64_t nc = (int64_t)ny * nx;
     const double R = rain_at(m, t);
     /* forward recomputation to recover the clamp branch */
-    links_all(m, s, h, qx, qy, dt, a->w.qxn, a->w.qyn);
+    links_all(m, s, NULL, h, qx, qy, dt, a->w.qxn, a->w.qyn);
     continuity_unclamped(m, h, a->w.qxn, a->w.qyn, dt, mu * R * dt, a->w.hu);
     double gm = 0.0;
     for (int64_t i = 0; i < nc; ++i) {
@@ -726,7 +759,7 @@ int orc_loss(const orc_model* m, orc_member* st, double t_end, double sample_dt,
 int orc_adjoint(const orc_model* m, orc_member* st, double t_end, double sample_dt, int32_t K,
                 const int32_t* grc, const double* obs, int32_t ckpt_every, double* loss, double* grad_n,
                 double* grad_mu, double* dt_out, double* tend_out, int64_t out_cap, int64_t* n_steps_out) {
-    if (!model_valid(m) || !st || !(sample_dt > 0.0) || ckpt_every < 1) return ORC_EINVAL;
+    if (!model_valid(m) || !st || !(sample_dt > 0.0) || ckpt_every < 1 || m->cls) return ORC_EINVAL;
     const int64_t nc = (int64_t)m->ny * m->nx;
     const int64_t nqx = (int64_t)m->ny * (m->nx + 1), nqy = (int64_t)(m->ny + 1) * m->nx;
     const int64_t nst = nc + nqx + nqy;
@@ -803,7 +836,7 @@ int orc_adjoint(const orc_model* m, orc_member* st, double t_end, double sample_
 /* Adjoint of a single step with a given dt (for transpose checks). */
 int orc_adj_step(const orc_model* m, double s, double mu, const double* h, const double* qx, const double* qy,
                  double dt, double t, double* lh, double* lqx, double* lqy, double* grad_n, double* grad_mu) {
-    if (!model_valid(m) || !(dt > 0.0)) return ORC_EINVAL;
+    if (!model_valid(m) || !(dt > 0.0) || m->cls) return ORC_EINVAL;
     const int64_t nc = (int64_t)m->ny * m->nx;
     adj_scratch as;
     as.lhe = (double*)malloc(sizeof(double) * (size_t)nc);

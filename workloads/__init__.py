@@ -229,6 +229,14 @@ class Catchment:
     truth_n_scale: float = 1.0
     truth_rain_mult: float = 1.0
     h0: np.ndarray | None = None
+    # land cover (Sec. 4.1, Table 1); None: shared Manning field x member scale
+    land_class: np.ndarray | None = None      # uint8 [ny, nx]: 0 hardened ground, 1 green land, 2 water
+    class_runoff: np.ndarray | None = None    # [3]
+    class_drain: np.ndarray | None = None     # [3] int
+    class_n: np.ndarray | None = None         # [N, 3] per-member Manning n of each class
+    drain: np.ndarray | None = None           # [N] drainage rate, m/s
+    truth_class_n: np.ndarray | None = None   # [3]
+    truth_drain: float = 0.0
 
 
 @dataclass
@@ -251,8 +259,36 @@ class Workload:
     extra: dict = field(default_factory=dict)
 
 
+# Land cover of the synthetic city (Sec. 4.1, Table 1): streets and roofs are
+# hardened ground, open lot area is green land, the lowest 3 % of the open
+# ground are water bodies.  Per-member roughness is drawn uniformly within
+# Table 1's initial-ensemble ranges; the drainage rate of hardened ground within
+# +-50 % of the paper's 12 mm/h.
+CLASS_HARD, CLASS_GREEN, CLASS_WATER = 0, 1, 2
+CLASS_N_RANGE = ((0.010, 0.022), (0.08, 0.22), (0.016, 0.030))
+CLASS_N_TRUTH = (0.017, 0.15, 0.020)
+CLASS_RUNOFF = (1.0, 0.9, 1.0)
+CLASS_DRAIN = (1, 0, 0)
+DRAIN_MMH = 12.0
+
+
+def land_cover(dem: np.ndarray, bmask: np.ndarray, period: int = 12, street: int = 2,
+               water_frac: float = 0.03) -> np.ndarray:
+    ny, nx = dem.shape
+    r = np.arange(ny)[:, None] % period
+    c = np.arange(nx)[None, :] % period
+    streets = (r < street) | (c < street)
+    cls = np.full((ny, nx), CLASS_GREEN, dtype=np.uint8)
+    cls[streets | bmask] = CLASS_HARD
+    green = cls == CLASS_GREEN
+    if np.any(green):
+        cut = np.quantile(dem[green], water_frac)
+        cls[green & (dem <= cut)] = CLASS_WATER
+    return cls
+
+
 def urban_catchment(name: str, ny: int, nx: int, n_members: int, seed: int, n_gauges: int = 5,
-                    dx: float = 3.0, open_slope: float = 1e-3) -> Catchment:
+                    dx: float = 3.0, open_slope: float = 1e-3, with_land_cover: bool = False) -> Catchment:
     rng = np.random.default_rng(seed)
     dem, bmask = dem_urban(ny, nx, rng)
     manning = np.full((ny, nx), 0.03, dtype=np.float32)
@@ -261,10 +297,22 @@ def urban_catchment(name: str, ny: int, nx: int, n_members: int, seed: int, n_ga
     gauges = pick_gauges(~bmask, n_gauges, rng)
     ts = float(lognormal(rng, 1)[0])
     tm = float(lognormal(rng, 1)[0])
-    return Catchment(name=name, ny=ny, nx=nx, dx=dx, dem=dem, manning=manning,
-                     edge_kind=(EDGE_OPEN,) * 4, edge_slope=(open_slope,) * 4,
-                     n_members=n_members, n_scale=s, rain_mult=mu, gauges=gauges, street=~bmask,
-                     truth_n_scale=ts, truth_rain_mult=tm)
+    cat = Catchment(name=name, ny=ny, nx=nx, dx=dx, dem=dem, manning=manning,
+                    edge_kind=(EDGE_OPEN,) * 4, edge_slope=(open_slope,) * 4,
+                    n_members=n_members, n_scale=s, rain_mult=mu, gauges=gauges, street=~bmask,
+                    truth_n_scale=ts, truth_rain_mult=tm)
+    if with_land_cover:
+        lrng = np.random.default_rng(seed + 5)       # its own stream: the draws above do not move
+        cat.land_class = land_cover(dem, bmask)
+        cat.class_runoff = np.array(CLASS_RUNOFF)
+        cat.class_drain = np.array(CLASS_DRAIN, dtype=np.int32)
+        lo = np.array([a for a, _ in CLASS_N_RANGE])
+        hi = np.array([b for _, b in CLASS_N_RANGE])
+        cat.class_n = lrng.uniform(lo, hi, size=(n_members, 3))
+        cat.drain = lrng.uniform(0.5, 1.5, size=n_members) * DRAIN_MMH / 3.6e6
+        cat.truth_class_n = np.array(CLASS_N_TRUTH)
+        cat.truth_drain = DRAIN_MMH / 3.6e6
+    return cat
 
 
 def config1(ny: int = 128, nx: int = 128) -> Workload:
@@ -308,10 +356,11 @@ def config4(members_each: int = 24, shapes=((512, 512), (768, 1536), (1024, 1024
                     rain_interval=300.0, t_end=1800.0, real_bytes=4, pf_every=300.0, seed=seed)
 
 
-def config5(ny: int = 2000, nx: int = 2000, n_members: int = 96) -> Workload:
-    """Paper-scale single GPU: 4.0 M cells x 96 members, 3600 s, PF every 600 s, 10 gauges."""
+def config5(ny: int = 2000, nx: int = 2000, n_members: int = 96, with_land_cover: bool = False) -> Workload:
+    """Paper-scale single GPU: 4.0 M cells x 96 members, 3600 s, PF every 600 s, 10 gauges
+    (optionally with the land cover of Sec. 4.1: class roughness, runoff, drainage)."""
     seed = seed_for(5)
-    c = urban_catchment("urban2000", ny, nx, n_members, seed, n_gauges=10)
+    c = urban_catchment("urban2000", ny, nx, n_members, seed, n_gauges=10, with_land_cover=with_land_cover)
     return Workload(name="c5_urban2000x96_pf", catchments=[c], rain=chicago_hyetograph(),
                     rain_interval=300.0, t_end=3600.0, real_bytes=4, pf_every=600.0, seed=seed,
                     extra={"adj_window": 900.0, "ckpt_every": 100})
