@@ -66,6 +66,8 @@ typedef struct flood_grid {
     const float* h0;           /* host [ny*nx] initial depth >= 0, or NULL for a dry start */
     int32_t edge_kind[4];      /* FLOOD_EDGE_WALL or FLOOD_EDGE_OPEN per edge N,E,S,W */
     double edge_slope[4];      /* outward water-surface slope of an open edge, > 0 */
+    const uint8_t* land_class; /* host [ny*nx] land-cover class of each cell (< n_classes of the params),
+                                  or NULL: no land cover (Sec. 4.1, Fig. 6) */
 } flood_grid;
 
 /* Forcing and numerics shared by all members of a catchment. */
@@ -90,8 +92,21 @@ typedef struct flood_params {
     int32_t march_rows;        /* 0: autotune; else rows per strip of the row-marching kernel, 1..4096 */
     int32_t march_members;     /* 0: autotune; else members marched together by one wavefront: 1, 2, 4, 8 */
     int32_t track_peak;        /* 1: keep each member's running maximum depth (ensemble products, Sec. 4.4,
-                                  Figs. 15-16); costs a read and a write of one value per member-cell-step;
-                                  excludes step_kernel 2.  0: off */
+                                  Figs. 15-16); costs a read and a write of one value per member-cell-step.
+                                  0: off */
+    /* Land cover (Sec. 4.1, Table 1), used when the grid has a class map:
+     * each member has its own Manning n per class (link value: mean of the two
+     * cells' values; edge links: the inner cell's), the rain reaching a cell is
+     * the member's rain times the runoff coefficient of the cell's class, and
+     * cells of draining classes lose the member's drainage rate, up to the water
+     * they hold after the step (logged as drained volume).  The shared Manning
+     * field and n_scale are not used.  Needs member_interleave 0 or 1,
+     * step_kernel 0 or 3, and nx a multiple of 4 (FP32) or 2 (FP64). */
+    int32_t n_classes;              /* 0 (no land cover) .. 4 */
+    const double* class_runoff;     /* host [n_classes], each in [0, 1] */
+    const int32_t* class_drain;     /* host [n_classes], 1: the drainage rate applies, 0: it does not */
+    const double* member_class_n;   /* host [n_members*n_classes], member-major, finite, > 0 */
+    const double* member_drain;     /* host [n_members] drainage rates in m/s, finite, >= 0 (NULL: 0) */
 } flood_params;
 
 typedef struct flood_handle flood_handle;
@@ -180,10 +195,16 @@ flood_status flood_set_params(flood_handle* h, int32_t catchment, const float* m
 /* Mass ledger of one catchment, each output host [N] or NULL:
  * storage = sum h dx^2, rain_in = total rain volume added, outflow = volume
  * that left through open edges, clamp = volume added by clamping negative
- * depths to zero; t = member times; steps = steps taken.  Invariant:
- * storage - storage(t=0) = rain_in - outflow + clamp. */
+ * depths to zero, drained = volume lost to drainage (land cover); t = member
+ * times; steps = steps taken.  Invariant:
+ * storage - storage(t=0) = rain_in - outflow + clamp - drained. */
 flood_status flood_get_ledger(flood_handle* h, int32_t catchment, double* storage, double* rain_in,
-                              double* outflow, double* clamp, double* t, int64_t* steps);
+                              double* outflow, double* clamp, double* drained, double* t, int64_t* steps);
+
+/* Land-cover parameters of every member (they follow their members through
+ * resampling): class_n_out host [N*n_classes] member-major, drain_out host [N];
+ * either may be NULL.  ESTATE on a catchment without land cover. */
+flood_status flood_get_land_params(flood_handle* h, int32_t catchment, double* class_n_out, double* drain_out);
 
 /* Current log-weights (host [N]) and per-member rain multipliers / n scales. */
 flood_status flood_get_weights(flood_handle* h, int32_t catchment, double* logw, double* rain_mult,

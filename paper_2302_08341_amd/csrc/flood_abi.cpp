@@ -107,6 +107,16 @@ flood_status validate_params(const flood_params* p, std::string& err) {
         return FLOOD_EINVAL;
     }
     if (p->track_peak != 0 && p->track_peak != 1) { err = "track_peak must be 0 or 1"; return FLOOD_EINVAL; }
+    if (p->n_classes < 0 || p->n_classes > 4) { err = "n_classes must be in [0, 4]"; return FLOOD_EINVAL; }
+    if (p->n_classes > 0) {
+        if (!p->class_runoff || !p->class_drain) { err = "class_runoff and class_drain are required"; return FLOOD_EINVAL; }
+        for (int k = 0; k < p->n_classes; ++k) {
+            if (!(p->class_runoff[k] >= 0.0 && p->class_runoff[k] <= 1.0)) { err = "class_runoff must be in [0, 1]"; return FLOOD_EINVAL; }
+            if (p->class_drain[k] != 0 && p->class_drain[k] != 1) { err = "class_drain must be 0 or 1"; return FLOOD_EINVAL; }
+        }
+        if (p->step_kernel == 1 || p->step_kernel == 2) { err = "land cover needs step_kernel 0 or 3"; return FLOOD_EINVAL; }
+        if (p->member_interleave > 1) { err = "land cover needs member_interleave 0 or 1"; return FLOOD_EINVAL; }
+    }
     return FLOOD_OK;
 }
 
@@ -156,6 +166,28 @@ flood_status flood_create_batch(int32_t n_catch, const flood_grid* grids, const 
         }
         const int N = members_per_catch[i];
         if (N < 1 || N > FLOOD_MAX_MEMBERS) { g_create_error = "members per catchment must be in [1, 1024]"; return FLOOD_EINVAL; }
+        const int K = params[i].n_classes;
+        if ((K > 0) != (grids[i].land_class != nullptr)) {
+            g_create_error = "a class map and n_classes > 0 go together";
+            return FLOOD_EINVAL;
+        }
+        if (K > 0) {
+            const size_t ncell = (size_t)grids[i].ny * grids[i].nx;
+            for (size_t j = 0; j < ncell; ++j)
+                if (grids[i].land_class[j] >= K) { g_create_error = "land_class values must be < n_classes"; return FLOOD_EINVAL; }
+            if (!params[i].member_class_n) { g_create_error = "member_class_n is required"; return FLOOD_EINVAL; }
+            for (size_t j = 0; j < (size_t)N * K; ++j)
+                if (!(params[i].member_class_n[j] > 0.0) || !finite_d(params[i].member_class_n[j])) {
+                    g_create_error = "member_class_n must be finite and > 0";
+                    return FLOOD_EINVAL;
+                }
+            if (params[i].member_drain)
+                for (int m = 0; m < N; ++m)
+                    if (!(params[i].member_drain[m] >= 0.0) || !finite_d(params[i].member_drain[m])) {
+                        g_create_error = "member_drain must be finite and >= 0";
+                        return FLOOD_EINVAL;
+                    }
+        }
         for (int m = 0; m < N; ++m) {
             if (n_scale && n_scale[i] && (!(n_scale[i][m] > 0.0) || !finite_d(n_scale[i][m]))) {
                 g_create_error = "n_scale must be finite and > 0";
@@ -229,9 +261,14 @@ flood_status flood_set_params(flood_handle* h, int32_t catchment, const float* m
 }
 
 flood_status flood_get_ledger(flood_handle* h, int32_t catchment, double* storage, double* rain_in, double* outflow,
-                              double* clamp, double* t, int64_t* steps) {
+                              double* clamp, double* drained, double* t, int64_t* steps) {
     FLOOD_NEED_HANDLE(h);
-    return h->impl->get_ledger(catchment, storage, rain_in, outflow, clamp, t, steps, h->err);
+    return h->impl->get_ledger(catchment, storage, rain_in, outflow, clamp, drained, t, steps, h->err);
+}
+
+flood_status flood_get_land_params(flood_handle* h, int32_t catchment, double* class_n_out, double* drain_out) {
+    FLOOD_NEED_HANDLE(h);
+    return h->impl->get_land_params(catchment, class_n_out, drain_out, h->err);
 }
 
 flood_status flood_get_weights(flood_handle* h, int32_t catchment, double* logw, double* rain_mult, double* n_scale) {

@@ -23,6 +23,7 @@ constexpr int kMaxCatch = 8;
 constexpr int kBins = 64;      // partial-max bins per member for the depth maximum
 constexpr int kBlock = 256;    // lanes per workgroup of the step kernels
 constexpr int kMaxMembers = 1024;
+constexpr int kMaxClasses = 4;  // land-cover classes
 
 template <typename T> struct HBits;
 template <> struct HBits<float> { using type = uint32_t; };
@@ -40,6 +41,8 @@ template <typename T> struct MemberStep {
     int32_t active;
     int32_t parity;  // state copy holding the state before this step
     int32_t slot;    // adjoint record: the member's step index within the tape segment
+    T cn[kMaxClasses];  // land cover: the member's Manning n of each class
+    T drain;            // land cover: drainage depth of the step (rate x dt)
 };
 
 template <typename T> struct CatchDev {
@@ -69,6 +72,11 @@ template <typename T> struct CatchDev {
     const T* n;
     double* out_acc;          // [n_members][2*(nx+ny)] outflow volume per edge link (N, S, W, E)
     T* peak;                  // running maximum depth, state layout, one copy; null when not tracked
+    // land cover (row-march kernel only): class map, runoff coefficient per class,
+    // bit k of drain_mask set when class k drains; cls null: shared Manning field
+    const uint8_t* cls;
+    T class_rc[kMaxClasses];
+    int32_t drain_mask;
 };
 
 template <typename T> struct StepLaunch {
@@ -80,6 +88,7 @@ template <typename T> struct StepLaunch {
     const MemberStep<T>* ms;  // indexed by global member
     typename HBits<T>::type* hbins;  // [kBins][n_total]
     double* vclamp;           // [n_total]
+    double* vdrain;           // [n_total] drained volume (land cover)
     uint8_t* clamp_out;       // recompute only: 1 where the new depth was clamped at zero
     // tape recomputation by the row-march kernel: c[0]'s copy-0 arrays are tape
     // slot 0; a member reads slot ms.slot and writes slot ms.slot + 1, and its
@@ -121,6 +130,8 @@ template <typename T> struct PlanLaunch {
     int32_t* any_log;         // set to 1 when any member steps
     int32_t tag_value;
     int32_t* seg_cnt;         // optional, by m - m_begin: steps taken since the last checkpoint
+    const double* clsn;       // optional [n_total][kMaxClasses] land-cover Manning n per member
+    const double* drain;      // optional [n_total] drainage rate per member, m/s
 };
 
 // ---------------------------------------------------------------------------
@@ -132,7 +143,8 @@ template <typename T> void launch_step_mi(int mi, const StepLaunch<T>& L, hipStr
 template <typename T> void launch_march(const StepLaunch<T>& L, int seg, int total_waves, hipStream_t s);
 // cells per lane of the vectorised row-marching kernel (nx must be a multiple of it)
 template <typename T> constexpr int march_vec() { return sizeof(T) == 4 ? 4 : 2; }
-template <typename T> void launch_marchv(const StepLaunch<T>& L, int nt, int pf, int total_waves, hipStream_t s);
+template <typename T>
+void launch_marchv(const StepLaunch<T>& L, int nt, int pf, int land, int total_waves, hipStream_t s);
 // wavefronts of a row-march launch over one catchment: strips x member units,
 // units padded to a multiple of four in wavefront order 2
 inline int march_waves(int strips, int units, int order) { return strips * (order == 2 ? (units + 3) / 4 * 4 : units); }
@@ -240,6 +252,9 @@ struct PfArgs {
     int32_t* anc;             // [N] out
     double* neff;             // [1] out
     int32_t* flag;            // [1] out: 1 if resampled
+    double* clsn;             // land cover, permuted with the members: [N][kMaxClasses] or null
+    double* drain;            // [N] or null
+    double* vdrain;           // [N]
 };
 void launch_pf(const PfArgs& a, hipStream_t s);
 // running maxima follow their members on resampling: gather into tmp, then commit

@@ -31,6 +31,8 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     ms.active = 0;
     ms.parity = P.par[m];
     ms.slot = -1;
+    for (int k = 0; k < kMaxClasses; ++k) ms.cn[k] = T(0);
+    ms.drain = T(0);
     const double t = P.t[m];
     const double t_end = *P.t_end;
     const int lm = m - P.m_begin;
@@ -90,6 +92,9 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     ms.dxdt = C.dx * dt;
     ms.active = 1;
     if (P.seg_cnt) ms.slot = P.seg_cnt[lm]++;
+    if (P.clsn)
+        for (int k = 0; k < kMaxClasses; ++k) ms.cn[k] = (T)P.clsn[(size_t)m * kMaxClasses + k];
+    if (P.drain) ms.drain = (T)(P.drain[m] * dt);
     P.ms[m] = ms;
     if (P.ms_log) {
         P.ms_log[lm] = ms;
@@ -756,7 +761,7 @@ __global__ __launch_bounds__(kBlock) void k_march(const StepLaunch<T> L) {
 // computes.  Loads use a column clamped into the grid and a row clamped to the
 // last row, so no lane needs a branch or a zero fill around them: values of
 // lanes outside the grid and of the row below the last are read but never used.
-template <typename T, int V, int NT, int REC, int PF>
+template <typename T, int V, int NT, int REC, int PF, int LC>
 __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
     using HB = typename HBits<T>::type;
     const int lane = threadIdx.x & 63;
@@ -824,17 +829,51 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
     const T* __restrict__ Nn = C.n;
     const T g = C.g, hdry = C.hdry;
     const int nb = 2 * (nx + ny);
+    // land cover: the cell's roughness is the member's value for its class, and
+    // its rain is scaled by the class's runoff coefficient (select chains: the
+    // member's table stays in scalar registers)
+    const uint8_t* __restrict__ CLS = LC ? C.cls : nullptr;
+    const bool lc = LC && CLS != nullptr;
+    auto rough = [&](uint32_t k) -> T {
+        T v = ms.cn[0];
+        v = (k == 1u) ? ms.cn[1] : v;
+        v = (k == 2u) ? ms.cn[2] : v;
+        return (k == 3u) ? ms.cn[3] : v;
+    };
+    auto runoff = [&](uint32_t k) -> T {
+        T v = C.class_rc[0];
+        v = (k == 1u) ? C.class_rc[1] : v;
+        v = (k == 2u) ? C.class_rc[2] : v;
+        return (k == 3u) ? C.class_rc[3] : v;
+    };
+    // roughness of V cells from the shared field, or from their classes (whose
+    // packed bytes are returned in cw)
+    auto load_n = [&](size_t c, T (&nv)[V], uint32_t& cw) {
+        if (lc) {
+            if constexpr (V == 4)
+                cw = *reinterpret_cast<const uint32_t*>(CLS + c);
+            else
+                cw = *reinterpret_cast<const uint16_t*>(CLS + c);
+#pragma unroll
+            for (int j = 0; j < V; ++j) nv[j] = rough((cw >> (8 * j)) & 0xffu);
+        } else {
+            cw = 0;
+            vload<T, V>(Nn + c, nv);
+        }
+    };
 
     size_t ca = (size_t)r0 * nx + xa;
     T hc[V], zc[V], nc[V], fN[V];
+    uint32_t ccw;
     vload<T, V>(H + ca, hc);
     vload<T, V>(Z + ca, zc);
-    vload<T, V>(Nn + ca, nc);
+    load_n(ca, nc, ccw);
     if (r0 > 0) {
         T hN[V], zN[V], nN[V], qN[V];
+        uint32_t cwN;
         vload<T, V>(H + ca - nx, hN);
         vload<T, V>(Z + ca - nx, zN);
-        vload<T, V>(Nn + ca - nx, nN);
+        load_n(ca - nx, nN, cwN);
         vload<T, V>(QY + ca - nx, qN);
 #pragma unroll
         for (int j = 0; j < V; ++j) {
@@ -849,9 +888,11 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
 #pragma unroll
         for (int j = 0; j < V; ++j) fN[j] = T(0);
     }
-    // current row's links (qE, qS) and the row below (hs, zs, ns)
+    // current row's links (qE, qS) and the row below (hs, zs, ns, classes csw)
     T hs[V], zs[V], ns[V], qE[V], qS[V];
-    auto load_row = [&](size_t c, bool below, T (&qe)[V], T (&qs)[V], T (&h2)[V], T (&z2)[V], T (&n2)[V]) {
+    uint32_t csw = 0;
+    auto load_row = [&](size_t c, bool below, T (&qe)[V], T (&qs)[V], T (&h2)[V], T (&z2)[V], T (&n2)[V],
+                        uint32_t& cw2) {
         const size_t cb = below ? c + nx : c;
         if (NT) {
             vload_nt<T, V>(QX + c, qe);
@@ -862,18 +903,20 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
         }
         vload<T, V>(H + cb, h2);
         vload<T, V>(Z + cb, z2);
-        vload<T, V>(Nn + cb, n2);
+        load_n(cb, n2, cw2);
     };
-    if (PF) load_row(ca, r0 + 1 < ny, qE, qS, hs, zs, ns);
+    if (PF) load_row(ca, r0 + 1 < ny, qE, qS, hs, zs, ns, csw);
     HB vmax = 0;
     T vcl = T(0);
+    T vdr = T(0);
     for (int r = r0; r < r1; ++r) {
         const bool hasS = r + 1 < ny;
         T hs2[V], zs2[V], ns2[V], qE2[V], qS2[V];
+        uint32_t csw2 = 0;
         if (PF) {
-            if (r + 1 < r1) load_row(ca + nx, r + 2 < ny, qE2, qS2, hs2, zs2, ns2);
+            if (r + 1 < r1) load_row(ca + nx, r + 2 < ny, qE2, qS2, hs2, zs2, ns2, csw2);
         } else {
-            load_row(ca, hasS, qE, qS, hs, zs, ns);
+            load_row(ca, hasS, qE, qS, hs, zs, ns, csw);
         }
         // east neighbour of the lane's last cell = first cell of the next lane
         const T hE = __shfl_down(hc[0], 1, 64);
@@ -922,10 +965,16 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
 #pragma unroll
         for (int j = 0; j < V; ++j) {
             const T dv = ((fW[j] - fE[j]) + fN[j]) - fS[j];
-            T hn = (hc[j] + ms.dtdx * dv) + ms.rinc;
+            const uint32_t kc = (ccw >> (8 * j)) & 0xffu;
+            const T rn = lc ? ms.rinc * runoff(kc) : ms.rinc;
+            T hn = (hc[j] + ms.dtdx * dv) + rn;
             cf[j] = hn < T(0);
             vcl += (own && hn < T(0)) ? -hn : T(0);
             hn = (hn < T(0)) ? T(0) : hn;
+            // drainage of draining classes, up to the water the cell holds
+            const T loss = (lc && ((C.drain_mask >> kc) & 1)) ? fmin(ms.drain, hn) : T(0);
+            hn = hn - loss;
+            vdr += own ? loss : T(0);
             hn = (hn == T(0)) ? T(0) : hn;
             hn4[j] = hn;
             const HB hb = to_bits(hn);
@@ -985,7 +1034,9 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
             zc[j] = zs[j];
             nc[j] = ns[j];
         }
+        ccw = csw;
         if (PF) {
+            csw = csw2;
 #pragma unroll
             for (int j = 0; j < V; ++j) {
                 qE[j] = qE2[j];
@@ -1004,6 +1055,11 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
         }
         double cl = (double)vcl;
         for (int off = 32; off > 0; off >>= 1) cl += __shfl_xor(cl, off, 64);
+        if (lc) {
+            double dr = (double)vdr;
+            for (int off = 32; off > 0; off >>= 1) dr += __shfl_xor(dr, off, 64);
+            if (lane == 0 && dr != 0.0) atomicAdd(&L.vdrain[C.member_off + k], dr * (C.dx * C.dx));
+        }
         if (lane == 0) {
             if (vmax != 0) {
                 HB* a = L.hbins + (size_t)(blockIdx.x & (kBins - 1)) * L.n_total + C.member_off + k;
@@ -1015,18 +1071,27 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
     }
 }
 
-template <typename T> void launch_marchv(const StepLaunch<T>& L, int nt, int pf, int total_waves, hipStream_t s) {
-    const int per = kBlock / 64;
-    const dim3 grid((total_waves + per - 1) / per);
+template <typename T, int LC>
+static void launch_marchv_lc(const StepLaunch<T>& L, int nt, int pf, const dim3 grid, hipStream_t s) {
     constexpr int V = march_vec<T>();
     if (nt && pf)
-        hipLaunchKernelGGL((k_marchv<T, V, 1, 0, 1>), grid, dim3(kBlock), 0, s, L);
+        hipLaunchKernelGGL((k_marchv<T, V, 1, 0, 1, LC>), grid, dim3(kBlock), 0, s, L);
     else if (nt)
-        hipLaunchKernelGGL((k_marchv<T, V, 1, 0, 0>), grid, dim3(kBlock), 0, s, L);
+        hipLaunchKernelGGL((k_marchv<T, V, 1, 0, 0, LC>), grid, dim3(kBlock), 0, s, L);
     else if (pf)
-        hipLaunchKernelGGL((k_marchv<T, V, 0, 0, 1>), grid, dim3(kBlock), 0, s, L);
+        hipLaunchKernelGGL((k_marchv<T, V, 0, 0, 1, LC>), grid, dim3(kBlock), 0, s, L);
     else
-        hipLaunchKernelGGL((k_marchv<T, V, 0, 0, 0>), grid, dim3(kBlock), 0, s, L);
+        hipLaunchKernelGGL((k_marchv<T, V, 0, 0, 0, LC>), grid, dim3(kBlock), 0, s, L);
+}
+
+template <typename T>
+void launch_marchv(const StepLaunch<T>& L, int nt, int pf, int land, int total_waves, hipStream_t s) {
+    const int per = kBlock / 64;
+    const dim3 grid((total_waves + per - 1) / per);
+    if (land)
+        launch_marchv_lc<T, 1>(L, nt, pf, grid, s);
+    else
+        launch_marchv_lc<T, 0>(L, nt, pf, grid, s);
 }
 
 // Tape recomputation of the adjoint: the same step, reading and writing tape
@@ -1038,13 +1103,13 @@ template <typename T> void launch_marchv_rec(const StepLaunch<T>& L, int pf, int
     const dim3 grid((total_waves + per - 1) / per);
     constexpr int V = march_vec<T>();
     if (pf)
-        hipLaunchKernelGGL((k_marchv<T, V, 0, 1, 1>), grid, dim3(kBlock), 0, s, L);
+        hipLaunchKernelGGL((k_marchv<T, V, 0, 1, 1, 0>), grid, dim3(kBlock), 0, s, L);
     else
-        hipLaunchKernelGGL((k_marchv<T, V, 0, 1, 0>), grid, dim3(kBlock), 0, s, L);
+        hipLaunchKernelGGL((k_marchv<T, V, 0, 1, 0, 0>), grid, dim3(kBlock), 0, s, L);
 }
 
-template void launch_marchv<float>(const StepLaunch<float>&, int, int, int, hipStream_t);
-template void launch_marchv<double>(const StepLaunch<double>&, int, int, int, hipStream_t);
+template void launch_marchv<float>(const StepLaunch<float>&, int, int, int, int, hipStream_t);
+template void launch_marchv<double>(const StepLaunch<double>&, int, int, int, int, hipStream_t);
 template void launch_marchv_rec<float>(const StepLaunch<float>&, int, int, hipStream_t);
 template void launch_marchv_rec<double>(const StepLaunch<double>&, int, int, hipStream_t);
 

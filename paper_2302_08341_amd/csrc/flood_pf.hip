@@ -109,10 +109,15 @@ __global__ __launch_bounds__(1024) void k_pf(const PfArgs a) {
     const int anc = systematic_lane(N, sw, C, a.u0);
     // replacement (step V): slot m takes its ancestor's scalars; the state arrays
     // are copied by k_permute into the slot's other state copy
-    double t = 0, s = 0, mu = 0, vr = 0, vo = 0, vc = 0;
+    double t = 0, s = 0, mu = 0, vr = 0, vo = 0, vc = 0, vd = 0, dr = 0;
+    double cn[kMaxClasses] = {0.0, 0.0, 0.0, 0.0};
     int64_t st = 0;
     int sp = 0, mypar = 0;
     if (m < N) {
+        if (a.clsn)
+            for (int k = 0; k < kMaxClasses; ++k) cn[k] = a.clsn[(size_t)anc * kMaxClasses + k];
+        if (a.drain) dr = a.drain[anc];
+        vd = a.vdrain[anc];
         t = a.t[anc];
         s = a.s[anc];
         mu = a.mu[anc];
@@ -132,6 +137,10 @@ __global__ __launch_bounds__(1024) void k_pf(const PfArgs a) {
         a.vrain[m] = vr;
         a.vout[m] = vo;
         a.vclamp[m] = vc;
+        if (a.clsn)
+            for (int k = 0; k < kMaxClasses; ++k) a.clsn[(size_t)m * kMaxClasses + k] = cn[k];
+        if (a.drain) a.drain[m] = dr;
+        a.vdrain[m] = vd;
         a.steps[m] = st;
         a.logw[m] = -log((double)N);
         a.src_par[m] = sp;

@@ -26,7 +26,8 @@ struct ImplBase {
     virtual flood_status set_params(int c, const float* manning, const double* n_scale, const double* rain_mult,
                                     std::string& err) = 0;
     virtual flood_status get_ledger(int c, double* storage, double* rain_in, double* outflow, double* clamp,
-                                    double* t, int64_t* steps, std::string& err) = 0;
+                                    double* drained, double* t, int64_t* steps, std::string& err) = 0;
+    virtual flood_status get_land_params(int c, double* class_n, double* drain, std::string& err) = 0;
     virtual flood_status get_weights(int c, double* logw, double* rain_mult, double* n_scale,
                                      std::string& err) = 0;
     virtual flood_status products(int c, double threshold, int n_pct, const double* pct, const double* weights,

@@ -46,6 +46,8 @@ template <typename T> struct Impl : ImplBase {
         CatchDev<T> dev{};
         size_t state_elems = 0, strip_w = 0, strip_n = 0;
         T* peak_tmp = nullptr;    // resampling scratch of the running maximum
+        int n_classes = 0;        // land cover: 0 none
+        double rain_cells = 0.0;  // rain-receiving cell count (land cover: sum of runoff coefficients)
     };
 
     hipStream_t st = nullptr;
@@ -64,6 +66,8 @@ template <typename T> struct Impl : ImplBase {
     double *t = nullptr, *s = nullptr, *mu = nullptr, *logw = nullptr, *vrain = nullptr, *vout = nullptr,
            *vclamp = nullptr;
     int64_t* steps = nullptr;
+    double *clsn = nullptr, *drain = nullptr, *vdrain = nullptr;   // land cover per member; drained volume
+    bool any_land = false;
     int32_t *par = nullptr, *fault = nullptr, *status = nullptr;
     HB* hbins = nullptr;
     MemberStep<T>* ms = nullptr;
@@ -162,11 +166,12 @@ template <typename T> struct Impl : ImplBase {
         SL.ms = ms;
         SL.hbins = hbins;
         SL.vclamp = vclamp;
+        SL.vdrain = vdrain;
     }
 
     void launch_steps(const StepLaunch<T>& L) {
         if (variant == 3 && !L.recompute)
-            launch_marchv<T>(L, march_nt, march_pf, total_waves, st);
+            launch_marchv<T>(L, march_nt, march_pf, any_land ? 1 : 0, total_waves, st);
         else if (variant == 2 && !L.recompute)
             launch_march<T>(L, march_seg, total_waves, st);
         else
@@ -251,6 +256,17 @@ template <typename T> struct Impl : ImplBase {
             variant = 2;
         }
         if (mi != 1) variant = 1;
+        // land cover runs on the vectorised row-march kernel only (per-member class
+        // tables in scalar registers)
+        any_land = false;
+        for (int i = 0; i < nc; ++i) any_land |= grids[i].land_class != nullptr && params[i].n_classes > 0;
+        if (any_land) {
+            if (mi != 1 || !vector_ok()) {
+                err = "land cover needs member_interleave 1 and nx a multiple of " + std::to_string(march_vec<T>());
+                return FLOOD_EINVAL;
+            }
+            variant = 3;
+        }
         for (int i = 0; i < nc; ++i) {
             cats[i].tile_rows = params[i].tile_rows ? params[i].tile_rows : ch.tile_rows;
             cats[i].cpb = params[i].chunks_per_block ? params[i].chunks_per_block : ch.cpb;
@@ -306,6 +322,25 @@ template <typename T> struct Impl : ImplBase {
             }
             d.z = zz;
             d.n = nn;
+            // land cover: class map, runoff coefficients, draining classes
+            c.n_classes = (grids[i].land_class && params[i].n_classes > 0) ? params[i].n_classes : 0;
+            d.cls = nullptr;
+            d.drain_mask = 0;
+            for (int k = 0; k < kMaxClasses; ++k) d.class_rc[k] = T(1);
+            c.rain_cells = (double)ncell;
+            if (c.n_classes) {
+                uint8_t* dc;
+                CHK(dalloc(&dc, ncell, err));
+                HIPCHK(hipMemcpy(dc, grids[i].land_class, ncell, hipMemcpyHostToDevice));
+                d.cls = dc;
+                for (int k = 0; k < c.n_classes; ++k) {
+                    d.class_rc[k] = (T)params[i].class_runoff[k];
+                    if (params[i].class_drain[k]) d.drain_mask |= 1 << k;
+                }
+                double rcs = 0.0;   // cell order, as the rain volume of the ledger is summed
+                for (size_t j = 0; j < ncell; ++j) rcs += params[i].class_runoff[grids[i].land_class[j]];
+                c.rain_cells = rcs;
+            }
             if (c.p.track_peak) {
                 CHK(dalloc(&d.peak, c.state_elems, err));
                 CHK(dalloc(&c.peak_tmp, c.state_elems, err));
@@ -331,6 +366,9 @@ template <typename T> struct Impl : ImplBase {
         CHK(dalloc(&vout, n_total, err));
         CHK(dalloc(&vclamp, n_total, err));
         CHK(dalloc(&steps, n_total, err));
+        CHK(dalloc(&clsn, (size_t)n_total * kMaxClasses, err));
+        CHK(dalloc(&drain, n_total, err));
+        CHK(dalloc(&vdrain, n_total, err));
         CHK(dalloc(&par, n_total, err));
         CHK(dalloc(&fault, n_total, err));
         CHK(dalloc(&status, 1, err));
@@ -340,15 +378,23 @@ template <typename T> struct Impl : ImplBase {
         CHK(dalloc(&d_count, 2, err));
         {
             std::vector<double> hs(n_total), hm(n_total), hl(n_total), z0(n_total, 0.0);
+            std::vector<double> hcn((size_t)n_total * kMaxClasses, 0.0), hdr(n_total, 0.0);
             for (int i = 0; i < nc; ++i) {
                 const Cat& c = cats[i];
                 for (int m = 0; m < c.N; ++m) {
                     const int g = c.dev.member_off + m;
-                    hs[g] = (n_scale && n_scale[i]) ? n_scale[i][m] : 1.0;
+                    hs[g] = (n_scale && n_scale[i] && !c.n_classes) ? n_scale[i][m] : 1.0;
                     hm[g] = (rain_mult && rain_mult[i]) ? rain_mult[i][m] : 1.0;
                     hl[g] = -std::log((double)c.N);
+                    if (c.n_classes) {
+                        for (int k = 0; k < c.n_classes; ++k)
+                            hcn[(size_t)g * kMaxClasses + k] = params[i].member_class_n[(size_t)m * c.n_classes + k];
+                        hdr[g] = params[i].member_drain ? params[i].member_drain[m] : 0.0;
+                    }
                 }
             }
+            HIPCHK(hipMemcpy(clsn, hcn.data(), hcn.size() * sizeof(double), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(drain, hdr.data(), n_total * sizeof(double), hipMemcpyHostToDevice));
             HIPCHK(hipMemcpy(s, hs.data(), n_total * sizeof(double), hipMemcpyHostToDevice));
             HIPCHK(hipMemcpy(mu, hm.data(), n_total * sizeof(double), hipMemcpyHostToDevice));
             HIPCHK(hipMemcpy(logw, hl.data(), n_total * sizeof(double), hipMemcpyHostToDevice));
@@ -357,6 +403,7 @@ template <typename T> struct Impl : ImplBase {
         HIPCHK(hipMemsetAsync(vrain, 0, n_total * sizeof(double), st));
         HIPCHK(hipMemsetAsync(vout, 0, n_total * sizeof(double), st));
         HIPCHK(hipMemsetAsync(vclamp, 0, n_total * sizeof(double), st));
+        HIPCHK(hipMemsetAsync(vdrain, 0, n_total * sizeof(double), st));
         HIPCHK(hipMemsetAsync(steps, 0, n_total * sizeof(int64_t), st));
         HIPCHK(hipMemsetAsync(par, 0, n_total * sizeof(int32_t), st));
         HIPCHK(hipMemsetAsync(fault, 0, n_total * sizeof(int32_t), st));
@@ -413,7 +460,7 @@ template <typename T> struct Impl : ImplBase {
             pc.dt_fixed = c.p.dt_fixed;
             pc.g = c.p.g;
             pc.dx = c.dx;
-            pc.ncells = (double)c.ny * (double)c.nx;
+            pc.ncells = c.rain_cells;
         }
         PL.t_end = d_tend;
         PL.t = t;
@@ -429,6 +476,8 @@ template <typename T> struct Impl : ImplBase {
         PL.dtlog = nullptr;
         PL.telog = nullptr;
         PL.dtlog_cap = 0;
+        PL.clsn = any_land ? clsn : nullptr;
+        PL.drain = any_land ? drain : nullptr;
         PL.m_begin = 0;
         PL.m_end = n_total;
         PL.ms_log = nullptr;
@@ -459,7 +508,7 @@ template <typename T> struct Impl : ImplBase {
     flood_status autotune_geometry(const TuneKey& key, const flood_params* params, std::string& err) {
         TuneChoice cached;
         if (tune_lookup(key, mi, cached)) {
-            if (!params[0].step_kernel && mi == 1) variant = cached.variant;
+            if (!params[0].step_kernel && mi == 1 && !any_land) variant = cached.variant;
             if (!params[0].march_members) march_seg = cached.march_seg;
             march_order = cached.march_order;
             for (int i = 0; i < n_catch; ++i) {
@@ -522,8 +571,8 @@ template <typename T> struct Impl : ImplBase {
             int variant, rows, cpb, mrows, seg, order;
         };
         std::vector<Cand> cands;
-        const bool want1 = params[0].step_kernel == 0 || params[0].step_kernel == 1 || mi != 1;
-        const bool want2 = mi == 1 && (params[0].step_kernel == 0 || params[0].step_kernel == 2);
+        const bool want1 = !any_land && (params[0].step_kernel == 0 || params[0].step_kernel == 1 || mi != 1);
+        const bool want2 = !any_land && mi == 1 && (params[0].step_kernel == 0 || params[0].step_kernel == 2);
         const bool want3 = vector_ok() && (params[0].step_kernel == 0 || params[0].step_kernel == 3);
         if (want1)
             for (int r : {1, 2, 4, 8})
@@ -628,7 +677,7 @@ template <typename T> struct Impl : ImplBase {
         // only a search over the full candidate set is remembered: a handle that
         // pinned part of the geometry measured a subset, whose best need not be
         // the best for a later handle of the same shape
-        bool free_search = true;
+        bool free_search = !any_land;
         for (int i = 0; i < n_catch; ++i)
             free_search &= params[i].tile_rows == 0 && params[i].chunks_per_block == 0 &&
                            params[i].step_kernel == 0 && params[i].march_rows == 0 &&
@@ -831,6 +880,9 @@ template <typename T> struct Impl : ImplBase {
         a.anc = d_anc;
         a.neff = d_neff;
         a.flag = d_flag;
+        a.clsn = C.n_classes ? clsn + (size_t)off * kMaxClasses : nullptr;
+        a.drain = C.n_classes ? drain + off : nullptr;
+        a.vdrain = vdrain + off;
         launch_pf(a, st);
         launch_permute<T>(mi, C.dev, d_anc, d_src, d_dst, d_flag, st);
         if (C.dev.peak) launch_permute_peak<T>(mi, C.dev, d_anc, d_flag, C.peak_tmp, st);
@@ -938,6 +990,10 @@ template <typename T> struct Impl : ImplBase {
         CHK(check_catch(c, err));
         const Cat& C = cats[c];
         const size_t ncell = (size_t)C.ny * C.nx;
+        if (C.n_classes && (manning || n_scale)) {
+            err = "with land cover the roughness is per class and member; manning_n and n_scale do not apply";
+            return FLOOD_EINVAL;
+        }
         if (manning)
             for (size_t i = 0; i < ncell; ++i)
                 if (!(manning[i] > 0.0f) || !std::isfinite(manning[i])) { err = "manning_n must be finite and > 0"; return FLOOD_EINVAL; }
@@ -956,8 +1012,8 @@ template <typename T> struct Impl : ImplBase {
         return FLOOD_OK;
     }
 
-    flood_status get_ledger(int c, double* storage, double* rain_in, double* outflow, double* clamp, double* tt,
-                            int64_t* stp, std::string& err) override {
+    flood_status get_ledger(int c, double* storage, double* rain_in, double* outflow, double* clamp,
+                            double* drained, double* tt, int64_t* stp, std::string& err) override {
         CHK(check_catch(c, err));
         const Cat& C = cats[c];
         const int off = C.dev.member_off;
@@ -971,9 +1027,27 @@ template <typename T> struct Impl : ImplBase {
         if (rain_in) HIPCHK(hipMemcpyAsync(rain_in, vrain + off, C.N * sizeof(double), hipMemcpyDeviceToHost, st));
         if (outflow) HIPCHK(hipMemcpyAsync(outflow, vout + off, C.N * sizeof(double), hipMemcpyDeviceToHost, st));
         if (clamp) HIPCHK(hipMemcpyAsync(clamp, vclamp + off, C.N * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (drained) HIPCHK(hipMemcpyAsync(drained, vdrain + off, C.N * sizeof(double), hipMemcpyDeviceToHost, st));
         if (tt) HIPCHK(hipMemcpyAsync(tt, t + off, C.N * sizeof(double), hipMemcpyDeviceToHost, st));
         if (stp) HIPCHK(hipMemcpyAsync(stp, steps + off, C.N * sizeof(int64_t), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        return FLOOD_OK;
+    }
+
+    flood_status get_land_params(int c, double* cn, double* dr, std::string& err) override {
+        CHK(check_catch(c, err));
+        const Cat& C = cats[c];
+        if (!C.n_classes) { err = "this catchment has no land cover"; return FLOOD_ESTATE; }
+        const int off = C.dev.member_off;
+        HIPCHK(hipStreamSynchronize(st));
+        if (cn) {
+            std::vector<double> all((size_t)C.N * kMaxClasses);
+            HIPCHK(hipMemcpy(all.data(), clsn + (size_t)off * kMaxClasses, all.size() * sizeof(double),
+                             hipMemcpyDeviceToHost));
+            for (int m = 0; m < C.N; ++m)
+                for (int k = 0; k < C.n_classes; ++k) cn[(size_t)m * C.n_classes + k] = all[(size_t)m * kMaxClasses + k];
+        }
+        if (dr) HIPCHK(hipMemcpy(dr, drain + off, C.N * sizeof(double), hipMemcpyDeviceToHost));
         return FLOOD_OK;
     }
 
@@ -1019,6 +1093,9 @@ template <typename T> struct Impl : ImplBase {
         v.push_back({vout, n * 8});
         v.push_back({vclamp, n * 8});
         v.push_back({steps, n * 8});
+        v.push_back({clsn, n * kMaxClasses * 8});
+        v.push_back({drain, n * 8});
+        v.push_back({vdrain, n * 8});
         v.push_back({par, n * 4});
         v.push_back({fault, n * 4});
         v.push_back({hbins, (size_t)kBins * n * sizeof(HB)});
@@ -1032,6 +1109,7 @@ template <typename T> struct Impl : ImplBase {
             hd.push_back(C.nx);
             hd.push_back(C.N);
             hd.push_back(C.dev.peak ? 1 : 0);
+            hd.push_back(C.n_classes);
         }
     }
 
@@ -1237,6 +1315,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                               std::string& err) {
     CHK(check_catch(c, err));
     Cat& C = cats[c];
+    if (C.n_classes) { err = "the adjoint does not support land cover"; return FLOOD_EINVAL; }
     if (!(sample_dt > 0.0) || !finite_d(sample_dt)) { err = "sample_dt must be finite and > 0"; return FLOOD_EINVAL; }
     if (!finite_d(t_end)) { err = "t_end must be finite"; return FLOOD_EINVAL; }
     if (K < 0 || K > 4096) { err = "n_gauges must be in [0, 4096]"; return FLOOD_EINVAL; }
@@ -1459,7 +1538,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                         PLg.any_log = any_log + L;
                         PLg.tag_value = smp;
                         launch_plan<T>(PLg, st);
-                        launch_marchv<T>(SLm, march_nt, march_pf, tw, st);
+                        launch_marchv<T>(SLm, march_nt, march_pf, 0, tw, st);
                         ++L;
                     }
                     launch_count_active(Gg, t + off + g0, fault + off + g0, d_tend, status, d_count, st);

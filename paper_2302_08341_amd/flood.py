@@ -22,7 +22,8 @@ EDGE_WALL, EDGE_OPEN = 0, 1
 FIELD_H, FIELD_QX, FIELD_QY, FIELD_PEAK = 0, 1, 2, 3
 EXPORTED = ["flood_create", "flood_create_batch", "flood_step", "flood_assimilate", "flood_adjoint",
             "flood_get_field", "flood_set_state", "flood_set_params", "flood_get_ledger", "flood_get_weights",
-            "flood_systematic_resample", "flood_ensemble_products", "flood_save", "flood_load",
+            "flood_systematic_resample", "flood_ensemble_products", "flood_get_land_params", "flood_save",
+            "flood_load",
             "flood_get_config", "flood_timing", "flood_get_timing", "flood_last_error", "flood_strerror",
             "flood_destroy"]
 
@@ -40,7 +41,8 @@ _STATUS = {FLOOD_EINVAL: "EINVAL", FLOOD_ENOMEM: "ENOMEM", FLOOD_EHIP: "EHIP", F
 class FloodGrid(C.Structure):
     _fields_ = [("ny", C.c_int32), ("nx", C.c_int32), ("dx", C.c_double),
                 ("dem", C.POINTER(C.c_float)), ("manning_n", C.POINTER(C.c_float)), ("h0", C.POINTER(C.c_float)),
-                ("edge_kind", C.c_int32 * 4), ("edge_slope", C.c_double * 4)]
+                ("edge_kind", C.c_int32 * 4), ("edge_slope", C.c_double * 4),
+                ("land_class", C.POINTER(C.c_uint8))]
 
 
 class FloodParams(C.Structure):
@@ -49,7 +51,9 @@ class FloodParams(C.Structure):
                 ("dt_fixed", C.c_double), ("g", C.c_double), ("real_bytes", C.c_int32),
                 ("member_interleave", C.c_int32), ("tile_rows", C.c_int32), ("chunks_per_block", C.c_int32),
                 ("step_kernel", C.c_int32), ("march_rows", C.c_int32), ("march_members", C.c_int32),
-                ("track_peak", C.c_int32)]
+                ("track_peak", C.c_int32), ("n_classes", C.c_int32), ("class_runoff", C.POINTER(C.c_double)),
+                ("class_drain", C.POINTER(C.c_int32)), ("member_class_n", C.POINTER(C.c_double)),
+                ("member_drain", C.POINTER(C.c_double))]
 
 
 _lib = None
@@ -77,7 +81,8 @@ def load_library():
         "flood_get_field": [H, C.c_int32, C.c_int32, C.c_int32, dp],
         "flood_set_state": [H, C.c_int32, C.c_int32, dp, dp, dp, C.c_double],
         "flood_set_params": [H, C.c_int32, fp, dp, dp],
-        "flood_get_ledger": [H, C.c_int32, dp, dp, dp, dp, dp, lp],
+        "flood_get_ledger": [H, C.c_int32, dp, dp, dp, dp, dp, dp, lp],
+        "flood_get_land_params": [H, C.c_int32, dp, dp],
         "flood_get_weights": [H, C.c_int32, dp, dp, dp],
         "flood_systematic_resample": [dp, C.c_int32, C.c_double, ip, C.c_void_p],
         "flood_ensemble_products": [H, C.c_int32, C.c_double, C.c_int32, dp, dp, dp, dp],
@@ -141,24 +146,34 @@ def current_stream():
 # ---------------------------------------------------------------------------
 # C-named functions
 # ---------------------------------------------------------------------------
-def make_grid(dem, manning, dx, edge_kind=(0, 0, 0, 0), edge_slope=(0, 0, 0, 0), h0=None):
+def make_grid(dem, manning, dx, edge_kind=(0, 0, 0, 0), edge_slope=(0, 0, 0, 0), h0=None, land_class=None):
     dem, manning, h0 = _f32(dem), _f32(manning), _f32(h0)
     ny, nx = dem.shape
+    lc = None if land_class is None else np.ascontiguousarray(np.asarray(land_class, dtype=np.uint8))
     g = FloodGrid(ny, nx, float(dx), _fp(dem), _fp(manning), _fp(h0), (C.c_int32 * 4)(*edge_kind),
-                  (C.c_double * 4)(*[float(x) for x in edge_slope]))
-    g._keep = (dem, manning, h0)
+                  (C.c_double * 4)(*[float(x) for x in edge_slope]),
+                  lc.ctypes.data_as(C.POINTER(C.c_uint8)) if lc is not None else None)
+    g._keep = (dem, manning, h0, lc)
     return g
 
 
 def make_params(rain, rain_interval=300.0, cfl_alpha=0.7, h_dry=1e-3, dt_cap=10.0, dt_fixed=0.0, g=9.81,
                 real_bytes=4, member_interleave=0, tile_rows=0, chunks_per_block=0, step_kernel=0, march_rows=0,
-                march_members=0, track_peak=0):
+                march_members=0, track_peak=0, class_runoff=None, class_drain=None, member_class_n=None,
+                member_drain=None):
     rain = _f64(np.asarray(rain, dtype=np.float64).ravel())
+    rc = None if class_runoff is None else _f64(np.asarray(class_runoff, dtype=np.float64).ravel())
+    cd = None if class_drain is None else np.ascontiguousarray(np.asarray(class_drain, dtype=np.int32).ravel())
+    cn = None if member_class_n is None else _f64(np.asarray(member_class_n, dtype=np.float64).ravel())
+    md = None if member_drain is None else _f64(np.asarray(member_drain, dtype=np.float64).ravel())
     p = FloodParams(_dp(rain) if rain.size else None, int(rain.size), float(rain_interval), float(cfl_alpha),
                     float(h_dry), float(dt_cap), float(dt_fixed), float(g), int(real_bytes),
                     int(member_interleave), int(tile_rows), int(chunks_per_block), int(step_kernel),
-                    int(march_rows), int(march_members), int(bool(track_peak)))
-    p._keep = (rain,)
+                    int(march_rows), int(march_members), int(bool(track_peak)),
+                    0 if rc is None else int(rc.size), _dp(rc) if rc is not None else None,
+                    cd.ctypes.data_as(C.POINTER(C.c_int32)) if cd is not None else None,
+                    _dp(cn) if cn is not None else None, _dp(md) if md is not None else None)
+    p._keep = (rain, rc, cd, cn, md)
     return p
 
 
@@ -247,14 +262,21 @@ def flood_set_params(h, catchment, manning=None, n_scale=None, rain_mult=None):
 
 
 def flood_get_ledger(h, catchment, n_members):
-    out = {k: np.zeros(n_members) for k in ("storage", "rain_in", "outflow", "clamp", "t")}
+    out = {k: np.zeros(n_members) for k in ("storage", "rain_in", "outflow", "clamp", "drain", "t")}
     steps = np.zeros(n_members, dtype=np.int64)
     rc = load_library().flood_get_ledger(h, int(catchment), _dp(out["storage"]), _dp(out["rain_in"]),
-                                         _dp(out["outflow"]), _dp(out["clamp"]), _dp(out["t"]),
+                                         _dp(out["outflow"]), _dp(out["clamp"]), _dp(out["drain"]), _dp(out["t"]),
                                          steps.ctypes.data_as(C.POINTER(C.c_int64)))
     _check(rc, h)
     out["steps"] = steps
     return out
+
+
+def flood_get_land_params(h, catchment, n_members, n_classes):
+    cn = np.zeros(n_members * max(n_classes, 1))
+    dr = np.zeros(n_members)
+    _check(load_library().flood_get_land_params(h, int(catchment), _dp(cn), _dp(dr)), h)
+    return cn[:n_members * n_classes].reshape(n_members, n_classes), dr
 
 
 def flood_get_weights(h, catchment, n_members):
@@ -315,10 +337,11 @@ class FloodEnsemble:
         grids, params = [], []
         for c in self.catchments:
             grids.append(make_grid(c["dem"], c["manning"], c["dx"], c.get("edge_kind", (0, 0, 0, 0)),
-                                   c.get("edge_slope", (0, 0, 0, 0)), c.get("h0")))
+                                   c.get("edge_slope", (0, 0, 0, 0)), c.get("h0"), c.get("land_class")))
             params.append(make_params(rain, rain_interval, cfl_alpha, h_dry, dt_cap, dt_fixed, g, real_bytes,
                                       member_interleave, tile_rows, chunks_per_block, step_kernel, march_rows,
-                                      march_members, track_peak))
+                                      march_members, track_peak, c.get("class_runoff"), c.get("class_drain"),
+                                      c.get("class_n"), c.get("drain")))
         self._keep = (grids, params)
         self.stream = current_stream() if stream == "torch" else stream
         self.h = flood_create_batch(grids, params, [c["n_members"] for c in self.catchments],
@@ -332,8 +355,12 @@ class FloodEnsemble:
             if catchments is not None and i not in catchments:
                 continue
             n = c.n_members if members is None else members
-            cs.append(dict(dem=c.dem, manning=c.manning, dx=c.dx, edge_kind=c.edge_kind, edge_slope=c.edge_slope,
-                           h0=c.h0, n_members=n, n_scale=c.n_scale[:n], rain_mult=c.rain_mult[:n]))
+            d = dict(dem=c.dem, manning=c.manning, dx=c.dx, edge_kind=c.edge_kind, edge_slope=c.edge_slope,
+                     h0=c.h0, n_members=n, n_scale=c.n_scale[:n], rain_mult=c.rain_mult[:n])
+            if getattr(c, "land_class", None) is not None:
+                d.update(land_class=c.land_class, class_runoff=c.class_runoff, class_drain=c.class_drain,
+                         class_n=c.class_n[:n], drain=c.drain[:n])
+            cs.append(d)
         kw = dict(rain_interval=wl.rain_interval, cfl_alpha=wl.cfl_alpha, h_dry=wl.h_dry, dt_cap=wl.dt_cap,
                   dt_fixed=wl.dt_fixed, g=wl.g, real_bytes=wl.real_bytes)
         kw.update(over)
@@ -381,6 +408,12 @@ class FloodEnsemble:
 
     def weights(self, catchment=0):
         return flood_get_weights(self.h, catchment, self.n_members(catchment))
+
+    def land_params(self, catchment=0):
+        """(member class roughness [N, n_classes], member drainage rates [N]) of a land-cover catchment."""
+        c = self.catchments[catchment]
+        k = 0 if c.get("class_runoff") is None else len(c["class_runoff"])
+        return flood_get_land_params(self.h, catchment, self.n_members(catchment), k)
 
     def save(self, path):
         flood_save(self.h, path)
