@@ -26,6 +26,7 @@ region:
     (512^2, 768x1536, 1024^2, 2000^2, 24 members each) over its first 300 s;
   * the running maximum depth tracked through the first window (its cost) and
     the ensemble products of every cell (Sec. 4.4, Figs. 15-16);
+  * the same ensemble with land cover (Table 1) over its first window;
   * the streaming ceiling of one elementwise kernel (2 GiB in, 2 GiB out).
 
 The timed cycles run last among full-size launches of the step kernel, so
@@ -79,8 +80,18 @@ def cpu_baseline(cfg, cores, n_steps):
     ctx = mp.get_context("spawn")
     jobs = [(cfg, i % cfg["members"], n_steps) for i in range(cores)]
     t0 = time.perf_counter()
-    with ctx.Pool(cores) as pool:
+    # close and join rather than the context manager's terminate: the workers end
+    # on their own instead of by a signal (profilers that preload a library into
+    # every child can stall on a signalled exit)
+    pool = ctx.Pool(cores)
+    try:
         res = pool.map(_cpu_worker, jobs)
+        pool.close()
+    except BaseException:
+        pool.terminate()
+        raise
+    finally:
+        pool.join()
     wall = time.perf_counter() - t0
     mcu = sum(r[0] for r in res)
     busy = max(r[1] for r in res)
@@ -248,6 +259,29 @@ def leg_products(FloodEnsemble, wl, window):
             "cells_reaching_0.2m_in_any_member": int(np.count_nonzero(prob > 0))}
 
 
+def leg_land_cover(FloodEnsemble, W, args):
+    """The same grid and ensemble with land cover (Table 1): per-member class
+    roughness, runoff coefficient, drainage of hardened ground; first window."""
+    import torch
+    wl = W.config5(args.ny, args.nx, args.members, with_land_cover=True)
+    c = wl.catchments[0]
+    ncell = c.ny * c.nx
+    ens = FloodEnsemble.from_workload(wl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.step(args.window)
+    torch.cuda.synchronize()
+    t_step = time.perf_counter() - t0
+    led = ens.ledger()
+    steps = int(led["steps"].sum())
+    ens.close()
+    log("land cover leg: %.2f s, %d member steps" % (t_step, steps))
+    return {"workload": "first %.0f s of this ensemble with land cover (3 classes, %.0f %% hardened ground)"
+                        % (args.window, 100.0 * np.mean(c.land_class == W.CLASS_HARD)),
+            "MCUps": steps * ncell / t_step,
+            "drained_over_rain": float(led["drain"].sum() / led["rain_in"].sum())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +304,9 @@ def main():
     ap.add_argument("--plain-members", type=int, default=8)
     ap.add_argument("--no-c4", action="store_true")
     ap.add_argument("--no-products", action="store_true")
+    ap.add_argument("--no-land-cover", action="store_true")
+    ap.add_argument("--land-cover", action="store_true",
+                    help="with --kernel-only: the ensemble with land cover (Table 1)")
     ap.add_argument("--c4-window", type=float, default=300.0)
     ap.add_argument("--c4-plain-members", type=int, default=2)
     ap.add_argument("--mi", type=int, default=0)
@@ -296,12 +333,19 @@ def main():
         cpu = cpu_baseline(cfg, cores, args.cpu_steps)
         log("oracle baseline %.3e MCU/s" % cpu["value"])
 
+    if args.kernel_only:
+        # one step per call: batches of captured steps would add launches with no member left to step
+        os.environ["FLOOD_GRAPH_STEPS"] = "1"
     import torch
     import workloads as W
     from paper_2302_08341_amd import FloodEnsemble
 
     torch.cuda.set_device(0)
-    wl = W.CONFIGS[args.config](args.ny, args.nx, args.members)
+    if args.land_cover and not args.kernel_only:
+        ap.error("--land-cover times the step kernel only (with --kernel-only); the benchmark line "
+                 "carries the land-cover leg in detail")
+    wl = (W.config5(args.ny, args.nx, args.members, with_land_cover=True) if args.land_cover
+          else W.CONFIGS[args.config](args.ny, args.nx, args.members))
     c = wl.catchments[0]
     N = c.n_members
     ncell = c.ny * c.nx
@@ -330,6 +374,8 @@ def main():
         detail["batched_vs_plain_c4"] = leg_c4(FloodEnsemble, W, args.c4_window, args.c4_plain_members)
     if not args.no_products and not args.kernel_only:
         detail["ensemble_products"] = leg_products(FloodEnsemble, wl, args.window)
+    if not args.no_land_cover and not args.kernel_only and args.config == 5:
+        detail["land_cover"] = leg_land_cover(FloodEnsemble, W, args)
 
     ens = FloodEnsemble.from_workload(wl, member_interleave=args.mi, tile_rows=args.rows,
                                       chunks_per_block=args.cpb, step_kernel=args.kernel,

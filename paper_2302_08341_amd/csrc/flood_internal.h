@@ -75,6 +75,7 @@ template <typename T> struct CatchDev {
     // land cover (row-march kernel only): class map, runoff coefficient per class,
     // bit k of drain_mask set when class k drains; cls null: shared Manning field
     const uint8_t* cls;
+    double* drain_acc;        // [n_members][kBins] drained volume, one bin per workgroup id mod kBins
     T class_rc[kMaxClasses];
     int32_t drain_mask;
 };
@@ -88,7 +89,6 @@ template <typename T> struct StepLaunch {
     const MemberStep<T>* ms;  // indexed by global member
     typename HBits<T>::type* hbins;  // [kBins][n_total]
     double* vclamp;           // [n_total]
-    double* vdrain;           // [n_total] drained volume (land cover)
     uint8_t* clamp_out;       // recompute only: 1 where the new depth was clamped at zero
     // tape recomputation by the row-march kernel: c[0]'s copy-0 arrays are tape
     // slot 0; a member reads slot ms.slot and writes slot ms.slot + 1, and its

@@ -1058,7 +1058,10 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
         if (lc) {
             double dr = (double)vdr;
             for (int off = 32; off > 0; off >>= 1) dr += __shfl_xor(dr, off, 64);
-            if (lane == 0 && dr != 0.0) atomicAdd(&L.vdrain[C.member_off + k], dr * (C.dx * C.dx));
+            // spread over kBins accumulators per member: the wavefronts in flight
+            // mostly belong to one member, so a single address would serialise them
+            if (lane == 0 && dr != 0.0)
+                atomicAdd(C.drain_acc + (size_t)k * kBins + (blockIdx.x & (kBins - 1)), dr * (C.dx * C.dx));
         }
         if (lane == 0) {
             if (vmax != 0) {

@@ -166,7 +166,6 @@ template <typename T> struct Impl : ImplBase {
         SL.ms = ms;
         SL.hbins = hbins;
         SL.vclamp = vclamp;
-        SL.vdrain = vdrain;
     }
 
     void launch_steps(const StepLaunch<T>& L) {
@@ -265,6 +264,10 @@ template <typename T> struct Impl : ImplBase {
                 err = "land cover needs member_interleave 1 and nx a multiple of " + std::to_string(march_vec<T>());
                 return FLOOD_EINVAL;
             }
+            if (params[0].step_kernel == 1 || params[0].step_kernel == 2) {
+                err = "land cover runs on step kernel 3 only";
+                return FLOOD_EINVAL;
+            }
             variant = 3;
         }
         for (int i = 0; i < nc; ++i) {
@@ -325,6 +328,7 @@ template <typename T> struct Impl : ImplBase {
             // land cover: class map, runoff coefficients, draining classes
             c.n_classes = (grids[i].land_class && params[i].n_classes > 0) ? params[i].n_classes : 0;
             d.cls = nullptr;
+            d.drain_acc = nullptr;
             d.drain_mask = 0;
             for (int k = 0; k < kMaxClasses; ++k) d.class_rc[k] = T(1);
             c.rain_cells = (double)ncell;
@@ -333,6 +337,8 @@ template <typename T> struct Impl : ImplBase {
                 CHK(dalloc(&dc, ncell, err));
                 HIPCHK(hipMemcpy(dc, grids[i].land_class, ncell, hipMemcpyHostToDevice));
                 d.cls = dc;
+                CHK(dalloc(&d.drain_acc, (size_t)c.N * kBins, err));
+                HIPCHK(hipMemsetAsync(d.drain_acc, 0, (size_t)c.N * kBins * sizeof(double), st));
                 for (int k = 0; k < c.n_classes; ++k) {
                     d.class_rc[k] = (T)params[i].class_runoff[k];
                     if (params[i].class_drain[k]) d.drain_mask |= 1 << k;
@@ -546,12 +552,17 @@ template <typename T> struct Impl : ImplBase {
         std::vector<std::vector<HB>> bins_saved(1);
         bins_saved[0].resize((size_t)kBins * n_total);
         HIPCHK(hipMemcpy(bins_saved[0].data(), hbins, bins_saved[0].size() * sizeof(HB), hipMemcpyDeviceToHost));
-        // the outflow accumulators are touched by trial steps: fold them first, restore after
-        std::vector<std::vector<double>> acc_saved(n_catch);
+        // the outflow and drainage accumulators are touched by trial steps: save, restore after
+        std::vector<std::vector<double>> acc_saved(n_catch), dacc_saved(n_catch);
         for (int i = 0; i < n_catch; ++i) {
             const size_t n = (size_t)cats[i].N * 2 * (cats[i].nx + cats[i].ny);
             acc_saved[i].resize(n);
             HIPCHK(hipMemcpy(acc_saved[i].data(), cats[i].dev.out_acc, n * sizeof(double), hipMemcpyDeviceToHost));
+            if (cats[i].dev.drain_acc) {
+                dacc_saved[i].resize((size_t)cats[i].N * kBins);
+                HIPCHK(hipMemcpy(dacc_saved[i].data(), cats[i].dev.drain_acc, dacc_saved[i].size() * sizeof(double),
+                                 hipMemcpyDeviceToHost));
+            }
         }
         // trial launches must not touch the running maxima
         std::vector<T*> peaks(n_catch);
@@ -663,9 +674,13 @@ template <typename T> struct Impl : ImplBase {
         HIPCHK(hipMemcpy(ms, saved.data(), n_total * sizeof(MemberStep<T>), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(vclamp, saved_clamp.data(), n_total * sizeof(double), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(hbins, bins_saved[0].data(), bins_saved[0].size() * sizeof(HB), hipMemcpyHostToDevice));
-        for (int i = 0; i < n_catch; ++i)
+        for (int i = 0; i < n_catch; ++i) {
             HIPCHK(hipMemcpy(cats[i].dev.out_acc, acc_saved[i].data(), acc_saved[i].size() * sizeof(double),
                              hipMemcpyHostToDevice));
+            if (cats[i].dev.drain_acc)
+                HIPCHK(hipMemcpy(cats[i].dev.drain_acc, dacc_saved[i].data(), dacc_saved[i].size() * sizeof(double),
+                                 hipMemcpyHostToDevice));
+        }
         TuneChoice c;
         c.mi = mi;
         c.tile_rows = bc.rows;
@@ -850,6 +865,7 @@ template <typename T> struct Impl : ImplBase {
         const int off = C.dev.member_off;
         const int nb = 2 * (C.nx + C.ny);
         launch_flush_outflow(C.N, nb, C.dev.out_acc, vout + off, st);
+        if (C.dev.drain_acc) launch_flush_outflow(C.N, kBins, C.dev.drain_acc, vdrain + off, st);
         if (K > 0) {
             HIPCHK(hipMemcpyAsync(d_grc, grc, 2 * K * sizeof(int32_t), hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(d_obs, obs, K * sizeof(double), hipMemcpyHostToDevice, st));
@@ -1018,6 +1034,7 @@ template <typename T> struct Impl : ImplBase {
         const Cat& C = cats[c];
         const int off = C.dev.member_off;
         launch_flush_outflow(C.N, 2 * (C.nx + C.ny), C.dev.out_acc, vout + off, st);
+        if (C.dev.drain_acc) launch_flush_outflow(C.N, kBins, C.dev.drain_acc, vdrain + off, st);
         if (storage) {
             HIPCHK(hipMemsetAsync(d_stage, 0, C.N * sizeof(double), st));
             launch_storage<T>(mi, C.dev, par, d_stage, st);
@@ -1082,6 +1099,7 @@ template <typename T> struct Impl : ImplBase {
             }
             v.push_back({const_cast<T*>(C.dev.n), (size_t)C.ny * C.nx * sizeof(T)});
             v.push_back({C.dev.out_acc, (size_t)C.N * 2 * (C.nx + C.ny) * sizeof(double)});
+            if (C.dev.drain_acc) v.push_back({C.dev.drain_acc, (size_t)C.N * kBins * sizeof(double)});
             if (C.dev.peak) v.push_back({C.dev.peak, C.state_elems * sizeof(T)});
         }
         const size_t n = n_total;

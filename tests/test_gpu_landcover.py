@@ -177,6 +177,10 @@ def test_refusals(fl):
     with pytest.raises(fl.FloodError) as ex:
         fl.flood_set_params(e.h, 0, np.full(CAT.dem.shape, 0.03, np.float32), None, None)
     assert ex.value.status == fl.FLOOD_EINVAL
+    for kw in (dict(step_kernel=1), dict(step_kernel=2), dict(member_interleave=4)):
+        with pytest.raises(fl.FloodError) as ex:
+            _ens(fl, real_bytes=4, **kw)
+        assert ex.value.status == fl.FLOOD_EINVAL
     plain = fl.FloodEnsemble([dict(dem=CAT.dem, manning=CAT.manning, dx=CAT.dx, n_members=2)], RAIN, real_bytes=4)
     with pytest.raises(fl.FloodError) as ex:
         plain.land_params()
