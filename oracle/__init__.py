@@ -45,7 +45,9 @@ class _Model(C.Structure):
                 ("alpha", C.c_double), ("h_dry", C.c_double), ("dt_cap", C.c_double),
                 ("dt_fixed", C.c_double), ("g", C.c_double), ("wet_fp32", C.c_int32),
                 ("cls", C.POINTER(C.c_uint8)), ("n_classes", C.c_int32),
-                ("class_runoff", C.POINTER(C.c_double)), ("class_drain", C.POINTER(C.c_int32))]
+                ("class_runoff", C.POINTER(C.c_double)), ("class_drain", C.POINTER(C.c_int32)),
+                ("n_inflow", C.c_int32), ("inflow", C.POINTER(C.c_int32)), ("inflow_q", C.POINTER(C.c_double)),
+                ("n_series", C.c_int32)]
 
 
 class _Member(C.Structure):
@@ -53,7 +55,8 @@ class _Member(C.Structure):
                 ("t", C.c_double), ("s", C.c_double), ("mu", C.c_double),
                 ("v_rain", C.c_double), ("v_out", C.c_double), ("v_clamp", C.c_double),
                 ("steps", C.c_int64), ("hmax", C.POINTER(C.c_double)),
-                ("class_n", C.POINTER(C.c_double)), ("drain_rate", C.c_double), ("v_drain", C.c_double)]
+                ("class_n", C.POINTER(C.c_double)), ("drain_rate", C.c_double), ("v_drain", C.c_double),
+                ("v_in", C.c_double)]
 
 
 _lib = None
@@ -78,6 +81,8 @@ def _load():
         lib.orc_storage.argtypes = [Mp, dp]
         lib.orc_pf_weights.argtypes = [C.c_int32, C.c_int32, dp, dp, dp, dp, dp, dp, dp]
         lib.orc_systematic.argtypes = [C.c_int32, dp, C.c_double, ip]
+        lib.orc_section_flow.argtypes = [Mp, dp, dp, C.c_int32, ip, dp]
+        lib.orc_obs_sigma.argtypes = [C.c_int32, dp, dp, C.c_double, dp]
         lib.orc_pf.argtypes = [C.c_int32, C.c_int32, dp, dp, dp, dp, C.c_double, C.c_double, dp, ip, ip]
         lib.orc_loss.argtypes = [Mp, Sp, C.c_double, C.c_double, C.c_int32, ip, dp, dp, dp, C.c_int64, dp]
         lib.orc_adjoint.argtypes = [Mp, Sp, C.c_double, C.c_double, C.c_int32, ip, dp, C.c_int32, dp, dp, dp,
@@ -105,7 +110,7 @@ class Model:
 
     def __init__(self, dem, manning, dx, rain, rain_interval=300.0, edge_kind=(0, 0, 0, 0),
                  edge_slope=(0.0, 0.0, 0.0, 0.0), alpha=0.7, h_dry=1e-3, dt_cap=10.0, dt_fixed=0.0, g=9.81,
-                 wet_fp32=False, land_class=None, class_runoff=None, class_drain=None):
+                 wet_fp32=False, land_class=None, class_runoff=None, class_drain=None, inflow=None, inflow_q=None):
         """wet_fp32: take each link's wet/dry decision in single precision (flow depth
         in difference form, rounded to float, against h_dry rounded to float), as a
         single-precision model does; for comparisons from the same float state.
@@ -114,7 +119,12 @@ class Model:
         class_drain [n_classes] switch on land cover (Sec. 4.1, Table 1): each member
         then carries its own Manning n per class and a drainage rate (Member.class_n,
         Member.drain_rate), rain is scaled by the cell's runoff coefficient, and
-        draining classes lose water at the member's rate, up to what they hold."""
+        draining classes lose water at the member's rate, up to what they hold.
+
+        inflow [n, 3] (edge N=0 E=1 S=2 W=3, position along the edge, series index)
+        and inflow_q [n_series, n_rain] (inward discharge per unit width, m^2/s,
+        piecewise constant over the rain blocks) prescribe inflow hydrographs on
+        edge links (Sec. 4.1)."""
         self.z = _f64(dem)
         self.n = _f64(manning)
         self.ny, self.nx = self.z.shape
@@ -138,11 +148,20 @@ class Model:
             self.cls = None
             self.n_classes = 0
             cls_p, rc_p, dr_p = C.POINTER(C.c_uint8)(), C.POINTER(C.c_double)(), C.POINTER(C.c_int32)()
+        if inflow is not None and len(inflow) > 0:
+            self.inflow = np.ascontiguousarray(np.asarray(inflow, dtype=np.int32).reshape(-1, 3))
+            self.inflow_q = np.ascontiguousarray(np.asarray(inflow_q, dtype=np.float64))
+            assert self.inflow_q.ndim == 2 and self.inflow_q.shape[1] == n_rain
+            inf_p, infq_p = _ip(self.inflow), _dp(self.inflow_q)
+            n_inf, n_ser = self.inflow.shape[0], self.inflow_q.shape[0]
+        else:
+            self.inflow = self.inflow_q = None
+            inf_p, infq_p, n_inf, n_ser = C.POINTER(C.c_int32)(), C.POINTER(C.c_double)(), 0, 0
         self._m = _Model(self.ny, self.nx, self.dx, _dp(self.z), _dp(self.n),
                          (C.c_int32 * 4)(*edge_kind), (C.c_double * 4)(*edge_slope),
                          _dp(self.rain), n_rain, float(rain_interval), float(alpha), float(h_dry),
                          float(dt_cap), float(dt_fixed), float(g), int(bool(wet_fp32)),
-                         cls_p, int(self.n_classes), rc_p, dr_p)
+                         cls_p, int(self.n_classes), rc_p, dr_p, n_inf, inf_p, infq_p, n_ser)
         self.edge_kind = tuple(edge_kind)
         self.edge_slope = tuple(edge_slope)
         self.h_dry = h_dry
@@ -155,6 +174,8 @@ class Model:
                   alpha=wl.cfl_alpha, h_dry=wl.h_dry, dt_cap=wl.dt_cap, dt_fixed=wl.dt_fixed, g=wl.g)
         if getattr(c, "land_class", None) is not None:
             kw.update(land_class=c.land_class, class_runoff=c.class_runoff, class_drain=c.class_drain)
+        if getattr(c, "inflow", None) is not None:
+            kw.update(inflow=c.inflow, inflow_q=c.inflow_q)
         kw.update(over)
         return cls(c.dem, c.manning, c.dx, wl.rain, **kw)
 
@@ -180,6 +201,7 @@ class Member:
     class_n: Optional[np.ndarray] = None  # land cover: this member's Manning n per class
     drain_rate: float = 0.0               # land cover: drainage rate, m/s
     v_drain: float = 0.0
+    v_in: float = 0.0                     # volume entered through inflow links
 
     @classmethod
     def dry(cls, model: Model, s=1.0, mu=1.0, h0=None, track_max=False, class_n=None, drain_rate=0.0):
@@ -193,7 +215,8 @@ class Member:
         return Member(self.h.copy(), self.qx.copy(), self.qy.copy(), self.t, self.s, self.mu, self.v_rain,
                       self.v_out, self.v_clamp, self.steps, list(self.dt_log),
                       None if self.hmax is None else self.hmax.copy(),
-                      None if self.class_n is None else self.class_n.copy(), self.drain_rate, self.v_drain)
+                      None if self.class_n is None else self.class_n.copy(), self.drain_rate, self.v_drain,
+                      self.v_in)
 
     def _c(self):
         for a in (self.h, self.qx, self.qy):
@@ -203,11 +226,13 @@ class Member:
         hm = _dp(self.hmax) if self.hmax is not None else C.POINTER(C.c_double)()
         cn = _dp(self.class_n) if self.class_n is not None else C.POINTER(C.c_double)()
         return _Member(_dp(self.h), _dp(self.qx), _dp(self.qy), self.t, self.s, self.mu, self.v_rain,
-                       self.v_out, self.v_clamp, self.steps, hm, cn, float(self.drain_rate), self.v_drain)
+                       self.v_out, self.v_clamp, self.steps, hm, cn, float(self.drain_rate), self.v_drain,
+                       self.v_in)
 
     def _back(self, cm):
         self.t, self.v_rain, self.v_out, self.v_clamp, self.steps = cm.t, cm.v_rain, cm.v_out, cm.v_clamp, cm.steps
         self.v_drain = cm.v_drain
+        self.v_in = cm.v_in
 
 
 def dt_cfl(model: Model, h) -> float:
@@ -245,10 +270,34 @@ def storage(model: Model, h) -> float:
     return _load().orc_storage(model.ptr, _dp(h))
 
 
-def pf_weights(y, d, sigma, logw_prior):
+def section_flow(model: Model, mem: Member, links) -> float:
+    """Streamflow through a section (Sec. 4.4), m^3/s: links [n, 4] = (kind 0 x-link /
+    1 y-link, r, c, sign) in the oracle's link indexing."""
+    l = np.ascontiguousarray(np.asarray(links, dtype=np.int32).reshape(-1, 4))
+    out = C.c_double(0.0)
+    rc = _load().orc_section_flow(model.ptr, _dp(mem.qx), _dp(mem.qy), l.shape[0], _ip(l), C.byref(out))
+    if rc:
+        raise ValueError("orc_section_flow failed: %d" % rc)
+    return out.value
+
+
+def obs_sigma(d, floor, alpha: float) -> np.ndarray:
+    """Eq. 9's standard deviations: max(alpha |d_k|, floor_k) (alpha = 0: floor_k)."""
+    d, floor = _f64(d).ravel(), _f64(floor).ravel()
+    out = np.zeros(d.size)
+    rc = _load().orc_obs_sigma(d.size, _dp(d), _dp(floor), float(alpha), _dp(out))
+    if rc:
+        raise ValueError("orc_obs_sigma failed: %d" % rc)
+    return out
+
+
+def pf_weights(y, d, sigma, logw_prior, alpha: float = 0.0):
+    """Posterior log-weights, weights and N_eff; sigma is the floor of the relative
+    standard deviation when alpha > 0 (obs_sigma)."""
     y = _f64(y)
     N, K = y.shape
-    d, sigma, lw = _f64(d), _f64(sigma), _f64(logw_prior)
+    d, lw = _f64(d), _f64(logw_prior)
+    sigma = obs_sigma(d, sigma, alpha) if alpha > 0.0 else _f64(sigma)
     lp = np.zeros(N)
     w = np.zeros(N)
     neff = C.c_double(0.0)
@@ -267,11 +316,13 @@ def systematic(w, u0: float) -> np.ndarray:
     return anc
 
 
-def pf(y, d, sigma, logw, neff_frac: float, u0: float):
-    """Filter update; returns (new logw, neff, ancestors, resampled)."""
+def pf(y, d, sigma, logw, neff_frac: float, u0: float, alpha: float = 0.0):
+    """Filter update; returns (new logw, neff, ancestors, resampled).  alpha > 0:
+    relative standard deviations with sigma as their floor (obs_sigma)."""
     y = _f64(y)
     N, K = y.shape
-    d, sigma = _f64(d), _f64(sigma)
+    d = _f64(d)
+    sigma = obs_sigma(d, sigma, alpha) if alpha > 0.0 else _f64(sigma)
     lw = _f64(logw).copy()
     neff = C.c_double(0.0)
     anc = np.zeros(N, dtype=np.int32)
@@ -302,10 +353,15 @@ class Ensemble:
     def advance(self, t_end: float, log_dt=False):
         return [advance(self.model, m, t_end, log_dt=log_dt) for m in self.members]
 
-    def assimilate(self, gauges, obs, sigma, neff_frac, u0, beta=None):
-        """Filter cycle steps I-V of Sec. 3.3: gauge values, weights, N_eff, resampling, replacement."""
+    def assimilate(self, gauges, obs, sigma, neff_frac, u0, beta=None, sections=(), alpha=0.0):
+        """Filter cycle steps I-V of Sec. 3.3: gauge values, weights, N_eff, resampling, replacement.
+        sections: streamflow sections (links as in section_flow) observed after the
+        depth gauges; obs and sigma then hold the depths first, then the flows."""
         y = gauge_values(self.members, gauges)
-        lw, neff, anc, res = pf(y, obs, sigma, self.logw, neff_frac, u0)
+        if len(sections):
+            yq = np.array([[section_flow(self.model, m, sec) for sec in sections] for m in self.members])
+            y = np.concatenate([y, yq], axis=1)
+        lw, neff, anc, res = pf(y, obs, sigma, self.logw, neff_frac, u0, alpha)
         self.logw = lw
         if res:
             old = [m.copy() for m in self.members]

@@ -54,6 +54,14 @@ typedef struct {
     int32_t n_classes;
     const double* class_runoff; /* [n_classes] fraction of the rain that stays on the surface */
     const int32_t* class_drain; /* [n_classes] 1: the member's drainage rate applies to the class */
+    /* inflow hydrographs (Sec. 4.1): edge links with a prescribed discharge into
+     * the domain, taken from series that are piecewise constant over the rain
+     * blocks (zero outside them); an inflow link replaces the edge's wall or open
+     * condition on that link */
+    int32_t n_inflow;
+    const int32_t* inflow;     /* [n_inflow][3]: edge (N, E, S, W), position along it, series index */
+    const double* inflow_q;    /* [n_series][n_rain] inward discharge per unit width, m^2/s */
+    int32_t n_series;
 } orc_model;
 
 typedef struct {
@@ -69,6 +77,7 @@ typedef struct {
     const double* class_n;     /* land cover: [n_classes] this member's Manning n of each class */
     double drain_rate;         /* land cover: drainage rate of draining classes, m/s */
     double v_drain;            /* drained volume */
+    double v_in;               /* volume that entered through inflow links */
 } orc_member;
 
 /* ------------------------------------------------------------------------ */
@@ -153,8 +162,22 @@ static double link_open(const orc_model* m, double s, double qo, double hi, doub
     return fmax(qn, 0.0);
 }
 
-/* All new link discharges from the old state (h, qx, qy).  Returns the
- * outflow volume leaving through open edges during dt. */
+/* Inward discharge of the edge link at position pos of edge e at time t, or -1
+ * when the link is no inflow link (inflow discharges are >= 0). */
+static double inflow_at(const orc_model* m, int e, int pos, double t) {
+    for (int32_t k = 0; k < m->n_inflow; ++k) {
+        const int32_t* f = m->inflow + 3 * (int64_t)k;
+        if (f[0] != e || f[1] != pos) continue;
+        double jf = floor(t / m->rain_interval);
+        if (jf < 0.0 || jf >= (double)m->n_rain) return 0.0;
+        return m->inflow_q[(int64_t)f[2] * m->n_rain + (int64_t)jf];
+    }
+    return -1.0;
+}
+
+/* All new link discharges from the old state (h, qx, qy) at time t.  Returns
+ * the outflow volume leaving through open edges during dt; the volume entering
+ * through inflow links is added to *vin. */
 /* Manning n of cell i for one member: the shared field (scaled at the link by
  * the member's factor s) or, with land-cover classes, the member's value for
  * the cell's class (Table 1), unscaled. */
@@ -163,7 +186,7 @@ static double cell_rough(const orc_model* m, const double* class_n, int64_t i) {
 }
 
 static double links_all(const orc_model* m, double s, const double* class_n, const double* h, const double* qx,
-                        const double* qy, double dt, double* qxn, double* qyn) {
+                        const double* qy, double dt, double t, double* qxn, double* qyn, double* vin) {
     if (m->cls) s = 1.0;
     const int ny = m->ny, nx = m->nx;
     const double dx = m->dx;
@@ -171,7 +194,11 @@ static double links_all(const orc_model* m, double s, const double* class_n, con
     for (int r = 0; r < ny; ++r) {
         for (int c = 0; c <= nx; ++c) {
             int64_t li = (int64_t)r * (nx + 1) + c;
-            if (c == 0) {
+            if ((c == 0 || c == nx) && inflow_at(m, c == 0 ? EDGE_W : EDGE_E, r, t) >= 0.0) {
+                double qi = inflow_at(m, c == 0 ? EDGE_W : EDGE_E, r, t);
+                qxn[li] = c == 0 ? qi : -qi;
+                *vin += qi * dx * dt;
+            } else if (c == 0) {
                 int64_t i = (int64_t)r * nx;
                 double qo = 0.0;
                 if (m->edge_kind[EDGE_W] == EDGE_OPEN)
@@ -195,7 +222,11 @@ static double links_all(const orc_model* m, double s, const double* class_n, con
     for (int r = 0; r <= ny; ++r) {
         for (int c = 0; c < nx; ++c) {
             int64_t li = (int64_t)r * nx + c;
-            if (r == 0) {
+            if ((r == 0 || r == ny) && inflow_at(m, r == 0 ? EDGE_N : EDGE_S, c, t) >= 0.0) {
+                double qi = inflow_at(m, r == 0 ? EDGE_N : EDGE_S, c, t);
+                qyn[li] = r == 0 ? qi : -qi;
+                *vin += qi * dx * dt;
+            } else if (r == 0) {
                 int64_t i = c;
                 double qo = 0.0;
                 if (m->edge_kind[EDGE_N] == EDGE_OPEN)
@@ -269,7 +300,7 @@ static void scratch_free(orc_scratch* w) {
 static void step_core(const orc_model* m, orc_member* st, double dt, orc_scratch* w) {
     const int64_t nc = (int64_t)m->ny * m->nx;
     const double area = m->dx * m->dx;
-    st->v_out += links_all(m, st->s, st->class_n, st->h, st->qx, st->qy, dt, w->qxn, w->qyn);
+    st->v_out += links_all(m, st->s, st->class_n, st->h, st->qx, st->qy, dt, st->t, w->qxn, w->qyn, &st->v_in);
     double rain_depth = st->mu * rain_at(m, st->t) * dt;
     continuity_unclamped(m, st->h, w->qxn, w->qyn, dt, rain_depth, w->hu);
     double rain_cells = 0.0;
@@ -302,6 +333,16 @@ static int model_valid(const orc_model* m) {
     if (m->n_rain < 0 || (m->n_rain > 0 && !m->rain)) return 0;
     if (!(m->dt_fixed > 0.0) && (!(m->alpha > 0.0) || !(m->dt_cap > 0.0))) return 0;
     if (m->cls && (m->n_classes < 1 || m->n_classes > 8 || !m->class_runoff || !m->class_drain)) return 0;
+    if (m->n_inflow < 0 || (m->n_inflow > 0 && (!m->inflow || !m->inflow_q || m->n_series < 1))) return 0;
+    for (int32_t k = 0; k < m->n_inflow; ++k) {
+        const int32_t* f = m->inflow + 3 * (int64_t)k;
+        const int32_t len = (f[0] == EDGE_N || f[0] == EDGE_S) ? m->nx : m->ny;
+        if (f[0] < 0 || f[0] > 3 || f[1] < 0 || f[1] >= len || f[2] < 0 || f[2] >= m->n_series) return 0;
+        for (int32_t j = 0; j < k; ++j)
+            if (m->inflow[3 * j] == f[0] && m->inflow[3 * j + 1] == f[1]) return 0;
+    }
+    for (int64_t j = 0; j < (int64_t)m->n_series * m->n_rain; ++j)
+        if (!(m->inflow_q[j] >= 0.0)) return 0;
     return 1;
 }
 
@@ -357,6 +398,45 @@ double orc_storage(const orc_model* m, const double* h) {
     int64_t nc = (int64_t)m->ny * m->nx;
     for (int64_t i = 0; i < nc; ++i) s += h[i] * m->dx * m->dx;
     return s;
+}
+
+/* Streamflow through a section (Sec. 4.4): the discharges of the links that
+ * cross it, accumulated with the orientation of each link, times the cell
+ * width.  links [n_links][4]: kind (0 x-link, 1 y-link), r, c in the link
+ * indexing of this file (x-link (r, c), c = 0..nx; y-link (r, c), r = 0..ny),
+ * sign (+1 or -1).  Returns m^3/s. */
+int orc_section_flow(const orc_model* m, const double* qx, const double* qy, int32_t n_links, const int32_t* links,
+                     double* q_out) {
+    if (!m || n_links < 0 || (n_links > 0 && !links) || !q_out) return ORC_EINVAL;
+    double acc = 0.0;
+    for (int32_t k = 0; k < n_links; ++k) {
+        const int32_t* l = links + 4 * (int64_t)k;
+        double q;
+        if (l[0] == 0 && l[1] >= 0 && l[1] < m->ny && l[2] >= 0 && l[2] <= m->nx)
+            q = qx[(int64_t)l[1] * (m->nx + 1) + l[2]];
+        else if (l[0] == 1 && l[1] >= 0 && l[1] <= m->ny && l[2] >= 0 && l[2] < m->nx)
+            q = qy[(int64_t)l[1] * m->nx + l[2]];
+        else
+            return ORC_EINVAL;
+        if (l[3] != 1 && l[3] != -1) return ORC_EINVAL;
+        acc += (double)l[3] * q;
+    }
+    *q_out = acc * m->dx;
+    return ORC_OK;
+}
+
+/* Observation standard deviations of Eq. 9's diagonal covariance.  alpha > 0:
+ * relative to the observed value (Sec. 4.4 uses 5 % of each observation),
+ * sigma_k = alpha |d_k|, bounded below by floor_k so that an observation of zero
+ * keeps a finite likelihood; alpha = 0: sigma_k = floor_k. */
+int orc_obs_sigma(int32_t K, const double* d, const double* floor_, double alpha, double* sigma) {
+    if (K < 0 || !(alpha >= 0.0)) return ORC_EINVAL;
+    for (int32_t k = 0; k < K; ++k) {
+        double rel = alpha * fabs(d[k]);
+        sigma[k] = rel > floor_[k] ? rel : floor_[k];
+        if (!(sigma[k] > 0.0)) return ORC_EINVAL;
+    }
+    return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -544,7 +624,8 @@ static void adj_step(const orc_model* m, double s, double mu, const double* h, c
     const int64_t nc = (int64_t)ny * nx;
     const double R = rain_at(m, t);
     /* forward recomputation to recover the clamp branch */
-    links_all(m, s, NULL, h, qx, qy, dt, a->w.qxn, a->w.qyn);
+    double vin = 0.0;          /* no inflow links here: the adjoint refuses them */
+    links_all(m, s, NULL, h, qx, qy, dt, t, a->w.qxn, a->w.qyn, &vin);
     continuity_unclamped(m, h, a->w.qxn, a->w.qyn, dt, mu * R * dt, a->w.hu);
     double gm = 0.0;
     for (int64_t i = 0; i < nc; ++i) {
@@ -743,7 +824,7 @@ static int forward_loss(const orc_model* m, orc_member* st, double t_end, double
 int orc_loss(const orc_model* m, orc_member* st, double t_end, double sample_dt, int32_t K,
              const int32_t* grc, const double* obs, const double* replay_dt, const double* replay_tend,
              int64_t n_replay, double* loss) {
-    if (!model_valid(m) || !st || !(sample_dt > 0.0)) return ORC_EINVAL;
+    if (!model_valid(m) || !st || !(sample_dt > 0.0) || m->n_inflow) return ORC_EINVAL;
     orc_record rp = {n_replay, n_replay, (double*)replay_dt, (double*)replay_tend, NULL};
     return forward_loss(m, st, t_end, sample_dt, K, grc, obs, replay_dt ? &rp : NULL, NULL, loss, NULL,
                         1, NULL);
@@ -759,7 +840,7 @@ int orc_loss(const orc_model* m, orc_member* st, double t_end, double sample_dt,
 int orc_adjoint(const orc_model* m, orc_member* st, double t_end, double sample_dt, int32_t K,
                 const int32_t* grc, const double* obs, int32_t ckpt_every, double* loss, double* grad_n,
                 double* grad_mu, double* dt_out, double* tend_out, int64_t out_cap, int64_t* n_steps_out) {
-    if (!model_valid(m) || !st || !(sample_dt > 0.0) || ckpt_every < 1 || m->cls) return ORC_EINVAL;
+    if (!model_valid(m) || !st || !(sample_dt > 0.0) || ckpt_every < 1 || m->cls || m->n_inflow) return ORC_EINVAL;
     const int64_t nc = (int64_t)m->ny * m->nx;
     const int64_t nqx = (int64_t)m->ny * (m->nx + 1), nqy = (int64_t)(m->ny + 1) * m->nx;
     const int64_t nst = nc + nqx + nqy;
@@ -836,7 +917,7 @@ int orc_adjoint(const orc_model* m, orc_member* st, double t_end, double sample_
 /* Adjoint of a single step with a given dt (for transpose checks). */
 int orc_adj_step(const orc_model* m, double s, double mu, const double* h, const double* qx, const double* qy,
                  double dt, double t, double* lh, double* lqx, double* lqy, double* grad_n, double* grad_mu) {
-    if (!model_valid(m) || !(dt > 0.0) || m->cls) return ORC_EINVAL;
+    if (!model_valid(m) || !(dt > 0.0) || m->cls || m->n_inflow) return ORC_EINVAL;
     const int64_t nc = (int64_t)m->ny * m->nx;
     adj_scratch as;
     as.lhe = (double*)malloc(sizeof(double) * (size_t)nc);

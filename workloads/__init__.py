@@ -237,6 +237,10 @@ class Catchment:
     drain: np.ndarray | None = None           # [N] drainage rate, m/s
     truth_class_n: np.ndarray | None = None   # [3]
     truth_drain: float = 0.0
+    # inflow hydrographs (Sec. 4.1) and streamflow sections (Sec. 4.4); None: none
+    inflow: np.ndarray | None = None          # int32 [n, 3]: edge (N, E, S, W), position, series
+    inflow_q: np.ndarray | None = None        # [n_series, n_blocks] inward discharge per unit width, m^2/s
+    sections: list | None = None              # int32 [n_links, 4] each: kind (0 x / 1 y), r, c, sign
 
 
 @dataclass
@@ -287,8 +291,31 @@ def land_cover(dem: np.ndarray, bmask: np.ndarray, period: int = 12, street: int
     return cls
 
 
+# Two synthetic stream outlets on the north edge (Sec. 4.1 assigns synthetic
+# hydrographs to the boundary cells of two stream outlets; the paper's series
+# are not available): each enters along a street, two links wide, with a
+# triangular hydrograph over the 12 rain blocks, the second 0.6 of the first and
+# one block later.  A streamflow section crosses each street a quarter of the way
+# down (Sec. 4.4: two flow gauges), two cells wider than the street on each side.
+HYDROGRAPH = (0.05, 0.10, 0.20, 0.35, 0.50, 0.45, 0.35, 0.25, 0.18, 0.12, 0.08, 0.05)
+
+
+def stream_inflow(ny: int, nx: int, n_blocks: int = 12, period: int = 12):
+    base = np.interp(np.arange(n_blocks), np.linspace(0, n_blocks - 1, len(HYDROGRAPH)), HYDROGRAPH)
+    second = 0.6 * np.concatenate([[base[0]], base[:-1]])
+    cols = sorted({min(max(period * int(round(nx * f / period)), 0), nx - 2) for f in (1 / 3, 2 / 3)})
+    inflow, sections = [], []
+    rs = min(ny - 1, max(1, ny // 4))
+    for j, c0 in enumerate(cols):
+        inflow += [(0, c0, j), (0, c0 + 1, j)]
+        sections.append(np.array([(1, rs, c, 1) for c in range(max(c0 - 2, 0), min(c0 + 4, nx))], dtype=np.int32))
+    q = np.array([base, second][:len(cols)])
+    return np.array(inflow, dtype=np.int32), q, sections
+
+
 def urban_catchment(name: str, ny: int, nx: int, n_members: int, seed: int, n_gauges: int = 5,
-                    dx: float = 3.0, open_slope: float = 1e-3, with_land_cover: bool = False) -> Catchment:
+                    dx: float = 3.0, open_slope: float = 1e-3, with_land_cover: bool = False,
+                    with_inflow: bool = False) -> Catchment:
     rng = np.random.default_rng(seed)
     dem, bmask = dem_urban(ny, nx, rng)
     manning = np.full((ny, nx), 0.03, dtype=np.float32)
@@ -312,6 +339,8 @@ def urban_catchment(name: str, ny: int, nx: int, n_members: int, seed: int, n_ga
         cat.drain = lrng.uniform(0.5, 1.5, size=n_members) * DRAIN_MMH / 3.6e6
         cat.truth_class_n = np.array(CLASS_N_TRUTH)
         cat.truth_drain = DRAIN_MMH / 3.6e6
+    if with_inflow:
+        cat.inflow, cat.inflow_q, cat.sections = stream_inflow(ny, nx)
     return cat
 
 
@@ -356,11 +385,13 @@ def config4(members_each: int = 24, shapes=((512, 512), (768, 1536), (1024, 1024
                     rain_interval=300.0, t_end=1800.0, real_bytes=4, pf_every=300.0, seed=seed)
 
 
-def config5(ny: int = 2000, nx: int = 2000, n_members: int = 96, with_land_cover: bool = False) -> Workload:
+def config5(ny: int = 2000, nx: int = 2000, n_members: int = 96, with_land_cover: bool = False,
+            with_inflow: bool = False) -> Workload:
     """Paper-scale single GPU: 4.0 M cells x 96 members, 3600 s, PF every 600 s, 10 gauges
     (optionally with the land cover of Sec. 4.1: class roughness, runoff, drainage)."""
     seed = seed_for(5)
-    c = urban_catchment("urban2000", ny, nx, n_members, seed, n_gauges=10, with_land_cover=with_land_cover)
+    c = urban_catchment("urban2000", ny, nx, n_members, seed, n_gauges=10, with_land_cover=with_land_cover,
+                        with_inflow=with_inflow)
     return Workload(name="c5_urban2000x96_pf", catchments=[c], rain=chicago_hyetograph(),
                     rain_interval=300.0, t_end=3600.0, real_bytes=4, pf_every=600.0, seed=seed,
                     extra={"adj_window": 900.0, "ckpt_every": 100})
