@@ -107,6 +107,20 @@ typedef struct flood_params {
     const int32_t* class_drain;     /* host [n_classes], 1: the drainage rate applies, 0: it does not */
     const double* member_class_n;   /* host [n_members*n_classes], member-major, finite, > 0 */
     const double* member_drain;     /* host [n_members] drainage rates in m/s, finite, >= 0 (NULL: 0) */
+    /* Inflow hydrographs (Sec. 4.1: the boundary cells of two stream outlets
+     * carry synthetic discharge series).  An inflow link is an edge link whose
+     * discharge into the domain is prescribed by a series, piecewise constant
+     * over the rain blocks (block j holds inflow_q[series*n_rain + j]; zero
+     * outside the series); it replaces the edge's wall or open condition on
+     * that link and its volume is logged as inflow, not outflow.  The same for
+     * every member.  Needs member_interleave 0 or 1, step_kernel 0 or 3 and nx
+     * a multiple of 4 (FP32) or 2 (FP64); the adjoint refuses it. */
+    int32_t n_inflow;               /* 0 .. 2*(nx+ny) inflow links */
+    const int32_t* inflow;          /* host [n_inflow*3]: edge (N=0, E=1, S=2, W=3), position along the edge
+                                       (column on N/S, row on E/W), series index; each link at most once */
+    int32_t n_series;               /* 1 .. 4 when n_inflow > 0 */
+    const double* inflow_q;         /* host [n_series*n_rain] inward discharge per unit width, m^2/s,
+                                       finite, >= 0 */
 } flood_params;
 
 typedef struct flood_handle flood_handle;
@@ -195,11 +209,43 @@ flood_status flood_set_params(flood_handle* h, int32_t catchment, const float* m
 /* Mass ledger of one catchment, each output host [N] or NULL:
  * storage = sum h dx^2, rain_in = total rain volume added, outflow = volume
  * that left through open edges, clamp = volume added by clamping negative
- * depths to zero, drained = volume lost to drainage (land cover); t = member
- * times; steps = steps taken.  Invariant:
- * storage - storage(t=0) = rain_in - outflow + clamp - drained. */
+ * depths to zero, drained = volume lost to drainage (land cover), inflow =
+ * volume that entered through inflow links; t = member times; steps = steps
+ * taken.  Invariant:
+ * storage - storage(t=0) = rain_in + inflow - outflow + clamp - drained. */
 flood_status flood_get_ledger(flood_handle* h, int32_t catchment, double* storage, double* rain_in,
-                              double* outflow, double* clamp, double* drained, double* t, int64_t* steps);
+                              double* outflow, double* clamp, double* drained, double* inflow, double* t,
+                              int64_t* steps);
+
+/* Streamflow gauges (Sec. 4.4: the flow through a section is the sum of the
+ * fluxes on the links across it).  Registers the sections of one catchment,
+ * replacing any registered before (n_sections 0 clears them):
+ *   link_count  host [n_sections], each >= 1; at most 65536 links in all
+ *   links       host [sum of link_count][4]: kind (0 x-link, 1 y-link), r, c,
+ *               sign (+1 or -1), in the host discharge layouts above (x-link
+ *               (r, c): 0 <= r < ny, 0 <= c <= nx; y-link (r, c): 0 <= r <= ny,
+ *               0 <= c < nx)
+ * The discharge of section s is dx * sum over its links of sign * q, m^3/s.
+ * At most 64 sections.  Errors: EINVAL. */
+flood_status flood_set_sections(flood_handle* h, int32_t catchment, int32_t n_sections, const int32_t* link_count,
+                                const int32_t* links);
+
+/* Discharge through every registered section for every member, host
+ * [N*n_sections] member-major.  ESTATE when no section is registered. */
+flood_status flood_get_sections(flood_handle* h, int32_t catchment, double* q_out);
+
+/* Particle-filter cycle of flood_assimilate on depth gauges and streamflow
+ * gauges together: the observation vector is the n_gauges depths followed by
+ * the discharges of every registered section (Sec. 4.4: three depth and two
+ * flow gauges).  obs and sigma are host [n_gauges + n_sections].  alpha > 0:
+ * relative observation error, sigma_k = max(alpha |d_k|, sigma[k]) (Sec. 4.4
+ * uses alpha = 0.05; sigma is the floor that keeps an observation of zero
+ * usable); alpha = 0: sigma_k = sigma[k].  Other arguments, outputs and errors
+ * as flood_assimilate. */
+flood_status flood_assimilate_obs(flood_handle* h, int32_t catchment, int32_t n_gauges, const int32_t* gauge_rc,
+                                  const double* obs, const double* sigma, double alpha, double neff_frac, double u0,
+                                  const double* beta, double* neff_out, int32_t* ancestors_out,
+                                  int32_t* resampled_out);
 
 /* Land-cover parameters of every member (they follow their members through
  * resampling): class_n_out host [N*n_classes] member-major, drain_out host [N];

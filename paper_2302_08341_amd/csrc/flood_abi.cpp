@@ -117,6 +117,19 @@ flood_status validate_params(const flood_params* p, std::string& err) {
         if (p->step_kernel == 1 || p->step_kernel == 2) { err = "land cover needs step_kernel 0 or 3"; return FLOOD_EINVAL; }
         if (p->member_interleave > 1) { err = "land cover needs member_interleave 0 or 1"; return FLOOD_EINVAL; }
     }
+    if (p->n_inflow < 0) { err = "n_inflow must be >= 0"; return FLOOD_EINVAL; }
+    if (p->n_inflow > 0) {
+        if (!p->inflow) { err = "inflow is required"; return FLOOD_EINVAL; }
+        if (p->n_series < 1 || p->n_series > 4) { err = "n_series must be in [1, 4]"; return FLOOD_EINVAL; }
+        if (p->n_rain > 0 && !p->inflow_q) { err = "inflow_q is required"; return FLOOD_EINVAL; }
+        for (int j = 0; j < p->n_series * p->n_rain; ++j)
+            if (!(p->inflow_q[j] >= 0.0) || !finite_d(p->inflow_q[j])) {
+                err = "inflow_q must be finite and >= 0";
+                return FLOOD_EINVAL;
+            }
+        if (p->step_kernel == 1 || p->step_kernel == 2) { err = "inflow links need step_kernel 0 or 3"; return FLOOD_EINVAL; }
+        if (p->member_interleave > 1) { err = "inflow links need member_interleave 0 or 1"; return FLOOD_EINVAL; }
+    }
     return FLOOD_OK;
 }
 
@@ -166,6 +179,30 @@ flood_status flood_create_batch(int32_t n_catch, const flood_grid* grids, const 
         }
         const int N = members_per_catch[i];
         if (N < 1 || N > FLOOD_MAX_MEMBERS) { g_create_error = "members per catchment must be in [1, 1024]"; return FLOOD_EINVAL; }
+        // inflow links against the grid: edge, position, series, each link once
+        if (params[i].n_inflow > 2 * (grids[i].nx + grids[i].ny)) {
+            g_create_error = "n_inflow must be <= 2*(nx+ny)";
+            return FLOOD_EINVAL;
+        }
+        {
+            std::vector<uint8_t> seen(2 * ((size_t)grids[i].nx + grids[i].ny), 0);
+            for (int k = 0; k < params[i].n_inflow; ++k) {
+                const int32_t* f = params[i].inflow + 3 * k;
+                const int e = f[0], pos = f[1];
+                if (e < 0 || e > 3) { g_create_error = "inflow edge must be 0..3"; return FLOOD_EINVAL; }
+                const int len = (e == 0 || e == 2) ? grids[i].nx : grids[i].ny;
+                if (pos < 0 || pos >= len) { g_create_error = "inflow position outside the edge"; return FLOOD_EINVAL; }
+                if (f[2] < 0 || f[2] >= params[i].n_series) {
+                    g_create_error = "inflow series index must be < n_series";
+                    return FLOOD_EINVAL;
+                }
+                const size_t at = e == 0 ? pos : e == 2 ? grids[i].nx + pos
+                                                : e == 3 ? 2 * (size_t)grids[i].nx + pos
+                                                         : 2 * (size_t)grids[i].nx + grids[i].ny + pos;
+                if (seen[at]) { g_create_error = "an inflow link appears twice"; return FLOOD_EINVAL; }
+                seen[at] = 1;
+            }
+        }
         const int K = params[i].n_classes;
         if ((K > 0) != (grids[i].land_class != nullptr)) {
             g_create_error = "a class map and n_classes > 0 go together";
@@ -231,8 +268,28 @@ flood_status flood_assimilate(flood_handle* h, int32_t catchment, int32_t n_gaug
                               const double* beta, double* neff_out, int32_t* ancestors_out,
                               int32_t* resampled_out) {
     FLOOD_NEED_HANDLE(h);
-    return h->impl->assimilate(catchment, n_gauges, gauge_rc, obs, sigma, neff_frac, u0, beta, neff_out,
+    return h->impl->assimilate(catchment, n_gauges, gauge_rc, obs, sigma, 0, 0.0, neff_frac, u0, beta, neff_out,
                                ancestors_out, resampled_out, h->err);
+}
+
+flood_status flood_assimilate_obs(flood_handle* h, int32_t catchment, int32_t n_gauges, const int32_t* gauge_rc,
+                                  const double* obs, const double* sigma, double alpha, double neff_frac, double u0,
+                                  const double* beta, double* neff_out, int32_t* ancestors_out,
+                                  int32_t* resampled_out) {
+    FLOOD_NEED_HANDLE(h);
+    return h->impl->assimilate(catchment, n_gauges, gauge_rc, obs, sigma, 1, alpha, neff_frac, u0, beta, neff_out,
+                               ancestors_out, resampled_out, h->err);
+}
+
+flood_status flood_set_sections(flood_handle* h, int32_t catchment, int32_t n_sections, const int32_t* link_count,
+                                const int32_t* links) {
+    FLOOD_NEED_HANDLE(h);
+    return h->impl->set_sections(catchment, n_sections, link_count, links, h->err);
+}
+
+flood_status flood_get_sections(flood_handle* h, int32_t catchment, double* q_out) {
+    FLOOD_NEED_HANDLE(h);
+    return h->impl->get_sections(catchment, q_out, h->err);
 }
 
 flood_status flood_adjoint(flood_handle* h, int32_t catchment, double t_end, double sample_dt, int32_t n_gauges,
@@ -261,9 +318,9 @@ flood_status flood_set_params(flood_handle* h, int32_t catchment, const float* m
 }
 
 flood_status flood_get_ledger(flood_handle* h, int32_t catchment, double* storage, double* rain_in, double* outflow,
-                              double* clamp, double* drained, double* t, int64_t* steps) {
+                              double* clamp, double* drained, double* inflow, double* t, int64_t* steps) {
     FLOOD_NEED_HANDLE(h);
-    return h->impl->get_ledger(catchment, storage, rain_in, outflow, clamp, drained, t, steps, h->err);
+    return h->impl->get_ledger(catchment, storage, rain_in, outflow, clamp, drained, inflow, t, steps, h->err);
 }
 
 flood_status flood_get_land_params(flood_handle* h, int32_t catchment, double* class_n_out, double* drain_out) {

@@ -24,6 +24,8 @@ constexpr int kBins = 64;      // partial-max bins per member for the depth maxi
 constexpr int kBlock = 256;    // lanes per workgroup of the step kernels
 constexpr int kMaxMembers = 1024;
 constexpr int kMaxClasses = 4;  // land-cover classes
+constexpr int kMaxSeries = 4;     // inflow hydrograph series per catchment
+constexpr int kMaxSections = 64;  // streamflow sections per catchment
 
 template <typename T> struct HBits;
 template <> struct HBits<float> { using type = uint32_t; };
@@ -43,6 +45,7 @@ template <typename T> struct MemberStep {
     int32_t slot;    // adjoint record: the member's step index within the tape segment
     T cn[kMaxClasses];  // land cover: the member's Manning n of each class
     T drain;            // land cover: drainage depth of the step (rate x dt)
+    T qin[kMaxSeries];  // inward discharge of each inflow series during the step
 };
 
 template <typename T> struct CatchDev {
@@ -78,6 +81,9 @@ template <typename T> struct CatchDev {
     double* drain_acc;        // [n_members][kBins] drained volume, one bin per workgroup id mod kBins
     T class_rc[kMaxClasses];
     int32_t drain_mask;
+    // inflow links: series index of each edge link in the order of out_acc
+    // (N, S, W, E), -1 for none; null when the catchment has no inflow link
+    const int8_t* inflow_id;
 };
 
 template <typename T> struct StepLaunch {
@@ -103,6 +109,11 @@ struct PlanCatch {
     const double* rain;
     double rain_interval, alpha, hdry, dt_cap, dt_fixed, g, dx;
     double ncells;
+    // inflow hydrographs: [n_series][n_rain] discharge per unit width; wq[j] =
+    // links of series j x dx, so the inflow rate is sum_j wq[j] q_j
+    const double* inflow_q;
+    int32_t n_series;
+    double wq[kMaxSeries];
 };
 
 template <typename T> struct PlanLaunch {
@@ -117,6 +128,7 @@ template <typename T> struct PlanLaunch {
     int32_t* fault;
     int32_t* status;          // bit 0: non-finite depth seen
     double* vrain;
+    double* vin;              // [n_total] inflow volume
     typename HBits<T>::type* hbins;
     MemberStep<T>* ms;
     double* dtlog;            // optional [n_total][dtlog_cap] step lengths
@@ -144,7 +156,7 @@ template <typename T> void launch_march(const StepLaunch<T>& L, int seg, int tot
 // cells per lane of the vectorised row-marching kernel (nx must be a multiple of it)
 template <typename T> constexpr int march_vec() { return sizeof(T) == 4 ? 4 : 2; }
 template <typename T>
-void launch_marchv(const StepLaunch<T>& L, int nt, int pf, int land, int total_waves, hipStream_t s);
+void launch_marchv(const StepLaunch<T>& L, int nt, int pf, int ext, int total_waves, hipStream_t s);
 // wavefronts of a row-march launch over one catchment: strips x member units,
 // units padded to a multiple of four in wavefront order 2
 inline int march_waves(int strips, int units, int order) { return strips * (order == 2 ? (units + 3) / 4 * 4 : units); }
@@ -167,7 +179,15 @@ void launch_set_field(int mi, const CatchDev<T>& C, int member, int par, int whi
                       hipStream_t s);
 template <typename T>
 void launch_gauges(int mi, const CatchDev<T>& C, const int32_t* par, int n_gauges, const int32_t* grc,
-                   double* y, hipStream_t s);
+                   double* y, int y_stride, hipStream_t s);
+// streamflow sections: each link is (code, index): code bits 0-1 the array
+// (0 qx cell, 1 qy cell, 2 west strip row, 3 north strip column), bit 2 set
+// for a negative sign; index the cell (r*nx + c) or strip position.
+// out[m*out_stride + out_off + s] = dx * sum of sign * q over section s.
+template <typename T>
+void launch_sections(int mi, const CatchDev<T>& C, const int32_t* par, int n_sections, const int32_t* offs,
+                     const int32_t* code, const int32_t* index, double* out, int out_stride, int out_off,
+                     hipStream_t s);
 void launch_flush_outflow(int n_members, int nb, double* out_acc, double* vout, hipStream_t s);
 // ensemble products of the running maximum depth: prob [ny*nx], pct [n_pct][ny*nx]
 template <typename T>
@@ -255,6 +275,8 @@ struct PfArgs {
     double* clsn;             // land cover, permuted with the members: [N][kMaxClasses] or null
     double* drain;            // [N] or null
     double* vdrain;           // [N]
+    double* vin;              // [N]
+    double alpha;             // > 0: sigma_k = max(alpha |d_k|, sigma[k])
 };
 void launch_pf(const PfArgs& a, hipStream_t s);
 // running maxima follow their members on resampling: gather into tmp, then commit

@@ -33,6 +33,7 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     ms.slot = -1;
     for (int k = 0; k < kMaxClasses; ++k) ms.cn[k] = T(0);
     ms.drain = T(0);
+    for (int k = 0; k < kMaxSeries; ++k) ms.qin[k] = T(0);
     const double t = P.t[m];
     const double t_end = *P.t_end;
     const int lm = m - P.m_begin;
@@ -95,6 +96,17 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     if (P.clsn)
         for (int k = 0; k < kMaxClasses; ++k) ms.cn[k] = (T)P.clsn[(size_t)m * kMaxClasses + k];
     if (P.drain) ms.drain = (T)(P.drain[m] * dt);
+    if (C.n_series > 0) {
+        // inflow hydrographs: the series value of the current rain block
+        double vq = 0.0;
+        for (int j = 0; j < C.n_series; ++j) {
+            const double q = (jf >= 0.0 && jf < (double)C.n_rain) ? C.inflow_q[(size_t)j * C.n_rain + (int64_t)jf]
+                                                                     : 0.0;
+            ms.qin[j] = (T)q;
+            vq += C.wq[j] * q;
+        }
+        P.vin[m] += vq * dt;
+    }
     P.ms[m] = ms;
     if (P.ms_log) {
         P.ms_log[lm] = ms;
@@ -501,24 +513,75 @@ void launch_set_field(int mi, const CatchDev<T>& C, int member, int par, int whi
 // Observation operator: depth of every member at every gauge cell, [N*K].
 template <typename T, int MI>
 __global__ __launch_bounds__(256) void k_gauges(const CatchDev<T> C, const int32_t* par, int K, const int32_t* grc,
-                                                double* y) {
+                                                double* y, int ys) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= C.n_members * K) return;
     const int m = e / K, k = e % K;
     const T* h = C.h[par[C.member_off + m]];
-    y[e] = (double)h[state_index<T, MI>(C, m, grc[2 * k], grc[2 * k + 1])];
+    y[(size_t)m * ys + k] = (double)h[state_index<T, MI>(C, m, grc[2 * k], grc[2 * k + 1])];
 }
 
 template <typename T>
 void launch_gauges(int mi, const CatchDev<T>& C, const int32_t* par, int n_gauges, const int32_t* grc, double* y,
-                   hipStream_t s) {
+                   int ys, hipStream_t s) {
     dim3 grid((C.n_members * n_gauges + 255) / 256);
     if (grid.x == 0) return;
     switch (mi) {
-        case 1: hipLaunchKernelGGL((k_gauges<T, 1>), grid, dim3(256), 0, s, C, par, n_gauges, grc, y); break;
-        case 2: hipLaunchKernelGGL((k_gauges<T, 2>), grid, dim3(256), 0, s, C, par, n_gauges, grc, y); break;
-        case 4: hipLaunchKernelGGL((k_gauges<T, 4>), grid, dim3(256), 0, s, C, par, n_gauges, grc, y); break;
-        default: hipLaunchKernelGGL((k_gauges<T, 8>), grid, dim3(256), 0, s, C, par, n_gauges, grc, y); break;
+        case 1: hipLaunchKernelGGL((k_gauges<T, 1>), grid, dim3(256), 0, s, C, par, n_gauges, grc, y, ys); break;
+        case 2: hipLaunchKernelGGL((k_gauges<T, 2>), grid, dim3(256), 0, s, C, par, n_gauges, grc, y, ys); break;
+        case 4: hipLaunchKernelGGL((k_gauges<T, 4>), grid, dim3(256), 0, s, C, par, n_gauges, grc, y, ys); break;
+        default: hipLaunchKernelGGL((k_gauges<T, 8>), grid, dim3(256), 0, s, C, par, n_gauges, grc, y, ys); break;
+    }
+}
+
+// Streamflow through sections (Sec. 4.4): one workgroup per (section, member)
+// sums sign * q over the section's links in FP64 (lanes stride the links, then
+// a fixed reduction tree), times dx.
+template <typename T, int MI>
+__global__ __launch_bounds__(256) void k_sections(const CatchDev<T> C, const int32_t* par, const int32_t* offs,
+                                                  const int32_t* code, const int32_t* index, double* out,
+                                                  int ostride, int ooff) {
+    const int sec = blockIdx.x, m = blockIdx.y;
+    const int p = par[C.member_off + m];
+    const int chunk = m / MI, lane = m % MI;
+    const size_t plane = (size_t)C.ny * C.nx * MI;
+    double acc = 0.0;
+    for (int l = offs[sec] + (int)threadIdx.x; l < offs[sec + 1]; l += 256) {
+        const int cd = code[l], ix = index[l];
+        double q;
+        switch (cd & 3) {
+            case 0: q = (double)C.qx[p][(size_t)chunk * plane + (size_t)ix * MI + lane]; break;
+            case 1: q = (double)C.qy[p][(size_t)chunk * plane + (size_t)ix * MI + lane]; break;
+            case 2: q = (double)C.qw[p][((size_t)chunk * C.ny + ix) * MI + lane]; break;
+            default: q = (double)C.qn[p][((size_t)chunk * C.nx + ix) * MI + lane]; break;
+        }
+        acc += (cd & 4) ? -q : q;
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    __shared__ double part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[(size_t)m * ostride + ooff + sec] = ((part[0] + part[1]) + (part[2] + part[3])) * C.dx;
+}
+
+template <typename T>
+void launch_sections(int mi, const CatchDev<T>& C, const int32_t* par, int n_sections, const int32_t* offs,
+                     const int32_t* code, const int32_t* index, double* out, int ostride, int ooff, hipStream_t s) {
+    if (n_sections <= 0 || C.n_members <= 0) return;
+    const dim3 grid(n_sections, C.n_members);
+    switch (mi) {
+        case 1:
+            hipLaunchKernelGGL((k_sections<T, 1>), grid, dim3(256), 0, s, C, par, offs, code, index, out, ostride, ooff);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_sections<T, 2>), grid, dim3(256), 0, s, C, par, offs, code, index, out, ostride, ooff);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_sections<T, 4>), grid, dim3(256), 0, s, C, par, offs, code, index, out, ostride, ooff);
+            break;
+        default:
+            hipLaunchKernelGGL((k_sections<T, 8>), grid, dim3(256), 0, s, C, par, offs, code, index, out, ostride, ooff);
+            break;
     }
 }
 
@@ -556,10 +619,14 @@ template void launch_get_field<float>(int, const CatchDev<float>&, int, int, int
 template void launch_get_field<double>(int, const CatchDev<double>&, int, int, int, double*, hipStream_t);
 template void launch_set_field<float>(int, const CatchDev<float>&, int, int, int, const double*, hipStream_t);
 template void launch_set_field<double>(int, const CatchDev<double>&, int, int, int, const double*, hipStream_t);
-template void launch_gauges<float>(int, const CatchDev<float>&, const int32_t*, int, const int32_t*, double*,
+template void launch_gauges<float>(int, const CatchDev<float>&, const int32_t*, int, const int32_t*, double*, int,
                                    hipStream_t);
-template void launch_gauges<double>(int, const CatchDev<double>&, const int32_t*, int, const int32_t*, double*,
+template void launch_gauges<double>(int, const CatchDev<double>&, const int32_t*, int, const int32_t*, double*, int,
                                     hipStream_t);
+template void launch_sections<float>(int, const CatchDev<float>&, const int32_t*, int, const int32_t*,
+                                     const int32_t*, const int32_t*, double*, int, int, hipStream_t);
+template void launch_sections<double>(int, const CatchDev<double>&, const int32_t*, int, const int32_t*,
+                                      const int32_t*, const int32_t*, double*, int, int, hipStream_t);
 
 }  // namespace flood
 
@@ -761,7 +828,7 @@ __global__ __launch_bounds__(kBlock) void k_march(const StepLaunch<T> L) {
 // computes.  Loads use a column clamped into the grid and a row clamped to the
 // last row, so no lane needs a branch or a zero fill around them: values of
 // lanes outside the grid and of the row below the last are read but never used.
-template <typename T, int V, int NT, int REC, int PF, int LC>
+template <typename T, int V, int NT, int REC, int PF, int EXT>
 __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
     using HB = typename HBits<T>::type;
     const int lane = threadIdx.x & 63;
@@ -829,11 +896,22 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
     const T* __restrict__ Nn = C.n;
     const T g = C.g, hdry = C.hdry;
     const int nb = 2 * (nx + ny);
+    // inflow links (edge links with a prescribed inward discharge): the series
+    // index of an edge link in the out_acc order, or -1; the series value is
+    // picked by a select chain (a per-lane index into the step record would
+    // go through private memory)
+    const int8_t* __restrict__ INF = (EXT & 2) ? C.inflow_id : nullptr;
+    auto inflow_q = [&](int id) -> T {
+        T v = ms.qin[0];
+        v = (id == 1) ? ms.qin[1] : v;
+        v = (id == 2) ? ms.qin[2] : v;
+        return (id == 3) ? ms.qin[3] : v;
+    };
     // land cover: the cell's roughness is the member's value for its class, and
     // its rain is scaled by the class's runoff coefficient (select chains: the
     // member's table stays in scalar registers)
-    const uint8_t* __restrict__ CLS = LC ? C.cls : nullptr;
-    const bool lc = LC && CLS != nullptr;
+    const uint8_t* __restrict__ CLS = (EXT & 1) ? C.cls : nullptr;
+    const bool lc = (EXT & 1) && CLS != nullptr;
     auto rough = [&](uint32_t k) -> T {
         T v = ms.cn[0];
         v = (k == 1u) ? ms.cn[1] : v;
@@ -888,6 +966,13 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
 #pragma unroll
         for (int j = 0; j < V; ++j) fN[j] = T(0);
     }
+    if (INF && r0 == 0) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const int id = INF[xa + j];
+            if (id >= 0) fN[j] = inflow_q(id);
+        }
+    }
     // current row's links (qE, qS) and the row below (hs, zs, ns, classes csw)
     T hs[V], zs[V], ns[V], qE[V], qS[V];
     uint32_t csw = 0;
@@ -934,17 +1019,23 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
         if (eastw) {
 #pragma unroll
             for (int j = 0; j < V; ++j)
-                if (xl + j + 1 == nx)
+                if (xl + j + 1 == nx) {
                     fE[j] = C.edge_open[1] ? link_open(qE[j], hc[j], g * (nc[j] * nc[j]), C.edge_slope[1], ms, hdry)
                                            : T(0);
+                    const int id = INF ? (int)INF[2 * nx + ny + r] : -1;
+                    if (id >= 0) fE[j] = -inflow_q(id);
+                }
         }
         T fW[V];
         fW[0] = __shfl_up(fE[V - 1], 1, 64);
 #pragma unroll
         for (int j = 1; j < V; ++j) fW[j] = fE[j - 1];
-        if (westw && xl == 0)
+        if (westw && xl == 0) {
             fW[0] = C.edge_open[3] ? -link_open(-QWs[r], hc[0], g * (nc[0] * nc[0]), C.edge_slope[3], ms, hdry)
                                    : T(0);
+            const int id = INF ? (int)INF[2 * nx + r] : -1;
+            if (id >= 0) fW[0] = inflow_q(id);
+        }
         T fS[V];
         if (hasS) {
 #pragma unroll
@@ -952,13 +1043,22 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
                 const T nf = T(0.5) * (nc[j] + ns[j]);
                 fS[j] = link_in(qS[j], hc[j], hs[j], zs[j] - zc[j], g * (nf * nf), ms, hdry);
             }
-        } else if (C.edge_open[2]) {
-#pragma unroll
-            for (int j = 0; j < V; ++j)
-                fS[j] = link_open(qS[j], hc[j], g * (nc[j] * nc[j]), C.edge_slope[2], ms, hdry);
         } else {
+            if (C.edge_open[2]) {
 #pragma unroll
-            for (int j = 0; j < V; ++j) fS[j] = T(0);
+                for (int j = 0; j < V; ++j)
+                    fS[j] = link_open(qS[j], hc[j], g * (nc[j] * nc[j]), C.edge_slope[2], ms, hdry);
+            } else {
+#pragma unroll
+                for (int j = 0; j < V; ++j) fS[j] = T(0);
+            }
+            if (INF) {
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    const int id = INF[nx + xa + j];
+                    if (id >= 0) fS[j] = -inflow_q(id);
+                }
+            }
         }
         T hn4[V];
         uint8_t cf[V];
@@ -1017,13 +1117,16 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
             // outflow through open edges (FP64 per member and edge link)
             if (!REC && (westw || eastw || r == 0 || !hasS)) {
                 double* acc = C.out_acc + (size_t)k * nb;
+                // inflow links are not outflow: their volume is logged by the step planner
+                auto out = [&](int e) { return !INF || INF[e] < 0; };
 #pragma unroll
                 for (int j = 0; j < V; ++j) {
                     const int x = xl + j;
-                    if (r == 0 && C.edge_open[0]) acc[x] += -(double)fN[j] * ms.dxdt;
-                    if (!hasS && C.edge_open[2]) acc[nx + x] += (double)fS[j] * ms.dxdt;
-                    if (x == 0 && C.edge_open[3]) acc[2 * nx + r] += -(double)fW[j] * ms.dxdt;
-                    if (x + 1 == nx && C.edge_open[1]) acc[2 * nx + ny + r] += (double)fE[j] * ms.dxdt;
+                    if (r == 0 && C.edge_open[0] && out(x)) acc[x] += -(double)fN[j] * ms.dxdt;
+                    if (!hasS && C.edge_open[2] && out(nx + x)) acc[nx + x] += (double)fS[j] * ms.dxdt;
+                    if (x == 0 && C.edge_open[3] && out(2 * nx + r)) acc[2 * nx + r] += -(double)fW[j] * ms.dxdt;
+                    if (x + 1 == nx && C.edge_open[1] && out(2 * nx + ny + r))
+                        acc[2 * nx + ny + r] += (double)fE[j] * ms.dxdt;
                 }
             }
         }
@@ -1074,27 +1177,31 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
     }
 }
 
-template <typename T, int LC>
-static void launch_marchv_lc(const StepLaunch<T>& L, int nt, int pf, const dim3 grid, hipStream_t s) {
+template <typename T, int EXT>
+static void launch_marchv_ext(const StepLaunch<T>& L, int nt, int pf, const dim3 grid, hipStream_t s) {
     constexpr int V = march_vec<T>();
     if (nt && pf)
-        hipLaunchKernelGGL((k_marchv<T, V, 1, 0, 1, LC>), grid, dim3(kBlock), 0, s, L);
+        hipLaunchKernelGGL((k_marchv<T, V, 1, 0, 1, EXT>), grid, dim3(kBlock), 0, s, L);
     else if (nt)
-        hipLaunchKernelGGL((k_marchv<T, V, 1, 0, 0, LC>), grid, dim3(kBlock), 0, s, L);
+        hipLaunchKernelGGL((k_marchv<T, V, 1, 0, 0, EXT>), grid, dim3(kBlock), 0, s, L);
     else if (pf)
-        hipLaunchKernelGGL((k_marchv<T, V, 0, 0, 1, LC>), grid, dim3(kBlock), 0, s, L);
+        hipLaunchKernelGGL((k_marchv<T, V, 0, 0, 1, EXT>), grid, dim3(kBlock), 0, s, L);
     else
-        hipLaunchKernelGGL((k_marchv<T, V, 0, 0, 0, LC>), grid, dim3(kBlock), 0, s, L);
+        hipLaunchKernelGGL((k_marchv<T, V, 0, 0, 0, EXT>), grid, dim3(kBlock), 0, s, L);
 }
 
+// ext: bit 0 land cover, bit 1 inflow links; an instantiation carries only the
+// code of the extensions it names, so the plain step keeps its register budget
 template <typename T>
-void launch_marchv(const StepLaunch<T>& L, int nt, int pf, int land, int total_waves, hipStream_t s) {
+void launch_marchv(const StepLaunch<T>& L, int nt, int pf, int ext, int total_waves, hipStream_t s) {
     const int per = kBlock / 64;
     const dim3 grid((total_waves + per - 1) / per);
-    if (land)
-        launch_marchv_lc<T, 1>(L, nt, pf, grid, s);
-    else
-        launch_marchv_lc<T, 0>(L, nt, pf, grid, s);
+    switch (ext & 3) {
+        case 0: launch_marchv_ext<T, 0>(L, nt, pf, grid, s); break;
+        case 1: launch_marchv_ext<T, 1>(L, nt, pf, grid, s); break;
+        case 2: launch_marchv_ext<T, 2>(L, nt, pf, grid, s); break;
+        default: launch_marchv_ext<T, 3>(L, nt, pf, grid, s); break;
+    }
 }
 
 // Tape recomputation of the adjoint: the same step, reading and writing tape

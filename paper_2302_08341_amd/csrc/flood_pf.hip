@@ -80,7 +80,13 @@ __global__ __launch_bounds__(1024) void k_pf(const PfArgs a) {
     if (m < N) {
         double acc = 0.0;
         for (int k = 0; k < K; ++k) {
-            const double e = (a.y[(size_t)m * K + k] - a.d[k]) / a.sigma[k];
+            // relative observation error with a floor (Sec. 4.4), or absolute
+            double sg = a.sigma[k];
+            if (a.alpha > 0.0) {
+                const double rel = a.alpha * fabs(a.d[k]);
+                sg = rel > sg ? rel : sg;
+            }
+            const double e = (a.y[(size_t)m * K + k] - a.d[k]) / sg;
             acc += e * e;
         }
         av = a.logw[m] + -0.5 * acc;
@@ -109,7 +115,7 @@ __global__ __launch_bounds__(1024) void k_pf(const PfArgs a) {
     const int anc = systematic_lane(N, sw, C, a.u0);
     // replacement (step V): slot m takes its ancestor's scalars; the state arrays
     // are copied by k_permute into the slot's other state copy
-    double t = 0, s = 0, mu = 0, vr = 0, vo = 0, vc = 0, vd = 0, dr = 0;
+    double t = 0, s = 0, mu = 0, vr = 0, vo = 0, vc = 0, vd = 0, dr = 0, vi = 0;
     double cn[kMaxClasses] = {0.0, 0.0, 0.0, 0.0};
     int64_t st = 0;
     int sp = 0, mypar = 0;
@@ -118,6 +124,7 @@ __global__ __launch_bounds__(1024) void k_pf(const PfArgs a) {
             for (int k = 0; k < kMaxClasses; ++k) cn[k] = a.clsn[(size_t)anc * kMaxClasses + k];
         if (a.drain) dr = a.drain[anc];
         vd = a.vdrain[anc];
+        vi = a.vin[anc];
         t = a.t[anc];
         s = a.s[anc];
         mu = a.mu[anc];
@@ -141,6 +148,7 @@ __global__ __launch_bounds__(1024) void k_pf(const PfArgs a) {
             for (int k = 0; k < kMaxClasses; ++k) a.clsn[(size_t)m * kMaxClasses + k] = cn[k];
         if (a.drain) a.drain[m] = dr;
         a.vdrain[m] = vd;
+        a.vin[m] = vi;
         a.steps[m] = st;
         a.logw[m] = -log((double)N);
         a.src_par[m] = sp;

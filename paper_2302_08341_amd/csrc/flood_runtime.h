@@ -15,8 +15,12 @@ struct ImplBase {
     virtual ~ImplBase() {}
     virtual flood_status step(double t_end, std::string& err) = 0;
     virtual flood_status assimilate(int c, int K, const int32_t* grc, const double* obs, const double* sigma,
-                                    double neff_frac, double u0, const double* beta, double* neff_out,
-                                    int32_t* anc_out, int32_t* res_out, std::string& err) = 0;
+                                    int with_sections, double alpha, double neff_frac, double u0,
+                                    const double* beta, double* neff_out, int32_t* anc_out, int32_t* res_out,
+                                    std::string& err) = 0;
+    virtual flood_status set_sections(int c, int n, const int32_t* count, const int32_t* links,
+                                      std::string& err) = 0;
+    virtual flood_status get_sections(int c, double* q_out, std::string& err) = 0;
     virtual flood_status adjoint(int c, double t_end, double sample_dt, int K, const int32_t* grc,
                                  const double* obs, int ckpt_every, double* loss_out, double* grad_n_out,
                                  double* grad_mult_out, std::string& err) = 0;
@@ -26,7 +30,8 @@ struct ImplBase {
     virtual flood_status set_params(int c, const float* manning, const double* n_scale, const double* rain_mult,
                                     std::string& err) = 0;
     virtual flood_status get_ledger(int c, double* storage, double* rain_in, double* outflow, double* clamp,
-                                    double* drained, double* t, int64_t* steps, std::string& err) = 0;
+                                    double* drained, double* inflow, double* t, int64_t* steps,
+                                    std::string& err) = 0;
     virtual flood_status get_land_params(int c, double* class_n, double* drain, std::string& err) = 0;
     virtual flood_status get_weights(int c, double* logw, double* rain_mult, double* n_scale,
                                      std::string& err) = 0;

@@ -48,6 +48,16 @@ template <typename T> struct Impl : ImplBase {
         T* peak_tmp = nullptr;    // resampling scratch of the running maximum
         int n_classes = 0;        // land cover: 0 none
         double rain_cells = 0.0;  // rain-receiving cell count (land cover: sum of runoff coefficients)
+        // inflow hydrographs
+        int n_series = 0;
+        double* d_inflow_q = nullptr;
+        double wq[kMaxSeries] = {0, 0, 0, 0};
+        // streamflow sections (configuration, not state: not in snapshots)
+        int n_sec = 0;
+        int32_t* d_sec_offs = nullptr;
+        int32_t* d_sec_code = nullptr;
+        int32_t* d_sec_index = nullptr;
+        size_t sec_cap = 0;
     };
 
     hipStream_t st = nullptr;
@@ -67,7 +77,11 @@ template <typename T> struct Impl : ImplBase {
            *vclamp = nullptr;
     int64_t* steps = nullptr;
     double *clsn = nullptr, *drain = nullptr, *vdrain = nullptr;   // land cover per member; drained volume
+    double* vin = nullptr;    // inflow volume per member
     bool any_land = false;
+    bool any_inflow = false;
+    // land cover and inflow links exist in the vectorised row-march kernel only
+    bool vector_only() const { return any_land || any_inflow; }
     int32_t *par = nullptr, *fault = nullptr, *status = nullptr;
     HB* hbins = nullptr;
     MemberStep<T>* ms = nullptr;
@@ -170,7 +184,7 @@ template <typename T> struct Impl : ImplBase {
 
     void launch_steps(const StepLaunch<T>& L) {
         if (variant == 3 && !L.recompute)
-            launch_marchv<T>(L, march_nt, march_pf, any_land ? 1 : 0, total_waves, st);
+            launch_marchv<T>(L, march_nt, march_pf, (any_land ? 1 : 0) | (any_inflow ? 2 : 0), total_waves, st);
         else if (variant == 2 && !L.recompute)
             launch_march<T>(L, march_seg, total_waves, st);
         else
@@ -258,14 +272,20 @@ template <typename T> struct Impl : ImplBase {
         // land cover runs on the vectorised row-march kernel only (per-member class
         // tables in scalar registers)
         any_land = false;
-        for (int i = 0; i < nc; ++i) any_land |= grids[i].land_class != nullptr && params[i].n_classes > 0;
-        if (any_land) {
+        any_inflow = false;
+        for (int i = 0; i < nc; ++i) {
+            any_land |= grids[i].land_class != nullptr && params[i].n_classes > 0;
+            any_inflow |= params[i].n_inflow > 0;
+        }
+        if (any_land || any_inflow) {
+            const char* what = any_land ? "land cover" : "inflow links";
             if (mi != 1 || !vector_ok()) {
-                err = "land cover needs member_interleave 1 and nx a multiple of " + std::to_string(march_vec<T>());
+                err = std::string(what) + " need member_interleave 1 and nx a multiple of " +
+                      std::to_string(march_vec<T>());
                 return FLOOD_EINVAL;
             }
             if (params[0].step_kernel == 1 || params[0].step_kernel == 2) {
-                err = "land cover runs on step kernel 3 only";
+                err = std::string(what) + " run on step kernel 3 only";
                 return FLOOD_EINVAL;
             }
             variant = 3;
@@ -347,6 +367,28 @@ template <typename T> struct Impl : ImplBase {
                 for (size_t j = 0; j < ncell; ++j) rcs += params[i].class_runoff[grids[i].land_class[j]];
                 c.rain_cells = rcs;
             }
+            // inflow links: series of each edge link in the out_acc order (N, S, W, E)
+            d.inflow_id = nullptr;
+            c.n_series = params[i].n_inflow > 0 ? params[i].n_series : 0;
+            if (c.n_series) {
+                const int nbl = 2 * (c.nx + c.ny);
+                std::vector<int8_t> id(nbl, -1);
+                for (int k = 0; k < kMaxSeries; ++k) c.wq[k] = 0.0;
+                for (int k = 0; k < params[i].n_inflow; ++k) {
+                    const int32_t* f = params[i].inflow + 3 * k;
+                    const int e = f[0], pos = f[1];
+                    const int at = e == 0 ? pos : e == 2 ? c.nx + pos : e == 3 ? 2 * c.nx + pos : 2 * c.nx + c.ny + pos;
+                    id[at] = (int8_t)f[2];
+                    c.wq[f[2]] += c.dx;
+                }
+                int8_t* did;
+                CHK(dalloc(&did, (size_t)nbl, err));
+                HIPCHK(hipMemcpy(did, id.data(), nbl, hipMemcpyHostToDevice));
+                d.inflow_id = did;
+                const size_t nq = (size_t)c.n_series * std::max(c.p.n_rain, 0);
+                CHK(dalloc(&c.d_inflow_q, std::max<size_t>(nq, 1), err));
+                if (nq) HIPCHK(hipMemcpy(c.d_inflow_q, params[i].inflow_q, nq * sizeof(double), hipMemcpyHostToDevice));
+            }
             if (c.p.track_peak) {
                 CHK(dalloc(&d.peak, c.state_elems, err));
                 CHK(dalloc(&c.peak_tmp, c.state_elems, err));
@@ -375,6 +417,7 @@ template <typename T> struct Impl : ImplBase {
         CHK(dalloc(&clsn, (size_t)n_total * kMaxClasses, err));
         CHK(dalloc(&drain, n_total, err));
         CHK(dalloc(&vdrain, n_total, err));
+        CHK(dalloc(&vin, n_total, err));
         CHK(dalloc(&par, n_total, err));
         CHK(dalloc(&fault, n_total, err));
         CHK(dalloc(&status, 1, err));
@@ -410,6 +453,7 @@ template <typename T> struct Impl : ImplBase {
         HIPCHK(hipMemsetAsync(vout, 0, n_total * sizeof(double), st));
         HIPCHK(hipMemsetAsync(vclamp, 0, n_total * sizeof(double), st));
         HIPCHK(hipMemsetAsync(vdrain, 0, n_total * sizeof(double), st));
+        HIPCHK(hipMemsetAsync(vin, 0, n_total * sizeof(double), st));
         HIPCHK(hipMemsetAsync(steps, 0, n_total * sizeof(int64_t), st));
         HIPCHK(hipMemsetAsync(par, 0, n_total * sizeof(int32_t), st));
         HIPCHK(hipMemsetAsync(fault, 0, n_total * sizeof(int32_t), st));
@@ -467,6 +511,9 @@ template <typename T> struct Impl : ImplBase {
             pc.g = c.p.g;
             pc.dx = c.dx;
             pc.ncells = c.rain_cells;
+            pc.inflow_q = c.d_inflow_q;
+            pc.n_series = c.n_series;
+            for (int k = 0; k < kMaxSeries; ++k) pc.wq[k] = c.wq[k];
         }
         PL.t_end = d_tend;
         PL.t = t;
@@ -477,6 +524,7 @@ template <typename T> struct Impl : ImplBase {
         PL.fault = fault;
         PL.status = status;
         PL.vrain = vrain;
+        PL.vin = vin;
         PL.hbins = hbins;
         PL.ms = ms;
         PL.dtlog = nullptr;
@@ -514,7 +562,7 @@ template <typename T> struct Impl : ImplBase {
     flood_status autotune_geometry(const TuneKey& key, const flood_params* params, std::string& err) {
         TuneChoice cached;
         if (tune_lookup(key, mi, cached)) {
-            if (!params[0].step_kernel && mi == 1 && !any_land) variant = cached.variant;
+            if (!params[0].step_kernel && mi == 1 && !vector_only()) variant = cached.variant;
             if (!params[0].march_members) march_seg = cached.march_seg;
             march_order = cached.march_order;
             for (int i = 0; i < n_catch; ++i) {
@@ -582,8 +630,8 @@ template <typename T> struct Impl : ImplBase {
             int variant, rows, cpb, mrows, seg, order;
         };
         std::vector<Cand> cands;
-        const bool want1 = !any_land && (params[0].step_kernel == 0 || params[0].step_kernel == 1 || mi != 1);
-        const bool want2 = !any_land && mi == 1 && (params[0].step_kernel == 0 || params[0].step_kernel == 2);
+        const bool want1 = !vector_only() && (params[0].step_kernel == 0 || params[0].step_kernel == 1 || mi != 1);
+        const bool want2 = !vector_only() && mi == 1 && (params[0].step_kernel == 0 || params[0].step_kernel == 2);
         const bool want3 = vector_ok() && (params[0].step_kernel == 0 || params[0].step_kernel == 3);
         if (want1)
             for (int r : {1, 2, 4, 8})
@@ -692,7 +740,7 @@ template <typename T> struct Impl : ImplBase {
         // only a search over the full candidate set is remembered: a handle that
         // pinned part of the geometry measured a subset, whose best need not be
         // the best for a later handle of the same shape
-        bool free_search = !any_land;
+        bool free_search = !vector_only();
         for (int i = 0; i < n_catch; ++i)
             free_search &= params[i].tile_rows == 0 && params[i].chunks_per_block == 0 &&
                            params[i].step_kernel == 0 && params[i].march_rows == 0 &&
@@ -841,17 +889,23 @@ template <typename T> struct Impl : ImplBase {
     }
 
     flood_status assimilate(int c, int K, const int32_t* grc, const double* obs, const double* sigma,
-                            double neff_frac, double u0, const double* beta, double* neff_out, int32_t* anc_out,
-                            int32_t* res_out, std::string& err) override {
+                            int with_sections, double alpha, double neff_frac, double u0, const double* beta,
+                            double* neff_out, int32_t* anc_out, int32_t* res_out, std::string& err) override {
         CHK(check_catch(c, err));
         const Cat& C = cats[c];
-        if (K < 0 || K > 4096) { err = "n_gauges must be in [0, 4096]"; return FLOOD_EINVAL; }
-        if (K > 0 && (!grc || !obs || !sigma)) { err = "gauge_rc, obs and sigma are required"; return FLOOD_EINVAL; }
-        for (int k = 0; k < K; ++k) {
+        // observation vector: K gauge depths, then the registered sections' discharges
+        const int S = with_sections ? C.n_sec : 0;
+        const int KT = K + S;
+        if (K < 0 || KT > 4096) { err = "n_gauges (plus sections) must be in [0, 4096]"; return FLOOD_EINVAL; }
+        if (K > 0 && !grc) { err = "gauge_rc is required"; return FLOOD_EINVAL; }
+        if (KT > 0 && (!obs || !sigma)) { err = "obs and sigma are required"; return FLOOD_EINVAL; }
+        if (!(alpha >= 0.0) || !finite_d(alpha)) { err = "alpha must be finite and >= 0"; return FLOOD_EINVAL; }
+        for (int k = 0; k < K; ++k)
             if (grc[2 * k] < 0 || grc[2 * k] >= C.ny || grc[2 * k + 1] < 0 || grc[2 * k + 1] >= C.nx) {
                 err = "gauge outside the grid";
                 return FLOOD_EINVAL;
             }
+        for (int k = 0; k < KT; ++k) {
             if (!finite_d(obs[k])) { err = "obs must be finite"; return FLOOD_EINVAL; }
             if (!(sigma[k] > 0.0) || !finite_d(sigma[k])) { err = "sigma must be finite and > 0"; return FLOOD_EINVAL; }
         }
@@ -866,16 +920,19 @@ template <typename T> struct Impl : ImplBase {
         const int nb = 2 * (C.nx + C.ny);
         launch_flush_outflow(C.N, nb, C.dev.out_acc, vout + off, st);
         if (C.dev.drain_acc) launch_flush_outflow(C.N, kBins, C.dev.drain_acc, vdrain + off, st);
-        if (K > 0) {
-            HIPCHK(hipMemcpyAsync(d_grc, grc, 2 * K * sizeof(int32_t), hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemcpyAsync(d_obs, obs, K * sizeof(double), hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemcpyAsync(d_sigma, sigma, K * sizeof(double), hipMemcpyHostToDevice, st));
+        if (K > 0) HIPCHK(hipMemcpyAsync(d_grc, grc, 2 * K * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        if (KT > 0) {
+            HIPCHK(hipMemcpyAsync(d_obs, obs, KT * sizeof(double), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(d_sigma, sigma, KT * sizeof(double), hipMemcpyHostToDevice, st));
         }
         if (beta) HIPCHK(hipMemcpyAsync(d_beta, beta, C.N * sizeof(double), hipMemcpyHostToDevice, st));
-        launch_gauges<T>(mi, C.dev, par, K, d_grc, d_y, st);
+        launch_gauges<T>(mi, C.dev, par, K, d_grc, d_y, KT, st);
+        launch_sections<T>(mi, C.dev, par, S, C.d_sec_offs, C.d_sec_code, C.d_sec_index, d_y, KT, K, st);
         PfArgs a{};
         a.N = C.N;
-        a.K = K;
+        a.K = KT;
+        a.alpha = alpha;
+        a.vin = vin + off;
         a.y = d_y;
         a.d = d_obs;
         a.sigma = d_sigma;
@@ -912,6 +969,67 @@ template <typename T> struct Impl : ImplBase {
         HIPCHK(hipStreamSynchronize(st));
         if (neff_out) *neff_out = hn;
         if (res_out) *res_out = hflag;
+        return FLOOD_OK;
+    }
+
+    // streamflow sections (Sec. 4.4): links in the host layouts, converted to
+    // the device arrays (east / south edge links are the last cell's qx / qy;
+    // west / north edge links live in the edge strips)
+    flood_status set_sections(int c, int n, const int32_t* count, const int32_t* links, std::string& err) override {
+        CHK(check_catch(c, err));
+        Cat& C = cats[c];
+        if (n < 0 || n > kMaxSections) { err = "n_sections must be in [0, 64]"; return FLOOD_EINVAL; }
+        if (n > 0 && (!count || !links)) { err = "link_count and links are required"; return FLOOD_EINVAL; }
+        std::vector<int32_t> offs(1, 0), code, index;
+        for (int sct = 0; sct < n; ++sct) {
+            if (count[sct] < 1) { err = "every section needs at least one link"; return FLOOD_EINVAL; }
+            if ((int64_t)offs.back() + count[sct] > 65536) { err = "at most 65536 section links"; return FLOOD_EINVAL; }
+            for (int l = offs.back(); l < offs.back() + count[sct]; ++l) {
+                const int32_t* f = links + 4 * (size_t)l;
+                const int kind = f[0], r = f[1], cc = f[2], sg = f[3];
+                if (sg != 1 && sg != -1) { err = "link sign must be +1 or -1"; return FLOOD_EINVAL; }
+                int cd, ix;
+                if (kind == 0 && r >= 0 && r < C.ny && cc >= 0 && cc <= C.nx) {
+                    cd = cc == 0 ? 2 : 0;
+                    ix = cc == 0 ? r : r * C.nx + cc - 1;
+                } else if (kind == 1 && r >= 0 && r <= C.ny && cc >= 0 && cc < C.nx) {
+                    cd = r == 0 ? 3 : 1;
+                    ix = r == 0 ? cc : (r - 1) * C.nx + cc;
+                } else {
+                    err = "section link outside the grid (kind 0: r < ny, c <= nx; kind 1: r <= ny, c < nx)";
+                    return FLOOD_EINVAL;
+                }
+                code.push_back(cd | (sg < 0 ? 4 : 0));
+                index.push_back(ix);
+            }
+            offs.push_back(offs.back() + count[sct]);
+        }
+        const size_t L = code.size();
+        if (L > C.sec_cap) {
+            CHK(dalloc(&C.d_sec_code, L, err));
+            CHK(dalloc(&C.d_sec_index, L, err));
+            C.sec_cap = L;
+        }
+        if (!C.d_sec_offs) CHK(dalloc(&C.d_sec_offs, (size_t)kMaxSections + 1, err));
+        HIPCHK(hipMemcpyAsync(C.d_sec_offs, offs.data(), offs.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        if (L) {
+            HIPCHK(hipMemcpyAsync(C.d_sec_code, code.data(), L * sizeof(int32_t), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(C.d_sec_index, index.data(), L * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        C.n_sec = n;
+        return FLOOD_OK;
+    }
+
+    flood_status get_sections(int c, double* q_out, std::string& err) override {
+        CHK(check_catch(c, err));
+        const Cat& C = cats[c];
+        if (!q_out) { err = "q_out is NULL"; return FLOOD_EINVAL; }
+        if (C.n_sec == 0) { err = "no section is registered for this catchment"; return FLOOD_ESTATE; }
+        launch_sections<T>(mi, C.dev, par, C.n_sec, C.d_sec_offs, C.d_sec_code, C.d_sec_index, d_y, C.n_sec, 0, st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(q_out, d_y, (size_t)C.N * C.n_sec * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
         return FLOOD_OK;
     }
 
@@ -1029,7 +1147,7 @@ template <typename T> struct Impl : ImplBase {
     }
 
     flood_status get_ledger(int c, double* storage, double* rain_in, double* outflow, double* clamp,
-                            double* drained, double* tt, int64_t* stp, std::string& err) override {
+                            double* drained, double* inflow, double* tt, int64_t* stp, std::string& err) override {
         CHK(check_catch(c, err));
         const Cat& C = cats[c];
         const int off = C.dev.member_off;
@@ -1045,6 +1163,7 @@ template <typename T> struct Impl : ImplBase {
         if (outflow) HIPCHK(hipMemcpyAsync(outflow, vout + off, C.N * sizeof(double), hipMemcpyDeviceToHost, st));
         if (clamp) HIPCHK(hipMemcpyAsync(clamp, vclamp + off, C.N * sizeof(double), hipMemcpyDeviceToHost, st));
         if (drained) HIPCHK(hipMemcpyAsync(drained, vdrain + off, C.N * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (inflow) HIPCHK(hipMemcpyAsync(inflow, vin + off, C.N * sizeof(double), hipMemcpyDeviceToHost, st));
         if (tt) HIPCHK(hipMemcpyAsync(tt, t + off, C.N * sizeof(double), hipMemcpyDeviceToHost, st));
         if (stp) HIPCHK(hipMemcpyAsync(stp, steps + off, C.N * sizeof(int64_t), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -1114,6 +1233,7 @@ template <typename T> struct Impl : ImplBase {
         v.push_back({clsn, n * kMaxClasses * 8});
         v.push_back({drain, n * 8});
         v.push_back({vdrain, n * 8});
+        v.push_back({vin, n * 8});
         v.push_back({par, n * 4});
         v.push_back({fault, n * 4});
         v.push_back({hbins, (size_t)kBins * n * sizeof(HB)});
@@ -1121,13 +1241,14 @@ template <typename T> struct Impl : ImplBase {
     }
 
     void header(std::vector<int64_t>& hd) const {
-        hd = {0x464c4f4f44534e31LL, (int64_t)sizeof(T), mi, n_catch, n_total};
+        hd = {0x464c4f4f44534e32LL, (int64_t)sizeof(T), mi, n_catch, n_total};
         for (auto& C : cats) {
             hd.push_back(C.ny);
             hd.push_back(C.nx);
             hd.push_back(C.N);
             hd.push_back(C.dev.peak ? 1 : 0);
             hd.push_back(C.n_classes);
+            hd.push_back(C.n_series);
         }
     }
 
@@ -1334,6 +1455,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
     CHK(check_catch(c, err));
     Cat& C = cats[c];
     if (C.n_classes) { err = "the adjoint does not support land cover"; return FLOOD_EINVAL; }
+    if (C.n_series) { err = "the adjoint does not support inflow links"; return FLOOD_EINVAL; }
     if (!(sample_dt > 0.0) || !finite_d(sample_dt)) { err = "sample_dt must be finite and > 0"; return FLOOD_EINVAL; }
     if (!finite_d(t_end)) { err = "t_end must be finite"; return FLOOD_EINVAL; }
     if (K < 0 || K > 4096) { err = "n_gauges must be in [0, 4096]"; return FLOOD_EINVAL; }

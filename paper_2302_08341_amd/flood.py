@@ -23,7 +23,7 @@ FIELD_H, FIELD_QX, FIELD_QY, FIELD_PEAK = 0, 1, 2, 3
 EXPORTED = ["flood_create", "flood_create_batch", "flood_step", "flood_assimilate", "flood_adjoint",
             "flood_get_field", "flood_set_state", "flood_set_params", "flood_get_ledger", "flood_get_weights",
             "flood_systematic_resample", "flood_ensemble_products", "flood_get_land_params", "flood_save",
-            "flood_load",
+            "flood_load", "flood_set_sections", "flood_get_sections", "flood_assimilate_obs",
             "flood_get_config", "flood_timing", "flood_get_timing", "flood_last_error", "flood_strerror",
             "flood_destroy"]
 
@@ -53,7 +53,8 @@ class FloodParams(C.Structure):
                 ("step_kernel", C.c_int32), ("march_rows", C.c_int32), ("march_members", C.c_int32),
                 ("track_peak", C.c_int32), ("n_classes", C.c_int32), ("class_runoff", C.POINTER(C.c_double)),
                 ("class_drain", C.POINTER(C.c_int32)), ("member_class_n", C.POINTER(C.c_double)),
-                ("member_drain", C.POINTER(C.c_double))]
+                ("member_drain", C.POINTER(C.c_double)), ("n_inflow", C.c_int32),
+                ("inflow", C.POINTER(C.c_int32)), ("n_series", C.c_int32), ("inflow_q", C.POINTER(C.c_double))]
 
 
 _lib = None
@@ -81,7 +82,11 @@ def load_library():
         "flood_get_field": [H, C.c_int32, C.c_int32, C.c_int32, dp],
         "flood_set_state": [H, C.c_int32, C.c_int32, dp, dp, dp, C.c_double],
         "flood_set_params": [H, C.c_int32, fp, dp, dp],
-        "flood_get_ledger": [H, C.c_int32, dp, dp, dp, dp, dp, dp, lp],
+        "flood_get_ledger": [H, C.c_int32, dp, dp, dp, dp, dp, dp, dp, lp],
+        "flood_set_sections": [H, C.c_int32, C.c_int32, ip, ip],
+        "flood_get_sections": [H, C.c_int32, dp],
+        "flood_assimilate_obs": [H, C.c_int32, C.c_int32, ip, dp, dp, C.c_double, C.c_double, C.c_double, dp, dp,
+                                 ip, ip],
         "flood_get_land_params": [H, C.c_int32, dp, dp],
         "flood_get_weights": [H, C.c_int32, dp, dp, dp],
         "flood_systematic_resample": [dp, C.c_int32, C.c_double, ip, C.c_void_p],
@@ -160,20 +165,25 @@ def make_grid(dem, manning, dx, edge_kind=(0, 0, 0, 0), edge_slope=(0, 0, 0, 0),
 def make_params(rain, rain_interval=300.0, cfl_alpha=0.7, h_dry=1e-3, dt_cap=10.0, dt_fixed=0.0, g=9.81,
                 real_bytes=4, member_interleave=0, tile_rows=0, chunks_per_block=0, step_kernel=0, march_rows=0,
                 march_members=0, track_peak=0, class_runoff=None, class_drain=None, member_class_n=None,
-                member_drain=None):
+                member_drain=None, inflow=None, inflow_q=None):
     rain = _f64(np.asarray(rain, dtype=np.float64).ravel())
     rc = None if class_runoff is None else _f64(np.asarray(class_runoff, dtype=np.float64).ravel())
     cd = None if class_drain is None else np.ascontiguousarray(np.asarray(class_drain, dtype=np.int32).ravel())
     cn = None if member_class_n is None else _f64(np.asarray(member_class_n, dtype=np.float64).ravel())
     md = None if member_drain is None else _f64(np.asarray(member_drain, dtype=np.float64).ravel())
+    inf = None if inflow is None else np.ascontiguousarray(np.asarray(inflow, dtype=np.int32).reshape(-1, 3))
+    iq = None if inflow_q is None else _f64(np.atleast_2d(np.asarray(inflow_q, dtype=np.float64)))
+    n_inf = 0 if inf is None else inf.shape[0]
+    n_ser = 0 if iq is None or n_inf == 0 else iq.shape[0]
     p = FloodParams(_dp(rain) if rain.size else None, int(rain.size), float(rain_interval), float(cfl_alpha),
                     float(h_dry), float(dt_cap), float(dt_fixed), float(g), int(real_bytes),
                     int(member_interleave), int(tile_rows), int(chunks_per_block), int(step_kernel),
                     int(march_rows), int(march_members), int(bool(track_peak)),
                     0 if rc is None else int(rc.size), _dp(rc) if rc is not None else None,
                     cd.ctypes.data_as(C.POINTER(C.c_int32)) if cd is not None else None,
-                    _dp(cn) if cn is not None else None, _dp(md) if md is not None else None)
-    p._keep = (rain, rc, cd, cn, md)
+                    _dp(cn) if cn is not None else None, _dp(md) if md is not None else None,
+                    n_inf, _ip(inf) if n_inf else None, n_ser, _dp(iq) if n_ser and iq.size else None)
+    p._keep = (rain, rc, cd, cn, md, inf, iq)
     return p
 
 
@@ -220,6 +230,40 @@ def flood_assimilate(h, catchment, gauges, obs, sigma, neff_frac=0.8, u0=0.5, be
     return neff.value, anc, bool(res.value)
 
 
+def flood_assimilate_obs(h, catchment, gauges, obs, sigma, alpha=0.0, neff_frac=0.8, u0=0.5, beta=None,
+                         n_members=None):
+    """Filter cycle on depth gauges followed by every registered streamflow section;
+    obs and sigma hold the depths first, then the flows; alpha > 0: relative error
+    with sigma as its floor."""
+    g = np.ascontiguousarray(np.asarray(gauges, dtype=np.int32).reshape(-1, 2))
+    obs, sigma, beta = _f64(obs), _f64(sigma), _f64(beta)
+    N = n_members
+    neff = C.c_double(0)
+    anc = np.zeros(N, dtype=np.int32)
+    res = C.c_int32(0)
+    rc = load_library().flood_assimilate_obs(h, int(catchment), g.shape[0], _ip(g), _dp(obs), _dp(sigma),
+                                             float(alpha), float(neff_frac), float(u0), _dp(beta), C.byref(neff),
+                                             _ip(anc), C.byref(res))
+    _check(rc, h)
+    return neff.value, anc, bool(res.value)
+
+
+def flood_set_sections(h, catchment, sections):
+    """Register streamflow sections: a list of [n_links, 4] arrays (kind 0 x-link / 1 y-link,
+    r, c, sign) in the host discharge layouts."""
+    secs = [np.asarray(s, dtype=np.int32).reshape(-1, 4) for s in sections]
+    counts = np.array([x.shape[0] for x in secs], dtype=np.int32)
+    links = np.ascontiguousarray(np.concatenate(secs) if secs else np.zeros((0, 4), np.int32), dtype=np.int32)
+    _check(load_library().flood_set_sections(h, int(catchment), len(secs), _ip(counts) if len(secs) else None,
+                                             _ip(links) if links.size else None), h)
+
+
+def flood_get_sections(h, catchment, n_members, n_sections):
+    out = np.zeros(max(n_members * n_sections, 1))
+    _check(load_library().flood_get_sections(h, int(catchment), _dp(out)), h)
+    return out[:n_members * n_sections].reshape(n_members, n_sections)
+
+
 def flood_adjoint(h, catchment, t_end, sample_dt, gauges, obs, ckpt_every, ny, nx, n_members):
     g = np.ascontiguousarray(np.asarray(gauges, dtype=np.int32).reshape(-1, 2))
     obs = _f64(obs)
@@ -262,11 +306,11 @@ def flood_set_params(h, catchment, manning=None, n_scale=None, rain_mult=None):
 
 
 def flood_get_ledger(h, catchment, n_members):
-    out = {k: np.zeros(n_members) for k in ("storage", "rain_in", "outflow", "clamp", "drain", "t")}
+    out = {k: np.zeros(n_members) for k in ("storage", "rain_in", "outflow", "clamp", "drain", "inflow", "t")}
     steps = np.zeros(n_members, dtype=np.int64)
     rc = load_library().flood_get_ledger(h, int(catchment), _dp(out["storage"]), _dp(out["rain_in"]),
-                                         _dp(out["outflow"]), _dp(out["clamp"]), _dp(out["drain"]), _dp(out["t"]),
-                                         steps.ctypes.data_as(C.POINTER(C.c_int64)))
+                                         _dp(out["outflow"]), _dp(out["clamp"]), _dp(out["drain"]),
+                                         _dp(out["inflow"]), _dp(out["t"]), steps.ctypes.data_as(C.POINTER(C.c_int64)))
     _check(rc, h)
     out["steps"] = steps
     return out
@@ -341,12 +385,16 @@ class FloodEnsemble:
             params.append(make_params(rain, rain_interval, cfl_alpha, h_dry, dt_cap, dt_fixed, g, real_bytes,
                                       member_interleave, tile_rows, chunks_per_block, step_kernel, march_rows,
                                       march_members, track_peak, c.get("class_runoff"), c.get("class_drain"),
-                                      c.get("class_n"), c.get("drain")))
+                                      c.get("class_n"), c.get("drain"), c.get("inflow"), c.get("inflow_q")))
         self._keep = (grids, params)
         self.stream = current_stream() if stream == "torch" else stream
         self.h = flood_create_batch(grids, params, [c["n_members"] for c in self.catchments],
                                     [c.get("n_scale") for c in self.catchments],
                                     [c.get("rain_mult") for c in self.catchments], self.stream)
+        self._n_sections = [0] * len(self.catchments)
+        for i, c in enumerate(self.catchments):
+            if c.get("sections") is not None and len(c["sections"]):
+                self.set_sections(c["sections"], i)
 
     @classmethod
     def from_workload(cls, wl, catchments=None, members=None, **over):
@@ -360,6 +408,10 @@ class FloodEnsemble:
             if getattr(c, "land_class", None) is not None:
                 d.update(land_class=c.land_class, class_runoff=c.class_runoff, class_drain=c.class_drain,
                          class_n=c.class_n[:n], drain=c.drain[:n])
+            if getattr(c, "inflow", None) is not None:
+                d.update(inflow=c.inflow, inflow_q=c.inflow_q)
+            if getattr(c, "sections", None) is not None:
+                d.update(sections=c.sections)
             cs.append(d)
         kw = dict(rain_interval=wl.rain_interval, cfl_alpha=wl.cfl_alpha, h_dry=wl.h_dry, dt_cap=wl.dt_cap,
                   dt_fixed=wl.dt_fixed, g=wl.g, real_bytes=wl.real_bytes)
@@ -379,6 +431,19 @@ class FloodEnsemble:
     def assimilate(self, catchment, gauges, obs, sigma, neff_frac=0.8, u0=0.5, beta=None):
         return flood_assimilate(self.h, catchment, gauges, obs, sigma, neff_frac, u0, beta,
                                 n_members=self.n_members(catchment))
+
+    def assimilate_obs(self, catchment, gauges, obs, sigma, alpha=0.0, neff_frac=0.8, u0=0.5, beta=None):
+        """Depth gauges and the registered streamflow sections together (see flood_assimilate_obs)."""
+        return flood_assimilate_obs(self.h, catchment, gauges, obs, sigma, alpha, neff_frac, u0, beta,
+                                    n_members=self.n_members(catchment))
+
+    def set_sections(self, sections, catchment=0):
+        flood_set_sections(self.h, catchment, sections)
+        self._n_sections[catchment] = len(sections)
+
+    def sections(self, catchment=0):
+        """Discharge through every registered section, [N, n_sections] (m^3/s)."""
+        return flood_get_sections(self.h, catchment, self.n_members(catchment), self._n_sections[catchment])
 
     def adjoint(self, catchment, t_end, sample_dt, gauges, obs, ckpt_every=100):
         ny, nx = self.shape(catchment)

@@ -129,6 +129,55 @@ def test_land_cover_is_validated_before_touching_the_device(lib, bad):
     assert lib.flood_last_error(None)
 
 
+@pytest.mark.parametrize("bad", ["edge", "position", "series_index", "duplicate", "negative_q", "nan_q",
+                                 "n_series", "missing_q", "missing_links", "too_many", "kernel", "interleave"])
+def test_inflow_is_validated_before_touching_the_device(lib, bad):
+    from paper_2302_08341_amd import flood
+    g = _grid()                                     # 4 x 5 cells
+    inflow = [(0, 2, 0), (3, 1, 1)]
+    q = [[0.01, 0.02], [0.0, 0.03]]
+    extra = {}
+    if bad == "edge":
+        inflow = [(4, 0, 0)]
+    elif bad == "position":
+        inflow = [(1, 4, 0)]                         # east edge has rows 0..3
+    elif bad == "series_index":
+        inflow = [(0, 0, 2)]
+    elif bad == "duplicate":
+        inflow = [(0, 2, 0), (0, 2, 1)]
+    elif bad == "negative_q":
+        q = [[0.01, -0.02], [0.0, 0.03]]
+    elif bad == "nan_q":
+        q = [[0.01, float("nan")], [0.0, 0.03]]
+    elif bad == "n_series":
+        q = [[0.01, 0.0]] * 5
+        inflow = [(0, 0, 4)]
+    elif bad == "kernel":
+        extra = dict(step_kernel=2)
+    elif bad == "interleave":
+        extra = dict(member_interleave=4)
+    p = flood.make_params([1e-5, 2e-5], real_bytes=4, inflow=inflow, inflow_q=q, **extra)
+    if bad == "missing_q":
+        p.inflow_q = None
+    elif bad == "missing_links":
+        p.inflow = None
+    elif bad == "too_many":
+        p.n_inflow = 2 * (4 + 5) + 1
+    h = C.c_void_p()
+    rc = lib.flood_create(C.byref(g), C.byref(p), 2, None, None, None, C.byref(h))
+    assert rc == flood.FLOOD_EINVAL, bad
+    assert not h.value
+    assert lib.flood_last_error(None)
+
+
+def test_section_and_observation_calls_reject_a_null_handle(lib):
+    from paper_2302_08341_amd import flood
+    assert lib.flood_set_sections(None, 0, 0, None, None) == flood.FLOOD_EINVAL
+    assert lib.flood_get_sections(None, 0, None) == flood.FLOOD_EINVAL
+    assert lib.flood_assimilate_obs(None, 0, 0, None, None, None, 0.05, 0.8, 0.5, None, None, None,
+                                    None) == flood.FLOOD_EINVAL
+
+
 def test_null_handle_calls_are_rejected(lib):
     from paper_2302_08341_amd import flood
     assert lib.flood_step(None, 1.0) == flood.FLOOD_EINVAL
@@ -159,3 +208,16 @@ def test_no_cpu_fallback_without_device(lib):
     h = C.c_void_p()
     rc = lib.flood_create(C.byref(g), C.byref(p), 2, None, None, None, C.byref(h))
     assert rc == flood.FLOOD_EHIP
+
+
+def test_valid_inflow_passes_validation(lib):
+    # with no device the call gets past validation and fails at the first HIP call
+    from paper_2302_08341_amd import flood
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    p = flood.make_params([1e-5, 2e-5], real_bytes=4, inflow=[(0, 2, 0), (3, 1, 1), (2, 0, 0), (1, 3, 1)],
+                          inflow_q=[[0.01, 0.02], [0.0, 0.03]])
+    h = C.c_void_p()
+    g = _grid()
+    assert lib.flood_create(C.byref(g), C.byref(p), 2, None, None, None, C.byref(h)) == flood.FLOOD_EHIP

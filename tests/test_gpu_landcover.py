@@ -15,6 +15,7 @@ import tempfile
 import numpy as np
 import pytest
 
+import trajectory as TR
 import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -71,19 +72,6 @@ def test_fp64_trajectory_and_ledger_match_oracle(fl, orc):
     assert resid.max() <= 1e-12
 
 
-def _divergence(h, qx, qy, ref, dx):
-    """Distances of a trajectory from the reference member: largest depth error,
-    cells beyond 1e-4 m, largest section and edge discharge error relative to the
-    largest section discharge (sections as in the forward tests)."""
-    d = np.abs(h - ref.h)
-    sec = lambda a, b: np.concatenate([a[:, ::4].sum(axis=0), b[::4, :].sum(axis=1)]) * dx
-    edge = lambda a, b: np.array([b[0].sum(), a[:, -1].sum(), b[-1].sum(), a[:, 0].sum()]) * dx
-    sr, er = sec(ref.qx, ref.qy), edge(ref.qx, ref.qy)
-    qs = max(np.abs(sr).max(), np.abs(er).max())
-    return np.array([d.max(), np.count_nonzero(d > 1e-4), np.abs(sec(qx, qy) - sr).max() / qs,
-                     np.abs(edge(qx, qy) - er).max() / qs])
-
-
 def test_fp32_trajectory_matches_oracle(fl, orc):
     # With land cover most of the ground is hardened and drained, and sits near
     # h_dry.  There the trajectory branches on when a cell crosses h_dry: the FP64
@@ -98,17 +86,18 @@ def test_fp32_trajectory_matches_oracle(fl, orc):
     e = _ens(fl, real_bytes=4)
     e.step(1500.0)
     led = e.ledger()
-    tight = np.array([1e-4, 0, 1e-4, 1e-4])
     for i in range(4):
         _, ref = _oracle(orc, i, 1500.0)
-        spread, dspread = np.zeros(4), 0.0
-        for f in (1 + 1e-6, 1 - 1e-6, 1 + 1e-5, 1 - 1e-5):
-            _, p = _oracle(orc, i, 1500.0, mu_factor=f)
-            spread = np.maximum(spread, _divergence(p.h, p.qx, p.qy, ref, CAT.dx))
-            dspread = max(dspread, abs(p.v_drain - ref.v_drain) / ref.v_drain)
-        got = _divergence(e.field(i), e.field(i, fl.FIELD_QX), e.field(i, fl.FIELD_QY), ref, CAT.dx)
-        print("member", i, "GPU FP32", got, "oracle spread", spread, flush=True)
-        assert np.all(got <= np.maximum(tight, spread))
+        runs = {}
+
+        def run(f):
+            runs[f] = _oracle(orc, i, 1500.0, mu_factor=f)[1]
+            return runs[f]
+        sp = TR.spread(run, ref, CAT.dx)
+        dspread = max(abs(p.v_drain - ref.v_drain) / ref.v_drain for p in runs.values())
+        got = TR.divergence(e.field(i), e.field(i, fl.FIELD_QX), e.field(i, fl.FIELD_QY), ref, CAT.dx)
+        print("member", i, "GPU FP32", got, "oracle spread", sp, flush=True)
+        assert np.all(got <= np.maximum(TR.TIGHT, sp))
         assert led["drain"][i] == pytest.approx(ref.v_drain, rel=max(1e-4, dspread))
         assert led["rain_in"][i] == pytest.approx(ref.v_rain, rel=1e-6)
     resid = np.abs(led["storage"] - (led["rain_in"] - led["outflow"] + led["clamp"] - led["drain"])) / led["rain_in"]
