@@ -27,6 +27,8 @@ region:
   * the running maximum depth tracked through the first window (its cost) and
     the ensemble products of every cell (Sec. 4.4, Figs. 15-16);
   * the same ensemble with land cover (Table 1) over its first window;
+  * the same ensemble with two stream outlets (inflow hydrographs) over its
+    first window and a filter cycle on depths and streamflow together;
   * the streaming ceiling of one elementwise kernel (2 GiB in, 2 GiB out).
 
 The timed cycles run last among full-size launches of the step kernel, so
@@ -282,6 +284,39 @@ def leg_land_cover(FloodEnsemble, W, args):
             "drained_over_rain": float(led["drain"].sum() / led["rain_in"].sum())}
 
 
+def leg_streams(FloodEnsemble, W, args):
+    """The same grid and ensemble with two stream outlets (inflow hydrographs,
+    Sec. 4.1) over its first window, then one filter cycle on the depth gauges and
+    the two streamflow sections together with 5 % relative error (Sec. 4.4)."""
+    import torch
+    wl = W.config5(args.ny, args.nx, args.members, with_inflow=True)
+    c = wl.catchments[0]
+    ncell = c.ny * c.nx
+    ens = FloodEnsemble.from_workload(wl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.step(args.window)
+    torch.cuda.synchronize()
+    t_step = time.perf_counter() - t0
+    led = ens.ledger()
+    steps = int(led["steps"].sum())
+    K = c.gauges.shape[0]
+    y = np.concatenate([np.array([ens.field(i)[c.gauges[:, 0], c.gauges[:, 1]] for i in (0,)]),
+                        ens.sections()[:1]], axis=1)[0]
+    obs = y * np.random.default_rng(wl.seed + 9).normal(1.0, 0.05, size=y.size)
+    floor = np.concatenate([np.full(K, 0.01), np.full(len(c.sections), 0.01)])
+    t0 = time.perf_counter()
+    neff, _, res = ens.assimilate_obs(0, c.gauges, obs, floor, alpha=0.05, neff_frac=0.8, u0=0.5)
+    t_pf = time.perf_counter() - t0
+    ens.close()
+    log("streams leg: %.2f s stepping, filter on %d depths + %d flows %.4f s" % (t_step, K, len(c.sections), t_pf))
+    return {"workload": "first %.0f s of this ensemble with two stream outlets (inflow hydrographs on 4 edge "
+                        "links) and 2 streamflow sections" % args.window,
+            "MCUps": steps * ncell / t_step,
+            "inflow_over_rain": float(led["inflow"].sum() / led["rain_in"].sum()),
+            "filter_depths_and_flows_s": t_pf, "filter_neff": neff, "filter_resampled": bool(res)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,6 +340,7 @@ def main():
     ap.add_argument("--no-c4", action="store_true")
     ap.add_argument("--no-products", action="store_true")
     ap.add_argument("--no-land-cover", action="store_true")
+    ap.add_argument("--no-streams", action="store_true")
     ap.add_argument("--land-cover", action="store_true",
                     help="with --kernel-only: the ensemble with land cover (Table 1)")
     ap.add_argument("--c4-window", type=float, default=300.0)
@@ -376,6 +412,8 @@ def main():
         detail["ensemble_products"] = leg_products(FloodEnsemble, wl, args.window)
     if not args.no_land_cover and not args.kernel_only and args.config == 5:
         detail["land_cover"] = leg_land_cover(FloodEnsemble, W, args)
+    if not args.no_streams and not args.kernel_only and args.config == 5:
+        detail["streams"] = leg_streams(FloodEnsemble, W, args)
 
     ens = FloodEnsemble.from_workload(wl, member_interleave=args.mi, tile_rows=args.rows,
                                       chunks_per_block=args.cpb, step_kernel=args.kernel,
