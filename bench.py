@@ -548,7 +548,8 @@ def main():
                    "sim_time_s": [args.warmup * args.window, n_cycles * args.window],
                    "member_interleave": conf["member_interleave"], "tile_rows": conf["tile_rows"],
                    "chunks_per_block": conf["chunks_per_block"], "step_kernel": conf["step_kernel"],
-                   "march_rows": conf["march_rows"], "march_members": conf["march_members"]},
+                   "march_rows": conf["march_rows"], "march_members": conf["march_members"],
+                   "march_order": conf["march_order"]},
         "roofline": roof,
         "cpu_baseline": cpu,
         "detail": detail,

@@ -285,11 +285,12 @@ flood_status flood_load(flood_handle* h, const char* path);
 
 /* Kernel configuration in use: member interleave, tile rows and chunks per
  * workgroup of catchment 0, the number of steps captured per graph, the step
- * kernel variant (1 tiled, 2 row-marching, 3 vectorised row-marching), its rows per strip and members per
- * wavefront.  Any output may be NULL. */
+ * kernel variant (1 tiled, 2 row-marching, 3 vectorised row-marching), its rows per strip, members per
+ * wavefront and wavefront order (0-4: which of member, strip along x and row of strips runs fastest,
+ * and how the rows are spread over the XCDs).  Any output may be NULL. */
 flood_status flood_get_config(const flood_handle* h, int32_t* member_interleave, int32_t* tile_rows,
                               int32_t* chunks_per_block, int32_t* graph_steps, int32_t* step_kernel,
-                              int32_t* march_rows, int32_t* march_members);
+                              int32_t* march_rows, int32_t* march_members, int32_t* march_order);
 
 /* Average duration in ms of the step kernel over the timed region opened by
  * flood_timing(h, 1) and closed by flood_timing(h, 0); per-launch HIP events

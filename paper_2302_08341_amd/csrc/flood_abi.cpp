@@ -363,9 +363,10 @@ flood_status flood_load(flood_handle* h, const char* path) {
 }
 
 flood_status flood_get_config(const flood_handle* h, int32_t* mi, int32_t* tile_rows, int32_t* cpb, int32_t* gsteps,
-                              int32_t* step_kernel, int32_t* march_rows, int32_t* march_members) {
+                              int32_t* step_kernel, int32_t* march_rows, int32_t* march_members,
+                              int32_t* march_order) {
     if (!h || !h->impl) return FLOOD_EINVAL;
-    h->impl->get_config(mi, tile_rows, cpb, gsteps, step_kernel, march_rows, march_members);
+    h->impl->get_config(mi, tile_rows, cpb, gsteps, step_kernel, march_rows, march_members, march_order);
     return FLOOD_OK;
 }
 

@@ -80,8 +80,17 @@ __device__ __forceinline__ size_t state_index(const CatchDev<T>& C, int member, 
 //      wavefronts of a workgroup march the same strip for four units, so the
 //      shared arrays are fetched once per workgroup and each member's rows are
 //      still streamed strip after strip
-// Order 2 pads the unit count to a multiple of four; padding wavefronts get
-// false.
+//   3  strips along x fastest, then units, then rows of strips: the 8 XCDs,
+//      each walking a contiguous range of workgroups, take bands of rows of
+//      every member instead of whole members, so members that are already done
+//      leave every XCD the same share of work, and all units of a row of
+//      strips run on one XCD close in time (the shared bed and roughness of
+//      those rows stay in its L2)
+//   4  the rows of strips cut into 8 bands (one per XCD range of workgroups),
+//      then units, then rows of strips within the band, then strips along x:
+//      order 1 inside each XCD, with every XCD holding a band of every unit
+// Order 2 pads the unit count to a multiple of four and order 4 the rows of
+// strips to a multiple of eight; padding wavefronts get false.
 template <typename T>
 __device__ __forceinline__ bool march_wave(const CatchDev<T>& C, int local, int units, int& k, int& sx, int& sy) {
     if (C.march_order == 0) {
@@ -94,6 +103,22 @@ __device__ __forceinline__ bool march_wave(const CatchDev<T>& C, int local, int 
         const int rest = local / C.strips_x;
         sy = rest % C.strips_y;
         k = rest / C.strips_y;
+    } else if (C.march_order == 4) {
+        const int bh = (C.strips_y + 7) >> 3;                 // rows of strips per band
+        const int per_unit = bh * C.strips_x;
+        const int band = local / (per_unit * units);
+        const int rem = local - band * per_unit * units;
+        k = rem / per_unit;
+        const int rem2 = rem - k * per_unit;
+        sy = band * bh + rem2 / C.strips_x;
+        sx = rem2 % C.strips_x;
+        return sy < C.strips_y && k < units;
+    } else if (C.march_order == 3) {
+        sx = local % C.strips_x;
+        const int rest = local / C.strips_x;
+        k = rest % units;
+        sy = rest / units;
+        return sy < C.strips_y;
     } else {
         const int q = local & 3;
         const int rest = local >> 2;

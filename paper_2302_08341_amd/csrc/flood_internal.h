@@ -159,7 +159,12 @@ template <typename T>
 void launch_marchv(const StepLaunch<T>& L, int nt, int pf, int ext, int total_waves, hipStream_t s);
 // wavefronts of a row-march launch over one catchment: strips x member units,
 // units padded to a multiple of four in wavefront order 2
-inline int march_waves(int strips, int units, int order) { return strips * (order == 2 ? (units + 3) / 4 * 4 : units); }
+// wavefronts of one row-march launch over a catchment (see march_wave)
+inline int march_waves(int strips_x, int strips_y, int units, int order) {
+    if (order == 2) return strips_x * strips_y * ((units + 3) / 4 * 4);
+    if (order == 4) return strips_x * ((strips_y + 7) / 8 * 8) * units;
+    return strips_x * strips_y * units;
+}
 void launch_count_active(int n_total, const double* t, const int32_t* fault, const double* t_end,
                          const int32_t* status, int32_t* out, hipStream_t s);
 template <typename HB> void launch_zero_bins(int off, int n, int n_total, HB* bins, hipStream_t s);

@@ -40,7 +40,7 @@ struct ImplBase {
     virtual flood_status save(const char* path, std::string& err) = 0;
     virtual flood_status load(const char* path, std::string& err) = 0;
     virtual void get_config(int32_t* mi, int32_t* tile_rows, int32_t* cpb, int32_t* gsteps, int32_t* step_kernel,
-                            int32_t* march_rows, int32_t* march_members) const = 0;
+                            int32_t* march_rows, int32_t* march_members, int32_t* march_order) const = 0;
     virtual flood_status timing(bool on, std::string& err) = 0;
     virtual void get_timing(double* avg_ms, int64_t* launches) const = 0;
 };

@@ -66,6 +66,7 @@ template <typename T> struct Impl : ImplBase {
     int variant = 1;          // 1 tiled step kernel, 2 row-marching step kernel (mi == 1)
     int march_seg = 2;        // members per wavefront of the row-marching kernel
     int march_order = 1;      // wavefront order of the row-marching kernel
+    int forced_order = -1;    // >= 0: the only order the tuner tries
     int march_nt = 1;         // non-temporal state streams in the vectorised row-marching kernel
     int march_pf = 1;         // one row of load lookahead in the vectorised row-marching kernel
     int total_waves = 0;      // waves of one row-marching launch
@@ -169,7 +170,7 @@ template <typename T> struct Impl : ImplBase {
             d.strips_x = (c.nx + strip_w - 1) / strip_w;
             d.strips_y = (c.ny + d.march_rows - 1) / d.march_rows;
             d.wave_begin = waves;
-            d.n_waves = march_waves(d.strips_x * d.strips_y, variant == 3 ? c.N : (c.N + march_seg - 1) / march_seg,
+            d.n_waves = march_waves(d.strips_x, d.strips_y, variant == 3 ? c.N : (c.N + march_seg - 1) / march_seg,
                                     march_order);
             d.march_order = march_order;
             waves += d.n_waves;
@@ -215,7 +216,10 @@ template <typename T> struct Impl : ImplBase {
             st = own_stream;
         }
         n_catch = nc;
-        if (const char* mo = std::getenv("FLOOD_MARCH_ORDER")) march_order = std::min(2, std::max(0, std::atoi(mo)));
+        if (const char* mo = std::getenv("FLOOD_MARCH_ORDER")) {   // restricts the tuner to one order
+            march_order = std::min(4, std::max(0, std::atoi(mo)));
+            forced_order = march_order;
+        }
         if (const char* nt = std::getenv("FLOOD_MARCH_NT")) march_nt = std::atoi(nt) ? 1 : 0;
         if (const char* pf = std::getenv("FLOOD_MARCH_PF")) march_pf = std::atoi(pf) ? 1 : 0;
         const char* ng = std::getenv("FLOOD_NO_GRAPH");
@@ -564,7 +568,7 @@ template <typename T> struct Impl : ImplBase {
         if (tune_lookup(key, mi, cached)) {
             if (!params[0].step_kernel && mi == 1 && !vector_only()) variant = cached.variant;
             if (!params[0].march_members) march_seg = cached.march_seg;
-            march_order = cached.march_order;
+            march_order = forced_order >= 0 ? forced_order : cached.march_order;
             for (int i = 0; i < n_catch; ++i) {
                 if (!params[i].tile_rows) cats[i].tile_rows = cached.tile_rows;
                 if (!params[i].chunks_per_block) cats[i].cpb = cached.cpb;
@@ -643,14 +647,16 @@ template <typename T> struct Impl : ImplBase {
                 segs.push_back(params[0].march_members);
             else
                 segs = {1, 2, 4, 8};
-            for (int od : {0, 1, 2})
+            for (int od : {0, 1, 2, 3, 4})
                 for (int sg : segs)
+                    if (forced_order < 0 || od == forced_order)
                     for (int mr : {8, 16, 32, 64, 128})
                         cands.push_back({2, cats[0].tile_rows, cats[0].cpb, mr, sg, od});
         }
         if (want3)
-            for (int od : {0, 1, 2})
-                for (int mr : {4, 8, 16, 32, 64}) cands.push_back({3, cats[0].tile_rows, cats[0].cpb, mr, 1, od});
+            for (int od : {0, 1, 2, 3, 4})
+                if (forced_order < 0 || od == forced_order)
+                    for (int mr : {4, 8, 16, 32, 64}) cands.push_back({3, cats[0].tile_rows, cats[0].cpb, mr, 1, od});
         Cand bc = cands.empty()
                       ? Cand{variant, cats[0].tile_rows, cats[0].cpb, cats[0].march_rows, march_seg, march_order}
                       : cands[0];
@@ -699,6 +705,26 @@ template <typename T> struct Impl : ImplBase {
                 bc = cands[i];
             }
         }
+        // trial launches step every member, but in an assimilation window members
+        // finish at different times; order 4 keeps the XCDs evenly loaded then, so
+        // it is taken when it is within 1 % of the fastest
+        if (bc.variant >= 2 && bc.order != 4) {
+            const float best_all = best;
+            int pick = -1;
+            float pick_t = 1e30f;
+            for (const auto& r : round2) {
+                const Cand& cd = cands[r.second];
+                if (cd.variant == bc.variant && cd.order == 4 && cd.seg == bc.seg && r.first <= 1.01f * best_all &&
+                    r.first < pick_t) {
+                    pick = (int)r.second;
+                    pick_t = r.first;
+                }
+            }
+            if (pick >= 0) {
+                bc = cands[pick];
+                best = pick_t;
+            }
+        }
         // geometries of the same kernel and order within 1 % of the fastest are
         // indistinguishable by timing; the tallest strip re-reads the fewest halo rows
         for (const auto& r : round2) {
@@ -740,7 +766,7 @@ template <typename T> struct Impl : ImplBase {
         // only a search over the full candidate set is remembered: a handle that
         // pinned part of the geometry measured a subset, whose best need not be
         // the best for a later handle of the same shape
-        bool free_search = !vector_only();
+        bool free_search = !vector_only() && forced_order < 0;
         for (int i = 0; i < n_catch; ++i)
             free_search &= params[i].tile_rows == 0 && params[i].chunks_per_block == 0 &&
                            params[i].step_kernel == 0 && params[i].march_rows == 0 &&
@@ -1374,8 +1400,9 @@ template <typename T> struct Impl : ImplBase {
     }
 
     void get_config(int32_t* omi, int32_t* rows, int32_t* cpb, int32_t* gs, int32_t* vk, int32_t* mr,
-                    int32_t* mseg) const override {
+                    int32_t* mseg, int32_t* mord) const override {
         if (mseg) *mseg = march_seg;
+        if (mord) *mord = march_order;
         if (omi) *omi = mi;
         if (rows) *rows = cats[0].tile_rows;
         if (cpb) *cpb = std::min(cats[0].cpb, cats[0].n_chunks);
@@ -1430,7 +1457,7 @@ static CatchDev<T> group_view(const CatchDev<T>& C, int mi, int g0, int G, T* co
     v.strips_y = (C.ny + v.march_rows - 1) / v.march_rows;
     v.wave_begin = 0;
     v.march_order = kAdjMarchOrder;
-    v.n_waves = march_waves(v.strips_x * v.strips_y, G, v.march_order);
+    v.n_waves = march_waves(v.strips_x, v.strips_y, G, v.march_order);
     v.member_off = C.member_off + g0;
     v.n_members = G;
     v.n_chunks = (G + mi - 1) / mi;

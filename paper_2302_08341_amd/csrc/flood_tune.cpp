@@ -67,7 +67,10 @@ bool tune_lookup(const TuneKey& k, int mi, TuneChoice& out) {
     int a, b, c, d, e, f2, g2;
     bool found = false;
     while (std::fscanf(f, "%511s %d %d %d %d %d %d %d", key, &a, &b, &c, &d, &e, &f2, &g2) == 8) {
-        if (want == key) {
+        // an entry outside the geometries this library launches is ignored
+        const bool sane = (a == 1 || a == 2 || a == 4 || a == 8) && b >= 1 && b <= 8 && c >= 1 && d >= 1 && d <= 3 &&
+                          e >= 1 && e <= 4096 && (f2 == 1 || f2 == 2 || f2 == 4 || f2 == 8) && g2 >= 0 && g2 <= 4;
+        if (want == key && sane) {
             out.mi = a;
             out.tile_rows = b;
             out.cpb = c;

@@ -93,7 +93,7 @@ def load_library():
         "flood_ensemble_products": [H, C.c_int32, C.c_double, C.c_int32, dp, dp, dp, dp],
         "flood_save": [H, C.c_char_p],
         "flood_load": [H, C.c_char_p],
-        "flood_get_config": [H, ip, ip, ip, ip, ip, ip, ip],
+        "flood_get_config": [H, ip, ip, ip, ip, ip, ip, ip, ip],
         "flood_timing": [H, C.c_int32],
         "flood_get_timing": [H, dp, lp],
     }
@@ -345,11 +345,11 @@ def flood_load(h, path):
 
 
 def flood_get_config(h):
-    v = [C.c_int32(0) for _ in range(7)]
+    v = [C.c_int32(0) for _ in range(8)]
     _check(load_library().flood_get_config(h, *[C.byref(x) for x in v]), h)
     return {"member_interleave": v[0].value, "tile_rows": v[1].value, "chunks_per_block": v[2].value,
             "graph_steps": v[3].value, "step_kernel": v[4].value, "march_rows": v[5].value,
-            "march_members": v[6].value}
+            "march_members": v[6].value, "march_order": v[7].value}
 
 
 def flood_timing(h, enable):

@@ -169,9 +169,10 @@ URBAN4 = W.urban_catchment("par4", 61, 300, 3, W.seed_for(2, 4), n_gauges=3)   #
 
 @pytest.mark.parametrize("rb", [4, 8])
 @pytest.mark.parametrize("mr", [1, 5, 16, 100])
-@pytest.mark.parametrize("order", [0, 1, 2])
+@pytest.mark.parametrize("order", [0, 1, 2, 3, 4])
 def test_vectorised_march_is_bit_exact(fl, rb, mr, order, monkeypatch):
-    # wavefront orders: 2 takes the members in quads and pads 3 members to 4
+    # wavefront orders: 2 takes the members in quads and pads 3 members to 4,
+    # 4 cuts the rows of strips into 8 bands and pads them
     rain = W.chicago_hyetograph()
     ref = _ens(fl, URBAN4, rain, 3, real_bytes=rb, member_interleave=1, tile_rows=4, chunks_per_block=3,
                step_kernel=1)
@@ -186,7 +187,7 @@ def test_vectorised_march_is_bit_exact(fl, rb, mr, order, monkeypatch):
     np.testing.assert_array_equal(e.ledger()["outflow"], ref.ledger()["outflow"])
 
 
-@pytest.mark.parametrize("order", [0, 2])
+@pytest.mark.parametrize("order", [0, 2, 3, 4])
 @pytest.mark.parametrize("mm", [1, 2])
 def test_row_march_orders_are_bit_exact(fl, order, mm, monkeypatch):
     rain = W.chicago_hyetograph()
