@@ -86,11 +86,13 @@ __device__ __forceinline__ size_t state_index(const CatchDev<T>& C, int member, 
 //      leave every XCD the same share of work, and all units of a row of
 //      strips run on one XCD close in time (the shared bed and roughness of
 //      those rows stay in its L2)
-//   4  the rows of strips cut into 8 bands (one per XCD range of workgroups),
-//      then units, then rows of strips within the band, then strips along x:
-//      order 1 inside each XCD, with every XCD holding a band of every unit
+//   4  the rows of strips cut into march_bands bands (a multiple of 8, so each
+//      XCD range of workgroups holds whole bands), then units, then rows of
+//      strips within the band, then strips along x: order 1 inside each band,
+//      with every XCD holding bands of every unit, and a band's bed and
+//      roughness shared by the units that follow one another on that XCD
 // Order 2 pads the unit count to a multiple of four and order 4 the rows of
-// strips to a multiple of eight; padding wavefronts get false.
+// strips to a multiple of the band count; padding wavefronts get false.
 template <typename T>
 __device__ __forceinline__ bool march_wave(const CatchDev<T>& C, int local, int units, int& k, int& sx, int& sy) {
     if (C.march_order == 0) {
@@ -104,7 +106,7 @@ __device__ __forceinline__ bool march_wave(const CatchDev<T>& C, int local, int 
         sy = rest % C.strips_y;
         k = rest / C.strips_y;
     } else if (C.march_order == 4) {
-        const int bh = (C.strips_y + 7) >> 3;                 // rows of strips per band
+        const int bh = (C.strips_y + C.march_bands - 1) / C.march_bands;   // rows of strips per band
         const int per_unit = bh * C.strips_x;
         const int band = local / (per_unit * units);
         const int rem = local - band * per_unit * units;

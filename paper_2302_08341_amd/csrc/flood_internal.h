@@ -63,6 +63,7 @@ template <typename T> struct CatchDev {
     int32_t march_rows, strips_x, strips_y;
     int32_t wave_begin, n_waves;
     int32_t march_order;      // wavefront order, see march_wave
+    int32_t march_bands;      // order 4: bands of rows of strips, a multiple of 8
     T edge_slope[4];
     T hdry, g;
     double dx;
@@ -160,9 +161,9 @@ void launch_marchv(const StepLaunch<T>& L, int nt, int pf, int ext, int total_wa
 // wavefronts of a row-march launch over one catchment: strips x member units,
 // units padded to a multiple of four in wavefront order 2
 // wavefronts of one row-march launch over a catchment (see march_wave)
-inline int march_waves(int strips_x, int strips_y, int units, int order) {
+inline int march_waves(int strips_x, int strips_y, int units, int order, int bands = 8) {
     if (order == 2) return strips_x * strips_y * ((units + 3) / 4 * 4);
-    if (order == 4) return strips_x * ((strips_y + 7) / 8 * 8) * units;
+    if (order == 4) return strips_x * ((strips_y + bands - 1) / bands * bands) * units;
     return strips_x * strips_y * units;
 }
 void launch_count_active(int n_total, const double* t, const int32_t* fault, const double* t_end,

@@ -67,6 +67,7 @@ template <typename T> struct Impl : ImplBase {
     int march_seg = 2;        // members per wavefront of the row-marching kernel
     int march_order = 1;      // wavefront order of the row-marching kernel
     int forced_order = -1;    // >= 0: the only order the tuner tries
+    int march_bands = 0;      // order 4: bands of rows of strips (multiple of 8); 0: from the L2 size
     int march_nt = 1;         // non-temporal state streams in the vectorised row-marching kernel
     int march_pf = 1;         // one row of load lookahead in the vectorised row-marching kernel
     int total_waves = 0;      // waves of one row-marching launch
@@ -170,8 +171,19 @@ template <typename T> struct Impl : ImplBase {
             d.strips_x = (c.nx + strip_w - 1) / strip_w;
             d.strips_y = (c.ny + d.march_rows - 1) / d.march_rows;
             d.wave_begin = waves;
+            {
+                // order 4: enough bands that one band's bed and roughness (2 values
+                // per cell) stay within about 1 MiB, a quarter of one XCD's L2,
+                // while the units of the band pass through it
+                int bands = march_bands;
+                if (bands <= 0) {
+                    const double shared_bytes = (double)c.ny * c.nx * 2.0 * sizeof(T);
+                    bands = (int)std::ceil(shared_bytes / (1 << 20) / 8.0) * 8;
+                }
+                d.march_bands = std::max(8, std::min(bands, (d.strips_y + 7) / 8 * 8));
+            }
             d.n_waves = march_waves(d.strips_x, d.strips_y, variant == 3 ? c.N : (c.N + march_seg - 1) / march_seg,
-                                    march_order);
+                                    march_order, d.march_bands);
             d.march_order = march_order;
             waves += d.n_waves;
             SL.c[i] = d;
@@ -216,6 +228,10 @@ template <typename T> struct Impl : ImplBase {
             st = own_stream;
         }
         n_catch = nc;
+        if (const char* mb = std::getenv("FLOOD_MARCH_BANDS")) {
+            const int v = std::atoi(mb);
+            if (v >= 8 && v <= 1024) march_bands = v / 8 * 8;
+        }
         if (const char* mo = std::getenv("FLOOD_MARCH_ORDER")) {   // restricts the tuner to one order
             march_order = std::min(4, std::max(0, std::atoi(mo)));
             forced_order = march_order;

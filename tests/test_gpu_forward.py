@@ -187,6 +187,24 @@ def test_vectorised_march_is_bit_exact(fl, rb, mr, order, monkeypatch):
     np.testing.assert_array_equal(e.ledger()["outflow"], ref.ledger()["outflow"])
 
 
+@pytest.mark.parametrize("bands", [16, 32, 64])
+@pytest.mark.parametrize("mr", [1, 3])
+def test_banded_order_is_bit_exact(fl, bands, mr, monkeypatch):
+    # more bands than rows of strips are clamped; partial bands are padded
+    rain = W.chicago_hyetograph()
+    ref = _ens(fl, URBAN4, rain, 3, real_bytes=4, member_interleave=1, tile_rows=4, chunks_per_block=3,
+               step_kernel=1)
+    ref.step(350.0)
+    monkeypatch.setenv("FLOOD_MARCH_ORDER", "4")
+    monkeypatch.setenv("FLOOD_MARCH_BANDS", str(bands))
+    e = _ens(fl, URBAN4, rain, 3, real_bytes=4, member_interleave=1, step_kernel=3, march_rows=mr)
+    assert e.config()["march_order"] == 4
+    e.step(350.0)
+    for i in range(3):
+        for w in (fl.FIELD_H, fl.FIELD_QX, fl.FIELD_QY):
+            np.testing.assert_array_equal(e.field(i, w), ref.field(i, w))
+
+
 @pytest.mark.parametrize("order", [0, 2, 3, 4])
 @pytest.mark.parametrize("mm", [1, 2])
 def test_row_march_orders_are_bit_exact(fl, order, mm, monkeypatch):
