@@ -1452,7 +1452,7 @@ template <typename T> struct Impl : ImplBase {
 // interleave, so its gradients do not depend on what the tuner picked.
 constexpr int kAdjTileRows = 4;
 constexpr int kAdjMarchRows = 8;
-constexpr int kAdjMarchOrder = 1;
+constexpr int kAdjMarchOrder = 4;   // rows of strips in bands spread over the XCDs (see march_wave)
 
 template <typename T>
 static CatchDev<T> group_view(const CatchDev<T>& C, int mi, int g0, int G, T* const h[2], T* const qx[2],
@@ -1473,7 +1473,11 @@ static CatchDev<T> group_view(const CatchDev<T>& C, int mi, int g0, int G, T* co
     v.strips_y = (C.ny + v.march_rows - 1) / v.march_rows;
     v.wave_begin = 0;
     v.march_order = kAdjMarchOrder;
-    v.n_waves = march_waves(v.strips_x, v.strips_y, G, v.march_order);
+    if (const char* ao = std::getenv("FLOOD_ADJ_ORDER")) v.march_order = std::min(4, std::max(0, std::atoi(ao)));
+    // bands of about 1 MiB of bed and roughness, as in the forward (a multiple of 8)
+    v.march_bands = std::max(8, std::min((int)std::ceil((double)C.ny * C.nx * 2.0 * sizeof(T) / (1 << 20) / 8.0) * 8,
+                                         (v.strips_y + 7) / 8 * 8));
+    v.n_waves = march_waves(v.strips_x, v.strips_y, G, v.march_order, v.march_bands);
     v.member_off = C.member_off + g0;
     v.n_members = G;
     v.n_chunks = (G + mi - 1) / mi;
