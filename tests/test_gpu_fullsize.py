@@ -160,3 +160,46 @@ def test_fullsize_ensemble_products_on_sampled_cells(fl, orc):
         np.testing.assert_array_equal(pc[i].ravel()[cells], rpc[i])
     assert np.all(w == w[0])          # equal weights before any filter update
     ens.close()
+
+
+@pytest.mark.parametrize("extra", ["land_cover", "inflow"])
+def test_fullsize_extensions_one_step_of_sampled_members(fl, orc, extra):
+    # the benchmark's land-cover and stream-outlet ensembles (2000 x 2000 x 96,
+    # tuned configuration), first 300 s; then one step of sampled members from the
+    # GPU's own float state against the oracle with float wet/dry decisions, the
+    # mass ledger of every member with its extra term, and (inflow) the section
+    # operator on the GPU's own discharges
+    wl = W.config5(with_land_cover=extra == "land_cover", with_inflow=extra == "inflow")
+    c = wl.catchments[0]
+    ens = fl.FloodEnsemble.from_workload(wl)
+    t0 = 300.0
+    ens.step(t0)
+    led = ens.ledger()
+    gain = led["rain_in"] + led["inflow"]
+    resid = np.abs(led["storage"] - (gain - led["outflow"] + led["clamp"] - led["drain"])) / gain
+    assert resid.max() <= 1e-6, resid.max()
+    saved = {i: (ens.field(i), ens.field(i, fl.FIELD_QX), ens.field(i, fl.FIELD_QY)) for i in (5, 71)}
+    if extra == "inflow":
+        q = ens.sections()
+        m = orc.Model.from_workload(wl)
+        for i, (h, qx, qy) in saved.items():
+            mem = orc.Member(h, qx, qy)
+            ref = np.array([orc.section_flow(m, mem, s) for s in c.sections])
+            mag = np.array([c.dx * np.abs([qx[r, cc] if k == 0 else qy[r, cc] for k, r, cc, _ in s]).sum()
+                            for s in c.sections])
+            assert np.all(np.abs(q[i] - ref) <= 1e-12 * mag + 1e-300)
+    dt = 0.05
+    ens.step(t0 + dt)
+    m = orc.Model.from_workload(wl, wet_fp32=True)
+    for i, (h, qx, qy) in saved.items():
+        kw = dict(class_n=c.class_n[i].copy(), drain_rate=float(c.drain[i])) if extra == "land_cover" else {}
+        ref = orc.Member(h.copy(), qx.copy(), qy.copy(), t=t0, s=c.n_scale[i], mu=c.rain_mult[i], **kw)
+        orc.step(m, ref, dt)
+        tol = 1e-6 + 4.0 * np.spacing(np.abs(ref.h).astype(np.float32)).astype(np.float64)
+        d = np.abs(ens.field(i) - ref.h)
+        print(extra, "member", i, "max |dh|", d.max(), flush=True)
+        assert np.all(d <= tol)
+        qs = max(np.abs(ref.qx).max(), np.abs(ref.qy).max())
+        assert np.abs(ens.field(i, fl.FIELD_QX) - ref.qx).max() <= 1e-5 * qs
+        assert np.abs(ens.field(i, fl.FIELD_QY) - ref.qy).max() <= 1e-5 * qs
+    ens.close()
