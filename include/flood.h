@@ -196,7 +196,7 @@ flood_status flood_get_field(flood_handle* h, int32_t catchment, int32_t member,
 
 /* Overwrite one member's state (h: ny*nx, qx: ny*(nx+1), qy: (ny+1)*nx, all
  * host doubles, rounded to the handle's precision) and its time t.  Depths
- * must be >= 0 and finite.  Wall links must be zero.  A tracked running maximum
+ * must be >= 0 and finite.  Wall links must be zero (inflow links excepted).  A tracked running maximum
  * restarts from the new depths. */
 flood_status flood_set_state(flood_handle* h, int32_t catchment, int32_t member, const double* hh,
                              const double* qx, const double* qy, double t);

@@ -51,6 +51,7 @@ template <typename T> struct Impl : ImplBase {
         // inflow hydrographs
         int n_series = 0;
         double* d_inflow_q = nullptr;
+        std::vector<int8_t> h_inflow_id;   // host copy of dev.inflow_id (empty: no inflow link)
         double wq[kMaxSeries] = {0, 0, 0, 0};
         // streamflow sections (configuration, not state: not in snapshots)
         int n_sec = 0;
@@ -401,6 +402,7 @@ template <typename T> struct Impl : ImplBase {
                     id[at] = (int8_t)f[2];
                     c.wq[f[2]] += c.dx;
                 }
+                c.h_inflow_id = id;
                 int8_t* did;
                 CHK(dalloc(&did, (size_t)nbl, err));
                 HIPCHK(hipMemcpy(did, id.data(), nbl, hipMemcpyHostToDevice));
@@ -1137,13 +1139,17 @@ template <typename T> struct Impl : ImplBase {
             if (!finite_d(qx[i])) { err = "qx must be finite"; return FLOOD_EINVAL; }
         for (size_t i = 0; i < (size_t)(ny + 1) * nx; ++i)
             if (!finite_d(qy[i])) { err = "qy must be finite"; return FLOOD_EINVAL; }
+        // wall links carry no flow, except inflow links (edge-link order N, S, W, E)
+        auto wall = [&](int e, int at) {
+            return C.edge_kind[e] == FLOOD_EDGE_WALL && (C.h_inflow_id.empty() || C.h_inflow_id[at] < 0);
+        };
         for (int r = 0; r < ny; ++r) {
-            if (C.edge_kind[3] == FLOOD_EDGE_WALL && qx[(size_t)r * (nx + 1)] != 0.0) { err = "west wall link must be 0"; return FLOOD_EINVAL; }
-            if (C.edge_kind[1] == FLOOD_EDGE_WALL && qx[(size_t)r * (nx + 1) + nx] != 0.0) { err = "east wall link must be 0"; return FLOOD_EINVAL; }
+            if (wall(3, 2 * nx + r) && qx[(size_t)r * (nx + 1)] != 0.0) { err = "west wall link must be 0"; return FLOOD_EINVAL; }
+            if (wall(1, 2 * nx + ny + r) && qx[(size_t)r * (nx + 1) + nx] != 0.0) { err = "east wall link must be 0"; return FLOOD_EINVAL; }
         }
         for (int cc = 0; cc < nx; ++cc) {
-            if (C.edge_kind[0] == FLOOD_EDGE_WALL && qy[cc] != 0.0) { err = "north wall link must be 0"; return FLOOD_EINVAL; }
-            if (C.edge_kind[2] == FLOOD_EDGE_WALL && qy[(size_t)ny * nx + cc] != 0.0) { err = "south wall link must be 0"; return FLOOD_EINVAL; }
+            if (wall(0, cc) && qy[cc] != 0.0) { err = "north wall link must be 0"; return FLOOD_EINVAL; }
+            if (wall(2, nx + cc) && qy[(size_t)ny * nx + cc] != 0.0) { err = "south wall link must be 0"; return FLOOD_EINVAL; }
         }
         const int g = C.dev.member_off + m;
         int p;

@@ -244,3 +244,54 @@ def test_refusals(fl):
     with pytest.raises(fl.FloodError) as ex:
         e.sections()
     assert ex.value.status == fl.FLOOD_ESTATE
+
+
+@pytest.mark.parametrize("rb", [8, 4])
+def test_inflow_on_every_edge_matches_oracle(fl, orc, rb):
+    # inflow links on all four edges (corners included) and over walls and open
+    # edges, on a grid whose width spans two strips with a ragged tail; FP64 over
+    # the run, FP32 one step from the same float state
+    ny, nx = 37, 264
+    rng = np.random.default_rng(W.seed_for(2, 63))
+    z = (np.add.outer(np.linspace(0, 1.5, ny), np.linspace(0, 0.8, nx)) + rng.uniform(0, 0.3, (ny, nx)))
+    z = z.astype(np.float32)
+    n = np.full((ny, nx), 0.03, np.float32)
+    inflow = [(0, 0, 0), (0, 131, 1), (0, nx - 1, 2), (1, 0, 3), (1, 17, 0), (1, ny - 1, 1),
+              (2, 5, 2), (2, nx - 1, 3), (3, 0, 1), (3, ny - 1, 2), (3, 20, 0)]
+    q = np.array([[0.02, 0.05, 0.0, 0.01], [0.03, 0.0, 0.04, 0.02], [0.0, 0.01, 0.02, 0.03],
+                  [0.05, 0.05, 0.01, 0.0]])
+    edge_kind, edge_slope = (1, 0, 1, 0), (1e-3, 0.0, 1e-3, 0.0)
+    rain = np.array([20.0, 40.0, 10.0, 0.0]) / 3.6e6
+    cat = dict(dem=z, manning=n, dx=3.0, edge_kind=edge_kind, edge_slope=edge_slope, n_members=2,
+               n_scale=np.array([1.0, 1.2]), rain_mult=np.array([1.0, 0.8]), inflow=inflow, inflow_q=q)
+    e = fl.FloodEnsemble([cat], rain, real_bytes=rb)
+    m = orc.Model(z, n, 3.0, rain, edge_kind=edge_kind, edge_slope=edge_slope, inflow=inflow, inflow_q=q)
+    if rb == 8:
+        e.step(1000.0)
+        led = e.ledger()
+        for i, (s, mu) in enumerate(((1.0, 1.0), (1.2, 0.8))):
+            mem = orc.Member.dry(m, s=s, mu=mu)
+            orc.advance(m, mem, 1000.0)
+            assert np.abs(e.field(i) - mem.h).max() <= 1e-9
+            qs = max(np.abs(mem.qx).max(), np.abs(mem.qy).max())
+            assert np.abs(e.field(i, fl.FIELD_QX) - mem.qx).max() <= 1e-9 * qs
+            assert np.abs(e.field(i, fl.FIELD_QY) - mem.qy).max() <= 1e-9 * qs
+            assert led["inflow"][i] == pytest.approx(mem.v_in, rel=1e-12)
+            assert led["outflow"][i] == pytest.approx(mem.v_out, rel=1e-10)
+        return
+    mem = orc.Member.dry(m, s=1.2, mu=0.8)
+    orc.advance(m, mem, 700.0)
+    h32, qx32, qy32 = (a.astype(np.float32).astype(np.float64) for a in (mem.h, mem.qx, mem.qy))
+    e.set_state(1, h32, qx32, qy32, 700.0)
+    e.step(700.0)
+    dt = 0.05
+    e.step(700.0 + dt)
+    m32 = orc.Model(z, n, 3.0, rain, edge_kind=edge_kind, edge_slope=edge_slope, inflow=inflow, inflow_q=q,
+                    wet_fp32=True)
+    ref = orc.Member(h32.copy(), qx32.copy(), qy32.copy(), t=700.0, s=1.2, mu=0.8)
+    orc.step(m32, ref, dt)
+    tol = 1e-6 + 4.0 * np.spacing(np.abs(ref.h).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(e.field(1) - ref.h) <= tol)
+    qs = max(np.abs(ref.qx).max(), np.abs(ref.qy).max())
+    assert np.abs(e.field(1, fl.FIELD_QX) - ref.qx).max() <= 1e-5 * qs
+    assert np.abs(e.field(1, fl.FIELD_QY) - ref.qy).max() <= 1e-5 * qs
