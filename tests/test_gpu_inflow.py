@@ -295,3 +295,58 @@ def test_inflow_on_every_edge_matches_oracle(fl, orc, rb):
     qs = max(np.abs(ref.qx).max(), np.abs(ref.qy).max())
     assert np.abs(e.field(1, fl.FIELD_QX) - ref.qx).max() <= 1e-5 * qs
     assert np.abs(e.field(1, fl.FIELD_QY) - ref.qy).max() <= 1e-5 * qs
+
+
+def test_land_cover_with_inflow_matches_oracle(fl, orc):
+    # both extensions in one handle (their own kernel instantiation), FP64 over the run
+    c = W.urban_catchment("lcinf", 38, 52, 3, W.seed_for(2, 64), n_gauges=2, with_land_cover=True,
+                          with_inflow=True)
+    cat = dict(dem=c.dem, manning=c.manning, dx=c.dx, edge_kind=c.edge_kind, edge_slope=c.edge_slope, n_members=3,
+               n_scale=c.n_scale, rain_mult=c.rain_mult, land_class=c.land_class, class_runoff=c.class_runoff,
+               class_drain=c.class_drain, class_n=c.class_n, drain=c.drain, inflow=c.inflow, inflow_q=c.inflow_q,
+               sections=c.sections)
+    e = fl.FloodEnsemble([cat], RAIN, real_bytes=8)
+    e.step(1200.0)
+    led = e.ledger()
+    q = e.sections()
+    m = orc.Model(c.dem, c.manning, c.dx, RAIN, edge_kind=c.edge_kind, edge_slope=c.edge_slope,
+                  land_class=c.land_class, class_runoff=c.class_runoff, class_drain=c.class_drain, inflow=c.inflow,
+                  inflow_q=c.inflow_q)
+    for i in range(3):
+        mem = orc.Member.dry(m, s=c.n_scale[i], mu=c.rain_mult[i], class_n=c.class_n[i], drain_rate=c.drain[i])
+        orc.advance(m, mem, 1200.0)
+        assert np.abs(e.field(i) - mem.h).max() <= 1e-9
+        for k, v in (("inflow", mem.v_in), ("drain", mem.v_drain), ("rain_in", mem.v_rain)):
+            assert led[k][i] == pytest.approx(v, rel=1e-10)
+        ref = np.array([orc.section_flow(m, mem, s) for s in c.sections])
+        assert np.abs(q[i] - ref).max() <= 1e-9 * max(np.abs(ref).max(), 1e-12)
+    gain = led["rain_in"] + led["inflow"]
+    resid = np.abs(led["storage"] - (gain - led["outflow"] + led["clamp"] - led["drain"])) / gain
+    assert resid.max() <= 1e-12
+
+
+def test_filter_at_the_member_limit_and_on_flows_alone(fl, orc):
+    # 1024 members (the most one workgroup filters) on a small grid, observed
+    # through the sections only (no depth gauge), relative error
+    c = W.urban_catchment("max", 20, 24, 1024, W.seed_for(2, 65), n_gauges=1, with_inflow=True)
+    cat = dict(dem=c.dem, manning=c.manning, dx=c.dx, edge_kind=c.edge_kind, edge_slope=c.edge_slope,
+               n_members=1024, n_scale=c.n_scale, rain_mult=c.rain_mult, inflow=c.inflow, inflow_q=c.inflow_q,
+               sections=c.sections)
+    e = fl.FloodEnsemble([cat], RAIN, real_bytes=4)
+    e.step(900.0)
+    yq = e.sections()
+    assert yq.shape == (1024, len(c.sections))
+    obs = yq[17] * 1.02
+    floor = np.full(len(c.sections), 1e-4)
+    lw0 = e.weights()[0]
+    before = {j: e.field(j) for j in range(0, 1024, 97)}
+    neff, anc, res = e.assimilate_obs(0, np.zeros((0, 2), np.int32), obs, floor, alpha=0.05, neff_frac=0.8, u0=0.3)
+    _, w_ref, neff_ref = orc.pf_weights(yq, obs, floor, lw0, alpha=0.05)
+    assert neff == pytest.approx(neff_ref, rel=1e-12)
+    if res:
+        np.testing.assert_array_equal(anc, orc.systematic(w_ref, 0.3))
+        for j in range(0, 1024, 97):
+            if anc[j] in before:
+                np.testing.assert_array_equal(e.field(j), before[anc[j]])
+    else:
+        np.testing.assert_allclose(np.exp(e.weights()[0]), w_ref, rtol=1e-12, atol=1e-300)
