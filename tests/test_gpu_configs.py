@@ -1,0 +1,129 @@
+"""Parity on the other workloads at their full sizes, in the tuned launch
+configuration: C2 (1024 x 1024 x 32, filter every 300 s), C3 (1024 x 1024 x 16,
+adjoint of an 8-gauge misfit sampled every 10 s) and C4 (four uneven catchments
+of 24 members in one batched launch).  The oracle checks sampled outputs one by
+one; properties hold for every member.
+
+Bars as in the benchmark's full-size tests: one step 1e-6 m + 4 FP32 ulp of the
+depth and 1e-5 of the largest discharge (float wet/dry decisions on both sides);
+weights 1e-12, ancestors bit-exact given the weights; mass ledger 1e-6; adjoint
+loss 1e-4, gradients 1e-3; batched = one handle, bit-exact.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2302_08341_amd import flood
+    flood.load_library()
+    return flood
+
+
+def _ledger_closes(led):
+    gain = led["rain_in"] + led["inflow"]
+    resid = np.abs(led["storage"] - (gain - led["outflow"] + led["clamp"] - led["drain"])) / gain
+    assert resid.max() <= 1e-6, resid.max()
+
+
+def _one_step(fl, orc, ens, wl, ci, members, t0, dt=0.05):
+    c = wl.catchments[ci]
+    saved = {i: (ens.field(i, catchment=ci), ens.field(i, fl.FIELD_QX, ci), ens.field(i, fl.FIELD_QY, ci))
+             for i in members}
+    ens.step(t0 + dt)
+    m = orc.Model.from_workload(wl, catchment=ci, wet_fp32=True)
+    for i, (h, qx, qy) in saved.items():
+        ref = orc.Member(h.copy(), qx.copy(), qy.copy(), t=t0, s=c.n_scale[i], mu=c.rain_mult[i])
+        orc.step(m, ref, dt)
+        tol = 1e-6 + 4.0 * np.spacing(np.abs(ref.h).astype(np.float32)).astype(np.float64)
+        d = np.abs(ens.field(i, catchment=ci) - ref.h)
+        assert np.all(d <= tol), (ci, i, d.max())
+        qs = max(np.abs(ref.qx).max(), np.abs(ref.qy).max())
+        assert np.abs(ens.field(i, fl.FIELD_QX, ci) - ref.qx).max() <= 1e-5 * qs
+        assert np.abs(ens.field(i, fl.FIELD_QY, ci) - ref.qy).max() <= 1e-5 * qs
+
+
+def test_config2_filter_cycle_and_sampled_steps(fl, orc):
+    wl = W.config2()
+    c = wl.catchments[0]
+    ens = fl.FloodEnsemble.from_workload(wl)
+    ens.step(300.0)
+    _ledger_closes(ens.ledger())
+    K = c.gauges.shape[0]
+    y = np.array([ens.field(i)[c.gauges[:, 0], c.gauges[:, 1]] for i in range(c.n_members)])
+    obs = y[11] + np.random.default_rng(W.seed_for(2, 70)).normal(0.0, 0.05, K)
+    sigma = np.full(K, wl.obs_sigma)
+    lw0 = ens.weights()[0]
+    neff, _, res = ens.assimilate(0, c.gauges, obs, sigma, 1e-9, 0.5)
+    assert not res
+    _, w_ref, neff_ref = orc.pf_weights(y, obs, sigma, lw0)
+    w_gpu = np.exp(ens.weights()[0])
+    np.testing.assert_allclose(w_gpu, w_ref, rtol=1e-12, atol=1e-300)
+    assert neff == pytest.approx(neff_ref, rel=1e-12)
+    for u0 in (0.0, 0.61):
+        np.testing.assert_array_equal(fl.flood_systematic_resample(w_gpu, u0), orc.systematic(w_gpu, u0))
+    _one_step(fl, orc, ens, wl, 0, (0, 31), 300.0)
+    ens.close()
+
+
+def test_config3_adjoint_of_a_sampled_member(fl, orc):
+    wl = W.config3()
+    c = wl.catchments[0]
+    ens = fl.FloodEnsemble.from_workload(wl)
+    t0 = 600.0
+    ens.step(t0)
+    i = 9
+    h, qx, qy = ens.field(i), ens.field(i, fl.FIELD_QX), ens.field(i, fl.FIELD_QY)
+    ens.close()
+    K = c.gauges.shape[0]
+    t1, sdt = t0 + 20.0, wl.sample_dt
+    obs = np.random.default_rng(W.seed_for(3, 70)).uniform(0.0, 0.05, size=(2, K))
+    cat = dict(dem=c.dem, manning=c.manning, dx=c.dx, edge_kind=c.edge_kind, edge_slope=c.edge_slope,
+               n_members=1, n_scale=c.n_scale[i:i + 1], rain_mult=c.rain_mult[i:i + 1])
+    p = fl.FloodEnsemble([cat], wl.rain, rain_interval=wl.rain_interval, real_bytes=wl.real_bytes)
+    p.set_state(0, h, qx, qy, t0)
+    L, gn, gm = p.adjoint(0, t1, sdt, c.gauges, obs, ckpt_every=wl.extra["ckpt_every"])
+    p.close()
+    m = orc.Model.from_workload(wl)
+    mem = orc.Member(h.copy(), qx.copy(), qy.copy(), t=t0, s=c.n_scale[i], mu=c.rain_mult[i])
+    Lo, gno, gmo, _ = orc.adjoint(m, mem, t1, sdt, c.gauges, obs, ckpt_every=wl.extra["ckpt_every"])
+    assert L == pytest.approx(Lo, rel=1e-4)
+    assert gm[0] == pytest.approx(gmo, rel=1e-3)
+    assert np.linalg.norm(gn - gno) <= 1e-3 * np.linalg.norm(gno)
+
+
+def test_config4_batched_catchments(fl, orc):
+    wl = W.config4()
+    ens = fl.FloodEnsemble.from_workload(wl)
+    ens.step(300.0)
+    i = 5
+    for ci, c in enumerate(wl.catchments):
+        _ledger_closes(ens.ledger(ci))
+        cat = dict(dem=c.dem, manning=c.manning, dx=c.dx, edge_kind=c.edge_kind, edge_slope=c.edge_slope,
+                   n_members=1, n_scale=c.n_scale[i:i + 1], rain_mult=c.rain_mult[i:i + 1])
+        p = fl.FloodEnsemble([cat], wl.rain, rain_interval=wl.rain_interval, real_bytes=wl.real_bytes)
+        p.step(300.0)
+        for w in (fl.FIELD_H, fl.FIELD_QX, fl.FIELD_QY):
+            np.testing.assert_array_equal(p.field(0, w), ens.field(i, w, ci))
+        p.close()
+    # one step of a sampled member of every catchment, all in the same batched launch
+    saved = {ci: {i: (ens.field(i, catchment=ci), ens.field(i, fl.FIELD_QX, ci), ens.field(i, fl.FIELD_QY, ci))}
+             for ci in range(len(wl.catchments))}
+    ens.step(300.05)
+    for ci, c in enumerate(wl.catchments):
+        m = orc.Model.from_workload(wl, catchment=ci, wet_fp32=True)
+        h, qx, qy = saved[ci][i]
+        ref = orc.Member(h.copy(), qx.copy(), qy.copy(), t=300.0, s=c.n_scale[i], mu=c.rain_mult[i])
+        orc.step(m, ref, 0.05)
+        tol = 1e-6 + 4.0 * np.spacing(np.abs(ref.h).astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(ens.field(i, catchment=ci) - ref.h) <= tol)
+        qs = max(np.abs(ref.qx).max(), np.abs(ref.qy).max())
+        assert np.abs(ens.field(i, fl.FIELD_QX, ci) - ref.qx).max() <= 1e-5 * qs
+    ens.close()
