@@ -357,8 +357,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: members shard across GPUs without communication between "
-              "filter updates, and this build measures the single-GPU path (see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU (--gpus 1): the ensemble's members would shard across GPUs with no "
+              "communication between filter updates, and only the single-GPU path is timed here.",
+              file=sys.stderr)
         sys.exit(2)
 
     cfg = {"config": args.config, "ny": args.ny, "nx": args.nx, "members": args.members}

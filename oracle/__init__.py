@@ -7,8 +7,9 @@ imports, links or calls it; the two share no code.  The arithmetic lives in
 only marshals arguments and performs the particle filter's member copy, which
 is plain array copying.
 
-Readings of the paper that the oracle adopts (where it is silent or
-ambiguous) are listed in DESIGN.md under "Readings".
+Where the paper is silent or ambiguous, the C source states the reading it
+takes beside the code that takes it (wet/dry threshold, donor limiter, open
+edges, land cover, inflow links, sections, relative observation error).
 """
 from __future__ import annotations
 
