@@ -991,6 +991,13 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
         load_n(cb, n2, cw2);
     };
     if (PF) load_row(ca, r0 + 1 < ny, qE, qS, hs, zs, ns, csw);
+    // PF == 2: a second row in flight (the links of the next row and the state
+    // of the row after it), so each row's loads have two rows of work to arrive
+    T hsB[V], zsB[V], nsB[V], qEB[V], qSB[V];
+    uint32_t cswB = 0;
+#pragma unroll
+    for (int j = 0; j < V; ++j) hsB[j] = zsB[j] = nsB[j] = qEB[j] = qSB[j] = T(0);
+    if (PF == 2 && r0 + 1 < r1) load_row(ca + nx, r0 + 2 < ny, qEB, qSB, hsB, zsB, nsB, cswB);
     HB vmax = 0;
     T vcl = T(0);
     T vdr = T(0);
@@ -998,7 +1005,9 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
         const bool hasS = r + 1 < ny;
         T hs2[V], zs2[V], ns2[V], qE2[V], qS2[V];
         uint32_t csw2 = 0;
-        if (PF) {
+        if (PF == 2) {
+            if (r + 2 < r1) load_row(ca + 2 * (size_t)nx, r + 3 < ny, qE2, qS2, hs2, zs2, ns2, csw2);
+        } else if (PF) {
             if (r + 1 < r1) load_row(ca + nx, r + 2 < ny, qE2, qS2, hs2, zs2, ns2, csw2);
         } else {
             load_row(ca, hasS, qE, qS, hs, zs, ns, csw);
@@ -1138,7 +1147,23 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
             nc[j] = ns[j];
         }
         ccw = csw;
-        if (PF) {
+        if (PF == 2) {
+            csw = cswB;
+            cswB = csw2;
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                qE[j] = qEB[j];
+                qS[j] = qSB[j];
+                hs[j] = hsB[j];
+                zs[j] = zsB[j];
+                ns[j] = nsB[j];
+                qEB[j] = qE2[j];
+                qSB[j] = qS2[j];
+                hsB[j] = hs2[j];
+                zsB[j] = zs2[j];
+                nsB[j] = ns2[j];
+            }
+        } else if (PF) {
             csw = csw2;
 #pragma unroll
             for (int j = 0; j < V; ++j) {
@@ -1180,7 +1205,9 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
 template <typename T, int EXT>
 static void launch_marchv_ext(const StepLaunch<T>& L, int nt, int pf, const dim3 grid, hipStream_t s) {
     constexpr int V = march_vec<T>();
-    if (nt && pf)
+    if (nt && pf == 2)
+        hipLaunchKernelGGL((k_marchv<T, V, 1, 0, 2, EXT>), grid, dim3(kBlock), 0, s, L);
+    else if (nt && pf)
         hipLaunchKernelGGL((k_marchv<T, V, 1, 0, 1, EXT>), grid, dim3(kBlock), 0, s, L);
     else if (nt)
         hipLaunchKernelGGL((k_marchv<T, V, 1, 0, 0, EXT>), grid, dim3(kBlock), 0, s, L);

@@ -238,7 +238,7 @@ template <typename T> struct Impl : ImplBase {
             forced_order = march_order;
         }
         if (const char* nt = std::getenv("FLOOD_MARCH_NT")) march_nt = std::atoi(nt) ? 1 : 0;
-        if (const char* pf = std::getenv("FLOOD_MARCH_PF")) march_pf = std::atoi(pf) ? 1 : 0;
+        if (const char* pf = std::getenv("FLOOD_MARCH_PF")) march_pf = std::min(2, std::max(0, std::atoi(pf)));
         const char* ng = std::getenv("FLOOD_NO_GRAPH");
         use_graph = !(ng && ng[0] == '1');
         if (const char* gs = std::getenv("FLOOD_GRAPH_STEPS")) {   // steps per captured batch

@@ -187,6 +187,25 @@ def test_vectorised_march_is_bit_exact(fl, rb, mr, order, monkeypatch):
     np.testing.assert_array_equal(e.ledger()["outflow"], ref.ledger()["outflow"])
 
 
+@pytest.mark.parametrize("pf", [0, 1, 2])
+@pytest.mark.parametrize("rb", [4, 8])
+@pytest.mark.parametrize("mr", [1, 2, 5, 16])
+def test_row_lookahead_depths_are_bit_exact(fl, pf, rb, mr, monkeypatch):
+    # no lookahead, one row and two rows of loads in flight: strips of 1 and 2 rows
+    # (nothing or only the prologue row ahead) and a last strip shorter than the rest
+    rain = W.chicago_hyetograph()
+    ref = _ens(fl, URBAN4, rain, 3, real_bytes=rb, member_interleave=1, tile_rows=4, chunks_per_block=3,
+               step_kernel=1)
+    ref.step(350.0)
+    monkeypatch.setenv("FLOOD_MARCH_PF", str(pf))
+    e = _ens(fl, URBAN4, rain, 3, real_bytes=rb, member_interleave=1, step_kernel=3, march_rows=mr)
+    e.step(350.0)
+    for i in range(3):
+        for w in (fl.FIELD_H, fl.FIELD_QX, fl.FIELD_QY):
+            np.testing.assert_array_equal(e.field(i, w), ref.field(i, w))
+    np.testing.assert_array_equal(e.ledger()["outflow"], ref.ledger()["outflow"])
+
+
 @pytest.mark.parametrize("bands", [16, 32, 64])
 @pytest.mark.parametrize("mr", [1, 3])
 def test_banded_order_is_bit_exact(fl, bands, mr, monkeypatch):
