@@ -132,7 +132,10 @@ def test_batched_equals_one_handle_per_member(fl):
         p.step(900.0)
         np.testing.assert_array_equal(p.field(0), b.field(i))
         np.testing.assert_array_equal(p.field(0, fl.FIELD_PEAK), b.field(i, fl.FIELD_PEAK))
-        assert p.ledger()["drain"][0] == b.ledger()["drain"][i]
+        # the drained volume is summed by FP64 atomics into bins chosen by the
+        # workgroup id, which differs between the two launches: equal up to the
+        # order of those sums
+        assert p.ledger()["drain"][0] == pytest.approx(b.ledger()["drain"][i], rel=1e-12)
         p.close()
 
 
