@@ -132,6 +132,17 @@ __device__ __forceinline__ bool march_wave(const CatchDev<T>& C, int local, int 
     return k < units;
 }
 
+// v as held by lane src of the wavefront (ds_bpermute: byte address = 4 x lane)
+__device__ __forceinline__ float lane_read(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_read(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // V adjacent cells moved with one V-wide access (p must be V-element aligned)
 template <typename T, int V> struct VecOf;
 template <> struct VecOf<float, 4> { typedef float __attribute__((ext_vector_type(4))) type; };

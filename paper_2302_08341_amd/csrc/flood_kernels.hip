@@ -912,18 +912,28 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
     // member's table stays in scalar registers)
     const uint8_t* __restrict__ CLS = (EXT & 1) ? C.cls : nullptr;
     const bool lc = (EXT & 1) && CLS != nullptr;
-    auto rough = [&](uint32_t k) -> T {
-        T v = ms.cn[0];
-        v = (k == 1u) ? ms.cn[1] : v;
-        v = (k == 2u) ? ms.cn[2] : v;
-        return (k == 3u) ? ms.cn[3] : v;
-    };
-    auto runoff = [&](uint32_t k) -> T {
-        T v = C.class_rc[0];
-        v = (k == 1u) ? C.class_rc[1] : v;
-        v = (k == 2u) ? C.class_rc[2] : v;
-        return (k == 3u) ? C.class_rc[3] : v;
-    };
+    // the member's class table lives in lanes: 0-3 its Manning n of each class,
+    // 4-7 the runoff coefficients, 8-11 the drainage depth of the step for
+    // draining classes (0 for the others); a cell's entries are read from those
+    // lanes with ds_bpermute, a cross-lane read served by the LDS unit, instead
+    // of compare-and-select chains on the VALU.  Every lookup is made where the
+    // whole wavefront is active (the early returns above are wavefront-uniform).
+    T tab = T(0);
+    if (lc) {
+        const int k = lane & 3;
+        T cn = ms.cn[0], rc = C.class_rc[0];
+        cn = (k == 1) ? ms.cn[1] : cn;
+        cn = (k == 2) ? ms.cn[2] : cn;
+        cn = (k == 3) ? ms.cn[3] : cn;
+        rc = (k == 1) ? C.class_rc[1] : rc;
+        rc = (k == 2) ? C.class_rc[2] : rc;
+        rc = (k == 3) ? C.class_rc[3] : rc;
+        const T dk = ((C.drain_mask >> k) & 1) ? ms.drain : T(0);
+        tab = lane < 4 ? cn : lane < 8 ? rc : lane < 12 ? dk : T(0);
+    }
+    auto lut = [&](uint32_t k, int base) -> T { return lane_read(tab, (int)k + base); };
+    auto rough = [&](uint32_t k) -> T { return lut(k, 0); };
+    auto runoff = [&](uint32_t k) -> T { return lut(k, 4); };
     // roughness of V cells from the shared field, or from their classes (whose
     // packed bytes are returned in cw)
     auto load_n = [&](size_t c, T (&nv)[V], uint32_t& cw) {
@@ -1081,7 +1091,7 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
             vcl += (own && hn < T(0)) ? -hn : T(0);
             hn = (hn < T(0)) ? T(0) : hn;
             // drainage of draining classes, up to the water the cell holds
-            const T loss = (lc && ((C.drain_mask >> kc) & 1)) ? fmin(ms.drain, hn) : T(0);
+            const T loss = lc ? fmin(lut(kc, 8), hn) : T(0);
             hn = hn - loss;
             vdr += own ? loss : T(0);
             hn = (hn == T(0)) ? T(0) : hn;
