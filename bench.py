@@ -317,6 +317,53 @@ def leg_streams(FloodEnsemble, W, args):
             "filter_depths_and_flows_s": t_pf, "filter_neff": neff, "filter_resampled": bool(res)}
 
 
+class ClockSampler:
+    """Samples the GPU compute clock from sysfs in a host thread (read-only; the
+    memory clock of this part is fixed).  Reports median / min / max MHz."""
+
+    def __init__(self, period=0.05):
+        import glob
+        import threading
+        paths = sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk"))
+        self.path = paths[0] if paths else None
+        self.period = period
+        self.samples = []
+        self._stop = threading.Event()
+        self._thread = threading.Thread(target=self._run, daemon=True)
+
+    def _read(self):
+        try:
+            for line in open(self.path):
+                if line.rstrip().endswith("*"):
+                    return float(line.split(":")[1].strip().split("Mhz")[0].split("MHz")[0])
+        except (OSError, ValueError, IndexError):
+            return None
+        return None
+
+    def _run(self):
+        while not self._stop.is_set():
+            v = self._read()
+            if v is not None:
+                self.samples.append(v)
+            self._stop.wait(self.period)
+
+    def start(self):
+        if self.path:
+            self._thread.start()
+        return self
+
+    def stop(self):
+        if not self.path:
+            return None
+        self._stop.set()
+        self._thread.join()
+        if not self.samples:
+            return None
+        v = np.array(self.samples)
+        return {"median_MHz": float(np.median(v)), "min_MHz": float(v.min()), "max_MHz": float(v.max()),
+                "samples": int(v.size)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -467,11 +514,13 @@ def main():
     if not args.no_kernel_timing:
         ens.timing(True)
     torch.cuda.synchronize()
+    clocks = ClockSampler().start()
     t0 = time.perf_counter()
     for k in range(args.warmup, n_cycles):
         cycle(k)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    clock_stats = clocks.stop()
     if not args.no_kernel_timing:
         ens.timing(False)
     led1 = ens.ledger()
@@ -526,6 +575,7 @@ def main():
         log("plain leg done")
 
     detail["copy_ceiling_GBps"] = elementwise_ceiling(torch)
+    detail["gpu_clock_in_timed_region"] = clock_stats
     detail.update({"member_steps": member_steps, "mcu": mcu, "elapsed_s": elapsed, "cycles": cycle_log[args.warmup:],
                    "resampled": resampled[args.warmup:], "mass_balance_rel": mass,
                    "paper_context": "8x P100: 4.69e10 MCU/s (96 x 4.0 M cells x 14,400 steps in 118 s)"})
