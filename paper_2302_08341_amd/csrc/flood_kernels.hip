@@ -1287,6 +1287,8 @@ template void launch_march<double>(const StepLaunch<double>&, int, int, hipStrea
 constexpr int kProdCells = 64;
 constexpr int kProdMaxPct = 16;
 
+constexpr int kProdUnroll = 8;   // percentile candidates evaluated per pass over the members
+
 template <typename T, int MI, bool LDS>
 __global__ __launch_bounds__(kProdCells) void k_products(const CatchDev<T> C, double thr, int n_pct,
                                                          const double* __restrict__ pct,
@@ -1318,12 +1320,28 @@ __global__ __launch_bounds__(kProdCells) void k_products(const CatchDev<T> C, do
         best[i] = INFINITY;
         lim[i] = pct[i] * W;
     }
-    for (int k = 0; k < N; ++k) {
-        const T vk = value(k);
-        double cum = 0.0;
-        for (int m = 0; m < N; ++m) cum += (value(m) <= vk) ? w[m] : 0.0;
-        for (int i = 0; i < n_pct; ++i)
-            if (cum >= lim[i] && (double)vk < best[i]) best[i] = (double)vk;
+    // kProdUnroll candidates k per pass over the members: independent sums (each
+    // still in member order), one read of each member value per pass
+    for (int k0 = 0; k0 < N; k0 += kProdUnroll) {
+        T vk[kProdUnroll];
+        double cum[kProdUnroll];
+#pragma unroll
+        for (int q = 0; q < kProdUnroll; ++q) {
+            vk[q] = value(k0 + q < N ? k0 + q : N - 1);
+            cum[q] = 0.0;
+        }
+        for (int m = 0; m < N; ++m) {
+            const T vm = value(m);
+            const double wm = w[m];
+#pragma unroll
+            for (int q = 0; q < kProdUnroll; ++q) cum[q] += (vm <= vk[q]) ? wm : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kProdUnroll; ++q) {
+            if (k0 + q >= N) break;
+            for (int i = 0; i < n_pct; ++i)
+                if (cum[q] >= lim[i] && (double)vk[q] < best[i]) best[i] = (double)vk[q];
+        }
     }
     for (int i = 0; i < n_pct; ++i) pout[(size_t)i * ncell + cell] = best[i];
 }
