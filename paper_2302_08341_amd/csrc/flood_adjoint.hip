@@ -20,11 +20,13 @@ namespace flood {
 template <typename T>
 __device__ __forceinline__ void link_in_d(T q, T h1, T h2, T dz, T G, T Gn, const MemberStep<T>& ms, T hdry,
                                           T& dq, T& dh1, T& dh2, T& cn) {
-    dq = dh1 = dh2 = cn = T(0);
+    // evaluated without branches and selected at the end, as in the forward:
+    // dry, limited and free links in one wavefront do not split it, and a dry
+    // link's intermediate values (possibly inf or NaN) are discarded
     const T d = h1 - h2;
     const bool up1 = d >= dz;
     const T hf = up1 ? h1 - fmax(dz, T(0)) : h2 - fmax(-dz, T(0));
-    if (!(hf > hdry)) return;
+    const bool wet = hf > hdry;
     const T p = pow_m73(hf);
     const T A = G * ms.s2dt * p;
     const T aq = fabs(q);
@@ -33,26 +35,22 @@ __device__ __forceinline__ void link_in_d(T q, T h1, T h2, T dz, T G, T Gn, cons
     const T invD = qdiv(T(1), D);
     const T F = qdiv(num, D);
     const T sg = q > T(0) ? T(1) : (q < T(0) ? T(-1) : T(0));
-    if (F > T(0)) {
-        const T cap = h1 * ms.capf;
-        if (cap < F) {
-            dh1 = ms.capf;
-            return;
-        }
-    } else {
-        const T cap = -h2 * ms.capf;
-        if (F < cap) {
-            dh2 = -ms.capf;
-            return;
-        }
-    }
+    // donor limiter: a limited link depends on its upwind depth only
+    const bool pos = F > T(0);
+    const bool cap1 = pos && (h1 * ms.capf < F);
+    const bool cap2 = !pos && (F < -h2 * ms.capf);
+    const bool free_ = wet && !cap1 && !cap2;
     const T slope = dz - d;                          // dx times the surface slope
-    const T dDdhf = T(-7.0 / 3.0) * A * aq / hf;
+    const T dDdhf = T(-7.0 / 3.0) * A * aq * qdiv(T(1), hf);
     const T t_hf = -ms.gdtdx * slope - F * dDdhf;    // d(num - F D)/d(hf)
-    dq = (T(1) - F * A * sg) * invD;
-    dh1 = ((up1 ? t_hf : T(0)) + ms.gdtdx * hf) * invD;
-    dh2 = ((up1 ? T(0) : t_hf) - ms.gdtdx * hf) * invD;
-    cn = -F * aq * invD * Gn * ms.s2dt * p;
+    const T dq_ = (T(1) - F * A * sg) * invD;
+    const T dh1_ = ((up1 ? t_hf : T(0)) + ms.gdtdx * hf) * invD;
+    const T dh2_ = ((up1 ? T(0) : t_hf) - ms.gdtdx * hf) * invD;
+    const T cn_ = -F * aq * invD * Gn * ms.s2dt * p;
+    dq = free_ ? dq_ : T(0);
+    cn = free_ ? cn_ : T(0);
+    dh1 = !wet ? T(0) : (cap1 ? ms.capf : (cap2 ? T(0) : dh1_));
+    dh2 = !wet ? T(0) : (cap2 ? -ms.capf : (cap1 ? T(0) : dh2_));
 }
 
 // Open edge link (outward discharge qo, inner depth h), partials with respect
