@@ -908,8 +908,7 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
         return (id == 3) ? ms.qin[3] : v;
     };
     // land cover: the cell's roughness is the member's value for its class, and
-    // its rain is scaled by the class's runoff coefficient (select chains: the
-    // member's table stays in scalar registers)
+    // its rain is scaled by the class's runoff coefficient
     const uint8_t* __restrict__ CLS = (EXT & 1) ? C.cls : nullptr;
     const bool lc = (EXT & 1) && CLS != nullptr;
     // the member's class table lives in lanes: 0-3 its Manning n of each class,

@@ -31,5 +31,9 @@ def test_traffic_summary_is_tied_to_kernel_sources(tmp_path, monkeypatch):
                  % bench.kernel_source_hash())
     assert bench.measured_traffic("k_marchv", "urban8x8x2") == pytest.approx(1234.5)
     assert bench.measured_traffic("k_marchv", "urban8x8x4") is None
+    # comments and layout are not the kernel
+    (tmp_path / bench.KERNEL_SOURCES[0]).write_text("// a note\nkernel  /* more */ source\n  "
+                                                    + bench.KERNEL_SOURCES[0] + "  // end\n")
+    assert bench.measured_traffic("k_marchv", "urban8x8x2") == pytest.approx(1234.5)
     (tmp_path / bench.KERNEL_SOURCES[0]).write_text("changed kernel")
     assert bench.measured_traffic("k_marchv", "urban8x8x2") is None
