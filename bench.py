@@ -20,7 +20,8 @@ region:
   * step kernels alone (MCU over summed kernel time);
   * forward + adjoint over the first 900 s of the same ensemble (Manning-field
     and rain-multiplier gradients of a 10-s gauge misfit, checkpoints every
-    100 steps) against the forward alone over the same window;
+    100 steps) against the forward alone over the same window, one handle
+    each, timed twice in turns from the dry state and compared by their means;
   * batched against plain (one handle and one launch per member) on this
     workload over its first window, and on the four-catchment batch
     (512^2, 768x1536, 1024^2, 2000^2, 24 members each) over its first 300 s;
@@ -182,30 +183,52 @@ def elementwise_ceiling(torch):
     return gbs
 
 
-def leg_adjoint(FloodEnsemble, wl, obs_adj, window, sample_dt, ckpt):
-    """Forward + adjoint over [0, window] of the full ensemble, against the forward alone."""
+def leg_adjoint(FloodEnsemble, wl, obs_adj, window, sample_dt, ckpt, reps=2):
+    """Forward + adjoint over [0, window] of the full ensemble against the forward
+    alone, one handle each, timed in turns reps times and compared by their means.
+    Every run starts from the dry state (set before the clock starts); the
+    adjoint's scratch stays on its handle between runs, as in a calibration loop
+    that calls the adjoint again and again."""
     c = wl.catchments[0]
     ncell = c.ny * c.nx
-    ens = FloodEnsemble.from_workload(wl)
-    t0 = time.perf_counter()
-    ens.step(window)
-    t_fwd = time.perf_counter() - t0
-    steps_fwd = int(ens.ledger()["steps"].sum())
-    ens.close()
-    log("adjoint leg: forward alone %.2f s" % t_fwd)
-    ens = FloodEnsemble.from_workload(wl)
     obs = np.stack([obs_adj[t] for t in sorted(obs_adj)])
-    t0 = time.perf_counter()
-    loss, gn, gm = ens.adjoint(0, window, sample_dt, c.gauges, obs, ckpt_every=ckpt)
-    t_adj = time.perf_counter() - t0
-    steps_adj = int(ens.ledger()["steps"].sum())
-    ens.close()
-    log("adjoint leg: forward + adjoint %.2f s" % t_adj)
+    dry = (np.zeros((c.ny, c.nx)), np.zeros((c.ny, c.nx + 1)), np.zeros((c.ny + 1, c.nx)))
+    fwd = FloodEnsemble.from_workload(wl)
+    adj = FloodEnsemble.from_workload(wl)
+
+    def restart(e):
+        for i in range(c.n_members):
+            e.set_state(i, *dry, 0.0)
+
+    def steps(e):
+        return int(e.ledger()["steps"].sum())
+
+    t_fwd, t_adj = [], []
+    for r in range(reps):
+        if r:
+            restart(fwd)
+            restart(adj)
+        s0 = steps(fwd)
+        t0 = time.perf_counter()
+        fwd.step(window)
+        t_fwd.append(time.perf_counter() - t0)
+        steps_fwd = steps(fwd) - s0
+        log("adjoint leg: forward alone %.2f s" % t_fwd[-1])
+        s0 = steps(adj)
+        t0 = time.perf_counter()
+        loss, gn, gm = adj.adjoint(0, window, sample_dt, c.gauges, obs, ckpt_every=ckpt)
+        t_adj.append(time.perf_counter() - t0)
+        steps_adj = steps(adj) - s0
+        log("adjoint leg: forward + adjoint %.2f s" % t_adj[-1])
+    fwd.close()
+    adj.close()
+    tf, ta = float(np.mean(t_fwd)), float(np.mean(t_adj))
     return {"workload": "first %.0f s of the same ensemble (%d x %d cells x %d members), loss = squared misfit "
                         "at %d gauges every %.0f s, checkpoints every %d steps" % (
                             window, c.ny, c.nx, c.n_members, c.gauges.shape[0], sample_dt, ckpt),
-            "fwd_adj_MCUps": steps_adj * ncell / t_adj, "fwd_MCUps": steps_fwd * ncell / t_fwd,
-            "member_steps": steps_adj, "fwd_s": t_fwd, "fwd_adj_s": t_adj, "adj_over_fwd": t_adj / t_fwd,
+            "fwd_adj_MCUps": steps_adj * ncell / ta, "fwd_MCUps": steps_fwd * ncell / tf,
+            "member_steps": steps_adj, "fwd_s": tf, "fwd_adj_s": ta, "adj_over_fwd": ta / tf,
+            "runs_fwd_s": t_fwd, "runs_fwd_adj_s": t_adj,
             "loss": float(loss), "grad_n_norm": float(np.linalg.norm(gn)),
             "grad_mult_mean_abs": float(np.mean(np.abs(gm)))}
 
@@ -391,6 +414,7 @@ def main():
     ap.add_argument("--adj-window", type=float, default=900.0)
     ap.add_argument("--adj-sample", type=float, default=10.0)
     ap.add_argument("--adj-ckpt", type=int, default=100)
+    ap.add_argument("--adj-reps", type=int, default=2, help="forward and forward + adjoint runs, in turns")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-members", type=int, default=8)
     ap.add_argument("--no-c4", action="store_true")
@@ -462,7 +486,7 @@ def main():
     # forward + adjoint first: the timed cycles below are then the last full-size step launches
     if adj_times and not args.kernel_only:
         detail["fwd_adj"] = leg_adjoint(FloodEnsemble, wl, obs_adj,
-                                        args.adj_window, args.adj_sample, args.adj_ckpt)
+                                        args.adj_window, args.adj_sample, args.adj_ckpt, max(1, args.adj_reps))
     if not args.no_c4 and not args.kernel_only:
         detail["batched_vs_plain_c4"] = leg_c4(FloodEnsemble, W, args.c4_window, args.c4_plain_members)
     if not args.no_products and not args.kernel_only:

@@ -187,6 +187,15 @@ flood_status flood_adjoint(flood_handle* h, int32_t catchment, double t_end, dou
                            int32_t n_gauges, const int32_t* gauge_rc, const double* obs, int32_t ckpt_every,
                            double* loss_out, double* grad_n_out, double* grad_mult_out);
 
+/* flood_adjoint keeps its scratch on the handle for the next call: the tape
+ * (ckpt_every + 1 states of a member group), its clamp flags, two adjoint
+ * copies, the Manning accumulators and the checkpoints, in all up to half the
+ * device memory that was free at the first call.  Allocating and freeing that
+ * much on every call would cost seconds once the memory has been recycled.
+ * flood_adjoint_release frees it now (flood_destroy frees it too); a later
+ * flood_adjoint allocates it again.  Errors: EINVAL (NULL handle). */
+flood_status flood_adjoint_release(flood_handle* h);
+
 /* Copy one member's field to host memory in the host layout described above
  * (H: ny*nx, QX: ny*(nx+1), QY: (ny+1)*nx, PEAK: ny*nx), converted to double.
  * PEAK, the member's running maximum depth since creation (or its last

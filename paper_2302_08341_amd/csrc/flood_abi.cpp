@@ -370,6 +370,11 @@ flood_status flood_get_config(const flood_handle* h, int32_t* mi, int32_t* tile_
     return FLOOD_OK;
 }
 
+flood_status flood_adjoint_release(flood_handle* h) {
+    FLOOD_NEED_HANDLE(h);
+    return h->impl->adjoint_release(h->err);
+}
+
 flood_status flood_timing(flood_handle* h, int32_t enable) {
     FLOOD_NEED_HANDLE(h);
     return h->impl->timing(enable != 0, h->err);

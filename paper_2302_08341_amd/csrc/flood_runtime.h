@@ -24,6 +24,7 @@ struct ImplBase {
     virtual flood_status adjoint(int c, double t_end, double sample_dt, int K, const int32_t* grc,
                                  const double* obs, int ckpt_every, double* loss_out, double* grad_n_out,
                                  double* grad_mult_out, std::string& err) = 0;
+    virtual flood_status adjoint_release(std::string& err) = 0;
     virtual flood_status get_field(int c, int m, int which, double* out, std::string& err) = 0;
     virtual flood_status set_state(int c, int m, const double* h, const double* qx, const double* qy, double t,
                                    std::string& err) = 0;

@@ -117,8 +117,63 @@ template <typename T> struct Impl : ImplBase {
     StepLaunch<T> SL{};
     PlanLaunch<T> PL{};
 
+    // Adjoint scratch kept on the handle between flood_adjoint calls: the tape,
+    // its clamp flags, the two adjoint copies, the Manning accumulators and the
+    // checkpoints (up to half the device memory that was free).  Allocating and
+    // freeing that much per call costs seconds once the memory has been used and
+    // freed before.  Released by adjoint_release and the destructor.
+    struct Scratch {
+        void* p = nullptr;
+        size_t bytes = 0;
+    };
+    Scratch adj_tape, adj_clamp, adj_lam, adj_nacc;
+    std::vector<Scratch> adj_ckpt;
+
+    size_t adj_held() const {
+        size_t b = adj_tape.bytes + adj_clamp.bytes + adj_lam.bytes + adj_nacc.bytes;
+        for (const Scratch& c : adj_ckpt) b += c.bytes;
+        return b;
+    }
+
+    // at least `bytes` in b: the held block if it is large enough, else a new one
+    flood_status adj_reserve(Scratch& b, size_t bytes, std::string& err) {
+        bytes = std::max<size_t>(bytes, 16);
+        if (b.p && b.bytes >= bytes) return FLOOD_OK;
+        if (b.p) {
+            HIPCHK(hipStreamSynchronize(st));
+            (void)hipFree(b.p);
+            b.p = nullptr;
+            b.bytes = 0;
+        }
+        if (hipMalloc(&b.p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            b.p = nullptr;
+            err = "hipMalloc of " + std::to_string(bytes) + " bytes failed in flood_adjoint";
+            return FLOOD_ENOMEM;
+        }
+        b.bytes = bytes;
+        return FLOOD_OK;
+    }
+
+    void adj_free_all() {
+        (void)hipStreamSynchronize(st);
+        for (Scratch* b : {&adj_tape, &adj_clamp, &adj_lam, &adj_nacc})
+            if (b->p) (void)hipFree(b->p);
+        for (Scratch& c : adj_ckpt)
+            if (c.p) (void)hipFree(c.p);
+        adj_tape = adj_clamp = adj_lam = adj_nacc = Scratch{};
+        adj_ckpt.clear();
+    }
+
+    flood_status adjoint_release(std::string& err) override {
+        (void)err;
+        adj_free_all();
+        return FLOOD_OK;
+    }
+
     ~Impl() override {
         (void)hipStreamSynchronize(st);
+        adj_free_all();
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         for (auto e : ev)
@@ -1531,6 +1586,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
     // member groups sized so that the tape (ckpt_every + 1 states) fits in half the free memory
     size_t free_b = 0, total_b = 0;
     HIPCHK(hipMemGetInfo(&free_b, &total_b));
+    free_b += adj_held();   // held from an earlier call: reused or replaced below
     const size_t per_member_state = (3 * ncell + C.ny + C.nx) * sizeof(T);
     const size_t per_member_slot = per_member_state + ncell;   // + clamp flags
     size_t G = (size_t)(0.5 * (double)free_b) / ((size_t)(ckpt_every + 1) * per_member_slot + 8 * per_member_state);
@@ -1541,6 +1597,12 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
     }
     G = (G / mi) * mi;
     if (G < (size_t)mi) { err = "adjoint tape does not fit in device memory"; return FLOOD_ENOMEM; }
+    // as many groups as memory needs, all of one size: equal launches, and a
+    // grouping that small changes of free memory do not move
+    {
+        const size_t n_groups = ((size_t)N + G - 1) / G;
+        G = (((size_t)N + n_groups - 1) / n_groups + mi - 1) / mi * mi;
+    }
 
     // device scratch owned by this call
     std::vector<void*> tmp;
@@ -1590,9 +1652,12 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
     T* tape = nullptr;
     uint8_t* clamp = nullptr;
     T* lam = nullptr;
-    CHK(talloc((size_t)(ckpt_every + 1) * slot_elems * sizeof(T), (void**)&tape));
-    CHK(talloc((size_t)ckpt_every * elemsG, (void**)&clamp));
-    CHK(talloc(2 * slot_elems * sizeof(T), (void**)&lam));
+    CHK(adj_reserve(adj_tape, (size_t)(ckpt_every + 1) * slot_elems * sizeof(T), err));
+    CHK(adj_reserve(adj_clamp, (size_t)ckpt_every * elemsG, err));
+    CHK(adj_reserve(adj_lam, 2 * slot_elems * sizeof(T), err));
+    tape = static_cast<T*>(adj_tape.p);
+    clamp = static_cast<uint8_t*>(adj_clamp.p);
+    lam = static_cast<T*>(adj_lam.p);
     // per-launch record
     MemberStep<T>* ms_log = nullptr;
     double* rdt_log = nullptr;
@@ -1612,7 +1677,8 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
     if (march_adj) {
         CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_lpar));
         CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_segcnt));
-        CHK(talloc(elemsG * sizeof(T), (void**)&d_nacc));
+        CHK(adj_reserve(adj_nacc, elemsG * sizeof(T), err));
+        d_nacc = static_cast<T*>(adj_nacc.p);
     }
     size_t log_cap = 4096;
     auto grow_log = [&](size_t need) -> flood_status {
@@ -1638,6 +1704,14 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
         tag_log = tg;
         any_log = an;
         log_cap = cap;
+        return FLOOD_OK;
+    };
+
+    // checkpoint i of a member group: the i-th held block, grown to a group state
+    auto checkpoint = [&](int i, T** p) -> flood_status {
+        if ((int)adj_ckpt.size() <= i) adj_ckpt.resize(i + 1);
+        CHK(adj_reserve(adj_ckpt[i], slot_elems * sizeof(T), err));
+        *p = static_cast<T*>(adj_ckpt[i].p);
         return FLOOD_OK;
     };
 
@@ -1714,7 +1788,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                     for (int i = 0; i < B; ++i) {
                         if (L % ckpt_every == 0) {
                             T* ck;
-                            CHK(talloc(slot_elems * sizeof(T), (void**)&ck));
+                            CHK(checkpoint((int)ckpts.size(), &ck));
                             ckpts.push_back(ck);
                             T* ch[2] = {ck, ck};
                             T* cx[2] = {ck + elemsG, ck + elemsG};
@@ -1813,11 +1887,6 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
             launch_sum_parts(V.strips_x * V.strips_y, Gg, d_mubar, d_gm + g0, st);
             HIPCHK(hipGetLastError());
             HIPCHK(hipStreamSynchronize(st));
-            for (T* p : ckpts) {
-                auto it = std::find(tmp.begin(), tmp.end(), (void*)p);
-                if (it != tmp.end()) tmp.erase(it);
-                (void)hipFree(p);
-            }
             continue;
         }
 
@@ -1836,7 +1905,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                 for (int i = 0; i < B; ++i) {
                     if (L % ckpt_every == 0) {
                         T* ck;
-                        CHK(talloc(slot_elems * sizeof(T), (void**)&ck));
+                        CHK(checkpoint((int)ckpts.size(), &ck));
                         ckpts.push_back(ck);
                         T* ch[2] = {ck, ck};
                         T* cx[2] = {ck + elemsG, ck + elemsG};
@@ -1941,11 +2010,6 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
         launch_sum_parts(nblk, Gg, d_mubar, d_gm + g0, st);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
-        for (T* p : ckpts) {
-            auto it = std::find(tmp.begin(), tmp.end(), (void*)p);
-            if (it != tmp.end()) tmp.erase(it);
-            (void)hipFree(p);
-        }
     }
     double loss_h = 0.0;
     HIPCHK(hipMemcpyAsync(&loss_h, d_loss, sizeof(double), hipMemcpyDeviceToHost, st));

@@ -24,7 +24,8 @@ EXPORTED = ["flood_create", "flood_create_batch", "flood_step", "flood_assimilat
             "flood_get_field", "flood_set_state", "flood_set_params", "flood_get_ledger", "flood_get_weights",
             "flood_systematic_resample", "flood_ensemble_products", "flood_get_land_params", "flood_save",
             "flood_load", "flood_set_sections", "flood_get_sections", "flood_assimilate_obs",
-            "flood_get_config", "flood_timing", "flood_get_timing", "flood_last_error", "flood_strerror",
+            "flood_get_config", "flood_timing", "flood_get_timing", "flood_adjoint_release", "flood_last_error",
+            "flood_strerror",
             "flood_destroy"]
 
 
@@ -96,6 +97,7 @@ def load_library():
         "flood_get_config": [H, ip, ip, ip, ip, ip, ip, ip, ip],
         "flood_timing": [H, C.c_int32],
         "flood_get_timing": [H, dp, lp],
+        "flood_adjoint_release": [H],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -352,6 +354,11 @@ def flood_get_config(h):
             "march_members": v[6].value, "march_order": v[7].value}
 
 
+def flood_adjoint_release(h):
+    """Free the scratch flood_adjoint keeps on the handle between calls."""
+    _check(load_library().flood_adjoint_release(h), h)
+
+
 def flood_timing(h, enable):
     _check(load_library().flood_timing(h, 1 if enable else 0), h)
 
@@ -494,6 +501,10 @@ class FloodEnsemble:
 
     def get_timing(self):
         return flood_get_timing(self.h)
+
+    def adjoint_release(self):
+        """Free the adjoint's scratch (tape, checkpoints) held since the last adjoint call."""
+        flood_adjoint_release(self.h)
 
     def close(self):
         if self.h:

@@ -182,6 +182,7 @@ def test_null_handle_calls_are_rejected(lib):
     from paper_2302_08341_amd import flood
     assert lib.flood_step(None, 1.0) == flood.FLOOD_EINVAL
     assert lib.flood_get_field(None, 0, 0, 0, None) == flood.FLOOD_EINVAL
+    assert lib.flood_adjoint_release(None) == flood.FLOOD_EINVAL
     lib.flood_destroy(None)   # NULL-safe
 
 

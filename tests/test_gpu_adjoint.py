@@ -171,6 +171,30 @@ def test_adjoint_checkpoint_interval_and_groups_are_consistent(fl, monkeypatch, 
     assert np.linalg.norm(grp[1] - ref[1]) <= 1e-6 * np.linalg.norm(ref[1])
 
 
+@SK
+def test_repeated_calls_on_one_handle_reuse_the_held_scratch(fl, sk):
+    # flood_adjoint keeps its tape and checkpoints on the handle: the second call
+    # reuses them, a longer checkpoint interval grows them, a shorter one runs in
+    # the larger blocks, and after flood_adjoint_release the next call allocates
+    # them again; every call gives a fresh handle's results exactly
+    z, n, h0, s, mu, g = _smooth(n_members=4)
+    rain = [2e-4, 1e-4]
+    obs = np.random.default_rng(0).uniform(0.3, 0.5, size=(4, len(g)))
+    kw = dict(real_bytes=4, step_kernel=sk)
+    ny, nx = z.shape
+    e = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, **kw)
+    for ck, release in ((5, False), (5, False), (12, False), (3, True), (12, False)):
+        ref = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, **kw).adjoint(0, 40.0, 10.0, g, obs, ck)
+        for i in range(4):
+            e.set_state(i, h0.astype(np.float64), np.zeros((ny, nx + 1)), np.zeros((ny + 1, nx)), 0.0)
+        got = e.adjoint(0, 40.0, 10.0, g, obs, ck)
+        assert got[0] == ref[0]
+        np.testing.assert_array_equal(got[1], ref[1])
+        np.testing.assert_array_equal(got[2], ref[2])
+        if release:
+            e.adjoint_release()
+
+
 def test_adjoint_interleave_variants_agree(fl):
     z, n, h0, s, mu, g = _smooth(n_members=4)
     rain = [2e-4, 1e-4]
