@@ -1275,74 +1275,103 @@ template void launch_march<double>(const StepLaunch<double>&, int, int, hipStrea
 
 
 // ---------------------------------------------------------------------------
-// Ensemble products of the running maximum depth (Sec. 4.4, Figs. 15-16).  One
-// lane per cell; a workgroup of 64 cells stages its cells' member values in
-// LDS (member-major, so the staging loads are contiguous in every member's
-// plane), then each lane forms, in member order and FP64, the weight of the
-// members at or above the threshold and, for every member k, the weight of the
-// members at or below member k's value; the smallest value whose weight
-// reaches p W is the p-quantile (inverted distribution function).
+// Ensemble products of the running maximum depth (Sec. 4.4, Figs. 15-16).  A
+// workgroup covers 64 cells with four wavefronts, one lane per cell in each:
+// it stages its cells' member values in LDS (member-major, so the staging
+// loads are contiguous in every member's plane), the first wavefront forms, in
+// member order and FP64, the weight of the members at or above the threshold,
+// and the four wavefronts share the candidates k: for each, the weight of the
+// members at or below member k's value, again in member order; the smallest
+// value whose weight reaches p W is the p-quantile (inverted distribution
+// function), a minimum over the candidates that is the same in any order.
 // ---------------------------------------------------------------------------
 constexpr int kProdCells = 64;
+constexpr int kProdWaves = 4;      // wavefronts per workgroup, splitting the candidates
 constexpr int kProdMaxPct = 16;
 
 constexpr int kProdUnroll = 8;   // percentile candidates evaluated per pass over the members
 
 template <typename T, int MI, bool LDS>
-__global__ __launch_bounds__(kProdCells) void k_products(const CatchDev<T> C, double thr, int n_pct,
-                                                         const double* __restrict__ pct,
-                                                         const double* __restrict__ w, double W,
-                                                         double* __restrict__ prob, double* __restrict__ pout) {
+__global__ __launch_bounds__(kProdCells * kProdWaves) void k_products(const CatchDev<T> C, double thr, int n_pct,
+                                                                       const double* __restrict__ pct,
+                                                                       const double* __restrict__ w, double W,
+                                                                       double* __restrict__ prob,
+                                                                       double* __restrict__ pout) {
     extern __shared__ unsigned char smem[];
     T* vals = reinterpret_cast<T*>(smem);
     const int N = C.n_members;
     const size_t ncell = (size_t)C.ny * C.nx;
-    const size_t cell = (size_t)blockIdx.x * kProdCells + threadIdx.x;
+    const int lane = (int)threadIdx.x % kProdCells;
+    const int wave = (int)threadIdx.x / kProdCells;
+    const size_t cell = (size_t)blockIdx.x * kProdCells + lane;
     const bool in = cell < ncell;
     const int r = in ? (int)(cell / C.nx) : 0, c = in ? (int)(cell % C.nx) : 0;
     auto value = [&](int m) -> T {
-        if constexpr (LDS) return vals[(size_t)m * kProdCells + threadIdx.x];
+        if constexpr (LDS) return vals[(size_t)m * kProdCells + lane];
         else return C.peak[state_index<T, MI>(C, m, r, c)];
     };
     if constexpr (LDS) {
-        for (int m = 0; m < N; ++m) vals[(size_t)m * kProdCells + threadIdx.x] = in ? C.peak[state_index<T, MI>(C, m, r, c)] : T(0);
-        __syncthreads();
+        for (int m = wave; m < N; m += kProdWaves)
+            vals[(size_t)m * kProdCells + lane] = in ? C.peak[state_index<T, MI>(C, m, r, c)] : T(0);
     }
-    if (!in) return;
-    double hit = 0.0;
-    for (int m = 0; m < N; ++m) hit += ((double)value(m) >= thr) ? w[m] : 0.0;
-    if (prob) prob[cell] = hit / W;
-    if (n_pct == 0 || !pout) return;
+    __syncthreads();
+    const bool want_pct = n_pct > 0 && pout != nullptr;   // the same for the whole grid
     double best[kProdMaxPct];
     double lim[kProdMaxPct];
     for (int i = 0; i < n_pct; ++i) {
         best[i] = INFINITY;
         lim[i] = pct[i] * W;
     }
-    // kProdUnroll candidates k per pass over the members: independent sums (each
-    // still in member order), one read of each member value per pass
-    for (int k0 = 0; k0 < N; k0 += kProdUnroll) {
-        T vk[kProdUnroll];
-        double cum[kProdUnroll];
-#pragma unroll
-        for (int q = 0; q < kProdUnroll; ++q) {
-            vk[q] = value(k0 + q < N ? k0 + q : N - 1);
-            cum[q] = 0.0;
+    if (in) {
+        if (wave == 0) {
+            // w_m x 1 or x 0 in one FMA: the sum of the selected weights, rounded as
+            // the plain additions are (weights are finite and >= 0)
+            double hit = 0.0;
+            for (int m = 0; m < N; ++m) hit = __builtin_fma(w[m], ((double)value(m) >= thr) ? 1.0 : 0.0, hit);
+            if (prob) prob[cell] = hit / W;
         }
-        for (int m = 0; m < N; ++m) {
-            const T vm = value(m);
-            const double wm = w[m];
+        // kProdUnroll candidates k per pass over the members: independent sums
+        // (each still in member order), one read of each member value per pass;
+        // the wavefronts take interleaved groups of candidates
+        if (want_pct) {
+            for (int k0 = wave * kProdUnroll; k0 < N; k0 += kProdWaves * kProdUnroll) {
+                T vk[kProdUnroll];
+                double cum[kProdUnroll];
 #pragma unroll
-            for (int q = 0; q < kProdUnroll; ++q) cum[q] += (vm <= vk[q]) ? wm : 0.0;
-        }
+                for (int q = 0; q < kProdUnroll; ++q) {
+                    vk[q] = value(k0 + q < N ? k0 + q : N - 1);
+                    cum[q] = 0.0;
+                }
+                for (int m = 0; m < N; ++m) {
+                    const T vm = value(m);
+                    const double wm = w[m];
 #pragma unroll
-        for (int q = 0; q < kProdUnroll; ++q) {
-            if (k0 + q >= N) break;
-            for (int i = 0; i < n_pct; ++i)
-                if (cum[q] >= lim[i] && (double)vk[q] < best[i]) best[i] = (double)vk[q];
+                    for (int q = 0; q < kProdUnroll; ++q) cum[q] = __builtin_fma(wm, (vm <= vk[q]) ? 1.0 : 0.0, cum[q]);
+                }
+#pragma unroll
+                for (int q = 0; q < kProdUnroll; ++q) {
+                    if (k0 + q >= N) break;
+                    for (int i = 0; i < n_pct; ++i)
+                        if (cum[q] >= lim[i] && (double)vk[q] < best[i]) best[i] = (double)vk[q];
+                }
+            }
         }
     }
-    for (int i = 0; i < n_pct; ++i) pout[(size_t)i * ncell + cell] = best[i];
+    if (!want_pct) return;   // uniform: no wavefront is left waiting at the barriers below
+    // minimum over the wavefronts' candidates, through LDS (the staged values are done with)
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(smem);   // [wave][percentile][lane]
+    for (int i = 0; i < n_pct; ++i) red[((size_t)wave * n_pct + i) * kProdCells + lane] = best[i];
+    __syncthreads();
+    if (wave == 0 && in)
+        for (int i = 0; i < n_pct; ++i) {
+            double b = red[(size_t)i * kProdCells + lane];
+            for (int v = 1; v < kProdWaves; ++v) {
+                const double o = red[((size_t)v * n_pct + i) * kProdCells + lane];
+                b = o < b ? o : b;
+            }
+            pout[(size_t)i * ncell + cell] = b;
+        }
 }
 
 template <typename T, int MI>
@@ -1350,13 +1379,14 @@ static void launch_products_mi(const CatchDev<T>& C, double thr, int n_pct, cons
                                double W, double* prob, double* pout, hipStream_t s) {
     const size_t ncell = (size_t)C.ny * C.nx;
     const dim3 grid((unsigned)((ncell + kProdCells - 1) / kProdCells));
-    const size_t lds = (size_t)C.n_members * kProdCells * sizeof(T);
-    if (lds <= 48 * 1024)
-        hipLaunchKernelGGL((k_products<T, MI, true>), grid, dim3(kProdCells), lds, s, C, thr, n_pct, pct, w, W, prob,
-                           pout);
+    const dim3 block(kProdCells * kProdWaves);
+    const size_t stage = (size_t)C.n_members * kProdCells * sizeof(T);
+    const size_t red = (size_t)kProdWaves * std::max(n_pct, 1) * kProdCells * sizeof(double);
+    if (stage <= 48 * 1024)
+        hipLaunchKernelGGL((k_products<T, MI, true>), grid, block, std::max(stage, red), s, C, thr, n_pct, pct, w, W,
+                           prob, pout);
     else
-        hipLaunchKernelGGL((k_products<T, MI, false>), grid, dim3(kProdCells), 0, s, C, thr, n_pct, pct, w, W, prob,
-                           pout);
+        hipLaunchKernelGGL((k_products<T, MI, false>), grid, block, red, s, C, thr, n_pct, pct, w, W, prob, pout);
 }
 
 template <typename T>
