@@ -1172,10 +1172,23 @@ template <typename T> struct Impl : ImplBase {
         return FLOOD_OK;
     }
 
-    flood_status recompute_hmax(int c, std::string& err) {
+    // depth maximum of every member of catchment c, or (m >= 0) of member m only
+    flood_status recompute_hmax(int c, std::string& err, int m = -1) {
         const Cat& C = cats[c];
-        launch_zero_bins<HB>(C.dev.member_off, C.N, n_total, hbins, st);
-        launch_hmax_init<T>(mi, C.dev, par, hbins, n_total, st);
+        if (m >= 0 && mi == 1) {
+            // a one-member view: members in planes, so member m's plane is its own array
+            CatchDev<T> one = C.dev;
+            const size_t plane = (size_t)C.ny * C.nx;
+            for (int k = 0; k < 2; ++k) one.h[k] = C.dev.h[k] + (size_t)m * plane;
+            one.member_off = C.dev.member_off + m;
+            one.n_members = 1;
+            one.n_chunks = 1;
+            launch_zero_bins<HB>(one.member_off, 1, n_total, hbins, st);
+            launch_hmax_init<T>(mi, one, par, hbins, n_total, st);
+        } else {
+            launch_zero_bins<HB>(C.dev.member_off, C.N, n_total, hbins, st);
+            launch_hmax_init<T>(mi, C.dev, par, hbins, n_total, st);
+        }
         HIPCHK(hipGetLastError());
         return FLOOD_OK;
     }
@@ -1217,7 +1230,7 @@ template <typename T> struct Impl : ImplBase {
             HIPCHK(hipStreamSynchronize(st));
         }
         HIPCHK(hipMemcpy(t + g, &tt, sizeof(double), hipMemcpyHostToDevice));
-        CHK(recompute_hmax(c, err));
+        CHK(recompute_hmax(c, err, m));
         HIPCHK(hipStreamSynchronize(st));
         return FLOOD_OK;
     }
