@@ -975,10 +975,22 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
 #pragma unroll
         for (int j = 0; j < V; ++j) fN[j] = T(0);
     }
+    // inflow ids of the strip's north and south edge links, one byte per cell of
+    // the lane (0xff: none), read before the row loop so that the loop keeps no
+    // table addresses; the west and east ids are read per row, wavefront-uniform
+    uint32_t nid4 = 0xffffffffu, sid4 = 0xffffffffu;
+    if (INF) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            if (r0 == 0) nid4 = (nid4 & ~(0xffu << (8 * j))) | ((uint32_t)(uint8_t)INF[xa + j] << (8 * j));
+            if (r1 == ny) sid4 = (sid4 & ~(0xffu << (8 * j))) | ((uint32_t)(uint8_t)INF[nx + xa + j] << (8 * j));
+        }
+    }
+    auto id_of = [](uint32_t w, int j) -> int { return (int)(int8_t)(uint8_t)((w >> (8 * j)) & 0xffu); };
     if (INF && r0 == 0) {
 #pragma unroll
         for (int j = 0; j < V; ++j) {
-            const int id = INF[xa + j];
+            const int id = id_of(nid4, j);
             if (id >= 0) fN[j] = inflow_q(id);
         }
     }
@@ -1012,6 +1024,8 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
     T vdr = T(0);
     for (int r = r0; r < r1; ++r) {
         const bool hasS = r + 1 < ny;
+        const int idW = (INF && westw) ? (int)INF[2 * nx + r] : -1;
+        const int idE = (INF && eastw) ? (int)INF[2 * nx + ny + r] : -1;
         T hs2[V], zs2[V], ns2[V], qE2[V], qS2[V];
         uint32_t csw2 = 0;
         if (PF == 2) {
@@ -1040,8 +1054,7 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
                 if (xl + j + 1 == nx) {
                     fE[j] = C.edge_open[1] ? link_open(qE[j], hc[j], g * (nc[j] * nc[j]), C.edge_slope[1], ms, hdry)
                                            : T(0);
-                    const int id = INF ? (int)INF[2 * nx + ny + r] : -1;
-                    if (id >= 0) fE[j] = -inflow_q(id);
+                    if (idE >= 0) fE[j] = -inflow_q(idE);
                 }
         }
         T fW[V];
@@ -1051,8 +1064,7 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
         if (westw && xl == 0) {
             fW[0] = C.edge_open[3] ? -link_open(-QWs[r], hc[0], g * (nc[0] * nc[0]), C.edge_slope[3], ms, hdry)
                                    : T(0);
-            const int id = INF ? (int)INF[2 * nx + r] : -1;
-            if (id >= 0) fW[0] = inflow_q(id);
+            if (idW >= 0) fW[0] = inflow_q(idW);
         }
         T fS[V];
         if (hasS) {
@@ -1073,7 +1085,7 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
             if (INF) {
 #pragma unroll
                 for (int j = 0; j < V; ++j) {
-                    const int id = INF[nx + xa + j];
+                    const int id = id_of(sid4, j);
                     if (id >= 0) fS[j] = -inflow_q(id);
                 }
             }
@@ -1136,15 +1148,13 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
             if (!REC && (westw || eastw || r == 0 || !hasS)) {
                 double* acc = C.out_acc + (size_t)k * nb;
                 // inflow links are not outflow: their volume is logged by the step planner
-                auto out = [&](int e) { return !INF || INF[e] < 0; };
 #pragma unroll
                 for (int j = 0; j < V; ++j) {
                     const int x = xl + j;
-                    if (r == 0 && C.edge_open[0] && out(x)) acc[x] += -(double)fN[j] * ms.dxdt;
-                    if (!hasS && C.edge_open[2] && out(nx + x)) acc[nx + x] += (double)fS[j] * ms.dxdt;
-                    if (x == 0 && C.edge_open[3] && out(2 * nx + r)) acc[2 * nx + r] += -(double)fW[j] * ms.dxdt;
-                    if (x + 1 == nx && C.edge_open[1] && out(2 * nx + ny + r))
-                        acc[2 * nx + ny + r] += (double)fE[j] * ms.dxdt;
+                    if (r == 0 && C.edge_open[0] && id_of(nid4, j) < 0) acc[x] += -(double)fN[j] * ms.dxdt;
+                    if (!hasS && C.edge_open[2] && id_of(sid4, j) < 0) acc[nx + x] += (double)fS[j] * ms.dxdt;
+                    if (x == 0 && C.edge_open[3] && idW < 0) acc[2 * nx + r] += -(double)fW[j] * ms.dxdt;
+                    if (x + 1 == nx && C.edge_open[1] && idE < 0) acc[2 * nx + ny + r] += (double)fE[j] * ms.dxdt;
                 }
             }
         }
