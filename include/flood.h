@@ -153,6 +153,42 @@ flood_status flood_create_batch(int32_t n_catch, const flood_grid* grids, const 
  * reach t_end), EHIP. */
 flood_status flood_step(flood_handle* h, double t_end);
 
+/* flood_step with a bound: every member takes at most max_steps (>= 1) more
+ * steps toward t_end, each exactly the step flood_step would take (Eq. 4 or
+ * the fixed step, clipped to rain-block edges and t_end).  With max_steps = 1
+ * a caller observes every step of a trajectory, e.g. to replay it in a
+ * reference model.  Errors: as flood_step; EINVAL when max_steps < 1. */
+flood_status flood_step_n(flood_handle* h, double t_end, int64_t max_steps);
+
+/* Wet/dry decision each link of one member takes in its next step, from the
+ * member's current state (Sec. 2.1: a link carries flow only when the flow
+ * depth of Eq. 3 exceeds h_dry; the paper's remark on wet-dry fronts is why
+ * this decision is exported for checking).  The flow depth is formed exactly
+ * as the step kernels form it: the depth of the cell with the higher water
+ * surface minus the positive part of the bed step towards the other cell.
+ * Open edge links are wet when their inner cell's depth exceeds h_dry; walls
+ * and inflow links take no decision and read 0.
+ *   wet_x host [ny*(nx+1)], wet_y host [(ny+1)*nx] (the QX / QY layouts), 1 or 0
+ * Errors: EINVAL (indices, NULL outputs), EHIP.  Synchronises the stream. */
+flood_status flood_get_wet_mask(flood_handle* h, int32_t catchment, int32_t member, uint8_t* wet_x, uint8_t* wet_y);
+
+/* Step log for replaying trajectories in a reference model: from this call
+ * on, every step of every member records its length dt and its end time
+ * (Eq. 4 step, clipped; FP64 as the handle uses them), up to capacity entries
+ * per member; a member's counter keeps counting past the capacity.  Each call
+ * restarts every counter; capacity 0 closes the log.  A particle-filter copy
+ * does not move logs: slot j's log is the history of slot j.  The adjoint's
+ * own forward run is not logged.  Errors: EINVAL (capacity outside
+ * [0, 2^24]), ENOMEM. */
+flood_status flood_log_steps(flood_handle* h, int32_t capacity);
+
+/* Copy the step log of one catchment: dt_out and t_end_out host [N*capacity]
+ * member-major (entry i of member m at m*capacity + i), count_out host [N]
+ * steps taken since the log was opened (entries beyond the capacity were
+ * dropped).  Any output may be NULL.  ESTATE when no log is open. */
+flood_status flood_get_step_log(flood_handle* h, int32_t catchment, double* dt_out, double* t_end_out,
+                                int64_t* count_out);
+
 /* Particle-filter cycle of Sec. 3.3 on one catchment whose members are all at
  * the same time: (I) gauge depths y_ik = h_i(gauge_k), (II) weights
  * w_i ~ w_i^- exp(-1/2 sum_k ((y_ik - d_k)/sigma_k)^2) (Eqs. 9-11, computed in

@@ -77,6 +77,10 @@ def _load():
         lib.orc_dt_cfl.restype = C.c_double
         lib.orc_dt_cfl.argtypes = [Mp, dp]
         lib.orc_step.argtypes = [Mp, Sp, C.c_double]
+        u8 = C.POINTER(C.c_uint8)
+        lib.orc_step_forced.argtypes = [Mp, Sp, C.c_double, C.c_double, u8, u8]
+        lib.orc_link_depths.argtypes = [Mp, dp, dp, dp]
+        lib.orc_wet_masks.argtypes = [Mp, dp, C.c_double, C.c_int32, u8, u8]
         lib.orc_advance.argtypes = [Mp, Sp, C.c_double, C.c_int64, dp, C.c_int64, lp]
         lib.orc_storage.restype = C.c_double
         lib.orc_storage.argtypes = [Mp, dp]
@@ -247,6 +251,63 @@ def step(model: Model, mem: Member, dt: float) -> None:
     if rc:
         raise ValueError("orc_step failed: %d" % rc)
     mem._back(cm)
+
+
+def _u8(a):
+    return a.ctypes.data_as(C.POINTER(C.c_uint8))
+
+
+def step_forced(model: Model, mem: Member, dt: float, t_next: float, wet_x, wet_y) -> None:
+    """One step of length dt ending at t_next with every link's wet/dry decision given
+    (wet_x [ny, nx+1], wet_y [ny+1, nx], 1 wet / 0 dry): replay of another model's
+    trajectory, its step lengths and its decisions."""
+    wx = np.ascontiguousarray(wet_x, dtype=np.uint8)
+    wy = np.ascontiguousarray(wet_y, dtype=np.uint8)
+    assert wx.shape == (model.ny, model.nx + 1) and wy.shape == (model.ny + 1, model.nx)
+    cm = mem._c()
+    rc = _load().orc_step_forced(model.ptr, C.byref(cm), float(dt), float(t_next), _u8(wx), _u8(wy))
+    if rc:
+        raise ValueError("orc_step_forced failed: %d" % rc)
+    mem._back(cm)
+
+
+def replay(model: Model, mem: Member, dts, t_ends) -> None:
+    """Advance mem by the given steps (lengths dts, end times t_ends), each link deciding
+    wet/dry itself."""
+    for dt, te in zip(dts, t_ends):
+        step(model, mem, float(dt))
+        mem.t = float(te)
+
+
+def link_depths(model: Model, h):
+    """Eq. 3 flow depth of every link as written (higher surface minus higher bed; edge
+    links: the inner depth): (hx [ny, nx+1], hy [ny+1, nx])."""
+    h = _f64(h)
+    hx = np.zeros((model.ny, model.nx + 1))
+    hy = np.zeros((model.ny + 1, model.nx))
+    rc = _load().orc_link_depths(model.ptr, _dp(h), _dp(hx), _dp(hy))
+    if rc:
+        raise ValueError("orc_link_depths failed: %d" % rc)
+    return hx, hy
+
+
+MASK_LITERAL, MASK_FLOAT, MASK_DIFF64 = 0, 1, 2
+
+
+def wet_masks(model: Model, h, t: float = 0.0, fp32: bool = False, mode: int = None):
+    """Wet/dry decision of every link for the next step from depths h at time t (uint8
+    (wet_x [ny, nx+1], wet_y [ny+1, nx])).  mode MASK_LITERAL: in double as Eq. 3 is
+    written; MASK_FLOAT (or fp32=True): in single precision, flow depth in difference
+    form; MASK_DIFF64: in double, difference form (a double-precision model's own)."""
+    h = _f64(h)
+    if mode is None:
+        mode = MASK_FLOAT if fp32 else MASK_LITERAL
+    wx = np.zeros((model.ny, model.nx + 1), dtype=np.uint8)
+    wy = np.zeros((model.ny + 1, model.nx), dtype=np.uint8)
+    rc = _load().orc_wet_masks(model.ptr, _dp(h), float(t), int(mode), _u8(wx), _u8(wy))
+    if rc:
+        raise ValueError("orc_wet_masks failed: %d" % rc)
+    return wx, wy
 
 
 def advance(model: Model, mem: Member, t_end: float, max_steps: int = 10 ** 12, log_dt: bool = False) -> int:

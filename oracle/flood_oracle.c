@@ -131,15 +131,29 @@ static int wet_link_f32(const orc_model* m, double h1, double z1, double h2, dou
 
 static int wet_edge_f32(const orc_model* m, double h) { return (float)h > (float)m->h_dry; }
 
+/* The same decision in double precision: the difference form of the flow depth
+ * rounds differently from the literal one only where the flow depth is within
+ * a rounding of h_dry.  Used to compare with a double-precision model from the
+ * same state. */
+static int wet_link_diff64(const orc_model* m, double h1, double z1, double h2, double z2) {
+    const double dz = z2 - z1;
+    const double d = h1 - h2;
+    const double hf = (d >= dz) ? h1 - fmax(dz, 0.0) : h2 - fmax(-dz, 0.0);
+    return hf > m->h_dry;
+}
+
 /* Interior link between cell 1 (west or north) and cell 2 (east or south).
  * The donor limiter keeps each link from draining more than a quarter of its
- * upwind cell in one step. */
+ * upwind cell in one step.  force < 0: the link decides wet/dry itself; 0 or 1:
+ * the decision is given (replay of another model's decisions, see
+ * orc_step_forced); a link given as wet with no flow depth still carries none. */
 static double link_interior(const orc_model* m, double s, double q, double h1, double z1, double n1,
-                            double h2, double z2, double n2, double dt) {
+                            double h2, double z2, double n2, double dt, int force) {
     double eta1 = h1 + z1;
     double eta2 = h2 + z2;
     double hf = fmax(eta1, eta2) - fmax(z1, z2);
-    if (m->wet_fp32 ? !wet_link_f32(m, h1, z1, h2, z2) : !(hf > m->h_dry)) return 0.0;
+    int wet = force >= 0 ? (force && hf > 0.0) : m->wet_fp32 ? wet_link_f32(m, h1, z1, h2, z2) : hf > m->h_dry;
+    if (!wet) return 0.0;
     double S = (eta2 - eta1) / m->dx;
     double nf = s * 0.5 * (n1 + n2);
     double qn = (q - m->g * hf * dt * S) / (1.0 + m->g * nf * nf * fabs(q) * dt / pow(hf, 7.0 / 3.0));
@@ -153,9 +167,10 @@ static double link_interior(const orc_model* m, double s, double q, double h1, d
 /* Open edge link, outward discharge qo >= 0 driven by a fixed outward
  * water-surface slope Se; the flow depth is the inner cell's depth. */
 static double link_open(const orc_model* m, double s, double qo, double hi, double ni, double Se,
-                        double dt) {
+                        double dt, int force) {
     double hf = hi;
-    if (m->wet_fp32 ? !wet_edge_f32(m, hi) : !(hf > m->h_dry)) return 0.0;
+    int wet = force >= 0 ? (force && hf > 0.0) : m->wet_fp32 ? wet_edge_f32(m, hi) : hf > m->h_dry;
+    if (!wet) return 0.0;
     double nf = s * ni;
     double qn = (qo + m->g * hf * dt * Se) / (1.0 + m->g * nf * nf * fabs(qo) * dt / pow(hf, 7.0 / 3.0));
     qn = fmin(qn, hi * m->dx / (4.0 * dt));
@@ -185,8 +200,11 @@ static double cell_rough(const orc_model* m, const double* class_n, int64_t i) {
     return m->cls ? class_n[m->cls[i]] : m->n[i];
 }
 
+/* fwx, fwy: optional wet/dry decisions of every link in the x- and y-link
+ * layouts (replay); NULL: every link decides itself. */
 static double links_all(const orc_model* m, double s, const double* class_n, const double* h, const double* qx,
-                        const double* qy, double dt, double t, double* qxn, double* qyn, double* vin) {
+                        const double* qy, double dt, double t, double* qxn, double* qyn, double* vin,
+                        const uint8_t* fwx, const uint8_t* fwy) {
     if (m->cls) s = 1.0;
     const int ny = m->ny, nx = m->nx;
     const double dx = m->dx;
@@ -202,20 +220,22 @@ static double links_all(const orc_model* m, double s, const double* class_n, con
                 int64_t i = (int64_t)r * nx;
                 double qo = 0.0;
                 if (m->edge_kind[EDGE_W] == EDGE_OPEN)
-                    qo = link_open(m, s, -qx[li], h[i], cell_rough(m, class_n, i), m->edge_slope[EDGE_W], dt);
+                    qo = link_open(m, s, -qx[li], h[i], cell_rough(m, class_n, i), m->edge_slope[EDGE_W], dt,
+                                   fwx ? fwx[li] : -1);
                 qxn[li] = -qo;
                 vout += qo * dx * dt;
             } else if (c == nx) {
                 int64_t i = (int64_t)r * nx + nx - 1;
                 double qo = 0.0;
                 if (m->edge_kind[EDGE_E] == EDGE_OPEN)
-                    qo = link_open(m, s, qx[li], h[i], cell_rough(m, class_n, i), m->edge_slope[EDGE_E], dt);
+                    qo = link_open(m, s, qx[li], h[i], cell_rough(m, class_n, i), m->edge_slope[EDGE_E], dt,
+                                   fwx ? fwx[li] : -1);
                 qxn[li] = qo;
                 vout += qo * dx * dt;
             } else {
                 int64_t i1 = (int64_t)r * nx + c - 1, i2 = i1 + 1;
                 qxn[li] = link_interior(m, s, qx[li], h[i1], m->z[i1], cell_rough(m, class_n, i1), h[i2], m->z[i2],
-                                        cell_rough(m, class_n, i2), dt);
+                                        cell_rough(m, class_n, i2), dt, fwx ? fwx[li] : -1);
             }
         }
     }
@@ -230,20 +250,22 @@ static double links_all(const orc_model* m, double s, const double* class_n, con
                 int64_t i = c;
                 double qo = 0.0;
                 if (m->edge_kind[EDGE_N] == EDGE_OPEN)
-                    qo = link_open(m, s, -qy[li], h[i], cell_rough(m, class_n, i), m->edge_slope[EDGE_N], dt);
+                    qo = link_open(m, s, -qy[li], h[i], cell_rough(m, class_n, i), m->edge_slope[EDGE_N], dt,
+                                   fwy ? fwy[li] : -1);
                 qyn[li] = -qo;
                 vout += qo * dx * dt;
             } else if (r == ny) {
                 int64_t i = (int64_t)(ny - 1) * nx + c;
                 double qo = 0.0;
                 if (m->edge_kind[EDGE_S] == EDGE_OPEN)
-                    qo = link_open(m, s, qy[li], h[i], cell_rough(m, class_n, i), m->edge_slope[EDGE_S], dt);
+                    qo = link_open(m, s, qy[li], h[i], cell_rough(m, class_n, i), m->edge_slope[EDGE_S], dt,
+                                   fwy ? fwy[li] : -1);
                 qyn[li] = qo;
                 vout += qo * dx * dt;
             } else {
                 int64_t i1 = (int64_t)(r - 1) * nx + c, i2 = i1 + nx;
                 qyn[li] = link_interior(m, s, qy[li], h[i1], m->z[i1], cell_rough(m, class_n, i1), h[i2], m->z[i2],
-                                        cell_rough(m, class_n, i2), dt);
+                                        cell_rough(m, class_n, i2), dt, fwy ? fwy[li] : -1);
             }
         }
     }
@@ -297,10 +319,12 @@ static void scratch_free(orc_scratch* w) {
 }
 
 /* One step of length dt starting at st->t (time is not advanced here). */
-static void step_core(const orc_model* m, orc_member* st, double dt, orc_scratch* w) {
+static void step_core(const orc_model* m, orc_member* st, double dt, orc_scratch* w, const uint8_t* fwx,
+                      const uint8_t* fwy) {
     const int64_t nc = (int64_t)m->ny * m->nx;
     const double area = m->dx * m->dx;
-    st->v_out += links_all(m, st->s, st->class_n, st->h, st->qx, st->qy, dt, st->t, w->qxn, w->qyn, &st->v_in);
+    st->v_out += links_all(m, st->s, st->class_n, st->h, st->qx, st->qy, dt, st->t, w->qxn, w->qyn, &st->v_in,
+                           fwx, fwy);
     double rain_depth = st->mu * rain_at(m, st->t) * dt;
     continuity_unclamped(m, st->h, w->qxn, w->qyn, dt, rain_depth, w->hu);
     double rain_cells = 0.0;
@@ -351,9 +375,99 @@ int orc_step(const orc_model* m, orc_member* st, double dt) {
     if (!model_valid(m) || !st || !(dt > 0.0) || (m->cls && !st->class_n)) return ORC_EINVAL;
     orc_scratch w;
     if (scratch_alloc(m, &w)) return ORC_ENOMEM;
-    step_core(m, st, dt, &w);
+    step_core(m, st, dt, &w, NULL, NULL);
     st->t += dt;
     scratch_free(&w);
+    return ORC_OK;
+}
+
+/* One step of length dt ending at time t_next, with every link's wet/dry
+ * decision taken from wet_x [ny*(nx+1)] and wet_y [(ny+1)*nx] (1 wet, 0 dry)
+ * instead of from the state.  This replays a trajectory of another model that
+ * took its own decisions (a single-precision model near the h_dry threshold):
+ * with the same step lengths and the same decisions, the two trajectories
+ * differ by rounding only.  Inflow links keep their prescribed discharge. */
+int orc_step_forced(const orc_model* m, orc_member* st, double dt, double t_next, const uint8_t* wet_x,
+                    const uint8_t* wet_y) {
+    if (!model_valid(m) || !st || !(dt > 0.0) || !wet_x || !wet_y || (m->cls && !st->class_n)) return ORC_EINVAL;
+    orc_scratch w;
+    if (scratch_alloc(m, &w)) return ORC_ENOMEM;
+    step_core(m, st, dt, &w, wet_x, wet_y);
+    st->t = t_next;
+    scratch_free(&w);
+    return ORC_OK;
+}
+
+/* Flow depth of every link from depths h, as written in Eq. 3: the higher
+ * water surface minus the higher bed; an edge link's flow depth is its inner
+ * cell's depth.  hx [ny*(nx+1)], hy [(ny+1)*nx]. */
+int orc_link_depths(const orc_model* m, const double* h, double* hx, double* hy) {
+    if (!m || !h || !hx || !hy) return ORC_EINVAL;
+    const int ny = m->ny, nx = m->nx;
+    for (int r = 0; r < ny; ++r)
+        for (int c = 0; c <= nx; ++c) {
+            int64_t li = (int64_t)r * (nx + 1) + c;
+            if (c == 0 || c == nx) {
+                hx[li] = h[(int64_t)r * nx + (c == 0 ? 0 : nx - 1)];
+            } else {
+                int64_t i1 = (int64_t)r * nx + c - 1, i2 = i1 + 1;
+                hx[li] = fmax(h[i1] + m->z[i1], h[i2] + m->z[i2]) - fmax(m->z[i1], m->z[i2]);
+            }
+        }
+    for (int r = 0; r <= ny; ++r)
+        for (int c = 0; c < nx; ++c) {
+            int64_t li = (int64_t)r * nx + c;
+            if (r == 0 || r == ny) {
+                hy[li] = h[(int64_t)(r == 0 ? 0 : ny - 1) * nx + c];
+            } else {
+                int64_t i1 = (int64_t)(r - 1) * nx + c, i2 = i1 + nx;
+                hy[li] = fmax(h[i1] + m->z[i1], h[i2] + m->z[i2]) - fmax(m->z[i1], m->z[i2]);
+            }
+        }
+    return ORC_OK;
+}
+
+/* Wet/dry decision of every link from depths h at time t, the one the next
+ * step takes: interior links by their flow depth against h_dry, open edge
+ * links by the inner depth, walls and inflow links 0 (no decision).  mode 0:
+ * in double as Eq. 3 is written; 1: in single precision (wet_link_f32); 2: in
+ * double in the difference form (wet_link_diff64). */
+int orc_wet_masks(const orc_model* m, const double* h, double t, int32_t mode, uint8_t* wx, uint8_t* wy) {
+    if (!model_valid(m) || !h || !wx || !wy || mode < 0 || mode > 2) return ORC_EINVAL;
+    const int fp32 = mode == 1;
+    const int ny = m->ny, nx = m->nx;
+    for (int r = 0; r < ny; ++r)
+        for (int c = 0; c <= nx; ++c) {
+            int64_t li = (int64_t)r * (nx + 1) + c;
+            if (c == 0 || c == nx) {
+                int e = c == 0 ? EDGE_W : EDGE_E;
+                double hi = h[(int64_t)r * nx + (c == 0 ? 0 : nx - 1)];
+                wx[li] = m->edge_kind[e] == EDGE_OPEN && inflow_at(m, e, r, t) < 0.0 &&
+                         (fp32 ? wet_edge_f32(m, hi) : hi > m->h_dry);
+            } else {
+                int64_t i1 = (int64_t)r * nx + c - 1, i2 = i1 + 1;
+                double hf = fmax(h[i1] + m->z[i1], h[i2] + m->z[i2]) - fmax(m->z[i1], m->z[i2]);
+                wx[li] = fp32        ? wet_link_f32(m, h[i1], m->z[i1], h[i2], m->z[i2])
+                         : mode == 2 ? wet_link_diff64(m, h[i1], m->z[i1], h[i2], m->z[i2])
+                                     : hf > m->h_dry;
+            }
+        }
+    for (int r = 0; r <= ny; ++r)
+        for (int c = 0; c < nx; ++c) {
+            int64_t li = (int64_t)r * nx + c;
+            if (r == 0 || r == ny) {
+                int e = r == 0 ? EDGE_N : EDGE_S;
+                double hi = h[(int64_t)(r == 0 ? 0 : ny - 1) * nx + c];
+                wy[li] = m->edge_kind[e] == EDGE_OPEN && inflow_at(m, e, c, t) < 0.0 &&
+                         (fp32 ? wet_edge_f32(m, hi) : hi > m->h_dry);
+            } else {
+                int64_t i1 = (int64_t)(r - 1) * nx + c, i2 = i1 + nx;
+                double hf = fmax(h[i1] + m->z[i1], h[i2] + m->z[i2]) - fmax(m->z[i1], m->z[i2]);
+                wy[li] = fp32        ? wet_link_f32(m, h[i1], m->z[i1], h[i2], m->z[i2])
+                         : mode == 2 ? wet_link_diff64(m, h[i1], m->z[i1], h[i2], m->z[i2])
+                                     : hf > m->h_dry;
+            }
+        }
     return ORC_OK;
 }
 
@@ -383,7 +497,7 @@ int orc_advance(const orc_model* m, orc_member* st, double t_end, int64_t max_st
     while (st->t < t_end && k < max_steps) {
         double t_next;
         double dt = plan_step(m, st->h, st->t, t_end, &t_next);
-        step_core(m, st, dt, &w);
+        step_core(m, st, dt, &w, NULL, NULL);
         st->t = t_next;
         if (dt_log && k < dt_log_cap) dt_log[k] = dt;
         ++k;
@@ -625,7 +739,7 @@ static void adj_step(const orc_model* m, double s, double mu, const double* h, c
     const double R = rain_at(m, t);
     /* forward recomputation to recover the clamp branch */
     double vin = 0.0;          /* no inflow links here: the adjoint refuses them */
-    links_all(m, s, NULL, h, qx, qy, dt, t, a->w.qxn, a->w.qyn, &vin);
+    links_all(m, s, NULL, h, qx, qy, dt, t, a->w.qxn, a->w.qyn, &vin, NULL, NULL);
     continuity_unclamped(m, h, a->w.qxn, a->w.qyn, dt, mu * R * dt, a->w.hu);
     double gm = 0.0;
     for (int64_t i = 0; i < nc; ++i) {
@@ -802,7 +916,7 @@ static int forward_loss(const orc_model* m, orc_member* st, double t_end, double
             } else {
                 dt = plan_step(m, st->h, st->t, ts, &t_next);
             }
-            step_core(m, st, dt, &w);
+            step_core(m, st, dt, &w, NULL, NULL);
             st->t = t_next;
             int32_t tag = (st->t >= ts) ? smp : -1;
             if (rec && rec_push(rec, dt, t_next, tag)) { rc = ORC_ENOMEM; break; }
@@ -884,7 +998,7 @@ int orc_adjoint(const orc_model* m, orc_member* st, double t_end, double sample_
                 memcpy(nxt, cur, sizeof(double) * (size_t)nst);
                 tm.h = nxt; tm.qx = nxt + nc; tm.qy = nxt + nc + nqx;
                 tm.t = (n == 0) ? t0 : rec.t_end[n - 1];
-                step_core(m, &tm, rec.dt[n], &as.w);
+                step_core(m, &tm, rec.dt[n], &as.w, NULL, NULL);
             }
             for (int64_t n = n1 - 1; n >= n0; --n) {
                 const double* before = tape + (n - n0) * nst;

@@ -260,7 +260,31 @@ flood_status flood_create(const flood_grid* grid, const flood_params* params, in
 flood_status flood_step(flood_handle* h, double t_end) {
     FLOOD_NEED_HANDLE(h);
     if (!std::isfinite(t_end)) { h->err = "t_end must be finite"; return FLOOD_EINVAL; }
-    return h->impl->step(t_end, h->err);
+    return h->impl->step(t_end, -1, h->err);
+}
+
+flood_status flood_step_n(flood_handle* h, double t_end, int64_t max_steps) {
+    FLOOD_NEED_HANDLE(h);
+    if (!std::isfinite(t_end)) { h->err = "t_end must be finite"; return FLOOD_EINVAL; }
+    if (max_steps < 1) { h->err = "max_steps must be >= 1"; return FLOOD_EINVAL; }
+    return h->impl->step(t_end, max_steps, h->err);
+}
+
+flood_status flood_get_wet_mask(flood_handle* h, int32_t catchment, int32_t member, uint8_t* wet_x, uint8_t* wet_y) {
+    FLOOD_NEED_HANDLE(h);
+    return h->impl->get_wet_mask(catchment, member, wet_x, wet_y, h->err);
+}
+
+flood_status flood_log_steps(flood_handle* h, int32_t capacity) {
+    FLOOD_NEED_HANDLE(h);
+    if (capacity < 0 || capacity > (1 << 24)) { h->err = "capacity must be in [0, 2^24]"; return FLOOD_EINVAL; }
+    return h->impl->log_steps(capacity, h->err);
+}
+
+flood_status flood_get_step_log(flood_handle* h, int32_t catchment, double* dt_out, double* t_end_out,
+                                int64_t* count_out) {
+    FLOOD_NEED_HANDLE(h);
+    return h->impl->get_step_log(catchment, dt_out, t_end_out, count_out, h->err);
 }
 
 flood_status flood_assimilate(flood_handle* h, int32_t catchment, int32_t n_gauges, const int32_t* gauge_rc,

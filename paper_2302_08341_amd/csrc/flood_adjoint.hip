@@ -25,7 +25,7 @@ __device__ __forceinline__ void link_in_d(T q, T h1, T h2, T dz, T G, T Gn, cons
     // link's intermediate values (possibly inf or NaN) are discarded
     const T d = h1 - h2;
     const bool up1 = d >= dz;
-    const T hf = up1 ? h1 - fmax(dz, T(0)) : h2 - fmax(-dz, T(0));
+    const T hf = link_depth(h1, h2, dz);
     const bool wet = hf > hdry;
     const T p = pow_m73(hf);
     const T A = G * ms.s2dt * p;

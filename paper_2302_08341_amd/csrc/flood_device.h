@@ -26,10 +26,12 @@ template <> __device__ __forceinline__ double from_bits<double>(unsigned long lo
     return __longlong_as_double((long long)b);
 }
 
-// h^(-7/3) of the friction denominator of Eq. 2.
-__device__ __forceinline__ float pow_m73(float h) {
-    return __builtin_amdgcn_exp2f(-2.33333333333333333f * __builtin_amdgcn_logf(h));
-}
+// h^(-7/3) of the friction denominator of Eq. 2, as 1 / (h^2 cbrt(h)): a few
+// ulp.  The hardware exp2(-7/3 log2 h) is cheaper but carries the logarithm's
+// error times the exponent's size, about 2e-6 relative, the same sign step
+// after step; on shallow friction-dominated links that systematic error moved
+// single-precision discharges by 3e-4 of the largest discharge within 80 steps.
+__device__ __forceinline__ float pow_m73(float h) { return __builtin_amdgcn_rcpf(h * h * cbrtf(h)); }
 __device__ __forceinline__ double pow_m73(double h) { return 1.0 / pow(h, 7.0 / 3.0); }
 
 __device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
@@ -43,10 +45,61 @@ __device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
 // the end, so dry and wet links in one wavefront do not split it; a dry link's
 // intermediate values (possibly inf or NaN from the friction power) are
 // discarded by the final select.
+// 32-bit integer hash (an xorshift-multiply finaliser) used as a counter-based
+// random number generator: the random bits of a cell in a step are a function
+// of the member's step count and the cell index only, so they are the same
+// whichever kernel, tiling or batch computes the cell.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Depth update of Eq. 1, h + inc.  In single precision it is rounded
+// stochastically: the exact sum is split into its rounded value s and the
+// exact error e (h + inc = s + e, Knuth's TwoSum, exact with contraction off),
+// and s moves one ulp toward e with probability |e| / ulp, resolved to 2^-16.
+// The expected result is the exact sum (to 2^-17 ulp), so rounding errors no
+// longer pile up in one direction where nearly equal small increments (rain on
+// a pond) meet the same large depth step after step: the stored depth and the
+// mass ledger drift like a random walk instead of linearly.  The 16 random bits
+// of a cell are half of the hash of (seed, cell pair), so a lane moving
+// adjacent cells hashes once per pair.  In double precision the sum is
+// rounded to nearest.
+template <typename T> __device__ __forceinline__ T depth_add(T h, T inc, uint32_t seed, uint32_t cell);
+template <> __device__ __forceinline__ float depth_add<float>(float h, float inc, uint32_t seed, uint32_t cell) {
+    const float s = h + inc;
+    const float bb = s - h;
+    const float e = (h - (s - bb)) + (inc - bb);
+    const uint32_t sb = __float_as_uint(s);
+    const bool away = (e > 0.0f) == (s > 0.0f);          // toward e: away from zero when e has s's sign
+    const float nb = __uint_as_float(away ? sb + 1u : sb - 1u);
+    const float gap = fabsf(nb - s);
+    const uint32_t r = mix32(seed ^ (cell >> 1)) >> ((cell & 1u) << 4);
+    const float u = (float)(r & 0xffffu) * 0x1p-16f;
+    return (e != 0.0f && s != 0.0f && u * gap < fabsf(e)) ? nb : s;
+}
+template <> __device__ __forceinline__ double depth_add<double>(double h, double inc, uint32_t, uint32_t) {
+    return h + inc;
+}
+
+// Eq. 3 flow depth of an interior link in difference form: the depth of the
+// cell with the higher water surface minus the positive part of the bed step
+// towards the other cell.  Every kernel that decides whether a link is wet
+// (step, adjoint, exported wet/dry mask) forms the flow depth here, so their
+// decisions agree bit for bit.
+template <typename T> __device__ __forceinline__ T link_depth(T h1, T h2, T dz) {
+    const T d = h1 - h2;
+    return (d >= dz) ? h1 - fmax(dz, T(0)) : h2 - fmax(-dz, T(0));
+}
+
 template <typename T>
 __device__ __forceinline__ T link_in(T q, T h1, T h2, T dz, T G, const MemberStep<T>& ms, T hdry) {
     const T d = h1 - h2;
-    const T hf = (d >= dz) ? h1 - fmax(dz, T(0)) : h2 - fmax(-dz, T(0));
+    const T hf = link_depth(h1, h2, dz);
     const T num = q - ms.gdtdx * hf * (dz - d);
     const T A = G * ms.s2dt * pow_m73(hf);
     const T qn = qdiv(num, T(1) + A * fabs(q));

@@ -43,6 +43,7 @@ template <typename T> struct MemberStep {
     int32_t active;
     int32_t parity;  // state copy holding the state before this step
     int32_t slot;    // adjoint record: the member's step index within the tape segment
+    uint32_t seed;   // random seed of the step's depth rounding, from the member's time
     T cn[kMaxClasses];  // land cover: the member's Manning n of each class
     T drain;            // land cover: drainage depth of the step (rate x dt)
     T qin[kMaxSeries];  // inward discharge of each inflow series during the step
@@ -134,7 +135,9 @@ template <typename T> struct PlanLaunch {
     MemberStep<T>* ms;
     double* dtlog;            // optional [n_total][dtlog_cap] step lengths
     double* telog;            // optional [n_total][dtlog_cap] step end times
+    int64_t* log_n;           // [n_total] steps logged since the log was opened (may exceed dtlog_cap)
     int32_t dtlog_cap;
+    const int64_t* step_lim;  // optional [n_total]: a member whose step count has reached it does not step
     int32_t m_begin, m_end;   // members planned by this launch (global indices)
     // adjoint record of this launch (null when not recording), indexed by m - m_begin
     MemberStep<T>* ms_log;
@@ -166,8 +169,17 @@ inline int march_waves(int strips_x, int strips_y, int units, int order, int ban
     if (order == 4) return strips_x * ((strips_y + bands - 1) / bands * bands) * units;
     return strips_x * strips_y * units;
 }
+// members still short of t_end (and, when lim is given, of their step limit)
 void launch_count_active(int n_total, const double* t, const int32_t* fault, const double* t_end,
-                         const int32_t* status, int32_t* out, hipStream_t s);
+                         const int32_t* status, const int64_t* steps, const int64_t* lim, int32_t* out,
+                         hipStream_t s);
+// lim[m] = steps[m] + n for the n_total members (n < 0: no limit)
+void launch_step_limit(int n_total, const int64_t* steps, int64_t n, int64_t* lim, hipStream_t s);
+// wet/dry decision every link of one member takes in the next step, from the
+// member's current state (copy p), in the host link layouts: wx [ny][nx+1],
+// wy [ny+1][nx]; 1 wet, 0 dry, wall or inflow link
+template <typename T>
+void launch_wetmask(int mi, const CatchDev<T>& C, int member, int p, uint8_t* wx, uint8_t* wy, hipStream_t s);
 template <typename HB> void launch_zero_bins(int off, int n, int n_total, HB* bins, hipStream_t s);
 template <typename HB>
 void launch_permute_bins(int off, int n, int n_total, HB* bins, const int32_t* anc, const int32_t* flag,

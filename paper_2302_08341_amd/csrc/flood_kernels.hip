@@ -31,13 +31,14 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     ms.active = 0;
     ms.parity = P.par[m];
     ms.slot = -1;
+    ms.seed = 0;
     for (int k = 0; k < kMaxClasses; ++k) ms.cn[k] = T(0);
     ms.drain = T(0);
     for (int k = 0; k < kMaxSeries; ++k) ms.qin[k] = T(0);
     const double t = P.t[m];
     const double t_end = *P.t_end;
     const int lm = m - P.m_begin;
-    if (P.fault[m] || !(t < t_end)) {
+    if (P.fault[m] || !(t < t_end) || (P.step_lim && P.steps[m] >= P.step_lim[m])) {
         P.ms[m] = ms;
         if (P.ms_log) {
             P.ms_log[lm] = ms;
@@ -92,6 +93,12 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     ms.rinc = (T)(P.mu[m] * R * dt);
     ms.dxdt = C.dx * dt;
     ms.active = 1;
+    {
+        // the step's random bits follow from the member's time: a state set back
+        // to an earlier time replays the same rounding
+        const uint64_t tb = (uint64_t)__double_as_longlong(t);
+        ms.seed = mix32((uint32_t)tb ^ mix32((uint32_t)(tb >> 32) + 0x632be5abu));
+    }
     if (P.seg_cnt) ms.slot = P.seg_cnt[lm]++;
     if (P.clsn)
         for (int k = 0; k < kMaxClasses; ++k) ms.cn[k] = (T)P.clsn[(size_t)m * kMaxClasses + k];
@@ -115,9 +122,13 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
         P.any_log[0] = 1;
     }
     const int64_t st = P.steps[m];
-    if (P.dtlog && st < P.dtlog_cap) {
-        P.dtlog[(size_t)m * P.dtlog_cap + st] = dt;
-        P.telog[(size_t)m * P.dtlog_cap + st] = tn;
+    if (P.dtlog) {
+        const int64_t li = P.log_n[m];
+        if (li < P.dtlog_cap) {
+            P.dtlog[(size_t)m * P.dtlog_cap + li] = dt;
+            P.telog[(size_t)m * P.dtlog_cap + li] = tn;
+        }
+        P.log_n[m] = li + 1;
     }
     P.t[m] = tn;
     P.par[m] = ms.parity ^ 1;
@@ -269,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepLaunch<T> L) {
                 fN = C.edge_open[0] ? -link_open(-qN, h0, GN, C.edge_slope[0], ms, hdry) : T(0);
             // Eq. 1 with the four links of Sec. 3.1 (west/east x-links, north/south y-links)
             const T dv = ((fW - fE) + fN) - fS;
-            hn = (h0 + ms.dtdx * dv) + ms.rinc;
+            hn = depth_add(h0, ms.dtdx * dv + ms.rinc, ms.seed, (uint32_t)(cy * nx + cx));
             const bool clamped = hn < T(0);
             if (clamped) {
                 if (!rec) atomicAdd(&L.vclamp[C.member_off + ml], -(double)hn * (C.dx * C.dx));
@@ -324,11 +335,13 @@ template <typename T> void launch_step_mi(int mi, const StepLaunch<T>& L, hipStr
 // members still short of t_end
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_count_active(int n, const double* t, const int32_t* fault,
-                                                      const double* t_end, const int32_t* status, int32_t* out) {
+                                                      const double* t_end, const int32_t* status,
+                                                      const int64_t* steps, const int64_t* lim, int32_t* out) {
     __shared__ int part[4];
     int c = 0;
     const double te = *t_end;
-    for (int m = threadIdx.x; m < n; m += 256) c += (!fault[m] && t[m] < te) ? 1 : 0;
+    for (int m = threadIdx.x; m < n; m += 256)
+        c += (!fault[m] && t[m] < te && (!lim || steps[m] < lim[m])) ? 1 : 0;
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
     __syncthreads();
@@ -339,8 +352,18 @@ __global__ __launch_bounds__(256) void k_count_active(int n, const double* t, co
 }
 
 void launch_count_active(int n_total, const double* t, const int32_t* fault, const double* t_end,
-                         const int32_t* status, int32_t* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(256), 0, s, n_total, t, fault, t_end, status, out);
+                         const int32_t* status, const int64_t* steps, const int64_t* lim, int32_t* out,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(256), 0, s, n_total, t, fault, t_end, status, steps, lim, out);
+}
+
+__global__ __launch_bounds__(256) void k_step_limit(int n, const int64_t* steps, int64_t add, int64_t* lim) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < n) lim[m] = add < 0 ? INT64_MAX : steps[m] + add;
+}
+
+void launch_step_limit(int n_total, const int64_t* steps, int64_t n, int64_t* lim, hipStream_t s) {
+    hipLaunchKernelGGL(k_step_limit, dim3((n_total + 255) / 256), dim3(256), 0, s, n_total, steps, n, lim);
 }
 
 template <typename HB> __global__ __launch_bounds__(256) void k_zero_bins(int off, int n, int n_total, HB* bins) {
@@ -510,6 +533,58 @@ void launch_set_field(int mi, const CatchDev<T>& C, int member, int par, int whi
     launch_field<T>(mi, C, member, par, which, const_cast<double*>(in), 1, s);
 }
 
+// Wet/dry decision of every link of member m from its state in copy p, in the
+// host link layouts (x-links [ny][nx+1], y-links [ny+1][nx]).  Interior links
+// use link_depth, as the step does; an open edge link is wet when its inner
+// cell's depth exceeds h_dry; walls and inflow links (prescribed discharge,
+// no decision) are 0.  One lane per link.
+template <typename T, int MI>
+__global__ __launch_bounds__(256) void k_wetmask(const CatchDev<T> C, int m, int p, uint8_t* wx, uint8_t* wy) {
+    const int ny = C.ny, nx = C.nx;
+    const size_t nxl = (size_t)ny * (nx + 1), nyl = (size_t)(ny + 1) * nx;
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nxl + nyl) return;
+    const T* H = C.h[p];
+    const T hdry = C.hdry;
+    auto hat = [&](int r, int c) -> T { return H[state_index<T, MI>(C, m, r, c)]; };
+    auto zat = [&](int r, int c) -> T { return C.z[(size_t)r * nx + c]; };
+    // inflow link ids in the order N (c), S (nx + c), W (2 nx + r), E (2 nx + ny + r)
+    auto inflow = [&](int i) -> bool { return C.inflow_id && C.inflow_id[i] >= 0; };
+    uint8_t w = 0;
+    if (e < nxl) {
+        const int r = (int)(e / (nx + 1)), c = (int)(e % (nx + 1));
+        if (c == 0)
+            w = C.edge_open[3] && !inflow(2 * nx + r) && hat(r, 0) > hdry;
+        else if (c == nx)
+            w = C.edge_open[1] && !inflow(2 * nx + ny + r) && hat(r, nx - 1) > hdry;
+        else
+            w = link_depth(hat(r, c - 1), hat(r, c), zat(r, c) - zat(r, c - 1)) > hdry;
+        wx[e] = w;
+    } else {
+        const size_t f = e - nxl;
+        const int r = (int)(f / nx), c = (int)(f % nx);
+        if (r == 0)
+            w = C.edge_open[0] && !inflow(c) && hat(0, c) > hdry;
+        else if (r == ny)
+            w = C.edge_open[2] && !inflow(nx + c) && hat(ny - 1, c) > hdry;
+        else
+            w = link_depth(hat(r - 1, c), hat(r, c), zat(r, c) - zat(r - 1, c)) > hdry;
+        wy[f] = w;
+    }
+}
+
+template <typename T>
+void launch_wetmask(int mi, const CatchDev<T>& C, int member, int p, uint8_t* wx, uint8_t* wy, hipStream_t s) {
+    const size_t n = (size_t)C.ny * (C.nx + 1) + (size_t)(C.ny + 1) * C.nx;
+    dim3 grid((unsigned)((n + 255) / 256));
+    switch (mi) {
+        case 1: hipLaunchKernelGGL((k_wetmask<T, 1>), grid, dim3(256), 0, s, C, member, p, wx, wy); break;
+        case 2: hipLaunchKernelGGL((k_wetmask<T, 2>), grid, dim3(256), 0, s, C, member, p, wx, wy); break;
+        case 4: hipLaunchKernelGGL((k_wetmask<T, 4>), grid, dim3(256), 0, s, C, member, p, wx, wy); break;
+        default: hipLaunchKernelGGL((k_wetmask<T, 8>), grid, dim3(256), 0, s, C, member, p, wx, wy); break;
+    }
+}
+
 // Observation operator: depth of every member at every gauge cell, [N*K].
 template <typename T, int MI>
 __global__ __launch_bounds__(256) void k_gauges(const CatchDev<T> C, const int32_t* par, int K, const int32_t* grc,
@@ -619,6 +694,8 @@ template void launch_get_field<float>(int, const CatchDev<float>&, int, int, int
 template void launch_get_field<double>(int, const CatchDev<double>&, int, int, int, double*, hipStream_t);
 template void launch_set_field<float>(int, const CatchDev<float>&, int, int, int, const double*, hipStream_t);
 template void launch_set_field<double>(int, const CatchDev<double>&, int, int, int, const double*, hipStream_t);
+template void launch_wetmask<float>(int, const CatchDev<float>&, int, int, uint8_t*, uint8_t*, hipStream_t);
+template void launch_wetmask<double>(int, const CatchDev<double>&, int, int, uint8_t*, uint8_t*, hipStream_t);
 template void launch_gauges<float>(int, const CatchDev<float>&, const int32_t*, int, const int32_t*, double*, int,
                                    hipStream_t);
 template void launch_gauges<double>(int, const CatchDev<double>&, const int32_t*, int, const int32_t*, double*, int,
@@ -770,7 +847,7 @@ __global__ __launch_bounds__(kBlock) void k_march(const StepLaunch<T> L) {
                 else
                     fS = C.edge_open[2] ? link_open(qS, h0, gb, C.edge_slope[2], m, hdry) : T(0);
                 const T dv = ((fW - fE) + fN[s]) - fS;
-                T hn = (h0 + m.dtdx * dv) + m.rinc;
+                T hn = depth_add(h0, m.dtdx * dv + m.rinc, m.seed, (uint32_t)(r * nx + x));
                 if (hn < T(0)) {
                     atomicAdd(&L.vclamp[C.member_off + k], -(double)hn * (C.dx * C.dx));
                     hn = T(0);
@@ -1097,7 +1174,7 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
             const T dv = ((fW[j] - fE[j]) + fN[j]) - fS[j];
             const uint32_t kc = (ccw >> (8 * j)) & 0xffu;
             const T rn = lc ? ms.rinc * runoff(kc) : ms.rinc;
-            T hn = (hc[j] + ms.dtdx * dv) + rn;
+            T hn = depth_add(hc[j], ms.dtdx * dv + rn, ms.seed, (uint32_t)(r * nx + xl + j));
             cf[j] = hn < T(0);
             vcl += (own && hn < T(0)) ? -hn : T(0);
             hn = (hn < T(0)) ? T(0) : hn;

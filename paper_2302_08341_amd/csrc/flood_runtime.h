@@ -13,7 +13,10 @@ namespace flood {
 
 struct ImplBase {
     virtual ~ImplBase() {}
-    virtual flood_status step(double t_end, std::string& err) = 0;
+    virtual flood_status step(double t_end, int64_t max_steps, std::string& err) = 0;
+    virtual flood_status get_wet_mask(int c, int m, uint8_t* wx, uint8_t* wy, std::string& err) = 0;
+    virtual flood_status log_steps(int32_t cap, std::string& err) = 0;
+    virtual flood_status get_step_log(int c, double* dt, double* te, int64_t* count, std::string& err) = 0;
     virtual flood_status assimilate(int c, int K, const int32_t* grc, const double* obs, const double* sigma,
                                     int with_sections, double alpha, double neff_frac, double u0,
                                     const double* beta, double* neff_out, int32_t* anc_out, int32_t* res_out,

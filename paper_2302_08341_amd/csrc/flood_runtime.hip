@@ -79,6 +79,11 @@ template <typename T> struct Impl : ImplBase {
     double *t = nullptr, *s = nullptr, *mu = nullptr, *logw = nullptr, *vrain = nullptr, *vout = nullptr,
            *vclamp = nullptr;
     int64_t* steps = nullptr;
+    int64_t* step_lim = nullptr;   // per-member step limit of the current flood_step_n call
+    // step log opened by flood_log_steps: [n_total][log_cap] lengths and end times
+    double *dtlog = nullptr, *telog = nullptr;
+    int64_t* log_n = nullptr;
+    int32_t log_cap = 0;
     double *clsn = nullptr, *drain = nullptr, *vdrain = nullptr;   // land cover per member; drained volume
     double* vin = nullptr;    // inflow volume per member
     bool any_land = false;
@@ -180,6 +185,8 @@ template <typename T> struct Impl : ImplBase {
             if (e) (void)hipEventDestroy(e);
         for (auto e : tev) (void)hipEventDestroy(e);
         for (void* p : allocs) (void)hipFree(p);
+        if (dtlog) (void)hipFree(dtlog);
+        if (telog) (void)hipFree(telog);
         if (h_tend) (void)hipHostFree(h_tend);
         if (h_count) (void)hipHostFree(h_count);
         if (own_stream) (void)hipStreamDestroy(own_stream);
@@ -491,6 +498,8 @@ template <typename T> struct Impl : ImplBase {
         CHK(dalloc(&vout, n_total, err));
         CHK(dalloc(&vclamp, n_total, err));
         CHK(dalloc(&steps, n_total, err));
+        CHK(dalloc(&step_lim, n_total, err));
+        CHK(dalloc(&log_n, n_total, err));
         CHK(dalloc(&clsn, (size_t)n_total * kMaxClasses, err));
         CHK(dalloc(&drain, n_total, err));
         CHK(dalloc(&vdrain, n_total, err));
@@ -532,6 +541,8 @@ template <typename T> struct Impl : ImplBase {
         HIPCHK(hipMemsetAsync(vdrain, 0, n_total * sizeof(double), st));
         HIPCHK(hipMemsetAsync(vin, 0, n_total * sizeof(double), st));
         HIPCHK(hipMemsetAsync(steps, 0, n_total * sizeof(int64_t), st));
+        HIPCHK(hipMemsetAsync(log_n, 0, n_total * sizeof(int64_t), st));
+        launch_step_limit(n_total, steps, -1, step_lim, st);
         HIPCHK(hipMemsetAsync(par, 0, n_total * sizeof(int32_t), st));
         HIPCHK(hipMemsetAsync(fault, 0, n_total * sizeof(int32_t), st));
         HIPCHK(hipMemsetAsync(status, 0, sizeof(int32_t), st));
@@ -552,6 +563,7 @@ template <typename T> struct Impl : ImplBase {
         CHK(dalloc(&d_stage, stage_elems, err));
         HIPCHK(hipHostMalloc((void**)&h_tend, sizeof(double), hipHostMallocDefault));
         HIPCHK(hipHostMalloc((void**)&h_count, 4 * sizeof(int32_t), hipHostMallocDefault));
+        std::memset(h_count, 0, 4 * sizeof(int32_t));
         HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
 
@@ -606,7 +618,9 @@ template <typename T> struct Impl : ImplBase {
         PL.ms = ms;
         PL.dtlog = nullptr;
         PL.telog = nullptr;
+        PL.log_n = log_n;
         PL.dtlog_cap = 0;
+        PL.step_lim = step_lim;
         PL.clsn = any_land ? clsn : nullptr;
         PL.drain = any_land ? drain : nullptr;
         PL.m_begin = 0;
@@ -903,17 +917,20 @@ template <typename T> struct Impl : ImplBase {
                 }
             }
         }
-        launch_count_active(n_total, t, fault, d_tend, status, d_count, st);
+        launch_count_active(n_total, t, fault, d_tend, status, steps, step_lim, d_count, st);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(h_count + 2 * slot, d_count, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
         HIPCHK(hipEventRecord(ev[slot], st));
         return FLOOD_OK;
     }
 
-    flood_status step(double t_end, std::string& err) override {
+    flood_status step(double t_end, int64_t max_steps, std::string& err) override {
         CHK(ensure_graph(err));
+        // a status word is only read for batches launched by this call
+        std::memset(h_count, 0, 4 * sizeof(int32_t));
         *h_tend = t_end;
         HIPCHK(hipMemcpyAsync(d_tend, h_tend, sizeof(double), hipMemcpyHostToDevice, st));
+        launch_step_limit(n_total, steps, max_steps, step_lim, st);
         // the first batch runs alone (a call that needs a single batch launches nothing
         // more); after that two batches are kept in flight
         CHK(launch_batch(0, err));
@@ -947,6 +964,7 @@ template <typename T> struct Impl : ImplBase {
             }
             tev_used = 0;
         }
+        // status words of the batches this call launched (slot 1 only when more than one batch ran)
         const int stat = h_count[2 * (slot ^ 1) + 1] | h_count[2 * slot + 1];
         if (stat) {
             err = "a member produced a non-finite depth and was frozen";
@@ -1169,6 +1187,68 @@ template <typename T> struct Impl : ImplBase {
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(out, d_stage, field_size(C, which) * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        return FLOOD_OK;
+    }
+
+    // wet/dry decision of every link of one member for its next step
+    flood_status get_wet_mask(int c, int m, uint8_t* wx, uint8_t* wy, std::string& err) override {
+        CHK(check_catch(c, err));
+        const Cat& C = cats[c];
+        if (m < 0 || m >= C.N) { err = "member index out of range"; return FLOOD_EINVAL; }
+        if (!wx || !wy) { err = "wet_x and wet_y are required"; return FLOOD_EINVAL; }
+        int p;
+        CHK(member_parity(C.dev.member_off + m, &p, err));
+        const size_t nxl = (size_t)C.ny * (C.nx + 1), nyl = (size_t)(C.ny + 1) * C.nx;
+        uint8_t* d = reinterpret_cast<uint8_t*>(d_stage);   // stage_elems doubles >= nxl + nyl bytes
+        launch_wetmask<T>(mi, C.dev, m, p, d, d + nxl, st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(wx, d, nxl, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(wy, d + nxl, nyl, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return FLOOD_OK;
+    }
+
+    // step log: capacity entries per member, counters restarted; 0 closes it
+    flood_status log_steps(int32_t cap, std::string& err) override {
+        HIPCHK(hipStreamSynchronize(st));
+        if (dtlog) (void)hipFree(dtlog);
+        if (telog) (void)hipFree(telog);
+        dtlog = telog = nullptr;
+        log_cap = 0;
+        if (cap > 0) {
+            const size_t n = (size_t)n_total * cap * sizeof(double);
+            if (hipMalloc((void**)&dtlog, n) != hipSuccess || hipMalloc((void**)&telog, n) != hipSuccess) {
+                (void)hipGetLastError();
+                if (dtlog) (void)hipFree(dtlog);
+                dtlog = nullptr;
+                telog = nullptr;
+                err = "hipMalloc of the step log failed";
+                PL.dtlog = PL.telog = nullptr;
+                PL.dtlog_cap = 0;
+                invalidate_graph();
+                return FLOOD_ENOMEM;
+            }
+            log_cap = cap;
+        }
+        HIPCHK(hipMemsetAsync(log_n, 0, n_total * sizeof(int64_t), st));
+        PL.dtlog = dtlog;
+        PL.telog = telog;
+        PL.dtlog_cap = log_cap;
+        invalidate_graph();   // the captured planner carries the log pointers
+        HIPCHK(hipStreamSynchronize(st));
+        return FLOOD_OK;
+    }
+
+    flood_status get_step_log(int c, double* dt_out, double* te_out, int64_t* count_out, std::string& err) override {
+        CHK(check_catch(c, err));
+        const Cat& C = cats[c];
+        if (log_cap == 0) { err = "no step log is open (flood_log_steps)"; return FLOOD_ESTATE; }
+        const int off = C.dev.member_off;
+        const size_t n = (size_t)C.N * log_cap;
+        HIPCHK(hipStreamSynchronize(st));
+        if (dt_out) HIPCHK(hipMemcpy(dt_out, dtlog + (size_t)off * log_cap, n * sizeof(double), hipMemcpyDeviceToHost));
+        if (te_out) HIPCHK(hipMemcpy(te_out, telog + (size_t)off * log_cap, n * sizeof(double), hipMemcpyDeviceToHost));
+        if (count_out) HIPCHK(hipMemcpy(count_out, log_n + off, C.N * sizeof(int64_t), hipMemcpyDeviceToHost));
         return FLOOD_OK;
     }
 
@@ -1773,6 +1853,9 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
         SLg.total_blocks = SLg.c[0].n_blocks;
         SLg.recompute = 0;
         PlanLaunch<T> PLg = PL;
+        PLg.step_lim = nullptr;
+        PLg.dtlog = nullptr;
+        PLg.telog = nullptr;
         PLg.m_begin = off + g0;
         PLg.m_end = off + g0 + Gg;
         if (march_adj) {
@@ -1821,7 +1904,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                         launch_marchv<T>(SLm, march_nt, march_pf, 0, tw, st);
                         ++L;
                     }
-                    launch_count_active(Gg, t + off + g0, fault + off + g0, d_tend, status, d_count, st);
+                    launch_count_active(Gg, t + off + g0, fault + off + g0, d_tend, status, nullptr, nullptr, d_count, st);
                     HIPCHK(hipGetLastError());
                     HIPCHK(hipMemcpyAsync(h_count, d_count, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
                     HIPCHK(hipStreamSynchronize(st));
@@ -1937,7 +2020,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                     launch_step_mi<T>(mi, SLg, st);
                     ++L;
                 }
-                launch_count_active(Gg, t + off + g0, fault + off + g0, d_tend, status, d_count, st);
+                launch_count_active(Gg, t + off + g0, fault + off + g0, d_tend, status, nullptr, nullptr, d_count, st);
                 HIPCHK(hipGetLastError());
                 HIPCHK(hipMemcpyAsync(h_count, d_count, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
                 HIPCHK(hipStreamSynchronize(st));

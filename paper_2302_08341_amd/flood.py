@@ -24,9 +24,9 @@ EXPORTED = ["flood_create", "flood_create_batch", "flood_step", "flood_assimilat
             "flood_get_field", "flood_set_state", "flood_set_params", "flood_get_ledger", "flood_get_weights",
             "flood_systematic_resample", "flood_ensemble_products", "flood_get_land_params", "flood_save",
             "flood_load", "flood_set_sections", "flood_get_sections", "flood_assimilate_obs",
-            "flood_get_config", "flood_timing", "flood_get_timing", "flood_adjoint_release", "flood_last_error",
-            "flood_strerror",
-            "flood_destroy"]
+            "flood_get_config", "flood_timing", "flood_get_timing", "flood_adjoint_release", "flood_step_n",
+            "flood_get_wet_mask", "flood_log_steps", "flood_get_step_log", "flood_last_error",
+            "flood_strerror", "flood_destroy"]
 
 
 class FloodError(RuntimeError):
@@ -69,6 +69,12 @@ def load_library():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libflood.so not found at %s: build it with __graft_entry__.build() or "
                            "python paper_2302_08341_amd/build.py" % LIB_PATH)
+    # torch carries its own HIP runtime; when torch is present it is loaded first, so
+    # that the library binds to the same runtime (one HIP runtime per process)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     H = C.c_void_p
     dp, ip, lp, fp = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_float)
@@ -98,6 +104,10 @@ def load_library():
         "flood_timing": [H, C.c_int32],
         "flood_get_timing": [H, dp, lp],
         "flood_adjoint_release": [H],
+        "flood_step_n": [H, C.c_double, C.c_int64],
+        "flood_get_wet_mask": [H, C.c_int32, C.c_int32, C.POINTER(C.c_uint8), C.POINTER(C.c_uint8)],
+        "flood_log_steps": [H, C.c_int32],
+        "flood_get_step_log": [H, C.c_int32, dp, dp, lp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -216,6 +226,34 @@ def flood_create(grid, params, n_members, n_scale=None, rain_mult=None, stream=N
 
 def flood_step(h, t_end):
     _check(load_library().flood_step(h, float(t_end)), h)
+
+
+def flood_step_n(h, t_end, max_steps):
+    _check(load_library().flood_step_n(h, float(t_end), int(max_steps)), h)
+
+
+def flood_get_wet_mask(h, catchment, member, ny, nx):
+    wx = np.zeros((ny, nx + 1), dtype=np.uint8)
+    wy = np.zeros((ny + 1, nx), dtype=np.uint8)
+    u8 = C.POINTER(C.c_uint8)
+    rc = load_library().flood_get_wet_mask(h, int(catchment), int(member), wx.ctypes.data_as(u8),
+                                           wy.ctypes.data_as(u8))
+    _check(rc, h)
+    return wx, wy
+
+
+def flood_log_steps(h, capacity):
+    _check(load_library().flood_log_steps(h, int(capacity)), h)
+
+
+def flood_get_step_log(h, catchment, n_members, capacity):
+    dt = np.zeros((n_members, capacity))
+    te = np.zeros((n_members, capacity))
+    cnt = np.zeros(n_members, dtype=np.int64)
+    rc = load_library().flood_get_step_log(h, int(catchment), _dp(dt), _dp(te),
+                                           cnt.ctypes.data_as(C.POINTER(C.c_int64)))
+    _check(rc, h)
+    return dt, te, cnt
 
 
 def flood_assimilate(h, catchment, gauges, obs, sigma, neff_frac=0.8, u0=0.5, beta=None, n_members=None):
@@ -434,6 +472,24 @@ class FloodEnsemble:
 
     def step(self, t_end):
         flood_step(self.h, t_end)
+
+    def step_n(self, t_end, max_steps):
+        """At most max_steps steps of every member toward t_end (flood_step_n)."""
+        flood_step_n(self.h, t_end, max_steps)
+
+    def wet_mask(self, member, catchment=0):
+        """(wet_x [ny, nx+1], wet_y [ny+1, nx]) uint8: the links' wet/dry decision for the next step."""
+        ny, nx = self.shape(catchment)
+        return flood_get_wet_mask(self.h, catchment, member, ny, nx)
+
+    def log_steps(self, capacity):
+        """Open (restart) the step log with capacity entries per member; 0 closes it."""
+        self._log_cap = int(capacity)
+        flood_log_steps(self.h, capacity)
+
+    def step_log(self, catchment=0):
+        """(dt [N, cap], t_end [N, cap], count [N]) logged since log_steps."""
+        return flood_get_step_log(self.h, catchment, self.n_members(catchment), self._log_cap)
 
     def assimilate(self, catchment, gauges, obs, sigma, neff_frac=0.8, u0=0.5, beta=None):
         return flood_assimilate(self.h, catchment, gauges, obs, sigma, neff_frac, u0, beta,

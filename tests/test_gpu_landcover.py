@@ -2,12 +2,11 @@
 per-member Manning n per class, runoff coefficient of the rain per class,
 drainage of draining classes at each member's rate, drained volume in the ledger.
 
-Bars: FP64 1e-9 m over the run; FP32 over the run within the larger of the
-bars used without land cover and the FP64 oracle's own spread under rain
-multipliers moved by +-1e-6 and +-1e-5 (the drained ground branches at h_dry);
-one step from an identical float state 1e-6 m (float wet/dry decisions on both sides); ledger
-terms 1e-4 (FP32) / 1e-10 (FP64) relative, balance 1e-6 / 1e-12.  Member
-parameters follow resampling and snapshots exactly.
+Bars: FP64 1e-9 m over the run; one step from an identical float state
+1e-6 m (float wet/dry decisions on both sides); ledger terms 1e-4 (FP32) /
+1e-10 (FP64) relative, balance 1e-6 / 1e-12.  Member parameters follow
+resampling and snapshots exactly.  The FP32 trajectory is held by replay in
+tests/test_gpu_trajectory.py.
 """
 import os
 import tempfile
@@ -15,7 +14,6 @@ import tempfile
 import numpy as np
 import pytest
 
-import trajectory as TR
 import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -70,38 +68,6 @@ def test_fp64_trajectory_and_ledger_match_oracle(fl, orc):
     assert np.all(led["drain"] > 0.0)
     resid = np.abs(led["storage"] - (led["rain_in"] - led["outflow"] + led["clamp"] - led["drain"])) / led["rain_in"]
     assert resid.max() <= 1e-12
-
-
-def test_fp32_trajectory_matches_oracle(fl, orc):
-    # With land cover most of the ground is hardened and drained, and sits near
-    # h_dry.  There the trajectory branches on when a cell crosses h_dry: the FP64
-    # oracle itself, with the rain multiplier moved by 1e-6 (the size FP32 rounding
-    # reaches over a thousand steps), moves by up to 9e-3 m and by a third of the
-    # largest section discharge.  So each FP32 distance from the oracle is held to
-    # the larger of the bar used without land cover (1e-4 m, no cell beyond it,
-    # sections and edges 1e-4) and the oracle's own spread over rain multipliers
-    # moved by +-1e-6 and +-1e-5; the ledger likewise.  The arithmetic itself is
-    # held to 1e-9 m by the FP64 run and to 1e-6 m by one FP32 step from an
-    # identical state.
-    e = _ens(fl, real_bytes=4)
-    e.step(1500.0)
-    led = e.ledger()
-    for i in range(4):
-        _, ref = _oracle(orc, i, 1500.0)
-        runs = {}
-
-        def run(f):
-            runs[f] = _oracle(orc, i, 1500.0, mu_factor=f)[1]
-            return runs[f]
-        sp = TR.spread(run, ref, CAT.dx)
-        dspread = max(abs(p.v_drain - ref.v_drain) / ref.v_drain for p in runs.values())
-        got = TR.divergence(e.field(i), e.field(i, fl.FIELD_QX), e.field(i, fl.FIELD_QY), ref, CAT.dx)
-        print("member", i, "GPU FP32", got, "oracle spread", sp, flush=True)
-        assert np.all(got <= np.maximum(TR.TIGHT, sp))
-        assert led["drain"][i] == pytest.approx(ref.v_drain, rel=max(1e-4, dspread))
-        assert led["rain_in"][i] == pytest.approx(ref.v_rain, rel=1e-6)
-    resid = np.abs(led["storage"] - (led["rain_in"] - led["outflow"] + led["clamp"] - led["drain"])) / led["rain_in"]
-    assert resid.max() <= 1e-6
 
 
 def test_one_step_from_an_identical_float_state(fl, orc):
