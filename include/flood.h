@@ -212,11 +212,20 @@ flood_status flood_assimilate(flood_handle* h, int32_t catchment, int32_t n_gaug
  * S = floor((t_end - t0)/sample_dt), over the members of one catchment that
  * are all at time t0, with respect to the catchment's shared Manning field
  * (grad_n_out, host [ny*nx]) and each member's rain multiplier
- * (grad_mult_out, host [N]).  The forward run records its step lengths and
- * stores a checkpoint every ckpt_every steps; the reverse sweep recomputes
- * each segment into a tape and applies the discrete adjoint of the step with
- * those step lengths and the forward's wet/dry, limiter and clamp branches
- * held fixed.  On return the members are at the last sample time.
+ * (grad_mult_out, host [N]).  The members are taken in groups that fit the
+ * device memory.  The forward run of a group records every step of every
+ * member, its length and its state, in a tape of ckpt_every + 1 states per
+ * member; when a member has taken ckpt_every steps the segment ends and the
+ * group's states become a checkpoint.  The reverse sweep applies the discrete
+ * adjoint of the step with the recorded step lengths and the forward's
+ * wet/dry, limiter and clamp branches held fixed: the last segment straight
+ * from the tape, each earlier one after recomputing it from its checkpoint.
+ * A ckpt_every at least the members' step count therefore means no
+ * recomputation, at the price of tape memory (and smaller groups).  The loss
+ * and the rain-multiplier gradients do not depend on ckpt_every; the Manning
+ * field's only through the single-precision rounding of its accumulation (the
+ * contributions of four members are added together per reverse step).  On
+ * return the members are at the last sample time.
  *   obs host [S*n_gauges]; loss_out, grad_n_out, grad_mult_out may be NULL.
  * Errors: EINVAL, ENOMEM (tape does not fit), ESTATE, ENUMERIC, EHIP. */
 flood_status flood_adjoint(flood_handle* h, int32_t catchment, double t_end, double sample_dt,
@@ -327,6 +336,13 @@ flood_status flood_ensemble_products(flood_handle* h, int32_t catchment, double 
  * ledger to a file (portable only between handles of identical shape). */
 flood_status flood_save(flood_handle* h, const char* path);
 flood_status flood_load(flood_handle* h, const char* path);
+
+/* Memory plan of the last flood_adjoint call on the handle: member groups,
+ * members per group, and tape segments summed over the groups (segments beyond
+ * one per group were recomputed from checkpoints).  Any output may be NULL;
+ * zeros before the first call. */
+flood_status flood_get_adjoint_info(const flood_handle* h, int32_t* groups, int32_t* group_size,
+                                    int32_t* segments);
 
 /* Kernel configuration in use: member interleave, tile rows and chunks per
  * workgroup of catchment 0, the number of steps captured per graph, the step

@@ -399,6 +399,12 @@ flood_status flood_adjoint_release(flood_handle* h) {
     return h->impl->adjoint_release(h->err);
 }
 
+flood_status flood_get_adjoint_info(const flood_handle* h, int32_t* groups, int32_t* group_size, int32_t* segments) {
+    if (!h || !h->impl) return FLOOD_EINVAL;
+    h->impl->get_adjoint_info(groups, group_size, segments);
+    return FLOOD_OK;
+}
+
 flood_status flood_timing(flood_handle* h, int32_t enable) {
     FLOOD_NEED_HANDLE(h);
     return h->impl->timing(enable != 0, h->err);

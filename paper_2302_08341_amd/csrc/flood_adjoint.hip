@@ -9,6 +9,8 @@
 // member's rain multiplier.  It is written in gather form: every lane owns one
 // (cell, member), recomputes the four links around its cell from the tape and
 // collects their contributions, so nothing is scattered with atomics.
+#include <algorithm>
+
 #include "flood_device.h"
 
 namespace flood {
@@ -305,27 +307,40 @@ __device__ __forceinline__ void le_load(const T* lh, const uint8_t* cl, T (&d)[V
     for (int j = 0; j < V; ++j) d[j] = ((f >> (8 * j)) & 0xffu) ? T(0) : v[j];
 }
 
-// Reverse step in row-march form.  Geometry as the forward row march: one
-// wavefront per (strip of 62 V cells, member), marching down the strip's rows;
-// lanes 0 and 63 are halo lanes.  Per row each lane evaluates the derivatives
-// of the east and south links of its V cells once; the west link of its first
-// cell comes from the neighbouring lane and the north link from the previous
-// row, so every link is differentiated once per step.  Contributions to a
-// cell's depth adjoint are added in the order east, south, west, north (as in
-// k_adj).  The Manning-field adjoint of each cell is accumulated per member
-// (no atomics) and the rain-multiplier adjoint per (strip, member).
+// Reverse step in row-march form.  Geometry as the forward row march: a
+// wavefront marches a strip of 62 V cells down its rows for one member; lanes
+// 0 and 63 are halo lanes.  A workgroup holds the four members of a member
+// quad on the same strip (wavefront w: member 4u + w), so their contributions
+// to the shared Manning-field adjoint are added in LDS, member by member in
+// that order, and the quad's accumulator in HBM is read and written once per
+// cell and step: 2 B per member-cell update instead of 8 with one accumulator
+// per member.  Per row each lane evaluates the derivatives of the east and
+// south links of its V cells once; the west link of its first cell comes from
+// the neighbouring lane and the north link from the previous row, so every
+// link is differentiated once per step.  Contributions to a cell's depth
+// adjoint are added in the order east, south, west, north (as in k_adj).  The
+// rain-multiplier adjoint is accumulated per (strip, member).  Members that do
+// not step in this launch (or pad the last quad) skip the march and keep their
+// adjoint in place, but still meet the workgroup barrier.
 template <typename T, int V>
 __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
+    extern __shared__ unsigned char adj_lds[];
     const CatchDev<T>& C = A.c;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int wg = xcd_remap(blockIdx.x, gridDim.x) * (kBlock / 64) + wave;
-    if (wg >= C.n_waves) return;
-    int k, sx, sy;
-    if (!march_wave(C, wg, C.n_members, k, sx, sy)) return;
-    const MemberStep<T> ms = A.ms[k];
-    if (!ms.active) return;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int nq = (C.n_members + 3) / 4;
+    int u, sx, sy;
+    if (!march_wave(C, b, nq, u, sx, sy)) return;   // uniform over the workgroup
+    const int k = 4 * u + wave;
+    bool actq[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) actq[w] = 4 * u + w < C.n_members && A.ms[4 * u + w].active;
+    const bool act = actq[wave];
     const int nx = C.nx, ny = C.ny;
+    const int rows = C.march_rows;
+    // this wavefront's Manning contributions, [row][lane][V]
+    T* NL = reinterpret_cast<T*>(adj_lds) + (size_t)wave * rows * 64 * V;
     const int xl = sx * (62 * V) - V + V * lane;
     const bool inx = xl >= 0 && xl < nx;
     const bool own = lane >= 1 && lane <= 62 && inx;
@@ -335,206 +350,231 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
     const int r0 = sy * C.march_rows;
     const int r1 = min(r0 + C.march_rows, ny);
     const size_t plane = (size_t)ny * nx;
-    const size_t so = (size_t)ms.slot * A.slot_stride;
-    const T* __restrict__ H = C.h[0] + so + (size_t)k * plane;
-    const T* __restrict__ QX = C.qx[0] + so + (size_t)k * plane;
-    const T* __restrict__ QY = C.qy[0] + so + (size_t)k * plane;
-    const T* __restrict__ QWs = C.qw[0] + so + (size_t)k * ny;
-    const T* __restrict__ QNs = C.qn[0] + so + (size_t)k * nx;
-    const uint8_t* __restrict__ CL = A.clamp + (size_t)ms.slot * A.clamp_stride + (size_t)k * plane;
-    const int lp = A.lpar[k];
-    const T* __restrict__ LH = A.lh[lp] + (size_t)k * plane;
-    const T* __restrict__ LQX = A.lqx[lp] + (size_t)k * plane;
-    const T* __restrict__ LQY = A.lqy[lp] + (size_t)k * plane;
-    const T* __restrict__ LQWs = A.lqw[lp] + (size_t)k * ny;
-    const T* __restrict__ LQNs = A.lqn[lp] + (size_t)k * nx;
-    T* __restrict__ LHo = A.lh[lp ^ 1] + (size_t)k * plane;
-    T* __restrict__ LQXo = A.lqx[lp ^ 1] + (size_t)k * plane;
-    T* __restrict__ LQYo = A.lqy[lp ^ 1] + (size_t)k * plane;
-    T* __restrict__ LQWo = A.lqw[lp ^ 1] + (size_t)k * ny;
-    T* __restrict__ LQNo = A.lqn[lp ^ 1] + (size_t)k * nx;
-    T* __restrict__ NA = A.nacc + (size_t)k * plane;
-    const T* __restrict__ Z = C.z;
-    const T* __restrict__ Nn = C.n;
-    const T g = C.g, hdry = C.hdry, kk = ms.dtdx;
+    if (act) {
+        const MemberStep<T> ms = A.ms[k];
+        const size_t so = (size_t)ms.slot * A.slot_stride;
+        const T* __restrict__ H = C.h[0] + so + (size_t)k * plane;
+        const T* __restrict__ QX = C.qx[0] + so + (size_t)k * plane;
+        const T* __restrict__ QY = C.qy[0] + so + (size_t)k * plane;
+        const T* __restrict__ QWs = C.qw[0] + so + (size_t)k * ny;
+        const T* __restrict__ QNs = C.qn[0] + so + (size_t)k * nx;
+        const uint8_t* __restrict__ CL = A.clamp + (size_t)ms.slot * A.clamp_stride + (size_t)k * plane;
+        const int lp = A.lpar[k];
+        const T* __restrict__ LH = A.lh[lp] + (size_t)k * plane;
+        const T* __restrict__ LQX = A.lqx[lp] + (size_t)k * plane;
+        const T* __restrict__ LQY = A.lqy[lp] + (size_t)k * plane;
+        const T* __restrict__ LQWs = A.lqw[lp] + (size_t)k * ny;
+        const T* __restrict__ LQNs = A.lqn[lp] + (size_t)k * nx;
+        T* __restrict__ LHo = A.lh[lp ^ 1] + (size_t)k * plane;
+        T* __restrict__ LQXo = A.lqx[lp ^ 1] + (size_t)k * plane;
+        T* __restrict__ LQYo = A.lqy[lp ^ 1] + (size_t)k * plane;
+        T* __restrict__ LQWo = A.lqw[lp ^ 1] + (size_t)k * ny;
+        T* __restrict__ LQNo = A.lqn[lp ^ 1] + (size_t)k * nx;
+        const T* __restrict__ Z = C.z;
+        const T* __restrict__ Nn = C.n;
+        const T g = C.g, hdry = C.hdry, kk = ms.dtdx;
 
-    size_t ca = (size_t)r0 * nx + xa;
-    T hc[V], zc[V], nc[V], lec[V], pNh[V], pNn[V];
-    vload<T, V>(H + ca, hc);
-    vload<T, V>(Z + ca, zc);
-    vload<T, V>(Nn + ca, nc);
-    le_load<T, V>(LH + ca, CL + ca, lec);
-    if (r0 > 0) {
-        // the south links of the row above the strip feed its first row's north links
-        T hN[V], zN[V], nN[V], qN[V], lqN[V], leN[V];
-        vload<T, V>(H + ca - nx, hN);
-        vload<T, V>(Z + ca - nx, zN);
-        vload<T, V>(Nn + ca - nx, nN);
-        vload<T, V>(QY + ca - nx, qN);
-        vload<T, V>(LQY + ca - nx, lqN);
-        le_load<T, V>(LH + ca - nx, CL + ca - nx, leN);
-#pragma unroll
-        for (int j = 0; j < V; ++j) {
-            const T nf = T(0.5) * (nN[j] + nc[j]);
-            T dq, d1, d2, cn;
-            link_in_d(qN[j], hN[j], hc[j], zc[j] - zN[j], g * (nf * nf), g * nf, ms, hdry, dq, d1, d2, cn);
-            const T lt = lqN[j] + kk * (lec[j] - leN[j]);
-            pNh[j] = lt * d2;
-            pNn[j] = lt * cn;
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < V; ++j) pNh[j] = pNn[j] = T(0);
-    }
-    double lsum = 0.0;
-    for (int r = r0; r < r1; ++r) {
-        const bool hasS = r + 1 < ny;
-        const size_t cs = hasS ? ca + nx : ca;
-        T qE[V], qS[V], lqE[V], lqS[V], hs[V], zs[V], ns[V], les[V];
-        vload<T, V>(QX + ca, qE);
-        vload<T, V>(QY + ca, qS);
-        vload<T, V>(LQX + ca, lqE);
-        vload<T, V>(LQY + ca, lqS);
-        vload<T, V>(H + cs, hs);
-        vload<T, V>(Z + cs, zs);
-        vload<T, V>(Nn + cs, ns);
-        le_load<T, V>(LH + cs, CL + cs, les);
-        // east neighbour of the lane's last cell = first cell of the next lane
-        const T hE = __shfl_down(hc[0], 1, 64);
-        const T zE = __shfl_down(zc[0], 1, 64);
-        const T nE = __shfl_down(nc[0], 1, 64);
-        const T leE = __shfl_down(lec[0], 1, 64);
-        T ltE[V], dqE[V], d1E[V], d2E[V], cnE[V];
-#pragma unroll
-        for (int j = 0; j < V; ++j) {
-            const T h2 = (j + 1 < V) ? hc[j + 1] : hE;
-            const T z2 = (j + 1 < V) ? zc[j + 1] : zE;
-            const T n2 = (j + 1 < V) ? nc[j + 1] : nE;
-            const T le2 = (j + 1 < V) ? lec[j + 1] : leE;
-            const T nf = T(0.5) * (nc[j] + n2);
-            link_in_d(qE[j], hc[j], h2, z2 - zc[j], g * (nf * nf), g * nf, ms, hdry, dqE[j], d1E[j], d2E[j], cnE[j]);
-            ltE[j] = lqE[j] + kk * (le2 - lec[j]);
-        }
-        if (eastw) {
-#pragma unroll
+        size_t ca = (size_t)r0 * nx + xa;
+        T hc[V], zc[V], nc[V], lec[V], pNh[V], pNn[V];
+        vload<T, V>(H + ca, hc);
+        vload<T, V>(Z + ca, zc);
+        vload<T, V>(Nn + ca, nc);
+        le_load<T, V>(LH + ca, CL + ca, lec);
+        if (r0 > 0) {
+            // the south links of the row above the strip feed its first row's north links
+            T hN[V], zN[V], nN[V], qN[V], lqN[V], leN[V];
+            vload<T, V>(H + ca - nx, hN);
+            vload<T, V>(Z + ca - nx, zN);
+            vload<T, V>(Nn + ca - nx, nN);
+            vload<T, V>(QY + ca - nx, qN);
+            vload<T, V>(LQY + ca - nx, lqN);
+            le_load<T, V>(LH + ca - nx, CL + ca - nx, leN);
+    #pragma unroll
             for (int j = 0; j < V; ++j) {
-                if (xl + j + 1 != nx) continue;
-                d2E[j] = T(0);
-                if (C.edge_open[1]) {
-                    link_open_d(qE[j], hc[j], g * (nc[j] * nc[j]), T(2) * g * nc[j], C.edge_slope[1], ms, hdry,
-                                dqE[j], d1E[j], cnE[j]);
-                    ltE[j] = lqE[j] - kk * lec[j];
-                } else {
-                    dqE[j] = d1E[j] = cnE[j] = ltE[j] = T(0);
-                }
-            }
-        }
-        // west link of the first cell: the previous lane's last east link
-        const T wH = __shfl_up(ltE[V - 1] * d2E[V - 1], 1, 64);
-        const T wN = __shfl_up(ltE[V - 1] * cnE[V - 1], 1, 64);
-        // south links
-        T ltS[V], dqS[V], d1S[V], d2S[V], cnS[V];
-        if (hasS) {
-#pragma unroll
-            for (int j = 0; j < V; ++j) {
-                const T nf = T(0.5) * (nc[j] + ns[j]);
-                link_in_d(qS[j], hc[j], hs[j], zs[j] - zc[j], g * (nf * nf), g * nf, ms, hdry, dqS[j], d1S[j],
-                          d2S[j], cnS[j]);
-                ltS[j] = lqS[j] + kk * (les[j] - lec[j]);
+                const T nf = T(0.5) * (nN[j] + nc[j]);
+                T dq, d1, d2, cn;
+                link_in_d(qN[j], hN[j], hc[j], zc[j] - zN[j], g * (nf * nf), g * nf, ms, hdry, dq, d1, d2, cn);
+                const T lt = lqN[j] + kk * (lec[j] - leN[j]);
+                pNh[j] = lt * d2;
+                pNn[j] = lt * cn;
             }
         } else {
-#pragma unroll
+    #pragma unroll
+            for (int j = 0; j < V; ++j) pNh[j] = pNn[j] = T(0);
+        }
+        double lsum = 0.0;
+        for (int r = r0; r < r1; ++r) {
+            const bool hasS = r + 1 < ny;
+            const size_t cs = hasS ? ca + nx : ca;
+            T qE[V], qS[V], lqE[V], lqS[V], hs[V], zs[V], ns[V], les[V];
+            vload<T, V>(QX + ca, qE);
+            vload<T, V>(QY + ca, qS);
+            vload<T, V>(H + cs, hs);
+            vload<T, V>(LQX + ca, lqE);
+            vload<T, V>(LQY + ca, lqS);
+            vload<T, V>(Z + cs, zs);
+            vload<T, V>(Nn + cs, ns);
+            le_load<T, V>(LH + cs, CL + cs, les);
+            // east neighbour of the lane's last cell = first cell of the next lane
+            const T hE = __shfl_down(hc[0], 1, 64);
+            const T zE = __shfl_down(zc[0], 1, 64);
+            const T nE = __shfl_down(nc[0], 1, 64);
+            const T leE = __shfl_down(lec[0], 1, 64);
+            T ltE[V], dqE[V], d1E[V], d2E[V], cnE[V];
+    #pragma unroll
             for (int j = 0; j < V; ++j) {
-                d2S[j] = T(0);
-                if (C.edge_open[2]) {
-                    link_open_d(qS[j], hc[j], g * (nc[j] * nc[j]), T(2) * g * nc[j], C.edge_slope[2], ms, hdry,
-                                dqS[j], d1S[j], cnS[j]);
-                    ltS[j] = lqS[j] - kk * lec[j];
-                } else {
-                    dqS[j] = d1S[j] = cnS[j] = ltS[j] = T(0);
+                const T h2 = (j + 1 < V) ? hc[j + 1] : hE;
+                const T z2 = (j + 1 < V) ? zc[j + 1] : zE;
+                const T n2 = (j + 1 < V) ? nc[j + 1] : nE;
+                const T le2 = (j + 1 < V) ? lec[j + 1] : leE;
+                const T nf = T(0.5) * (nc[j] + n2);
+                link_in_d(qE[j], hc[j], h2, z2 - zc[j], g * (nf * nf), g * nf, ms, hdry, dqE[j], d1E[j], d2E[j], cnE[j]);
+                ltE[j] = lqE[j] + kk * (le2 - lec[j]);
+            }
+            if (eastw) {
+    #pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    if (xl + j + 1 != nx) continue;
+                    d2E[j] = T(0);
+                    if (C.edge_open[1]) {
+                        link_open_d(qE[j], hc[j], g * (nc[j] * nc[j]), T(2) * g * nc[j], C.edge_slope[1], ms, hdry,
+                                    dqE[j], d1E[j], cnE[j]);
+                        ltE[j] = lqE[j] - kk * lec[j];
+                    } else {
+                        dqE[j] = d1E[j] = cnE[j] = ltE[j] = T(0);
+                    }
                 }
             }
-        }
-        if (own) {
-            T nh4[V], oqx4[V], oqy4[V], na4[V];
-            vload<T, V>(NA + ca, na4);
-#pragma unroll
-            for (int j = 0; j < V; ++j) {
-                const int x = xl + j;
-                const T le_c = lec[j];
-                // east, south (this cell is cell 1), west, north (cell 2), as in k_adj
-                T nh = le_c;
-                T nac = T(0);
-                nh += ltE[j] * d1E[j];
-                nac += ltE[j] * cnE[j];
-                nh += ltS[j] * d1S[j];
-                nac += ltS[j] * cnS[j];
-                if (j == 0 && westw && x == 0) {
-                    // west edge link; its strip holds -qo
-                    T oqw = T(0);
-                    if (C.edge_open[3]) {
-                        T dq, d1, cn;
-                        link_open_d(-QWs[r], hc[0], g * (nc[0] * nc[0]), T(2) * g * nc[0], C.edge_slope[3], ms,
-                                    hdry, dq, d1, cn);
-                        const T lt = LQWs[r] + kk * le_c;
-                        oqw = lt * dq;
-                        nh -= lt * d1;
-                        nac -= lt * cn;
-                    }
-                    LQWo[r] = oqw;
-                } else {
-                    nh += (j > 0) ? ltE[j - 1] * d2E[j - 1] : wH;
-                    nac += (j > 0) ? ltE[j - 1] * cnE[j - 1] : wN;
+            // west link of the first cell: the previous lane's last east link
+            const T wH = __shfl_up(ltE[V - 1] * d2E[V - 1], 1, 64);
+            const T wN = __shfl_up(ltE[V - 1] * cnE[V - 1], 1, 64);
+            // south links
+            T ltS[V], dqS[V], d1S[V], d2S[V], cnS[V];
+            if (hasS) {
+    #pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    const T nf = T(0.5) * (nc[j] + ns[j]);
+                    link_in_d(qS[j], hc[j], hs[j], zs[j] - zc[j], g * (nf * nf), g * nf, ms, hdry, dqS[j], d1S[j],
+                              d2S[j], cnS[j]);
+                    ltS[j] = lqS[j] + kk * (les[j] - lec[j]);
                 }
-                if (r > 0) {
-                    nh += pNh[j];
-                    nac += pNn[j];
-                } else {
-                    // north edge link; its strip holds -qo
-                    T oqn = T(0);
-                    if (C.edge_open[0]) {
-                        T dq, d1, cn;
-                        link_open_d(-QNs[x], hc[j], g * (nc[j] * nc[j]), T(2) * g * nc[j], C.edge_slope[0], ms,
-                                    hdry, dq, d1, cn);
-                        const T lt = LQNs[x] + kk * le_c;
-                        oqn = lt * dq;
-                        nh -= lt * d1;
-                        nac -= lt * cn;
+            } else {
+    #pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    d2S[j] = T(0);
+                    if (C.edge_open[2]) {
+                        link_open_d(qS[j], hc[j], g * (nc[j] * nc[j]), T(2) * g * nc[j], C.edge_slope[2], ms, hdry,
+                                    dqS[j], d1S[j], cnS[j]);
+                        ltS[j] = lqS[j] - kk * lec[j];
+                    } else {
+                        dqS[j] = d1S[j] = cnS[j] = ltS[j] = T(0);
                     }
-                    LQNo[x] = oqn;
                 }
-                nh4[j] = nh;
-                oqx4[j] = ltE[j] * dqE[j];
-                oqy4[j] = ltS[j] * dqS[j];
-                na4[j] += nac;
-                lsum += (double)le_c;
             }
-            vstore<T, V>(LHo + ca, nh4);
-            vstore<T, V>(LQXo + ca, oqx4);
-            vstore<T, V>(LQYo + ca, oqy4);
-            vstore<T, V>(NA + ca, na4);
+            if (own) {
+                T nh4[V], oqx4[V], oqy4[V], na4[V];
+    #pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    const int x = xl + j;
+                    const T le_c = lec[j];
+                    // east, south (this cell is cell 1), west, north (cell 2), as in k_adj
+                    T nh = le_c;
+                    T nac = T(0);
+                    nh += ltE[j] * d1E[j];
+                    nac += ltE[j] * cnE[j];
+                    nh += ltS[j] * d1S[j];
+                    nac += ltS[j] * cnS[j];
+                    if (j == 0 && westw && x == 0) {
+                        // west edge link; its strip holds -qo
+                        T oqw = T(0);
+                        if (C.edge_open[3]) {
+                            T dq, d1, cn;
+                            link_open_d(-QWs[r], hc[0], g * (nc[0] * nc[0]), T(2) * g * nc[0], C.edge_slope[3], ms,
+                                        hdry, dq, d1, cn);
+                            const T lt = LQWs[r] + kk * le_c;
+                            oqw = lt * dq;
+                            nh -= lt * d1;
+                            nac -= lt * cn;
+                        }
+                        LQWo[r] = oqw;
+                    } else {
+                        nh += (j > 0) ? ltE[j - 1] * d2E[j - 1] : wH;
+                        nac += (j > 0) ? ltE[j - 1] * cnE[j - 1] : wN;
+                    }
+                    if (r > 0) {
+                        nh += pNh[j];
+                        nac += pNn[j];
+                    } else {
+                        // north edge link; its strip holds -qo
+                        T oqn = T(0);
+                        if (C.edge_open[0]) {
+                            T dq, d1, cn;
+                            link_open_d(-QNs[x], hc[j], g * (nc[j] * nc[j]), T(2) * g * nc[j], C.edge_slope[0], ms,
+                                        hdry, dq, d1, cn);
+                            const T lt = LQNs[x] + kk * le_c;
+                            oqn = lt * dq;
+                            nh -= lt * d1;
+                            nac -= lt * cn;
+                        }
+                        LQNo[x] = oqn;
+                    }
+                    nh4[j] = nh;
+                    oqx4[j] = ltE[j] * dqE[j];
+                    oqy4[j] = ltS[j] * dqS[j];
+                    na4[j] = nac;
+                    lsum += (double)le_c;
+                }
+                vstore<T, V>(LHo + ca, nh4);
+                vstore<T, V>(LQXo + ca, oqx4);
+                vstore<T, V>(LQYo + ca, oqy4);
+    #pragma unroll
+                for (int j = 0; j < V; ++j) NL[((size_t)(r - r0) * 64 + lane) * V + j] = na4[j];
+            }
+    #pragma unroll
+            for (int j = 0; j < V; ++j) {
+                hc[j] = hs[j];
+                zc[j] = zs[j];
+                nc[j] = ns[j];
+                lec[j] = les[j];
+                pNh[j] = ltS[j] * d2S[j];
+                pNn[j] = ltS[j] * cnS[j];
+            }
+            ca += nx;
         }
+        // rain-multiplier adjoint: the depth adjoint after the step summed over the
+        // strip's cells, times R dt of the member's step
+        for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+        if (lane == 0) A.mubar_part[(size_t)(sy * C.strips_x + sx) * C.n_members + k] += lsum * A.rdt[k];
+    }
+    __syncthreads();
+    // the quad's Manning-field adjoint: wavefront w adds rows w, w + 4, ... of the
+    // strip, the contributions of the stepping members in member order
+    if (!(actq[0] || actq[1] || actq[2] || actq[3]) || !own) return;
+    T* __restrict__ NA = A.nacc + (size_t)u * plane;
+    const T* L0 = reinterpret_cast<const T*>(adj_lds);
+    for (int i = wave; i < r1 - r0; i += 4) {
+        const size_t ca = (size_t)(r0 + i) * nx + xa;
+        T na4[V];
+        vload<T, V>(NA + ca, na4);
 #pragma unroll
         for (int j = 0; j < V; ++j) {
-            hc[j] = hs[j];
-            zc[j] = zs[j];
-            nc[j] = ns[j];
-            lec[j] = les[j];
-            pNh[j] = ltS[j] * d2S[j];
-            pNn[j] = ltS[j] * cnS[j];
+            T add = T(0);
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                if (actq[w]) add += L0[(((size_t)w * rows + i) * 64 + lane) * V + j];
+            na4[j] += add;
         }
-        ca += nx;
+        vstore<T, V>(NA + ca, na4);
     }
-    // rain-multiplier adjoint: the depth adjoint after the step summed over the
-    // strip's cells, times R dt of the member's step
-    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
-    if (lane == 0) A.mubar_part[(size_t)(sy * C.strips_x + sx) * C.n_members + k] += lsum * A.rdt[k];
 }
 
-template <typename T> void launch_adjoint_march(const AdjvLaunch<T>& A, int total_waves, hipStream_t s) {
-    const int per = kBlock / 64;
-    const dim3 grid((total_waves + per - 1) / per);
-    hipLaunchKernelGGL((k_adjv<T, march_vec<T>()>), grid, dim3(kBlock), 0, s, A);
+template <typename T> void launch_adjoint_march(const AdjvLaunch<T>& A, hipStream_t s) {
+    constexpr int V = march_vec<T>();
+    const CatchDev<T>& C = A.c;
+    const int nq = (C.n_members + 3) / 4;
+    const dim3 grid(march_waves(C.strips_x, C.strips_y, nq, C.march_order, C.march_bands));
+    const size_t lds = (size_t)4 * C.march_rows * 64 * V * sizeof(T);
+    hipLaunchKernelGGL((k_adjv<T, V>), grid, dim3(kBlock), lds, s, A);
 }
 
 // One lane per member of the group.
@@ -568,6 +608,96 @@ void launch_adj_pre(int G, const MemberStep<T>* ms_prev, const MemberStep<T>* ms
     const size_t plane = (size_t)tape.ny * tape.nx;
     hipLaunchKernelGGL((k_adj_pre<T>), dim3((G + 255) / 256), dim3(256), 0, s, G, ms_prev, ms_cur, tags, K, grc, obs,
                        (const T*)tape.h[0], slot_stride, plane, tape.nx, lpar, lh0, lh1);
+}
+
+// One wavefront per member of the group.  With distinct gauge cells the lanes
+// seed one gauge each; otherwise lane 0 seeds them in order (a cell seen twice
+// takes both seeds).
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_plan(int G, int stride, int i, const int32_t* n, const MemberStep<T>* rec,
+                                                  const double* rec_rdt, const int32_t* rec_tag, int K, int distinct,
+                                                  const int32_t* grc, const double* obs, const T* tape_h,
+                                                  size_t slot_stride, size_t plane, int nx, int32_t* lpar,
+                                                  int32_t* prev, MemberStep<T>* ms_out, double* rdt_out, T* lh0,
+                                                  T* lh1) {
+    const int lane = threadIdx.x & 63;
+    const int m = blockIdx.x * (blockDim.x >> 6) + (int)(threadIdx.x >> 6);
+    if (m >= G) return;
+    int p = lpar[m];
+    const int was = prev[m];
+    if (was) p ^= 1;
+    const int j = n[m] - 1 - i;
+    if (lane == 0) {
+        lpar[m] = p;
+        prev[m] = j >= 0;
+    }
+    if (j < 0) {
+        if (lane == 0) {
+            MemberStep<T> ms{};
+            ms.active = 0;
+            ms_out[m] = ms;
+            rdt_out[m] = 0.0;
+        }
+        return;
+    }
+    const size_t r = (size_t)j * stride + m;
+    if (lane == 0) {
+        ms_out[m] = rec[r];
+        rdt_out[m] = rec_rdt[r];
+    }
+    const int smp = rec_tag[r];
+    if (K == 0 || smp < 0) return;
+    const T* h = tape_h + (size_t)(j + 1) * slot_stride + (size_t)m * plane;
+    T* lh = (p ? lh1 : lh0) + (size_t)m * plane;
+    if (distinct) {
+        for (int q = lane; q < K; q += 64) {
+            const size_t cell = (size_t)grc[2 * q] * nx + grc[2 * q + 1];
+            lh[cell] += (T)(2.0 * ((double)h[cell] - obs[(size_t)smp * K + q]));
+        }
+    } else if (lane == 0) {
+        for (int q = 0; q < K; ++q) {
+            const size_t cell = (size_t)grc[2 * q] * nx + grc[2 * q + 1];
+            lh[cell] += (T)(2.0 * ((double)h[cell] - obs[(size_t)smp * K + q]));
+        }
+    }
+}
+
+template <typename T>
+void launch_adj_plan(int G, int stride, int i, const int32_t* n, const MemberStep<T>* rec, const double* rec_rdt,
+                     const int32_t* rec_tag, int K, int distinct, const int32_t* grc, const double* obs,
+                     const T* tape_h, size_t slot_stride, size_t plane, int nx, int32_t* lpar, int32_t* prev,
+                     MemberStep<T>* ms_out, double* rdt_out, T* lh0, T* lh1, hipStream_t s) {
+    hipLaunchKernelGGL((k_adj_plan<T>), dim3((G + 3) / 4), dim3(256), 0, s, G, stride, i, n, rec, rec_rdt, rec_tag, K,
+                       distinct, grc, obs, tape_h, slot_stride, plane, nx, lpar, prev, ms_out, rdt_out, lh0, lh1);
+}
+
+// Member m of the group, element e of its plane and edge strips: tape slot
+// slot[m] -> destination copy (dpar[dst.member_off + m], or 0).  Members in planes.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tape_gather(const CatchDev<T> tape, size_t slot_stride, const int32_t* slot,
+                                                     const CatchDev<T> dst, const int32_t* dpar) {
+    const int m = blockIdx.y;
+    const size_t plane = (size_t)tape.ny * tape.nx;
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t so = (size_t)slot[m] * slot_stride;
+    const int p = dpar ? dpar[dst.member_off + m] : 0;
+    if (e < plane) {
+        const size_t i = (size_t)m * plane + e;
+        dst.h[p][i] = tape.h[0][so + i];
+        dst.qx[p][i] = tape.qx[0][so + i];
+        dst.qy[p][i] = tape.qy[0][so + i];
+    }
+    if (e < (size_t)tape.ny) dst.qw[p][(size_t)m * tape.ny + e] = tape.qw[0][so + (size_t)m * tape.ny + e];
+    if (e < (size_t)tape.nx) dst.qn[p][(size_t)m * tape.nx + e] = tape.qn[0][so + (size_t)m * tape.nx + e];
+}
+
+template <typename T>
+void launch_tape_gather(const CatchDev<T>& tape, size_t slot_stride, const int32_t* slot, const CatchDev<T>& dst,
+                        const int32_t* dpar, hipStream_t s) {
+    const size_t plane = (size_t)tape.ny * tape.nx;
+    const size_t n = std::max(plane, (size_t)std::max(tape.ny, tape.nx));
+    hipLaunchKernelGGL((k_tape_gather<T>), dim3((unsigned)((n + 255) / 256), tape.n_members), dim3(256), 0, s, tape,
+                       slot_stride, slot, dst, dpar);
 }
 
 // nbar[c] += sum over the group's members of their Manning-field adjoint
@@ -692,14 +822,26 @@ void launch_sum_parts(int n_blocks, int n_members, const double* parts, double* 
     hipLaunchKernelGGL(k_sum_parts, dim3(n_members), dim3(256), 0, s, n_blocks, n_members, parts, out);
 }
 
-template void launch_adjoint_march<float>(const AdjvLaunch<float>&, int, hipStream_t);
-template void launch_adjoint_march<double>(const AdjvLaunch<double>&, int, hipStream_t);
+template void launch_adjoint_march<float>(const AdjvLaunch<float>&, hipStream_t);
+template void launch_adjoint_march<double>(const AdjvLaunch<double>&, hipStream_t);
 template void launch_adj_pre<float>(int, const MemberStep<float>*, const MemberStep<float>*, const int32_t*, int,
                                     const int32_t*, const double*, const CatchDev<float>&, size_t, int32_t*, float*,
                                     float*, hipStream_t);
 template void launch_adj_pre<double>(int, const MemberStep<double>*, const MemberStep<double>*, const int32_t*, int,
                                      const int32_t*, const double*, const CatchDev<double>&, size_t, int32_t*,
                                      double*, double*, hipStream_t);
+template void launch_adj_plan<float>(int, int, int, const int32_t*, const MemberStep<float>*, const double*,
+                                     const int32_t*, int, int, const int32_t*, const double*, const float*, size_t,
+                                     size_t, int, int32_t*, int32_t*, MemberStep<float>*, double*, float*, float*,
+                                     hipStream_t);
+template void launch_adj_plan<double>(int, int, int, const int32_t*, const MemberStep<double>*, const double*,
+                                      const int32_t*, int, int, const int32_t*, const double*, const double*, size_t,
+                                      size_t, int, int32_t*, int32_t*, MemberStep<double>*, double*, double*, double*,
+                                      hipStream_t);
+template void launch_tape_gather<float>(const CatchDev<float>&, size_t, const int32_t*, const CatchDev<float>&,
+                                        const int32_t*, hipStream_t);
+template void launch_tape_gather<double>(const CatchDev<double>&, size_t, const int32_t*, const CatchDev<double>&,
+                                         const int32_t*, hipStream_t);
 template void launch_nacc_reduce<float>(int, size_t, const float*, double*, hipStream_t);
 template void launch_nacc_reduce<double>(int, size_t, const double*, double*, hipStream_t);
 template void launch_adjoint_step<float>(int, const AdjLaunch<float>&, hipStream_t);

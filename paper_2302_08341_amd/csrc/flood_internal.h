@@ -148,6 +148,26 @@ template <typename T> struct PlanLaunch {
     int32_t* seg_cnt;         // optional, by m - m_begin: steps taken since the last checkpoint
     const double* clsn;       // optional [n_total][kMaxClasses] land-cover Manning n per member
     const double* drain;      // optional [n_total] drainage rate per member, m/s
+    // member-local records (rec_stride > 0): the record of a member's step goes to
+    // [slot][rec_stride] + (m - m_begin), slot = its step index in the tape segment,
+    // and members that do not step write nothing
+    int32_t rec_stride;
+    // sample schedule of the adjoint's recording forward (s_dt > 0): a member's step
+    // is also clipped to its next sample time s_t0 + (smp + 1) s_dt; a step ending
+    // there carries the sample index as its tag and moves the member to the next
+    // sample.  The gauge misfit of the state after a tagged step is added to the
+    // member's loss by the member's next planner call, from its current tape slot.
+    double s_t0, s_dt;
+    int32_t* smp;             // [group] next sample index
+    int32_t* pend;            // [group] sample whose misfit is still to be taken, or -1
+    const T* tape_h;          // tape slot 0 depths: member planes, slots slot_stride apart
+    size_t slot_stride;
+    size_t plane;
+    int32_t nx;
+    int32_t n_gauges;
+    const int32_t* grc;       // [n_gauges][2]
+    const double* obs;        // [samples][n_gauges]
+    double* loss_m;           // [group] misfit per member (FP64, sample order)
 };
 
 // ---------------------------------------------------------------------------
@@ -245,10 +265,10 @@ template <typename T> struct AdjvLaunch {
     const int32_t* lpar;      // [group members] copy holding the adjoint after the step
     const MemberStep<T>* ms;  // [group members] record of this launch
     const double* rdt;        // [group members]
-    T* nacc;                  // [group members][cell] Manning-field adjoint per member (accumulated)
+    T* nacc;                  // [member quads][cell] Manning-field adjoint per quad of members (accumulated)
     double* mubar_part;       // [strips][group members] rain-multiplier adjoint partials (accumulated)
 };
-template <typename T> void launch_adjoint_march(const AdjvLaunch<T>& A, int total_waves, hipStream_t s);
+template <typename T> void launch_adjoint_march(const AdjvLaunch<T>& A, hipStream_t s);
 // before each reverse launch: flip the adjoint copy of members that stepped in
 // the previously reversed launch, then seed the gauge misfit of this launch
 template <typename T>
@@ -257,7 +277,29 @@ void launch_adj_pre(int G, const MemberStep<T>* ms_prev, const MemberStep<T>* ms
                     int32_t* lpar, T* lh0, T* lh1, hipStream_t s);
 template <typename T>
 void launch_nacc_reduce(int G, size_t ncell, const T* nacc, double* nbar, hipStream_t s);
-template <typename T> void launch_marchv_rec(const StepLaunch<T>& L, int pf, int total_waves, hipStream_t s);
+// Reverse planner of launch i of a tape segment whose member k took n[k] steps
+// (records [slot][stride], member k at k):
+// member k reverses its step j = n[k] - 1 - i (inactive when j < 0).  Flips the
+// adjoint copy index of members that stepped in the previous reverse launch,
+// writes this launch's step coefficients (ms_out, rdt_out) from the member-local
+// records, and seeds the gauge misfit of a step that completed a
+// sample, 2 (h - d), read from the tape slot after the step (distinct: no two
+// gauges share a cell, so the gauges are seeded in parallel).
+template <typename T>
+void launch_adj_plan(int G, int stride, int i, const int32_t* n, const MemberStep<T>* rec, const double* rec_rdt,
+                     const int32_t* rec_tag, int K, int distinct, const int32_t* grc, const double* obs, const T* tape_h,
+                     size_t slot_stride, size_t plane, int nx, int32_t* lpar, int32_t* prev, MemberStep<T>* ms_out,
+                     double* rdt_out, T* lh0, T* lh1, hipStream_t s);
+// Copy each member's state from its tape slot slot[m] (tape: copy-0 arrays are
+// slot 0) to dst, into copy dpar[dst.member_off + m] (dpar null: copy 0).
+template <typename T>
+void launch_tape_gather(const CatchDev<T>& tape, size_t slot_stride, const int32_t* slot, const CatchDev<T>& dst,
+                        const int32_t* dpar, hipStream_t s);
+// [0] members of the group still short of t_end, [1] status word, [2] largest seg_cnt
+void launch_count_group(int G, const double* t, const int32_t* fault, const double* t_end, const int32_t* status,
+                        const int32_t* seg_cnt, int32_t* out, hipStream_t s);
+template <typename T>
+void launch_marchv_rec(const StepLaunch<T>& L, int pf, int record, int total_waves, hipStream_t s);
 template <typename T>
 void launch_inject(int mi, const CatchDev<T>& after, const int32_t* tags, int K, const int32_t* grc,
                    const double* obs, T* lh, hipStream_t s);

@@ -16,11 +16,17 @@ namespace flood {
 // ---------------------------------------------------------------------------
 // step planner: per-member Eq. 4 step, clipped to rain-block edges and t_end
 // ---------------------------------------------------------------------------
+// One wavefront per member: lane k folds depth-maximum bin k (kBins = 64) and
+// the lanes share the gauge misfit; the plan itself is the same scalar work on
+// every lane, written out by lane 0.
 template <typename T>
 __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     using HB = typename HBits<T>::type;
-    const int m = P.m_begin + blockIdx.x * blockDim.x + threadIdx.x;
+    static_assert(kBins == 64, "one depth-maximum bin per lane");
+    const int lane = threadIdx.x & 63;
+    const int m = P.m_begin + blockIdx.x * (blockDim.x >> 6) + (int)(threadIdx.x >> 6);
     if (m >= P.m_end) return;
+    const bool w0 = lane == 0;
     int ci = 0;
     for (int i = 1; i < P.n_catch; ++i)
         if (m >= P.c[i].member_off) ci = i;
@@ -38,29 +44,49 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     const double t = P.t[m];
     const double t_end = *P.t_end;
     const int lm = m - P.m_begin;
+    if (P.pend && P.pend[lm] >= 0) {
+        // misfit of the state after the member's last step, which completed sample pend
+        const int smp = P.pend[lm];
+        const T* h = P.tape_h + (size_t)P.seg_cnt[lm] * P.slot_stride + (size_t)lm * P.plane;
+        double acc = 0.0;
+        for (int q = lane; q < P.n_gauges; q += 64) {
+            const double d = (double)h[(size_t)P.grc[2 * q] * P.nx + P.grc[2 * q + 1]] -
+                             P.obs[(size_t)smp * P.n_gauges + q];
+            acc += d * d;
+        }
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (w0) {
+            P.loss_m[lm] += acc;
+            P.pend[lm] = -1;
+        }
+    }
     if (P.fault[m] || !(t < t_end) || (P.step_lim && P.steps[m] >= P.step_lim[m])) {
-        P.ms[m] = ms;
-        if (P.ms_log) {
-            P.ms_log[lm] = ms;
-            P.rdt_log[lm] = 0.0;
-            P.tag_log[lm] = -1;
+        if (w0) {
+            P.ms[m] = ms;
+            if (P.ms_log && !P.rec_stride) {
+                P.ms_log[lm] = ms;
+                P.rdt_log[lm] = 0.0;
+                P.tag_log[lm] = -1;
+            }
         }
         return;
     }
-    HB hb = 0;
-    for (int k = 0; k < kBins; ++k) {
-        const HB v = P.hbins[(size_t)k * P.n_total + m];
-        hb = v > hb ? v : hb;
+    HB hb = P.hbins[(size_t)lane * P.n_total + m];
+    for (int off = 32; off > 0; off >>= 1) {
+        const HB o = __shfl_xor(hb, off, 64);
+        hb = o > hb ? o : hb;
     }
     const T H = from_bits<T>(hb);
     if (!(H <= (sizeof(T) == 4 ? T(FLT_MAX) : T(DBL_MAX)))) {
-        P.fault[m] = 1;
-        atomicOr(P.status, 1);
-        P.ms[m] = ms;
-        if (P.ms_log) {
-            P.ms_log[lm] = ms;
-            P.rdt_log[lm] = 0.0;
-            P.tag_log[lm] = -1;
+        if (w0) {
+            P.fault[m] = 1;
+            atomicOr(P.status, 1);
+            P.ms[m] = ms;
+            if (P.ms_log && !P.rec_stride) {
+                P.ms_log[lm] = ms;
+                P.rdt_log[lm] = 0.0;
+                P.tag_log[lm] = -1;
+            }
         }
         return;
     }
@@ -76,7 +102,9 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     const double jf = floor(t / C.rain_interval);
     const double R = (jf >= 0.0 && jf < (double)C.n_rain) ? C.rain[(int64_t)jf] : 0.0;
     const double edge = (jf + 1.0 > (double)C.n_rain) ? INFINITY : (jf + 1.0) * C.rain_interval;
-    const double tev = t_end < edge ? t_end : edge;
+    double tev = t_end < edge ? t_end : edge;
+    const double ts = P.s_dt > 0.0 ? P.s_t0 + (double)(P.smp[lm] + 1) * P.s_dt : INFINITY;
+    if (ts < tev) tev = ts;
     double tn;
     if (dt >= tev - t) {
         dt = tev - t;
@@ -84,6 +112,9 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     } else {
         tn = t + dt;
     }
+    // every lane has read its bin: clear it for the step's new maximum
+    P.hbins[(size_t)lane * P.n_total + m] = 0;
+    if (!w0) return;
     const double s = P.s[m];
     ms.dtdx = (T)(dt / C.dx);
     ms.gdtdx = (T)(C.g * dt / C.dx);
@@ -115,11 +146,20 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
         P.vin[m] += vq * dt;
     }
     P.ms[m] = ms;
+    int tag = (tn == t_end) ? P.tag_value : -1;
+    if (P.s_dt > 0.0) {
+        tag = (tn == ts) ? P.smp[lm] : -1;
+        if (tag >= 0) {
+            P.smp[lm] = tag + 1;
+            P.pend[lm] = tag;
+        }
+    }
     if (P.ms_log) {
-        P.ms_log[lm] = ms;
-        P.rdt_log[lm] = R * dt;
-        P.tag_log[lm] = (tn == t_end) ? P.tag_value : -1;
-        P.any_log[0] = 1;
+        const size_t li = P.rec_stride ? (size_t)ms.slot * P.rec_stride + lm : (size_t)lm;
+        P.ms_log[li] = ms;
+        P.rdt_log[li] = R * dt;
+        P.tag_log[li] = tag;
+        if (P.any_log) P.any_log[0] = 1;
     }
     const int64_t st = P.steps[m];
     if (P.dtlog) {
@@ -134,12 +174,11 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     P.par[m] = ms.parity ^ 1;
     P.steps[m] = st + 1;
     P.vrain[m] += (double)ms.rinc * C.ncells * (C.dx * C.dx);
-    for (int k = 0; k < kBins; ++k) P.hbins[(size_t)k * P.n_total + m] = 0;
 }
 
 template <typename T> void launch_plan(const PlanLaunch<T>& P, hipStream_t s) {
     const int n = P.m_end - P.m_begin;
-    if (n > 0) hipLaunchKernelGGL(k_plan<T>, dim3((n + 255) / 256), dim3(256), 0, s, P);
+    if (n > 0) hipLaunchKernelGGL(k_plan<T>, dim3((n + 3) / 4), dim3(256), 0, s, P);
 }
 
 // ---------------------------------------------------------------------------
@@ -355,6 +394,37 @@ void launch_count_active(int n_total, const double* t, const int32_t* fault, con
                          const int32_t* status, const int64_t* steps, const int64_t* lim, int32_t* out,
                          hipStream_t s) {
     hipLaunchKernelGGL(k_count_active, dim3(1), dim3(256), 0, s, n_total, t, fault, t_end, status, steps, lim, out);
+}
+
+__global__ __launch_bounds__(256) void k_count_group(int n, const double* t, const int32_t* fault,
+                                                     const double* t_end, const int32_t* status,
+                                                     const int32_t* seg_cnt, int32_t* out) {
+    __shared__ int part[4], mpart[4];
+    int c = 0, mx = 0;
+    const double te = *t_end;
+    for (int m = threadIdx.x; m < n; m += 256) {
+        c += (!fault[m] && t[m] < te) ? 1 : 0;
+        mx = max(mx, seg_cnt[m]);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        c += __shfl_xor(c, off, 64);
+        mx = max(mx, __shfl_xor(mx, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        part[threadIdx.x >> 6] = c;
+        mpart[threadIdx.x >> 6] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = part[0] + part[1] + part[2] + part[3];
+        out[1] = status[0];
+        out[2] = max(max(mpart[0], mpart[1]), max(mpart[2], mpart[3]));
+    }
+}
+
+void launch_count_group(int G, const double* t, const int32_t* fault, const double* t_end, const int32_t* status,
+                        const int32_t* seg_cnt, int32_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_count_group, dim3(1), dim3(256), 0, s, G, t, fault, t_end, status, seg_cnt, out);
 }
 
 __global__ __launch_bounds__(256) void k_step_limit(int n, const int64_t* steps, int64_t add, int64_t* lim) {
@@ -905,6 +975,10 @@ __global__ __launch_bounds__(kBlock) void k_march(const StepLaunch<T> L) {
 // computes.  Loads use a column clamped into the grid and a row clamped to the
 // last row, so no lane needs a branch or a zero fill around them: values of
 // lanes outside the grid and of the row below the last are read but never used.
+// REC = 0: the plain step between the member's two state copies.  REC = 1: tape
+// recomputation for the adjoint (slot ms.slot to slot ms.slot + 1, clamp flags,
+// no ledger).  REC = 2: the adjoint's recording forward, the same slots and
+// flags with the plain step's ledger, depth-maximum bins and outflow.
 template <typename T, int V, int NT, int REC, int PF, int EXT>
 __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
     using HB = typename HBits<T>::type;
@@ -1206,7 +1280,7 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
                     *reinterpret_cast<uint16_t*>(cl) = (uint16_t)(cf[0] | (cf[1] << 8));
                 }
             }
-            if constexpr (!REC) {
+            if constexpr (REC != 1) {
                 if (C.peak) {
                     T* PK = C.peak + (size_t)k * plane + ca;
                     T pk4[V];
@@ -1222,7 +1296,7 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
                 for (int j = 0; j < V; ++j) QNo[xl + j] = fN[j];
             }
             // outflow through open edges (FP64 per member and edge link)
-            if (!REC && (westw || eastw || r == 0 || !hasS)) {
+            if (REC != 1 && (westw || eastw || r == 0 || !hasS)) {
                 double* acc = C.out_acc + (size_t)k * nb;
                 // inflow links are not outflow: their volume is logged by the step planner
 #pragma unroll
@@ -1272,7 +1346,7 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
         }
         ca += nx;
     }
-    if constexpr (!REC) {
+    if constexpr (REC != 1) {
         for (int off = 32; off > 0; off >>= 1) {
             const HB o = __shfl_xor(vmax, off, 64);
             vmax = o > vmax ? o : vmax;
@@ -1327,24 +1401,33 @@ void launch_marchv(const StepLaunch<T>& L, int nt, int pf, int ext, int total_wa
     }
 }
 
-// Tape recomputation of the adjoint: the same step, reading and writing tape
-// slots, recording clamp flags, leaving the ledger, the outflow accumulators and
-// the depth maximum alone; members that did not step in the recorded launch are
-// skipped (their slots are not advanced).
-template <typename T> void launch_marchv_rec(const StepLaunch<T>& L, int pf, int total_waves, hipStream_t s) {
+// Tape recomputation of the adjoint (record = 0): the same step, reading and
+// writing tape slots, recording clamp flags, leaving the ledger, the outflow
+// accumulators and the depth maximum alone; members that do not step in the
+// launch are skipped (their slots are not advanced).  Recording forward
+// (record = 1): the same slots and clamp flags, plus everything the plain step
+// updates (depth maximum bins, clamp and outflow ledgers, running maximum).
+template <typename T>
+void launch_marchv_rec(const StepLaunch<T>& L, int pf, int record, int total_waves, hipStream_t s) {
     const int per = kBlock / 64;
     const dim3 grid((total_waves + per - 1) / per);
     constexpr int V = march_vec<T>();
-    if (pf)
+    if (record) {
+        if (pf)
+            hipLaunchKernelGGL((k_marchv<T, V, 1, 2, 1, 0>), grid, dim3(kBlock), 0, s, L);
+        else
+            hipLaunchKernelGGL((k_marchv<T, V, 1, 2, 0, 0>), grid, dim3(kBlock), 0, s, L);
+    } else if (pf) {
         hipLaunchKernelGGL((k_marchv<T, V, 0, 1, 1, 0>), grid, dim3(kBlock), 0, s, L);
-    else
+    } else {
         hipLaunchKernelGGL((k_marchv<T, V, 0, 1, 0, 0>), grid, dim3(kBlock), 0, s, L);
+    }
 }
 
 template void launch_marchv<float>(const StepLaunch<float>&, int, int, int, int, hipStream_t);
 template void launch_marchv<double>(const StepLaunch<double>&, int, int, int, int, hipStream_t);
-template void launch_marchv_rec<float>(const StepLaunch<float>&, int, int, hipStream_t);
-template void launch_marchv_rec<double>(const StepLaunch<double>&, int, int, hipStream_t);
+template void launch_marchv_rec<float>(const StepLaunch<float>&, int, int, int, hipStream_t);
+template void launch_marchv_rec<double>(const StepLaunch<double>&, int, int, int, hipStream_t);
 
 template <typename T> void launch_march(const StepLaunch<T>& L, int seg, int total_waves, hipStream_t s) {
     const int per = kBlock / 64;

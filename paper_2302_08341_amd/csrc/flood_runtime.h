@@ -47,6 +47,7 @@ struct ImplBase {
                             int32_t* march_rows, int32_t* march_members, int32_t* march_order) const = 0;
     virtual flood_status timing(bool on, std::string& err) = 0;
     virtual void get_timing(double* avg_ms, int64_t* launches) const = 0;
+    virtual void get_adjoint_info(int32_t* groups, int32_t* group_size, int32_t* segments) const = 0;
 };
 
 const char* status_name(flood_status s);

@@ -97,6 +97,8 @@ template <typename T> struct Impl : ImplBase {
     int32_t* d_count = nullptr;
     double* h_tend = nullptr;      // pinned
     int32_t* h_count = nullptr;    // pinned [2 slots][2]
+    int32_t* h_cnt3 = nullptr;     // pinned [2 slots][3]: the adjoint forward's batch counts
+    int last_adj_groups = 0, last_adj_group_size = 0, last_adj_segments = 0;
     hipEvent_t ev[2] = {nullptr, nullptr};
 
     // particle filter scratch
@@ -170,6 +172,12 @@ template <typename T> struct Impl : ImplBase {
         adj_ckpt.clear();
     }
 
+    void get_adjoint_info(int32_t* groups, int32_t* group_size, int32_t* segments) const override {
+        if (groups) *groups = last_adj_groups;
+        if (group_size) *group_size = last_adj_group_size;
+        if (segments) *segments = last_adj_segments;
+    }
+
     flood_status adjoint_release(std::string& err) override {
         (void)err;
         adj_free_all();
@@ -189,6 +197,7 @@ template <typename T> struct Impl : ImplBase {
         if (telog) (void)hipFree(telog);
         if (h_tend) (void)hipHostFree(h_tend);
         if (h_count) (void)hipHostFree(h_count);
+        if (h_cnt3) (void)hipHostFree(h_cnt3);
         if (own_stream) (void)hipStreamDestroy(own_stream);
     }
 
@@ -1622,7 +1631,9 @@ static CatchDev<T> group_view(const CatchDev<T>& C, int mi, int g0, int G, T* co
     v.tiles_y = (C.ny + ty - 1) / ty;
     // row-march geometry (members in planes), likewise fixed
     const int strip_w = 62 * march_vec<T>();
-    v.march_rows = std::min(kAdjMarchRows, C.ny);
+    int rows = kAdjMarchRows;   // at most 16: the reverse step stages 4 x rows x 64 x V values in LDS
+    if (const char* ar = std::getenv("FLOOD_ADJ_ROWS")) rows = std::min(16, std::max(1, std::atoi(ar)));
+    v.march_rows = std::min(rows, C.ny);
     v.strips_x = (C.nx + strip_w - 1) / strip_w;
     v.strips_y = (C.ny + v.march_rows - 1) / v.march_rows;
     v.wave_begin = 0;
@@ -1669,6 +1680,13 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
         }
     double t0;
     CHK(common_time(c, &t0, err));
+    int gauges_distinct = 1;
+    {
+        std::vector<int64_t> cells(K);
+        for (int k = 0; k < K; ++k) cells[k] = (int64_t)grc[2 * k] * C.nx + grc[2 * k + 1];
+        std::sort(cells.begin(), cells.end());
+        for (int k = 1; k < K; ++k) gauges_distinct &= cells[k] != cells[k - 1];
+    }
     const int S = (int)std::floor((t_end - t0) / sample_dt + 1e-9);
     if (S < 1) { err = "no sample time in (t0, t_end]"; return FLOOD_EINVAL; }
     for (size_t i = 0; i < (size_t)S * K; ++i)
@@ -1682,7 +1700,14 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
     free_b += adj_held();   // held from an earlier call: reused or replaced below
     const size_t per_member_state = (3 * ncell + C.ny + C.nx) * sizeof(T);
     const size_t per_member_slot = per_member_state + ncell;   // + clamp flags
-    size_t G = (size_t)(0.5 * (double)free_b) / ((size_t)(ckpt_every + 1) * per_member_slot + 8 * per_member_state);
+    // members in planes with a vectorisable row length: the adjoint runs in
+    // row-march form (forward, tape recomputation and reverse step), otherwise
+    // in the tiled form that also serves interleaved members
+    const bool march_adj = mi == 1 && variant == 3;
+    // the row-march form keeps a whole segment of every group member's steps in
+    // the tape, so it takes most of the free memory (the tiled form half of it)
+    const double share = march_adj ? 0.85 : 0.5;
+    size_t G = (size_t)(share * (double)free_b) / ((size_t)(ckpt_every + 1) * per_member_slot + 8 * per_member_state);
     G = std::min<size_t>(G, (size_t)N);
     if (const char* eg = std::getenv("FLOOD_ADJ_GROUP")) {   // testing: force smaller member groups
         const long v = std::atol(eg);
@@ -1693,8 +1718,12 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
     // as many groups as memory needs, all of one size: equal launches, and a
     // grouping that small changes of free memory do not move
     {
+        // the row-march reverse step works on member quads: whole quads when memory allows
+        if (march_adj && G >= 4) G = G / 4 * 4;
         const size_t n_groups = ((size_t)N + G - 1) / G;
-        G = (((size_t)N + n_groups - 1) / n_groups + mi - 1) / mi * mi;
+        size_t Ge = (((size_t)N + n_groups - 1) / n_groups + mi - 1) / mi * mi;
+        if (march_adj && G >= 4) Ge = std::min(G, (Ge + 3) / 4 * 4);
+        G = Ge;
     }
 
     // device scratch owned by this call
@@ -1718,10 +1747,6 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
         }
     } guard{tmp, st};
 
-    // members in planes with a vectorisable row length: the adjoint runs in
-    // row-march form (forward, tape recomputation and reverse step), otherwise
-    // in the tiled form that also serves interleaved members
-    const bool march_adj = mi == 1 && variant == 3;
     const int Gi = (int)G;
     const int chunksG = (Gi + mi - 1) / mi;
     const size_t elemsG = (size_t)chunksG * ncell * mi;
@@ -1763,16 +1788,68 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
         if (march_adj) nblk = tv.strips_x * tv.strips_y;
     }
     CHK(talloc((size_t)nblk * Gi * sizeof(double), (void**)&d_mubar));
-    // row-march form: per-member adjoint copy index and Manning-field accumulators
+    // row-march form: per-member adjoint copy index, Manning-field accumulators,
+    // member-local step records ([segment][slot][member]) and per-member counters
     int32_t* d_lpar = nullptr;
     int32_t* d_segcnt = nullptr;
+    int32_t *d_smp = nullptr, *d_pend = nullptr, *d_prev = nullptr, *d_cnt3 = nullptr;
+    double *d_lossm = nullptr, *d_rdtcur = nullptr;
+    MemberStep<T>* d_mscur = nullptr;
     T* d_nacc = nullptr;
+    MemberStep<T>* rec_ms = nullptr;
+    double* rec_rdt = nullptr;
+    int32_t* rec_tag = nullptr;
+    size_t rec_cap = 0;
+    int32_t* seg_n = nullptr;
+    size_t segn_cap = 0;
+    double loss_host = 0.0;
     if (march_adj) {
         CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_lpar));
         CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_segcnt));
-        CHK(adj_reserve(adj_nacc, elemsG * sizeof(T), err));
+        CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_smp));
+        CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_pend));
+        CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_prev));
+        CHK(talloc(6 * sizeof(int32_t), (void**)&d_cnt3));
+        CHK(talloc((size_t)Gi * sizeof(double), (void**)&d_lossm));
+        CHK(talloc((size_t)Gi * sizeof(double), (void**)&d_rdtcur));
+        CHK(talloc((size_t)Gi * sizeof(MemberStep<T>), (void**)&d_mscur));
+        // one Manning-field accumulator per member quad
+        CHK(adj_reserve(adj_nacc, (size_t)((Gi + 3) / 4) * ncell * sizeof(T), err));
         d_nacc = static_cast<T*>(adj_nacc.p);
+        if (!h_cnt3) HIPCHK(hipHostMalloc((void**)&h_cnt3, 6 * sizeof(int32_t), hipHostMallocDefault));
     }
+    // grow the member-local records to hold n entries (contents kept)
+    auto grow_rec = [&](size_t n) -> flood_status {
+        if (n <= rec_cap) return FLOOD_OK;
+        size_t cap = std::max<size_t>(rec_cap * 2, n);
+        MemberStep<T>* a;
+        double* r;
+        int32_t* g;
+        CHK(talloc(cap * sizeof(MemberStep<T>), (void**)&a));
+        CHK(talloc(cap * sizeof(double), (void**)&r));
+        CHK(talloc(cap * sizeof(int32_t), (void**)&g));
+        if (rec_cap) {
+            HIPCHK(hipMemcpyAsync(a, rec_ms, rec_cap * sizeof(MemberStep<T>), hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(r, rec_rdt, rec_cap * sizeof(double), hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(g, rec_tag, rec_cap * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+        }
+        rec_ms = a;
+        rec_rdt = r;
+        rec_tag = g;
+        rec_cap = cap;
+        return FLOOD_OK;
+    };
+    auto grow_segn = [&](size_t n) -> flood_status {
+        if (n <= segn_cap) return FLOOD_OK;
+        size_t cap = std::max<size_t>(segn_cap * 2, n);
+        int32_t* a;
+        CHK(talloc(cap * sizeof(int32_t), (void**)&a));
+        if (segn_cap) HIPCHK(hipMemcpyAsync(a, seg_n, segn_cap * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+        seg_n = a;
+        segn_cap = cap;
+        return FLOOD_OK;
+    };
+    int n_segments = 0;
     size_t log_cap = 4096;
     auto grow_log = [&](size_t need) -> flood_status {
         if (need <= log_cap && ms_log) return FLOOD_OK;
@@ -1860,103 +1937,196 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
         PLg.m_end = off + g0 + Gg;
         if (march_adj) {
             // ---------------- row-march form ----------------
-            // Forward: the step kernel of flood_step on the group, with the planner
-            // recording every launch and numbering each member's steps within the
-            // current tape segment (ckpt_every launches, checkpoint at its start).
+            // Recording forward: the step kernel writes each member's steps into its
+            // tape slots directly (slot j -> j + 1), so the last tape segment needs no
+            // recomputation.  A segment ends when a member has taken ckpt_every steps
+            // in it: every member's state is then copied to slot 0 and to a
+            // checkpoint.  Step records are member-local ([slot][member]), and the
+            // members' sample times are scheduled on the device, so the forward
+            // runs in batches of launches without a host round trip per sample.
             const int tw = V.n_waves;
+            const size_t plane = ncell;
+            const CatchDev<T> TV = slot_view(tape, 0);
+            // the recording forward also keeps the group's outflow and running maximum
+            CatchDev<T> TVF = TV;
+            TVF.out_acc = V.out_acc;
+            TVF.peak = V.peak;
             StepLaunch<T> SLm = SL;
             SLm.n_catch = 1;
             SLm.c[0] = V;
             SLm.total_blocks = 0;
             SLm.recompute = 0;
+            // launches per batch: a member takes at most one step per launch, so a
+            // batch never takes a member past the segment's ckpt_every steps
+            const int B = std::min(8, ckpt_every);
+            const size_t seg_recs = (size_t)ckpt_every * Gi;
+            std::vector<int> seg_nmax;
+            int seg = 0;
+            CHK(grow_rec(seg_recs));
+            auto rec_at = [&](int sg) { return rec_ms + (size_t)sg * seg_recs; };
+            HIPCHK(hipMemsetAsync(rec_ms, 0, seg_recs * sizeof(MemberStep<T>), st));
+            launch_snapshot<T>(mi, V, par, TV, st);
+            T* ck0;
+            CHK(checkpoint(0, &ck0));
+            HIPCHK(hipMemcpyAsync(ck0, tape, slot_elems * sizeof(T), hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemsetAsync(d_segcnt, 0, (size_t)Gi * sizeof(int32_t), st));
+            HIPCHK(hipMemsetAsync(d_smp, 0, (size_t)Gi * sizeof(int32_t), st));
+            HIPCHK(hipMemsetAsync(d_pend, 0xff, (size_t)Gi * sizeof(int32_t), st));
+            HIPCHK(hipMemsetAsync(d_lossm, 0, (size_t)Gi * sizeof(double), st));
             PLg.seg_cnt = d_segcnt;
-            std::vector<T*> ckpts;
+            PLg.rec_stride = Gi;
+            PLg.any_log = nullptr;
+            PLg.tag_value = -1;
+            PLg.s_t0 = t0;
+            PLg.s_dt = sample_dt;
+            PLg.smp = d_smp;
+            PLg.pend = d_pend;
+            PLg.tape_h = tape;
+            PLg.slot_stride = slot_elems;
+            PLg.plane = plane;
+            PLg.nx = C.nx;
+            PLg.n_gauges = K;
+            PLg.grc = d_grc2;
+            PLg.obs = d_obs2;
+            PLg.loss_m = d_lossm;
+            auto set_seg = [&](int sg) {
+                PLg.ms_log = rec_at(sg);
+                PLg.rdt_log = rec_rdt + (size_t)sg * seg_recs;
+                PLg.tag_log = rec_tag + (size_t)sg * seg_recs;
+            };
+            set_seg(0);
+            *h_tend = t0 + (double)S * sample_dt;
+            HIPCHK(hipMemcpyAsync(d_tend, h_tend, sizeof(double), hipMemcpyHostToDevice, st));
+            StepLaunch<T> RF = SLm;
+            RF.c[0] = TVF;
+            RF.ms = ms;
+            RF.clamp_out = clamp;
+            RF.slot_stride = slot_elems;
+            RF.clamp_stride = elemsG;
             int64_t L = 0;
-            CHK(grow_log(4096));
-            HIPCHK(hipMemsetAsync(any_log, 0, log_cap * sizeof(int32_t), st));
-            for (int smp = 0; smp < S; ++smp) {
-                *h_tend = t0 + (double)(smp + 1) * sample_dt;
-                HIPCHK(hipMemcpyAsync(d_tend, h_tend, sizeof(double), hipMemcpyHostToDevice, st));
-                HIPCHK(hipStreamSynchronize(st));
-                for (;;) {
-                    const int B = 8;
-                    CHK(grow_log((size_t)L + B + 1));
-                    for (int i = 0; i < B; ++i) {
-                        if (L % ckpt_every == 0) {
-                            T* ck;
-                            CHK(checkpoint((int)ckpts.size(), &ck));
-                            ckpts.push_back(ck);
-                            T* ch[2] = {ck, ck};
-                            T* cx[2] = {ck + elemsG, ck + elemsG};
-                            T* cyy[2] = {ck + 2 * elemsG, ck + 2 * elemsG};
-                            T* cw[2] = {ck + 3 * elemsG, ck + 3 * elemsG};
-                            T* cn[2] = {ck + 3 * elemsG + wG, ck + 3 * elemsG + wG};
-                            CatchDev<T> D = group_view(C.dev, mi, g0, Gg, ch, cx, cyy, cw, cn);
-                            launch_snapshot<T>(mi, V, par, D, st);
-                            HIPCHK(hipMemsetAsync(d_segcnt, 0, (size_t)Gi * sizeof(int32_t), st));
-                        }
-                        PLg.ms_log = ms_log + (size_t)L * Gi;
-                        PLg.rdt_log = rdt_log + (size_t)L * Gi;
-                        PLg.tag_log = tag_log + (size_t)L * Gi;
-                        PLg.any_log = any_log + L;
-                        PLg.tag_value = smp;
-                        launch_plan<T>(PLg, st);
-                        launch_marchv<T>(SLm, march_nt, march_pf, 0, tw, st);
-                        ++L;
-                    }
-                    launch_count_active(Gg, t + off + g0, fault + off + g0, d_tend, status, nullptr, nullptr, d_count, st);
-                    HIPCHK(hipGetLastError());
-                    HIPCHK(hipMemcpyAsync(h_count, d_count, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            auto launch_fwd_batch = [&](int slot) -> flood_status {
+                for (int i = 0; i < B; ++i) {
+                    launch_plan<T>(PLg, st);
+                    launch_marchv_rec<T>(RF, march_pf, 1, tw, st);
+                }
+                L += B;
+                launch_count_group(Gg, t + off + g0, fault + off + g0, d_tend, status, d_segcnt, d_cnt3 + 3 * slot, st);
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipMemcpyAsync(h_cnt3 + 3 * slot, d_cnt3 + 3 * slot, 3 * sizeof(int32_t),
+                                      hipMemcpyDeviceToHost, st));
+                HIPCHK(hipEventRecord(ev[slot], st));
+                return FLOOD_OK;
+            };
+            // end the current segment: its step counts, and every member's state to
+            // slot 0 and to the next checkpoint
+            auto roll = [&](int nmax) -> flood_status {
+                HIPCHK(hipMemcpyAsync(seg_n + (size_t)seg * Gi, d_segcnt, (size_t)Gi * sizeof(int32_t),
+                                      hipMemcpyDeviceToDevice, st));
+                seg_nmax.push_back(nmax);
+                ++seg;
+                CHK(grow_rec((size_t)(seg + 1) * seg_recs));
+                CHK(grow_segn((size_t)(seg + 1) * Gi));
+                HIPCHK(hipMemsetAsync(rec_at(seg), 0, seg_recs * sizeof(MemberStep<T>), st));
+                launch_tape_gather<T>(TV, slot_elems, d_segcnt, TV, nullptr, st);
+                T* ck;
+                CHK(checkpoint(seg, &ck));
+                HIPCHK(hipMemcpyAsync(ck, tape, slot_elems * sizeof(T), hipMemcpyDeviceToDevice, st));
+                HIPCHK(hipMemsetAsync(d_segcnt, 0, (size_t)Gi * sizeof(int32_t), st));
+                set_seg(seg);
+                return FLOOD_OK;
+            };
+            CHK(grow_segn((size_t)Gi));
+            // two batches in flight while the segment has room for both
+            CHK(launch_fwd_batch(0));
+            int inflight = 1, next = 1, wait_slot = 0, mx = 0;
+            for (;;) {
+                if (inflight == 1 && mx + 2 * B <= ckpt_every) {
+                    CHK(launch_fwd_batch(next));
+                    next ^= 1;
+                    inflight = 2;
+                }
+                HIPCHK(hipEventSynchronize(ev[wait_slot]));
+                --inflight;
+                const int active = h_cnt3[3 * wait_slot], stat = h_cnt3[3 * wait_slot + 1];
+                mx = h_cnt3[3 * wait_slot + 2];
+                wait_slot ^= 1;
+                if (stat) {
                     HIPCHK(hipStreamSynchronize(st));
-                    if (h_count[1]) {
-                        err = "a member produced a non-finite depth during the adjoint forward";
-                        return FLOOD_ENUMERIC;
+                    err = "a member produced a non-finite depth during the adjoint forward";
+                    return FLOOD_ENUMERIC;
+                }
+                if (active == 0) {
+                    if (inflight) {
+                        HIPCHK(hipEventSynchronize(ev[wait_slot]));
+                        mx = std::max(mx, (int)h_cnt3[3 * wait_slot + 2]);
                     }
-                    if (h_count[0] == 0) break;
-                    if (L > max_launch) {
-                        err = "adjoint forward exceeded the launch limit";
+                    break;
+                }
+                if (L > max_launch) {
+                    HIPCHK(hipStreamSynchronize(st));
+                    err = "adjoint forward exceeded the launch limit";
+                    return FLOOD_ESTATE;
+                }
+                if (inflight == 0) {
+                    if (mx + B > ckpt_every) {
+                        CHK(roll(mx));
+                        mx = 0;
+                    }
+                    if (mx + B > ckpt_every) {   // cannot happen: B <= ckpt_every
+                        err = "adjoint tape segment overflow";
                         return FLOOD_ESTATE;
                     }
+                    CHK(launch_fwd_batch(next));
+                    next ^= 1;
+                    inflight = 1;
                 }
-                launch_misfit<T>(mi, V, par, K, d_grc2, d_obs2 + (size_t)smp * K, d_loss, st);
             }
-            std::vector<int32_t> any_h(L);
-            HIPCHK(hipMemcpyAsync(any_h.data(), any_log, L * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
+            launch_plan<T>(PLg, st);   // misfit of the samples completed by the last steps
+            HIPCHK(hipMemcpyAsync(seg_n + (size_t)seg * Gi, d_segcnt, (size_t)Gi * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, st));
+            seg_nmax.push_back(mx);
+            // the members' end states back into the handle
+            launch_tape_gather<T>(TV, slot_elems, d_segcnt, V, par, st);
+            {
+                std::vector<double> lm(Gg);
+                HIPCHK(hipMemcpyAsync(lm.data(), d_lossm, Gg * sizeof(double), hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                for (int m = 0; m < Gg; ++m) loss_host += lm[m];
+            }
+            n_segments += (int)seg_nmax.size();
 
-            // Reverse, segment by segment from the last: recompute the segment's
-            // launches into per-member tape slots, then apply the reverse steps in
-            // reverse launch order.  A member that did not step in a launch keeps
-            // its slot, its adjoint copy and its accumulators untouched.
+            // Reverse, segment by segment from the last, each member walking back
+            // through its own steps (reverse launch i of a segment reverses step
+            // n[k] - 1 - i of member k), so every launch carries every member that
+            // has steps left.  Earlier segments are first recomputed from their
+            // checkpoints, member by member in the same way.
             HIPCHK(hipMemsetAsync(lam, 0, 2 * slot_elems * sizeof(T), st));
             HIPCHK(hipMemsetAsync(d_mubar, 0, (size_t)nblk * Gi * sizeof(double), st));
             HIPCHK(hipMemsetAsync(d_lpar, 0, (size_t)Gi * sizeof(int32_t), st));
-            HIPCHK(hipMemsetAsync(d_nacc, 0, elemsG * sizeof(T), st));
-            const CatchDev<T> TV = slot_view(tape, 0);
+            HIPCHK(hipMemsetAsync(d_prev, 0, (size_t)Gi * sizeof(int32_t), st));
+            HIPCHK(hipMemsetAsync(d_nacc, 0, (size_t)((Gg + 3) / 4) * ncell * sizeof(T), st));
             T* lb[2] = {lam, lam + slot_elems};
-            int64_t l_prev = -1;
-            for (int ck = (int)ckpts.size() - 1; ck >= 0; --ck) {
-                const int64_t L0 = (int64_t)ck * ckpt_every;
-                const int64_t L1 = std::min<int64_t>(L0 + ckpt_every, L);
-                std::vector<int64_t> useful;
-                for (int64_t l = L0; l < L1; ++l)
-                    if (any_h[l]) useful.push_back(l);
-                if (useful.empty()) continue;
-                HIPCHK(hipMemcpyAsync(tape, ckpts[ck], slot_elems * sizeof(T), hipMemcpyDeviceToDevice, st));
-                for (int64_t l : useful) {
-                    StepLaunch<T> R = SLm;
-                    R.c[0] = TV;
-                    R.ms = ms_log + (size_t)l * Gi - (off + g0);
-                    R.clamp_out = clamp;
-                    R.slot_stride = slot_elems;
-                    R.clamp_stride = elemsG;
-                    launch_marchv_rec<T>(R, march_pf, tw, st);
+            for (int sg = (int)seg_nmax.size() - 1; sg >= 0; --sg) {
+                const int nmax = seg_nmax[sg];
+                if (nmax == 0) continue;
+                const MemberStep<T>* recs = rec_at(sg);
+                if (sg != (int)seg_nmax.size() - 1) {
+                    HIPCHK(hipMemcpyAsync(tape, adj_ckpt[sg].p, slot_elems * sizeof(T), hipMemcpyDeviceToDevice, st));
+                    for (int r = 0; r < nmax; ++r) {
+                        StepLaunch<T> R = SLm;
+                        R.c[0] = TV;
+                        R.ms = recs + (size_t)r * Gi - (off + g0);
+                        R.clamp_out = clamp;
+                        R.slot_stride = slot_elems;
+                        R.clamp_stride = elemsG;
+                        launch_marchv_rec<T>(R, march_pf, 0, tw, st);
+                    }
                 }
-                for (int j = (int)useful.size() - 1; j >= 0; --j) {
-                    const int64_t l = useful[j];
-                    launch_adj_pre<T>(Gg, l_prev >= 0 ? ms_log + (size_t)l_prev * Gi : nullptr, ms_log + (size_t)l * Gi,
-                                      tag_log + (size_t)l * Gi, K, d_grc2, d_obs2, TV, slot_elems, d_lpar, lb[0], lb[1],
-                                      st);
+                for (int i = 0; i < nmax; ++i) {
+                    launch_adj_plan<T>(Gg, Gi, i, seg_n + (size_t)sg * Gi, recs, rec_rdt + (size_t)sg * seg_recs,
+                                       rec_tag + (size_t)sg * seg_recs, K, gauges_distinct, d_grc2, d_obs2, tape,
+                                       slot_elems, plane,
+                                       C.nx, d_lpar, d_prev, d_mscur, d_rdtcur, lb[0], lb[1], st);
                     AdjvLaunch<T> A{};
                     A.c = TV;
                     A.slot_stride = slot_elems;
@@ -1970,16 +2140,15 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                         A.lqn[w] = lb[w] + 3 * elemsG + wG;
                     }
                     A.lpar = d_lpar;
-                    A.ms = ms_log + (size_t)l * Gi;
-                    A.rdt = rdt_log + (size_t)l * Gi;
+                    A.ms = d_mscur;
+                    A.rdt = d_rdtcur;
                     A.nacc = d_nacc;
                     A.mubar_part = d_mubar;
-                    launch_adjoint_march<T>(A, tw, st);
-                    l_prev = l;
+                    launch_adjoint_march<T>(A, st);
                 }
                 HIPCHK(hipGetLastError());
             }
-            launch_nacc_reduce<T>(Gg, ncell, d_nacc, d_nbar, st);
+            launch_nacc_reduce<T>((Gg + 3) / 4, ncell, d_nacc, d_nbar, st);
             launch_sum_parts(V.strips_x * V.strips_y, Gg, d_mubar, d_gm + g0, st);
             HIPCHK(hipGetLastError());
             HIPCHK(hipStreamSynchronize(st));
@@ -2109,6 +2278,11 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
     }
     double loss_h = 0.0;
     HIPCHK(hipMemcpyAsync(&loss_h, d_loss, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (march_adj) loss_h = loss_host;
+    last_adj_groups = (int)((N + Gi - 1) / Gi);
+    last_adj_group_size = Gi;
+    last_adj_segments = n_segments;
     if (grad_n_out) HIPCHK(hipMemcpyAsync(grad_n_out, d_nbar, ncell * sizeof(double), hipMemcpyDeviceToHost, st));
     if (grad_mult_out) HIPCHK(hipMemcpyAsync(grad_mult_out, d_gm, N * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));

@@ -25,7 +25,8 @@ EXPORTED = ["flood_create", "flood_create_batch", "flood_step", "flood_assimilat
             "flood_systematic_resample", "flood_ensemble_products", "flood_get_land_params", "flood_save",
             "flood_load", "flood_set_sections", "flood_get_sections", "flood_assimilate_obs",
             "flood_get_config", "flood_timing", "flood_get_timing", "flood_adjoint_release", "flood_step_n",
-            "flood_get_wet_mask", "flood_log_steps", "flood_get_step_log", "flood_last_error",
+            "flood_get_wet_mask", "flood_log_steps", "flood_get_step_log", "flood_get_adjoint_info",
+            "flood_last_error",
             "flood_strerror", "flood_destroy"]
 
 
@@ -108,6 +109,7 @@ def load_library():
         "flood_get_wet_mask": [H, C.c_int32, C.c_int32, C.POINTER(C.c_uint8), C.POINTER(C.c_uint8)],
         "flood_log_steps": [H, C.c_int32],
         "flood_get_step_log": [H, C.c_int32, dp, dp, lp],
+        "flood_get_adjoint_info": [H, ip, ip, ip],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -408,6 +410,12 @@ def flood_get_timing(h):
     return avg.value, n.value
 
 
+def flood_get_adjoint_info(h):
+    g, n, sg = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    _check(load_library().flood_get_adjoint_info(h, C.byref(g), C.byref(n), C.byref(sg)), h)
+    return {"groups": g.value, "group_size": n.value, "segments": sg.value}
+
+
 def flood_destroy(h):
     if h:
         load_library().flood_destroy(h)
@@ -557,6 +565,10 @@ class FloodEnsemble:
 
     def get_timing(self):
         return flood_get_timing(self.h)
+
+    def adjoint_info(self):
+        """Member groups, group size and tape segments of the last adjoint call."""
+        return flood_get_adjoint_info(self.h)
 
     def adjoint_release(self):
         """Free the adjoint's scratch (tape, checkpoints) held since the last adjoint call."""

@@ -162,7 +162,12 @@ def test_adjoint_checkpoint_interval_and_groups_are_consistent(fl, monkeypatch, 
     other = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, **kw).adjoint(0, 40.0, 10.0, g, obs, 3)
     assert other[0] == ref[0]
     np.testing.assert_array_equal(other[2], ref[2])
-    np.testing.assert_array_equal(other[1], ref[1])
+    if sk == 1:
+        np.testing.assert_array_equal(other[1], ref[1])
+    else:
+        # the row-march form adds the Manning-field contributions of a member quad in
+        # FP32 per reverse launch, and which steps share a launch follows the segments
+        assert np.linalg.norm(other[1] - ref[1]) <= 1e-6 * np.linalg.norm(ref[1])
     monkeypatch.setenv("FLOOD_ADJ_GROUP", "1")
     grp = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, member_interleave=1, **kw).adjoint(
         0, 40.0, 10.0, g, obs, 5)
@@ -217,7 +222,8 @@ def test_adjoint_forms_agree(fl, rb, tol):
     obs = np.random.default_rng(0).uniform(0.3, 0.5, size=(4, len(g)))
     res = [_ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, real_bytes=rb, step_kernel=sk, cfl_alpha=0.5).adjoint(
         0, 40.0, 10.0, g, obs, 6) for sk in (1, 3)]
-    assert res[1][0] == res[0][0]
+    # the loss: the same FP64 misfit terms, summed per member in the row-march form
+    assert res[1][0] == pytest.approx(res[0][0], rel=1e-14)
     np.testing.assert_allclose(res[1][2], res[0][2], rtol=tol)
     assert np.linalg.norm(res[1][1] - res[0][1]) <= tol * np.linalg.norm(res[0][1])
 
