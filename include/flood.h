@@ -316,6 +316,19 @@ flood_status flood_get_weights(flood_handle* h, int32_t catchment, double* logw,
 flood_status flood_systematic_resample(const double* w, int32_t n, double u0, int32_t* anc_out,
                                        void* hip_stream);
 
+/* flood_systematic_resample for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernel and the same ancestors, but the weights and
+ * ancestors are staged in a 12 KiB device array of the library (one per GPU,
+ * kept until the process ends) instead of buffers allocated per call; nothing
+ * is allocated.  Runs on the current device.  n at most FLOOD_MAX_MEMBERS
+ * (1024): larger n, or weights that are negative, non-finite or sum to zero,
+ * give EINVAL before any HIP call.  Calls that overlap on one GPU (other host
+ * threads, other streams) share the staging array and race.  Synchronises the
+ * stream.  Errors: EINVAL, EHIP. */
+flood_status flood_systematic_resample_noalloc(const double* w, int32_t n, double u0, int32_t* anc_out,
+                                               void* hip_stream);
+
 /* Ensemble products of the running maximum depth (Sec. 4.4, Figs. 15-16) of
  * one catchment, per cell, with member weights w (host [N], finite, >= 0,
  * positive sum; NULL: equal weights) and W = sum of w in member order:

@@ -368,6 +368,18 @@ flood_status flood_systematic_resample(const double* w, int32_t n, double u0, in
     return systematic_resample_impl(w, n, u0, anc_out, (hipStream_t)hip_stream);
 }
 
+flood_status flood_systematic_resample_noalloc(const double* w, int32_t n, double u0, int32_t* anc_out,
+                                               void* hip_stream) {
+    if (!w || !anc_out || n < 1 || n > FLOOD_MAX_MEMBERS || !(u0 >= 0.0 && u0 < 1.0)) return FLOOD_EINVAL;
+    double tot = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (!(w[i] >= 0.0) || !finite_d(w[i])) return FLOOD_EINVAL;
+        tot += w[i];
+    }
+    if (!(tot > 0.0) || !finite_d(tot)) return FLOOD_EINVAL;
+    return systematic_resample_noalloc_impl(w, n, u0, anc_out, (hipStream_t)hip_stream);
+}
+
 flood_status flood_ensemble_products(flood_handle* h, int32_t catchment, double threshold, int32_t n_pct,
                                      const double* pct, const double* weights, double* prob_out, double* pct_out) {
     FLOOD_NEED_HANDLE(h);

@@ -7,7 +7,9 @@
 // summed by one lane in member order, so the ancestors depend only on the
 // weights and the offset, not on the reduction tree.
 #include <cmath>
+#include <mutex>
 
+#include "../../include/flood.h"
 #include "flood_internal.h"
 
 namespace flood {
@@ -174,6 +176,55 @@ __global__ __launch_bounds__(1024) void k_systematic(int n, const double* w, dou
 void launch_systematic(int n, const double* w, double u0, int32_t* anc, hipStream_t s) {
     const int threads = ((n + 63) / 64) * 64;
     hipLaunchKernelGGL(k_systematic, dim3(1), dim3(threads), 0, s, n, w, u0, anc);
+}
+
+// Device staging of flood_systematic_resample_noalloc: the weights (kMaxMembers
+// doubles) followed by the ancestors (kMaxMembers int32) of one call, 12 KiB,
+// one copy on each GPU the library runs on, held until the process ends.  Every
+// call on a GPU reuses it, so calls that overlap on one GPU race.  Host code
+// never passes this name to a kernel or a copy: it takes the array's device
+// address once per device (hipGetSymbolAddress) and uses that.
+static __device__ __align__(256) unsigned char scratch[kMaxMembers * (sizeof(double) + sizeof(int32_t))];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+flood_status systematic_resample_noalloc_impl(const double* w, int n, double u0, int32_t* anc, hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return FLOOD_EHIP;
+    }
+    void* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void* p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+                (void)hipGetLastError();
+                return FLOOD_EHIP;
+            }
+            g_scratch_ptr[dev] = p;
+        }
+        base = g_scratch_ptr[dev];
+    }
+    double* dw = static_cast<double*>(base);
+    int32_t* da = reinterpret_cast<int32_t*>(static_cast<unsigned char*>(base) + kMaxMembers * sizeof(double));
+    if (hipMemcpyAsync(dw, w, n * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return FLOOD_EHIP;
+    }
+    launch_systematic(n, dw, u0, da, s);
+    if (hipGetLastError() != hipSuccess) return FLOOD_EHIP;
+    if (hipMemcpyAsync(anc, da, n * sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipGetLastError();
+        return FLOOD_EHIP;
+    }
+    return FLOOD_OK;
 }
 
 // Copy every resampled slot's state from its ancestor (copy src_par) into the

@@ -67,4 +67,5 @@ flood_status create_impl(flood_handle* h, int n_catch, const flood_grid* grids, 
                          const int32_t* members, const double* const* n_scale, const double* const* rain_mult,
                          hipStream_t stream, std::string& err);
 flood_status systematic_resample_impl(const double* w, int n, double u0, int32_t* anc, hipStream_t s);
+flood_status systematic_resample_noalloc_impl(const double* w, int n, double u0, int32_t* anc, hipStream_t s);
 }  // namespace flood

@@ -26,6 +26,7 @@ EXPORTED = ["flood_create", "flood_create_batch", "flood_step", "flood_assimilat
             "flood_load", "flood_set_sections", "flood_get_sections", "flood_assimilate_obs",
             "flood_get_config", "flood_timing", "flood_get_timing", "flood_adjoint_release", "flood_step_n",
             "flood_get_wet_mask", "flood_log_steps", "flood_get_step_log", "flood_get_adjoint_info",
+            "flood_systematic_resample_noalloc",
             "flood_last_error",
             "flood_strerror", "flood_destroy"]
 
@@ -98,6 +99,7 @@ def load_library():
         "flood_get_land_params": [H, C.c_int32, dp, dp],
         "flood_get_weights": [H, C.c_int32, dp, dp, dp],
         "flood_systematic_resample": [dp, C.c_int32, C.c_double, ip, C.c_void_p],
+        "flood_systematic_resample_noalloc": [dp, C.c_int32, C.c_double, ip, C.c_void_p],
         "flood_ensemble_products": [H, C.c_int32, C.c_double, C.c_int32, dp, dp, dp, dp],
         "flood_save": [H, C.c_char_p],
         "flood_load": [H, C.c_char_p],
@@ -375,6 +377,15 @@ def flood_systematic_resample(w, u0, stream=None):
     w = _f64(w)
     anc = np.zeros(w.size, dtype=np.int32)
     _check(load_library().flood_systematic_resample(_dp(w), w.size, float(u0), _ip(anc), stream), None)
+    return anc
+
+
+def flood_systematic_resample_noalloc(w, u0, stream=None):
+    """flood_systematic_resample without any device allocation (library staging array)."""
+    w = _f64(w)
+    anc = np.zeros(w.size, dtype=np.int32)
+    rc = load_library().flood_systematic_resample_noalloc(_dp(w), w.size, float(u0), _ip(anc), stream)
+    _check(rc, None)
     return anc
 
 
