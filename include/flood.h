@@ -350,6 +350,20 @@ flood_status flood_ensemble_products(flood_handle* h, int32_t catchment, double 
 flood_status flood_save(flood_handle* h, const char* path);
 flood_status flood_load(flood_handle* h, const char* path);
 
+/* The same snapshot kept on the device, in one buffer held by the handle
+ * (about twice the state of every member, since both state copies are kept):
+ * op FLOOD_SNAPSHOT_TAKE copies everything flood_save would write into it
+ * (allocated on first use, reused after), FLOOD_SNAPSHOT_RESTORE copies it
+ * back (ESTATE if none was taken) and clears the numeric-fault status,
+ * FLOOD_SNAPSHOT_RELEASE frees it.  Stream-ordered, returns after enqueueing.
+ * Lets a caller evaluate runs from one state repeatedly (a gradient-based
+ * calibration loop) without host transfers.  Errors: EINVAL, ENOMEM, ESTATE,
+ * EHIP. */
+#define FLOOD_SNAPSHOT_TAKE 1
+#define FLOOD_SNAPSHOT_RESTORE 2
+#define FLOOD_SNAPSHOT_RELEASE 3
+flood_status flood_device_snapshot(flood_handle* h, int32_t op);
+
 /* Memory plan of the last flood_adjoint call on the handle: member groups,
  * members per group, and tape segments summed over the groups (segments beyond
  * one per group were recomputed from checkpoints).  Any output may be NULL;

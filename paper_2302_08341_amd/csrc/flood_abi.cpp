@@ -398,6 +398,15 @@ flood_status flood_load(flood_handle* h, const char* path) {
     return h->impl->load(path, h->err);
 }
 
+flood_status flood_device_snapshot(flood_handle* h, int32_t op) {
+    FLOOD_NEED_HANDLE(h);
+    if (op != FLOOD_SNAPSHOT_TAKE && op != FLOOD_SNAPSHOT_RESTORE && op != FLOOD_SNAPSHOT_RELEASE) {
+        h->err = "op must be FLOOD_SNAPSHOT_TAKE, FLOOD_SNAPSHOT_RESTORE or FLOOD_SNAPSHOT_RELEASE";
+        return FLOOD_EINVAL;
+    }
+    return h->impl->device_snapshot(op, h->err);
+}
+
 flood_status flood_get_config(const flood_handle* h, int32_t* mi, int32_t* tile_rows, int32_t* cpb, int32_t* gsteps,
                               int32_t* step_kernel, int32_t* march_rows, int32_t* march_members,
                               int32_t* march_order) {

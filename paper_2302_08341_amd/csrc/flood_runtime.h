@@ -43,6 +43,7 @@ struct ImplBase {
                                   double* prob_out, double* pct_out, std::string& err) = 0;
     virtual flood_status save(const char* path, std::string& err) = 0;
     virtual flood_status load(const char* path, std::string& err) = 0;
+    virtual flood_status device_snapshot(int op, std::string& err) = 0;
     virtual void get_config(int32_t* mi, int32_t* tile_rows, int32_t* cpb, int32_t* gsteps, int32_t* step_kernel,
                             int32_t* march_rows, int32_t* march_members, int32_t* march_order) const = 0;
     virtual flood_status timing(bool on, std::string& err) = 0;

@@ -198,6 +198,7 @@ template <typename T> struct Impl : ImplBase {
         if (h_tend) (void)hipHostFree(h_tend);
         if (h_count) (void)hipHostFree(h_count);
         if (h_cnt3) (void)hipHostFree(h_cnt3);
+        if (snap.p) (void)hipFree(snap.p);
         if (own_stream) (void)hipStreamDestroy(own_stream);
     }
 
@@ -1443,6 +1444,54 @@ template <typename T> struct Impl : ImplBase {
         v.push_back({fault, n * 4});
         v.push_back({hbins, (size_t)kBins * n * sizeof(HB)});
         return v;
+    }
+
+    // device snapshot (flood_device_snapshot): every blob of a file snapshot,
+    // copied back to back into one device buffer held by the handle
+    Scratch snap;
+    bool snap_valid = false;
+
+    flood_status device_snapshot(int op, std::string& err) override {
+        if (op == FLOOD_SNAPSHOT_RELEASE) {
+            HIPCHK(hipStreamSynchronize(st));
+            if (snap.p) (void)hipFree(snap.p);
+            snap = Scratch{};
+            snap_valid = false;
+            return FLOOD_OK;
+        }
+        const std::vector<Blob> bl = blobs();
+        size_t total = 0;
+        for (const Blob& b : bl) total += (b.bytes + 255) / 256 * 256;
+        if (op == FLOOD_SNAPSHOT_TAKE) {
+            if (!snap.p || snap.bytes < total) {
+                HIPCHK(hipStreamSynchronize(st));
+                if (snap.p) (void)hipFree(snap.p);
+                snap = Scratch{};
+                snap_valid = false;
+                if (hipMalloc(&snap.p, total) != hipSuccess) {
+                    (void)hipGetLastError();
+                    snap.p = nullptr;
+                    err = "hipMalloc of " + std::to_string(total) + " bytes for the device snapshot failed";
+                    return FLOOD_ENOMEM;
+                }
+                snap.bytes = total;
+            }
+            size_t off = 0;
+            for (const Blob& b : bl) {
+                HIPCHK(hipMemcpyAsync(static_cast<char*>(snap.p) + off, b.p, b.bytes, hipMemcpyDeviceToDevice, st));
+                off += (b.bytes + 255) / 256 * 256;
+            }
+            snap_valid = true;
+            return FLOOD_OK;
+        }
+        if (!snap_valid) { err = "no device snapshot has been taken"; return FLOOD_ESTATE; }
+        size_t off = 0;
+        for (const Blob& b : bl) {
+            HIPCHK(hipMemcpyAsync(b.p, static_cast<char*>(snap.p) + off, b.bytes, hipMemcpyDeviceToDevice, st));
+            off += (b.bytes + 255) / 256 * 256;
+        }
+        HIPCHK(hipMemsetAsync(status, 0, sizeof(int32_t), st));
+        return FLOOD_OK;
     }
 
     void header(std::vector<int64_t>& hd) const {

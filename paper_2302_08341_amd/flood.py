@@ -20,13 +20,14 @@ LIB_PATH = os.path.join(HERE, "libflood.so")
 FLOOD_OK, FLOOD_EINVAL, FLOOD_ENOMEM, FLOOD_EHIP, FLOOD_ESTATE, FLOOD_ENUMERIC = 0, -1, -2, -3, -4, -5
 EDGE_WALL, EDGE_OPEN = 0, 1
 FIELD_H, FIELD_QX, FIELD_QY, FIELD_PEAK = 0, 1, 2, 3
+SNAPSHOT_TAKE, SNAPSHOT_RESTORE, SNAPSHOT_RELEASE = 1, 2, 3
 EXPORTED = ["flood_create", "flood_create_batch", "flood_step", "flood_assimilate", "flood_adjoint",
             "flood_get_field", "flood_set_state", "flood_set_params", "flood_get_ledger", "flood_get_weights",
             "flood_systematic_resample", "flood_ensemble_products", "flood_get_land_params", "flood_save",
             "flood_load", "flood_set_sections", "flood_get_sections", "flood_assimilate_obs",
             "flood_get_config", "flood_timing", "flood_get_timing", "flood_adjoint_release", "flood_step_n",
             "flood_get_wet_mask", "flood_log_steps", "flood_get_step_log", "flood_get_adjoint_info",
-            "flood_systematic_resample_noalloc",
+            "flood_systematic_resample_noalloc", "flood_device_snapshot",
             "flood_last_error",
             "flood_strerror", "flood_destroy"]
 
@@ -100,6 +101,7 @@ def load_library():
         "flood_get_weights": [H, C.c_int32, dp, dp, dp],
         "flood_systematic_resample": [dp, C.c_int32, C.c_double, ip, C.c_void_p],
         "flood_systematic_resample_noalloc": [dp, C.c_int32, C.c_double, ip, C.c_void_p],
+        "flood_device_snapshot": [H, C.c_int32],
         "flood_ensemble_products": [H, C.c_int32, C.c_double, C.c_int32, dp, dp, dp, dp],
         "flood_save": [H, C.c_char_p],
         "flood_load": [H, C.c_char_p],
@@ -389,6 +391,10 @@ def flood_systematic_resample_noalloc(w, u0, stream=None):
     return anc
 
 
+def flood_device_snapshot(h, op):
+    _check(load_library().flood_device_snapshot(h, int(op)), h)
+
+
 def flood_save(h, path):
     _check(load_library().flood_save(h, path.encode()), h)
 
@@ -564,6 +570,17 @@ class FloodEnsemble:
 
     def save(self, path):
         flood_save(self.h, path)
+
+    def snapshot(self):
+        """Keep every member's state on the device (flood_device_snapshot, TAKE)."""
+        flood_device_snapshot(self.h, SNAPSHOT_TAKE)
+
+    def restore(self):
+        """Return to the last device snapshot (flood_device_snapshot, RESTORE)."""
+        flood_device_snapshot(self.h, SNAPSHOT_RESTORE)
+
+    def snapshot_release(self):
+        flood_device_snapshot(self.h, SNAPSHOT_RELEASE)
 
     def load(self, path):
         flood_load(self.h, path)

@@ -140,3 +140,36 @@ def test_products_validation(fl):
         with pytest.raises(fl.FloodError) as ex:
             t.products(0.2, **bad)
         assert ex.value.status == fl.FLOOD_EINVAL
+
+
+def test_device_snapshot_restores_what_a_file_snapshot_restores(fl):
+    e = _ens(fl, real_bytes=4, track_peak=True)
+    e.step(900.0)
+    with pytest.raises(fl.FloodError):
+        e.restore()                     # nothing taken yet
+    e.snapshot()
+    path = os.path.join(tempfile.mkdtemp(), "snap.bin")
+    e.save(path)
+    obs = e.field(3)[CAT.gauges[:, 0], CAT.gauges[:, 1]]
+    e.assimilate(0, CAT.gauges, obs, np.full(4, 1e-5), 1.0, 1.0)
+    e.step(1300.0)
+    e.restore()
+    f = _ens(fl, real_bytes=4, track_peak=True)
+    f.load(path)
+    for i in range(5):
+        for k in (fl.FIELD_H, fl.FIELD_QX, fl.FIELD_QY, fl.FIELD_PEAK):
+            np.testing.assert_array_equal(e.field(i, k), f.field(i, k))
+    le, lf = e.ledger(), f.ledger()
+    for k in le:
+        np.testing.assert_array_equal(le[k], lf[k])
+    np.testing.assert_array_equal(e.weights(), f.weights())
+    # both continue identically, and the snapshot survives a restore
+    e.step(1500.0)
+    f.step(1500.0)
+    np.testing.assert_array_equal(e.field(2), f.field(2))
+    e.restore()
+    e.step(1500.0)
+    np.testing.assert_array_equal(e.field(2), f.field(2))
+    e.snapshot_release()
+    with pytest.raises(fl.FloodError):
+        e.restore()
