@@ -23,19 +23,35 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "flood_oracle.c")
-_LIB = os.path.join(_HERE, "_liborc.so")
+# FLOOD_ORACLE_LIB names another build of the same source (the sanitizer build
+# of the CPU test suite); it is loaded as it is, never rebuilt
+_LIB_ENV = os.environ.get("FLOOD_ORACLE_LIB")
+_LIB = _LIB_ENV or os.path.join(_HERE, "_liborc.so")
 
 EDGE_WALL, EDGE_OPEN = 0, 1
 
 
+_CFLAGS = ["-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-Wall"]
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (serial, -O2, no FP contraction)."""
+    if _LIB_ENV:
+        return _LIB
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                               "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2"] + _CFLAGS + ["-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def build_sanitized(path: str) -> str:
+    """Compile the same source with AddressSanitizer and UndefinedBehaviorSanitizer
+    (every report fatal) into path; load it by setting FLOOD_ORACLE_LIB and
+    preloading gcc's libasan."""
+    subprocess.check_call(["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=all"] + _CFLAGS + ["-o", path, _SRC, "-lm"])
+    return path
 
 
 class _Model(C.Structure):
@@ -66,7 +82,7 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not _LIB_ENV and (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
             build(force=True)
         lib = C.CDLL(_LIB)
         dp = C.POINTER(C.c_double)

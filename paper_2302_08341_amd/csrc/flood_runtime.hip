@@ -13,6 +13,9 @@
 
 #include "flood_internal.h"
 #include "flood_runtime.h"
+#include "flood_validate.h"
+
+static_assert(flood::kMaxSections == flood::kMaxSectionsAbi, "one limit on sections");
 #include "flood_tune.h"
 
 namespace flood {
@@ -1023,24 +1026,7 @@ template <typename T> struct Impl : ImplBase {
         // observation vector: K gauge depths, then the registered sections' discharges
         const int S = with_sections ? C.n_sec : 0;
         const int KT = K + S;
-        if (K < 0 || KT > 4096) { err = "n_gauges (plus sections) must be in [0, 4096]"; return FLOOD_EINVAL; }
-        if (K > 0 && !grc) { err = "gauge_rc is required"; return FLOOD_EINVAL; }
-        if (KT > 0 && (!obs || !sigma)) { err = "obs and sigma are required"; return FLOOD_EINVAL; }
-        if (!(alpha >= 0.0) || !finite_d(alpha)) { err = "alpha must be finite and >= 0"; return FLOOD_EINVAL; }
-        for (int k = 0; k < K; ++k)
-            if (grc[2 * k] < 0 || grc[2 * k] >= C.ny || grc[2 * k + 1] < 0 || grc[2 * k + 1] >= C.nx) {
-                err = "gauge outside the grid";
-                return FLOOD_EINVAL;
-            }
-        for (int k = 0; k < KT; ++k) {
-            if (!finite_d(obs[k])) { err = "obs must be finite"; return FLOOD_EINVAL; }
-            if (!(sigma[k] > 0.0) || !finite_d(sigma[k])) { err = "sigma must be finite and > 0"; return FLOOD_EINVAL; }
-        }
-        if (!(neff_frac > 0.0 && neff_frac <= 1.0)) { err = "neff_frac must be in (0, 1]"; return FLOOD_EINVAL; }
-        if (!(u0 >= 0.0 && u0 < 1.0)) { err = "u0 must be in [0, 1)"; return FLOOD_EINVAL; }
-        if (beta)
-            for (int m = 0; m < C.N; ++m)
-                if (!(beta[m] >= 0.0) || !finite_d(beta[m])) { err = "beta must be finite and >= 0"; return FLOOD_EINVAL; }
+        CHK(check_observations(C.ny, C.nx, C.N, K, S, grc, obs, sigma, alpha, neff_frac, u0, beta, err));
         double tc;
         CHK(common_time(c, &tc, err));
         const int off = C.dev.member_off;
@@ -1105,32 +1091,8 @@ template <typename T> struct Impl : ImplBase {
     flood_status set_sections(int c, int n, const int32_t* count, const int32_t* links, std::string& err) override {
         CHK(check_catch(c, err));
         Cat& C = cats[c];
-        if (n < 0 || n > kMaxSections) { err = "n_sections must be in [0, 64]"; return FLOOD_EINVAL; }
-        if (n > 0 && (!count || !links)) { err = "link_count and links are required"; return FLOOD_EINVAL; }
-        std::vector<int32_t> offs(1, 0), code, index;
-        for (int sct = 0; sct < n; ++sct) {
-            if (count[sct] < 1) { err = "every section needs at least one link"; return FLOOD_EINVAL; }
-            if ((int64_t)offs.back() + count[sct] > 65536) { err = "at most 65536 section links"; return FLOOD_EINVAL; }
-            for (int l = offs.back(); l < offs.back() + count[sct]; ++l) {
-                const int32_t* f = links + 4 * (size_t)l;
-                const int kind = f[0], r = f[1], cc = f[2], sg = f[3];
-                if (sg != 1 && sg != -1) { err = "link sign must be +1 or -1"; return FLOOD_EINVAL; }
-                int cd, ix;
-                if (kind == 0 && r >= 0 && r < C.ny && cc >= 0 && cc <= C.nx) {
-                    cd = cc == 0 ? 2 : 0;
-                    ix = cc == 0 ? r : r * C.nx + cc - 1;
-                } else if (kind == 1 && r >= 0 && r <= C.ny && cc >= 0 && cc < C.nx) {
-                    cd = r == 0 ? 3 : 1;
-                    ix = r == 0 ? cc : (r - 1) * C.nx + cc;
-                } else {
-                    err = "section link outside the grid (kind 0: r < ny, c <= nx; kind 1: r <= ny, c < nx)";
-                    return FLOOD_EINVAL;
-                }
-                code.push_back(cd | (sg < 0 ? 4 : 0));
-                index.push_back(ix);
-            }
-            offs.push_back(offs.back() + count[sct]);
-        }
+        std::vector<int32_t> offs, code, index;
+        CHK(parse_sections(C.ny, C.nx, n, count, links, offs, code, index, err));
         const size_t L = code.size();
         if (L > C.sec_cap) {
             CHK(dalloc(&C.d_sec_code, L, err));
@@ -1288,27 +1250,8 @@ template <typename T> struct Impl : ImplBase {
         CHK(check_catch(c, err));
         const Cat& C = cats[c];
         if (m < 0 || m >= C.N) { err = "member index out of range"; return FLOOD_EINVAL; }
-        if (!hh || !qx || !qy) { err = "h, qx and qy are required"; return FLOOD_EINVAL; }
-        if (!(tt >= 0.0) || !finite_d(tt)) { err = "t must be finite and >= 0"; return FLOOD_EINVAL; }
-        const int ny = C.ny, nx = C.nx;
-        for (size_t i = 0; i < (size_t)ny * nx; ++i)
-            if (!(hh[i] >= 0.0) || !finite_d(hh[i])) { err = "depths must be finite and >= 0"; return FLOOD_EINVAL; }
-        for (size_t i = 0; i < (size_t)ny * (nx + 1); ++i)
-            if (!finite_d(qx[i])) { err = "qx must be finite"; return FLOOD_EINVAL; }
-        for (size_t i = 0; i < (size_t)(ny + 1) * nx; ++i)
-            if (!finite_d(qy[i])) { err = "qy must be finite"; return FLOOD_EINVAL; }
-        // wall links carry no flow, except inflow links (edge-link order N, S, W, E)
-        auto wall = [&](int e, int at) {
-            return C.edge_kind[e] == FLOOD_EDGE_WALL && (C.h_inflow_id.empty() || C.h_inflow_id[at] < 0);
-        };
-        for (int r = 0; r < ny; ++r) {
-            if (wall(3, 2 * nx + r) && qx[(size_t)r * (nx + 1)] != 0.0) { err = "west wall link must be 0"; return FLOOD_EINVAL; }
-            if (wall(1, 2 * nx + ny + r) && qx[(size_t)r * (nx + 1) + nx] != 0.0) { err = "east wall link must be 0"; return FLOOD_EINVAL; }
-        }
-        for (int cc = 0; cc < nx; ++cc) {
-            if (wall(0, cc) && qy[cc] != 0.0) { err = "north wall link must be 0"; return FLOOD_EINVAL; }
-            if (wall(2, nx + cc) && qy[(size_t)ny * nx + cc] != 0.0) { err = "south wall link must be 0"; return FLOOD_EINVAL; }
-        }
+        CHK(check_state_args(C.ny, C.nx, C.edge_kind, C.h_inflow_id.empty() ? nullptr : C.h_inflow_id.data(), hh, qx,
+                             qy, tt, err));
         const int g = C.dev.member_off + m;
         int p;
         CHK(member_parity(g, &p, err));
@@ -1330,17 +1273,7 @@ template <typename T> struct Impl : ImplBase {
         CHK(check_catch(c, err));
         const Cat& C = cats[c];
         const size_t ncell = (size_t)C.ny * C.nx;
-        if (C.n_classes && (manning || n_scale)) {
-            err = "with land cover the roughness is per class and member; manning_n and n_scale do not apply";
-            return FLOOD_EINVAL;
-        }
-        if (manning)
-            for (size_t i = 0; i < ncell; ++i)
-                if (!(manning[i] > 0.0f) || !std::isfinite(manning[i])) { err = "manning_n must be finite and > 0"; return FLOOD_EINVAL; }
-        for (int m = 0; m < C.N; ++m) {
-            if (n_scale && (!(n_scale[m] > 0.0) || !finite_d(n_scale[m]))) { err = "n_scale must be finite and > 0"; return FLOOD_EINVAL; }
-            if (rain_mult && (!(rain_mult[m] >= 0.0) || !finite_d(rain_mult[m]))) { err = "rain_mult must be finite and >= 0"; return FLOOD_EINVAL; }
-        }
+        CHK(check_param_update(ncell, C.N, C.n_classes, manning, n_scale, rain_mult, err));
         HIPCHK(hipStreamSynchronize(st));
         if (manning) {
             std::vector<T> hn(ncell);
@@ -1511,23 +1444,10 @@ template <typename T> struct Impl : ImplBase {
                           double* prob_out, double* pct_out, std::string& err) override {
         CHK(check_catch(c, err));
         const Cat& C = cats[c];
-        if (!finite_d(threshold)) { err = "threshold must be finite"; return FLOOD_EINVAL; }
-        if (n_pct < 0 || n_pct > 16) { err = "n_pct must be in [0, 16]"; return FLOOD_EINVAL; }
-        if (n_pct > 0 && !pct) { err = "pct is NULL"; return FLOOD_EINVAL; }
-        for (int i = 0; i < n_pct; ++i)
-            if (!(pct[i] > 0.0 && pct[i] <= 1.0)) { err = "percentiles must be in (0, 1]"; return FLOOD_EINVAL; }
-        std::vector<double> w(C.N, 1.0);
+        std::vector<double> w;
+        CHK(check_products(C.N, threshold, n_pct, pct, weights, w, err));
         double W = 0.0;
-        if (weights)
-            for (int m = 0; m < C.N; ++m) {
-                if (!(weights[m] >= 0.0) || !finite_d(weights[m])) {
-                    err = "weights must be finite and >= 0";
-                    return FLOOD_EINVAL;
-                }
-                w[m] = weights[m];
-            }
         for (int m = 0; m < C.N; ++m) W += w[m];   // member order, as the kernel's sums
-        if (!(W > 0.0) || !finite_d(W)) { err = "weights must have a positive finite sum"; return FLOOD_EINVAL; }
         if (!C.dev.peak) {
             err = "the running maximum is kept only by handles created with track_peak = 1";
             return FLOOD_ESTATE;
@@ -1715,31 +1635,11 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                               std::string& err) {
     CHK(check_catch(c, err));
     Cat& C = cats[c];
-    if (C.n_classes) { err = "the adjoint does not support land cover"; return FLOOD_EINVAL; }
-    if (C.n_series) { err = "the adjoint does not support inflow links"; return FLOOD_EINVAL; }
-    if (!(sample_dt > 0.0) || !finite_d(sample_dt)) { err = "sample_dt must be finite and > 0"; return FLOOD_EINVAL; }
-    if (!finite_d(t_end)) { err = "t_end must be finite"; return FLOOD_EINVAL; }
-    if (K < 0 || K > 4096) { err = "n_gauges must be in [0, 4096]"; return FLOOD_EINVAL; }
-    if (K > 0 && (!grc || !obs)) { err = "gauge_rc and obs are required"; return FLOOD_EINVAL; }
-    if (ckpt_every < 1) { err = "ckpt_every must be >= 1"; return FLOOD_EINVAL; }
-    for (int k = 0; k < K; ++k)
-        if (grc[2 * k] < 0 || grc[2 * k] >= C.ny || grc[2 * k + 1] < 0 || grc[2 * k + 1] >= C.nx) {
-            err = "gauge outside the grid";
-            return FLOOD_EINVAL;
-        }
+    CHK(check_adjoint_args(C.ny, C.nx, C.n_classes, C.n_series, t_end, sample_dt, K, grc, obs, ckpt_every, err));
     double t0;
     CHK(common_time(c, &t0, err));
-    int gauges_distinct = 1;
-    {
-        std::vector<int64_t> cells(K);
-        for (int k = 0; k < K; ++k) cells[k] = (int64_t)grc[2 * k] * C.nx + grc[2 * k + 1];
-        std::sort(cells.begin(), cells.end());
-        for (int k = 1; k < K; ++k) gauges_distinct &= cells[k] != cells[k - 1];
-    }
-    const int S = (int)std::floor((t_end - t0) / sample_dt + 1e-9);
-    if (S < 1) { err = "no sample time in (t0, t_end]"; return FLOOD_EINVAL; }
-    for (size_t i = 0; i < (size_t)S * K; ++i)
-        if (!finite_d(obs[i])) { err = "obs must be finite"; return FLOOD_EINVAL; }
+    int S = 0, gauges_distinct = 1;
+    CHK(adjoint_samples(C.nx, t0, t_end, sample_dt, K, grc, obs, &S, &gauges_distinct, err));
 
     const size_t ncell = (size_t)C.ny * C.nx;
     const int N = C.N;

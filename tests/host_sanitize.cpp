@@ -1,0 +1,397 @@
+// Host-side argument validation of libflood, built without any device code and
+// run under AddressSanitizer and UndefinedBehaviorSanitizer on the CPU.
+//
+// Linked with the library's own flood_abi.cpp and flood_validate.cpp; the
+// device runtime is replaced by the stubs below (create_impl reports that there
+// is no device, the resampler is never reached), and a recording stand-in for
+// the handle's implementation shows which calls the C ABI lets through.  Every
+// rejected case must return FLOOD_EINVAL with a message and leave the stand-in
+// uncalled; every accepted one must reach it.  Exit status 0 when all hold.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "../include/flood.h"
+#include "../paper_2302_08341_amd/csrc/flood_runtime.h"
+#include "../paper_2302_08341_amd/csrc/flood_validate.h"
+
+namespace flood {
+flood_status create_impl(flood_handle*, int, const flood_grid*, const flood_params*, const int32_t*,
+                         const double* const*, const double* const*, hipStream_t, std::string& err) {
+    err = "no device in the host-only build";
+    return FLOOD_EHIP;
+}
+flood_status systematic_resample_impl(const double*, int, double, int32_t*, hipStream_t) { return FLOOD_EHIP; }
+flood_status systematic_resample_noalloc_impl(const double*, int, double, int32_t*, hipStream_t) { return FLOOD_EHIP; }
+}  // namespace flood
+
+static int g_fail = 0, g_cases = 0;
+static const double kNaN = std::numeric_limits<double>::quiet_NaN();
+static const double kInf = std::numeric_limits<double>::infinity();
+
+static void expect(bool ok, const char* what, int line) {
+    ++g_cases;
+    if (!ok) {
+        std::fprintf(stderr, "FAIL line %d: %s\n", line, what);
+        ++g_fail;
+    }
+}
+#define EXPECT(c) expect((c), #c, __LINE__)
+
+// the handle's implementation, recording how often it was reached
+struct Recorder : flood::ImplBase {
+    int calls = 0;
+    flood_status ok() { ++calls; return FLOOD_OK; }
+    flood_status step(double, int64_t, std::string&) override { return ok(); }
+    flood_status get_wet_mask(int, int, uint8_t*, uint8_t*, std::string&) override { return ok(); }
+    flood_status log_steps(int32_t, std::string&) override { return ok(); }
+    flood_status get_step_log(int, double*, double*, int64_t*, std::string&) override { return ok(); }
+    flood_status assimilate(int, int, const int32_t*, const double*, const double*, int, double, double, double,
+                            const double*, double*, int32_t*, int32_t*, std::string&) override { return ok(); }
+    flood_status set_sections(int, int, const int32_t*, const int32_t*, std::string&) override { return ok(); }
+    flood_status get_sections(int, double*, std::string&) override { return ok(); }
+    flood_status adjoint(int, double, double, int, const int32_t*, const double*, int, double*, double*, double*,
+                         std::string&) override { return ok(); }
+    flood_status adjoint_release(std::string&) override { return ok(); }
+    flood_status get_field(int, int, int, double*, std::string&) override { return ok(); }
+    flood_status set_state(int, int, const double*, const double*, const double*, double, std::string&) override { return ok(); }
+    flood_status set_params(int, const float*, const double*, const double*, std::string&) override { return ok(); }
+    flood_status get_ledger(int, double*, double*, double*, double*, double*, double*, double*, int64_t*,
+                            std::string&) override { return ok(); }
+    flood_status get_land_params(int, double*, double*, std::string&) override { return ok(); }
+    flood_status get_weights(int, double*, double*, double*, std::string&) override { return ok(); }
+    flood_status products(int, double, int, const double*, const double*, double*, double*, std::string&) override { return ok(); }
+    flood_status save(const char*, std::string&) override { return ok(); }
+    flood_status load(const char*, std::string&) override { return ok(); }
+    flood_status device_snapshot(int, std::string&) override { return ok(); }
+    void get_config(int32_t*, int32_t*, int32_t*, int32_t*, int32_t*, int32_t*, int32_t*, int32_t*) const override {}
+    flood_status timing(bool, std::string&) override { return ok(); }
+    void get_timing(double*, int64_t*) const override {}
+    void get_adjoint_info(int32_t*, int32_t*, int32_t*) const override {}
+};
+
+// a valid 3 x 4 catchment with every optional part switched on, which tests spoil one field at a time
+struct Setup {
+    int ny = 3, nx = 4;
+    std::vector<float> dem, man, h0;
+    std::vector<uint8_t> cls;
+    std::vector<double> rain{1e-5, 2e-5}, runoff{1.0, 0.5}, cn, drain, inq{0.1, 0.2}, ns, rm;
+    std::vector<int32_t> cdrain{0, 1}, inflow{3, 1, 0};
+    flood_grid g{};
+    flood_params p{};
+    int32_t members = 2;
+    Setup() {
+        dem.assign(ny * nx, 1.0f);
+        man.assign(ny * nx, 0.03f);
+        h0.assign(ny * nx, 0.0f);
+        cls.assign(ny * nx, 1);
+        cn.assign(members * 2, 0.03);
+        drain.assign(members, 1e-6);
+        ns.assign(members, 1.0);
+        rm.assign(members, 1.0);
+        g.ny = ny; g.nx = nx; g.dx = 2.0;
+        g.dem = dem.data(); g.manning_n = man.data(); g.h0 = h0.data();
+        for (int e = 0; e < 4; ++e) { g.edge_kind[e] = FLOOD_EDGE_WALL; g.edge_slope[e] = 0.0; }
+        g.edge_kind[1] = FLOOD_EDGE_OPEN; g.edge_slope[1] = 1e-3;
+        g.land_class = cls.data();
+        p.rain_rate = rain.data(); p.n_rain = 2; p.rain_interval = 300.0;
+        p.cfl_alpha = 0.7; p.h_dry = 1e-3; p.dt_cap = 5.0; p.dt_fixed = 0.0; p.g = 9.81;
+        p.real_bytes = 4; p.member_interleave = 0; p.tile_rows = 0; p.chunks_per_block = 0;
+        p.step_kernel = 0; p.march_rows = 0; p.march_members = 0; p.track_peak = 1;
+        p.n_classes = 2; p.class_runoff = runoff.data(); p.class_drain = cdrain.data();
+        p.member_class_n = cn.data(); p.member_drain = drain.data();
+        p.n_inflow = 1; p.inflow = inflow.data(); p.n_series = 1; p.inflow_q = inq.data();
+    }
+    flood_status create() {
+        const double* nsp[1] = {ns.data()};
+        const double* rmp[1] = {rm.data()};
+        flood_handle* h = reinterpret_cast<flood_handle*>(0x1);
+        const flood_status st = flood_create_batch(1, &g, &p, &members, nsp, rmp, nullptr, &h);
+        if (h != nullptr) std::fprintf(stderr, "out not cleared\n"), ++g_fail;
+        return st;
+    }
+};
+
+// a spoiled field must be refused with EINVAL and a message naming a reason
+#define REFUSED(mutation)                                                                  \
+    do {                                                                                   \
+        Setup s;                                                                           \
+        mutation;                                                                          \
+        const flood_status st_ = s.create();                                               \
+        expect(st_ == FLOOD_EINVAL && std::strlen(flood_last_error(nullptr)) > 0, #mutation, __LINE__); \
+    } while (0)
+
+static void creation() {
+    {
+        Setup s;
+        EXPECT(s.create() == FLOOD_EHIP);   // valid: validation passes, the stub reports no device
+        EXPECT(std::strcmp(flood_last_error(nullptr), "no device in the host-only build") == 0);
+        EXPECT(flood_create_batch(1, &s.g, &s.p, &s.members, nullptr, nullptr, nullptr, nullptr) == FLOOD_EINVAL);
+        flood_handle* h = nullptr;
+        EXPECT(flood_create_batch(0, &s.g, &s.p, &s.members, nullptr, nullptr, nullptr, &h) == FLOOD_EINVAL);
+        EXPECT(flood_create_batch(FLOOD_MAX_CATCHMENTS + 1, &s.g, &s.p, &s.members, nullptr, nullptr, nullptr, &h) ==
+               FLOOD_EINVAL);
+        EXPECT(flood_create_batch(1, nullptr, &s.p, &s.members, nullptr, nullptr, nullptr, &h) == FLOOD_EINVAL);
+        EXPECT(flood_create(&s.g, nullptr, 2, nullptr, nullptr, nullptr, &h) == FLOOD_EINVAL);
+        // two catchments that disagree on precision, interleave or kernel
+        flood_grid gg[2] = {s.g, s.g};
+        flood_params pp[2] = {s.p, s.p};
+        int32_t mm[2] = {2, 2};
+        pp[1].real_bytes = 8;
+        EXPECT(flood_create_batch(2, gg, pp, mm, nullptr, nullptr, nullptr, &h) == FLOOD_EINVAL);
+        pp[1] = s.p;
+        pp[1].step_kernel = 3;
+        EXPECT(flood_create_batch(2, gg, pp, mm, nullptr, nullptr, nullptr, &h) == FLOOD_EINVAL);
+        pp[1] = s.p;
+        EXPECT(flood_create_batch(2, gg, pp, mm, nullptr, nullptr, nullptr, &h) == FLOOD_EHIP);
+    }
+    // grid
+    REFUSED(s.g.ny = 0);
+    REFUSED(s.g.nx = -3);
+    REFUSED((s.g.ny = 1 << 15, s.g.nx = 1 << 14));
+    REFUSED(s.g.dx = 0.0);
+    REFUSED(s.g.dx = kInf);
+    REFUSED(s.g.dem = nullptr);
+    REFUSED(s.dem[5] = (float)kNaN);
+    REFUSED(s.man[0] = 0.0f);
+    REFUSED(s.man[11] = (float)kInf);
+    REFUSED(s.h0[3] = -1.0f);
+    REFUSED(s.g.edge_kind[2] = 7);
+    REFUSED(s.g.edge_slope[1] = 0.0);
+    REFUSED(s.g.edge_slope[1] = kNaN);
+    // forcing and numerics
+    REFUSED(s.p.n_rain = -1);
+    REFUSED(s.p.rain_rate = nullptr);
+    REFUSED(s.rain[1] = -1e-6);
+    REFUSED(s.rain[0] = kNaN);
+    REFUSED(s.p.rain_interval = 0.0);
+    REFUSED(s.p.g = 0.0);
+    REFUSED(s.p.h_dry = -1e-3);
+    REFUSED(s.p.dt_fixed = -0.5);
+    REFUSED(s.p.cfl_alpha = 1.5);
+    REFUSED(s.p.cfl_alpha = kNaN);
+    REFUSED(s.p.dt_cap = 0.0);
+    REFUSED(s.p.real_bytes = 2);
+    REFUSED(s.p.member_interleave = 3);
+    REFUSED(s.p.tile_rows = 16);
+    REFUSED(s.p.chunks_per_block = -1);
+    REFUSED(s.p.step_kernel = 4);
+    REFUSED((s.p.n_classes = 0, s.g.land_class = nullptr, s.p.n_inflow = 0, s.p.step_kernel = 2,
+             s.p.member_interleave = 2));
+    REFUSED(s.p.march_rows = 4097);
+    REFUSED(s.p.march_members = 3);
+    REFUSED(s.p.track_peak = 2);
+    // land cover
+    REFUSED(s.p.n_classes = 5);
+    REFUSED(s.p.class_runoff = nullptr);
+    REFUSED(s.runoff[1] = 1.5);
+    REFUSED(s.cdrain[0] = 2);
+    REFUSED(s.p.step_kernel = 1);
+    REFUSED(s.p.member_interleave = 2);
+    REFUSED(s.g.land_class = nullptr);
+    REFUSED((s.p.n_classes = 0, s.p.n_inflow = 0));
+    REFUSED(s.cls[7] = 2);
+    REFUSED(s.p.member_class_n = nullptr);
+    REFUSED(s.cn[3] = 0.0);
+    REFUSED(s.drain[1] = kNaN);
+    // inflow links
+    REFUSED(s.p.n_inflow = -1);
+    REFUSED(s.p.n_inflow = 2 * (3 + 4) + 1);
+    REFUSED(s.p.inflow = nullptr);
+    REFUSED(s.p.n_series = 0);
+    REFUSED(s.p.n_series = 5);
+    REFUSED(s.p.inflow_q = nullptr);
+    REFUSED(s.inq[1] = -0.1);
+    REFUSED(s.inflow[0] = 4);
+    REFUSED(s.inflow[1] = 3);                   // row 3 of a 3-row east/west edge
+    REFUSED(s.inflow[2] = 1);                   // series 1 of one
+    REFUSED((s.inflow = {3, 1, 0, 3, 1, 0}, s.p.inflow = s.inflow.data(), s.p.n_inflow = 2));
+    // members
+    REFUSED(s.members = 0);
+    REFUSED(s.members = FLOOD_MAX_MEMBERS + 1);
+    REFUSED(s.ns[0] = 0.0);
+    REFUSED(s.rm[1] = kNaN);
+    REFUSED(s.rm[0] = -1.0);
+}
+
+static void handle_calls() {
+    // calls without a handle
+    double d = 0.0;
+    int32_t i = 0;
+    int64_t l = 0;
+    EXPECT(flood_step(nullptr, 1.0) == FLOOD_EINVAL);
+    EXPECT(flood_step_n(nullptr, 1.0, 1) == FLOOD_EINVAL);
+    EXPECT(flood_get_field(nullptr, 0, 0, 0, &d) == FLOOD_EINVAL);
+    EXPECT(flood_save(nullptr, "x") == FLOOD_EINVAL);
+    EXPECT(flood_device_snapshot(nullptr, FLOOD_SNAPSHOT_TAKE) == FLOOD_EINVAL);
+    EXPECT(flood_get_config(nullptr, &i, &i, &i, &i, &i, &i, &i, &i) == FLOOD_EINVAL);
+    EXPECT(flood_get_timing(nullptr, &d, &l) == FLOOD_EINVAL);
+    EXPECT(flood_get_adjoint_info(nullptr, &i, &i, &i) == FLOOD_EINVAL);
+    flood_destroy(nullptr);
+    for (int st = 0; st >= -6; --st) EXPECT(std::strlen(flood_strerror(st)) > 0);
+
+    // calls on a handle: the ABI's own checks stop bad arguments before the implementation
+    flood_handle* h = new flood_handle();
+    Recorder* r = new Recorder();
+    h->impl.reset(r);
+    EXPECT(flood_step(h, kNaN) == FLOOD_EINVAL && r->calls == 0 && !h->err.empty());
+    EXPECT(flood_step(h, kInf) == FLOOD_EINVAL && r->calls == 0);
+    EXPECT(flood_step_n(h, 10.0, 0) == FLOOD_EINVAL && r->calls == 0);
+    EXPECT(flood_log_steps(h, -1) == FLOOD_EINVAL && r->calls == 0);
+    EXPECT(flood_log_steps(h, (1 << 24) + 1) == FLOOD_EINVAL && r->calls == 0);
+    EXPECT(flood_save(h, nullptr) == FLOOD_EINVAL && r->calls == 0);
+    EXPECT(flood_load(h, nullptr) == FLOOD_EINVAL && r->calls == 0);
+    EXPECT(flood_device_snapshot(h, 0) == FLOOD_EINVAL && r->calls == 0);
+    EXPECT(flood_device_snapshot(h, 4) == FLOOD_EINVAL && r->calls == 0);
+    EXPECT(flood_step(h, 10.0) == FLOOD_OK && r->calls == 1 && h->err.empty());   // a good call clears the message
+    EXPECT(flood_step_n(h, 10.0, 1) == FLOOD_OK && r->calls == 2);
+    EXPECT(flood_log_steps(h, 0) == FLOOD_OK && r->calls == 3);
+    EXPECT(flood_device_snapshot(h, FLOOD_SNAPSHOT_RELEASE) == FLOOD_OK && r->calls == 4);
+    flood_destroy(h);
+
+    // the resampler's checks run before any device work
+    std::vector<double> w{0.5, 0.25, 0.25};
+    std::vector<int32_t> anc(3);
+    EXPECT(flood_systematic_resample(nullptr, 3, 0.5, anc.data(), nullptr) == FLOOD_EINVAL);
+    EXPECT(flood_systematic_resample(w.data(), 0, 0.5, anc.data(), nullptr) == FLOOD_EINVAL);
+    EXPECT(flood_systematic_resample(w.data(), 3, 1.0, anc.data(), nullptr) == FLOOD_EINVAL);
+    EXPECT(flood_systematic_resample_noalloc(w.data(), FLOOD_MAX_MEMBERS + 1, 0.5, anc.data(), nullptr) == FLOOD_EINVAL);
+    w[1] = kNaN;
+    EXPECT(flood_systematic_resample(w.data(), 3, 0.5, anc.data(), nullptr) == FLOOD_EINVAL);
+    w.assign(3, 0.0);
+    EXPECT(flood_systematic_resample_noalloc(w.data(), 3, 0.5, anc.data(), nullptr) == FLOOD_EINVAL);
+    w.assign(3, 1e308);
+    EXPECT(flood_systematic_resample(w.data(), 3, 0.5, anc.data(), nullptr) == FLOOD_EINVAL);   // sum overflows
+    w.assign(3, 1.0);
+    EXPECT(flood_systematic_resample(w.data(), 3, 0.5, anc.data(), nullptr) == FLOOD_EHIP);     // reaches the stub
+}
+
+static void method_checks() {
+    using namespace flood;
+    std::string err;
+    const int ny = 3, nx = 4;
+    std::vector<double> h(ny * nx, 0.1), qx(ny * (nx + 1), 0.0), qy((ny + 1) * nx, 0.0);
+    const int32_t walls[4] = {FLOOD_EDGE_WALL, FLOOD_EDGE_OPEN, FLOOD_EDGE_WALL, FLOOD_EDGE_WALL};
+    std::vector<int8_t> inflow_id(2 * (nx + ny), -1);
+    EXPECT(check_state_args(ny, nx, walls, nullptr, h.data(), qx.data(), qy.data(), 10.0, err) == FLOOD_OK);
+    EXPECT(check_state_args(ny, nx, walls, nullptr, nullptr, qx.data(), qy.data(), 10.0, err) == FLOOD_EINVAL);
+    EXPECT(check_state_args(ny, nx, walls, nullptr, h.data(), qx.data(), qy.data(), -1.0, err) == FLOOD_EINVAL);
+    h[ny * nx - 1] = kNaN;
+    EXPECT(check_state_args(ny, nx, walls, nullptr, h.data(), qx.data(), qy.data(), 0.0, err) == FLOOD_EINVAL);
+    h[ny * nx - 1] = -0.5;
+    EXPECT(check_state_args(ny, nx, walls, nullptr, h.data(), qx.data(), qy.data(), 0.0, err) == FLOOD_EINVAL);
+    h[ny * nx - 1] = 0.1;
+    qx[nx] = 0.2;                                   // east edge of row 0: open, may carry flow
+    EXPECT(check_state_args(ny, nx, walls, nullptr, h.data(), qx.data(), qy.data(), 0.0, err) == FLOOD_OK);
+    qx[(nx + 1) * (ny - 1)] = 0.2;                  // west wall, last row
+    EXPECT(check_state_args(ny, nx, walls, nullptr, h.data(), qx.data(), qy.data(), 0.0, err) == FLOOD_EINVAL);
+    inflow_id[2 * nx + ny - 1] = 0;                 // ... unless it is an inflow link
+    EXPECT(check_state_args(ny, nx, walls, inflow_id.data(), h.data(), qx.data(), qy.data(), 0.0, err) == FLOOD_OK);
+    qy[ny * nx + 2] = -0.1;                         // south wall
+    EXPECT(check_state_args(ny, nx, walls, inflow_id.data(), h.data(), qx.data(), qy.data(), 0.0, err) == FLOOD_EINVAL);
+    qy[ny * nx + 2] = kInf;
+    EXPECT(check_state_args(ny, nx, walls, inflow_id.data(), h.data(), qx.data(), qy.data(), 0.0, err) == FLOOD_EINVAL);
+
+    std::vector<float> man(ny * nx, 0.03f);
+    std::vector<double> ns{1.0, 1.2}, rm{0.9, 1e300};
+    EXPECT(check_param_update(ny * nx, 2, 0, man.data(), ns.data(), rm.data(), err) == FLOOD_OK);   // large, finite
+    EXPECT(check_param_update(ny * nx, 2, 2, nullptr, nullptr, rm.data(), err) == FLOOD_OK);
+    EXPECT(check_param_update(ny * nx, 2, 2, man.data(), nullptr, nullptr, err) == FLOOD_EINVAL);
+    man[4] = -0.03f;
+    EXPECT(check_param_update(ny * nx, 2, 0, man.data(), nullptr, nullptr, err) == FLOOD_EINVAL);
+    rm[1] = kInf;
+    EXPECT(check_param_update(ny * nx, 2, 0, nullptr, nullptr, rm.data(), err) == FLOOD_EINVAL);
+    ns[0] = 0.0;
+    EXPECT(check_param_update(ny * nx, 2, 0, nullptr, ns.data(), nullptr, err) == FLOOD_EINVAL);
+
+    std::vector<int32_t> grc{0, 0, 2, 3};
+    std::vector<double> obs{0.1, 0.2, 5.0}, sig{0.01, 0.01, 0.1}, beta{1.0, 0.5};
+    EXPECT(check_observations(ny, nx, 2, 2, 1, grc.data(), obs.data(), sig.data(), 0.1, 0.5, 0.3, beta.data(), err) == FLOOD_OK);
+    EXPECT(check_observations(ny, nx, 2, -1, 0, grc.data(), obs.data(), sig.data(), 0.0, 0.5, 0.3, nullptr, err) == FLOOD_EINVAL);
+    EXPECT(check_observations(ny, nx, 2, 4000, 97, grc.data(), obs.data(), sig.data(), 0.0, 0.5, 0.3, nullptr, err) == FLOOD_EINVAL);
+    EXPECT(check_observations(ny, nx, 2, 2, 0, nullptr, obs.data(), sig.data(), 0.0, 0.5, 0.3, nullptr, err) == FLOOD_EINVAL);
+    EXPECT(check_observations(ny, nx, 2, 2, 0, grc.data(), obs.data(), nullptr, 0.0, 0.5, 0.3, nullptr, err) == FLOOD_EINVAL);
+    EXPECT(check_observations(ny, nx, 2, 2, 0, grc.data(), obs.data(), sig.data(), -1.0, 0.5, 0.3, nullptr, err) == FLOOD_EINVAL);
+    EXPECT(check_observations(ny, nx, 2, 2, 0, grc.data(), obs.data(), sig.data(), 0.0, 0.0, 0.3, nullptr, err) == FLOOD_EINVAL);
+    EXPECT(check_observations(ny, nx, 2, 2, 0, grc.data(), obs.data(), sig.data(), 0.0, 1.5, 0.3, nullptr, err) == FLOOD_EINVAL);
+    EXPECT(check_observations(ny, nx, 2, 2, 0, grc.data(), obs.data(), sig.data(), 0.0, 0.5, 1.0, nullptr, err) == FLOOD_EINVAL);
+    beta[1] = kNaN;
+    EXPECT(check_observations(ny, nx, 2, 2, 0, grc.data(), obs.data(), sig.data(), 0.0, 0.5, 0.3, beta.data(), err) == FLOOD_EINVAL);
+    sig[2] = 0.0;                                   // the section's error, only read when sections are observed
+    EXPECT(check_observations(ny, nx, 2, 2, 0, grc.data(), obs.data(), sig.data(), 0.0, 0.5, 0.3, nullptr, err) == FLOOD_OK);
+    EXPECT(check_observations(ny, nx, 2, 2, 1, grc.data(), obs.data(), sig.data(), 0.0, 0.5, 0.3, nullptr, err) == FLOOD_EINVAL);
+    obs[0] = kNaN;
+    EXPECT(check_observations(ny, nx, 2, 2, 0, grc.data(), obs.data(), sig.data(), 0.0, 0.5, 0.3, nullptr, err) == FLOOD_EINVAL);
+    obs[0] = 0.1;
+    grc[3] = nx;                                    // column nx is outside
+    EXPECT(check_observations(ny, nx, 2, 2, 0, grc.data(), obs.data(), sig.data(), 0.0, 0.5, 0.3, nullptr, err) == FLOOD_EINVAL);
+
+    // sections: two links of x, one of y; CSR offsets, direction codes and link indices
+    std::vector<int32_t> cnt{2, 1}, links{0, 1, 2, 1,  0, 1, 0, -1,  1, 3, 2, 1};
+    std::vector<int32_t> offs, code, index;
+    EXPECT(parse_sections(ny, nx, 2, cnt.data(), links.data(), offs, code, index, err) == FLOOD_OK);
+    EXPECT(offs == std::vector<int32_t>({0, 2, 3}));
+    EXPECT(code == std::vector<int32_t>({0, 2 | 4, 1}));
+    EXPECT(index == std::vector<int32_t>({1 * nx + 1, 1, 2 * nx + 2}));
+    EXPECT(parse_sections(ny, nx, 65, cnt.data(), links.data(), offs, code, index, err) == FLOOD_EINVAL);
+    EXPECT(parse_sections(ny, nx, 1, nullptr, links.data(), offs, code, index, err) == FLOOD_EINVAL);
+    links[3] = 0;                                   // sign
+    EXPECT(parse_sections(ny, nx, 2, cnt.data(), links.data(), offs, code, index, err) == FLOOD_EINVAL);
+    links[3] = 1;
+    links[9] = ny + 1;                              // y-link row beyond the south edge
+    EXPECT(parse_sections(ny, nx, 2, cnt.data(), links.data(), offs, code, index, err) == FLOOD_EINVAL);
+    links[9] = 3;
+    links[8] = 2;                                   // kind
+    EXPECT(parse_sections(ny, nx, 2, cnt.data(), links.data(), offs, code, index, err) == FLOOD_EINVAL);
+    cnt[1] = 0;
+    EXPECT(parse_sections(ny, nx, 2, cnt.data(), links.data(), offs, code, index, err) == FLOOD_EINVAL);
+    cnt[0] = 70000;
+    EXPECT(parse_sections(ny, nx, 1, cnt.data(), links.data(), offs, code, index, err) == FLOOD_EINVAL);
+
+    std::vector<double> pct{0.5, 1.0}, wts{1.0, 0.0, 2.0}, w;
+    EXPECT(check_products(3, 0.05, 2, pct.data(), wts.data(), w, err) == FLOOD_OK && w == wts);
+    EXPECT(check_products(3, 0.05, 0, nullptr, nullptr, w, err) == FLOOD_OK && w == std::vector<double>(3, 1.0));
+    EXPECT(check_products(3, kNaN, 0, nullptr, nullptr, w, err) == FLOOD_EINVAL);
+    EXPECT(check_products(3, 0.05, 17, pct.data(), nullptr, w, err) == FLOOD_EINVAL);
+    EXPECT(check_products(3, 0.05, 1, nullptr, nullptr, w, err) == FLOOD_EINVAL);
+    pct[0] = 0.0;
+    EXPECT(check_products(3, 0.05, 2, pct.data(), nullptr, w, err) == FLOOD_EINVAL);
+    wts.assign(3, 0.0);
+    EXPECT(check_products(3, 0.05, 0, nullptr, wts.data(), w, err) == FLOOD_EINVAL);
+    wts[1] = -1.0;
+    EXPECT(check_products(3, 0.05, 0, nullptr, wts.data(), w, err) == FLOOD_EINVAL);
+
+    grc = {0, 0, 2, 3, 0, 0};
+    std::vector<double> aobs(3 * 4, 0.2);
+    EXPECT(check_adjoint_args(ny, nx, 0, 0, 40.0, 10.0, 3, grc.data(), aobs.data(), 5, err) == FLOOD_OK);
+    EXPECT(check_adjoint_args(ny, nx, 2, 0, 40.0, 10.0, 3, grc.data(), aobs.data(), 5, err) == FLOOD_EINVAL);
+    EXPECT(check_adjoint_args(ny, nx, 0, 1, 40.0, 10.0, 3, grc.data(), aobs.data(), 5, err) == FLOOD_EINVAL);
+    EXPECT(check_adjoint_args(ny, nx, 0, 0, 40.0, 0.0, 3, grc.data(), aobs.data(), 5, err) == FLOOD_EINVAL);
+    EXPECT(check_adjoint_args(ny, nx, 0, 0, kInf, 10.0, 3, grc.data(), aobs.data(), 5, err) == FLOOD_EINVAL);
+    EXPECT(check_adjoint_args(ny, nx, 0, 0, 40.0, 10.0, 4097, grc.data(), aobs.data(), 5, err) == FLOOD_EINVAL);
+    EXPECT(check_adjoint_args(ny, nx, 0, 0, 40.0, 10.0, 3, grc.data(), nullptr, 5, err) == FLOOD_EINVAL);
+    EXPECT(check_adjoint_args(ny, nx, 0, 0, 40.0, 10.0, 3, grc.data(), aobs.data(), 0, err) == FLOOD_EINVAL);
+    int S = 0, distinct = -1;
+    EXPECT(adjoint_samples(nx, 0.0, 40.0, 10.0, 3, grc.data(), aobs.data(), &S, &distinct, err) == FLOOD_OK);
+    EXPECT(S == 4 && distinct == 0);               // gauge (0, 0) appears twice
+    EXPECT(adjoint_samples(nx, 0.0, 39.9, 10.0, 2, grc.data(), aobs.data(), &S, &distinct, err) == FLOOD_OK);
+    EXPECT(S == 3 && distinct == 1);
+    EXPECT(adjoint_samples(nx, 40.0, 40.0, 10.0, 2, grc.data(), aobs.data(), &S, &distinct, err) == FLOOD_EINVAL);
+    EXPECT(adjoint_samples(nx, 50.0, 40.0, 10.0, 2, grc.data(), aobs.data(), &S, &distinct, err) == FLOOD_EINVAL);
+    EXPECT(adjoint_samples(nx, 0.0, 1e12, 1e-3, 2, grc.data(), aobs.data(), &S, &distinct, err) == FLOOD_EINVAL);
+    aobs[3 * 3 - 1] = kNaN;                         // last observation of the third sample
+    EXPECT(adjoint_samples(nx, 0.0, 30.0, 10.0, 3, grc.data(), aobs.data(), &S, &distinct, err) == FLOOD_EINVAL);
+    EXPECT(adjoint_samples(nx, 0.0, 20.0, 10.0, 3, grc.data(), aobs.data(), &S, &distinct, err) == FLOOD_OK);
+}
+
+int main() {
+    creation();
+    handle_calls();
+    method_checks();
+    std::printf("host validation: %d cases, %d failed\n", g_cases, g_fail);
+    return g_fail ? 1 : 0;
+}

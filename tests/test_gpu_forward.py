@@ -380,3 +380,53 @@ def test_assimilate_requires_common_time(fl):
     with pytest.raises(fl.FloodError) as ei:
         e.assimilate(0, URBAN.gauges, np.zeros(4), np.full(4, 0.05))
     assert ei.value.status == fl.FLOOD_ESTATE
+
+
+@pytest.mark.parametrize("rb", [4, 8])
+def test_numeric_fault_freezes_one_member_and_spares_the_rest(fl, rb):
+    # a rain multiplier far beyond any physical storm drives one member's depth to
+    # a non-finite value; the step reports ENUMERIC, that member stays frozen at the
+    # step the fault was found, and the others go on exactly as in a clean run
+    rain = W.chicago_hyetograph()
+    bad = _ens(fl, URBAN, rain, 5, real_bytes=rb)
+    ref = _ens(fl, URBAN, rain, 5, real_bytes=rb)
+    bad.step(300.0)
+    ref.step(300.0)
+    bad.snapshot()
+    mu = URBAN.rain_mult[:5].copy()
+    mu[2] = 1e300
+    bad.set_params(rain_mult=mu)
+    with pytest.raises(fl.FloodError) as ei:
+        bad.step(600.0)
+    assert ei.value.status == fl.FLOOD_ENUMERIC
+    ref.step(600.0)
+    led = bad.ledger()
+    assert led["t"][2] < 600.0
+    assert np.all(led["t"][[0, 1, 3, 4]] == 600.0)
+    frozen = [bad.field(2, k) for k in (fl.FIELD_H, fl.FIELD_QX, fl.FIELD_QY)]
+    assert not np.all(np.isfinite(np.concatenate([f.ravel() for f in frozen])))
+    for i in (0, 1, 3, 4):
+        for k in (fl.FIELD_H, fl.FIELD_QX, fl.FIELD_QY):
+            np.testing.assert_array_equal(bad.field(i, k), ref.field(i, k))
+    # later calls keep reporting it; the frozen member does not move
+    with pytest.raises(fl.FloodError) as ei:
+        bad.step(900.0)
+    assert ei.value.status == fl.FLOOD_ENUMERIC
+    ref.step(900.0)
+    assert bad.ledger()["t"][2] == led["t"][2]
+    for k, f in zip((fl.FIELD_H, fl.FIELD_QX, fl.FIELD_QY), frozen):
+        np.testing.assert_array_equal(bad.field(2, k), f)
+    for i in (0, 1, 3, 4):
+        np.testing.assert_array_equal(bad.field(i), ref.field(i))
+    # the filter refuses a faulted catchment
+    with pytest.raises(fl.FloodError) as ei:
+        bad.assimilate(0, URBAN.gauges, np.zeros(len(URBAN.gauges)), np.full(len(URBAN.gauges), 1e-2))
+    assert ei.value.status == fl.FLOOD_ESTATE
+    # the device snapshot brings back the clean state, parameters and status
+    bad.restore()
+    ref2 = _ens(fl, URBAN, rain, 5, real_bytes=rb)
+    ref2.step(300.0)
+    bad.step(600.0)
+    ref2.step(600.0)
+    for i in range(5):
+        np.testing.assert_array_equal(bad.field(i), ref2.field(i))
