@@ -44,7 +44,8 @@ typedef int32_t flood_status;
 #define FLOOD_ENOMEM (-2)   /* device or pinned host allocation failed */
 #define FLOOD_EHIP (-3)     /* a HIP runtime call failed (no device, launch error) */
 #define FLOOD_ESTATE (-4)   /* call not valid in the handle's current state */
-#define FLOOD_ENUMERIC (-5) /* a member produced a non-finite depth; it is frozen */
+#define FLOOD_ENUMERIC (-5) /* a member's depth became non-finite, or so large that its Eq. 4 step no
+                               longer advances its clock (t + dt == t); that member is frozen */
 
 #define FLOOD_EDGE_WALL 0   /* zero-flux edge (Sec. 4.1 Neumann walls) */
 #define FLOOD_EDGE_OPEN 1   /* free outflow with a fixed outward surface slope */
@@ -149,8 +150,9 @@ flood_status flood_create_batch(int32_t n_catch, const flood_grid* grids, const 
  * clipped so that a step ends exactly on every rain-block edge and on t_end.
  * Members already at or beyond t_end are left unchanged.
  * Errors: EINVAL (t_end not finite), ESTATE (handle faulted), ENUMERIC (a
- * member produced a non-finite depth; it stays frozen and the others still
- * reach t_end), EHIP. */
+ * member's depth became non-finite or too large for its step to advance its
+ * clock; it stays frozen, the others still reach t_end, and later calls keep
+ * reporting it until a snapshot is restored), EHIP. */
 flood_status flood_step(flood_handle* h, double t_end);
 
 /* flood_step with a bound: every member takes at most max_steps (>= 1) more

@@ -33,7 +33,7 @@ const char* status_name(flood_status s) {
         case FLOOD_ENOMEM: return "out of memory";
         case FLOOD_EHIP: return "HIP runtime error";
         case FLOOD_ESTATE: return "invalid state for this call";
-        case FLOOD_ENUMERIC: return "non-finite depth";
+        case FLOOD_ENUMERIC: return "non-finite or runaway depth";
         default: return "unknown status";
     }
 }

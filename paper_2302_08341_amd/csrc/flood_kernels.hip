@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
         hb = o > hb ? o : hb;
     }
     const T H = from_bits<T>(hb);
-    if (!(H <= (sizeof(T) == 4 ? T(FLT_MAX) : T(DBL_MAX)))) {
+    const auto freeze = [&]() {
         if (w0) {
             P.fault[m] = 1;
             atomicOr(P.status, 1);
@@ -88,6 +88,9 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
                 P.tag_log[lm] = -1;
             }
         }
+    };
+    if (!(H <= (sizeof(T) == 4 ? T(FLT_MAX) : T(DBL_MAX)))) {
+        freeze();
         return;
     }
     double dt;
@@ -111,6 +114,12 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
         tn = tev;
     } else {
         tn = t + dt;
+    }
+    if (!(tn > t)) {
+        // an Eq. 4 step below the resolution of the member's clock (a depth so
+        // large that the member can no longer advance): a numeric fault too
+        freeze();
+        return;
     }
     // every lane has read its bin: clear it for the step's new maximum
     P.hbins[(size_t)lane * P.n_total + m] = 0;

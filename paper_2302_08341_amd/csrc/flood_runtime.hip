@@ -980,7 +980,7 @@ template <typename T> struct Impl : ImplBase {
         // status words of the batches this call launched (slot 1 only when more than one batch ran)
         const int stat = h_count[2 * (slot ^ 1) + 1] | h_count[2 * slot + 1];
         if (stat) {
-            err = "a member produced a non-finite depth and was frozen";
+            err = "a member's depth became non-finite or too large to advance its clock; it was frozen";
             return FLOOD_ENUMERIC;
         }
         return FLOOD_OK;
@@ -2001,7 +2001,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                 wait_slot ^= 1;
                 if (stat) {
                     HIPCHK(hipStreamSynchronize(st));
-                    err = "a member produced a non-finite depth during the adjoint forward";
+                    err = "a member's depth became non-finite or too large to advance its clock during the adjoint forward";
                     return FLOOD_ENUMERIC;
                 }
                 if (active == 0) {
@@ -2143,7 +2143,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                 HIPCHK(hipMemcpyAsync(h_count, d_count, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
                 HIPCHK(hipStreamSynchronize(st));
                 if (h_count[1]) {
-                    err = "a member produced a non-finite depth during the adjoint forward";
+                    err = "a member's depth became non-finite or too large to advance its clock during the adjoint forward";
                     return FLOOD_ENUMERIC;
                 }
                 if (h_count[0] == 0) break;

@@ -385,7 +385,9 @@ def test_assimilate_requires_common_time(fl):
 @pytest.mark.parametrize("rb", [4, 8])
 def test_numeric_fault_freezes_one_member_and_spares_the_rest(fl, rb):
     # a rain multiplier far beyond any physical storm drives one member's depth to
-    # a non-finite value; the step reports ENUMERIC, that member stays frozen at the
+    # a non-finite value, or to one so large that its Eq. 4 step no longer moves its
+    # clock (1e300 in double precision stays finite: 1e295 m after one step, then
+    # steps of 1e-148 s); the step reports ENUMERIC, that member stays frozen at the
     # step the fault was found, and the others go on exactly as in a clean run
     rain = W.chicago_hyetograph()
     bad = _ens(fl, URBAN, rain, 5, real_bytes=rb)
@@ -394,7 +396,7 @@ def test_numeric_fault_freezes_one_member_and_spares_the_rest(fl, rb):
     ref.step(300.0)
     bad.snapshot()
     mu = URBAN.rain_mult[:5].copy()
-    mu[2] = 1e300
+    mu[2] = 1e38 if rb == 4 else 1e300
     bad.set_params(rain_mult=mu)
     with pytest.raises(fl.FloodError) as ei:
         bad.step(600.0)
@@ -404,7 +406,7 @@ def test_numeric_fault_freezes_one_member_and_spares_the_rest(fl, rb):
     assert led["t"][2] < 600.0
     assert np.all(led["t"][[0, 1, 3, 4]] == 600.0)
     frozen = [bad.field(2, k) for k in (fl.FIELD_H, fl.FIELD_QX, fl.FIELD_QY)]
-    assert not np.all(np.isfinite(np.concatenate([f.ravel() for f in frozen])))
+    assert not np.all(np.isfinite(frozen[0])) or np.nanmax(frozen[0]) > 1e30
     for i in (0, 1, 3, 4):
         for k in (fl.FIELD_H, fl.FIELD_QX, fl.FIELD_QY):
             np.testing.assert_array_equal(bad.field(i, k), ref.field(i, k))

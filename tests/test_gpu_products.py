@@ -151,7 +151,7 @@ def test_device_snapshot_restores_what_a_file_snapshot_restores(fl):
     path = os.path.join(tempfile.mkdtemp(), "snap.bin")
     e.save(path)
     obs = e.field(3)[CAT.gauges[:, 0], CAT.gauges[:, 1]]
-    e.assimilate(0, CAT.gauges, obs, np.full(4, 1e-5), 1.0, 1.0)
+    e.assimilate(0, CAT.gauges, obs, np.full(4, 1e-5), 1.0, 0.3)
     e.step(1300.0)
     e.restore()
     f = _ens(fl, real_bytes=4, track_peak=True)
