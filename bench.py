@@ -10,18 +10,24 @@ simulated time (adaptive Eq. 4 steps, one fused kernel launch per step for
 all members) followed by the filter update (gauge gather, weights, N_eff,
 systematic resampling and member copy when N_eff < 0.8 N).  Observations
 come from a hidden truth member run beforehand plus N(0, 0.05^2) noise.
+Every cycle lies inside the one-hour storm: after its sixth window the
+ensemble restarts from its initial state (a device snapshot taken at t = 0,
+restored on the device inside the timed region), so cycle k covers window
+k mod 6.
 
 `value` is member-cell-updates per second (MCU/s) over the timed cycles,
-counted from the per-member step counters, filter updates included.  The JSON
-line also carries the roofline of the step kernel (HIP-event durations of
-every step launch in the timed region), the FP64 oracle timed on the host
-cores, and in `detail` the other parts of the metric, each outside the timed
-region:
+counted from the per-member step counters, filter updates and restarts
+included, on the library's captured-graph path.  The JSON line also carries
+the roofline of the step kernel (HIP events around every captured batch of
+steps in the timed region, so the duration per step launch holds the step's
+small planner kernel too), the FP64 oracle timed on the host cores, and in
+`detail` the other parts of the metric, each outside the timed region:
   * step kernels alone (MCU over summed kernel time);
   * forward + adjoint over the first 900 s of the same ensemble (Manning-field
     and rain-multiplier gradients of a 10-s gauge misfit, checkpoints every
-    100 steps) against the forward alone over the same window, one handle
-    each, timed twice in turns from the dry state and compared by their means;
+    1024 steps, so that each member group's tape is one segment) against the
+    forward alone over the same window, one handle each, timed twice in turns
+    from the dry state and compared by their means;
   * batched against plain (one handle and one launch per member) on this
     workload over its first window, and on the four-catchment batch
     (512^2, 768x1536, 1024^2, 2000^2, 24 members each) over its first 300 s;
@@ -80,6 +86,18 @@ def _cpu_worker(args):
     return n * c.ny * c.nx, el
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(cfg, cores, n_steps):
     ctx = mp.get_context("spawn")
     jobs = [(cfg, i % cfg["members"], n_steps) for i in range(cores)]
@@ -100,6 +118,7 @@ def cpu_baseline(cfg, cores, n_steps):
     mcu = sum(r[0] for r in res)
     busy = max(r[1] for r in res)
     return {"value": mcu / busy, "unit": "MCU/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": "FP64 serial oracle, one process per core, each running one member of the same "
                       "workload for its first %d steps from the dry start (%d member-runs, %.1f s per "
                       "process, %.1f s wall incl. start-up)" % (n_steps, cores, busy, wall)}
@@ -121,9 +140,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload_tag):
+def measured_traffic(kernel, workload_tag, alg_bytes=None):
     """HBM bytes per launch from the committed counter summary of this kernel and
-    workload, if it was taken on the current kernel sources; else None."""
+    workload, if it was taken on the current kernel sources, and (given this
+    run's algorithmic bytes per launch) on the same timed launches, i.e. the
+    summary's own algorithmic bytes per launch agree within 0.5 %; else None."""
     path = os.path.join(ROOT, "profiles", "%s_%s_traffic.md" % (kernel, workload_tag))
     if not os.path.exists(path):
         return None
@@ -136,7 +157,12 @@ def measured_traffic(kernel, workload_tag):
     if vals.get("kernel_sources_sha256") != kernel_source_hash():
         return None
     try:
-        return float(vals["traffic_bytes_per_launch"])
+        traffic = float(vals["traffic_bytes_per_launch"])
+        if alg_bytes is not None:
+            own = float(vals["algorithmic_bytes_per_launch"])
+            if abs(own - alg_bytes) > 0.005 * alg_bytes:
+                return None
+        return traffic
     except (KeyError, ValueError):
         return None
 
@@ -148,10 +174,10 @@ def ensemble_args(c, members, n_scale=None, rain_mult=None):
                 rain_mult=c.rain_mult[members] if rain_mult is None else rain_mult)
 
 
-def truth_observations(FloodEnsemble, W, wl, times, rng):
+def truth_depths(FloodEnsemble, wl, times):
     """Gauge depths of a hidden truth member (drawn from the same prior) at the
-    given times plus N(0, sigma^2) noise.  Runs on the tiled kernel so that the
-    step kernel measured below sees only ensemble launches."""
+    given times.  Runs on the tiled kernel so that the step kernel measured below
+    sees only ensemble launches."""
     c = wl.catchments[0]
     truth = FloodEnsemble([ensemble_args(c, None, [c.truth_n_scale], [c.truth_rain_mult])], wl.rain,
                           rain_interval=wl.rain_interval, real_bytes=wl.real_bytes, step_kernel=1,
@@ -159,8 +185,7 @@ def truth_observations(FloodEnsemble, W, wl, times, rng):
     out = {}
     for t in sorted(times):
         truth.step(t)
-        hv = truth.field(0)[c.gauges[:, 0], c.gauges[:, 1]]
-        out[t] = W.obs_noise(rng, hv, wl.obs_sigma)
+        out[t] = truth.field(0)[c.gauges[:, 0], c.gauges[:, 1]]
     truth.close()
     return out
 
@@ -413,7 +438,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adj-window", type=float, default=900.0)
     ap.add_argument("--adj-sample", type=float, default=10.0)
-    ap.add_argument("--adj-ckpt", type=int, default=100)
+    ap.add_argument("--adj-ckpt", type=int, default=1024)
     ap.add_argument("--adj-reps", type=int, default=2, help="forward and forward + adjoint runs, in turns")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-members", type=int, default=8)
@@ -469,16 +494,22 @@ def main():
     K = c.gauges.shape[0]
     sigma = np.full(K, wl.obs_sigma)
     n_cycles = args.warmup + args.steps
-    win_times = [(k + 1) * args.window for k in range(n_cycles)]
+    # the storm hour holds n_win windows; cycle k covers window k mod n_win and a
+    # cycle at window 0 after the first restarts from the initial state
+    n_win = max(1, int(round(wl.t_end / args.window)))
+    hour_times = [(j + 1) * args.window for j in range(n_win)]
+    win_times = [hour_times[k % n_win] for k in range(n_cycles)]
     n_adj = int(round(args.adj_window / args.adj_sample))
     adj_times = [(i + 1) * args.adj_sample for i in range(n_adj)] if not args.no_adjoint else []
     log("workload ready: %d x %d cells x %d members" % (c.ny, c.nx, N))
     # the filter's observations and draws have their own truth run and random stream,
     # so the timed cycles are the same whichever other legs run
     rng = np.random.default_rng(wl.seed + 7)
-    obs_all = truth_observations(FloodEnsemble, W, wl, win_times, rng)
+    truth = truth_depths(FloodEnsemble, wl, hour_times)
+    obs_all = [W.obs_noise(rng, truth[win_times[k]], wl.obs_sigma) for k in range(n_cycles)]
     draws = [W.pf_draws(rng, N) for _ in range(n_cycles)]
-    obs_adj = (truth_observations(FloodEnsemble, W, wl, adj_times, np.random.default_rng(wl.seed + 8))
+    rng_adj = np.random.default_rng(wl.seed + 8)
+    obs_adj = ({t: W.obs_noise(rng_adj, v, wl.obs_sigma) for t, v in truth_depths(FloodEnsemble, wl, adj_times).items()}
                if adj_times else {})
     log("truth observations done")
     detail = {}
@@ -500,13 +531,19 @@ def main():
                                       chunks_per_block=args.cpb, step_kernel=args.kernel,
                                       march_rows=args.march_rows, march_members=args.march_members)
     conf = ens.config()
+    ens.snapshot()             # the initial state, restored at the start of every later storm hour
     log("ensemble ready, step kernel %d" % conf["step_kernel"])
     resampled = []
     cycle_log = []
     n_plain = 0 if (args.no_plain or args.kernel_only) else min(args.plain_members, N)
     snap = {}
 
+    restarts = []
+
     def cycle(k):
+        if k and k % n_win == 0:
+            ens.restore()
+            restarts.append(k)
         s0 = int(ens.ledger()["steps"].sum())
         t0 = time.perf_counter()
         ens.step(win_times[k])
@@ -516,10 +553,11 @@ def main():
             for m in range(n_plain):
                 snap[m] = ens.field(m)
         u0, beta = draws[k]
-        neff, anc, res = ens.assimilate(0, c.gauges, obs_all[win_times[k]], sigma, 0.8, u0, beta)
+        neff, anc, res = ens.assimilate(0, c.gauges, obs_all[k], sigma, 0.8, u0, beta)
         t2 = time.perf_counter()
         resampled.append(bool(res))
-        cycle_log.append({"step_s": t1 - t0, "filter_s": t2 - t1, "member_steps": s1 - s0, "neff": float(neff)})
+        cycle_log.append({"window_end_s": win_times[k], "step_s": t1 - t0, "filter_s": t2 - t1,
+                          "member_steps": s1 - s0, "neff": float(neff)})
 
     for k in range(args.warmup):
         cycle(k)
@@ -527,12 +565,12 @@ def main():
     log("warm-up done")
     if args.kernel_only:
         # every launch steps every member: single steps of 0.02 s, shorter than Eq. 4 allows here
-        t = args.warmup * args.window
+        t = win_times[args.warmup - 1] if args.warmup else 0.0
         l0 = ens.ledger()
-        ens.timing(True)
+        ens.timing(1)          # an event pair around every step launch
         for i in range(args.kernel_only):
             ens.step(t + 0.02 * (i + 1))
-        ens.timing(False)
+        ens.timing(0)
         l1 = ens.ledger()
         avg_ms, launches = ens.get_timing()
         steps = int((l1["steps"] - l0["steps"]).sum())
@@ -543,9 +581,8 @@ def main():
                           "elementwise_copy_GBps": elementwise_ceiling(torch), "config": ens.config()}))
         return
 
-    led0 = ens.ledger()
     if not args.no_kernel_timing:
-        ens.timing(True)
+        ens.timing(2)          # an event pair around every captured batch; the graph path stays on
     torch.cuda.synchronize()
     clocks = ClockSampler().start()
     t0 = time.perf_counter()
@@ -555,12 +592,13 @@ def main():
     elapsed = time.perf_counter() - t0
     clock_stats = clocks.stop()
     if not args.no_kernel_timing:
-        ens.timing(False)
+        ens.timing(0)
     led1 = ens.ledger()
     avg_ms, launches = ens.get_timing()
     log("timed cycles done: %.2f s" % elapsed)
 
-    member_steps = int((led1["steps"] - led0["steps"]).sum())
+    # per-cycle counts: a restart sets the ledger's step counters back with the state
+    member_steps = int(sum(cl["member_steps"] for cl in cycle_log[args.warmup:]))
     mcu = member_steps * ncell
     value = mcu / elapsed
     mass = float(np.max(np.abs(led1["storage"] - (led1["rain_in"] - led1["outflow"] + led1["clamp"]))
@@ -574,15 +612,19 @@ def main():
         mcu_per_launch = mcu / launches
         alg_bytes = BYTES_PER_MCU * mcu_per_launch
         achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
-        traffic = measured_traffic(kname, workload_tag)
+        traffic = measured_traffic(kname, workload_tag, alg_bytes)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": KERNEL_TITLES.get(conf["step_kernel"], kname),
                 "avg_launch_ms": round(avg_ms, 4), "launches": launches,
+                "timing": "HIP events around each captured batch of %d steps on the graph path; the time per "
+                          "step launch holds the step kernel, its planner kernel and the gaps between them"
+                          % conf["graph_steps"] if conf.get("graph_steps") else
+                          "HIP events around each batch of step launches",
                 "algorithmic_bytes_per_launch": round(alg_bytes),
                 "traffic_over_algorithmic": round(traffic / alg_bytes, 3) if traffic else None,
                 "kernel_sources_sha256": kernel_source_hash()}
-        detail["kernel_only_MCUps"] = mcu / (launches * avg_ms * 1e-3)
+        detail["step_launches_only_MCUps"] = mcu / (launches * avg_ms * 1e-3)
 
     if n_plain:
         # plain: one handle and one launch per member over the first window
@@ -610,7 +652,8 @@ def main():
     detail["copy_ceiling_GBps"] = elementwise_ceiling(torch)
     detail["gpu_clock_in_timed_region"] = clock_stats
     detail.update({"member_steps": member_steps, "mcu": mcu, "elapsed_s": elapsed, "cycles": cycle_log[args.warmup:],
-                   "resampled": resampled[args.warmup:], "mass_balance_rel": mass,
+                   "resampled": resampled[args.warmup:], "restarts_at_cycles": restarts,
+                   "mass_balance_rel_since_last_restart": mass,
                    "paper_context": "8x P100: 4.69e10 MCU/s (96 x 4.0 M cells x 14,400 steps in 118 s)"})
 
     out = {
@@ -629,7 +672,7 @@ def main():
         "config": {"workload": "urban %dx%d cells x %d members, FP32, PF every %.0f s (%d gauges); one step = "
                                "one %.0f s assimilation cycle" % (c.ny, c.nx, N, args.window, K, args.window),
                    "cells": ncell, "members": N, "window_s": args.window,
-                   "sim_time_s": [args.warmup * args.window, n_cycles * args.window],
+                   "storm_s": wl.t_end, "timed_windows_end_s": win_times[args.warmup:],
                    "member_interleave": conf["member_interleave"], "tile_rows": conf["tile_rows"],
                    "chunks_per_block": conf["chunks_per_block"], "step_kernel": conf["step_kernel"],
                    "march_rows": conf["march_rows"], "march_members": conf["march_members"],

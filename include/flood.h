@@ -382,11 +382,19 @@ flood_status flood_get_config(const flood_handle* h, int32_t* member_interleave,
                               int32_t* chunks_per_block, int32_t* graph_steps, int32_t* step_kernel,
                               int32_t* march_rows, int32_t* march_members, int32_t* march_order);
 
-/* Average duration in ms of the step kernel over the timed region opened by
- * flood_timing(h, 1) and closed by flood_timing(h, 0); per-launch HIP events
- * on the handle's stream.  *launches receives the number of step launches. */
-flood_status flood_timing(flood_handle* h, int32_t enable);
-flood_status flood_get_timing(const flood_handle* h, double* avg_step_kernel_ms, int64_t* launches);
+/* Timing of the step launches of flood_step calls between flood_timing(h,
+ * mode) and flood_timing(h, 0), with HIP events on the handle's stream.
+ * FLOOD_TIMING_LAUNCH: an event pair around every step kernel launch (the
+ * captured graph path is off meanwhile), so the average is the step kernel's
+ * own duration.  FLOOD_TIMING_BATCH: an event pair around every batch of
+ * graph_steps steps (flood_get_config), the graph path kept; the average per
+ * step then also holds each step's planner kernel and the gaps between the
+ * batch's kernels.  flood_get_timing gives the average per step launch in ms
+ * and the number of step launches.  Errors: EINVAL (mode), EHIP. */
+#define FLOOD_TIMING_LAUNCH 1
+#define FLOOD_TIMING_BATCH 2
+flood_status flood_timing(flood_handle* h, int32_t mode);
+flood_status flood_get_timing(const flood_handle* h, double* avg_step_ms, int64_t* launches);
 
 const char* flood_last_error(const flood_handle* h); /* NULL h: last creation error of this thread */
 const char* flood_strerror(flood_status s);

@@ -426,9 +426,13 @@ flood_status flood_get_adjoint_info(const flood_handle* h, int32_t* groups, int3
     return FLOOD_OK;
 }
 
-flood_status flood_timing(flood_handle* h, int32_t enable) {
+flood_status flood_timing(flood_handle* h, int32_t mode) {
     FLOOD_NEED_HANDLE(h);
-    return h->impl->timing(enable != 0, h->err);
+    if (mode != 0 && mode != FLOOD_TIMING_LAUNCH && mode != FLOOD_TIMING_BATCH) {
+        h->err = "mode must be 0, FLOOD_TIMING_LAUNCH or FLOOD_TIMING_BATCH";
+        return FLOOD_EINVAL;
+    }
+    return h->impl->timing(mode, h->err);
 }
 
 flood_status flood_get_timing(const flood_handle* h, double* avg_ms, int64_t* launches) {

@@ -46,7 +46,7 @@ struct ImplBase {
     virtual flood_status device_snapshot(int op, std::string& err) = 0;
     virtual void get_config(int32_t* mi, int32_t* tile_rows, int32_t* cpb, int32_t* gsteps, int32_t* step_kernel,
                             int32_t* march_rows, int32_t* march_members, int32_t* march_order) const = 0;
-    virtual flood_status timing(bool on, std::string& err) = 0;
+    virtual flood_status timing(int mode, std::string& err) = 0;
     virtual void get_timing(double* avg_ms, int64_t* launches) const = 0;
     virtual void get_adjoint_info(int32_t* groups, int32_t* group_size, int32_t* segments) const = 0;
 };

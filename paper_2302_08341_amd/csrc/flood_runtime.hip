@@ -118,7 +118,9 @@ template <typename T> struct Impl : ImplBase {
     bool use_graph = true;
 
     // kernel timing
-    bool timing_on = false;
+    bool timing_on = false;      // per-launch events (graph capture off while on)
+    bool timing_batch = false;   // events around each batch of G steps (graph path kept)
+    std::vector<int32_t> tev_steps;   // step launches between each pair of events
     std::vector<hipEvent_t> tev;
     size_t tev_used = 0;
     double t_ms = 0.0;
@@ -909,18 +911,29 @@ template <typename T> struct Impl : ImplBase {
         return FLOOD_OK;
     }
 
+    flood_status next_event_pair(int32_t launches) {
+        while (tev.size() < tev_used + 2) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return FLOOD_EHIP;
+            tev.push_back(e);
+        }
+        if (tev_steps.size() < tev_used / 2 + 1) tev_steps.resize(tev_used / 2 + 1);
+        tev_steps[tev_used / 2] = launches;
+        return FLOOD_OK;
+    }
+
     flood_status launch_batch(int slot, std::string& err) {
+        if (timing_batch) {
+            if (next_event_pair(G)) { err = "hipEventCreate failed"; return FLOOD_EHIP; }
+            HIPCHK(hipEventRecord(tev[tev_used], st));
+        }
         if (gexec && !timing_on) {
             HIPCHK(hipGraphLaunch(gexec, st));
         } else {
             for (int i = 0; i < G; ++i) {
                 launch_plan<T>(PL, st);
                 if (timing_on) {
-                    while (tev.size() < tev_used + 2) {
-                        hipEvent_t e;
-                        HIPCHK(hipEventCreate(&e));
-                        tev.push_back(e);
-                    }
+                    if (next_event_pair(1)) { err = "hipEventCreate failed"; return FLOOD_EHIP; }
                     HIPCHK(hipEventRecord(tev[tev_used], st));
                     launch_steps(SL);
                     HIPCHK(hipEventRecord(tev[tev_used + 1], st));
@@ -929,6 +942,10 @@ template <typename T> struct Impl : ImplBase {
                     launch_steps(SL);
                 }
             }
+        }
+        if (timing_batch) {
+            HIPCHK(hipEventRecord(tev[tev_used + 1], st));
+            tev_used += 2;
         }
         launch_count_active(n_total, t, fault, d_tend, status, steps, step_lim, d_count, st);
         HIPCHK(hipGetLastError());
@@ -968,12 +985,12 @@ template <typename T> struct Impl : ImplBase {
             }
         }
         HIPCHK(hipStreamSynchronize(st));
-        if (timing_on) {
+        if (timing_on || timing_batch) {
             for (size_t i = 0; i < tev_used; i += 2) {
                 float el = 0;
                 HIPCHK(hipEventElapsedTime(&el, tev[i], tev[i + 1]));
                 t_ms += el;
-                t_launches += 1;
+                t_launches += tev_steps[i / 2];
             }
             tev_used = 0;
         }
@@ -1559,14 +1576,15 @@ template <typename T> struct Impl : ImplBase {
         if (mr) *mr = std::min(cats[0].march_rows, cats[0].ny);
     }
 
-    flood_status timing(bool on, std::string& err) override {
+    flood_status timing(int mode, std::string& err) override {
         HIPCHK(hipStreamSynchronize(st));
-        if (on) {
+        if (mode) {
             t_ms = 0.0;
             t_launches = 0;
             tev_used = 0;
         }
-        timing_on = on;
+        timing_on = mode == FLOOD_TIMING_LAUNCH;
+        timing_batch = mode == FLOOD_TIMING_BATCH;
         return FLOOD_OK;
     }
 

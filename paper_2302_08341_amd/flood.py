@@ -416,8 +416,13 @@ def flood_adjoint_release(h):
     _check(load_library().flood_adjoint_release(h), h)
 
 
-def flood_timing(h, enable):
-    _check(load_library().flood_timing(h, 1 if enable else 0), h)
+TIMING_LAUNCH, TIMING_BATCH = 1, 2
+
+
+def flood_timing(h, mode):
+    """mode: 0 / False off, 1 / True an event pair per step launch (graph path off),
+    2 an event pair per captured batch of steps (graph path kept)."""
+    _check(load_library().flood_timing(h, int(mode)), h)
 
 
 def flood_get_timing(h):
@@ -588,8 +593,8 @@ class FloodEnsemble:
     def config(self):
         return flood_get_config(self.h)
 
-    def timing(self, enable):
-        flood_timing(self.h, enable)
+    def timing(self, mode):
+        flood_timing(self.h, mode)
 
     def get_timing(self):
         return flood_get_timing(self.h)

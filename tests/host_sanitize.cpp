@@ -69,7 +69,7 @@ struct Recorder : flood::ImplBase {
     flood_status load(const char*, std::string&) override { return ok(); }
     flood_status device_snapshot(int, std::string&) override { return ok(); }
     void get_config(int32_t*, int32_t*, int32_t*, int32_t*, int32_t*, int32_t*, int32_t*, int32_t*) const override {}
-    flood_status timing(bool, std::string&) override { return ok(); }
+    flood_status timing(int, std::string&) override { return ok(); }
     void get_timing(double*, int64_t*) const override {}
     void get_adjoint_info(int32_t*, int32_t*, int32_t*) const override {}
 };
@@ -247,10 +247,13 @@ static void handle_calls() {
     EXPECT(flood_load(h, nullptr) == FLOOD_EINVAL && r->calls == 0);
     EXPECT(flood_device_snapshot(h, 0) == FLOOD_EINVAL && r->calls == 0);
     EXPECT(flood_device_snapshot(h, 4) == FLOOD_EINVAL && r->calls == 0);
+    EXPECT(flood_timing(h, 3) == FLOOD_EINVAL && r->calls == 0);
+    EXPECT(flood_timing(h, -1) == FLOOD_EINVAL && r->calls == 0);
     EXPECT(flood_step(h, 10.0) == FLOOD_OK && r->calls == 1 && h->err.empty());   // a good call clears the message
     EXPECT(flood_step_n(h, 10.0, 1) == FLOOD_OK && r->calls == 2);
     EXPECT(flood_log_steps(h, 0) == FLOOD_OK && r->calls == 3);
     EXPECT(flood_device_snapshot(h, FLOOD_SNAPSHOT_RELEASE) == FLOOD_OK && r->calls == 4);
+    EXPECT(flood_timing(h, FLOOD_TIMING_BATCH) == FLOOD_OK && flood_timing(h, 0) == FLOOD_OK && r->calls == 6);
     flood_destroy(h);
 
     // the resampler's checks run before any device work

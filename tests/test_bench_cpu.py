@@ -28,8 +28,11 @@ def test_traffic_summary_is_tied_to_kernel_sources(tmp_path, monkeypatch):
     (tmp_path / "profiles").mkdir()
     f = tmp_path / "profiles" / "k_marchv_urban8x8x2_traffic.md"
     f.write_text("# summary\n- kernel_sources_sha256: `%s`\n- traffic_bytes_per_launch: 1234.5\n"
-                 % bench.kernel_source_hash())
+                 "- algorithmic_bytes_per_launch: 1000\n" % bench.kernel_source_hash())
     assert bench.measured_traffic("k_marchv", "urban8x8x2") == pytest.approx(1234.5)
+    # only for the launches the counters were taken on (same algorithmic bytes per launch)
+    assert bench.measured_traffic("k_marchv", "urban8x8x2", 1003.0) == pytest.approx(1234.5)
+    assert bench.measured_traffic("k_marchv", "urban8x8x2", 1100.0) is None
     assert bench.measured_traffic("k_marchv", "urban8x8x4") is None
     # comments and layout are not the kernel
     (tmp_path / bench.KERNEL_SOURCES[0]).write_text("// a note\nkernel  /* more */ source\n  "
