@@ -382,17 +382,24 @@ flood_status flood_get_config(const flood_handle* h, int32_t* member_interleave,
                               int32_t* chunks_per_block, int32_t* graph_steps, int32_t* step_kernel,
                               int32_t* march_rows, int32_t* march_members, int32_t* march_order);
 
+/* Rows per strip of the row-marching step kernels for one catchment: in a
+ * handle holding catchments of different sizes the tuner refines them per
+ * catchment (the other outputs of flood_get_config are shared by all).
+ * Errors: EINVAL. */
+flood_status flood_get_march_rows(flood_handle* h, int32_t catchment, int32_t* march_rows);
+
 /* Timing of the step launches of flood_step calls between flood_timing(h,
- * mode) and flood_timing(h, 0), with HIP events on the handle's stream.
- * FLOOD_TIMING_LAUNCH: an event pair around every step kernel launch (the
- * captured graph path is off meanwhile), so the average is the step kernel's
- * own duration.  FLOOD_TIMING_BATCH: an event pair around every batch of
- * graph_steps steps (flood_get_config), the graph path kept; the average per
- * step then also holds each step's planner kernel and the gaps between the
- * batch's kernels.  flood_get_timing gives the average per step launch in ms
- * and the number of step launches.  Errors: EINVAL (mode), EHIP. */
+ * mode) and flood_timing(h, 0), with HIP events on the handle's stream; the
+ * average is the step kernel's own duration.  FLOOD_TIMING_LAUNCH: an event
+ * pair around every step kernel launch, launched one by one (the captured
+ * graph path is off meanwhile).  FLOOD_TIMING_GRAPH: the captured-graph path
+ * kept, with the event pairs recorded inside two captured batches used in
+ * turns (each read back before its batch is launched again).  flood_get_timing
+ * gives the average per step launch in ms and the number of step launches.
+ * Errors: EINVAL (mode), ESTATE (graph timing with the graph path disabled),
+ * EHIP (the runtime cannot record events inside a captured graph). */
 #define FLOOD_TIMING_LAUNCH 1
-#define FLOOD_TIMING_BATCH 2
+#define FLOOD_TIMING_GRAPH 2
 flood_status flood_timing(flood_handle* h, int32_t mode);
 flood_status flood_get_timing(const flood_handle* h, double* avg_step_ms, int64_t* launches);
 

@@ -426,10 +426,15 @@ flood_status flood_get_adjoint_info(const flood_handle* h, int32_t* groups, int3
     return FLOOD_OK;
 }
 
+flood_status flood_get_march_rows(flood_handle* h, int32_t catchment, int32_t* march_rows) {
+    FLOOD_NEED_HANDLE(h);
+    return h->impl->get_march_rows(catchment, march_rows, h->err);
+}
+
 flood_status flood_timing(flood_handle* h, int32_t mode) {
     FLOOD_NEED_HANDLE(h);
-    if (mode != 0 && mode != FLOOD_TIMING_LAUNCH && mode != FLOOD_TIMING_BATCH) {
-        h->err = "mode must be 0, FLOOD_TIMING_LAUNCH or FLOOD_TIMING_BATCH";
+    if (mode != 0 && mode != FLOOD_TIMING_LAUNCH && mode != FLOOD_TIMING_GRAPH) {
+        h->err = "mode must be 0, FLOOD_TIMING_LAUNCH or FLOOD_TIMING_GRAPH";
         return FLOOD_EINVAL;
     }
     return h->impl->timing(mode, h->err);

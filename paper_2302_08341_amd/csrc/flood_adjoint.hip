@@ -331,7 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int nq = (C.n_members + 3) / 4;
     int u, sx, sy;
-    if (!march_wave(C, b, nq, u, sx, sy)) return;   // uniform over the workgroup
+    if (!march_wave(C, b, nq, u, sx, sy, C.strips_xa)) return;   // uniform over the workgroup
     const int k = 4 * u + wave;
     bool actq[4];
 #pragma unroll
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
     const bool inx = xl >= 0 && xl < nx;
     const bool own = lane >= 1 && lane <= 62 && inx;
     const bool westw = sx == 0;                        // wavefront-uniform edge tests
-    const bool eastw = sx == C.strips_x - 1;
+    const bool eastw = sx == C.strips_xa - 1;
     const int xa = min(max(xl, 0), nx - V);            // load column (lanes outside the grid read, never use)
     const int r0 = sy * C.march_rows;
     const int r1 = min(r0 + C.march_rows, ny);
@@ -544,7 +544,7 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
         // rain-multiplier adjoint: the depth adjoint after the step summed over the
         // strip's cells, times R dt of the member's step
         for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
-        if (lane == 0) A.mubar_part[(size_t)(sy * C.strips_x + sx) * C.n_members + k] += lsum * A.rdt[k];
+        if (lane == 0) A.mubar_part[(size_t)(sy * C.strips_xa + sx) * C.n_members + k] += lsum * A.rdt[k];
     }
     __syncthreads();
     // the quad's Manning-field adjoint: wavefront w adds rows w, w + 4, ... of the
@@ -572,7 +572,7 @@ template <typename T> void launch_adjoint_march(const AdjvLaunch<T>& A, hipStrea
     constexpr int V = march_vec<T>();
     const CatchDev<T>& C = A.c;
     const int nq = (C.n_members + 3) / 4;
-    const dim3 grid(march_waves(C.strips_x, C.strips_y, nq, C.march_order, C.march_bands));
+    const dim3 grid(march_waves(C.strips_xa, C.strips_y, nq, C.march_order, C.march_bands));
     const size_t lds = (size_t)4 * C.march_rows * 64 * V * sizeof(T);
     hipLaunchKernelGGL((k_adjv<T, V>), grid, dim3(kBlock), lds, s, A);
 }

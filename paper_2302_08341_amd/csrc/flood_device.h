@@ -147,43 +147,56 @@ __device__ __forceinline__ size_t state_index(const CatchDev<T>& C, int member, 
 // Order 2 pads the unit count to a multiple of four and order 4 the rows of
 // strips to a multiple of the band count; padding wavefronts get false.
 template <typename T>
-__device__ __forceinline__ bool march_wave(const CatchDev<T>& C, int local, int units, int& k, int& sx, int& sy) {
+__device__ __forceinline__ bool march_wave(const CatchDev<T>& C, int local, int units, int& k, int& sx, int& sy,
+                                           int strips_x) {
     if (C.march_order == 0) {
         k = local % units;
         const int strip = local / units;
-        sy = strip / C.strips_x;
-        sx = strip - sy * C.strips_x;
+        sy = strip / strips_x;
+        sx = strip - sy * strips_x;
     } else if (C.march_order == 1) {
-        sx = local % C.strips_x;
-        const int rest = local / C.strips_x;
+        sx = local % strips_x;
+        const int rest = local / strips_x;
         sy = rest % C.strips_y;
         k = rest / C.strips_y;
     } else if (C.march_order == 4) {
         const int bh = (C.strips_y + C.march_bands - 1) / C.march_bands;   // rows of strips per band
-        const int per_unit = bh * C.strips_x;
+        const int per_unit = bh * strips_x;
         const int band = local / (per_unit * units);
         const int rem = local - band * per_unit * units;
         k = rem / per_unit;
         const int rem2 = rem - k * per_unit;
-        sy = band * bh + rem2 / C.strips_x;
-        sx = rem2 % C.strips_x;
+        sy = band * bh + rem2 / strips_x;
+        sx = rem2 % strips_x;
         return sy < C.strips_y && k < units;
     } else if (C.march_order == 3) {
-        sx = local % C.strips_x;
-        const int rest = local / C.strips_x;
+        sx = local % strips_x;
+        const int rest = local / strips_x;
         k = rest % units;
         sy = rest / units;
         return sy < C.strips_y;
     } else {
         const int q = local & 3;
         const int rest = local >> 2;
-        sx = rest % C.strips_x;
-        const int rest2 = rest / C.strips_x;
+        sx = rest % strips_x;
+        const int rest2 = rest / strips_x;
         sy = rest2 % C.strips_y;
         k = (rest2 / C.strips_y) * 4 + q;
     }
     return k < units;
 }
+
+template <typename T>
+__device__ __forceinline__ bool march_wave(const CatchDev<T>& C, int local, int units, int& k, int& sx, int& sy) {
+    return march_wave(C, local, units, k, sx, sy, C.strips_x);
+}
+
+// the cell beside a row-march strip, as loaded by the halo lanes of k_marchv
+template <typename T>
+struct Halo {
+    T h = T(0), z = T(0), n = T(0), q = T(0);   // depth, bed, roughness, east link
+    uint32_t cls = 0;                           // land-cover class (roughness from the member's table)
+};
 
 // v as held by lane src of the wavefront (ds_bpermute: byte address = 4 x lane)
 __device__ __forceinline__ float lane_read(float v, int src) {

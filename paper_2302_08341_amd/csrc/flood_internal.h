@@ -59,9 +59,11 @@ template <typename T> struct CatchDev {
     int32_t block_begin;      // first linear workgroup of this catchment in a launch
     int32_t n_blocks;
     int32_t edge_open[4];
-    // row-march variant (members in planes): strips of 62 cells x march_rows rows,
-    // one wavefront per (strip, group of march_seg members)
-    int32_t march_rows, strips_x, strips_y;
+    // row-march variants (members in planes): strips of march_rows rows, one
+    // wavefront per (strip, group of march_seg members); strips_x counts the
+    // strips of the kernel the view is launched with (62 cells for k_march, 64 V
+    // for k_marchv), strips_xa those of the adjoint's reverse step (62 V cells)
+    int32_t march_rows, strips_x, strips_y, strips_xa;
     int32_t wave_begin, n_waves;
     int32_t march_order;      // wavefront order, see march_wave
     int32_t march_bands;      // order 4: bands of rows of strips, a multiple of 8

@@ -974,10 +974,15 @@ __global__ __launch_bounds__(kBlock) void k_march(const StepLaunch<T> L) {
 // ---------------------------------------------------------------------------
 // Vectorised row-marching step (members in planes, nx a multiple of V): each
 // lane owns V adjacent cells and moves them with one V-wide load or store, so a
-// wavefront streams 64 V cells per row with five loads and three stores.
-// Lanes 0 and 63 are halo lanes (the strip's own cells are those of lanes
-// 1..62), which keeps every access V-aligned.  Same link functions and
-// operands as k_step: identical bits.
+// wavefront streams a strip of 64 V cells per row with five loads and three
+// stores.  Every lane owns cells: the strip starts at a multiple of 64 V cells,
+// so with a row pitch that is a multiple of 16 cells its stores cover whole
+// 64-byte blocks and no block is shared with a neighbouring strip.  The two
+// cells beside the strip come from four single-lane loads per row: lane 0 reads
+// the west neighbour (depth, bed, roughness and its east link) and computes the
+// strip's west link from it exactly as the neighbouring strip computes its
+// east link, lane 63 reads the east neighbour (depth, bed, roughness).  Same
+// link functions and operands as k_step: identical bits.
 // ---------------------------------------------------------------------------
 // PF = 1 issues the next row's loads before computing the current row (one row
 // of lookahead), so each wavefront keeps its own loads in flight while it
@@ -1005,12 +1010,16 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
     const MemberStep<T> ms = L.ms[C.member_off + k];
     if (!ms.active) return;
     const int nx = C.nx, ny = C.ny;
-    const int xl = sx * (62 * V) - V + V * lane;          // first cell of this lane
-    const bool inx = xl >= 0 && xl < nx;                   // nx % V == 0: all V cells or none
-    const bool own = lane >= 1 && lane <= 62 && inx;
+    const int x0 = sx * (64 * V);                          // first cell of the strip
+    const int xl = x0 + V * lane;                          // first cell of this lane
+    const bool own = xl < nx;                              // nx % V == 0: all V cells or none
     const bool westw = sx == 0;                            // wavefront-uniform edge tests
     const bool eastw = sx == C.strips_x - 1;
-    const int xa = min(max(xl, 0), nx - V);                // load column
+    const int xa = min(xl, nx - V);                        // load column
+    // halo: lane 0 the cell west of the strip, lane 63 the one east of it
+    // (clamped into the grid where there is none; then never used)
+    const bool halo_lane = lane == 0 || lane == 63;
+    const int xh = lane == 0 ? (westw ? 0 : x0 - 1) : (eastw ? nx - 1 : x0 + 64 * V);
     const int r0 = sy * C.march_rows;
     const int r1 = min(r0 + C.march_rows, ny);
     const size_t plane = (size_t)ny * nx;
@@ -1154,11 +1163,13 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
             if (id >= 0) fN[j] = inflow_q(id);
         }
     }
-    // current row's links (qE, qS) and the row below (hs, zs, ns, classes csw)
+    // current row's links (qE, qS), the row below (hs, zs, ns, classes csw) and
+    // the current row's halo cell (depth, bed, roughness or class, east link)
     T hs[V], zs[V], ns[V], qE[V], qS[V];
     uint32_t csw = 0;
+    Halo<T> hx;
     auto load_row = [&](size_t c, bool below, T (&qe)[V], T (&qs)[V], T (&h2)[V], T (&z2)[V], T (&n2)[V],
-                        uint32_t& cw2) {
+                        uint32_t& cw2, Halo<T>& ho) {
         const size_t cb = below ? c + nx : c;
         if (NT) {
             vload_nt<T, V>(QX + c, qe);
@@ -1170,15 +1181,29 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
         vload<T, V>(H + cb, h2);
         vload<T, V>(Z + cb, z2);
         load_n(cb, n2, cw2);
+        if (halo_lane) {
+            const size_t c1 = c - xa + xh;
+            ho.h = H[c1];
+            ho.z = Z[c1];
+            ho.q = QX[c1];
+            if (lc)
+                ho.cls = CLS[c1];
+            else
+                ho.n = Nn[c1];
+        }
     };
-    if (PF) load_row(ca, r0 + 1 < ny, qE, qS, hs, zs, ns, csw);
+    // roughness of the halo cell from its class: a cross-lane read, made with the
+    // whole wavefront active
+    auto halo_n = [&](const Halo<T>& ho) -> T { return lc ? rough(halo_lane ? ho.cls : 0u) : ho.n; };
+    if (PF) load_row(ca, r0 + 1 < ny, qE, qS, hs, zs, ns, csw, hx);
     // PF == 2: a second row in flight (the links of the next row and the state
     // of the row after it), so each row's loads have two rows of work to arrive
     T hsB[V], zsB[V], nsB[V], qEB[V], qSB[V];
     uint32_t cswB = 0;
+    Halo<T> hxB;
 #pragma unroll
     for (int j = 0; j < V; ++j) hsB[j] = zsB[j] = nsB[j] = qEB[j] = qSB[j] = T(0);
-    if (PF == 2 && r0 + 1 < r1) load_row(ca + nx, r0 + 2 < ny, qEB, qSB, hsB, zsB, nsB, cswB);
+    if (PF == 2 && r0 + 1 < r1) load_row(ca + nx, r0 + 2 < ny, qEB, qSB, hsB, zsB, nsB, cswB, hxB);
     HB vmax = 0;
     T vcl = T(0);
     T vdr = T(0);
@@ -1188,17 +1213,25 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
         const int idE = (INF && eastw) ? (int)INF[2 * nx + ny + r] : -1;
         T hs2[V], zs2[V], ns2[V], qE2[V], qS2[V];
         uint32_t csw2 = 0;
+        Halo<T> hx2;
         if (PF == 2) {
-            if (r + 2 < r1) load_row(ca + 2 * (size_t)nx, r + 3 < ny, qE2, qS2, hs2, zs2, ns2, csw2);
+            if (r + 2 < r1) load_row(ca + 2 * (size_t)nx, r + 3 < ny, qE2, qS2, hs2, zs2, ns2, csw2, hx2);
         } else if (PF) {
-            if (r + 1 < r1) load_row(ca + nx, r + 2 < ny, qE2, qS2, hs2, zs2, ns2, csw2);
+            if (r + 1 < r1) load_row(ca + nx, r + 2 < ny, qE2, qS2, hs2, zs2, ns2, csw2, hx2);
         } else {
-            load_row(ca, hasS, qE, qS, hs, zs, ns, csw);
+            load_row(ca, hasS, qE, qS, hs, zs, ns, csw, hx);
         }
-        // east neighbour of the lane's last cell = first cell of the next lane
-        const T hE = __shfl_down(hc[0], 1, 64);
-        const T zE = __shfl_down(zc[0], 1, 64);
-        const T nE = __shfl_down(nc[0], 1, 64);
+        const T nH = halo_n(hx);
+        // east neighbour of the lane's last cell = first cell of the next lane; for
+        // lane 63 the halo cell east of the strip
+        T hE = __shfl_down(hc[0], 1, 64);
+        T zE = __shfl_down(zc[0], 1, 64);
+        T nE = __shfl_down(nc[0], 1, 64);
+        if (lane == 63) {
+            hE = hx.h;
+            zE = hx.z;
+            nE = nH;
+        }
         T fE[V];
 #pragma unroll
         for (int j = 0; j < V; ++j) {
@@ -1219,6 +1252,12 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
         }
         T fW[V];
         fW[0] = __shfl_up(fE[V - 1], 1, 64);
+        if (lane == 0 && !westw) {
+            // the strip's west link, as the strip to the west computes it (its last
+            // cell's east link: same operands in the same order)
+            const T nf = T(0.5) * (nH + nc[0]);
+            fW[0] = link_in(hx.q, hx.h, hc[0], zc[0] - hx.z, g * (nf * nf), ms, hdry);
+        }
 #pragma unroll
         for (int j = 1; j < V; ++j) fW[j] = fE[j - 1];
         if (westw && xl == 0) {
@@ -1329,6 +1368,8 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
         if (PF == 2) {
             csw = cswB;
             cswB = csw2;
+            hx = hxB;
+            hxB = hx2;
 #pragma unroll
             for (int j = 0; j < V; ++j) {
                 qE[j] = qEB[j];
@@ -1344,6 +1385,7 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
             }
         } else if (PF) {
             csw = csw2;
+            hx = hx2;
 #pragma unroll
             for (int j = 0; j < V; ++j) {
                 qE[j] = qE2[j];

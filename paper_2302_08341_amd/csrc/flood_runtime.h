@@ -49,6 +49,7 @@ struct ImplBase {
     virtual flood_status timing(int mode, std::string& err) = 0;
     virtual void get_timing(double* avg_ms, int64_t* launches) const = 0;
     virtual void get_adjoint_info(int32_t* groups, int32_t* group_size, int32_t* segments) const = 0;
+    virtual flood_status get_march_rows(int c, int32_t* rows, std::string& err) const = 0;
 };
 
 const char* status_name(flood_status s);

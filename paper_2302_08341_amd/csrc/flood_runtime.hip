@@ -119,8 +119,14 @@ template <typename T> struct Impl : ImplBase {
 
     // kernel timing
     bool timing_on = false;      // per-launch events (graph capture off while on)
-    bool timing_batch = false;   // events around each batch of G steps (graph path kept)
+    bool timing_graph = false;   // per-launch events captured in the batch graphs
     std::vector<int32_t> tev_steps;   // step launches between each pair of events
+    // graph timing: one captured batch per slot, each with its own event pair
+    // around every step kernel, read back before that slot's batch is launched again
+    hipGraph_t tgraph[2] = {nullptr, nullptr};
+    hipGraphExec_t tgexec[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> tgev[2];
+    bool tg_pending[2] = {false, false};
     std::vector<hipEvent_t> tev;
     size_t tev_used = 0;
     double t_ms = 0.0;
@@ -194,9 +200,12 @@ template <typename T> struct Impl : ImplBase {
         adj_free_all();
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
+        drop_timing_graphs();
         for (auto e : ev)
             if (e) (void)hipEventDestroy(e);
         for (auto e : tev) (void)hipEventDestroy(e);
+        for (int sl = 0; sl < 2; ++sl)
+            for (auto e : tgev[sl]) (void)hipEventDestroy(e);
         for (void* p : allocs) (void)hipFree(p);
         if (dtlog) (void)hipFree(dtlog);
         if (telog) (void)hipFree(telog);
@@ -245,8 +254,9 @@ template <typename T> struct Impl : ImplBase {
             d.block_begin = begin;
             begin += d.n_blocks;
             d.march_rows = std::max(1, std::min(c.march_rows, c.ny));
-            const int strip_w = variant == 3 ? 62 * march_vec<T>() : 62;
+            const int strip_w = variant == 3 ? 64 * march_vec<T>() : 62;
             d.strips_x = (c.nx + strip_w - 1) / strip_w;
+            d.strips_xa = (c.nx + 62 * march_vec<T>() - 1) / (62 * march_vec<T>());
             d.strips_y = (c.ny + d.march_rows - 1) / d.march_rows;
             d.wave_begin = waves;
             {
@@ -293,6 +303,67 @@ template <typename T> struct Impl : ImplBase {
         if (graph) (void)hipGraphDestroy(graph);
         gexec = nullptr;
         graph = nullptr;
+        drop_timing_graphs();
+    }
+
+    void drop_timing_graphs() {
+        for (int sl = 0; sl < 2; ++sl) {
+            if (tgexec[sl]) (void)hipGraphExecDestroy(tgexec[sl]);
+            if (tgraph[sl]) (void)hipGraphDestroy(tgraph[sl]);
+            tgexec[sl] = nullptr;
+            tgraph[sl] = nullptr;
+            tg_pending[sl] = false;
+        }
+    }
+
+    // capture the two timing batches; EHIP when this runtime cannot record events
+    // inside a captured graph
+    flood_status ensure_timing_graphs(std::string& err) {
+        if (tgexec[0] && tgexec[1]) return FLOOD_OK;
+        if (!use_graph) {
+            err = "graph timing needs the captured-graph path (FLOOD_NO_GRAPH is set)";
+            return FLOOD_ESTATE;
+        }
+        for (int sl = 0; sl < 2; ++sl) {
+            while (tgev[sl].size() < (size_t)(2 * G)) {
+                hipEvent_t e;
+                HIPCHK(hipEventCreate(&e));
+                tgev[sl].push_back(e);
+            }
+            hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t er = hipSuccess;
+                for (int i = 0; i < G; ++i) {
+                    launch_plan<T>(PL, st);
+                    if (er == hipSuccess) er = hipEventRecord(tgev[sl][2 * i], st);
+                    launch_steps(SL);
+                    if (er == hipSuccess) er = hipEventRecord(tgev[sl][2 * i + 1], st);
+                }
+                e = hipStreamEndCapture(st, &tgraph[sl]);
+                if (e == hipSuccess) e = er;
+            }
+            if (e == hipSuccess && tgraph[sl]) e = hipGraphInstantiate(&tgexec[sl], tgraph[sl], nullptr, nullptr, 0);
+            if (e != hipSuccess || !tgexec[sl]) {
+                (void)hipGetLastError();
+                drop_timing_graphs();
+                err = std::string("events cannot be recorded inside a captured graph here: ") + hipGetErrorString(e);
+                return FLOOD_EHIP;
+            }
+        }
+        return FLOOD_OK;
+    }
+
+    // fold the kernel times of slot sl's last timing batch (complete by then)
+    flood_status harvest_timing(int sl, std::string& err) {
+        if (!tg_pending[sl]) return FLOOD_OK;
+        for (int i = 0; i < G; ++i) {
+            float el = 0;
+            HIPCHK(hipEventElapsedTime(&el, tgev[sl][2 * i], tgev[sl][2 * i + 1]));
+            t_ms += el;
+            t_launches += 1;
+        }
+        tg_pending[sl] = false;
+        return FLOOD_OK;
     }
 
     flood_status init(int nc, const flood_grid* grids, const flood_params* params, const int32_t* members,
@@ -674,7 +745,9 @@ template <typename T> struct Impl : ImplBase {
             for (int i = 0; i < n_catch; ++i) {
                 if (!params[i].tile_rows) cats[i].tile_rows = cached.tile_rows;
                 if (!params[i].chunks_per_block) cats[i].cpb = cached.cpb;
-                if (!params[i].march_rows) cats[i].march_rows = cached.march_rows;
+                if (!params[i].march_rows)
+                    cats[i].march_rows = (i < 8 && cached.march_rows_c[i] > 0) ? cached.march_rows_c[i]
+                                                                               : cached.march_rows;
             }
             layout_launch();
             return FLOOD_OK;
@@ -835,9 +908,6 @@ template <typename T> struct Impl : ImplBase {
                 cd.seg == bc.seg && cd.mrows > bc.mrows)
                 bc = cd;
         }
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
-        for (int i = 0; i < n_catch; ++i) cats[i].dev.peak = peaks[i];
         variant = bc.variant;
         march_seg = bc.seg;
         march_order = bc.order;
@@ -847,6 +917,51 @@ template <typename T> struct Impl : ImplBase {
             if (!params[i].march_rows) cats[i].march_rows = bc.mrows;
         }
         layout_launch();
+        // catchments of different sizes in one launch: each one's rows per strip
+        // refined in turn (the others held), timing the whole batched launch; a
+        // change is kept only when it is more than 1 % faster
+        if (n_catch > 1 && variant >= 2) {
+            const std::vector<int> rows_set = variant == 3 ? std::vector<int>{4, 8, 16, 32, 64}
+                                                           : std::vector<int>{8, 16, 32, 64, 128};
+            auto time_layout = [&](float* out) -> flood_status {
+                layout_launch();
+                launch_steps(SL);   // warm-up
+                float b5 = 1e30f;
+                for (int rep = 0; rep < 5; ++rep) {
+                    HIPCHK(hipEventRecord(a, st));
+                    launch_steps(SL);
+                    HIPCHK(hipEventRecord(b, st));
+                    HIPCHK(hipEventSynchronize(b));
+                    float el = 0;
+                    HIPCHK(hipEventElapsedTime(&el, a, b));
+                    b5 = std::min(b5, el);
+                }
+                *out = b5;
+                return FLOOD_OK;
+            };
+            float t_cur;
+            CHK(time_layout(&t_cur));
+            for (int i = 0; i < n_catch; ++i) {
+                if (params[i].march_rows) continue;
+                const int keep = cats[i].march_rows;
+                int best_r = keep;
+                for (int mr : rows_set) {
+                    if (mr == keep) continue;
+                    cats[i].march_rows = mr;
+                    float t;
+                    CHK(time_layout(&t));
+                    if (t < 0.99f * t_cur) {
+                        t_cur = t;
+                        best_r = mr;
+                    }
+                }
+                cats[i].march_rows = best_r;
+            }
+            layout_launch();
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        for (int i = 0; i < n_catch; ++i) cats[i].dev.peak = peaks[i];
         HIPCHK(hipMemcpy(ms, saved.data(), n_total * sizeof(MemberStep<T>), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(vclamp, saved_clamp.data(), n_total * sizeof(double), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(hbins, bins_saved[0].data(), bins_saved[0].size() * sizeof(HB), hipMemcpyHostToDevice));
@@ -865,6 +980,7 @@ template <typename T> struct Impl : ImplBase {
         c.march_rows = bc.mrows;
         c.march_seg = bc.seg;
         c.march_order = bc.order;
+        for (int i = 0; i < n_catch && i < 8; ++i) c.march_rows_c[i] = cats[i].march_rows;
         // only a search over the full candidate set is remembered: a handle that
         // pinned part of the geometry measured a subset, whose best need not be
         // the best for a later handle of the same shape
@@ -923,11 +1039,12 @@ template <typename T> struct Impl : ImplBase {
     }
 
     flood_status launch_batch(int slot, std::string& err) {
-        if (timing_batch) {
-            if (next_event_pair(G)) { err = "hipEventCreate failed"; return FLOOD_EHIP; }
-            HIPCHK(hipEventRecord(tev[tev_used], st));
-        }
-        if (gexec && !timing_on) {
+        if (timing_graph) {
+            CHK(ensure_timing_graphs(err));
+            CHK(harvest_timing(slot, err));
+            HIPCHK(hipGraphLaunch(tgexec[slot], st));
+            tg_pending[slot] = true;
+        } else if (gexec && !timing_on) {
             HIPCHK(hipGraphLaunch(gexec, st));
         } else {
             for (int i = 0; i < G; ++i) {
@@ -942,10 +1059,6 @@ template <typename T> struct Impl : ImplBase {
                     launch_steps(SL);
                 }
             }
-        }
-        if (timing_batch) {
-            HIPCHK(hipEventRecord(tev[tev_used + 1], st));
-            tev_used += 2;
         }
         launch_count_active(n_total, t, fault, d_tend, status, steps, step_lim, d_count, st);
         HIPCHK(hipGetLastError());
@@ -985,7 +1098,11 @@ template <typename T> struct Impl : ImplBase {
             }
         }
         HIPCHK(hipStreamSynchronize(st));
-        if (timing_on || timing_batch) {
+        if (timing_graph) {
+            CHK(harvest_timing(0, err));
+            CHK(harvest_timing(1, err));
+        }
+        if (timing_on) {
             for (size_t i = 0; i < tev_used; i += 2) {
                 float el = 0;
                 HIPCHK(hipEventElapsedTime(&el, tev[i], tev[i + 1]));
@@ -1576,6 +1693,13 @@ template <typename T> struct Impl : ImplBase {
         if (mr) *mr = std::min(cats[0].march_rows, cats[0].ny);
     }
 
+    flood_status get_march_rows(int c, int32_t* rows, std::string& err) const override {
+        CHK(check_catch(c, err));
+        if (!rows) { err = "march_rows is NULL"; return FLOOD_EINVAL; }
+        *rows = std::min(cats[c].march_rows, cats[c].ny);
+        return FLOOD_OK;
+    }
+
     flood_status timing(int mode, std::string& err) override {
         HIPCHK(hipStreamSynchronize(st));
         if (mode) {
@@ -1584,7 +1708,13 @@ template <typename T> struct Impl : ImplBase {
             tev_used = 0;
         }
         timing_on = mode == FLOOD_TIMING_LAUNCH;
-        timing_batch = mode == FLOOD_TIMING_BATCH;
+        timing_graph = false;
+        if (mode == FLOOD_TIMING_GRAPH) {
+            CHK(ensure_graph(err));
+            CHK(ensure_timing_graphs(err));
+            tg_pending[0] = tg_pending[1] = false;
+            timing_graph = true;
+        }
         return FLOOD_OK;
     }
 
@@ -1617,11 +1747,13 @@ static CatchDev<T> group_view(const CatchDev<T>& C, int mi, int g0, int G, T* co
     v.tiles_x = (C.nx + (1 << l) - 1) >> l;
     v.tiles_y = (C.ny + ty - 1) / ty;
     // row-march geometry (members in planes), likewise fixed
-    const int strip_w = 62 * march_vec<T>();
+    const int strip_w = 64 * march_vec<T>();       // the recorded forward and tape recomputation (k_marchv)
+    const int strip_wa = 62 * march_vec<T>();      // the reverse step (k_adjv)
     int rows = kAdjMarchRows;   // at most 16: the reverse step stages 4 x rows x 64 x V values in LDS
     if (const char* ar = std::getenv("FLOOD_ADJ_ROWS")) rows = std::min(16, std::max(1, std::atoi(ar)));
     v.march_rows = std::min(rows, C.ny);
     v.strips_x = (C.nx + strip_w - 1) / strip_w;
+    v.strips_xa = (C.nx + strip_wa - 1) / strip_wa;
     v.strips_y = (C.ny + v.march_rows - 1) / v.march_rows;
     v.wave_begin = 0;
     v.march_order = kAdjMarchOrder;
@@ -1752,7 +1884,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
         T* none[2] = {nullptr, nullptr};
         const CatchDev<T> tv = group_view(C.dev, mi, 0, std::min(Gi, N), none, none, none, none, none);
         nblk = tv.tiles_x * tv.tiles_y;
-        if (march_adj) nblk = tv.strips_x * tv.strips_y;
+        if (march_adj) nblk = tv.strips_xa * tv.strips_y;
     }
     CHK(talloc((size_t)nblk * Gi * sizeof(double), (void**)&d_mubar));
     // row-march form: per-member adjoint copy index, Manning-field accumulators,
@@ -2116,7 +2248,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                 HIPCHK(hipGetLastError());
             }
             launch_nacc_reduce<T>((Gg + 3) / 4, ncell, d_nacc, d_nbar, st);
-            launch_sum_parts(V.strips_x * V.strips_y, Gg, d_mubar, d_gm + g0, st);
+            launch_sum_parts(V.strips_xa * V.strips_y, Gg, d_mubar, d_gm + g0, st);
             HIPCHK(hipGetLastError());
             HIPCHK(hipStreamSynchronize(st));
             continue;

@@ -3,7 +3,8 @@
 // Measured choices are remembered for the life of the process, so handles of
 // one problem shape after the first do not measure again, and optionally in a
 // file: $FLOOD_TUNE_CACHE, one line per tuned problem,
-// "<key> mi tile_rows cpb variant march_rows march_seg march_order".  Set
+// "<key> mi tile_rows cpb variant march_rows march_seg march_order rows_1,...,rows_n"
+// (the last field: each catchment's rows per strip, 0 for march_rows).  Set
 // FLOOD_AUTOTUNE=0 to skip measuring and use the defaults (or the explicit
 // values given at creation).
 #include "flood_tune.h"
@@ -63,13 +64,27 @@ bool tune_lookup(const TuneKey& k, int mi, TuneChoice& out) {
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
     const std::string want = key_string(k, mi);
-    char key[512];
+    char line[1024], key[512], rows[256];
     int a, b, c, d, e, f2, g2;
     bool found = false;
-    while (std::fscanf(f, "%511s %d %d %d %d %d %d %d", key, &a, &b, &c, &d, &e, &f2, &g2) == 8) {
+    while (std::fgets(line, sizeof line, f)) {
+        rows[0] = 0;
+        const int got = std::sscanf(line, "%511s %d %d %d %d %d %d %d %255s", key, &a, &b, &c, &d, &e, &f2, &g2, rows);
+        if (got < 8) continue;
         // an entry outside the geometries this library launches is ignored
-        const bool sane = (a == 1 || a == 2 || a == 4 || a == 8) && b >= 1 && b <= 8 && c >= 1 && d >= 1 && d <= 3 &&
-                          e >= 1 && e <= 4096 && (f2 == 1 || f2 == 2 || f2 == 4 || f2 == 8) && g2 >= 0 && g2 <= 4;
+        bool sane = (a == 1 || a == 2 || a == 4 || a == 8) && b >= 1 && b <= 8 && c >= 1 && d >= 1 && d <= 3 &&
+                    e >= 1 && e <= 4096 && (f2 == 1 || f2 == 2 || f2 == 4 || f2 == 8) && g2 >= 0 && g2 <= 4;
+        int rc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (got == 9) {
+            const char* p = rows;
+            for (int i = 0; i < k.n_catch && i < 8 && *p; ++i) {
+                char* end = nullptr;
+                const long v = std::strtol(p, &end, 10);
+                if (end == p || v < 0 || v > 4096) { sane = false; break; }
+                rc[i] = (int)v;
+                p = *end == ',' ? end + 1 : end;
+            }
+        }
         if (want == key && sane) {
             out.mi = a;
             out.tile_rows = b;
@@ -78,6 +93,7 @@ bool tune_lookup(const TuneKey& k, int mi, TuneChoice& out) {
             out.march_rows = e;
             out.march_seg = f2;
             out.march_order = g2;
+            for (int i = 0; i < 8; ++i) out.march_rows_c[i] = rc[i];
             found = true;
         }
     }
@@ -94,8 +110,10 @@ void tune_store(const TuneKey& k, const TuneChoice& c) {
     if (!path || !path[0]) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %d %d %d %d %d\n", key_string(k, c.mi).c_str(), c.mi, c.tile_rows, c.cpb, c.variant,
-                 c.march_rows, c.march_seg, c.march_order);
+    std::string rows;
+    for (int i = 0; i < k.n_catch && i < 8; ++i) rows += (i ? "," : "") + std::to_string(c.march_rows_c[i]);
+    std::fprintf(f, "%s %d %d %d %d %d %d %d %s\n", key_string(k, c.mi).c_str(), c.mi, c.tile_rows, c.cpb, c.variant,
+                 c.march_rows, c.march_seg, c.march_order, rows.c_str());
     std::fclose(f);
 }
 

@@ -18,7 +18,8 @@ struct TuneChoice {
     int variant = 1;     // 1 tiled kernel, 2 row-marching kernel
     int march_rows = 32; // rows per strip of the row-marching kernel
     int march_seg = 2;   // members marched together by one wavefront
-    int march_order = 1; // wavefront order of the row-march kernels (0, 1 or 2)
+    int march_order = 1; // wavefront order of the row-march kernels (0 to 4)
+    int march_rows_c[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // per catchment, 0: march_rows
 };
 
 TuneChoice tune_default(const TuneKey& k);

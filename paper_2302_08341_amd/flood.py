@@ -27,7 +27,7 @@ EXPORTED = ["flood_create", "flood_create_batch", "flood_step", "flood_assimilat
             "flood_load", "flood_set_sections", "flood_get_sections", "flood_assimilate_obs",
             "flood_get_config", "flood_timing", "flood_get_timing", "flood_adjoint_release", "flood_step_n",
             "flood_get_wet_mask", "flood_log_steps", "flood_get_step_log", "flood_get_adjoint_info",
-            "flood_systematic_resample_noalloc", "flood_device_snapshot",
+            "flood_systematic_resample_noalloc", "flood_device_snapshot", "flood_get_march_rows",
             "flood_last_error",
             "flood_strerror", "flood_destroy"]
 
@@ -102,6 +102,7 @@ def load_library():
         "flood_systematic_resample": [dp, C.c_int32, C.c_double, ip, C.c_void_p],
         "flood_systematic_resample_noalloc": [dp, C.c_int32, C.c_double, ip, C.c_void_p],
         "flood_device_snapshot": [H, C.c_int32],
+        "flood_get_march_rows": [H, C.c_int32, ip],
         "flood_ensemble_products": [H, C.c_int32, C.c_double, C.c_int32, dp, dp, dp, dp],
         "flood_save": [H, C.c_char_p],
         "flood_load": [H, C.c_char_p],
@@ -391,6 +392,12 @@ def flood_systematic_resample_noalloc(w, u0, stream=None):
     return anc
 
 
+def flood_get_march_rows(h, catchment):
+    v = C.c_int32(0)
+    _check(load_library().flood_get_march_rows(h, int(catchment), C.byref(v)), h)
+    return int(v.value)
+
+
 def flood_device_snapshot(h, op):
     _check(load_library().flood_device_snapshot(h, int(op)), h)
 
@@ -416,12 +423,12 @@ def flood_adjoint_release(h):
     _check(load_library().flood_adjoint_release(h), h)
 
 
-TIMING_LAUNCH, TIMING_BATCH = 1, 2
+TIMING_LAUNCH, TIMING_GRAPH = 1, 2
 
 
 def flood_timing(h, mode):
-    """mode: 0 / False off, 1 / True an event pair per step launch (graph path off),
-    2 an event pair per captured batch of steps (graph path kept)."""
+    """mode: 0 / False off, 1 / True an event pair around every step launch with the
+    graph path off, 2 the same event pairs recorded inside the captured graphs."""
     _check(load_library().flood_timing(h, int(mode)), h)
 
 
@@ -575,6 +582,10 @@ class FloodEnsemble:
 
     def save(self, path):
         flood_save(self.h, path)
+
+    def march_rows(self, catchment=0):
+        """Rows per strip of the row-marching step kernels for one catchment."""
+        return flood_get_march_rows(self.h, catchment)
 
     def snapshot(self):
         """Keep every member's state on the device (flood_device_snapshot, TAKE)."""

@@ -102,6 +102,10 @@ def test_config3_adjoint_of_a_sampled_member(fl, orc):
 def test_config4_batched_catchments(fl, orc):
     wl = W.config4()
     ens = fl.FloodEnsemble.from_workload(wl)
+    # the tuner refines the rows per strip catchment by catchment
+    rows = [ens.march_rows(ci) for ci in range(len(wl.catchments))]
+    print("rows per strip by catchment:", rows, ens.config())
+    assert all(1 <= r <= c.ny for r, c in zip(rows, wl.catchments))
     ens.step(300.0)
     i = 5
     for ci, c in enumerate(wl.catchments):
