@@ -961,7 +961,10 @@ template <typename T> struct Impl : ImplBase {
         }
         (void)hipEventDestroy(a);
         (void)hipEventDestroy(b);
+        // the launch descriptors are built from the catchments again once the running
+        // maxima are back (trial launches ran without them)
         for (int i = 0; i < n_catch; ++i) cats[i].dev.peak = peaks[i];
+        layout_launch();
         HIPCHK(hipMemcpy(ms, saved.data(), n_total * sizeof(MemberStep<T>), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(vclamp, saved_clamp.data(), n_total * sizeof(double), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(hbins, bins_saved[0].data(), bins_saved[0].size() * sizeof(HB), hipMemcpyHostToDevice));
