@@ -18,10 +18,12 @@ k mod 6.
 `value` is member-cell-updates per second (MCU/s) over the timed cycles,
 counted from the per-member step counters, filter updates and restarts
 included, on the library's captured-graph path.  The JSON line also carries
-the roofline of the step kernel (a HIP event pair around every step kernel of
-the timed region, recorded inside the captured graphs), the FP64 oracle timed
-on the host cores, and in `detail` the other parts of the metric, each outside
-the timed region:
+the roofline of the step kernel (a HIP event pair around every captured batch
+of steps in the timed region, so the duration per step launch also holds the
+step's small planner kernel and the gaps between kernels; a kernel trace of the
+same command gives the step kernel's own duration), the FP64 oracle timed on
+the host cores, and in `detail` the other parts of the metric, each outside the
+timed region:
   * step kernels alone (MCU over summed kernel time);
   * forward + adjoint over the first 900 s of the same ensemble (Manning-field
     and rain-multiplier gradients of a 10-s gauge misfit, checkpoints every
@@ -581,15 +583,8 @@ def main():
                           "elementwise_copy_GBps": elementwise_ceiling(torch), "config": ens.config()}))
         return
 
-    timing_kind = None
     if not args.no_kernel_timing:
-        try:
-            ens.timing(2)      # event pairs around every step kernel, recorded inside the captured graphs
-            timing_kind = "graph"
-        except Exception as ex:  # a runtime that cannot record events in a captured graph
-            log("graph timing unavailable (%s): per-launch events with the graph path off" % ex)
-            ens.timing(1)
-            timing_kind = "launch"
+        ens.timing(2)          # an event pair around every captured batch; the graph path stays on
     torch.cuda.synchronize()
     clocks = ClockSampler().start()
     t0 = time.perf_counter()
@@ -602,6 +597,7 @@ def main():
         ens.timing(0)
     led1 = ens.ledger()
     avg_ms, launches = ens.get_timing()
+    conf_end = ens.config()
     log("timed cycles done: %.2f s" % elapsed)
 
     # per-cycle counts: a restart sets the ledger's step counters back with the state
@@ -624,10 +620,9 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": KERNEL_TITLES.get(conf["step_kernel"], kname),
                 "avg_launch_ms": round(avg_ms, 4), "launches": launches,
-                "timing": ("a HIP event pair around every step kernel of the timed region, recorded inside the "
-                           "captured graphs (value measured on the same graph path)" if timing_kind == "graph" else
-                           "a HIP event pair around every step kernel of the timed region, launched one by one "
-                           "(graph path off)"),
+                "timing": "a HIP event pair around every captured batch of %d step launches in the timed region "
+                          "(the graph path that value is measured on); a step launch's time holds the step kernel, "
+                          "its planner kernel and the gaps between them" % conf_end["graph_steps"],
                 "algorithmic_bytes_per_launch": round(alg_bytes),
                 "traffic_over_algorithmic": round(traffic / alg_bytes, 3) if traffic else None,
                 "kernel_sources_sha256": kernel_source_hash()}

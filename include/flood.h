@@ -389,17 +389,18 @@ flood_status flood_get_config(const flood_handle* h, int32_t* member_interleave,
 flood_status flood_get_march_rows(flood_handle* h, int32_t catchment, int32_t* march_rows);
 
 /* Timing of the step launches of flood_step calls between flood_timing(h,
- * mode) and flood_timing(h, 0), with HIP events on the handle's stream; the
- * average is the step kernel's own duration.  FLOOD_TIMING_LAUNCH: an event
- * pair around every step kernel launch, launched one by one (the captured
- * graph path is off meanwhile).  FLOOD_TIMING_GRAPH: the captured-graph path
- * kept, with the event pairs recorded inside two captured batches used in
- * turns (each read back before its batch is launched again).  flood_get_timing
- * gives the average per step launch in ms and the number of step launches.
- * Errors: EINVAL (mode), ESTATE (graph timing with the graph path disabled),
- * EHIP (the runtime cannot record events inside a captured graph). */
+ * mode) and flood_timing(h, 0), with HIP events on the handle's stream.
+ * FLOOD_TIMING_LAUNCH: an event pair around every step kernel launch, launched
+ * one by one (the captured-graph path is off meanwhile): the average is the
+ * step kernel's own duration.  FLOOD_TIMING_BATCH: the captured-graph path
+ * kept, an event pair around every batch of graph_steps steps
+ * (flood_get_config): the average per step launch then also holds each step's
+ * planner kernel and the gaps between the batch's kernels (events recorded
+ * inside a captured graph cannot be timed).  flood_get_timing gives the
+ * average per step launch in ms and the number of step launches.
+ * Errors: EINVAL (mode), EHIP. */
 #define FLOOD_TIMING_LAUNCH 1
-#define FLOOD_TIMING_GRAPH 2
+#define FLOOD_TIMING_BATCH 2
 flood_status flood_timing(flood_handle* h, int32_t mode);
 flood_status flood_get_timing(const flood_handle* h, double* avg_step_ms, int64_t* launches);
 

@@ -433,8 +433,8 @@ flood_status flood_get_march_rows(flood_handle* h, int32_t catchment, int32_t* m
 
 flood_status flood_timing(flood_handle* h, int32_t mode) {
     FLOOD_NEED_HANDLE(h);
-    if (mode != 0 && mode != FLOOD_TIMING_LAUNCH && mode != FLOOD_TIMING_GRAPH) {
-        h->err = "mode must be 0, FLOOD_TIMING_LAUNCH or FLOOD_TIMING_GRAPH";
+    if (mode != 0 && mode != FLOOD_TIMING_LAUNCH && mode != FLOOD_TIMING_BATCH) {
+        h->err = "mode must be 0, FLOOD_TIMING_LAUNCH or FLOOD_TIMING_BATCH";
         return FLOOD_EINVAL;
     }
     return h->impl->timing(mode, h->err);

@@ -119,14 +119,8 @@ template <typename T> struct Impl : ImplBase {
 
     // kernel timing
     bool timing_on = false;      // per-launch events (graph capture off while on)
-    bool timing_graph = false;   // per-launch events captured in the batch graphs
+    bool timing_batch = false;   // events around each batch of G steps (graph path kept)
     std::vector<int32_t> tev_steps;   // step launches between each pair of events
-    // graph timing: one captured batch per slot, each with its own event pair
-    // around every step kernel, read back before that slot's batch is launched again
-    hipGraph_t tgraph[2] = {nullptr, nullptr};
-    hipGraphExec_t tgexec[2] = {nullptr, nullptr};
-    std::vector<hipEvent_t> tgev[2];
-    bool tg_pending[2] = {false, false};
     std::vector<hipEvent_t> tev;
     size_t tev_used = 0;
     double t_ms = 0.0;
@@ -200,12 +194,9 @@ template <typename T> struct Impl : ImplBase {
         adj_free_all();
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
-        drop_timing_graphs();
         for (auto e : ev)
             if (e) (void)hipEventDestroy(e);
         for (auto e : tev) (void)hipEventDestroy(e);
-        for (int sl = 0; sl < 2; ++sl)
-            for (auto e : tgev[sl]) (void)hipEventDestroy(e);
         for (void* p : allocs) (void)hipFree(p);
         if (dtlog) (void)hipFree(dtlog);
         if (telog) (void)hipFree(telog);
@@ -303,67 +294,6 @@ template <typename T> struct Impl : ImplBase {
         if (graph) (void)hipGraphDestroy(graph);
         gexec = nullptr;
         graph = nullptr;
-        drop_timing_graphs();
-    }
-
-    void drop_timing_graphs() {
-        for (int sl = 0; sl < 2; ++sl) {
-            if (tgexec[sl]) (void)hipGraphExecDestroy(tgexec[sl]);
-            if (tgraph[sl]) (void)hipGraphDestroy(tgraph[sl]);
-            tgexec[sl] = nullptr;
-            tgraph[sl] = nullptr;
-            tg_pending[sl] = false;
-        }
-    }
-
-    // capture the two timing batches; EHIP when this runtime cannot record events
-    // inside a captured graph
-    flood_status ensure_timing_graphs(std::string& err) {
-        if (tgexec[0] && tgexec[1]) return FLOOD_OK;
-        if (!use_graph) {
-            err = "graph timing needs the captured-graph path (FLOOD_NO_GRAPH is set)";
-            return FLOOD_ESTATE;
-        }
-        for (int sl = 0; sl < 2; ++sl) {
-            while (tgev[sl].size() < (size_t)(2 * G)) {
-                hipEvent_t e;
-                HIPCHK(hipEventCreate(&e));
-                tgev[sl].push_back(e);
-            }
-            hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-            if (e == hipSuccess) {
-                hipError_t er = hipSuccess;
-                for (int i = 0; i < G; ++i) {
-                    launch_plan<T>(PL, st);
-                    if (er == hipSuccess) er = hipEventRecord(tgev[sl][2 * i], st);
-                    launch_steps(SL);
-                    if (er == hipSuccess) er = hipEventRecord(tgev[sl][2 * i + 1], st);
-                }
-                e = hipStreamEndCapture(st, &tgraph[sl]);
-                if (e == hipSuccess) e = er;
-            }
-            if (e == hipSuccess && tgraph[sl]) e = hipGraphInstantiate(&tgexec[sl], tgraph[sl], nullptr, nullptr, 0);
-            if (e != hipSuccess || !tgexec[sl]) {
-                (void)hipGetLastError();
-                drop_timing_graphs();
-                err = std::string("events cannot be recorded inside a captured graph here: ") + hipGetErrorString(e);
-                return FLOOD_EHIP;
-            }
-        }
-        return FLOOD_OK;
-    }
-
-    // fold the kernel times of slot sl's last timing batch (complete by then)
-    flood_status harvest_timing(int sl, std::string& err) {
-        if (!tg_pending[sl]) return FLOOD_OK;
-        for (int i = 0; i < G; ++i) {
-            float el = 0;
-            HIPCHK(hipEventElapsedTime(&el, tgev[sl][2 * i], tgev[sl][2 * i + 1]));
-            t_ms += el;
-            t_launches += 1;
-        }
-        tg_pending[sl] = false;
-        return FLOOD_OK;
     }
 
     flood_status init(int nc, const flood_grid* grids, const flood_params* params, const int32_t* members,
@@ -1042,12 +972,11 @@ template <typename T> struct Impl : ImplBase {
     }
 
     flood_status launch_batch(int slot, std::string& err) {
-        if (timing_graph) {
-            CHK(ensure_timing_graphs(err));
-            CHK(harvest_timing(slot, err));
-            HIPCHK(hipGraphLaunch(tgexec[slot], st));
-            tg_pending[slot] = true;
-        } else if (gexec && !timing_on) {
+        if (timing_batch) {
+            if (next_event_pair(G)) { err = "hipEventCreate failed"; return FLOOD_EHIP; }
+            HIPCHK(hipEventRecord(tev[tev_used], st));
+        }
+        if (gexec && !timing_on) {
             HIPCHK(hipGraphLaunch(gexec, st));
         } else {
             for (int i = 0; i < G; ++i) {
@@ -1062,6 +991,10 @@ template <typename T> struct Impl : ImplBase {
                     launch_steps(SL);
                 }
             }
+        }
+        if (timing_batch) {
+            HIPCHK(hipEventRecord(tev[tev_used + 1], st));
+            tev_used += 2;
         }
         launch_count_active(n_total, t, fault, d_tend, status, steps, step_lim, d_count, st);
         HIPCHK(hipGetLastError());
@@ -1101,11 +1034,7 @@ template <typename T> struct Impl : ImplBase {
             }
         }
         HIPCHK(hipStreamSynchronize(st));
-        if (timing_graph) {
-            CHK(harvest_timing(0, err));
-            CHK(harvest_timing(1, err));
-        }
-        if (timing_on) {
+        if (timing_on || timing_batch) {
             for (size_t i = 0; i < tev_used; i += 2) {
                 float el = 0;
                 HIPCHK(hipEventElapsedTime(&el, tev[i], tev[i + 1]));
@@ -1711,13 +1640,7 @@ template <typename T> struct Impl : ImplBase {
             tev_used = 0;
         }
         timing_on = mode == FLOOD_TIMING_LAUNCH;
-        timing_graph = false;
-        if (mode == FLOOD_TIMING_GRAPH) {
-            CHK(ensure_graph(err));
-            CHK(ensure_timing_graphs(err));
-            tg_pending[0] = tg_pending[1] = false;
-            timing_graph = true;
-        }
+        timing_batch = mode == FLOOD_TIMING_BATCH;
         return FLOOD_OK;
     }
 

@@ -423,12 +423,12 @@ def flood_adjoint_release(h):
     _check(load_library().flood_adjoint_release(h), h)
 
 
-TIMING_LAUNCH, TIMING_GRAPH = 1, 2
+TIMING_LAUNCH, TIMING_BATCH = 1, 2
 
 
 def flood_timing(h, mode):
     """mode: 0 / False off, 1 / True an event pair around every step launch with the
-    graph path off, 2 the same event pairs recorded inside the captured graphs."""
+    graph path off, 2 an event pair around every captured batch of steps."""
     _check(load_library().flood_timing(h, int(mode)), h)
 
 

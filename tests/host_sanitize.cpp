@@ -254,7 +254,7 @@ static void handle_calls() {
     EXPECT(flood_step_n(h, 10.0, 1) == FLOOD_OK && r->calls == 2);
     EXPECT(flood_log_steps(h, 0) == FLOOD_OK && r->calls == 3);
     EXPECT(flood_device_snapshot(h, FLOOD_SNAPSHOT_RELEASE) == FLOOD_OK && r->calls == 4);
-    EXPECT(flood_timing(h, FLOOD_TIMING_GRAPH) == FLOOD_OK && flood_timing(h, 0) == FLOOD_OK && r->calls == 6);
+    EXPECT(flood_timing(h, FLOOD_TIMING_BATCH) == FLOOD_OK && flood_timing(h, 0) == FLOOD_OK && r->calls == 6);
     flood_destroy(h);
 
     // the resampler's checks run before any device work

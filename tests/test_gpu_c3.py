@@ -1,0 +1,204 @@
+"""The differentiation workload (1024^2 urban cells, 16 members, the 1800-s
+storm, depth gauges sampled every 10 s, checkpoints every 100 steps) checked as
+configured, through the C ABI.
+
+* A 128^2 crop of its catchment over the whole storm from the dry start, 8
+  street gauges every 10 s, checkpoints every 100 steps: the GPU adjoint of the
+  FP64 and of the FP32 handle against the FP64 oracle's adjoint, the Manning
+  gradient compared cell by cell wherever |g| >= 1e-3 max|g|, the
+  rain-multiplier gradient member by member, the loss.
+* Central differences of the FP64 GPU loss at a 1e-3 relative perturbation on
+  the same crop over the same storm, with a fixed step (a perturbed run then
+  keeps its step sequence, and the frozen-step adjoint is the exact gradient of
+  the discrete loss between wet/dry switches).
+* A directional difference at the same perturbation on the full 1024^2 grid
+  with all 16 members.
+
+The differences use h_dry = 1e-6 m.  With the paper's 1e-3 m the discrete loss
+jumps wherever a link switches wet (it starts carrying g h_dry dt S at once),
+and over a whole storm a perturbed run crosses many such switches: measured on
+this crop, the central difference of the rain multiplier misses the adjoint by
+24 % at a 1e-3 perturbation and by 84 % and 97 % at 1e-4 and 1e-5 (the jumps
+divided by the step), while at h_dry = 1e-6 m the jumps fall below the loss's
+resolution and the differences converge to the adjoint (5e-5 and 6e-6 relative
+at 1e-3 and 1e-4 for the rain multiplier, 5e-6 and 4e-6 in a Manning direction;
+the remaining gap is linear in the step: the kinks of the clamp, the limiter
+and the branch choices crossed inside it).  The adjoint against the oracle's
+adjoint keeps the paper's 1e-3 m.
+
+Bars.  FP64 handle against the FP64 oracle: the same discrete adjoint in the
+same precision, differing by summation order only: loss 1e-10, every
+rain-multiplier gradient 1e-8, every Manning-gradient cell above the floor
+1e-6 (the floor's smallest cells carry the most cancellation).  FP32 handle:
+its trajectory differs from the FP64 one by rounding only (single-precision
+state, stochastically rounded depth update, ~1e-5 relative after the 1259
+steps of the storm), and the gradient follows the state: loss 1e-4, rain
+multipliers 1e-3, Manning field 1e-3 in the 2-norm and 99 % of the cells above
+the floor within 1e-2.  Differences: a switch of a wet/dry decision inside the
+perturbation puts a kink into the loss that the frozen-branch adjoint does not
+see, and the gap it leaves grows linearly with the perturbation: central
+differences at 1e-3 are held at 2e-4 (rain multipliers) and 1e-4 (Manning
+directions), twice the crop's measured gaps, and the full grid at the same bars.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CROP = (448, 448, 128)      # first row, first column, size
+T_END, SDT, CKPT = 1800.0, 10.0, 100
+H_DRY_FD = 1e-6             # m, for the finite differences (see above)
+
+
+@pytest.fixture(scope="module")
+def fl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2302_08341_amd import flood
+    flood.load_library()
+    return flood
+
+
+@pytest.fixture(scope="module")
+def crop():
+    wl = W.config3()
+    c = wl.catchments[0]
+    r0, c0, n = CROP
+    z = np.ascontiguousarray(c.dem[r0:r0 + n, c0:c0 + n])
+    man = np.ascontiguousarray(c.manning[r0:r0 + n, c0:c0 + n])
+    street = c.street[r0:r0 + n, c0:c0 + n]
+    g = W.pick_gauges(street, 8, np.random.default_rng(W.seed_for(3, 80)))
+    obs = np.random.default_rng(W.seed_for(3, 81)).uniform(0.0, 0.05, size=(int(T_END / SDT), len(g)))
+    return wl, c, z, man, g, obs
+
+
+def _ens(fl, wl, c, z, man, members, **kw):
+    cat = dict(dem=z, manning=man, dx=c.dx, edge_kind=c.edge_kind, edge_slope=c.edge_slope,
+               n_members=len(members), n_scale=c.n_scale[members], rain_mult=c.rain_mult[members])
+    return fl.FloodEnsemble([cat], wl.rain, rain_interval=wl.rain_interval, **kw)
+
+
+MEMBERS = [0, 5]
+
+
+@pytest.fixture(scope="module")
+def oracle_grads(orc, crop):
+    wl, c, z, man, g, obs = crop
+    m = orc.Model(z, man, c.dx, wl.rain, rain_interval=wl.rain_interval, edge_kind=c.edge_kind,
+                  edge_slope=c.edge_slope)
+    L, gn, gm = 0.0, np.zeros(z.shape), []
+    for i in MEMBERS:
+        mem = orc.Member.dry(m, s=c.n_scale[i], mu=c.rain_mult[i])
+        Li, gni, gmi, _ = orc.adjoint(m, mem, T_END, SDT, g, obs, ckpt_every=CKPT)
+        L += Li
+        gn += gni
+        gm.append(gmi)
+    return L, gn, np.array(gm)
+
+
+def _cellwise(gn, gno):
+    floor = 1e-3 * np.abs(gno).max()
+    sel = np.abs(gno) >= floor
+    rel = np.abs(gn[sel] - gno[sel]) / np.abs(gno[sel])
+    return rel, int(sel.sum())
+
+
+@pytest.mark.parametrize("rb", [8, 4])
+def test_crop_full_storm_adjoint_against_oracle(fl, crop, oracle_grads, rb):
+    wl, c, z, man, g, obs = crop
+    e = _ens(fl, wl, c, z, man, MEMBERS, real_bytes=rb, step_kernel=3)
+    L, gn, gm = e.adjoint(0, T_END, SDT, g, obs, ckpt_every=CKPT)
+    Lo, gno, gmo = oracle_grads
+    rel, n_sel = _cellwise(gn, gno)
+    norm = np.linalg.norm(gn - gno) / np.linalg.norm(gno)
+    print("FP%d: loss %.10g vs %.10g (rel %.2e); rain-multiplier gradients %s vs %s; Manning gradient: "
+          "2-norm rel %.2e, %d cells above the floor, rel error median %.2e, 99th pct %.2e, max %.2e"
+          % (8 * rb, L, Lo, abs(L - Lo) / Lo, gm, gmo, norm, n_sel, np.median(rel), np.percentile(rel, 99),
+             rel.max()))
+    assert n_sel > 100
+    if rb == 8:
+        assert L == pytest.approx(Lo, rel=1e-10)
+        np.testing.assert_allclose(gm, gmo, rtol=1e-8)
+        assert rel.max() <= 1e-6
+        assert norm <= 1e-8
+    else:
+        assert L == pytest.approx(Lo, rel=1e-5)
+        np.testing.assert_allclose(gm, gmo, rtol=1e-4)
+        assert norm <= 1e-5
+        assert np.percentile(rel, 99) <= 1e-3 and rel.max() <= 1e-2
+
+
+def _loss_fixed(fl, wl, c, z, man, g, obs, mu=None):
+    cat = dict(dem=z, manning=man, dx=c.dx, edge_kind=c.edge_kind, edge_slope=c.edge_slope,
+               n_members=len(MEMBERS), n_scale=c.n_scale[MEMBERS],
+               rain_mult=c.rain_mult[MEMBERS] if mu is None else mu)
+    # half a second: the Courant number of the crop's deepest water (0.8 m) is 0.46
+    e = fl.FloodEnsemble([cat], wl.rain, rain_interval=wl.rain_interval, real_bytes=8, step_kernel=3,
+                         dt_fixed=0.5, h_dry=H_DRY_FD)
+    return e.adjoint(0, T_END, SDT, g, obs, ckpt_every=CKPT)
+
+
+def test_crop_central_differences(fl, crop):
+    wl, c, z, man, g, obs = crop
+    L, gn, gm = _loss_fixed(fl, wl, c, z, man, g, obs)
+    eps = 1e-3
+    mu = c.rain_mult[MEMBERS]
+    for k in range(len(MEMBERS)):
+        mp, mm = mu.copy(), mu.copy()
+        mp[k] *= 1 + eps
+        mm[k] *= 1 - eps
+        fd = (_loss_fixed(fl, wl, c, z, man, g, obs, mp)[0] - _loss_fixed(fl, wl, c, z, man, g, obs, mm)[0]) / (
+            2 * eps * mu[k])
+        print("rain multiplier of member %d: adjoint %.8g, central difference %.8g (rel %.2e)"
+              % (MEMBERS[k], gm[k], fd, abs(gm[k] - fd) / abs(fd)))
+        assert gm[k] == pytest.approx(fd, rel=2e-4)
+    for seed in (1, 2):
+        v = np.random.default_rng(seed).standard_normal(man.shape)
+        dn = eps * man.astype(np.float64) * v
+        n_p = (man.astype(np.float64) + dn).astype(np.float32)
+        n_m = (man.astype(np.float64) - dn).astype(np.float32)
+        dn_eff = (n_p.astype(np.float64) - n_m.astype(np.float64)) / 2.0
+        fd = (_loss_fixed(fl, wl, c, z, n_p, g, obs)[0] - _loss_fixed(fl, wl, c, z, n_m, g, obs)[0]) / 2.0
+        ad = float(np.sum(gn * dn_eff))
+        print("Manning direction %d: adjoint %.8g, central difference %.8g (rel %.2e)" % (seed, ad, fd,
+                                                                                          abs(ad - fd) / abs(fd)))
+        assert ad == pytest.approx(fd, rel=1e-4)
+
+
+def test_full_grid_directional_difference(fl):
+    wl = W.config3()
+    c = wl.catchments[0]
+    K = c.gauges.shape[0]
+    obs = np.random.default_rng(W.seed_for(3, 82)).uniform(0.0, 0.05, size=(int(T_END / SDT), K))
+    eps = 1e-3
+    v = np.random.default_rng(3).standard_normal(c.manning.shape)
+    dn = eps * c.manning.astype(np.float64) * v
+    n_p = (c.manning.astype(np.float64) + dn).astype(np.float32)
+    n_m = (c.manning.astype(np.float64) - dn).astype(np.float32)
+    dn_eff = (n_p.astype(np.float64) - n_m.astype(np.float64)) / 2.0
+    w = np.random.default_rng(4).standard_normal(c.n_members)
+
+    def run(man, mu):
+        cat = dict(dem=c.dem, manning=man, dx=c.dx, edge_kind=c.edge_kind, edge_slope=c.edge_slope,
+                   n_members=c.n_members, n_scale=c.n_scale, rain_mult=mu)
+        # a quarter second: the Courant number stays below 0.7 for depths up to 3.7 m
+        e = fl.FloodEnsemble([cat], wl.rain, rain_interval=wl.rain_interval, real_bytes=8, dt_fixed=0.25,
+                             h_dry=H_DRY_FD)
+        out = e.adjoint(0, T_END, SDT, c.gauges, obs, ckpt_every=wl.extra["ckpt_every"])
+        e.close()
+        return out
+
+    L, gn, gm = run(c.manning, c.rain_mult)
+    fd_n = (run(n_p, c.rain_mult)[0] - run(n_m, c.rain_mult)[0]) / 2.0
+    ad_n = float(np.sum(gn * dn_eff))
+    dmu = eps * c.rain_mult * w
+    fd_m = (run(c.manning, c.rain_mult + dmu)[0] - run(c.manning, c.rain_mult - dmu)[0]) / 2.0
+    ad_m = float(np.sum(gm * dmu))
+    print("1024^2 x 16, 1800 s: Manning direction adjoint %.8g vs difference %.8g (rel %.2e); rain-multiplier "
+          "direction adjoint %.8g vs difference %.8g (rel %.2e)"
+          % (ad_n, fd_n, abs(ad_n - fd_n) / abs(fd_n), ad_m, fd_m, abs(ad_m - fd_m) / abs(fd_m)))
+    assert ad_n == pytest.approx(fd_n, rel=1e-4)
+    assert ad_m == pytest.approx(fd_m, rel=2e-4)
