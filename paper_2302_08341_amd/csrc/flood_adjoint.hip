@@ -321,8 +321,9 @@ __device__ __forceinline__ void le_load(const T* lh, const uint8_t* cl, T (&d)[V
 // adjoint are added in the order east, south, west, north (as in k_adj).  The
 // rain-multiplier adjoint is accumulated per (strip, member).  Members that do
 // not step in this launch (or pad the last quad) skip the march and keep their
-// adjoint in place, but still meet the workgroup barrier.
-template <typename T, int V>
+// adjoint in place, but still meet the workgroup barrier.  PF = 1 issues the
+// next row's loads before the current row's derivatives (one row of lookahead).
+template <typename T, int V, int PF>
 __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
     extern __shared__ unsigned char adj_lds[];
     const CatchDev<T>& C = A.c;
@@ -403,18 +404,29 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
             for (int j = 0; j < V; ++j) pNh[j] = pNn[j] = T(0);
         }
         double lsum = 0.0;
+        // a row's links (qE, qS and their adjoints) and the row below it (hs, zs, ns, les)
+        auto load_row = [&](size_t c, bool below, T (&qe)[V], T (&qs)[V], T (&lqe)[V], T (&lqs)[V], T (&h2)[V],
+                            T (&z2)[V], T (&n2)[V], T (&le2)[V]) {
+            const size_t cb = below ? c + nx : c;
+            vload<T, V>(QX + c, qe);
+            vload<T, V>(QY + c, qs);
+            vload<T, V>(H + cb, h2);
+            vload<T, V>(LQX + c, lqe);
+            vload<T, V>(LQY + c, lqs);
+            vload<T, V>(Z + cb, z2);
+            vload<T, V>(Nn + cb, n2);
+            le_load<T, V>(LH + cb, CL + cb, le2);
+        };
+        T qE[V], qS[V], lqE[V], lqS[V], hs[V], zs[V], ns[V], les[V];
+        if (PF) load_row(ca, r0 + 1 < ny, qE, qS, lqE, lqS, hs, zs, ns, les);
         for (int r = r0; r < r1; ++r) {
             const bool hasS = r + 1 < ny;
-            const size_t cs = hasS ? ca + nx : ca;
-            T qE[V], qS[V], lqE[V], lqS[V], hs[V], zs[V], ns[V], les[V];
-            vload<T, V>(QX + ca, qE);
-            vload<T, V>(QY + ca, qS);
-            vload<T, V>(H + cs, hs);
-            vload<T, V>(LQX + ca, lqE);
-            vload<T, V>(LQY + ca, lqS);
-            vload<T, V>(Z + cs, zs);
-            vload<T, V>(Nn + cs, ns);
-            le_load<T, V>(LH + cs, CL + cs, les);
+            T qE2[V], qS2[V], lqE2[V], lqS2[V], hs2[V], zs2[V], ns2[V], les2[V];
+            if (PF) {
+                if (r + 1 < r1) load_row(ca + nx, r + 2 < ny, qE2, qS2, lqE2, lqS2, hs2, zs2, ns2, les2);
+            } else {
+                load_row(ca, hasS, qE, qS, lqE, lqS, hs, zs, ns, les);
+            }
             // east neighbour of the lane's last cell = first cell of the next lane
             const T hE = __shfl_down(hc[0], 1, 64);
             const T zE = __shfl_down(zc[0], 1, 64);
@@ -539,6 +551,19 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
                 pNh[j] = ltS[j] * d2S[j];
                 pNn[j] = ltS[j] * cnS[j];
             }
+            if (PF) {
+    #pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    qE[j] = qE2[j];
+                    qS[j] = qS2[j];
+                    lqE[j] = lqE2[j];
+                    lqS[j] = lqS2[j];
+                    hs[j] = hs2[j];
+                    zs[j] = zs2[j];
+                    ns[j] = ns2[j];
+                    les[j] = les2[j];
+                }
+            }
             ca += nx;
         }
         // rain-multiplier adjoint: the depth adjoint after the step summed over the
@@ -574,7 +599,10 @@ template <typename T> void launch_adjoint_march(const AdjvLaunch<T>& A, hipStrea
     const int nq = (C.n_members + 3) / 4;
     const dim3 grid(march_waves(C.strips_xa, C.strips_y, nq, C.march_order, C.march_bands));
     const size_t lds = (size_t)4 * C.march_rows * 64 * V * sizeof(T);
-    hipLaunchKernelGGL((k_adjv<T, V>), grid, dim3(kBlock), lds, s, A);
+    if (A.pf)
+        hipLaunchKernelGGL((k_adjv<T, V, 1>), grid, dim3(kBlock), lds, s, A);
+    else
+        hipLaunchKernelGGL((k_adjv<T, V, 0>), grid, dim3(kBlock), lds, s, A);
 }
 
 // One lane per member of the group.

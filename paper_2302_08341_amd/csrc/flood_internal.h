@@ -269,6 +269,7 @@ template <typename T> struct AdjvLaunch {
     const double* rdt;        // [group members]
     T* nacc;                  // [member quads][cell] Manning-field adjoint per quad of members (accumulated)
     double* mubar_part;       // [strips][group members] rain-multiplier adjoint partials (accumulated)
+    int32_t pf;               // 1: one row of load lookahead in the reverse march
 };
 template <typename T> void launch_adjoint_march(const AdjvLaunch<T>& A, hipStream_t s);
 // before each reverse launch: flip the adjoint copy of members that stepped in

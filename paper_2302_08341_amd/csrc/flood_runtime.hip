@@ -74,6 +74,7 @@ template <typename T> struct Impl : ImplBase {
     int march_bands = 0;      // order 4: bands of rows of strips (multiple of 8); 0: from the L2 size
     int march_nt = 1;         // non-temporal state streams in the vectorised row-marching kernel
     int march_pf = 1;         // one row of load lookahead in the vectorised row-marching kernel
+    int adj_pf = 1;           // the same in the adjoint's reverse march
     int total_waves = 0;      // waves of one row-marching launch
     int n_catch = 0, n_total = 0;
     std::vector<Cat> cats;
@@ -317,6 +318,7 @@ template <typename T> struct Impl : ImplBase {
         }
         if (const char* nt = std::getenv("FLOOD_MARCH_NT")) march_nt = std::atoi(nt) ? 1 : 0;
         if (const char* pf = std::getenv("FLOOD_MARCH_PF")) march_pf = std::min(2, std::max(0, std::atoi(pf)));
+        if (const char* pf = std::getenv("FLOOD_ADJ_PF")) adj_pf = std::atoi(pf) ? 1 : 0;
         const char* ng = std::getenv("FLOOD_NO_GRAPH");
         use_graph = !(ng && ng[0] == '1');
         if (const char* gs = std::getenv("FLOOD_GRAPH_STEPS")) {   // steps per captured batch
@@ -2169,6 +2171,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                     A.rdt = d_rdtcur;
                     A.nacc = d_nacc;
                     A.mubar_part = d_mubar;
+                    A.pf = adj_pf;
                     launch_adjoint_march<T>(A, st);
                 }
                 HIPCHK(hipGetLastError());
