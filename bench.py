@@ -652,6 +652,13 @@ def main():
         log("plain leg done")
 
     detail["copy_ceiling_GBps"] = elementwise_ceiling(torch)
+    # the step's own access pattern without its arithmetic, halo cells or prologue rows
+    from paper_2302_08341_amd import flood as _fl
+    pat_gbps, pat_ms = _fl.flood_probe_stream(c.ny, c.nx, N, conf_end["march_rows"], 5)
+    detail["pattern_ceiling"] = {"GBps": pat_gbps, "ms_per_launch": pat_ms,
+                                 "what": "flood_probe_stream: the vectorised step's streams (3 state arrays in and "
+                                         "out, bed and roughness in, 16-byte accesses, %d-row strips of 256 cells) "
+                                         "with no arithmetic, all %d members every launch" % (conf_end["march_rows"], N)}
     detail["gpu_clock_in_timed_region"] = clock_stats
     detail.update({"member_steps": member_steps, "mcu": mcu, "elapsed_s": elapsed, "cycles": cycle_log[args.warmup:],
                    "resampled": resampled[args.warmup:], "restarts_at_cycles": restarts,

@@ -388,6 +388,20 @@ flood_status flood_get_config(const flood_handle* h, int32_t* member_interleave,
  * Errors: EINVAL. */
 flood_status flood_get_march_rows(flood_handle* h, int32_t catchment, int32_t* march_rows);
 
+/* Measurement helper: the attainable bandwidth of the row-marching step's
+ * access pattern on this device.  A streaming kernel with the vectorised step's
+ * geometry (a wavefront per strip of 256 cells and member, marching `rows` rows;
+ * per row three member state arrays read and written with 16-byte non-temporal
+ * accesses and the shared bed and roughness read) but no halo cells and no link
+ * arithmetic runs `reps` timed launches on n_members x ny x nx FP32 cells of
+ * buffers it allocates and frees (6 x 4 B per member-cell plus 8 B per cell);
+ * *gbps_out receives 24 B per member-cell update over the fastest launch and
+ * *ms_per_launch_out that launch's duration.  Errors: EINVAL (ny < 1, nx not a
+ * positive multiple of 4, more than 2^31 member-cells, rows outside 1..4096,
+ * reps outside 1..1000, NULL outputs), ENOMEM, EHIP. */
+flood_status flood_probe_stream(int32_t ny, int32_t nx, int32_t n_members, int32_t rows, int32_t reps,
+                                void* hip_stream, double* gbps_out, double* ms_per_launch_out);
+
 /* Timing of the step launches of flood_step calls between flood_timing(h,
  * mode) and flood_timing(h, 0), with HIP events on the handle's stream.
  * FLOOD_TIMING_LAUNCH: an event pair around every step kernel launch, launched

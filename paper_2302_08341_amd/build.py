@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libflood.so")
 SOURCES = ["flood_kernels.hip", "flood_pf.hip", "flood_adjoint.hip", "flood_runtime.hip", "flood_abi.cpp",
-           "flood_tune.cpp", "flood_validate.cpp"]
+           "flood_tune.cpp", "flood_validate.cpp", "flood_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function"]

@@ -308,12 +308,8 @@ __device__ __forceinline__ void le_load(const T* lh, const uint8_t* cl, T (&d)[V
 }
 
 // Reverse step in row-march form.  Geometry as the forward row march: a
-// wavefront marches a strip of 64 V cells down its rows for one member, every
-// lane owning V cells; the cells beside the strip come from single-lane loads
-// (lane 0: the west cell's depth, bed, roughness, east link and its adjoint,
-// and the depth adjoint; lane 63: the east cell's depth, bed, roughness and
-// depth adjoint), and lane 0 differentiates the strip's west link exactly as
-// the strip to the west differentiates its east link.  A workgroup holds the four members of a member
+// wavefront marches a strip of 62 V cells down its rows for one member; lanes
+// 0 and 63 are halo lanes.  A workgroup holds the four members of a member
 // quad on the same strip (wavefront w: member 4u + w), so their contributions
 // to the shared Manning-field adjoint are added in LDS, member by member in
 // that order, and the quad's accumulator in HBM is read and written once per
@@ -336,7 +332,7 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int nq = (C.n_members + 3) / 4;
     int u, sx, sy;
-    if (!march_wave(C, b, nq, u, sx, sy)) return;   // uniform over the workgroup
+    if (!march_wave(C, b, nq, u, sx, sy, C.strips_xa)) return;   // uniform over the workgroup
     const int k = 4 * u + wave;
     bool actq[4];
 #pragma unroll
@@ -346,16 +342,12 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
     const int rows = C.march_rows;
     // this wavefront's Manning contributions, [row][lane][V]
     T* NL = reinterpret_cast<T*>(adj_lds) + (size_t)wave * rows * 64 * V;
-    const int x0 = sx * (64 * V);                      // first cell of the strip
-    const int xl = x0 + V * lane;
-    const bool own = xl < nx;
+    const int xl = sx * (62 * V) - V + V * lane;
+    const bool inx = xl >= 0 && xl < nx;
+    const bool own = lane >= 1 && lane <= 62 && inx;
     const bool westw = sx == 0;                        // wavefront-uniform edge tests
-    const bool eastw = sx == C.strips_x - 1;
-    const int xa = min(xl, nx - V);                    // load column (lanes outside the grid read, never use)
-    // halo: lane 0 the cell west of the strip, lane 63 the one east of it (clamped
-    // into the grid where there is none; then never used)
-    const bool halo_lane = lane == 0 || lane == 63;
-    const int xh = lane == 0 ? (westw ? 0 : x0 - 1) : (eastw ? nx - 1 : x0 + 64 * V);
+    const bool eastw = sx == C.strips_xa - 1;
+    const int xa = min(max(xl, 0), nx - V);            // load column (lanes outside the grid read, never use)
     const int r0 = sy * C.march_rows;
     const int r1 = min(r0 + C.march_rows, ny);
     const size_t plane = (size_t)ny * nx;
@@ -414,7 +406,7 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
         double lsum = 0.0;
         // a row's links (qE, qS and their adjoints) and the row below it (hs, zs, ns, les)
         auto load_row = [&](size_t c, bool below, T (&qe)[V], T (&qs)[V], T (&lqe)[V], T (&lqs)[V], T (&h2)[V],
-                            T (&z2)[V], T (&n2)[V], T (&le2)[V], AdjHalo<T>& ho) {
+                            T (&z2)[V], T (&n2)[V], T (&le2)[V]) {
             const size_t cb = below ? c + nx : c;
             vload<T, V>(QX + c, qe);
             vload<T, V>(QY + c, qs);
@@ -424,41 +416,22 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
             vload<T, V>(Z + cb, z2);
             vload<T, V>(Nn + cb, n2);
             le_load<T, V>(LH + cb, CL + cb, le2);
-            if (halo_lane) {
-                // the row's halo cell (the row of the links, not the row below)
-                const size_t c1 = c - xa + xh;
-                ho.h = H[c1];
-                ho.z = Z[c1];
-                ho.n = Nn[c1];
-                ho.q = QX[c1];
-                ho.lq = LQX[c1];
-                ho.le = CL[c1] ? T(0) : LH[c1];
-            }
         };
         T qE[V], qS[V], lqE[V], lqS[V], hs[V], zs[V], ns[V], les[V];
-        AdjHalo<T> hx;
-        if (PF) load_row(ca, r0 + 1 < ny, qE, qS, lqE, lqS, hs, zs, ns, les, hx);
+        if (PF) load_row(ca, r0 + 1 < ny, qE, qS, lqE, lqS, hs, zs, ns, les);
         for (int r = r0; r < r1; ++r) {
             const bool hasS = r + 1 < ny;
             T qE2[V], qS2[V], lqE2[V], lqS2[V], hs2[V], zs2[V], ns2[V], les2[V];
-            AdjHalo<T> hx2;
             if (PF) {
-                if (r + 1 < r1) load_row(ca + nx, r + 2 < ny, qE2, qS2, lqE2, lqS2, hs2, zs2, ns2, les2, hx2);
+                if (r + 1 < r1) load_row(ca + nx, r + 2 < ny, qE2, qS2, lqE2, lqS2, hs2, zs2, ns2, les2);
             } else {
-                load_row(ca, hasS, qE, qS, lqE, lqS, hs, zs, ns, les, hx);
+                load_row(ca, hasS, qE, qS, lqE, lqS, hs, zs, ns, les);
             }
-            // east neighbour of the lane's last cell = first cell of the next lane; for
-            // lane 63 the halo cell east of the strip
-            T hE = __shfl_down(hc[0], 1, 64);
-            T zE = __shfl_down(zc[0], 1, 64);
-            T nE = __shfl_down(nc[0], 1, 64);
-            T leE = __shfl_down(lec[0], 1, 64);
-            if (lane == 63) {
-                hE = hx.h;
-                zE = hx.z;
-                nE = hx.n;
-                leE = hx.le;
-            }
+            // east neighbour of the lane's last cell = first cell of the next lane
+            const T hE = __shfl_down(hc[0], 1, 64);
+            const T zE = __shfl_down(zc[0], 1, 64);
+            const T nE = __shfl_down(nc[0], 1, 64);
+            const T leE = __shfl_down(lec[0], 1, 64);
             T ltE[V], dqE[V], d1E[V], d2E[V], cnE[V];
     #pragma unroll
             for (int j = 0; j < V; ++j) {
@@ -484,18 +457,9 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
                     }
                 }
             }
-            // west link of the first cell: the previous lane's last east link; for lane 0
-            // the strip's west link, with the operands the strip to the west uses
-            T wH = __shfl_up(ltE[V - 1] * d2E[V - 1], 1, 64);
-            T wN = __shfl_up(ltE[V - 1] * cnE[V - 1], 1, 64);
-            if (lane == 0 && !westw) {
-                const T nf = T(0.5) * (hx.n + nc[0]);
-                T dq, d1, d2, cn;
-                link_in_d(hx.q, hx.h, hc[0], zc[0] - hx.z, g * (nf * nf), g * nf, ms, hdry, dq, d1, d2, cn);
-                const T lt = hx.lq + kk * (lec[0] - hx.le);
-                wH = lt * d2;
-                wN = lt * cn;
-            }
+            // west link of the first cell: the previous lane's last east link
+            const T wH = __shfl_up(ltE[V - 1] * d2E[V - 1], 1, 64);
+            const T wN = __shfl_up(ltE[V - 1] * cnE[V - 1], 1, 64);
             // south links
             T ltS[V], dqS[V], d1S[V], d2S[V], cnS[V];
             if (hasS) {
@@ -588,7 +552,6 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
                 pNn[j] = ltS[j] * cnS[j];
             }
             if (PF) {
-                hx = hx2;
     #pragma unroll
                 for (int j = 0; j < V; ++j) {
                     qE[j] = qE2[j];
@@ -606,7 +569,7 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
         // rain-multiplier adjoint: the depth adjoint after the step summed over the
         // strip's cells, times R dt of the member's step
         for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
-        if (lane == 0) A.mubar_part[(size_t)(sy * C.strips_x + sx) * C.n_members + k] += lsum * A.rdt[k];
+        if (lane == 0) A.mubar_part[(size_t)(sy * C.strips_xa + sx) * C.n_members + k] += lsum * A.rdt[k];
     }
     __syncthreads();
     // the quad's Manning-field adjoint: wavefront w adds rows w, w + 4, ... of the
@@ -634,7 +597,7 @@ template <typename T> void launch_adjoint_march(const AdjvLaunch<T>& A, hipStrea
     constexpr int V = march_vec<T>();
     const CatchDev<T>& C = A.c;
     const int nq = (C.n_members + 3) / 4;
-    const dim3 grid(march_waves(C.strips_x, C.strips_y, nq, C.march_order, C.march_bands));
+    const dim3 grid(march_waves(C.strips_xa, C.strips_y, nq, C.march_order, C.march_bands));
     const size_t lds = (size_t)4 * C.march_rows * 64 * V * sizeof(T);
     if (A.pf)
         hipLaunchKernelGGL((k_adjv<T, V, 1>), grid, dim3(kBlock), lds, s, A);

@@ -198,13 +198,6 @@ struct Halo {
     uint32_t cls = 0;                           // land-cover class (roughness from the member's table)
 };
 
-// the cell beside a reverse-march strip: depth, bed, roughness, east link, the
-// link's adjoint and the depth adjoint after the clamp branch
-template <typename T>
-struct AdjHalo {
-    T h = T(0), z = T(0), n = T(0), q = T(0), lq = T(0), le = T(0);
-};
-
 // v as held by lane src of the wavefront (ds_bpermute: byte address = 4 x lane)
 __device__ __forceinline__ float lane_read(float v, int src) {
     return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));

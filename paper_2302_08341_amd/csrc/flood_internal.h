@@ -62,8 +62,8 @@ template <typename T> struct CatchDev {
     // row-march variants (members in planes): strips of march_rows rows, one
     // wavefront per (strip, group of march_seg members); strips_x counts the
     // strips of the kernel the view is launched with (62 cells for k_march, 64 V
-    // for k_marchv and the adjoint's reverse step)
-    int32_t march_rows, strips_x, strips_y;
+    // for k_marchv), strips_xa those of the adjoint's reverse step (62 V cells)
+    int32_t march_rows, strips_x, strips_y, strips_xa;
     int32_t wave_begin, n_waves;
     int32_t march_order;      // wavefront order, see march_wave
     int32_t march_bands;      // order 4: bands of rows of strips, a multiple of 8

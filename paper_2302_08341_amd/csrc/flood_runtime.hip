@@ -74,7 +74,7 @@ template <typename T> struct Impl : ImplBase {
     int march_bands = 0;      // order 4: bands of rows of strips (multiple of 8); 0: from the L2 size
     int march_nt = 1;         // non-temporal state streams in the vectorised row-marching kernel
     int march_pf = 1;         // one row of load lookahead in the vectorised row-marching kernel
-    int adj_pf = 0;           // the same in the adjoint's reverse march (off: its registers cost a wave per SIMD)
+    int adj_pf = 0;           // the same in the adjoint's reverse march (off: 4.64 s against 4.15 s per C5 call)
     int total_waves = 0;      // waves of one row-marching launch
     int n_catch = 0, n_total = 0;
     std::vector<Cat> cats;
@@ -248,6 +248,7 @@ template <typename T> struct Impl : ImplBase {
             d.march_rows = std::max(1, std::min(c.march_rows, c.ny));
             const int strip_w = variant == 3 ? 64 * march_vec<T>() : 62;
             d.strips_x = (c.nx + strip_w - 1) / strip_w;
+            d.strips_xa = (c.nx + 62 * march_vec<T>() - 1) / (62 * march_vec<T>());
             d.strips_y = (c.ny + d.march_rows - 1) / d.march_rows;
             d.wave_begin = waves;
             {
@@ -1674,11 +1675,13 @@ static CatchDev<T> group_view(const CatchDev<T>& C, int mi, int g0, int G, T* co
     v.tiles_x = (C.nx + (1 << l) - 1) >> l;
     v.tiles_y = (C.ny + ty - 1) / ty;
     // row-march geometry (members in planes), likewise fixed
-    const int strip_w = 64 * march_vec<T>();       // k_marchv (recorded forward, tape recomputation) and k_adjv
+    const int strip_w = 64 * march_vec<T>();       // the recorded forward and tape recomputation (k_marchv)
+    const int strip_wa = 62 * march_vec<T>();      // the reverse step (k_adjv)
     int rows = kAdjMarchRows;   // at most 16: the reverse step stages 4 x rows x 64 x V values in LDS
     if (const char* ar = std::getenv("FLOOD_ADJ_ROWS")) rows = std::min(16, std::max(1, std::atoi(ar)));
     v.march_rows = std::min(rows, C.ny);
     v.strips_x = (C.nx + strip_w - 1) / strip_w;
+    v.strips_xa = (C.nx + strip_wa - 1) / strip_wa;
     v.strips_y = (C.ny + v.march_rows - 1) / v.march_rows;
     v.wave_begin = 0;
     v.march_order = kAdjMarchOrder;
@@ -1809,7 +1812,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
         T* none[2] = {nullptr, nullptr};
         const CatchDev<T> tv = group_view(C.dev, mi, 0, std::min(Gi, N), none, none, none, none, none);
         nblk = tv.tiles_x * tv.tiles_y;
-        if (march_adj) nblk = tv.strips_x * tv.strips_y;
+        if (march_adj) nblk = tv.strips_xa * tv.strips_y;
     }
     CHK(talloc((size_t)nblk * Gi * sizeof(double), (void**)&d_mubar));
     // row-march form: per-member adjoint copy index, Manning-field accumulators,
@@ -2174,7 +2177,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                 HIPCHK(hipGetLastError());
             }
             launch_nacc_reduce<T>((Gg + 3) / 4, ncell, d_nacc, d_nbar, st);
-            launch_sum_parts(V.strips_x * V.strips_y, Gg, d_mubar, d_gm + g0, st);
+            launch_sum_parts(V.strips_xa * V.strips_y, Gg, d_mubar, d_gm + g0, st);
             HIPCHK(hipGetLastError());
             HIPCHK(hipStreamSynchronize(st));
             continue;

@@ -28,6 +28,7 @@ EXPORTED = ["flood_create", "flood_create_batch", "flood_step", "flood_assimilat
             "flood_get_config", "flood_timing", "flood_get_timing", "flood_adjoint_release", "flood_step_n",
             "flood_get_wet_mask", "flood_log_steps", "flood_get_step_log", "flood_get_adjoint_info",
             "flood_systematic_resample_noalloc", "flood_device_snapshot", "flood_get_march_rows",
+            "flood_probe_stream",
             "flood_last_error",
             "flood_strerror", "flood_destroy"]
 
@@ -103,6 +104,7 @@ def load_library():
         "flood_systematic_resample_noalloc": [dp, C.c_int32, C.c_double, ip, C.c_void_p],
         "flood_device_snapshot": [H, C.c_int32],
         "flood_get_march_rows": [H, C.c_int32, ip],
+        "flood_probe_stream": [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, dp, dp],
         "flood_ensemble_products": [H, C.c_int32, C.c_double, C.c_int32, dp, dp, dp, dp],
         "flood_save": [H, C.c_char_p],
         "flood_load": [H, C.c_char_p],
@@ -390,6 +392,15 @@ def flood_systematic_resample_noalloc(w, u0, stream=None):
     rc = load_library().flood_systematic_resample_noalloc(_dp(w), w.size, float(u0), _ip(anc), stream)
     _check(rc, None)
     return anc
+
+
+def flood_probe_stream(ny, nx, n_members, rows, reps=5):
+    """(GB/s, ms per launch) of a streaming kernel with the row-marching step's access
+    pattern and no arithmetic (see flood_probe_stream in include/flood.h)."""
+    gbps, ms = C.c_double(0.0), C.c_double(0.0)
+    _check(load_library().flood_probe_stream(int(ny), int(nx), int(n_members), int(rows), int(reps),
+                                            current_stream(), C.byref(gbps), C.byref(ms)))
+    return gbps.value, ms.value
 
 
 def flood_get_march_rows(h, catchment):
