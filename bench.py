@@ -654,11 +654,16 @@ def main():
     detail["copy_ceiling_GBps"] = elementwise_ceiling(torch)
     # the step's own access pattern without its arithmetic, halo cells or prologue rows
     from paper_2302_08341_amd import flood as _fl
-    pat_gbps, pat_ms = _fl.flood_probe_stream(c.ny, c.nx, N, conf_end["march_rows"], 5)
-    detail["pattern_ceiling"] = {"GBps": pat_gbps, "ms_per_launch": pat_ms,
-                                 "what": "flood_probe_stream: the vectorised step's streams (3 state arrays in and "
-                                         "out, bed and roughness in, 16-byte accesses, %d-row strips of 256 cells) "
-                                         "with no arithmetic, all %d members every launch" % (conf_end["march_rows"], N)}
+    pat = {}
+    for wps in (0, 4):
+        pat[wps] = _fl.flood_probe_stream(c.ny, c.nx, N, conf_end["march_rows"], 5, wps)
+    detail["pattern_ceiling"] = {
+        "GBps": pat[0][0], "ms_per_launch": pat[0][1],
+        "GBps_at_4_waves_per_simd": pat[4][0], "ms_per_launch_at_4_waves_per_simd": pat[4][1],
+        "what": "flood_probe_stream: the vectorised step's streams (3 state arrays in and out, bed and roughness "
+                "in, 16-byte accesses, %d-row strips of 256 cells) with no arithmetic, all %d members every "
+                "launch; at its own occupancy (8 waves per SIMD) and capped at the step kernel's (4)"
+                % (conf_end["march_rows"], N)}
     detail["gpu_clock_in_timed_region"] = clock_stats
     detail.update({"member_steps": member_steps, "mcu": mcu, "elapsed_s": elapsed, "cycles": cycle_log[args.warmup:],
                    "resampled": resampled[args.warmup:], "restarts_at_cycles": restarts,

@@ -396,11 +396,15 @@ flood_status flood_get_march_rows(flood_handle* h, int32_t catchment, int32_t* m
  * arithmetic runs `reps` timed launches on n_members x ny x nx FP32 cells of
  * buffers it allocates and frees (6 x 4 B per member-cell plus 8 B per cell);
  * *gbps_out receives 24 B per member-cell update over the fastest launch and
- * *ms_per_launch_out that launch's duration.  Errors: EINVAL (ny < 1, nx not a
- * positive multiple of 4, more than 2^31 member-cells, rows outside 1..4096,
- * reps outside 1..1000, NULL outputs), ENOMEM, EHIP. */
+ * *ms_per_launch_out that launch's duration.  waves_per_simd 3..8 caps the
+ * wavefronts sharing a SIMD (with LDS reserved per workgroup, at most 54 KiB),
+ * so the pattern can be measured at the step kernel's occupancy; 0 leaves it
+ * to the registers (8).  Errors: EINVAL (ny < 1, nx not a positive multiple of
+ * 4, more than 2^31 member-cells, rows outside 1..4096, reps outside 1..1000,
+ * waves_per_simd not 0 or 3..8, NULL outputs), ENOMEM, EHIP. */
 flood_status flood_probe_stream(int32_t ny, int32_t nx, int32_t n_members, int32_t rows, int32_t reps,
-                                void* hip_stream, double* gbps_out, double* ms_per_launch_out);
+                                int32_t waves_per_simd, void* hip_stream, double* gbps_out,
+                                double* ms_per_launch_out);
 
 /* Timing of the step launches of flood_step calls between flood_timing(h,
  * mode) and flood_timing(h, 0), with HIP events on the handle's stream.

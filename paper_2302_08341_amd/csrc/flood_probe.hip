@@ -11,6 +11,9 @@
 // are no halo cells, no prologue row and no link arithmetic: the written values
 // depend on every loaded value, so no load can be dropped.  What it reaches is
 // the ceiling for the step's 24 bytes per member-cell update with this pattern.
+// Its 32 registers let 8 wavefronts share a SIMD; waves_per_simd > 0 caps that
+// with LDS that every workgroup reserves (160 KiB per CU), so the pattern can
+// also be measured at the step kernel's own occupancy.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -65,8 +68,8 @@ __global__ __launch_bounds__(256) void k_stream_probe(int ny, int nx, int n_memb
     }
 }
 
-flood_status probe_stream_impl(int ny, int nx, int n_members, int rows, int reps, hipStream_t st, double* gbps,
-                               double* ms_per_launch, std::string& err) {
+flood_status probe_stream_impl(int ny, int nx, int n_members, int rows, int reps, int waves_per_simd, hipStream_t st,
+                               double* gbps, double* ms_per_launch, std::string& err) {
     const size_t plane = (size_t)ny * nx;
     const size_t state = plane * n_members;
     std::vector<void*> bufs;
@@ -102,6 +105,8 @@ flood_status probe_stream_impl(int ny, int nx, int n_members, int rows, int reps
     const int strips_x = (nx + 255) / 256, strips_y = (ny + rows - 1) / rows;
     const long long waves = (long long)strips_x * strips_y * n_members;
     const dim3 grid((unsigned)((waves + 3) / 4));
+    // a workgroup is four wavefronts, one per SIMD: k workgroups per CU are k waves per SIMD
+    const size_t lds = waves_per_simd > 0 ? (size_t)(160 * 1024 / waves_per_simd - 256) / 256 * 256 : 0;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         release();
@@ -113,7 +118,7 @@ flood_status probe_stream_impl(int ny, int nx, int n_members, int rows, int reps
     for (int rep = 0; rep <= reps && rc == FLOOD_OK; ++rep) {   // rep 0 warms up
         const int s = rep & 1;                                   // ping-pong like the step's two copies
         (void)hipEventRecord(e0, st);
-        hipLaunchKernelGGL(k_stream_probe, grid, dim3(256), 0, st, ny, nx, n_members, rows, strips_x, strips_y,
+        hipLaunchKernelGGL(k_stream_probe, grid, dim3(256), lds, st, ny, nx, n_members, rows, strips_x, strips_y,
                            a[3 * s], a[3 * s + 1], a[3 * s + 2], a[6], a[7], a[3 * (1 - s)], a[3 * (1 - s) + 1],
                            a[3 * (1 - s) + 2]);
         (void)hipEventRecord(e1, st);
@@ -138,12 +143,13 @@ flood_status probe_stream_impl(int ny, int nx, int n_members, int rows, int reps
 }  // namespace flood
 
 extern "C" flood_status flood_probe_stream(int32_t ny, int32_t nx, int32_t n_members, int32_t rows, int32_t reps,
-                                           void* hip_stream, double* gbps_out, double* ms_per_launch_out) {
+                                           int32_t waves_per_simd, void* hip_stream, double* gbps_out,
+                                           double* ms_per_launch_out) {
     if (ny < 1 || nx < 4 || nx % 4 || n_members < 1 || rows < 1 || rows > 4096 || reps < 1 || reps > 1000 ||
-        !gbps_out || !ms_per_launch_out)
+        (waves_per_simd != 0 && (waves_per_simd < 3 || waves_per_simd > 8)) || !gbps_out || !ms_per_launch_out)
         return FLOOD_EINVAL;
     if ((long long)ny * nx * n_members > (1LL << 31)) return FLOOD_EINVAL;   // 8 GiB per state array
     std::string err;
-    return flood::probe_stream_impl(ny, nx, n_members, rows, reps, (hipStream_t)hip_stream, gbps_out,
-                                    ms_per_launch_out, err);
+    return flood::probe_stream_impl(ny, nx, n_members, rows, reps, waves_per_simd, (hipStream_t)hip_stream,
+                                    gbps_out, ms_per_launch_out, err);
 }

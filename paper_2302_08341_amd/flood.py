@@ -104,7 +104,8 @@ def load_library():
         "flood_systematic_resample_noalloc": [dp, C.c_int32, C.c_double, ip, C.c_void_p],
         "flood_device_snapshot": [H, C.c_int32],
         "flood_get_march_rows": [H, C.c_int32, ip],
-        "flood_probe_stream": [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, dp, dp],
+        "flood_probe_stream": [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, dp,
+                               dp],
         "flood_ensemble_products": [H, C.c_int32, C.c_double, C.c_int32, dp, dp, dp, dp],
         "flood_save": [H, C.c_char_p],
         "flood_load": [H, C.c_char_p],
@@ -394,12 +395,12 @@ def flood_systematic_resample_noalloc(w, u0, stream=None):
     return anc
 
 
-def flood_probe_stream(ny, nx, n_members, rows, reps=5):
+def flood_probe_stream(ny, nx, n_members, rows, reps=5, waves_per_simd=0):
     """(GB/s, ms per launch) of a streaming kernel with the row-marching step's access
     pattern and no arithmetic (see flood_probe_stream in include/flood.h)."""
     gbps, ms = C.c_double(0.0), C.c_double(0.0)
     _check(load_library().flood_probe_stream(int(ny), int(nx), int(n_members), int(rows), int(reps),
-                                            current_stream(), C.byref(gbps), C.byref(ms)))
+                                            int(waves_per_simd), current_stream(), C.byref(gbps), C.byref(ms)))
     return gbps.value, ms.value
 
 

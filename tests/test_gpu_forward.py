@@ -457,10 +457,11 @@ def test_graph_timing_matches_launch_timing_and_changes_nothing(fl):
 
 
 def test_stream_probe_reports_a_bandwidth_and_refuses_bad_shapes(fl):
-    gbps, ms = fl.flood_probe_stream(256, 512, 4, 16, 3)
-    print("stream probe on 4 x 256 x 512 cells: %.0f GB/s, %.4f ms" % (gbps, ms))
-    assert 0.0 < gbps < 8000.0 and ms > 0.0
+    for wps in (0, 3, 4):
+        gbps, ms = fl.flood_probe_stream(256, 512, 4, 16, 3, wps)
+        print("stream probe on 4 x 256 x 512 cells, waves per SIMD %d: %.0f GB/s, %.4f ms" % (wps, gbps, ms))
+        assert 0.0 < gbps < 8000.0 and ms > 0.0
     for bad in ((0, 512, 4, 16, 3), (256, 510, 4, 16, 3), (256, 512, 0, 16, 3), (256, 512, 4, 0, 3),
-                (256, 512, 4, 16, 0), (65536, 65536, 1, 16, 3)):
+                (256, 512, 4, 16, 0), (65536, 65536, 1, 16, 3), (256, 512, 4, 16, 3, 9), (256, 512, 4, 16, 3, 2)):
         with pytest.raises(fl.FloodError):
             fl.flood_probe_stream(*bad)
