@@ -141,6 +141,8 @@ template <typename T> struct Impl : ImplBase {
     };
     Scratch adj_tape, adj_clamp, adj_lam, adj_nacc;
     std::vector<Scratch> adj_ckpt;
+    Scratch adj_row;            // one member's row of a state array, for reordering members
+    int32_t* d_order = nullptr; // [kMaxMembers + 1]: a member order and a set flag
 
     size_t adj_held() const {
         size_t b = adj_tape.bytes + adj_clamp.bytes + adj_lam.bytes + adj_nacc.bytes;
@@ -170,12 +172,81 @@ template <typename T> struct Impl : ImplBase {
 
     void adj_free_all() {
         (void)hipStreamSynchronize(st);
-        for (Scratch* b : {&adj_tape, &adj_clamp, &adj_lam, &adj_nacc})
+        for (Scratch* b : {&adj_tape, &adj_clamp, &adj_lam, &adj_nacc, &adj_row})
             if (b->p) (void)hipFree(b->p);
         for (Scratch& c : adj_ckpt)
             if (c.p) (void)hipFree(c.p);
-        adj_tape = adj_clamp = adj_lam = adj_nacc = Scratch{};
+        adj_tape = adj_clamp = adj_lam = adj_nacc = adj_row = Scratch{};
         adj_ckpt.clear();
+    }
+
+    // Reorder the members of catchment c (members in planes): slot i takes the member
+    // held in slot order[i], with everything that belongs to it (both state copies,
+    // edge strips, running maximum, outflow accumulators, depth-maximum bins, time,
+    // parameters, weight, ledger, copy index, fault flag).  Rows of the large arrays
+    // move along the cycles of the order through one row of staging.
+    flood_status reorder_members(int c, const std::vector<int32_t>& order, std::string& err) {
+        Cat& C = cats[c];
+        const int N = C.N, off = C.dev.member_off;
+        const size_t ncell = (size_t)C.ny * C.nx, nb = 2 * ((size_t)C.nx + C.ny);
+        struct Rows {
+            void* base;
+            size_t bytes;   // per member
+        };
+        std::vector<Rows> rows;
+        for (int k = 0; k < 2; ++k) {
+            rows.push_back({C.dev.h[k], ncell * sizeof(T)});
+            rows.push_back({C.dev.qx[k], ncell * sizeof(T)});
+            rows.push_back({C.dev.qy[k], ncell * sizeof(T)});
+            rows.push_back({C.dev.qw[k], (size_t)C.ny * sizeof(T)});
+            rows.push_back({C.dev.qn[k], (size_t)C.nx * sizeof(T)});
+        }
+        if (C.dev.peak) rows.push_back({C.dev.peak, ncell * sizeof(T)});
+        rows.push_back({C.dev.out_acc, nb * sizeof(double)});
+        if (C.dev.drain_acc) rows.push_back({C.dev.drain_acc, (size_t)kBins * sizeof(double)});
+        CHK(adj_reserve(adj_row, ncell * sizeof(T) > nb * sizeof(double) ? ncell * sizeof(T) : nb * sizeof(double), err));
+        auto row = [](const Rows& r, int i) { return static_cast<char*>(r.base) + (size_t)i * r.bytes; };
+        std::vector<char> seen(N, 0);
+        for (int i0 = 0; i0 < N; ++i0) {
+            if (seen[i0] || order[i0] == i0) {
+                seen[i0] = 1;
+                continue;
+            }
+            for (const Rows& r : rows) {
+                HIPCHK(hipMemcpyAsync(adj_row.p, row(r, i0), r.bytes, hipMemcpyDeviceToDevice, st));
+                int i = i0;
+                while (order[i] != i0) {
+                    HIPCHK(hipMemcpyAsync(row(r, i), row(r, order[i]), r.bytes, hipMemcpyDeviceToDevice, st));
+                    i = order[i];
+                }
+                HIPCHK(hipMemcpyAsync(row(r, i), adj_row.p, r.bytes, hipMemcpyDeviceToDevice, st));
+            }
+            for (int i = i0; !seen[i]; i = order[i]) seen[i] = 1;
+        }
+        // per-member scalars through the host
+        HIPCHK(hipStreamSynchronize(st));
+        auto scal = [&](void* base, size_t bytes) -> flood_status {
+            std::vector<char> a((size_t)N * bytes), b((size_t)N * bytes);
+            char* p = static_cast<char*>(base) + (size_t)off * bytes;
+            HIPCHK(hipMemcpy(a.data(), p, a.size(), hipMemcpyDeviceToHost));
+            for (int i = 0; i < N; ++i) std::memcpy(&b[(size_t)i * bytes], &a[(size_t)order[i] * bytes], bytes);
+            HIPCHK(hipMemcpy(p, b.data(), b.size(), hipMemcpyHostToDevice));
+            return FLOOD_OK;
+        };
+        for (double* a : {t, s, mu, logw, vrain, vout, vclamp, drain, vdrain, vin}) CHK(scal(a, sizeof(double)));
+        CHK(scal(steps, sizeof(int64_t)));
+        CHK(scal(clsn, kMaxClasses * sizeof(double)));
+        CHK(scal(par, sizeof(int32_t)));
+        CHK(scal(fault, sizeof(int32_t)));
+        // depth-maximum bins: slot i's maximum is member order[i]'s
+        if (!d_order) CHK(dalloc(&d_order, (size_t)kMaxMembers + 1, err));
+        std::vector<int32_t> ho(order);
+        ho.push_back(1);
+        HIPCHK(hipMemcpy(d_order, ho.data(), ho.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        launch_permute_bins<HB>(off, N, n_total, hbins, d_order, d_order + N, st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        return FLOOD_OK;
     }
 
     void get_adjoint_info(int32_t* groups, int32_t* group_size, int32_t* segments) const override {
@@ -1753,6 +1824,54 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
         G = Ge;
     }
 
+    // Several groups: the members are brought into the order of their expected step
+    // counts, so that a group's members take about as many steps (every launch of
+    // a group runs until its slowest member is done).  Eq. 4 ties the step count
+    // to the depth, and the depth a member reaches to its current depth and the
+    // rain it still receives: the key is the member's current maximum depth plus
+    // its rain multiplier times the rain depth of the window.  Slots are restored
+    // on every way out of the call; results do not depend on the order (the loss is
+    // summed in member order, each member's gradient is its own).
+    std::vector<int32_t> order(N), inv(N);
+    for (int i = 0; i < N; ++i) order[i] = inv[i] = i;
+    bool reordered = false;
+    if (march_adj && (size_t)N > G && !std::getenv("FLOOD_ADJ_NO_ORDER")) {
+        const int off = C.dev.member_off;
+        std::vector<HB> hb((size_t)kBins * n_total);
+        std::vector<double> hmu(N);
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(hb.data(), hbins, hb.size() * sizeof(HB), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(hmu.data(), mu + off, N * sizeof(double), hipMemcpyDeviceToHost));
+        double rain_depth = 0.0;   // rain depth of [t0, t_end] at multiplier 1
+        const double ri = C.p.rain_interval;
+        for (size_t j = 0; j < C.rain.size(); ++j) {
+            const double a = std::max(t0, (double)j * ri), b = std::min(t_end, (double)(j + 1) * ri);
+            if (b > a) rain_depth += C.rain[j] * (b - a);
+        }
+        std::vector<double> key(N);
+        for (int m = 0; m < N; ++m) {
+            HB mx = 0;
+            for (int b = 0; b < kBins; ++b) mx = std::max(mx, hb[(size_t)b * n_total + off + m]);
+            T hmax;
+            std::memcpy(&hmax, &mx, sizeof(T));
+            key[m] = (double)hmax + hmu[m] * rain_depth;
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+        for (int i = 0; i < N; ++i) inv[order[i]] = i;
+        for (int i = 0; i < N && !reordered; ++i) reordered = order[i] != i;
+    }
+    if (reordered) CHK(reorder_members(c, order, err));
+    struct Restore {
+        Impl* self;
+        int c;
+        const std::vector<int32_t>* inv;
+        bool armed;
+        ~Restore() {
+            std::string e;
+            if (armed) (void)self->reorder_members(c, *inv, e);
+        }
+    } restore{this, c, &inv, reordered};
+
     // device scratch owned by this call
     std::vector<void*> tmp;
     auto talloc = [&](size_t bytes, void** p) -> flood_status {
@@ -1830,6 +1949,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
     int32_t* seg_n = nullptr;
     size_t segn_cap = 0;
     double loss_host = 0.0;
+    std::vector<double> loss_slot(N, 0.0);   // each slot's misfit (row-march form)
     if (march_adj) {
         CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_lpar));
         CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_segcnt));
@@ -2118,7 +2238,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                 std::vector<double> lm(Gg);
                 HIPCHK(hipMemcpyAsync(lm.data(), d_lossm, Gg * sizeof(double), hipMemcpyDeviceToHost, st));
                 HIPCHK(hipStreamSynchronize(st));
-                for (int m = 0; m < Gg; ++m) loss_host += lm[m];
+                for (int m = 0; m < Gg; ++m) loss_slot[g0 + m] = lm[m];
             }
             n_segments += (int)seg_nmax.size();
 
@@ -2307,13 +2427,23 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
     double loss_h = 0.0;
     HIPCHK(hipMemcpyAsync(&loss_h, d_loss, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (march_adj) loss_h = loss_host;
+    if (march_adj) {
+        for (int m = 0; m < N; ++m) loss_host += loss_slot[inv[m]];   // member order
+        loss_h = loss_host;
+    }
     last_adj_groups = (int)((N + Gi - 1) / Gi);
     last_adj_group_size = Gi;
     last_adj_segments = n_segments;
     if (grad_n_out) HIPCHK(hipMemcpyAsync(grad_n_out, d_nbar, ncell * sizeof(double), hipMemcpyDeviceToHost, st));
-    if (grad_mult_out) HIPCHK(hipMemcpyAsync(grad_mult_out, d_gm, N * sizeof(double), hipMemcpyDeviceToHost, st));
+    std::vector<double> gm_slot(N);
+    HIPCHK(hipMemcpyAsync(gm_slot.data(), d_gm, N * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    if (grad_mult_out)
+        for (int i = 0; i < N; ++i) grad_mult_out[order[i]] = gm_slot[i];
+    if (reordered) {
+        restore.armed = false;
+        CHK(reorder_members(c, inv, err));
+    }
     if (loss_out) *loss_out = loss_h;
     (void)gm_host;
     return FLOOD_OK;

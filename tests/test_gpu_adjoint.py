@@ -261,3 +261,40 @@ def test_autograd_function(fl):
     assert loss.item() == ref[0]
     np.testing.assert_allclose(nt.grad.numpy(), 2.0 * ref[1], rtol=1e-6)
     np.testing.assert_allclose(mt.grad.numpy(), 2.0 * ref[2], rtol=1e-6)
+
+
+@pytest.mark.parametrize("rb", [4, 8])
+def test_members_taken_in_step_order_give_the_same_results(fl, monkeypatch, rb):
+    # with several member groups the adjoint puts members of similar expected step
+    # counts into one group (rain multipliers descending here, so the order is
+    # reversed); the loss, every member's rain-multiplier gradient and the state
+    # the call leaves behind are those of the call in slot order, bit for bit, and
+    # the Manning field (summed over members in another order) agrees to rounding
+    c = W.urban_catchment("order", 48, 64, 6, W.seed_for(3, 90), n_gauges=4)
+    mu = np.array([2.0, 1.8, 1.5, 1.2, 1.0, 0.8])
+    rain = W.chicago_hyetograph()
+    obs = np.random.default_rng(3).uniform(0.0, 0.05, size=(30, 4))
+    monkeypatch.setenv("FLOOD_ADJ_GROUP", "2")
+    out = {}
+    for name in ("ordered", "slots"):
+        if name == "slots":
+            monkeypatch.setenv("FLOOD_ADJ_NO_ORDER", "1")
+        e = fl.FloodEnsemble([dict(dem=c.dem, manning=c.manning, dx=c.dx, edge_kind=c.edge_kind,
+                                   edge_slope=c.edge_slope, n_members=6, n_scale=c.n_scale[:6], rain_mult=mu)],
+                             rain, real_bytes=rb, step_kernel=3)
+        e.step(600.0)
+        res = e.adjoint(0, 900.0, 10.0, c.gauges, obs, ckpt_every=40)
+        assert e.adjoint_info()["groups"] == 3
+        out[name] = (res, [e.field(i, k) for i in range(6) for k in (fl.FIELD_H, fl.FIELD_QX, fl.FIELD_QY)],
+                     e.ledger(), e.weights())
+    (La, gna, gma), fa, la, wa = out["ordered"]
+    (Lb, gnb, gmb), fb, lb, wb = out["slots"]
+    assert La == Lb
+    np.testing.assert_array_equal(gma, gmb)
+    assert np.linalg.norm(gna - gnb) <= 1e-6 * np.linalg.norm(gnb)
+    for x, y in zip(fa, fb):
+        np.testing.assert_array_equal(x, y)
+    for k in la:
+        np.testing.assert_array_equal(la[k], lb[k])
+    for x, y in zip(wa, wb):
+        np.testing.assert_array_equal(x, y)
