@@ -294,7 +294,9 @@ def test_members_taken_in_step_order_give_the_same_results(fl, monkeypatch, rb):
     assert np.linalg.norm(gna - gnb) <= 1e-6 * np.linalg.norm(gnb)
     for x, y in zip(fa, fb):
         np.testing.assert_array_equal(x, y)
+    # ledger terms that waves add with atomics (clamp volume, storage) carry the order
+    # the waves finish in, in any run
     for k in la:
-        np.testing.assert_array_equal(la[k], lb[k])
+        np.testing.assert_allclose(la[k], lb[k], rtol=1e-12, atol=0.0)
     for x, y in zip(wa, wb):
         np.testing.assert_array_equal(x, y)
