@@ -58,6 +58,21 @@ def test_fullsize_mass_ledger_every_member(c5):
     assert resid.max() <= 1e-6, resid.max()
 
 
+def test_fullsize_mass_ledger_over_the_storm_hour(fl):
+    # the whole 3600-s storm of every member: the FP32 depth updates' rounding
+    # (stochastic, so unbiased) must not accumulate past the bar
+    wl = W.config5()
+    ens = fl.FloodEnsemble.from_workload(wl)
+    ens.step(wl.t_end)
+    led = ens.ledger()
+    ens.close()
+    assert np.all(led["t"] == wl.t_end)
+    resid = np.abs(led["storage"] - (led["rain_in"] - led["outflow"] + led["clamp"])) / led["rain_in"]
+    print("mass ledger after %.0f s, %d member steps: worst residual %.3g of the rain" % (
+        wl.t_end, int(led["steps"].sum()), resid.max()))
+    assert resid.max() <= 1e-6, resid.max()
+
+
 def test_fullsize_batched_equals_one_handle_for_a_sampled_member(fl, c5):
     wl, ens, saved = c5
     c = wl.catchments[0]
