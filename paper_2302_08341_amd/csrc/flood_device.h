@@ -26,12 +26,20 @@ template <> __device__ __forceinline__ double from_bits<double>(unsigned long lo
     return __longlong_as_double((long long)b);
 }
 
-// h^(-7/3) of the friction denominator of Eq. 2, as 1 / (h^2 cbrt(h)): a few
-// ulp.  The hardware exp2(-7/3 log2 h) is cheaper but carries the logarithm's
-// error times the exponent's size, about 2e-6 relative, the same sign step
-// after step; on shallow friction-dominated links that systematic error moved
-// single-precision discharges by 3e-4 of the largest discharge within 80 steps.
-__device__ __forceinline__ float pow_m73(float h) { return __builtin_amdgcn_rcpf(h * h * cbrtf(h)); }
+// h^(-7/3) of the friction denominator of Eq. 2, as h^(-1/3) / h^2: a few ulp.
+// h^(-1/3) starts from the hardware exp2(-log2(h) / 3), whose error (the
+// logarithm's, a third of it carried by the exponent, a few 1e-7 relative) one
+// Newton step on y^3 h = 1 squares away.  The hardware exp2(-7/3 log2 h) alone
+// carries seven times that error, about 2e-6 relative and of one sign step
+// after step, which moved single-precision discharges on shallow
+// friction-dominated links by 3e-4 of the largest discharge within 80 steps.
+// For h > 0 only (dry links discard the result).
+__device__ __forceinline__ float pow_m73(float h) {
+    const float y0 = __builtin_amdgcn_exp2f(-0.333333343f * __builtin_amdgcn_logf(h));
+    const float t = (y0 * y0) * (y0 * h);
+    const float y = y0 + y0 * ((1.0f - t) * 0.333333343f);
+    return y * __builtin_amdgcn_rcpf(h * h);
+}
 __device__ __forceinline__ double pow_m73(double h) { return 1.0 / pow(h, 7.0 / 3.0); }
 
 __device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
