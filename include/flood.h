@@ -216,16 +216,21 @@ flood_status flood_assimilate(flood_handle* h, int32_t catchment, int32_t n_gaug
  * (grad_n_out, host [ny*nx]) and each member's rain multiplier
  * (grad_mult_out, host [N]).  The members are taken in groups that fit the
  * device memory.  The forward run of a group records every step of every
- * member, its length and its state, in a tape of ckpt_every + 1 states per
- * member; when a member has taken ckpt_every steps the segment ends and the
- * group's states become a checkpoint.  The reverse sweep applies the discrete
- * adjoint of the step with the recorded step lengths and the forward's
- * wet/dry, limiter and clamp branches held fixed: the last segment straight
- * from the tape, each earlier one after recomputing it from its checkpoint.
- * A ckpt_every at least the members' step count therefore means no
- * recomputation, at the price of tape memory (and smaller groups).  The loss
- * and the rain-multiplier gradients do not depend on ckpt_every; the Manning
- * field's only through the single-precision rounding of its accumulation (the
+ * member, its length and its state, in a tape: the row-march form (members in
+ * planes, step kernel 3) keeps one state per member step in a pool of blocks
+ * shared by the group, the tiled form ckpt_every + 1 states per member.  A
+ * segment ends when a member has taken ckpt_every steps in it (or the pool
+ * could run out), and the group's states become a checkpoint.  The reverse
+ * sweep applies the discrete adjoint of the step with the recorded step
+ * lengths and the forward's wet/dry, limiter and clamp branches held fixed:
+ * the last segment straight from the tape, each earlier one after recomputing
+ * it from its checkpoint.  A ckpt_every at least the members' step count
+ * therefore means no recomputation, at the price of tape memory (and smaller
+ * groups).  In the row-march form the members are taken most expected steps
+ * first, and each group holds as many members as the pool holds at the step
+ * counts of the group before it.  The loss and the rain-multiplier gradients
+ * do not depend on ckpt_every or the grouping; the Manning field's only
+ * through the single-precision rounding of its accumulation (the
  * contributions of four members are added together per reverse step).  On
  * return the members are at the last sample time.
  *   obs host [S*n_gauges]; loss_out, grad_n_out, grad_mult_out may be NULL.
@@ -235,10 +240,13 @@ flood_status flood_adjoint(flood_handle* h, int32_t catchment, double t_end, dou
                            double* loss_out, double* grad_n_out, double* grad_mult_out);
 
 /* flood_adjoint keeps its scratch on the handle for the next call: the tape
- * (ckpt_every + 1 states of a member group), its clamp flags, two adjoint
- * copies, the Manning accumulators and the checkpoints, in all up to half the
- * device memory that was free at the first call.  Allocating and freeing that
- * much on every call would cost seconds once the memory has been recycled.
+ * (row-march form: a pool of blocks in about 85 % of the device memory that was
+ * free at the first call, at most what min(N, 16) members taking ckpt_every
+ * steps each would use; tiled form: ckpt_every + 1 states of a member group and their clamp
+ * flags, up to half of it), two adjoint copies, the Manning accumulators and
+ * the checkpoints.  A later call keeps a held pool that is at least 15/16 of
+ * the one it would allocate.  Allocating and freeing that much on every call
+ * would cost seconds once the memory has been recycled.
  * flood_adjoint_release frees it now (flood_destroy frees it too); a later
  * flood_adjoint allocates it again.  Errors: EINVAL (NULL handle). */
 flood_status flood_adjoint_release(flood_handle* h);
@@ -367,9 +375,9 @@ flood_status flood_load(flood_handle* h, const char* path);
 flood_status flood_device_snapshot(flood_handle* h, int32_t op);
 
 /* Memory plan of the last flood_adjoint call on the handle: member groups,
- * members per group, and tape segments summed over the groups (segments beyond
- * one per group were recomputed from checkpoints).  Any output may be NULL;
- * zeros before the first call. */
+ * members of the largest group, and tape segments summed over the groups
+ * (segments beyond one per group were recomputed from checkpoints).  Any
+ * output may be NULL; zeros before the first call. */
 flood_status flood_get_adjoint_info(const flood_handle* h, int32_t* groups, int32_t* group_size,
                                     int32_t* segments);
 

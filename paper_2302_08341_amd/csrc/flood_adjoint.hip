@@ -292,21 +292,6 @@ template <typename T> void launch_adjoint_step(int mi, const AdjLaunch<T>& A, hi
     }
 }
 
-// Adjoint of the new depths after the clamp branch: zero where the forward
-// clamped the depth at zero, the stored adjoint elsewhere.
-template <typename T, int V>
-__device__ __forceinline__ void le_load(const T* lh, const uint8_t* cl, T (&d)[V]) {
-    T v[V];
-    vload<T, V>(lh, v);
-    uint32_t f;
-    if constexpr (V == 4)
-        f = *reinterpret_cast<const uint32_t*>(cl);
-    else
-        f = *reinterpret_cast<const uint16_t*>(cl);
-#pragma unroll
-    for (int j = 0; j < V; ++j) d[j] = ((f >> (8 * j)) & 0xffu) ? T(0) : v[j];
-}
-
 // Reverse step in row-march form.  Geometry as the forward row march: a
 // wavefront marches a strip of 62 V cells down its rows for one member; lanes
 // 0 and 63 are halo lanes.  A workgroup holds the four members of a member
@@ -319,6 +304,9 @@ __device__ __forceinline__ void le_load(const T* lh, const uint8_t* cl, T (&d)[V
 // the neighbouring lane and the north link from the previous row, so every
 // link is differentiated once per step.  Contributions to a cell's depth
 // adjoint are added in the order east, south, west, north (as in k_adj).  The
+// clamp branch comes from the tape: where the step before this one clamped the
+// depth (-0 in the tape), the depth adjoint written here is zero, so the reverse
+// of that step reads the adjoint of its new depths already masked.  The
 // rain-multiplier adjoint is accumulated per (strip, member).  Members that do
 // not step in this launch (or pad the last quad) skip the march and keep their
 // adjoint in place, but still meet the workgroup barrier.  PF = 1 issues the
@@ -353,13 +341,12 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
     const size_t plane = (size_t)ny * nx;
     if (act) {
         const MemberStep<T> ms = A.ms[k];
-        const size_t so = (size_t)ms.slot * A.slot_stride;
-        const T* __restrict__ H = C.h[0] + so + (size_t)k * plane;
-        const T* __restrict__ QX = C.qx[0] + so + (size_t)k * plane;
-        const T* __restrict__ QY = C.qy[0] + so + (size_t)k * plane;
-        const T* __restrict__ QWs = C.qw[0] + so + (size_t)k * ny;
-        const T* __restrict__ QNs = C.qn[0] + so + (size_t)k * nx;
-        const uint8_t* __restrict__ CL = A.clamp + (size_t)ms.slot * A.clamp_stride + (size_t)k * plane;
+        const size_t bs = (size_t)ms.blk;
+        const T* __restrict__ H = C.h[0] + bs * plane;
+        const T* __restrict__ QX = C.qx[0] + bs * plane;
+        const T* __restrict__ QY = C.qy[0] + bs * plane;
+        const T* __restrict__ QWs = C.qw[0] + bs * ny;
+        const T* __restrict__ QNs = C.qn[0] + bs * nx;
         const int lp = A.lpar[k];
         const T* __restrict__ LH = A.lh[lp] + (size_t)k * plane;
         const T* __restrict__ LQX = A.lqx[lp] + (size_t)k * plane;
@@ -380,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
         vload<T, V>(H + ca, hc);
         vload<T, V>(Z + ca, zc);
         vload<T, V>(Nn + ca, nc);
-        le_load<T, V>(LH + ca, CL + ca, lec);
+        vload<T, V>(LH + ca, lec);
         if (r0 > 0) {
             // the south links of the row above the strip feed its first row's north links
             T hN[V], zN[V], nN[V], qN[V], lqN[V], leN[V];
@@ -389,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
             vload<T, V>(Nn + ca - nx, nN);
             vload<T, V>(QY + ca - nx, qN);
             vload<T, V>(LQY + ca - nx, lqN);
-            le_load<T, V>(LH + ca - nx, CL + ca - nx, leN);
+            vload<T, V>(LH + ca - nx, leN);
     #pragma unroll
             for (int j = 0; j < V; ++j) {
                 const T nf = T(0.5) * (nN[j] + nc[j]);
@@ -415,7 +402,7 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
             vload<T, V>(LQY + c, lqs);
             vload<T, V>(Z + cb, z2);
             vload<T, V>(Nn + cb, n2);
-            le_load<T, V>(LH + cb, CL + cb, le2);
+            vload<T, V>(LH + cb, le2);
         };
         T qE[V], qS[V], lqE[V], lqS[V], hs[V], zs[V], ns[V], les[V];
         if (PF) load_row(ca, r0 + 1 < ny, qE, qS, lqE, lqS, hs, zs, ns, les);
@@ -530,7 +517,9 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
                         }
                         LQNo[x] = oqn;
                     }
-                    nh4[j] = nh;
+                    // zero where the step before this one clamped the depth (the tape's
+                    // -0): that step's reverse then sees no adjoint of the clamped depth
+                    nh4[j] = clamp_mark(hc[j]) ? T(0) : nh;
                     oqx4[j] = ltE[j] * dqE[j];
                     oqy4[j] = ltS[j] * dqS[j];
                     na4[j] = nac;
@@ -605,39 +594,6 @@ template <typename T> void launch_adjoint_march(const AdjvLaunch<T>& A, hipStrea
         hipLaunchKernelGGL((k_adjv<T, V, 0>), grid, dim3(kBlock), lds, s, A);
 }
 
-// One lane per member of the group.
-template <typename T>
-__global__ __launch_bounds__(256) void k_adj_pre(int G, const MemberStep<T>* ms_prev, const MemberStep<T>* ms_cur,
-                                                 const int32_t* tags, int K, const int32_t* grc, const double* obs,
-                                                 const T* tape_h, size_t slot_stride, size_t plane, int nx,
-                                                 int32_t* lpar, T* lh0, T* lh1) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= G) return;
-    int p = lpar[m];
-    if (ms_prev && ms_prev[m].active) {
-        p ^= 1;
-        lpar[m] = p;
-    }
-    if (K == 0 || !ms_cur[m].active) return;
-    const int s = tags[m];
-    if (s < 0) return;
-    const T* h = tape_h + (size_t)(ms_cur[m].slot + 1) * slot_stride + (size_t)m * plane;
-    T* lh = (p ? lh1 : lh0) + (size_t)m * plane;
-    for (int q = 0; q < K; ++q) {
-        const size_t cell = (size_t)grc[2 * q] * nx + grc[2 * q + 1];
-        lh[cell] += (T)(2.0 * ((double)h[cell] - obs[(size_t)s * K + q]));
-    }
-}
-
-template <typename T>
-void launch_adj_pre(int G, const MemberStep<T>* ms_prev, const MemberStep<T>* ms_cur, const int32_t* tags, int K,
-                    const int32_t* grc, const double* obs, const CatchDev<T>& tape, size_t slot_stride,
-                    int32_t* lpar, T* lh0, T* lh1, hipStream_t s) {
-    const size_t plane = (size_t)tape.ny * tape.nx;
-    hipLaunchKernelGGL((k_adj_pre<T>), dim3((G + 255) / 256), dim3(256), 0, s, G, ms_prev, ms_cur, tags, K, grc, obs,
-                       (const T*)tape.h[0], slot_stride, plane, tape.nx, lpar, lh0, lh1);
-}
-
 // One wavefront per member of the group.  With distinct gauge cells the lanes
 // seed one gauge each; otherwise lane 0 seeds them in order (a cell seen twice
 // takes both seeds).
@@ -645,9 +601,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_adj_plan(int G, int stride, int i, const int32_t* n, const MemberStep<T>* rec,
                                                   const double* rec_rdt, const int32_t* rec_tag, int K, int distinct,
                                                   const int32_t* grc, const double* obs, const T* tape_h,
-                                                  size_t slot_stride, size_t plane, int nx, int32_t* lpar,
-                                                  int32_t* prev, MemberStep<T>* ms_out, double* rdt_out, T* lh0,
-                                                  T* lh1) {
+                                                  size_t plane, int nx, int32_t* lpar, int32_t* prev,
+                                                  MemberStep<T>* ms_out, double* rdt_out, T* lh0, T* lh1) {
     const int lane = threadIdx.x & 63;
     const int m = blockIdx.x * (blockDim.x >> 6) + (int)(threadIdx.x >> 6);
     if (m >= G) return;
@@ -675,17 +630,18 @@ __global__ __launch_bounds__(256) void k_adj_plan(int G, int stride, int i, cons
     }
     const int smp = rec_tag[r];
     if (K == 0 || smp < 0) return;
-    const T* h = tape_h + (size_t)(j + 1) * slot_stride + (size_t)m * plane;
+    const T* h = tape_h + (size_t)rec[r].blk_next * plane;
     T* lh = (p ? lh1 : lh0) + (size_t)m * plane;
+    // a gauge cell whose depth the step clamped (-0 in the tape) passes no adjoint back
     if (distinct) {
         for (int q = lane; q < K; q += 64) {
             const size_t cell = (size_t)grc[2 * q] * nx + grc[2 * q + 1];
-            lh[cell] += (T)(2.0 * ((double)h[cell] - obs[(size_t)smp * K + q]));
+            if (!clamp_mark(h[cell])) lh[cell] += (T)(2.0 * ((double)h[cell] - obs[(size_t)smp * K + q]));
         }
     } else if (lane == 0) {
         for (int q = 0; q < K; ++q) {
             const size_t cell = (size_t)grc[2 * q] * nx + grc[2 * q + 1];
-            lh[cell] += (T)(2.0 * ((double)h[cell] - obs[(size_t)smp * K + q]));
+            if (!clamp_mark(h[cell])) lh[cell] += (T)(2.0 * ((double)h[cell] - obs[(size_t)smp * K + q]));
         }
     }
 }
@@ -693,39 +649,44 @@ __global__ __launch_bounds__(256) void k_adj_plan(int G, int stride, int i, cons
 template <typename T>
 void launch_adj_plan(int G, int stride, int i, const int32_t* n, const MemberStep<T>* rec, const double* rec_rdt,
                      const int32_t* rec_tag, int K, int distinct, const int32_t* grc, const double* obs,
-                     const T* tape_h, size_t slot_stride, size_t plane, int nx, int32_t* lpar, int32_t* prev,
-                     MemberStep<T>* ms_out, double* rdt_out, T* lh0, T* lh1, hipStream_t s) {
+                     const T* tape_h, size_t plane, int nx, int32_t* lpar, int32_t* prev, MemberStep<T>* ms_out,
+                     double* rdt_out, T* lh0, T* lh1, hipStream_t s) {
     hipLaunchKernelGGL((k_adj_plan<T>), dim3((G + 3) / 4), dim3(256), 0, s, G, stride, i, n, rec, rec_rdt, rec_tag, K,
-                       distinct, grc, obs, tape_h, slot_stride, plane, nx, lpar, prev, ms_out, rdt_out, lh0, lh1);
+                       distinct, grc, obs, tape_h, plane, nx, lpar, prev, ms_out, rdt_out, lh0, lh1);
 }
 
-// Member m of the group, element e of its plane and edge strips: tape slot
-// slot[m] -> destination copy (dpar[dst.member_off + m], or 0).  Members in planes.
+// Member m of the group, element e of its plane and edge strips: tape block
+// blk[m] -> destination copy (dpar[dst.member_off + m], or 0).  Members in
+// planes.  The destination may be the tape's first blocks (block m for member m)
+// as long as no member's source is one of them but its own; there (dpar null)
+// the depths keep their bits, into the ensemble's state (dpar given) a clamped
+// depth's -0 becomes +0.
 template <typename T>
-__global__ __launch_bounds__(256) void k_tape_gather(const CatchDev<T> tape, size_t slot_stride, const int32_t* slot,
-                                                     const CatchDev<T> dst, const int32_t* dpar) {
+__global__ __launch_bounds__(256) void k_tape_gather(const CatchDev<T> tape, const int32_t* blk, const CatchDev<T> dst,
+                                                     const int32_t* dpar) {
     const int m = blockIdx.y;
     const size_t plane = (size_t)tape.ny * tape.nx;
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t so = (size_t)slot[m] * slot_stride;
+    const size_t b = (size_t)blk[m];
     const int p = dpar ? dpar[dst.member_off + m] : 0;
     if (e < plane) {
         const size_t i = (size_t)m * plane + e;
-        dst.h[p][i] = tape.h[0][so + i];
-        dst.qx[p][i] = tape.qx[0][so + i];
-        dst.qy[p][i] = tape.qy[0][so + i];
+        const T hv = tape.h[0][b * plane + e];
+        dst.h[p][i] = (dpar && hv == T(0)) ? T(0) : hv;
+        dst.qx[p][i] = tape.qx[0][b * plane + e];
+        dst.qy[p][i] = tape.qy[0][b * plane + e];
     }
-    if (e < (size_t)tape.ny) dst.qw[p][(size_t)m * tape.ny + e] = tape.qw[0][so + (size_t)m * tape.ny + e];
-    if (e < (size_t)tape.nx) dst.qn[p][(size_t)m * tape.nx + e] = tape.qn[0][so + (size_t)m * tape.nx + e];
+    if (e < (size_t)tape.ny) dst.qw[p][(size_t)m * tape.ny + e] = tape.qw[0][b * tape.ny + e];
+    if (e < (size_t)tape.nx) dst.qn[p][(size_t)m * tape.nx + e] = tape.qn[0][b * tape.nx + e];
 }
 
 template <typename T>
-void launch_tape_gather(const CatchDev<T>& tape, size_t slot_stride, const int32_t* slot, const CatchDev<T>& dst,
-                        const int32_t* dpar, hipStream_t s) {
+void launch_tape_gather(const CatchDev<T>& tape, const int32_t* blk, const CatchDev<T>& dst, const int32_t* dpar,
+                        hipStream_t s) {
     const size_t plane = (size_t)tape.ny * tape.nx;
     const size_t n = std::max(plane, (size_t)std::max(tape.ny, tape.nx));
     hipLaunchKernelGGL((k_tape_gather<T>), dim3((unsigned)((n + 255) / 256), tape.n_members), dim3(256), 0, s, tape,
-                       slot_stride, slot, dst, dpar);
+                       blk, dst, dpar);
 }
 
 // nbar[c] += sum over the group's members of their Manning-field adjoint
@@ -852,23 +813,17 @@ void launch_sum_parts(int n_blocks, int n_members, const double* parts, double* 
 
 template void launch_adjoint_march<float>(const AdjvLaunch<float>&, hipStream_t);
 template void launch_adjoint_march<double>(const AdjvLaunch<double>&, hipStream_t);
-template void launch_adj_pre<float>(int, const MemberStep<float>*, const MemberStep<float>*, const int32_t*, int,
-                                    const int32_t*, const double*, const CatchDev<float>&, size_t, int32_t*, float*,
-                                    float*, hipStream_t);
-template void launch_adj_pre<double>(int, const MemberStep<double>*, const MemberStep<double>*, const int32_t*, int,
-                                     const int32_t*, const double*, const CatchDev<double>&, size_t, int32_t*,
-                                     double*, double*, hipStream_t);
 template void launch_adj_plan<float>(int, int, int, const int32_t*, const MemberStep<float>*, const double*,
                                      const int32_t*, int, int, const int32_t*, const double*, const float*, size_t,
-                                     size_t, int, int32_t*, int32_t*, MemberStep<float>*, double*, float*, float*,
+                                     int, int32_t*, int32_t*, MemberStep<float>*, double*, float*, float*,
                                      hipStream_t);
 template void launch_adj_plan<double>(int, int, int, const int32_t*, const MemberStep<double>*, const double*,
                                       const int32_t*, int, int, const int32_t*, const double*, const double*, size_t,
-                                      size_t, int, int32_t*, int32_t*, MemberStep<double>*, double*, double*, double*,
+                                      int, int32_t*, int32_t*, MemberStep<double>*, double*, double*, double*,
                                       hipStream_t);
-template void launch_tape_gather<float>(const CatchDev<float>&, size_t, const int32_t*, const CatchDev<float>&,
+template void launch_tape_gather<float>(const CatchDev<float>&, const int32_t*, const CatchDev<float>&,
                                         const int32_t*, hipStream_t);
-template void launch_tape_gather<double>(const CatchDev<double>&, size_t, const int32_t*, const CatchDev<double>&,
+template void launch_tape_gather<double>(const CatchDev<double>&, const int32_t*, const CatchDev<double>&,
                                          const int32_t*, hipStream_t);
 template void launch_nacc_reduce<float>(int, size_t, const float*, double*, hipStream_t);
 template void launch_nacc_reduce<double>(int, size_t, const double*, double*, hipStream_t);

@@ -94,6 +94,18 @@ template <> __device__ __forceinline__ double depth_add<double>(double h, double
     return h + inc;
 }
 
+// The adjoint's row-march tape keeps a depth that the step clamped at zero as
+// -0 (every other zero depth is +0), so the tape itself records the clamp
+// branch of each cell and step.  Only the tape carries -0: the step's values do
+// not depend on which zero it reads (a zero discharge may come out as -0), and
+// depths handed back to the ensemble are +0 again.
+template <typename T> __device__ __forceinline__ bool clamp_mark(T h) {
+    if constexpr (sizeof(T) == 4)
+        return __float_as_uint(h) == 0x80000000u;
+    else
+        return (unsigned long long)__double_as_longlong(h) == 0x8000000000000000ull;
+}
+
 // Eq. 3 flow depth of an interior link in difference form: the depth of the
 // cell with the higher water surface minus the positive part of the bed step
 // towards the other cell.  Every kernel that decides whether a link is wet

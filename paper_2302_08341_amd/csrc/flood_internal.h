@@ -43,6 +43,8 @@ template <typename T> struct MemberStep {
     int32_t active;
     int32_t parity;  // state copy holding the state before this step
     int32_t slot;    // adjoint record: the member's step index within the tape segment
+    int32_t blk;     // adjoint record: tape block holding the member's state before the step
+    int32_t blk_next;  // and the block the step writes
     uint32_t seed;   // random seed of the step's depth rounding, from the member's time
     T cn[kMaxClasses];  // land cover: the member's Manning n of each class
     T drain;            // land cover: drainage depth of the step (rate x dt)
@@ -99,12 +101,11 @@ template <typename T> struct StepLaunch {
     const MemberStep<T>* ms;  // indexed by global member
     typename HBits<T>::type* hbins;  // [kBins][n_total]
     double* vclamp;           // [n_total]
-    uint8_t* clamp_out;       // recompute only: 1 where the new depth was clamped at zero
-    // tape recomputation by the row-march kernel: c[0]'s copy-0 arrays are tape
-    // slot 0; a member reads slot ms.slot and writes slot ms.slot + 1, and its
-    // clamp flags go to clamp_out + ms.slot * clamp_stride
-    size_t slot_stride;
-    size_t clamp_stride;
+    uint8_t* clamp_out;       // tiled recompute only: 1 where the new depth was clamped at zero
+    // tape recording and recomputation by the row-march kernel: c[0]'s copy-0
+    // arrays are the tape's block pools (block b of a field at b times the member
+    // stride); a member reads block ms.blk and writes block ms.blk_next, a
+    // clamped depth as -0
 };
 
 struct PlanCatch {
@@ -158,12 +159,16 @@ template <typename T> struct PlanLaunch {
     // is also clipped to its next sample time s_t0 + (smp + 1) s_dt; a step ending
     // there carries the sample index as its tag and moves the member to the next
     // sample.  The gauge misfit of the state after a tagged step is added to the
-    // member's loss by the member's next planner call, from its current tape slot.
+    // member's loss by the member's next planner call, from its current tape block.
     double s_t0, s_dt;
     int32_t* smp;             // [group] next sample index
     int32_t* pend;            // [group] sample whose misfit is still to be taken, or -1
-    const T* tape_h;          // tape slot 0 depths: member planes, slots slot_stride apart
-    size_t slot_stride;
+    // tape blocks (with seg_cnt): a stepping member takes the next free block of
+    // the pool for its new state (pool_next counts the blocks in use) and cur_blk
+    // follows the block of its latest state
+    int32_t* cur_blk;         // [group]
+    int32_t* pool_next;       // device scalar
+    const T* tape_h;          // depth pool of the tape: block b's plane at b * plane
     size_t plane;
     int32_t nx;
     int32_t n_gauges;
@@ -251,14 +256,11 @@ template <typename T> struct AdjLaunch {
 template <typename T> void launch_adjoint_step(int mi, const AdjLaunch<T>& A, hipStream_t s);
 
 // Reverse step in row-march form (members in planes, nx a multiple of the
-// vector width).  The tape holds per-member slots: a member active in this
-// launch reads its state before the step from slot ms.slot; members that did
-// not step are skipped and keep their adjoint in place.
+// vector width).  The tape is a pool of blocks, one member state each: a member
+// active in this launch reads its state before the step from block ms.blk;
+// members that did not step are skipped and keep their adjoint in place.
 template <typename T> struct AdjvLaunch {
-    CatchDev<T> c;            // group view: copy-0 arrays are tape slot 0; strip / wave geometry
-    size_t slot_stride;       // elements between tape slots
-    const uint8_t* clamp;     // [slot][member][cell] clamp flags of the recomputed steps
-    size_t clamp_stride;
+    CatchDev<T> c;            // group view: copy-0 arrays are the tape's block pools; strip / wave geometry
     T* lh[2];                 // two copies of the adjoint state, [member][...]
     T* lqx[2];
     T* lqy[2];
@@ -272,12 +274,6 @@ template <typename T> struct AdjvLaunch {
     int32_t pf;               // 1: one row of load lookahead in the reverse march
 };
 template <typename T> void launch_adjoint_march(const AdjvLaunch<T>& A, hipStream_t s);
-// before each reverse launch: flip the adjoint copy of members that stepped in
-// the previously reversed launch, then seed the gauge misfit of this launch
-template <typename T>
-void launch_adj_pre(int G, const MemberStep<T>* ms_prev, const MemberStep<T>* ms_cur, const int32_t* tags, int K,
-                    const int32_t* grc, const double* obs, const CatchDev<T>& tape, size_t slot_stride,
-                    int32_t* lpar, T* lh0, T* lh1, hipStream_t s);
 template <typename T>
 void launch_nacc_reduce(int G, size_t ncell, const T* nacc, double* nbar, hipStream_t s);
 // Reverse planner of launch i of a tape segment whose member k took n[k] steps
@@ -286,21 +282,23 @@ void launch_nacc_reduce(int G, size_t ncell, const T* nacc, double* nbar, hipStr
 // adjoint copy index of members that stepped in the previous reverse launch,
 // writes this launch's step coefficients (ms_out, rdt_out) from the member-local
 // records, and seeds the gauge misfit of a step that completed a
-// sample, 2 (h - d), read from the tape slot after the step (distinct: no two
-// gauges share a cell, so the gauges are seeded in parallel).
+// sample, 2 (h - d), read from the tape block the step wrote (distinct: no two
+// gauges share a cell, so the gauges are seeded in parallel).  tape_h: the
+// tape's depth pool.
 template <typename T>
 void launch_adj_plan(int G, int stride, int i, const int32_t* n, const MemberStep<T>* rec, const double* rec_rdt,
                      const int32_t* rec_tag, int K, int distinct, const int32_t* grc, const double* obs, const T* tape_h,
-                     size_t slot_stride, size_t plane, int nx, int32_t* lpar, int32_t* prev, MemberStep<T>* ms_out,
-                     double* rdt_out, T* lh0, T* lh1, hipStream_t s);
-// Copy each member's state from its tape slot slot[m] (tape: copy-0 arrays are
-// slot 0) to dst, into copy dpar[dst.member_off + m] (dpar null: copy 0).
+                     size_t plane, int nx, int32_t* lpar, int32_t* prev, MemberStep<T>* ms_out, double* rdt_out,
+                     T* lh0, T* lh1, hipStream_t s);
+// Copy each member's state from tape block blk[m] (tape: copy-0 arrays are the
+// block pools) to dst, into copy dpar[dst.member_off + m] (dpar null: copy 0).
 template <typename T>
-void launch_tape_gather(const CatchDev<T>& tape, size_t slot_stride, const int32_t* slot, const CatchDev<T>& dst,
-                        const int32_t* dpar, hipStream_t s);
-// [0] members of the group still short of t_end, [1] status word, [2] largest seg_cnt
+void launch_tape_gather(const CatchDev<T>& tape, const int32_t* blk, const CatchDev<T>& dst, const int32_t* dpar,
+                        hipStream_t s);
+// [0] members of the group still short of t_end, [1] status word, [2] largest
+// seg_cnt, [3] tape blocks in use
 void launch_count_group(int G, const double* t, const int32_t* fault, const double* t_end, const int32_t* status,
-                        const int32_t* seg_cnt, int32_t* out, hipStream_t s);
+                        const int32_t* seg_cnt, const int32_t* pool_next, int32_t* out, hipStream_t s);
 template <typename T>
 void launch_marchv_rec(const StepLaunch<T>& L, int pf, int record, int total_waves, hipStream_t s);
 template <typename T>

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     ms.dxdt = 0.0;
     ms.active = 0;
     ms.parity = P.par[m];
-    ms.slot = -1;
+    ms.slot = ms.blk = ms.blk_next = -1;
     ms.seed = 0;
     for (int k = 0; k < kMaxClasses; ++k) ms.cn[k] = T(0);
     ms.drain = T(0);
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     if (P.pend && P.pend[lm] >= 0) {
         // misfit of the state after the member's last step, which completed sample pend
         const int smp = P.pend[lm];
-        const T* h = P.tape_h + (size_t)P.seg_cnt[lm] * P.slot_stride + (size_t)lm * P.plane;
+        const T* h = P.tape_h + (size_t)P.cur_blk[lm] * P.plane;
         double acc = 0.0;
         for (int q = lane; q < P.n_gauges; q += 64) {
             const double d = (double)h[(size_t)P.grc[2 * q] * P.nx + P.grc[2 * q + 1]] -
@@ -139,7 +139,13 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
         const uint64_t tb = (uint64_t)__double_as_longlong(t);
         ms.seed = mix32((uint32_t)tb ^ mix32((uint32_t)(tb >> 32) + 0x632be5abu));
     }
-    if (P.seg_cnt) ms.slot = P.seg_cnt[lm]++;
+    if (P.seg_cnt) {
+        // the member's new state goes to the next free block of the tape
+        ms.slot = P.seg_cnt[lm]++;
+        ms.blk = P.cur_blk[lm];
+        ms.blk_next = atomicAdd(P.pool_next, 1);
+        P.cur_blk[lm] = ms.blk_next;
+    }
     if (P.clsn)
         for (int k = 0; k < kMaxClasses; ++k) ms.cn[k] = (T)P.clsn[(size_t)m * kMaxClasses + k];
     if (P.drain) ms.drain = (T)(P.drain[m] * dt);
@@ -407,7 +413,8 @@ void launch_count_active(int n_total, const double* t, const int32_t* fault, con
 
 __global__ __launch_bounds__(256) void k_count_group(int n, const double* t, const int32_t* fault,
                                                      const double* t_end, const int32_t* status,
-                                                     const int32_t* seg_cnt, int32_t* out) {
+                                                     const int32_t* seg_cnt, const int32_t* pool_next,
+                                                     int32_t* out) {
     __shared__ int part[4], mpart[4];
     int c = 0, mx = 0;
     const double te = *t_end;
@@ -428,12 +435,14 @@ __global__ __launch_bounds__(256) void k_count_group(int n, const double* t, con
         out[0] = part[0] + part[1] + part[2] + part[3];
         out[1] = status[0];
         out[2] = max(max(mpart[0], mpart[1]), max(mpart[2], mpart[3]));
+        out[3] = *pool_next;
     }
 }
 
 void launch_count_group(int G, const double* t, const int32_t* fault, const double* t_end, const int32_t* status,
-                        const int32_t* seg_cnt, int32_t* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_count_group, dim3(1), dim3(256), 0, s, G, t, fault, t_end, status, seg_cnt, out);
+                        const int32_t* seg_cnt, const int32_t* pool_next, int32_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_count_group, dim3(1), dim3(256), 0, s, G, t, fault, t_end, status, seg_cnt, pool_next,
+                       out);
 }
 
 __global__ __launch_bounds__(256) void k_step_limit(int n, const int64_t* steps, int64_t add, int64_t* lim) {
@@ -990,9 +999,10 @@ __global__ __launch_bounds__(kBlock) void k_march(const StepLaunch<T> L) {
 // last row, so no lane needs a branch or a zero fill around them: values of
 // lanes outside the grid and of the row below the last are read but never used.
 // REC = 0: the plain step between the member's two state copies.  REC = 1: tape
-// recomputation for the adjoint (slot ms.slot to slot ms.slot + 1, clamp flags,
-// no ledger).  REC = 2: the adjoint's recording forward, the same slots and
-// flags with the plain step's ledger, depth-maximum bins and outflow.
+// recomputation for the adjoint (tape block ms.blk to block ms.blk_next, a
+// clamped depth stored as -0, no ledger).  REC = 2: the adjoint's recording
+// forward, the same blocks and marks with the plain step's ledger, depth-maximum
+// bins and outflow.
 template <typename T, int V, int NT, int REC, int PF, int EXT>
 __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
     using HB = typename HBits<T>::type;
@@ -1024,7 +1034,7 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
     const int r1 = min(r0 + C.march_rows, ny);
     const size_t plane = (size_t)ny * nx;
     // source and destination of this member's state: the two copies, or (tape
-    // recomputation) the member's tape slot and the next one
+    // recording and recomputation) the member's tape block and the block of its new state
     const T* __restrict__ H;
     const T* __restrict__ QX;
     const T* __restrict__ QY;
@@ -1036,18 +1046,17 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
     T* QWo;
     T* QNo;
     if constexpr (REC) {
-        const size_t so = (size_t)ms.slot * L.slot_stride;
-        const size_t sd = so + L.slot_stride;
-        H = C.h[0] + so + (size_t)k * plane;
-        QX = C.qx[0] + so + (size_t)k * plane;
-        QY = C.qy[0] + so + (size_t)k * plane;
-        Ho = C.h[0] + sd + (size_t)k * plane;
-        QXo = C.qx[0] + sd + (size_t)k * plane;
-        QYo = C.qy[0] + sd + (size_t)k * plane;
-        QWs = C.qw[0] + so + (size_t)k * ny;
-        QWo = C.qw[0] + sd + (size_t)k * ny;
-        QNs = C.qn[0] + so + (size_t)k * nx;
-        QNo = C.qn[0] + sd + (size_t)k * nx;
+        const size_t bs = (size_t)ms.blk, bd = (size_t)ms.blk_next;
+        H = C.h[0] + bs * plane;
+        QX = C.qx[0] + bs * plane;
+        QY = C.qy[0] + bs * plane;
+        Ho = C.h[0] + bd * plane;
+        QXo = C.qx[0] + bd * plane;
+        QYo = C.qy[0] + bd * plane;
+        QWs = C.qw[0] + bs * ny;
+        QWo = C.qw[0] + bd * ny;
+        QNs = C.qn[0] + bs * nx;
+        QNo = C.qn[0] + bd * nx;
     } else {
         const int sp = ms.parity, dp = sp ^ 1;
         H = C.h[sp] + (size_t)k * plane;
@@ -1290,7 +1299,7 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
             }
         }
         T hn4[V];
-        uint8_t cf[V];
+        bool cf[V];
 #pragma unroll
         for (int j = 0; j < V; ++j) {
             const T dv = ((fW[j] - fE[j]) + fN[j]) - fS[j];
@@ -1310,23 +1319,18 @@ __global__ __launch_bounds__(kBlock) void k_marchv(const StepLaunch<T> L) {
             vmax = (own && hb > vmax) ? hb : vmax;
         }
         if (own) {
+            // the tape keeps a clamped depth as -0 (the clamp branch for the adjoint)
+            T ho4[V];
+#pragma unroll
+            for (int j = 0; j < V; ++j) ho4[j] = (REC && cf[j]) ? -T(0) : hn4[j];
             if (NT) {
-                vstore_nt<T, V>(Ho + ca, hn4);
+                vstore_nt<T, V>(Ho + ca, ho4);
                 vstore_nt<T, V>(QXo + ca, fE);
                 vstore_nt<T, V>(QYo + ca, fS);
             } else {
-                vstore<T, V>(Ho + ca, hn4);
+                vstore<T, V>(Ho + ca, ho4);
                 vstore<T, V>(QXo + ca, fE);
                 vstore<T, V>(QYo + ca, fS);
-            }
-            if constexpr (REC) {
-                uint8_t* cl = L.clamp_out + (size_t)ms.slot * L.clamp_stride + (size_t)k * plane + ca;
-                if constexpr (V == 4) {
-                    *reinterpret_cast<uint32_t*>(cl) = (uint32_t)cf[0] | ((uint32_t)cf[1] << 8) |
-                                                       ((uint32_t)cf[2] << 16) | ((uint32_t)cf[3] << 24);
-                } else {
-                    *reinterpret_cast<uint16_t*>(cl) = (uint16_t)(cf[0] | (cf[1] << 8));
-                }
             }
             if constexpr (REC != 1) {
                 if (C.peak) {
@@ -1453,10 +1457,10 @@ void launch_marchv(const StepLaunch<T>& L, int nt, int pf, int ext, int total_wa
 }
 
 // Tape recomputation of the adjoint (record = 0): the same step, reading and
-// writing tape slots, recording clamp flags, leaving the ledger, the outflow
-// accumulators and the depth maximum alone; members that do not step in the
-// launch are skipped (their slots are not advanced).  Recording forward
-// (record = 1): the same slots and clamp flags, plus everything the plain step
+// writing tape blocks, marking clamped depths as -0, leaving the ledger, the
+// outflow accumulators and the depth maximum alone; members that do not step in
+// the launch are skipped.  Recording forward (record = 1): the same blocks and
+// marks, plus everything the plain step
 // updates (depth maximum bins, clamp and outflow ledgers, running maximum).
 template <typename T>
 void launch_marchv_rec(const StepLaunch<T>& L, int pf, int record, int total_waves, hipStream_t s) {

@@ -101,7 +101,7 @@ template <typename T> struct Impl : ImplBase {
     int32_t* d_count = nullptr;
     double* h_tend = nullptr;      // pinned
     int32_t* h_count = nullptr;    // pinned [2 slots][2]
-    int32_t* h_cnt3 = nullptr;     // pinned [2 slots][3]: the adjoint forward's batch counts
+    int32_t* h_cnt3 = nullptr;     // pinned [2 slots][4]: the adjoint forward's batch counts
     int last_adj_groups = 0, last_adj_group_size = 0, last_adj_segments = 0;
     hipEvent_t ev[2] = {nullptr, nullptr};
 
@@ -1732,6 +1732,26 @@ template <typename T> struct Impl : ImplBase {
 constexpr int kAdjTileRows = 4;
 constexpr int kAdjMarchRows = 8;
 constexpr int kAdjMarchOrder = 4;   // rows of strips in bands spread over the XCDs (see march_wave)
+constexpr size_t kAdjMaxGroup = 16;  // members of a row-march adjoint group at most
+
+// Members of a row-march adjoint group: as many as a pool of tape blocks holds
+// when each takes `steps` steps, plus its first state and two batches of bm
+// launches of slack (between 1 and gmax).
+static int adj_group_size(size_t pool, int steps, int bm, int gmax) {
+    const size_t per = (size_t)std::max(steps, 0) + 1 + 2 * (size_t)bm;
+    return (int)std::max<size_t>(1, std::min<size_t>(pool / per, (size_t)gmax));
+}
+
+// Rows per strip of a row-march view of G members, with the strip rows, bands
+// and wavefront count that follow from them.
+template <typename T>
+static void set_march_rows(CatchDev<T>& v, int rows, int G) {
+    v.march_rows = std::min(rows, v.ny);
+    v.strips_y = (v.ny + v.march_rows - 1) / v.march_rows;
+    v.march_bands = std::max(8, std::min((int)std::ceil((double)v.ny * v.nx * 2.0 * sizeof(T) / (1 << 20) / 8.0) * 8,
+                                         (v.strips_y + 7) / 8 * 8));
+    v.n_waves = march_waves(v.strips_x, v.strips_y, G, v.march_order, v.march_bands);
+}
 
 template <typename T>
 static CatchDev<T> group_view(const CatchDev<T>& C, int mi, int g0, int G, T* const h[2], T* const qx[2],
@@ -1802,40 +1822,68 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
     // row-march form (forward, tape recomputation and reverse step), otherwise
     // in the tiled form that also serves interleaved members
     const bool march_adj = mi == 1 && variant == 3;
-    // the row-march form keeps a whole segment of every group member's steps in
-    // the tape, so it takes most of the free memory (the tiled form half of it)
-    const double share = march_adj ? 0.85 : 0.5;
-    size_t G = (size_t)(share * (double)free_b) / ((size_t)(ckpt_every + 1) * per_member_slot + 8 * per_member_state);
-    G = std::min<size_t>(G, (size_t)N);
+    size_t env_group = 0;
     if (const char* eg = std::getenv("FLOOD_ADJ_GROUP")) {   // testing: force smaller member groups
         const long v = std::atol(eg);
-        if (v > 0) G = std::min<size_t>(G, (size_t)v);
+        if (v > 0) env_group = (size_t)v;
     }
-    G = (G / mi) * mi;
-    if (G < (size_t)mi) { err = "adjoint tape does not fit in device memory"; return FLOOD_ENOMEM; }
-    // as many groups as memory needs, all of one size: equal launches, and a
-    // grouping that small changes of free memory do not move
-    {
-        // the row-march reverse step works on member quads: whole quads when memory allows
-        if (march_adj && G >= 4) G = G / 4 * 4;
+    // recording-forward launches per batch (a member takes at most one step per launch)
+    const int Bm = std::min(8, ckpt_every);
+    size_t G = 0;         // tiled form: members per group; row-march form: the most members a group takes
+    size_t pool = 0;      // row-march form: tape blocks (one member state and its clamp flags each)
+    int g_first = 0;      // row-march form: members of the first group
+    if (march_adj) {
+        // The row-march form keeps every step of its group's members in a pool of
+        // tape blocks that takes most of the free memory: a member uses as many
+        // blocks as it takes steps, so members that step less leave room for more
+        // members in a group.  A group holds at most kAdjMaxGroup members (larger
+        // launches gain little); their adjoint copies, checkpoints and
+        // accumulators are kept outside the pool.
+        G = std::min<size_t>((size_t)N, kAdjMaxGroup);
+        if (env_group) G = std::min(G, env_group);
+        const double spare = 0.85 * (double)free_b - (double)(G * 8 * per_member_state);
+        pool = spare > 0.0 ? (size_t)(spare / (double)per_member_state) : 0;
+        // A pool held from an earlier call is kept when it is nearly as large:
+        // freeing and allocating a block of this size costs seconds, and the same
+        // pool gives the same member groups on every call.
+        const size_t held = adj_tape.bytes / per_member_state;
+        if (adj_tape.p && held >= pool - pool / 16) pool = held;
+        // never more than every member of the largest group taking ckpt_every steps
+        pool = std::min(pool, G * ((size_t)ckpt_every + 1 + 2 * (size_t)Bm));
+        if (const char* ep = std::getenv("FLOOD_ADJ_POOL")) {   // testing: a smaller pool
+            const long v = std::atol(ep);
+            if (v > 0) pool = std::min(pool, (size_t)v);
+        }
+        pool = std::min<size_t>(pool, (size_t)INT32_MAX);
+        // a group needs its members' first states and two batches of steps
+        if (pool < (size_t)(2 * Bm + 2)) { err = "adjoint tape does not fit in device memory"; return FLOOD_ENOMEM; }
+        g_first = adj_group_size(pool, ckpt_every, Bm, (int)G);
+    } else {
+        // the tiled form keeps ckpt_every + 1 states per member in half the free memory
+        G = (size_t)(0.5 * (double)free_b) / ((size_t)(ckpt_every + 1) * per_member_slot + 8 * per_member_state);
+        G = std::min<size_t>(G, (size_t)N);
+        if (env_group) G = std::min(G, env_group);
+        G = (G / mi) * mi;
+        if (G < (size_t)mi) { err = "adjoint tape does not fit in device memory"; return FLOOD_ENOMEM; }
+        // as many groups as memory needs, all of one size: equal launches, and a
+        // grouping that small changes of free memory do not move
         const size_t n_groups = ((size_t)N + G - 1) / G;
-        size_t Ge = (((size_t)N + n_groups - 1) / n_groups + mi - 1) / mi * mi;
-        if (march_adj && G >= 4) Ge = std::min(G, (Ge + 3) / 4 * 4);
-        G = Ge;
+        G = (((size_t)N + n_groups - 1) / n_groups + mi - 1) / mi * mi;
     }
 
     // Several groups: the members are brought into the order of their expected step
-    // counts, so that a group's members take about as many steps (every launch of
-    // a group runs until its slowest member is done).  Eq. 4 ties the step count
-    // to the depth, and the depth a member reaches to its current depth and the
-    // rain it still receives: the key is the member's current maximum depth plus
-    // its rain multiplier times the rain depth of the window.  Slots are restored
-    // on every way out of the call; results do not depend on the order (the loss is
-    // summed in member order, each member's gradient is its own).
+    // counts, most steps first, so that a group's members take about as many steps
+    // (every launch of a group runs until its slowest member is done) and each
+    // group can be sized from the step counts of the one before it.  Eq. 4 ties
+    // the step count to the depth, and the depth a member reaches to its current
+    // depth and the rain it still receives: the key is the member's current maximum
+    // depth plus its rain multiplier times the rain depth of the window.  Slots are
+    // restored on every way out of the call; results do not depend on the order
+    // (the loss is summed in member order, each member's gradient is its own).
     std::vector<int32_t> order(N), inv(N);
     for (int i = 0; i < N; ++i) order[i] = inv[i] = i;
     bool reordered = false;
-    if (march_adj && (size_t)N > G && !std::getenv("FLOOD_ADJ_NO_ORDER")) {
+    if (march_adj && N > g_first && !std::getenv("FLOOD_ADJ_NO_ORDER")) {
         const int off = C.dev.member_off;
         std::vector<HB> hb((size_t)kBins * n_total);
         std::vector<double> hmu(N);
@@ -1856,7 +1904,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
             std::memcpy(&hmax, &mx, sizeof(T));
             key[m] = (double)hmax + hmu[m] * rain_depth;
         }
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] > key[b]; });
         for (int i = 0; i < N; ++i) inv[order[i]] = i;
         for (int i = 0; i < N && !reordered; ++i) reordered = order[i] != i;
     }
@@ -1912,12 +1960,23 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
     }
     HIPCHK(hipMemsetAsync(d_loss, 0, sizeof(double), st));
     HIPCHK(hipMemsetAsync(d_nbar, 0, ncell * sizeof(double), st));
-    // tape (ckpt_every + 1 slots), clamp flags (ckpt_every slots), adjoint ping-pong
+    // Tape.  Row-march form: the pool of blocks, each field's blocks contiguous
+    // (block b of the depth at b * ncell, of the west edge strip at b * ny, ...),
+    // with a clamped depth kept as -0.  Tiled form: ckpt_every + 1 slots of the
+    // group state and ckpt_every slots of clamp flags.  Then the adjoint ping-pong.
     T* tape = nullptr;
     uint8_t* clamp = nullptr;
     T* lam = nullptr;
-    CHK(adj_reserve(adj_tape, (size_t)(ckpt_every + 1) * slot_elems * sizeof(T), err));
-    CHK(adj_reserve(adj_clamp, (size_t)ckpt_every * elemsG, err));
+    const size_t tape_elems = march_adj ? pool * (3 * ncell + C.ny + C.nx) : (size_t)(ckpt_every + 1) * slot_elems;
+    if (!march_adj) {
+        CHK(adj_reserve(adj_clamp, (size_t)ckpt_every * elemsG, err));
+    } else if (adj_clamp.p) {   // held from a tiled-form call: counted as free above
+        HIPCHK(hipStreamSynchronize(st));
+        (void)hipFree(adj_clamp.p);
+        adj_clamp.p = nullptr;
+        adj_clamp.bytes = 0;
+    }
+    CHK(adj_reserve(adj_tape, tape_elems * sizeof(T), err));
     CHK(adj_reserve(adj_lam, 2 * slot_elems * sizeof(T), err));
     tape = static_cast<T*>(adj_tape.p);
     clamp = static_cast<uint8_t*>(adj_clamp.p);
@@ -1939,6 +1998,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
     int32_t* d_lpar = nullptr;
     int32_t* d_segcnt = nullptr;
     int32_t *d_smp = nullptr, *d_pend = nullptr, *d_prev = nullptr, *d_cnt3 = nullptr;
+    int32_t *d_curblk = nullptr, *d_pool = nullptr;
     double *d_lossm = nullptr, *d_rdtcur = nullptr;
     MemberStep<T>* d_mscur = nullptr;
     T* d_nacc = nullptr;
@@ -1956,14 +2016,16 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
         CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_smp));
         CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_pend));
         CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_prev));
-        CHK(talloc(6 * sizeof(int32_t), (void**)&d_cnt3));
+        CHK(talloc(8 * sizeof(int32_t), (void**)&d_cnt3));
+        CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_curblk));
+        CHK(talloc(sizeof(int32_t), (void**)&d_pool));
         CHK(talloc((size_t)Gi * sizeof(double), (void**)&d_lossm));
         CHK(talloc((size_t)Gi * sizeof(double), (void**)&d_rdtcur));
         CHK(talloc((size_t)Gi * sizeof(MemberStep<T>), (void**)&d_mscur));
         // one Manning-field accumulator per member quad
         CHK(adj_reserve(adj_nacc, (size_t)((Gi + 3) / 4) * ncell * sizeof(T), err));
         d_nacc = static_cast<T*>(adj_nacc.p);
-        if (!h_cnt3) HIPCHK(hipHostMalloc((void**)&h_cnt3, 6 * sizeof(int32_t), hipHostMallocDefault));
+        if (!h_cnt3) HIPCHK(hipHostMalloc((void**)&h_cnt3, 8 * sizeof(int32_t), hipHostMallocDefault));
     }
     // grow the member-local records to hold n entries (contents kept)
     auto grow_rec = [&](size_t n) -> flood_status {
@@ -2036,8 +2098,22 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
     launch_flush_outflow(N, 2 * (C.nx + C.ny), C.dev.out_acc, vout + off, st);
     std::vector<double> gm_host(N, 0.0);
 
-    for (int g0 = 0; g0 < N; g0 += Gi) {
-        const int Gg = std::min(Gi, N - g0);
+    // row-march form: the members' step counts at the start of the call, block
+    // indices 0, 1, ... (a member's first block, and the pool's first free block)
+    std::vector<int64_t> steps0;
+    std::vector<int32_t> blk_iota;
+    if (march_adj) {
+        steps0.resize(N);
+        HIPCHK(hipMemcpyAsync(steps0.data(), steps + off, (size_t)N * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        blk_iota.resize((size_t)Gi + 1);
+        for (int i = 0; i <= Gi; ++i) blk_iota[i] = i;
+    }
+    int g_next = march_adj ? g_first : Gi, groups_run = 0, group_most = 0;
+    for (int g0 = 0, Gg = 0; g0 < N; g0 += Gg) {
+        Gg = std::min(g_next, N - g0);
+        ++groups_run;
+        group_most = std::max(group_most, Gg);
         const int chunk0 = g0 / mi;
         auto at = [&](T* base) { return base + (size_t)chunk0 * ncell * mi; };
         auto atw = [&](T* base) { return base + (size_t)chunk0 * C.ny * mi; };
@@ -2084,20 +2160,54 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
         PLg.m_end = off + g0 + Gg;
         if (march_adj) {
             // ---------------- row-march form ----------------
-            // Recording forward: the step kernel writes each member's steps into its
-            // tape slots directly (slot j -> j + 1), so the last tape segment needs no
-            // recomputation.  A segment ends when a member has taken ckpt_every steps
-            // in it: every member's state is then copied to slot 0 and to a
-            // checkpoint.  Step records are member-local ([slot][member]), and the
-            // members' sample times are scheduled on the device, so the forward
-            // runs in batches of launches without a host round trip per sample.
-            const int tw = V.n_waves;
+            // Recording forward: the step kernel writes each step of a member into
+            // the next free block of the tape pool (the member's first state is in
+            // block m, its latest in cur_blk[m]), so the last tape segment needs no
+            // recomputation.  A segment ends when a member has taken ckpt_every
+            // steps in it or the pool could run out within the next batch: every
+            // member's latest state is then copied to its first block and to a
+            // checkpoint.  Step records are member-local ([slot][member]) and carry
+            // the blocks, and the members' sample times are scheduled on the
+            // device, so the forward runs in batches of launches without a host
+            // round trip per sample.
             const size_t plane = ncell;
-            const CatchDev<T> TV = slot_view(tape, 0);
+            T* ph[2] = {tape, tape};
+            T* pqx[2] = {tape + pool * ncell, tape + pool * ncell};
+            T* pqy[2] = {tape + 2 * pool * ncell, tape + 2 * pool * ncell};
+            T* pqw[2] = {tape + 3 * pool * ncell, tape + 3 * pool * ncell};
+            T* pqn[2] = {pqw[0] + pool * C.ny, pqw[0] + pool * C.ny};
+            const CatchDev<T> TV = group_view(C.dev, mi, g0, Gg, ph, pqx, pqy, pqw, pqn);
             // the recording forward also keeps the group's outflow and running maximum
             CatchDev<T> TVF = TV;
             TVF.out_acc = V.out_acc;
             TVF.peak = V.peak;
+            if (const char* fr = std::getenv("FLOOD_ADJ_FROWS")) set_march_rows(TVF, std::max(1, std::atoi(fr)), Gg);
+            CatchDev<T> TVR = TV;   // tape recomputation: the forward's geometry
+            TVR.march_rows = TVF.march_rows;
+            TVR.strips_y = TVF.strips_y;
+            TVR.march_bands = TVF.march_bands;
+            TVR.n_waves = TVF.n_waves;
+            const int tw = TVF.n_waves;
+            // the group's first states (blocks 0 .. Gg - 1) to or from a checkpoint
+            // laid out as a group state of Gi members
+            auto ckpt_copy = [&](T* ck, bool save) -> flood_status {
+                T* const fp[5] = {ph[0], pqx[0], pqy[0], pqw[0], pqn[0]};
+                const size_t fo[5] = {0, elemsG, 2 * elemsG, 3 * elemsG, 3 * elemsG + wG};
+                const size_t fe[5] = {plane, plane, plane, (size_t)C.ny, (size_t)C.nx};
+                for (int f = 0; f < 5; ++f) {
+                    T* d = save ? ck + fo[f] : fp[f];
+                    const T* src = save ? fp[f] : ck + fo[f];
+                    HIPCHK(hipMemcpyAsync(d, src, (size_t)Gg * fe[f] * sizeof(T), hipMemcpyDeviceToDevice, st));
+                }
+                return FLOOD_OK;
+            };
+            // member m's latest state is in its first block, and the pool's other blocks are free
+            auto reset_blocks = [&]() -> flood_status {
+                HIPCHK(hipMemcpyAsync(d_curblk, blk_iota.data(), (size_t)Gg * sizeof(int32_t), hipMemcpyHostToDevice,
+                                      st));
+                HIPCHK(hipMemcpyAsync(d_pool, &blk_iota[Gg], sizeof(int32_t), hipMemcpyHostToDevice, st));
+                return FLOOD_OK;
+            };
             StepLaunch<T> SLm = SL;
             SLm.n_catch = 1;
             SLm.c[0] = V;
@@ -2105,7 +2215,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
             SLm.recompute = 0;
             // launches per batch: a member takes at most one step per launch, so a
             // batch never takes a member past the segment's ckpt_every steps
-            const int B = std::min(8, ckpt_every);
+            const int B = Bm;
             const size_t seg_recs = (size_t)ckpt_every * Gi;
             std::vector<int> seg_nmax;
             int seg = 0;
@@ -2115,12 +2225,15 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
             launch_snapshot<T>(mi, V, par, TV, st);
             T* ck0;
             CHK(checkpoint(0, &ck0));
-            HIPCHK(hipMemcpyAsync(ck0, tape, slot_elems * sizeof(T), hipMemcpyDeviceToDevice, st));
+            CHK(ckpt_copy(ck0, true));
+            CHK(reset_blocks());
             HIPCHK(hipMemsetAsync(d_segcnt, 0, (size_t)Gi * sizeof(int32_t), st));
             HIPCHK(hipMemsetAsync(d_smp, 0, (size_t)Gi * sizeof(int32_t), st));
             HIPCHK(hipMemsetAsync(d_pend, 0xff, (size_t)Gi * sizeof(int32_t), st));
             HIPCHK(hipMemsetAsync(d_lossm, 0, (size_t)Gi * sizeof(double), st));
             PLg.seg_cnt = d_segcnt;
+            PLg.cur_blk = d_curblk;
+            PLg.pool_next = d_pool;
             PLg.rec_stride = Gi;
             PLg.any_log = nullptr;
             PLg.tag_value = -1;
@@ -2129,7 +2242,6 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
             PLg.smp = d_smp;
             PLg.pend = d_pend;
             PLg.tape_h = tape;
-            PLg.slot_stride = slot_elems;
             PLg.plane = plane;
             PLg.nx = C.nx;
             PLg.n_gauges = K;
@@ -2147,9 +2259,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
             StepLaunch<T> RF = SLm;
             RF.c[0] = TVF;
             RF.ms = ms;
-            RF.clamp_out = clamp;
-            RF.slot_stride = slot_elems;
-            RF.clamp_stride = elemsG;
+            RF.clamp_out = nullptr;
             int64_t L = 0;
             auto launch_fwd_batch = [&](int slot) -> flood_status {
                 for (int i = 0; i < B; ++i) {
@@ -2157,15 +2267,16 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                     launch_marchv_rec<T>(RF, march_pf, 1, tw, st);
                 }
                 L += B;
-                launch_count_group(Gg, t + off + g0, fault + off + g0, d_tend, status, d_segcnt, d_cnt3 + 3 * slot, st);
+                launch_count_group(Gg, t + off + g0, fault + off + g0, d_tend, status, d_segcnt, d_pool,
+                                   d_cnt3 + 4 * slot, st);
                 HIPCHK(hipGetLastError());
-                HIPCHK(hipMemcpyAsync(h_cnt3 + 3 * slot, d_cnt3 + 3 * slot, 3 * sizeof(int32_t),
+                HIPCHK(hipMemcpyAsync(h_cnt3 + 4 * slot, d_cnt3 + 4 * slot, 4 * sizeof(int32_t),
                                       hipMemcpyDeviceToHost, st));
                 HIPCHK(hipEventRecord(ev[slot], st));
                 return FLOOD_OK;
             };
-            // end the current segment: its step counts, and every member's state to
-            // slot 0 and to the next checkpoint
+            // end the current segment: its step counts, and every member's latest
+            // state to its first block and to the next checkpoint
             auto roll = [&](int nmax) -> flood_status {
                 HIPCHK(hipMemcpyAsync(seg_n + (size_t)seg * Gi, d_segcnt, (size_t)Gi * sizeof(int32_t),
                                       hipMemcpyDeviceToDevice, st));
@@ -2174,28 +2285,37 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                 CHK(grow_rec((size_t)(seg + 1) * seg_recs));
                 CHK(grow_segn((size_t)(seg + 1) * Gi));
                 HIPCHK(hipMemsetAsync(rec_at(seg), 0, seg_recs * sizeof(MemberStep<T>), st));
-                launch_tape_gather<T>(TV, slot_elems, d_segcnt, TV, nullptr, st);
+                // a member's latest block is its own first block or one past the first Gg
+                launch_tape_gather<T>(TV, d_curblk, TV, nullptr, st);
                 T* ck;
                 CHK(checkpoint(seg, &ck));
-                HIPCHK(hipMemcpyAsync(ck, tape, slot_elems * sizeof(T), hipMemcpyDeviceToDevice, st));
+                CHK(ckpt_copy(ck, true));
+                CHK(reset_blocks());
                 HIPCHK(hipMemsetAsync(d_segcnt, 0, (size_t)Gi * sizeof(int32_t), st));
                 set_seg(seg);
                 return FLOOD_OK;
             };
+            // room for n more batches in the segment: no member past ckpt_every
+            // steps, no block past the pool
+            const size_t batch_blocks = (size_t)B * Gg;
+            auto room = [&](int mx, int used, int n) {
+                return mx + n * B <= ckpt_every && (size_t)used + n * batch_blocks <= pool;
+            };
             CHK(grow_segn((size_t)Gi));
             // two batches in flight while the segment has room for both
             CHK(launch_fwd_batch(0));
-            int inflight = 1, next = 1, wait_slot = 0, mx = 0;
+            int inflight = 1, next = 1, wait_slot = 0, mx = 0, used = Gg;
             for (;;) {
-                if (inflight == 1 && mx + 2 * B <= ckpt_every) {
+                if (inflight == 1 && room(mx, used, 2)) {
                     CHK(launch_fwd_batch(next));
                     next ^= 1;
                     inflight = 2;
                 }
                 HIPCHK(hipEventSynchronize(ev[wait_slot]));
                 --inflight;
-                const int active = h_cnt3[3 * wait_slot], stat = h_cnt3[3 * wait_slot + 1];
-                mx = h_cnt3[3 * wait_slot + 2];
+                const int active = h_cnt3[4 * wait_slot], stat = h_cnt3[4 * wait_slot + 1];
+                mx = h_cnt3[4 * wait_slot + 2];
+                used = h_cnt3[4 * wait_slot + 3];
                 wait_slot ^= 1;
                 if (stat) {
                     HIPCHK(hipStreamSynchronize(st));
@@ -2205,7 +2325,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                 if (active == 0) {
                     if (inflight) {
                         HIPCHK(hipEventSynchronize(ev[wait_slot]));
-                        mx = std::max(mx, (int)h_cnt3[3 * wait_slot + 2]);
+                        mx = std::max(mx, (int)h_cnt3[4 * wait_slot + 2]);
                     }
                     break;
                 }
@@ -2215,11 +2335,12 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                     return FLOOD_ESTATE;
                 }
                 if (inflight == 0) {
-                    if (mx + B > ckpt_every) {
+                    if (!room(mx, used, 1)) {
                         CHK(roll(mx));
                         mx = 0;
+                        used = Gg;
                     }
-                    if (mx + B > ckpt_every) {   // cannot happen: B <= ckpt_every
+                    if (!room(mx, used, 1)) {   // cannot happen: B <= ckpt_every, B Gg + Gg <= pool
                         err = "adjoint tape segment overflow";
                         return FLOOD_ESTATE;
                     }
@@ -2233,12 +2354,18 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                                   hipMemcpyDeviceToDevice, st));
             seg_nmax.push_back(mx);
             // the members' end states back into the handle
-            launch_tape_gather<T>(TV, slot_elems, d_segcnt, V, par, st);
+            launch_tape_gather<T>(TV, d_curblk, V, par, st);
             {
                 std::vector<double> lm(Gg);
+                std::vector<int64_t> sn(Gg);
                 HIPCHK(hipMemcpyAsync(lm.data(), d_lossm, Gg * sizeof(double), hipMemcpyDeviceToHost, st));
+                HIPCHK(hipMemcpyAsync(sn.data(), steps + off + g0, Gg * sizeof(int64_t), hipMemcpyDeviceToHost, st));
                 HIPCHK(hipStreamSynchronize(st));
                 for (int m = 0; m < Gg; ++m) loss_slot[g0 + m] = lm[m];
+                // the next group's members are expected to take no more steps than these
+                int64_t most = 0;
+                for (int m = 0; m < Gg; ++m) most = std::max(most, sn[m] - steps0[g0 + m]);
+                g_next = adj_group_size(pool, (int)std::min<int64_t>(most, ckpt_every), Bm, Gi);
             }
             n_segments += (int)seg_nmax.size();
 
@@ -2246,7 +2373,7 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
             // through its own steps (reverse launch i of a segment reverses step
             // n[k] - 1 - i of member k), so every launch carries every member that
             // has steps left.  Earlier segments are first recomputed from their
-            // checkpoints, member by member in the same way.
+            // checkpoints, member by member in the same way, into the same blocks.
             HIPCHK(hipMemsetAsync(lam, 0, 2 * slot_elems * sizeof(T), st));
             HIPCHK(hipMemsetAsync(d_mubar, 0, (size_t)nblk * Gi * sizeof(double), st));
             HIPCHK(hipMemsetAsync(d_lpar, 0, (size_t)Gi * sizeof(int32_t), st));
@@ -2258,27 +2385,21 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                 if (nmax == 0) continue;
                 const MemberStep<T>* recs = rec_at(sg);
                 if (sg != (int)seg_nmax.size() - 1) {
-                    HIPCHK(hipMemcpyAsync(tape, adj_ckpt[sg].p, slot_elems * sizeof(T), hipMemcpyDeviceToDevice, st));
+                    CHK(ckpt_copy(static_cast<T*>(adj_ckpt[sg].p), false));
                     for (int r = 0; r < nmax; ++r) {
                         StepLaunch<T> R = SLm;
-                        R.c[0] = TV;
+                        R.c[0] = TVR;
                         R.ms = recs + (size_t)r * Gi - (off + g0);
-                        R.clamp_out = clamp;
-                        R.slot_stride = slot_elems;
-                        R.clamp_stride = elemsG;
+                        R.clamp_out = nullptr;
                         launch_marchv_rec<T>(R, march_pf, 0, tw, st);
                     }
                 }
                 for (int i = 0; i < nmax; ++i) {
                     launch_adj_plan<T>(Gg, Gi, i, seg_n + (size_t)sg * Gi, recs, rec_rdt + (size_t)sg * seg_recs,
                                        rec_tag + (size_t)sg * seg_recs, K, gauges_distinct, d_grc2, d_obs2, tape,
-                                       slot_elems, plane,
-                                       C.nx, d_lpar, d_prev, d_mscur, d_rdtcur, lb[0], lb[1], st);
+                                       plane, C.nx, d_lpar, d_prev, d_mscur, d_rdtcur, lb[0], lb[1], st);
                     AdjvLaunch<T> A{};
                     A.c = TV;
-                    A.slot_stride = slot_elems;
-                    A.clamp = clamp;
-                    A.clamp_stride = elemsG;
                     for (int w = 0; w < 2; ++w) {
                         A.lh[w] = lb[w];
                         A.lqx[w] = lb[w] + elemsG;
@@ -2431,8 +2552,8 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
         for (int m = 0; m < N; ++m) loss_host += loss_slot[inv[m]];   // member order
         loss_h = loss_host;
     }
-    last_adj_groups = (int)((N + Gi - 1) / Gi);
-    last_adj_group_size = Gi;
+    last_adj_groups = groups_run;
+    last_adj_group_size = group_most;
     last_adj_segments = n_segments;
     if (grad_n_out) HIPCHK(hipMemcpyAsync(grad_n_out, d_nbar, ncell * sizeof(double), hipMemcpyDeviceToHost, st));
     std::vector<double> gm_slot(N);

@@ -266,12 +266,13 @@ def test_autograd_function(fl):
 @pytest.mark.parametrize("rb", [4, 8])
 def test_members_taken_in_step_order_give_the_same_results(fl, monkeypatch, rb):
     # with several member groups the adjoint puts members of similar expected step
-    # counts into one group (rain multipliers descending here, so the order is
-    # reversed); the loss, every member's rain-multiplier gradient and the state
-    # the call leaves behind are those of the call in slot order, bit for bit, and
-    # the Manning field (summed over members in another order) agrees to rounding
+    # counts into one group, most steps first (rain multipliers ascending here, so
+    # the order is reversed); the loss, every member's rain-multiplier gradient and
+    # the state the call leaves behind are those of the call in slot order, bit for
+    # bit, and the Manning field (summed over members in another order) agrees to
+    # rounding
     c = W.urban_catchment("order", 48, 64, 6, W.seed_for(3, 90), n_gauges=4)
-    mu = np.array([2.0, 1.8, 1.5, 1.2, 1.0, 0.8])
+    mu = np.array([0.8, 1.0, 1.2, 1.5, 1.8, 2.0])
     rain = W.chicago_hyetograph()
     obs = np.random.default_rng(3).uniform(0.0, 0.05, size=(30, 4))
     monkeypatch.setenv("FLOOD_ADJ_GROUP", "2")
@@ -299,4 +300,44 @@ def test_members_taken_in_step_order_give_the_same_results(fl, monkeypatch, rb):
     for k in la:
         np.testing.assert_allclose(la[k], lb[k], rtol=1e-12, atol=0.0)
     for x, y in zip(wa, wb):
+        np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("rb", [4, 8])
+def test_tape_pool_that_runs_out_ends_segments(fl, monkeypatch, rb):
+    # a tape pool of 18 blocks (a member's first state and two batches of 8 steps)
+    # holds one member at a time and ends its tape segment every few steps, long
+    # before the checkpoint interval: every earlier segment is recomputed from its
+    # checkpoint into the same blocks.  The loss and the rain-multiplier gradients
+    # are those of the call with the whole window in one segment, bit for bit, the
+    # Manning field agrees to rounding (which steps share a reverse launch follows
+    # the segments), and so does the state the call leaves behind
+    c = W.urban_catchment("pool", 48, 64, 6, W.seed_for(3, 91), n_gauges=4)
+    mu = np.array([0.8, 1.0, 1.2, 1.5, 1.8, 2.0])
+    rain = W.chicago_hyetograph()
+    obs = np.random.default_rng(4).uniform(0.0, 0.05, size=(30, 4))
+    out = {}
+    for name in ("whole", "pool"):
+        if name == "pool":
+            monkeypatch.setenv("FLOOD_ADJ_POOL", "18")
+        e = fl.FloodEnsemble([dict(dem=c.dem, manning=c.manning, dx=c.dx, edge_kind=c.edge_kind,
+                                   edge_slope=c.edge_slope, n_members=6, n_scale=c.n_scale[:6], rain_mult=mu)],
+                             rain, real_bytes=rb, step_kernel=3)
+        e.step(600.0)
+        s0 = e.ledger()["steps"].copy()
+        res = e.adjoint(0, 900.0, 10.0, c.gauges, obs, ckpt_every=1000)
+        info = e.adjoint_info()
+        steps = e.ledger()["steps"] - s0
+        print(name, info, "steps", steps)
+        out[name] = (res, info, [e.field(i, k) for i in range(6) for k in (fl.FIELD_H, fl.FIELD_QX, fl.FIELD_QY)])
+    (La, gna, gma), ia, fa = out["whole"]
+    (Lb, gnb, gmb), ib, fb = out["pool"]
+    assert ia["segments"] == ia["groups"] == 1
+    # a segment holds at most 16 steps of its member
+    assert steps.min() > 16
+    assert ib["group_size"] == 1 and ib["groups"] == 6 and ib["segments"] >= int(np.sum(-(-steps // 16)))
+    assert La == Lb
+    np.testing.assert_array_equal(gma, gmb)
+    assert np.linalg.norm(gna - gnb) <= 1e-6 * np.linalg.norm(gna)
+    for x, y in zip(fa, fb):
         np.testing.assert_array_equal(x, y)
