@@ -583,7 +583,7 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
 }
 
 template <typename T> void launch_adjoint_march(const AdjvLaunch<T>& A, hipStream_t s) {
-    constexpr int V = march_vec<T>();
+    constexpr int V = adj_vec<T>();
     const CatchDev<T>& C = A.c;
     const int nq = (C.n_members + 3) / 4;
     const dim3 grid(march_waves(C.strips_xa, C.strips_y, nq, C.march_order, C.march_bands));

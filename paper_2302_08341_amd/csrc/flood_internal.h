@@ -64,7 +64,7 @@ template <typename T> struct CatchDev {
     // row-march variants (members in planes): strips of march_rows rows, one
     // wavefront per (strip, group of march_seg members); strips_x counts the
     // strips of the kernel the view is launched with (62 cells for k_march, 64 V
-    // for k_marchv), strips_xa those of the adjoint's reverse step (62 V cells)
+    // for k_marchv), strips_xa those of the adjoint's reverse step (62 x 2 cells)
     int32_t march_rows, strips_x, strips_y, strips_xa;
     int32_t wave_begin, n_waves;
     int32_t march_order;      // wavefront order, see march_wave
@@ -186,6 +186,10 @@ template <typename T> void launch_step_mi(int mi, const StepLaunch<T>& L, hipStr
 template <typename T> void launch_march(const StepLaunch<T>& L, int seg, int total_waves, hipStream_t s);
 // cells per lane of the vectorised row-marching kernel (nx must be a multiple of it)
 template <typename T> constexpr int march_vec() { return sizeof(T) == 4 ? 4 : 2; }
+// Cells per lane of the adjoint's reverse row march, in both precisions: with
+// four FP32 cells per lane the reverse step needs 138 VGPRs (3 waves per SIMD),
+// with two 85 (5 waves per SIMD), and runs faster.
+template <typename T> constexpr int adj_vec() { return 2; }
 template <typename T>
 void launch_marchv(const StepLaunch<T>& L, int nt, int pf, int ext, int total_waves, hipStream_t s);
 // wavefronts of a row-march launch over one catchment: strips x member units,

@@ -31,27 +31,41 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     for (int i = 1; i < P.n_catch; ++i)
         if (m >= P.c[i].member_off) ci = i;
     const PlanCatch& C = P.c[ci];
+    const int lm = m - P.m_begin;
+    // The loads of the plan that depend on nothing else go out together, before
+    // any store (a planner is a chain of memory round trips, not of arithmetic).
+    const int par = P.par[m];
+    const double t = P.t[m];
+    const double t_end = *P.t_end;
+    const int fault = P.fault[m];
+    const int64_t st = P.steps[m];
+    const bool at_lim = P.step_lim && st >= P.step_lim[m];
+    HB hb = P.hbins[(size_t)lane * P.n_total + m];
+    const int pend = P.pend ? P.pend[lm] : -1;
+    const int cb = P.cur_blk ? P.cur_blk[lm] : 0;
+    const int nsmp = P.s_dt > 0.0 ? P.smp[lm] : 0;
+    const int nseg = P.seg_cnt ? P.seg_cnt[lm] : 0;
+    const double sc = P.s[m];
+    const double mu = P.mu[m];
+    const double jf = floor(t / C.rain_interval);
+    const double R = (jf >= 0.0 && jf < (double)C.n_rain) ? C.rain[(int64_t)jf] : 0.0;
     MemberStep<T> ms;
     ms.dtdx = ms.gdtdx = ms.gdt = ms.s2dt = ms.capf = ms.rinc = T(0);
     ms.dxdt = 0.0;
     ms.active = 0;
-    ms.parity = P.par[m];
+    ms.parity = par;
     ms.slot = ms.blk = ms.blk_next = -1;
     ms.seed = 0;
     for (int k = 0; k < kMaxClasses; ++k) ms.cn[k] = T(0);
     ms.drain = T(0);
     for (int k = 0; k < kMaxSeries; ++k) ms.qin[k] = T(0);
-    const double t = P.t[m];
-    const double t_end = *P.t_end;
-    const int lm = m - P.m_begin;
-    if (P.pend && P.pend[lm] >= 0) {
+    if (pend >= 0) {
         // misfit of the state after the member's last step, which completed sample pend
-        const int smp = P.pend[lm];
-        const T* h = P.tape_h + (size_t)P.cur_blk[lm] * P.plane;
+        const T* h = P.tape_h + (size_t)cb * P.plane;
         double acc = 0.0;
         for (int q = lane; q < P.n_gauges; q += 64) {
             const double d = (double)h[(size_t)P.grc[2 * q] * P.nx + P.grc[2 * q + 1]] -
-                             P.obs[(size_t)smp * P.n_gauges + q];
+                             P.obs[(size_t)pend * P.n_gauges + q];
             acc += d * d;
         }
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -60,7 +74,7 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
             P.pend[lm] = -1;
         }
     }
-    if (P.fault[m] || !(t < t_end) || (P.step_lim && P.steps[m] >= P.step_lim[m])) {
+    if (fault || !(t < t_end) || at_lim) {
         if (w0) {
             P.ms[m] = ms;
             if (P.ms_log && !P.rec_stride) {
@@ -71,7 +85,6 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
         }
         return;
     }
-    HB hb = P.hbins[(size_t)lane * P.n_total + m];
     for (int off = 32; off > 0; off >>= 1) {
         const HB o = __shfl_xor(hb, off, 64);
         hb = o > hb ? o : hb;
@@ -102,11 +115,9 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
         dt = C.alpha * C.dx / sqrt(C.g * Hd);
         if (dt > C.dt_cap) dt = C.dt_cap;
     }
-    const double jf = floor(t / C.rain_interval);
-    const double R = (jf >= 0.0 && jf < (double)C.n_rain) ? C.rain[(int64_t)jf] : 0.0;
     const double edge = (jf + 1.0 > (double)C.n_rain) ? INFINITY : (jf + 1.0) * C.rain_interval;
     double tev = t_end < edge ? t_end : edge;
-    const double ts = P.s_dt > 0.0 ? P.s_t0 + (double)(P.smp[lm] + 1) * P.s_dt : INFINITY;
+    const double ts = P.s_dt > 0.0 ? P.s_t0 + (double)(nsmp + 1) * P.s_dt : INFINITY;
     if (ts < tev) tev = ts;
     double tn;
     if (dt >= tev - t) {
@@ -124,13 +135,12 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     // every lane has read its bin: clear it for the step's new maximum
     P.hbins[(size_t)lane * P.n_total + m] = 0;
     if (!w0) return;
-    const double s = P.s[m];
     ms.dtdx = (T)(dt / C.dx);
     ms.gdtdx = (T)(C.g * dt / C.dx);
     ms.gdt = (T)(C.g * dt);
-    ms.s2dt = (T)(s * s * dt);
+    ms.s2dt = (T)(sc * sc * dt);
     ms.capf = (T)(C.dx / (4.0 * dt));
-    ms.rinc = (T)(P.mu[m] * R * dt);
+    ms.rinc = (T)(mu * R * dt);
     ms.dxdt = C.dx * dt;
     ms.active = 1;
     {
@@ -141,8 +151,9 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     }
     if (P.seg_cnt) {
         // the member's new state goes to the next free block of the tape
-        ms.slot = P.seg_cnt[lm]++;
-        ms.blk = P.cur_blk[lm];
+        ms.slot = nseg;
+        P.seg_cnt[lm] = nseg + 1;
+        ms.blk = cb;
         ms.blk_next = atomicAdd(P.pool_next, 1);
         P.cur_blk[lm] = ms.blk_next;
     }
@@ -163,7 +174,7 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
     P.ms[m] = ms;
     int tag = (tn == t_end) ? P.tag_value : -1;
     if (P.s_dt > 0.0) {
-        tag = (tn == ts) ? P.smp[lm] : -1;
+        tag = (tn == ts) ? nsmp : -1;
         if (tag >= 0) {
             P.smp[lm] = tag + 1;
             P.pend[lm] = tag;
@@ -176,7 +187,6 @@ __global__ __launch_bounds__(256) void k_plan(const PlanLaunch<T> P) {
         P.tag_log[li] = tag;
         if (P.any_log) P.any_log[0] = 1;
     }
-    const int64_t st = P.steps[m];
     if (P.dtlog) {
         const int64_t li = P.log_n[m];
         if (li < P.dtlog_cap) {

@@ -319,7 +319,7 @@ template <typename T> struct Impl : ImplBase {
             d.march_rows = std::max(1, std::min(c.march_rows, c.ny));
             const int strip_w = variant == 3 ? 64 * march_vec<T>() : 62;
             d.strips_x = (c.nx + strip_w - 1) / strip_w;
-            d.strips_xa = (c.nx + 62 * march_vec<T>() - 1) / (62 * march_vec<T>());
+            d.strips_xa = (c.nx + 62 * adj_vec<T>() - 1) / (62 * adj_vec<T>());
             d.strips_y = (c.ny + d.march_rows - 1) / d.march_rows;
             d.wave_begin = waves;
             {
@@ -1767,7 +1767,7 @@ static CatchDev<T> group_view(const CatchDev<T>& C, int mi, int g0, int G, T* co
     v.tiles_y = (C.ny + ty - 1) / ty;
     // row-march geometry (members in planes), likewise fixed
     const int strip_w = 64 * march_vec<T>();       // the recorded forward and tape recomputation (k_marchv)
-    const int strip_wa = 62 * march_vec<T>();      // the reverse step (k_adjv)
+    const int strip_wa = 62 * adj_vec<T>();        // the reverse step (k_adjv)
     int rows = kAdjMarchRows;   // at most 16: the reverse step stages 4 x rows x 64 x V values in LDS
     if (const char* ar = std::getenv("FLOOD_ADJ_ROWS")) rows = std::min(16, std::max(1, std::atoi(ar)));
     v.march_rows = std::min(rows, C.ny);
