@@ -324,7 +324,7 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
     const int k = 4 * u + wave;
     bool actq[4];
 #pragma unroll
-    for (int w = 0; w < 4; ++w) actq[w] = 4 * u + w < C.n_members && A.ms[4 * u + w].active;
+    for (int w = 0; w < 4; ++w) actq[w] = 4 * u + w < C.n_members && A.i < A.n[4 * u + w];
     const bool act = actq[wave];
     const int nx = C.nx, ny = C.ny;
     const int rows = C.march_rows;
@@ -340,14 +340,20 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
     const int r1 = min(r0 + C.march_rows, ny);
     const size_t plane = (size_t)ny * nx;
     if (act) {
-        const MemberStep<T> ms = A.ms[k];
+        // the member's step j = n[k] - 1 - i, its record, and the sample (if any)
+        // completed by its step before (whose seed goes into the depth adjoint written here)
+        const int jst = A.n[k] - 1 - A.i;
+        const size_t rr = (size_t)jst * A.stride + k;
+        const MemberStep<T> ms = A.rec[rr];
+        const double rdt = A.rec_rdt[rr];
+        const int tag_prev = (jst >= 1 && A.n_gauges > 0) ? A.rec_tag[rr - A.stride] : -1;
         const size_t bs = (size_t)ms.blk;
         const T* __restrict__ H = C.h[0] + bs * plane;
         const T* __restrict__ QX = C.qx[0] + bs * plane;
         const T* __restrict__ QY = C.qy[0] + bs * plane;
         const T* __restrict__ QWs = C.qw[0] + bs * ny;
         const T* __restrict__ QNs = C.qn[0] + bs * nx;
-        const int lp = A.lpar[k];
+        const int lp = A.lbase[k] ^ (A.i & 1);
         const T* __restrict__ LH = A.lh[lp] + (size_t)k * plane;
         const T* __restrict__ LQX = A.lqx[lp] + (size_t)k * plane;
         const T* __restrict__ LQY = A.lqy[lp] + (size_t)k * plane;
@@ -555,10 +561,23 @@ __global__ __launch_bounds__(kBlock) void k_adjv(const AdjvLaunch<T> A) {
             }
             ca += nx;
         }
+        if (tag_prev >= 0 && own) {
+            // the seeds 2 (h - d) of the sample the step before completed, in gauge
+            // order, added to the depth adjoint just written at the gauge cells among
+            // this lane's (none where that step clamped the depth); outside the row
+            // loop, so that the march itself carries no gauge work
+            for (int q = 0; q < A.n_gauges; ++q) {
+                const int gr = A.grc[2 * q], gc = A.grc[2 * q + 1];
+                if (gr < r0 || gr >= r1 || gc < xl || gc >= xl + V) continue;
+                const size_t cell = (size_t)gr * nx + gc;
+                const T hg = H[cell];
+                if (!clamp_mark(hg)) LHo[cell] += (T)(2.0 * ((double)hg - A.obs[(size_t)tag_prev * A.n_gauges + q]));
+            }
+        }
         // rain-multiplier adjoint: the depth adjoint after the step summed over the
         // strip's cells, times R dt of the member's step
         for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
-        if (lane == 0) A.mubar_part[(size_t)(sy * C.strips_xa + sx) * C.n_members + k] += lsum * A.rdt[k];
+        if (lane == 0) A.mubar_part[(size_t)(sy * C.strips_xa + sx) * C.n_members + k] += lsum * rdt;
     }
     __syncthreads();
     // the quad's Manning-field adjoint: wavefront w adds rows w, w + 4, ... of the
@@ -594,65 +613,38 @@ template <typename T> void launch_adjoint_march(const AdjvLaunch<T>& A, hipStrea
         hipLaunchKernelGGL((k_adjv<T, V, 0>), grid, dim3(kBlock), lds, s, A);
 }
 
-// One wavefront per member of the group.  With distinct gauge cells the lanes
-// seed one gauge each; otherwise lane 0 seeds them in order (a cell seen twice
-// takes both seeds).
+// One thread per member of the group (see launch_adj_segment); a cell seen by
+// two gauges takes both seeds, in gauge order.
 template <typename T>
-__global__ __launch_bounds__(256) void k_adj_plan(int G, int stride, int i, const int32_t* n, const MemberStep<T>* rec,
-                                                  const double* rec_rdt, const int32_t* rec_tag, int K, int distinct,
-                                                  const int32_t* grc, const double* obs, const T* tape_h,
-                                                  size_t plane, int nx, int32_t* lpar, int32_t* prev,
-                                                  MemberStep<T>* ms_out, double* rdt_out, T* lh0, T* lh1) {
-    const int lane = threadIdx.x & 63;
-    const int m = blockIdx.x * (blockDim.x >> 6) + (int)(threadIdx.x >> 6);
+__global__ __launch_bounds__(256) void k_adj_segment(int G, int stride, const int32_t* n_prev, const int32_t* n,
+                                                     const MemberStep<T>* rec, const int32_t* rec_tag, int K,
+                                                     const int32_t* grc, const double* obs, const T* tape_h,
+                                                     size_t plane, int nx, int32_t* lbase, T* lh0, T* lh1) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= G) return;
-    int p = lpar[m];
-    const int was = prev[m];
-    if (was) p ^= 1;
-    const int j = n[m] - 1 - i;
-    if (lane == 0) {
-        lpar[m] = p;
-        prev[m] = j >= 0;
+    int p = lbase[m];
+    if (n_prev) {
+        p ^= n_prev[m] & 1;
+        lbase[m] = p;
     }
-    if (j < 0) {
-        if (lane == 0) {
-            MemberStep<T> ms{};
-            ms.active = 0;
-            ms_out[m] = ms;
-            rdt_out[m] = 0.0;
-        }
-        return;
-    }
-    const size_t r = (size_t)j * stride + m;
-    if (lane == 0) {
-        ms_out[m] = rec[r];
-        rdt_out[m] = rec_rdt[r];
-    }
+    if (K == 0 || n[m] < 1) return;
+    const size_t r = (size_t)(n[m] - 1) * stride + m;
     const int smp = rec_tag[r];
-    if (K == 0 || smp < 0) return;
+    if (smp < 0) return;
     const T* h = tape_h + (size_t)rec[r].blk_next * plane;
     T* lh = (p ? lh1 : lh0) + (size_t)m * plane;
-    // a gauge cell whose depth the step clamped (-0 in the tape) passes no adjoint back
-    if (distinct) {
-        for (int q = lane; q < K; q += 64) {
-            const size_t cell = (size_t)grc[2 * q] * nx + grc[2 * q + 1];
-            if (!clamp_mark(h[cell])) lh[cell] += (T)(2.0 * ((double)h[cell] - obs[(size_t)smp * K + q]));
-        }
-    } else if (lane == 0) {
-        for (int q = 0; q < K; ++q) {
-            const size_t cell = (size_t)grc[2 * q] * nx + grc[2 * q + 1];
-            if (!clamp_mark(h[cell])) lh[cell] += (T)(2.0 * ((double)h[cell] - obs[(size_t)smp * K + q]));
-        }
+    for (int q = 0; q < K; ++q) {
+        const size_t cell = (size_t)grc[2 * q] * nx + grc[2 * q + 1];
+        if (!clamp_mark(h[cell])) lh[cell] += (T)(2.0 * ((double)h[cell] - obs[(size_t)smp * K + q]));
     }
 }
 
 template <typename T>
-void launch_adj_plan(int G, int stride, int i, const int32_t* n, const MemberStep<T>* rec, const double* rec_rdt,
-                     const int32_t* rec_tag, int K, int distinct, const int32_t* grc, const double* obs,
-                     const T* tape_h, size_t plane, int nx, int32_t* lpar, int32_t* prev, MemberStep<T>* ms_out,
-                     double* rdt_out, T* lh0, T* lh1, hipStream_t s) {
-    hipLaunchKernelGGL((k_adj_plan<T>), dim3((G + 3) / 4), dim3(256), 0, s, G, stride, i, n, rec, rec_rdt, rec_tag, K,
-                       distinct, grc, obs, tape_h, plane, nx, lpar, prev, ms_out, rdt_out, lh0, lh1);
+void launch_adj_segment(int G, int stride, const int32_t* n_prev, const int32_t* n, const MemberStep<T>* rec,
+                        const int32_t* rec_tag, int K, const int32_t* grc, const double* obs, const T* tape_h,
+                        size_t plane, int nx, int32_t* lbase, T* lh0, T* lh1, hipStream_t s) {
+    hipLaunchKernelGGL((k_adj_segment<T>), dim3((G + 255) / 256), dim3(256), 0, s, G, stride, n_prev, n, rec, rec_tag,
+                       K, grc, obs, tape_h, plane, nx, lbase, lh0, lh1);
 }
 
 // Member m of the group, element e of its plane and edge strips: tape block
@@ -813,14 +805,12 @@ void launch_sum_parts(int n_blocks, int n_members, const double* parts, double* 
 
 template void launch_adjoint_march<float>(const AdjvLaunch<float>&, hipStream_t);
 template void launch_adjoint_march<double>(const AdjvLaunch<double>&, hipStream_t);
-template void launch_adj_plan<float>(int, int, int, const int32_t*, const MemberStep<float>*, const double*,
-                                     const int32_t*, int, int, const int32_t*, const double*, const float*, size_t,
-                                     int, int32_t*, int32_t*, MemberStep<float>*, double*, float*, float*,
-                                     hipStream_t);
-template void launch_adj_plan<double>(int, int, int, const int32_t*, const MemberStep<double>*, const double*,
-                                      const int32_t*, int, int, const int32_t*, const double*, const double*, size_t,
-                                      int, int32_t*, int32_t*, MemberStep<double>*, double*, double*, double*,
-                                      hipStream_t);
+template void launch_adj_segment<float>(int, int, const int32_t*, const int32_t*, const MemberStep<float>*,
+                                        const int32_t*, int, const int32_t*, const double*, const float*, size_t, int,
+                                        int32_t*, float*, float*, hipStream_t);
+template void launch_adj_segment<double>(int, int, const int32_t*, const int32_t*, const MemberStep<double>*,
+                                         const int32_t*, int, const int32_t*, const double*, const double*, size_t,
+                                         int, int32_t*, double*, double*, hipStream_t);
 template void launch_tape_gather<float>(const CatchDev<float>&, const int32_t*, const CatchDev<float>&,
                                         const int32_t*, hipStream_t);
 template void launch_tape_gather<double>(const CatchDev<double>&, const int32_t*, const CatchDev<double>&,

@@ -270,9 +270,22 @@ template <typename T> struct AdjvLaunch {
     T* lqy[2];
     T* lqw[2];
     T* lqn[2];
-    const int32_t* lpar;      // [group members] copy holding the adjoint after the step
-    const MemberStep<T>* ms;  // [group members] record of this launch
-    const double* rdt;        // [group members]
+    // launch i of a tape segment whose member k took n[k] steps: member k reverses
+    // its step j = n[k] - 1 - i (none when j < 0), from the member-local records
+    // of the segment ([slot][stride], member k at k); its adjoint after the step is
+    // in copy lbase[k] ^ (i & 1)
+    int32_t i;
+    int32_t stride;
+    const int32_t* n;
+    const int32_t* lbase;
+    const MemberStep<T>* rec;
+    const double* rec_rdt;
+    const int32_t* rec_tag;
+    // gauge misfit: the seed of a sample completed by step j - 1 is added to the
+    // depth adjoint this launch writes (gauge cells [n_gauges][2], obs [samples][n_gauges])
+    int32_t n_gauges;
+    const int32_t* grc;
+    const double* obs;
     T* nacc;                  // [member quads][cell] Manning-field adjoint per quad of members (accumulated)
     double* mubar_part;       // [strips][group members] rain-multiplier adjoint partials (accumulated)
     int32_t pf;               // 1: one row of load lookahead in the reverse march
@@ -280,20 +293,19 @@ template <typename T> struct AdjvLaunch {
 template <typename T> void launch_adjoint_march(const AdjvLaunch<T>& A, hipStream_t s);
 template <typename T>
 void launch_nacc_reduce(int G, size_t ncell, const T* nacc, double* nbar, hipStream_t s);
-// Reverse planner of launch i of a tape segment whose member k took n[k] steps
-// (records [slot][stride], member k at k):
-// member k reverses its step j = n[k] - 1 - i (inactive when j < 0).  Flips the
-// adjoint copy index of members that stepped in the previous reverse launch,
-// writes this launch's step coefficients (ms_out, rdt_out) from the member-local
-// records, and seeds the gauge misfit of a step that completed a
-// sample, 2 (h - d), read from the tape block the step wrote (distinct: no two
-// gauges share a cell, so the gauges are seeded in parallel).  tape_h: the
-// tape's depth pool.
+// Start of the reverse of a tape segment whose member m took n[m] steps
+// (records [slot][stride], member m at m): first the adjoint copy index lbase[m]
+// moves past the n_prev[m] steps of the segment reversed before (n_prev null:
+// the group's last segment, lbase starts at 0), then the gauge misfit of a
+// sample completed by the segment's last step of the member, 2 (h - d), is
+// seeded into the adjoint of the depths after it (h read from the tape block
+// the step wrote; a gauge cell the step clamped gets none).  Seeds of the
+// samples completed by earlier steps are added by the reverse step itself.
+// tape_h: the tape's depth pool.
 template <typename T>
-void launch_adj_plan(int G, int stride, int i, const int32_t* n, const MemberStep<T>* rec, const double* rec_rdt,
-                     const int32_t* rec_tag, int K, int distinct, const int32_t* grc, const double* obs, const T* tape_h,
-                     size_t plane, int nx, int32_t* lpar, int32_t* prev, MemberStep<T>* ms_out, double* rdt_out,
-                     T* lh0, T* lh1, hipStream_t s);
+void launch_adj_segment(int G, int stride, const int32_t* n_prev, const int32_t* n, const MemberStep<T>* rec,
+                        const int32_t* rec_tag, int K, const int32_t* grc, const double* obs, const T* tape_h,
+                        size_t plane, int nx, int32_t* lbase, T* lh0, T* lh1, hipStream_t s);
 // Copy each member's state from tape block blk[m] (tape: copy-0 arrays are the
 // block pools) to dst, into copy dpar[dst.member_off + m] (dpar null: copy 0).
 template <typename T>

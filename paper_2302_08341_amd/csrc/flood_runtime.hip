@@ -1997,10 +1997,9 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
     // member-local step records ([segment][slot][member]) and per-member counters
     int32_t* d_lpar = nullptr;
     int32_t* d_segcnt = nullptr;
-    int32_t *d_smp = nullptr, *d_pend = nullptr, *d_prev = nullptr, *d_cnt3 = nullptr;
+    int32_t *d_smp = nullptr, *d_pend = nullptr, *d_cnt3 = nullptr;
     int32_t *d_curblk = nullptr, *d_pool = nullptr;
-    double *d_lossm = nullptr, *d_rdtcur = nullptr;
-    MemberStep<T>* d_mscur = nullptr;
+    double* d_lossm = nullptr;
     T* d_nacc = nullptr;
     MemberStep<T>* rec_ms = nullptr;
     double* rec_rdt = nullptr;
@@ -2015,13 +2014,10 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
         CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_segcnt));
         CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_smp));
         CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_pend));
-        CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_prev));
         CHK(talloc(8 * sizeof(int32_t), (void**)&d_cnt3));
         CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_curblk));
         CHK(talloc(sizeof(int32_t), (void**)&d_pool));
         CHK(talloc((size_t)Gi * sizeof(double), (void**)&d_lossm));
-        CHK(talloc((size_t)Gi * sizeof(double), (void**)&d_rdtcur));
-        CHK(talloc((size_t)Gi * sizeof(MemberStep<T>), (void**)&d_mscur));
         // one Manning-field accumulator per member quad
         CHK(adj_reserve(adj_nacc, (size_t)((Gi + 3) / 4) * ncell * sizeof(T), err));
         d_nacc = static_cast<T*>(adj_nacc.p);
@@ -2377,13 +2373,19 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
             HIPCHK(hipMemsetAsync(lam, 0, 2 * slot_elems * sizeof(T), st));
             HIPCHK(hipMemsetAsync(d_mubar, 0, (size_t)nblk * Gi * sizeof(double), st));
             HIPCHK(hipMemsetAsync(d_lpar, 0, (size_t)Gi * sizeof(int32_t), st));
-            HIPCHK(hipMemsetAsync(d_prev, 0, (size_t)Gi * sizeof(int32_t), st));
             HIPCHK(hipMemsetAsync(d_nacc, 0, (size_t)((Gg + 3) / 4) * ncell * sizeof(T), st));
             T* lb[2] = {lam, lam + slot_elems};
-            for (int sg = (int)seg_nmax.size() - 1; sg >= 0; --sg) {
+            const int last_seg = (int)seg_nmax.size() - 1;
+            for (int sg = last_seg; sg >= 0; --sg) {
                 const int nmax = seg_nmax[sg];
-                if (nmax == 0) continue;
                 const MemberStep<T>* recs = rec_at(sg);
+                const int32_t* nseg = seg_n + (size_t)sg * Gi;
+                if (nmax == 0) {   // no member stepped: only the adjoint copy indices move on
+                    launch_adj_segment<T>(Gg, Gi, sg == last_seg ? nullptr : nseg + Gi, nseg, recs,
+                                          rec_tag + (size_t)sg * seg_recs, 0, d_grc2, d_obs2, tape, plane, C.nx,
+                                          d_lpar, lb[0], lb[1], st);
+                    continue;
+                }
                 if (sg != (int)seg_nmax.size() - 1) {
                     CHK(ckpt_copy(static_cast<T*>(adj_ckpt[sg].p), false));
                     for (int r = 0; r < nmax; ++r) {
@@ -2394,25 +2396,32 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                         launch_marchv_rec<T>(R, march_pf, 0, tw, st);
                     }
                 }
+                launch_adj_segment<T>(Gg, Gi, sg == last_seg ? nullptr : nseg + Gi, nseg, recs,
+                                      rec_tag + (size_t)sg * seg_recs, K, d_grc2, d_obs2, tape, plane, C.nx, d_lpar,
+                                      lb[0], lb[1], st);
+                AdjvLaunch<T> A{};
+                A.c = TV;
+                for (int w = 0; w < 2; ++w) {
+                    A.lh[w] = lb[w];
+                    A.lqx[w] = lb[w] + elemsG;
+                    A.lqy[w] = lb[w] + 2 * elemsG;
+                    A.lqw[w] = lb[w] + 3 * elemsG;
+                    A.lqn[w] = lb[w] + 3 * elemsG + wG;
+                }
+                A.stride = Gi;
+                A.n = nseg;
+                A.lbase = d_lpar;
+                A.rec = recs;
+                A.rec_rdt = rec_rdt + (size_t)sg * seg_recs;
+                A.rec_tag = rec_tag + (size_t)sg * seg_recs;
+                A.n_gauges = K;
+                A.grc = d_grc2;
+                A.obs = d_obs2;
+                A.nacc = d_nacc;
+                A.mubar_part = d_mubar;
+                A.pf = adj_pf;
                 for (int i = 0; i < nmax; ++i) {
-                    launch_adj_plan<T>(Gg, Gi, i, seg_n + (size_t)sg * Gi, recs, rec_rdt + (size_t)sg * seg_recs,
-                                       rec_tag + (size_t)sg * seg_recs, K, gauges_distinct, d_grc2, d_obs2, tape,
-                                       plane, C.nx, d_lpar, d_prev, d_mscur, d_rdtcur, lb[0], lb[1], st);
-                    AdjvLaunch<T> A{};
-                    A.c = TV;
-                    for (int w = 0; w < 2; ++w) {
-                        A.lh[w] = lb[w];
-                        A.lqx[w] = lb[w] + elemsG;
-                        A.lqy[w] = lb[w] + 2 * elemsG;
-                        A.lqw[w] = lb[w] + 3 * elemsG;
-                        A.lqn[w] = lb[w] + 3 * elemsG + wG;
-                    }
-                    A.lpar = d_lpar;
-                    A.ms = d_mscur;
-                    A.rdt = d_rdtcur;
-                    A.nacc = d_nacc;
-                    A.mubar_part = d_mubar;
-                    A.pf = adj_pf;
+                    A.i = i;
                     launch_adjoint_march<T>(A, st);
                 }
                 HIPCHK(hipGetLastError());

@@ -95,6 +95,26 @@ def test_adjoint_fp64_matches_oracle(fl, orc, sk):
 
 
 @SK
+def test_adjoint_fp64_with_gauges_sharing_cells_matches_oracle(fl, orc, sk):
+    # two gauges on one cell: both misfits enter the loss and both seeds the
+    # adjoint, in gauge order
+    z, n, h0, s, mu, g = _smooth()
+    g = np.asarray(g).reshape(-1, 2)
+    g2 = np.vstack([g, g[:1], g[-1:], g[:1]])
+    rain = [2e-4, 1e-4]
+    obs = np.random.default_rng(5).uniform(0.3, 0.5, size=(4, len(g2)))
+    e = _ens(fl, z, n, h0, s, mu, rain, 20.0, EDGES, SLOPES, real_bytes=8, cfl_alpha=0.5, dt_cap=5.0,
+             step_kernel=sk)
+    L, gn, gm = e.adjoint(0, 40.0, 10.0, g2, obs, ckpt_every=7)
+    Lo, gno, gmo = _oracle_adjoint(orc, z, n, rain, 20.0, EDGES, SLOPES, s, mu, h0, None, 40.0, 10.0, g2, obs, 7,
+                                   alpha=0.5, dt_cap=5.0)
+    assert L == pytest.approx(Lo, rel=1e-10)
+    np.testing.assert_allclose(gm, gmo, rtol=1e-8)
+    assert np.linalg.norm(gn - gno) <= 1e-8 * np.linalg.norm(gno)
+    _cellwise_ok(gn, gno, 1e-7)
+
+
+@SK
 def test_adjoint_fp32_matches_oracle_on_wet_urban_state(fl, orc, sk):
     N = 3
     c = W.urban_catchment("adj", 64, 56, N, W.seed_for(3, 1), n_gauges=6)
