@@ -181,31 +181,39 @@ template <typename T> struct Impl : ImplBase {
     }
 
     // Reorder the members of catchment c (members in planes): slot i takes the member
-    // held in slot order[i], with everything that belongs to it (both state copies,
-    // edge strips, running maximum, outflow accumulators, depth-maximum bins, time,
+    // held in slot order[i], with everything that belongs to it (its state, edge
+    // strips, running maximum, outflow accumulators, depth-maximum bins, time,
     // parameters, weight, ledger, copy index, fault flag).  Rows of the large arrays
-    // move along the cycles of the order through one row of staging.
+    // move along the cycles of the order through one row of staging.  Of the two
+    // state copies only the one holding the member's state moves (into the same copy
+    // of its new slot, whose copy index moves with it); the other is the next step's
+    // output and holds nothing.
     flood_status reorder_members(int c, const std::vector<int32_t>& order, std::string& err) {
         Cat& C = cats[c];
         const int N = C.N, off = C.dev.member_off;
         const size_t ncell = (size_t)C.ny * C.nx, nb = 2 * ((size_t)C.nx + C.ny);
         struct Rows {
-            void* base;
-            size_t bytes;   // per member
+            void* base[2];   // the two state copies, or one array (base[1] null)
+            size_t bytes;    // per member
         };
         std::vector<Rows> rows;
-        for (int k = 0; k < 2; ++k) {
-            rows.push_back({C.dev.h[k], ncell * sizeof(T)});
-            rows.push_back({C.dev.qx[k], ncell * sizeof(T)});
-            rows.push_back({C.dev.qy[k], ncell * sizeof(T)});
-            rows.push_back({C.dev.qw[k], (size_t)C.ny * sizeof(T)});
-            rows.push_back({C.dev.qn[k], (size_t)C.nx * sizeof(T)});
-        }
-        if (C.dev.peak) rows.push_back({C.dev.peak, ncell * sizeof(T)});
-        rows.push_back({C.dev.out_acc, nb * sizeof(double)});
-        if (C.dev.drain_acc) rows.push_back({C.dev.drain_acc, (size_t)kBins * sizeof(double)});
+        rows.push_back({{C.dev.h[0], C.dev.h[1]}, ncell * sizeof(T)});
+        rows.push_back({{C.dev.qx[0], C.dev.qx[1]}, ncell * sizeof(T)});
+        rows.push_back({{C.dev.qy[0], C.dev.qy[1]}, ncell * sizeof(T)});
+        rows.push_back({{C.dev.qw[0], C.dev.qw[1]}, (size_t)C.ny * sizeof(T)});
+        rows.push_back({{C.dev.qn[0], C.dev.qn[1]}, (size_t)C.nx * sizeof(T)});
+        if (C.dev.peak) rows.push_back({{C.dev.peak, nullptr}, ncell * sizeof(T)});
+        rows.push_back({{C.dev.out_acc, nullptr}, nb * sizeof(double)});
+        if (C.dev.drain_acc) rows.push_back({{C.dev.drain_acc, nullptr}, (size_t)kBins * sizeof(double)});
         CHK(adj_reserve(adj_row, ncell * sizeof(T) > nb * sizeof(double) ? ncell * sizeof(T) : nb * sizeof(double), err));
-        auto row = [](const Rows& r, int i) { return static_cast<char*>(r.base) + (size_t)i * r.bytes; };
+        // the state copy of each slot's member before the move
+        std::vector<int32_t> hp(N);
+        HIPCHK(hipMemcpyAsync(hp.data(), par + off, (size_t)N * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        auto row = [&](const Rows& r, int i, int slot_of_member) {
+            const int k = r.base[1] ? hp[slot_of_member] : 0;
+            return static_cast<char*>(r.base[k]) + (size_t)i * r.bytes;
+        };
         std::vector<char> seen(N, 0);
         for (int i0 = 0; i0 < N; ++i0) {
             if (seen[i0] || order[i0] == i0) {
@@ -213,13 +221,14 @@ template <typename T> struct Impl : ImplBase {
                 continue;
             }
             for (const Rows& r : rows) {
-                HIPCHK(hipMemcpyAsync(adj_row.p, row(r, i0), r.bytes, hipMemcpyDeviceToDevice, st));
+                HIPCHK(hipMemcpyAsync(adj_row.p, row(r, i0, i0), r.bytes, hipMemcpyDeviceToDevice, st));
                 int i = i0;
                 while (order[i] != i0) {
-                    HIPCHK(hipMemcpyAsync(row(r, i), row(r, order[i]), r.bytes, hipMemcpyDeviceToDevice, st));
+                    HIPCHK(hipMemcpyAsync(row(r, i, order[i]), row(r, order[i], order[i]), r.bytes,
+                                          hipMemcpyDeviceToDevice, st));
                     i = order[i];
                 }
-                HIPCHK(hipMemcpyAsync(row(r, i), adj_row.p, r.bytes, hipMemcpyDeviceToDevice, st));
+                HIPCHK(hipMemcpyAsync(row(r, i, i0), adj_row.p, r.bytes, hipMemcpyDeviceToDevice, st));
             }
             for (int i = i0; !seen[i]; i = order[i]) seen[i] = 1;
         }
@@ -1997,8 +2006,8 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
     // member-local step records ([segment][slot][member]) and per-member counters
     int32_t* d_lpar = nullptr;
     int32_t* d_segcnt = nullptr;
-    int32_t *d_smp = nullptr, *d_pend = nullptr, *d_cnt3 = nullptr;
-    int32_t *d_curblk = nullptr, *d_pool = nullptr;
+    int32_t *d_smp = nullptr, *d_pend = nullptr;
+    int32_t *d_curblk = nullptr, *d_pool = nullptr, *d_hcnt3 = nullptr;
     double* d_lossm = nullptr;
     T* d_nacc = nullptr;
     MemberStep<T>* rec_ms = nullptr;
@@ -2014,7 +2023,6 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
         CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_segcnt));
         CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_smp));
         CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_pend));
-        CHK(talloc(8 * sizeof(int32_t), (void**)&d_cnt3));
         CHK(talloc((size_t)Gi * sizeof(int32_t), (void**)&d_curblk));
         CHK(talloc(sizeof(int32_t), (void**)&d_pool));
         CHK(talloc((size_t)Gi * sizeof(double), (void**)&d_lossm));
@@ -2022,6 +2030,8 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
         CHK(adj_reserve(adj_nacc, (size_t)((Gi + 3) / 4) * ncell * sizeof(T), err));
         d_nacc = static_cast<T*>(adj_nacc.p);
         if (!h_cnt3) HIPCHK(hipHostMalloc((void**)&h_cnt3, 8 * sizeof(int32_t), hipHostMallocDefault));
+        // the batch counts go straight into the pinned block (no copy command per batch)
+        HIPCHK(hipHostGetDevicePointer((void**)&d_hcnt3, h_cnt3, 0));
     }
     // grow the member-local records to hold n entries (contents kept)
     auto grow_rec = [&](size_t n) -> flood_status {
@@ -2264,10 +2274,8 @@ flood_status Impl<T>::adjoint(int c, double t_end, double sample_dt, int K, cons
                 }
                 L += B;
                 launch_count_group(Gg, t + off + g0, fault + off + g0, d_tend, status, d_segcnt, d_pool,
-                                   d_cnt3 + 4 * slot, st);
+                                   d_hcnt3 + 4 * slot, st);
                 HIPCHK(hipGetLastError());
-                HIPCHK(hipMemcpyAsync(h_cnt3 + 4 * slot, d_cnt3 + 4 * slot, 4 * sizeof(int32_t),
-                                      hipMemcpyDeviceToHost, st));
                 HIPCHK(hipEventRecord(ev[slot], st));
                 return FLOOD_OK;
             };
