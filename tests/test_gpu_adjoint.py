@@ -345,10 +345,17 @@ def test_tape_pool_that_runs_out_ends_segments(fl, monkeypatch, rb):
                              rain, real_bytes=rb, step_kernel=3)
         e.step(600.0)
         s0 = e.ledger()["steps"].copy()
+        clamp0 = e.ledger()["clamp"].copy()
         res = e.adjoint(0, 900.0, 10.0, c.gauges, obs, ckpt_every=1000)
         info = e.adjoint_info()
         steps = e.ledger()["steps"] - s0
         print(name, info, "steps", steps)
+        # the window clamps depths (the tape marks them as -0), and the state handed
+        # back holds +0 there
+        assert np.any(e.ledger()["clamp"] > clamp0)
+        for i in range(6):
+            h = e.field(i, fl.FIELD_H)
+            assert not np.any((h == 0.0) & np.signbit(h))
         out[name] = (res, info, [e.field(i, k) for i in range(6) for k in (fl.FIELD_H, fl.FIELD_QX, fl.FIELD_QY)])
     (La, gna, gma), ia, fa = out["whole"]
     (Lb, gnb, gmb), ib, fb = out["pool"]
